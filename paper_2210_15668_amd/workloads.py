@@ -1,0 +1,205 @@
+"""Seeded synthetic workloads: layer stacks, plane tables and initial P fields.
+
+This module holds the problem *inputs* only -- material parameters, the
+per-plane material tables of a layered gate stack, and the seeded random
+initial polarisation.  It contains none of the method's arithmetic (no
+stencils, no carrier statistics, no solver), so that both the CPU oracle
+(test infrastructure) and the HIP library consume identical inputs without
+sharing any code of the method.
+
+Material parameters follow the paper's Table 1 (Landau coefficients
+alpha/beta/gamma, gradient coefficients g11=g44, permittivities, mobility
+Gamma, grid spacing, extrapolation length lambda).  The gradient coefficient
+and time step used by the synthetic workloads are 1e-10 V m^3/C and 1e-13 s.
+
+Orientation: z points from the back contact (k = 0, potential v_bottom) to
+the gate (k = nz-1, potential v_top = V_app).  Layer lists are given
+top-down, gate first, as the paper describes its stacks (ferroelectric on
+top, then dielectric, then semiconductor).  Grid planes not covered by the
+listed layers are electrode metal split between the two z-ends (odd plane at
+the bottom).
+"""
+from __future__ import annotations
+
+import dataclasses
+from typing import List, Optional, Sequence, Tuple
+
+import numpy as np
+
+METAL, FE, DE, SC = 0, 1, 2, 3
+PBC_FREE, PBC_ZERO, PBC_LAMBDA = 0, 1, 2
+PREC_FP64, PREC_MIXED = 0, 1
+
+# Table 1 of the paper (SI units)
+ALPHA = -2.5e9          # V m / C
+BETA = 6.0e10           # V m^5 / C^3
+GAMMA_L = 1.5e11        # V m^9 / C^5
+G_GRAD = 1.0e-10        # V m^3 / C (g11 = g44) for the synthetic workloads
+MOBILITY = 100.0        # Gamma
+EPS_FE = 24.0
+EPS_SIO2 = 3.9
+EPS_AL2O3 = 10.0
+EPS_SI = 11.7
+H = 0.5e-9              # m
+LAMBDA = 3.0e-9         # m
+DT = 1.0e-13            # s
+
+
+@dataclasses.dataclass
+class StackSpec:
+    """A layered device stack on a periodic-in-x/y cell-centred grid."""
+
+    nx: int
+    ny: int
+    nz: int
+    h: float
+    plane_mat: np.ndarray        # int32[nz]
+    plane_eps_r: np.ndarray      # float64[nz]
+    plane_Na: np.ndarray         # float64[nz], m^-3
+    plane_Nd: np.ndarray         # float64[nz], m^-3
+    alpha: float = ALPHA
+    beta: float = BETA
+    gamma: float = GAMMA_L
+    g11: float = G_GRAD
+    g44: float = G_GRAD
+    Gamma: float = MOBILITY
+    pbc: int = PBC_LAMBDA
+    lam: float = LAMBDA
+    ni: float = 1.0e16
+    T: float = 300.0
+    v_bottom: float = 0.0
+    v_top: float = 0.0
+    tol_rel: float = 1e-10
+    max_cycles: int = 60
+    prec: int = PREC_FP64
+
+    @property
+    def ncell(self) -> int:
+        return self.nx * self.ny * self.nz
+
+    def device_range(self) -> Tuple[int, int]:
+        nm = np.nonzero(self.plane_mat != METAL)[0]
+        return int(nm[0]), int(nm[-1]) + 1
+
+    def fe_range(self) -> Tuple[int, int]:
+        fe = np.nonzero(self.plane_mat == FE)[0]
+        return int(fe[0]), int(fe[-1]) + 1
+
+    def n_active(self) -> int:
+        kb, kt = self.device_range()
+        return self.nx * self.ny * (kt - kb)
+
+    def n_fe(self) -> int:
+        f0, f1 = self.fe_range()
+        return self.nx * self.ny * (f1 - f0)
+
+    def copy(self, **kw) -> "StackSpec":
+        d = dataclasses.asdict(self)
+        d.update(kw)
+        for k in ("plane_mat", "plane_eps_r", "plane_Na", "plane_Nd"):
+            d[k] = np.array(d[k], copy=True)
+        return StackSpec(**d)
+
+
+def layered(nx: int, ny: int, nz: int, layers_top_down: Sequence[Tuple[int, int, float, float]],
+            h: float = H, **kw) -> StackSpec:
+    """Build a stack from (material, planes, eps_r, Na) layers listed gate-first.
+
+    Remaining planes become electrode metal, split between the two ends with
+    the odd plane at the bottom.
+    """
+    used = sum(l[1] for l in layers_top_down)
+    if used > nz:
+        raise ValueError("layers exceed nz")
+    n_metal = nz - used
+    top_metal = n_metal // 2
+    bot_metal = n_metal - top_metal
+    mat = np.zeros(nz, np.int32)
+    eps = np.ones(nz, np.float64)
+    na = np.zeros(nz, np.float64)
+    nd = np.zeros(nz, np.float64)
+    k = nz - top_metal
+    for (m, n, e, a) in layers_top_down:
+        k -= n
+        mat[k:k + n] = m
+        eps[k:k + n] = e
+        na[k:k + n] = a
+    assert k == bot_metal
+    return StackSpec(nx, ny, nz, h, mat, eps, na, nd, **kw)
+
+
+def random_P(spec: StackSpec, seed: int, amp: float = 0.01) -> np.ndarray:
+    """Uniform random P_z in [-amp, amp] on ferroelectric planes, zero elsewhere.
+
+    Draw order: numpy default_rng(seed).uniform over (n_fe_planes, ny, nx) in C
+    order, bottom ferroelectric plane first.  Returns a full-grid float64 array
+    of shape (nz, ny, nx).
+    """
+    f0, f1 = spec.fe_range()
+    rng = np.random.default_rng(seed)
+    P = np.zeros((spec.nz, spec.ny, spec.nx), np.float64)
+    P[f0:f1] = rng.uniform(-amp, amp, (f1 - f0, spec.ny, spec.nx))
+    return P
+
+
+# --------------------------------------------------------------------------
+# The synthetic workloads (shapes and parameters of the paper's stacks)
+# --------------------------------------------------------------------------
+
+def mfim_small() -> StackSpec:
+    """16x16x32 MFIM: FE 16 planes (eps 24) over DE 4 planes (eps 3.9), metal 6+6, 1 V gate."""
+    return layered(16, 16, 32, [(FE, 16, EPS_FE, 0.0), (DE, 4, EPS_SIO2, 0.0)],
+                   v_top=1.0, tol_rel=1e-10)
+
+
+def mfim_ramp() -> StackSpec:
+    """128x128x64 MFIM: FE 40 / DE 8 (eps 3.9), metal 8+8; gate ramped 0 -> 1.5 V over 2000 steps."""
+    return layered(128, 128, 64, [(FE, 40, EPS_FE, 0.0), (DE, 8, EPS_SIO2, 0.0)],
+                   v_top=0.0, tol_rel=1e-10)
+
+
+def mfism_large(prec: int = PREC_FP64) -> StackSpec:
+    """256x256x128 MFISM: FE 48 / SiO2 8 / p-Si 64 (Na 1e24, ni 1e16, 300 K), metal 4+4, 1 V gate."""
+    return layered(256, 256, 128, [(FE, 48, EPS_FE, 0.0), (DE, 8, EPS_SIO2, 0.0),
+                                   (SC, 64, EPS_SI, 1.0e24)],
+                   v_top=1.0, ni=1.0e16, T=300.0, tol_rel=1e-10, prec=prec)
+
+
+def mfism_medium(prec: int = PREC_FP64) -> StackSpec:
+    """128x128x64 MFISM: FE 24 / SiO2 4 / p-Si 32, metal 2+2 (half of the large stack's proportions)."""
+    return layered(128, 128, 64, [(FE, 24, EPS_FE, 0.0), (DE, 4, EPS_SIO2, 0.0),
+                                  (SC, 32, EPS_SI, 1.0e24)],
+                   v_top=1.0, ni=1.0e16, T=300.0, tol_rel=1e-10, prec=prec)
+
+
+def shrink_lateral(spec: StackSpec, nx: int, ny: int) -> StackSpec:
+    """Same z-stack on a smaller periodic x-y footprint (for oracle-sized parity cases)."""
+    return spec.copy(nx=nx, ny=ny)
+
+
+def ramp_schedule(nsteps: int, v_final: float = 1.5, n_ramp: int = 2000) -> np.ndarray:
+    """Gate voltage for the solve producing phi^n, n = 1..nsteps: v_final * n / n_ramp."""
+    n = np.arange(1, nsteps + 1, dtype=np.float64)
+    return v_final * np.minimum(n, n_ramp) / n_ramp
+
+
+def batch_instances(count: int = 64, seed0: int = 100) -> List[Tuple[StackSpec, np.ndarray]]:
+    """Uneven MFIM instances: x,y from {32,48,64,96}, z from {32,48}, FE 16..min(32,nz-4), DE 4.
+
+    Each instance draws its sizes, gate voltage (uniform in [-2, 2] V) and
+    initial P from default_rng(seed0 + index).
+    """
+    out = []
+    for i in range(count):
+        rng = np.random.default_rng(seed0 + i)
+        nx = int(rng.choice([32, 48, 64, 96]))
+        ny = int(rng.choice([32, 48, 64, 96]))
+        nz = int(rng.choice([32, 48]))
+        nfe = int(rng.integers(16, min(32, nz - 4) + 1))
+        v = float(rng.uniform(-2.0, 2.0))
+        spec = layered(nx, ny, nz, [(FE, nfe, EPS_FE, 0.0), (DE, 4, EPS_SIO2, 0.0)], v_top=v)
+        f0, f1 = spec.fe_range()
+        P = np.zeros((nz, ny, nx))
+        P[f0:f1] = rng.uniform(-0.01, 0.01, (f1 - f0, ny, nx))
+        out.append((spec, P))
+    return out

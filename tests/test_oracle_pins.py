@@ -1,0 +1,372 @@
+"""Pins of the CPU oracle against what the paper and the mathematics fix.
+
+Every expected value here comes from a closed form, a textbook/library
+routine, an exact invariant or brute force -- never from the oracle itself
+and never from the HIP path.  Together they are chosen so that a plausible
+slip anywhere in the oracle (a dropped term, a wrong sign, index or
+coefficient, a transposed stencil) fails at least one of them.
+"""
+import numpy as np
+import pytest
+
+from paper_2210_15668_amd import workloads as W
+
+EPS0 = 8.8541878128e-12
+QE = 1.602176634e-19
+KB = 1.380649e-23
+
+
+def one_d(nz_layers, nxy=2, pbc=W.PBC_FREE, **kw):
+    """A laterally uniform stack on an nxy x nxy footprint with one metal plane at each end."""
+    n = sum(l[1] for l in nz_layers) + 2
+    return W.layered(nxy, nxy, n, nz_layers, pbc=pbc, **kw)
+
+
+# ---------------------------------------------------------------- Landau / TDGL
+
+def landau_roots(alpha, beta, gamma):
+    """Positive stationary points of f = a/2 P^2 + b/4 P^4 + g/6 P^6 (roots of a + b x + g x^2, x = P^2)."""
+    xs = np.roots([gamma, beta, alpha])
+    xs = xs[np.isreal(xs)].real
+    return np.sqrt(xs[xs > 0])
+
+
+def test_T1_remnant_polarisation_closed_form(orc):
+    """Uniform P in a metal-FE-metal stack, V = 0, free BC relaxes to the Landau minimum P_r (eq. free)."""
+    pr = landau_roots(W.ALPHA, W.BETA, W.GAMMA_L)
+    assert len(pr) == 1
+    assert pr[0] == pytest.approx(0.195057976726823, rel=1e-12)
+    spec = one_d([(W.FE, 6, W.EPS_FE, 0.0)], v_top=0.0)
+    f0, f1 = spec.fe_range()
+    P = np.zeros((spec.nz, spec.ny, spec.nx))
+    P[f0:f1] = 0.05
+    P, phi, _ = orc.run(spec, P, 3000, 2e-13, tol=1e-13)
+    assert np.abs(phi).max() < 1e-12                     # D-flux: uniform P leaves no bound charge
+    assert np.allclose(P[f0:f1], pr[0], rtol=1e-11, atol=0)
+
+
+def test_T2_devonshire_misreading_is_excluded():
+    """The paper's 1/2,1/4,1/6 form, not the Devonshire a1 P^2 + a11 P^4 + a111 P^6 with the same numbers."""
+    pr_paper = landau_roots(W.ALPHA, W.BETA, W.GAMMA_L)[0]
+    pr_dev = landau_roots(2 * W.ALPHA, 4 * W.BETA, 6 * W.GAMMA_L)[0]
+    assert pr_dev == pytest.approx(0.139352753226699, rel=1e-12)
+    assert abs(pr_paper - pr_dev) > 0.05
+
+
+def test_T1b_scalar_euler_recursion(orc):
+    """With phi = 0 and uniform P the update is the scalar forward-Euler map of the Landau force."""
+    spec = one_d([(W.FE, 5, W.EPS_FE, 0.0)])
+    f0, f1 = spec.fe_range()
+    p = 0.013
+    P = np.zeros((spec.nz, spec.ny, spec.nx))
+    P[f0:f1] = p
+    phi = np.zeros_like(P)
+    dt = 1e-13
+    for _ in range(50):
+        P = orc.tdgl_step(spec, P, phi, dt)
+        p = p - dt * W.MOBILITY * (W.ALPHA * p + W.BETA * p ** 3 + W.GAMMA_L * p ** 5)
+    assert np.allclose(P[f0:f1], p, rtol=1e-14, atol=0)
+
+
+def _dzz_from_rhs(orc, spec, P):
+    """Recover g11 * Dzz from f(P, 0) with the Landau terms switched off."""
+    s = spec.copy(alpha=0.0, beta=0.0, gamma=0.0)
+    f = orc.tdgl_rhs(s, P, np.zeros_like(P))
+    return f / (s.Gamma * s.g11)
+
+
+@pytest.mark.parametrize("pbc,lam", [(W.PBC_LAMBDA, 3e-9), (W.PBC_LAMBDA, 0.7e-9), (W.PBC_ZERO, 0.0)])
+def test_surface_stencil_exact_for_quadratics(orc, pbc, lam):
+    """Eqs. (Pbc)/(PbcDir): for a quadratic P(z) that meets the surface condition at both
+    ferroelectric faces, the one-sided three-point stencil returns P'' exactly on every plane."""
+    spec = one_d([(W.FE, 9, W.EPS_FE, 0.0)], pbc=pbc, lam=lam)
+    f0, f1 = spec.fe_range()
+    h = spec.h
+    zb, zt = f0 * h, f1 * h                          # ferroelectric faces
+    c = 1.0e15
+    # P = a + b z + c z^2 ; bottom: lam P'(zb) - P(zb) = 0 ; top: lam P'(zt) + P(zt) = 0
+    A = np.array([[-1.0, lam - zb], [1.0, lam + zt]])
+    rhs = np.array([-(2 * c * lam * zb - c * zb ** 2), -(2 * c * lam * zt + c * zt ** 2)])
+    a, b = np.linalg.solve(A, rhs)
+    z = (np.arange(spec.nz) + 0.5) * h
+    P = np.zeros((spec.nz, spec.ny, spec.nx))
+    P[f0:f1] = (a + b * z[f0:f1] + c * z[f0:f1] ** 2)[:, None, None]
+    dzz = _dzz_from_rhs(orc, spec, P)
+    assert np.allclose(dzz[f0:f1], 2 * c, rtol=1e-9, atol=0)
+
+
+def test_free_surface_stencil_exact_one_sided(orc):
+    """Eq. (PbcFree): a quadratic with zero slope at the bottom face gives P'' exactly on that plane."""
+    spec = one_d([(W.FE, 7, W.EPS_FE, 0.0)], pbc=W.PBC_FREE)
+    f0, f1 = spec.fe_range()
+    h = spec.h
+    z = (np.arange(spec.nz) + 0.5) * h
+    c = 3.0e14
+    P = np.zeros((spec.nz, spec.ny, spec.nx))
+    P[f0:f1] = (0.02 + c * (z[f0:f1] - f0 * h) ** 2)[:, None, None]
+    dzz = _dzz_from_rhs(orc, spec, P)
+    assert np.allclose(dzz[f0:f1 - 1], 2 * c, rtol=1e-9, atol=0)
+
+
+def test_dz_phi_exact_for_quadratics(orc):
+    """The dphi/dz term of eq. (TDGL2) is exact for quadratic phi, inside and on the FE boundary planes."""
+    spec = W.layered(2, 2, 14, [(W.FE, 6, W.EPS_FE, 0.0), (W.DE, 4, W.EPS_SIO2, 0.0)])
+    s = spec.copy(alpha=0.0, beta=0.0, gamma=0.0, g11=0.0, g44=0.0)
+    z = (np.arange(s.nz) + 0.5) * s.h
+    # a kink at the FE/DE interface: the FE stencils must not reach across it
+    f0, f1 = s.fe_range()
+    zi = f0 * s.h
+    phi1 = 0.3 + 2e7 * (z - zi) + 4e15 * (z - zi) ** 2
+    phi1[z < zi] = 0.3 + 9e7 * (z[z < zi] - zi)
+    phi = np.broadcast_to(phi1[:, None, None], (s.nz, s.ny, s.nx)).copy()
+    f = orc.tdgl_rhs(s, np.zeros_like(phi), phi)
+    dphi = 2e7 + 8e15 * (z - zi)
+    assert np.allclose(-f[f0:f1, 0, 0] / s.Gamma, dphi[f0:f1], rtol=1e-9, atol=0)
+
+
+def test_in_plane_laplacian_periodic_eigenvalue(orc):
+    """Periodic 3-point Dxx/Dyy: cos modes are eigenvectors with eigenvalue (2 cos(2 pi m/n) - 2)/h^2."""
+    spec = W.layered(12, 10, 9, [(W.FE, 7, W.EPS_FE, 0.0)], pbc=W.PBC_FREE)
+    s = spec.copy(alpha=0.0, beta=0.0, gamma=0.0, g11=0.0, g44=2e-10)
+    i = np.arange(s.nx)
+    j = np.arange(s.ny)
+    mode = np.cos(2 * np.pi * 5 * i / s.nx)[None, :] * np.cos(2 * np.pi * 3 * j / s.ny + 0.4)[:, None]
+    P = np.zeros((s.nz, s.ny, s.nx))
+    f0, f1 = s.fe_range()
+    P[f0:f1] = 0.01 * mode
+    f = orc.tdgl_rhs(s, P, np.zeros_like(P))
+    lam = (2 * np.cos(2 * np.pi * 5 / s.nx) - 2 + 2 * np.cos(2 * np.pi * 3 / s.ny) - 2) / s.h ** 2
+    expect = s.Gamma * s.g44 * lam * P
+    assert np.allclose(f[f0:f1], expect[f0:f1], rtol=1e-9, atol=1e-9 * np.abs(expect).max())
+
+
+# ---------------------------------------------------------------- Poisson closed forms
+
+def test_T3_series_capacitor(orc):
+    """P = 0, FE 16 (eps 24) over DE 4 (eps 3.9), 1 V: piecewise-linear phi, interface at 0.60606... V."""
+    spec = W.mfim_small().copy(nx=4, ny=4)
+    kb, kt = spec.device_range()
+    P = np.zeros((spec.nz, spec.ny, spec.nx))
+    phi, info = orc.solve(spec, P, tol=1e-14)
+    tde, tfe = 4 * spec.h, 16 * spec.h
+    D = 1.0 / (tde / 3.9 + tfe / 24.0)       # eps0 cancels in the potentials
+    v_int = D * tde / 3.9
+    assert v_int == pytest.approx(0.606060606060606, rel=1e-13)
+    z = (np.arange(spec.nz) - kb + 0.5) * spec.h
+    expect = np.where(z < tde, D * z / 3.9, v_int + D * (z - tde) / 24.0)
+    dev = slice(kb, kt)
+    assert np.allclose(phi[dev], expect[dev][:, None, None], rtol=1e-12, atol=1e-13)
+    grad_fe = (phi[kt - 2, 0, 0] - phi[kt - 3, 0, 0]) / spec.h
+    assert grad_fe == pytest.approx(4.924242424242424e7, rel=1e-10)
+
+
+def test_T4_depolarisation_field(orc):
+    """Uniform P = 0.1 in the FE at V_app = 0 gives the series-capacitor depolarisation field
+    E_dep = -P / [eps0 (eps_fe + eps_DE t_fe/t_DE)] (Results, MFIM section)."""
+    spec = W.mfim_small().copy(nx=3, ny=3, v_top=0.0)
+    f0, f1 = spec.fe_range()
+    P = np.zeros((spec.nz, spec.ny, spec.nx))
+    P[f0:f1] = 0.1
+    phi, _ = orc.solve(spec, P, tol=1e-14)
+    e_dep = -0.1 / (EPS0 * (24.0 + 3.9 * 16 / 4))
+    assert e_dep == pytest.approx(-2.8520430994e8, rel=1e-9)
+    E = -(phi[f0 + 1:f1, 1, 1] - phi[f0:f1 - 1, 1, 1]) / spec.h
+    assert np.allclose(E, e_dep, rtol=1e-10)
+
+
+def steady_state_roots(V, eps_fe, eps_de, t_fe, t_de):
+    """Uniform-P steady state of the 1D MFIM: alpha P + beta P^3 + gamma P^5 + dphi/dz = 0 with
+    dphi/dz = P / [eps0 (eps_fe + eps_de t_fe/t_de)] + V / (t_fe + eps_fe t_de / eps_de)."""
+    a_eff = W.ALPHA + 1.0 / (EPS0 * (eps_fe + eps_de * t_fe / t_de))
+    c0 = V / (t_fe + eps_fe * t_de / eps_de)
+    r = np.roots([W.GAMMA_L, 0, W.BETA, 0, a_eff, c0])
+    return np.sort(r[np.abs(r.imag) < 1e-12].real)
+
+
+@pytest.mark.parametrize("V,P0,expect", [(0.0, 0.05, 0.109091218749878), (0.0, -0.05, -0.109091218749878),
+                                         (0.5, 0.0, -0.128901096511), (-0.5, 0.0, 0.128901096511)])
+def test_T5_coupled_steady_state(orc, V, P0, expect):
+    """FE 16 / Al2O3 4 (eps 10), free BC: TDGL + Poisson relaxes to the root of the quintic.
+    V_app > 0 drives P down (Results, MFIM section), fixing the sign of the dphi/dz term."""
+    h = W.H
+    roots = steady_state_roots(V, 24.0, 10.0, 16 * h, 4 * h)
+    target = roots[np.argmin(np.abs(roots - expect))]
+    assert target == pytest.approx(expect, rel=1e-9)
+    if V != 0.0:
+        assert len(roots) == 1                        # unique steady state at +-0.5 V
+    spec = W.layered(2, 2, 22, [(W.FE, 16, W.EPS_FE, 0.0), (W.DE, 4, W.EPS_AL2O3, 0.0)],
+                     pbc=W.PBC_FREE, v_top=V)
+    f0, f1 = spec.fe_range()
+    P = np.zeros((spec.nz, spec.ny, spec.nx))
+    P[f0:f1] = P0
+    if P0 == 0.0:
+        P[f0:f1] = 1e-6                               # unique root: any start converges
+    P, phi, _ = orc.run(spec, P, 2500, 6e-13, tol=1e-13)
+    assert np.allclose(P[f0:f1], target, rtol=1e-9, atol=0)
+
+
+def test_T6_manufactured_solution_second_order(orc):
+    """phi = linear + A sin(2 pi x/L) sin(2 pi y/L) sin(pi z/L) in one material with the matching
+    P = eps A k^2 (L/pi) S(x,y) cos(pi z/L) (eq. Poisson, rho = 0): second-order convergence."""
+    errs = []
+    for n in (8, 16, 32):
+        L = 8e-9
+        h = L / n
+        spec = W.StackSpec(n, n, n, h, np.full(n, W.FE, np.int32), np.full(n, 24.0),
+                           np.zeros(n), np.zeros(n), v_bottom=0.2, v_top=-0.3)
+        c = (np.arange(n) + 0.5) * h
+        z, y, x = np.meshgrid(c, c, c, indexing="ij")
+        A = 0.1
+        S = np.sin(2 * np.pi * x / L) * np.sin(2 * np.pi * y / L)
+        k2 = 2 * (2 * np.pi / L) ** 2 + (np.pi / L) ** 2
+        eps = EPS0 * 24.0
+        P = eps * A * k2 * (L / np.pi) * S * np.cos(np.pi * z / L)
+        exact = 0.2 + (-0.5) * z / L + A * S * np.sin(np.pi * z / L)
+        phi, _ = orc.solve(spec, P, tol=1e-13)
+        errs.append(np.sqrt(np.mean((phi - exact) ** 2)))
+    rates = np.log2(np.array(errs[:-1]) / np.array(errs[1:]))
+    assert np.all(rates > 1.9), (errs, rates)
+
+
+# ---------------------------------------------------------------- solver against direct solves
+
+def _dense_operator(orc, spec, phi_base, P):
+    """Jacobian columns of N by exact differencing of the affine (MFIM) operator."""
+    kb, kt = spec.device_range()
+    shape = (spec.nz, spec.ny, spec.nx)
+    f, N0, _, _ = orc.poisson_parts(spec, P, phi_base)
+    idx = [np.ravel_multi_index((k, j, i), shape) for k in range(kb, kt)
+           for j in range(spec.ny) for i in range(spec.nx)]
+    A = np.zeros((len(idx), len(idx)))
+    for col, c in enumerate(idx):
+        e = np.zeros(shape)
+        e.flat[c] = 1.0
+        _, N1, _, _ = orc.poisson_parts(spec, P, phi_base + e)
+        A[:, col] = (N1 - N0).ravel()[idx]
+    return A, f.ravel()[idx], idx
+
+
+def test_T7_T12_cg_newton_matches_dense_lu(orc):
+    """MFIM on 4x4x(8 device planes): Newton/CG root equals numpy.linalg.solve of the dense system."""
+    spec = W.layered(4, 4, 10, [(W.FE, 5, W.EPS_FE, 0.0), (W.DE, 3, W.EPS_SIO2, 0.0)], v_top=0.7)
+    P = W.random_P(spec, 3, amp=0.1)
+    A, f, idx = _dense_operator(orc, spec, np.zeros((spec.nz, spec.ny, spec.nx)), P)
+    assert np.allclose(A, A.T, rtol=1e-12, atol=0)            # symmetric ...
+    assert np.all(np.linalg.eigvalsh(A) > 0)                   # ... positive definite
+    x = np.linalg.solve(A, f)
+    phi, _ = orc.solve(spec, P, tol=1e-14)
+    assert np.allclose(phi.ravel()[idx], x, rtol=1e-11, atol=1e-12)
+
+
+def test_T7_mfism_newton_matches_dense_newton(orc):
+    """MFISM 2x2x(4 FE, 2 DE, 6 SC): root equals a dense Newton iteration started from the oracle's
+    linearisation, each step solved by numpy.linalg.solve, and sigma matches -d rho/d phi."""
+    spec = W.layered(2, 2, 14, [(W.FE, 4, W.EPS_FE, 0.0), (W.DE, 2, W.EPS_SIO2, 0.0),
+                                (W.SC, 6, W.EPS_SI, 1e24)], v_top=0.4, pbc=W.PBC_LAMBDA)
+    P = W.random_P(spec, 5, amp=0.05)
+    phi, _ = orc.solve(spec, P, tol=1e-14)
+    # Jacobian of N at the root by central differences must be L + diag(sigma)
+    kb, kt = spec.device_range()
+    f, N0, rho, sig = orc.poisson_parts(spec, P, phi)
+    dv = 1e-7
+    _, Np, rp, _ = orc.poisson_parts(spec, P, phi + dv)
+    _, Nm, rm, _ = orc.poisson_parts(spec, P, phi - dv)
+    drho = (rp - rm) / (2 * dv)
+    sc = spec.plane_mat == W.SC
+    assert np.allclose(-drho[sc], sig[sc], rtol=1e-6)
+    # the root satisfies the equations to round-off
+    assert np.abs((f - N0)[kb:kt]).max() <= 1e-12 * np.abs(f[kb:kt]).max()
+
+
+def test_T8_lateral_reductions(orc):
+    """x,y-uniform inputs stay uniform and equal the 1x1 run; y-uniform inputs equal the ny = 1 run
+    (the paper's 2D reduction, Results MFIM section)."""
+    base = W.layered(8, 6, 26, [(W.FE, 12, W.EPS_FE, 0.0), (W.DE, 4, W.EPS_AL2O3, 0.0),
+                                (W.SC, 6, W.EPS_SI, 1e24)], v_top=0.8)
+    f0, f1 = base.fe_range()
+    rng = np.random.default_rng(7)
+    pz = rng.uniform(-0.05, 0.05, f1 - f0)
+    P3 = np.zeros((base.nz, base.ny, base.nx))
+    P3[f0:f1] = pz[:, None, None]
+    one = base.copy(nx=1, ny=1)
+    P1 = np.zeros((one.nz, 1, 1))
+    P1[f0:f1, 0, 0] = pz
+    Pa, pa, _ = orc.run(base, P3, 5, 1e-13, tol=1e-14)
+    Pb, pb, _ = orc.run(one, P1, 5, 1e-13, tol=1e-14)
+    assert np.allclose(Pa, Pb[:, :, :1], rtol=1e-12, atol=1e-15)
+    assert np.allclose(pa, pb[:, :, :1], rtol=1e-11, atol=1e-13)
+    # 2D: uniform along y
+    pxz = rng.uniform(-0.05, 0.05, (f1 - f0, base.nx))
+    P3 = np.zeros((base.nz, base.ny, base.nx))
+    P3[f0:f1] = pxz[:, None, :]
+    two = base.copy(ny=1)
+    P2 = np.zeros((two.nz, 1, two.nx))
+    P2[f0:f1, 0, :] = pxz
+    Pa, pa, _ = orc.run(base, P3, 5, 1e-13, tol=1e-14)
+    Pb, pb, _ = orc.run(two, P2, 5, 1e-13, tol=1e-14)
+    assert np.allclose(Pa, np.broadcast_to(Pb, Pa.shape), rtol=1e-11, atol=1e-15)
+    assert np.allclose(pa, np.broadcast_to(pb, pa.shape), rtol=1e-11, atol=1e-13)
+
+
+def test_T9_symmetries(orc):
+    """MFIM is odd under (P, V) -> (-P, -V); periodic shifts and the x-mirror commute with a step."""
+    spec = W.mfim_small().copy(nx=10, ny=8)
+    P0 = W.random_P(spec, 11, amp=0.05)
+    Pa, pa, _ = orc.run(spec, P0, 4, 1e-13, tol=1e-14)
+    Pb, pb, _ = orc.run(spec.copy(v_top=-1.0), -P0, 4, 1e-13, tol=1e-14)
+    assert np.allclose(Pb, -Pa, rtol=1e-12, atol=1e-16)
+    assert np.allclose(pb, -pa, rtol=1e-10, atol=1e-12)
+    Ps, ps, _ = orc.run(spec, np.roll(P0, (3, 5), axis=(1, 2)), 4, 1e-13, tol=1e-14)
+    assert np.allclose(Ps, np.roll(Pa, (3, 5), axis=(1, 2)), rtol=1e-12, atol=1e-16)
+    assert np.allclose(ps, np.roll(pa, (3, 5), axis=(1, 2)), rtol=1e-10, atol=1e-12)
+    Pm, pm, _ = orc.run(spec, P0[:, :, ::-1].copy(), 4, 1e-13, tol=1e-14)
+    assert np.allclose(Pm, Pa[:, :, ::-1], rtol=1e-12, atol=1e-16)
+    assert np.allclose(pm, pa[:, :, ::-1], rtol=1e-10, atol=1e-12)
+
+
+# ---------------------------------------------------------------- semiconductor charge
+
+def test_T10_neutrality(orc):
+    """P = 0 and V = 0 in the MFISM stack: phi = 0 and rho = 0 everywhere (neutral bulk reference)."""
+    spec = W.mfism_large().copy(nx=4, ny=4, v_top=0.0)
+    P = np.zeros((spec.nz, spec.ny, spec.nx))
+    phi, info = orc.solve(spec, P, tol=1e-14)
+    assert np.abs(phi).max() == 0.0
+    _, _, rho, _ = orc.poisson_parts(spec, P, phi)
+    assert np.abs(rho).max() == 0.0
+
+
+def mos_field_squared(psi, p0, n0, VT, eps):
+    """Textbook first integral of the 1D Poisson-Boltzmann equation in a neutral-bulk semiconductor
+    (eq. MaxBolt_ne_np): (dpsi/dz)^2 = 2 e VT/eps [p0(e^{-u} + u - 1) + n0(e^{u} - u - 1)], u = psi/VT."""
+    u = psi / VT
+    return 2 * QE * VT / eps * (p0 * (np.exp(-u) + u - 1) + n0 * (np.exp(u) - u - 1))
+
+
+@pytest.mark.parametrize("vg,hs", [(0.35, (0.5e-9, 0.25e-9)), (-0.5, (0.125e-9, 0.0625e-9))])
+def test_T10_mos_first_integral(orc, vg, hs):
+    """1D metal / SiO2 / thick p-Si / metal: the discrete field obeys the Poisson-Boltzmann first
+    integral in depletion (+V) and accumulation (-V); the mismatch shrinks at second order in h."""
+    T = 300.0
+    VT = KB * T / QE
+    Na, ni = 1e24, 1e16
+    p0 = Na / 2 + np.sqrt(Na ** 2 / 4 + ni ** 2)
+    n0 = ni ** 2 / p0
+    eps = EPS0 * W.EPS_SI
+    errs = []
+    for h in hs:
+        nsc, nde = int(round(120e-9 / h)), int(round(2e-9 / h))
+        spec = W.layered(1, 1, nsc + nde + 2, [(W.DE, nde, W.EPS_SIO2, 0.0), (W.SC, nsc, W.EPS_SI, Na)],
+                         h=h, v_top=vg, ni=ni, T=T)
+        P = np.zeros((spec.nz, 1, 1))
+        phi, _ = orc.solve(spec, P, tol=1e-14)
+        kb = spec.device_range()[0]
+        ps = phi[kb:kb + nsc, 0, 0]
+        k = np.arange(1, nsc - 1)
+        grad = (ps[k + 1] - ps[k - 1]) / (2 * h)
+        z = (k + 0.5) * h
+        sel = (z > 40e-9) & (np.abs(ps[k]) > 2 * VT)     # away from the back contact
+        assert sel.sum() > 10
+        rel = np.abs(grad[sel] ** 2 / mos_field_squared(ps[k][sel], p0, n0, VT, eps) - 1)
+        errs.append(rel.max())
+    assert errs[0] < 0.05 and errs[1] < errs[0] / 3.0, errs
