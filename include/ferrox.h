@@ -1,0 +1,181 @@
+/*
+ * ferrox.h -- C ABI of the MI355X TDGL + Poisson time-step library.
+ *
+ * The library advances the coupled ferroelectric phase-field model of
+ * FerroX (arXiv 2210.15668, Methods): the polarisation P (z-component
+ * only, as in the Results overview) by the time-dependent Ginzburg-Landau
+ * equation, eq. (TDGL2), and the electric potential phi by the Poisson
+ * equation with spatially varying permittivity, eq. (Poisson), whose
+ * semiconductor charge is eq. (rho) with the Maxwell-Boltzmann carriers of
+ * eq. (MaxBolt_ne_np).  The time scheme is the paper's Step 0 / Step 1a /
+ * Step 1b (Numerical Approach): P^{n+1} = P^n + dt f(P^n, phi^n), then
+ * phi^{n+1} solved for P^{n+1} starting from phi^n.
+ *
+ * Conventions shared by every entry point
+ *  - SI units.  Grid of nx*ny*nz cubic cells of edge h; cell (i,j,k) lives at
+ *    index (k*ny + j)*nx + i (z-major, x fastest); k = 0 is the back contact,
+ *    k = nz-1 the gate.  Periodic in x and y; Dirichlet in z (section
+ *    "Electrical boundary conditions").
+ *  - Each z-plane carries one material (fx_material).  Metal planes must form
+ *    contiguous runs at the two z-ends; the planes between them are the
+ *    device, whose bottom face is held at v_bottom and top face at v_top
+ *    (V_app = v_top - v_bottom).  The ferroelectric must be one contiguous run
+ *    of at least 3 planes.
+ *  - Device pointers ("d_") are HIP device addresses on the current device;
+ *    host pointers ("h_") are ordinary process memory.  All work is enqueued
+ *    on the stream given to init_stack (a hipStream_t passed as void*;
+ *    NULL = the null stream).  Calls return after enqueueing, except where a
+ *    host-visible decision is needed (poisson_solve and run_steps read the
+ *    residual norm back once per multigrid cycle and therefore synchronise
+ *    the stream).
+ *  - Errors are reported by fx_status; no exception crosses the ABI.
+ *    last_error() returns a message for the most recent failure on the
+ *    calling thread.  A stack is not thread-safe: use it from one thread.
+ *  - The library allocates no device memory after init_stack: the caller
+ *    passes the fields and one workspace buffer.  init_stack allocates a
+ *    small pinned host buffer for norm read-back and host-side tables.
+ */
+#ifndef FERROX_H
+#define FERROX_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    FX_OK = 0,
+    FX_EINVAL = 1,      /* invalid descriptor or argument                               */
+    FX_ENOMEM = 2,      /* workspace too small, or host allocation failed               */
+    FX_EDEVICE = 3,     /* a HIP runtime call failed                                    */
+    FX_ENOCONV = 4,     /* max_cycles reached before ||r|| <= tol_rel ||f||              */
+    FX_ENONFINITE = 5,  /* residual became NaN/Inf                                      */
+    FX_ESTATE = 6       /* call not valid in the stack's current state                  */
+} fx_status;
+
+typedef enum { FX_MAT_METAL = 0, FX_MAT_FE = 1, FX_MAT_DE = 2, FX_MAT_SC = 3 } fx_material;
+
+/* Polarisation surface condition at both ferroelectric faces, eqs. (Pbc),
+ * (PbcFree), (PbcDir): lambda dP/dn + P = 0 with outward normal n. */
+typedef enum { FX_PBC_FREE = 0, FX_PBC_ZERO = 1, FX_PBC_LAMBDA = 2 } fx_pbc;
+
+/* FP64: every multigrid level in double.  MIXED: the multigrid correction
+ * (smoothing, restriction, prolongation, coarse levels) in float inside a
+ * double-precision defect-correction loop (residual, carriers, update). */
+typedef enum { FX_PREC_FP64 = 0, FX_PREC_MIXED = 1 } fx_precision;
+
+enum { FX_FIELD_P = 0, FX_FIELD_PHI = 1 };
+
+typedef struct fx_stack fx_stack;
+
+/* Problem statement (Table 1 and Methods of the paper).  Host arrays are
+ * read during init_stack only. */
+typedef struct {
+    int nx, ny, nz;              /* cells                                                   */
+    double h;                    /* cell edge [m]                                           */
+    const int *plane_mat;        /* nz fx_material codes, k = 0 bottom                      */
+    const double *plane_eps_r;   /* nz relative permittivities                              */
+    const double *plane_Na;      /* nz acceptor densities [m^-3] (semiconductor planes)     */
+    const double *plane_Nd;      /* nz donor densities [m^-3] (semiconductor planes)        */
+    double alpha, beta, gamma;   /* Landau f = alpha/2 P^2 + beta/4 P^4 + gamma/6 P^6, eq. (free) */
+    double g11, g44;             /* gradient coefficients (z; x and y), eq. (grad)         */
+    double Gamma;                /* kinetic coefficient, eq. (TDGL1)                        */
+    int pbc;                     /* fx_pbc                                                  */
+    double lambda;               /* extrapolation length [m] for FX_PBC_LAMBDA              */
+    double ni, T;                /* intrinsic density [m^-3], temperature [K]               */
+    double v_bottom, v_top;      /* contact potentials [V]                                  */
+    double tol_rel;              /* stop when ||f - N(phi)||_2 <= tol_rel ||f||_2           */
+    int max_cycles;              /* multigrid cycles allowed per Poisson solve              */
+    int prec;                    /* fx_precision                                            */
+    int flags;                   /* reserved, must be 0                                     */
+} fx_stack_desc;
+
+typedef struct {
+    int cycles;                  /* V-cycles (= Newton updates) used                        */
+    int status;                  /* fx_status of the solve                                  */
+    double res_norm;             /* final ||f - N(phi)||_2 (scaled by h^2/eps0)             */
+    double rhs_norm;             /* ||f||_2 (same scaling)                                  */
+} fx_solve_info;
+
+typedef struct {
+    int steps_done;
+    int total_cycles;            /* V-cycles summed over the steps                           */
+    int max_cycles_step;         /* largest per-step cycle count                             */
+    double last_res_rel;         /* final relative residual of the last step                 */
+} fx_run_info;
+
+/* Bytes of device workspace init_stack needs for this descriptor (0 if invalid). */
+size_t stack_workspace_bytes(const fx_stack_desc *desc);
+
+/*
+ * Validate desc, lay out the multigrid hierarchy in d_ws, upload the
+ * per-plane tables, and run Step 0: phi := 0 on the device, then solve the
+ * Poisson problem for the P held in d_P (Numerical Approach, Step 0).
+ *   d_P, d_phi : caller-owned device arrays of nx*ny*nz doubles.  d_P holds
+ *                P^0 (read; entries off ferroelectric planes are ignored and
+ *                treated as zero).  d_phi receives phi^0; metal planes hold
+ *                their contact potential.  Both must outlive the stack, and
+ *                after every call below they hold the stack's current P and
+ *                phi.
+ *   d_ws       : caller-owned device buffer of at least
+ *                stack_workspace_bytes(desc) bytes, 256-byte aligned.
+ *   stream     : hipStream_t (as void*) all work is enqueued on.
+ *   out        : receives the stack handle (host object owned by the library,
+ *                released by destroy_stack).
+ * Returns FX_EINVAL for an invalid descriptor (sizes < 1, h/Gamma/T <= 0,
+ * gamma <= 0, lambda < 0, metal planes not at the ends, ferroelectric not one
+ * run of >= 3 planes), FX_ENOMEM if ws_bytes is too small, FX_ENOCONV /
+ * FX_ENONFINITE if Step 0 fails (the stack is still created and returned).
+ */
+fx_status init_stack(const fx_stack_desc *desc, double *d_P, double *d_phi, void *d_ws,
+                     size_t ws_bytes, void *stream, fx_stack **out);
+
+/*
+ * Step 1a of the time scheme: P <- P + dt f(P, phi) with eq. (TDGL2), the
+ * current phi held fixed.  phi is not touched.  FX_EINVAL if dt <= 0.
+ */
+fx_status tdgl_step(fx_stack *s, double dt);
+
+/*
+ * Solve the Poisson problem, eq. (Poisson) with eq. (rho), for the current P
+ * with gate potential v_top, starting from the current phi (Step 1b warm
+ * start).  Stops when ||f - N(phi)||_2 <= tol_rel ||f||_2, f the
+ * right-hand side of the discrete system.  info may be NULL.
+ * FX_ENOCONV: max_cycles reached, phi holds the last iterate.
+ * FX_ENONFINITE: the residual is not finite; phi is restored to its value
+ * at entry.
+ */
+fx_status poisson_solve(fx_stack *s, double v_top, fx_solve_info *info);
+
+/*
+ * nsteps steps of Step 1a + Step 1b.  h_v_top_sched: host array of nsteps
+ * gate potentials, entry n used for the solve that produces phi^{n+1}; NULL
+ * keeps the current v_top.  Stops at the first failing solve and returns its
+ * status (info->steps_done counts completed steps).  info may be NULL.
+ */
+fx_status run_steps(fx_stack *s, int nsteps, double dt, const double *h_v_top_sched,
+                    fx_run_info *info);
+
+/* Copy the current P or phi (FX_FIELD_*) to / from host memory of
+ * nx*ny*nz doubles.  get_field synchronises the stream.  set_field of P
+ * zeroes entries off ferroelectric planes; set_field of phi rewrites the
+ * metal planes with their contact potentials. */
+fx_status get_field(fx_stack *s, int which, double *h_out);
+fx_status set_field(fx_stack *s, int which, const double *h_in);
+
+/* Number of multigrid levels and the sizes of level l (for diagnostics). */
+int stack_num_levels(const fx_stack *s);
+fx_status stack_level_shape(const fx_stack *s, int level, int *nx, int *ny, int *nz);
+
+/* Release the stack handle (not the caller's device buffers). */
+fx_status destroy_stack(fx_stack *s);
+
+/* Message of the most recent failing call on this thread ("" if none). */
+const char *last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FERROX_H */

@@ -1,0 +1,205 @@
+"""Thin ctypes binding of libferrox.so (the HIP library); argument marshalling only.
+
+Every step of the time step runs in the library's HIP kernels.  PyTorch is
+used only to own device memory (the P and phi fields and the workspace) and
+to supply the HIP stream.  If the library is missing this module raises: there
+is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Sequence
+
+import numpy as np
+
+from . import workloads as W
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libferrox.so")
+
+FX_OK, FX_EINVAL, FX_ENOMEM, FX_EDEVICE, FX_ENOCONV, FX_ENONFINITE, FX_ESTATE = range(7)
+FIELD_P, FIELD_PHI = 0, 1
+_STATUS = {0: "FX_OK", 1: "FX_EINVAL", 2: "FX_ENOMEM", 3: "FX_EDEVICE", 4: "FX_ENOCONV",
+           5: "FX_ENONFINITE", 6: "FX_ESTATE"}
+
+
+class FerroxError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{_STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class StackDesc(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int), ("ny", ctypes.c_int), ("nz", ctypes.c_int),
+                ("h", ctypes.c_double),
+                ("plane_mat", ctypes.POINTER(ctypes.c_int)),
+                ("plane_eps_r", ctypes.POINTER(ctypes.c_double)),
+                ("plane_Na", ctypes.POINTER(ctypes.c_double)),
+                ("plane_Nd", ctypes.POINTER(ctypes.c_double)),
+                ("alpha", ctypes.c_double), ("beta", ctypes.c_double), ("gamma", ctypes.c_double),
+                ("g11", ctypes.c_double), ("g44", ctypes.c_double), ("Gamma", ctypes.c_double),
+                ("pbc", ctypes.c_int), ("lam", ctypes.c_double),
+                ("ni", ctypes.c_double), ("T", ctypes.c_double),
+                ("v_bottom", ctypes.c_double), ("v_top", ctypes.c_double),
+                ("tol_rel", ctypes.c_double), ("max_cycles", ctypes.c_int),
+                ("prec", ctypes.c_int), ("flags", ctypes.c_int)]
+
+
+class SolveInfo(ctypes.Structure):
+    _fields_ = [("cycles", ctypes.c_int), ("status", ctypes.c_int),
+                ("res_norm", ctypes.c_double), ("rhs_norm", ctypes.c_double)]
+
+
+class RunInfo(ctypes.Structure):
+    _fields_ = [("steps_done", ctypes.c_int), ("total_cycles", ctypes.c_int),
+                ("max_cycles_step", ctypes.c_int), ("last_res_rel", ctypes.c_double)]
+
+
+# (name, restype, argtypes) of every entry point declared in include/ferrox.h
+_vp, _dp, _ip = ctypes.c_void_p, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int)
+_D = ctypes.POINTER(StackDesc)
+SIGNATURES = [
+    ("stack_workspace_bytes", ctypes.c_size_t, [_D]),
+    ("init_stack", ctypes.c_int, [_D, _vp, _vp, _vp, ctypes.c_size_t, _vp, ctypes.POINTER(_vp)]),
+    ("tdgl_step", ctypes.c_int, [_vp, ctypes.c_double]),
+    ("poisson_solve", ctypes.c_int, [_vp, ctypes.c_double, ctypes.POINTER(SolveInfo)]),
+    ("run_steps", ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_double, _dp, ctypes.POINTER(RunInfo)]),
+    ("get_field", ctypes.c_int, [_vp, ctypes.c_int, _dp]),
+    ("set_field", ctypes.c_int, [_vp, ctypes.c_int, _dp]),
+    ("stack_num_levels", ctypes.c_int, [_vp]),
+    ("stack_level_shape", ctypes.c_int, [_vp, ctypes.c_int, _ip, _ip, _ip]),
+    ("destroy_stack", ctypes.c_int, [_vp]),
+    ("last_error", ctypes.c_char_p, []),
+]
+
+_lib = None
+
+
+def lib():
+    """Load libferrox.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with __graft_entry__.build() "
+                              "(there is no CPU fallback)")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, res, args in SIGNATURES:
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _check(status: int):
+    if status != FX_OK:
+        raise FerroxError(status, lib().last_error().decode())
+
+
+class _DescHolder:
+    def __init__(self, spec: W.StackSpec):
+        self.mat = np.ascontiguousarray(spec.plane_mat, np.int32)
+        self.eps = np.ascontiguousarray(spec.plane_eps_r, np.float64)
+        self.na = np.ascontiguousarray(spec.plane_Na, np.float64)
+        self.nd = np.ascontiguousarray(spec.plane_Nd, np.float64)
+        dp = lambda a: a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        self.d = StackDesc(spec.nx, spec.ny, spec.nz, spec.h,
+                           self.mat.ctypes.data_as(ctypes.POINTER(ctypes.c_int)),
+                           dp(self.eps), dp(self.na), dp(self.nd),
+                           spec.alpha, spec.beta, spec.gamma, spec.g11, spec.g44, spec.Gamma,
+                           spec.pbc, spec.lam, spec.ni, spec.T, spec.v_bottom, spec.v_top,
+                           spec.tol_rel, spec.max_cycles, spec.prec, 0)
+
+
+def workspace_bytes(spec: W.StackSpec) -> int:
+    h = _DescHolder(spec)
+    return int(lib().stack_workspace_bytes(ctypes.byref(h.d)))
+
+
+class Stack:
+    """One device stack: P, phi and the workspace live in torch CUDA tensors.
+
+    Construction runs Step 0 (phi for P^0).  ``P`` and ``phi`` are float64
+    tensors of shape (nz, ny, nx) that always hold the current state.
+    """
+
+    def __init__(self, spec: W.StackSpec, P0, device: str = "cuda:0", stream=None, check_init: bool = True):
+        import torch
+        self._torch = torch
+        self.spec = spec
+        self.device = torch.device(device)
+        shape = (spec.nz, spec.ny, spec.nx)
+        if isinstance(P0, np.ndarray):
+            self.P = torch.from_numpy(np.ascontiguousarray(P0, np.float64)).to(self.device)
+        else:
+            self.P = P0.to(device=self.device, dtype=torch.float64).contiguous()
+        assert tuple(self.P.shape) == shape, (self.P.shape, shape)
+        self.phi = torch.zeros(shape, dtype=torch.float64, device=self.device)
+        self._desc = _DescHolder(spec)
+        nbytes = int(lib().stack_workspace_bytes(ctypes.byref(self._desc.d)))
+        if nbytes == 0:
+            raise FerroxError(FX_EINVAL, lib().last_error().decode())
+        self.ws = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        self._h = ctypes.c_void_p()
+        st = lib().init_stack(ctypes.byref(self._desc.d), self.P.data_ptr(), self.phi.data_ptr(),
+                              self.ws.data_ptr(), nbytes, self.stream.cuda_stream, ctypes.byref(self._h))
+        if not self._h.value:
+            _check(st)
+        self.init_status = st
+        if check_init:
+            _check(st)
+
+    # ---------------------------------------------------------------- API
+    def tdgl_step(self, dt: float):
+        _check(lib().tdgl_step(self._h, dt))
+
+    def poisson_solve(self, v_top: Optional[float] = None, check: bool = True) -> SolveInfo:
+        info = SolveInfo()
+        v = self.spec.v_top if v_top is None else v_top
+        st = lib().poisson_solve(self._h, v, ctypes.byref(info))
+        if check:
+            _check(st)
+        return info
+
+    def run_steps(self, nsteps: int, dt: float, v_sched: Optional[Sequence[float]] = None,
+                  check: bool = True) -> RunInfo:
+        info = RunInfo()
+        vs = None
+        if v_sched is not None:
+            self._vs = np.ascontiguousarray(v_sched, np.float64)
+            assert len(self._vs) >= nsteps
+            vs = self._vs.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        st = lib().run_steps(self._h, nsteps, dt, vs, ctypes.byref(info))
+        if check:
+            _check(st)
+        return info
+
+    def get(self, which: int) -> np.ndarray:
+        out = np.empty((self.spec.nz, self.spec.ny, self.spec.nx), np.float64)
+        _check(lib().get_field(self._h, which, out.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
+        return out
+
+    def set(self, which: int, arr: np.ndarray):
+        a = np.ascontiguousarray(arr, np.float64)
+        _check(lib().set_field(self._h, which, a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
+
+    def levels(self):
+        out = []
+        for l in range(lib().stack_num_levels(self._h)):
+            a, b, c = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+            _check(lib().stack_level_shape(self._h, l, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)))
+            out.append((a.value, b.value, c.value))
+        return out
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib().destroy_stack(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
