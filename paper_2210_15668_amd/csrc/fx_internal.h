@@ -15,6 +15,21 @@ constexpr double kEps0 = 8.8541878128e-12;
 // Per-plane flag bits of the finest (device) level.
 enum : int { PF_SC = 1, PF_P = 2 };
 
+constexpr int kMaxLevels = 24;
+
+// Device-side state of one Poisson solve.  done: 0 running, 1 converged,
+// 2 non-finite residual, 3 cycle budget exhausted.  Kernels of a cycle
+// return immediately once done != 0, so cycles can be enqueued ahead of the
+// host's convergence check.
+struct SolveCtrl {
+    int done;
+    int cycles;
+    int max_cycles;
+    int pad;
+    double tol2;       // tol_rel^2
+    double rn2, fn2;   // ||r||^2, ||f||^2 of the latest residual (scaled units)
+};
+
 // --------------------------------------------------------------------- TDGL
 struct TdglArgs {
     int nx, ny, f0, f1;          // ferroelectric planes [f0, f1) of the full grid
@@ -28,74 +43,90 @@ struct TdglArgs {
 };
 void launch_tdgl(const TdglArgs &a, hipStream_t st);
 
-// ------------------------------------------------- fine-level residual (FP64)
-// r = s (f - N(phi)) on the device slab (planes kb .. kb+nzd-1 of the full
-// grid), sigma = s e (p + n) / VT on the semiconductor planes; s = h^2/eps0.
-// Coefficient tables are in the same scaled units.  Per-block partial sums
-// of r^2 and (s f)^2 go to part[2*b], part[2*b+1].
-template <typename T>
-struct ResArgs {
-    int nx, ny, nzd, kb;
-    double v_b, v_t;
-    double p_scale;              // h / eps0   (scale * (1/h) for the bound-charge term)
-    double rho_scale;            // h^2 / eps0
-    double vt_inv;               // 1 / VT
-    double sig_scale;            // (h^2/eps0) * e / VT
-    const double *cxy, *czm, *czp;   // scaled, per device plane
-    const double *wl, *wr;           // P face weights of the face above plane k
-    const double *p0e, *n0e;         // e * p0, e * n0 per device plane
-    const int *pflags;
-    const double *phi;               // full grid
-    const double *P;                 // full grid
-    T *r;
-    T *sig;
-    int sig_lo, sig_hi;
-    double *part;
-};
-template <typename T> void launch_residual(const ResArgs<T> &a, hipStream_t st, int *nblocks);
-
-// --------------------------------------------------------------- multigrid
+// One multigrid level as the kernels see it.  Storage of e and r: with rb
+// set (nx even, ny even or 1: a proper red/black colouring under periodic
+// wrap) the cells of colour (i+j+k)&1 == 0 come first, then colour 1, each
+// in z-major row order; otherwise plain z-major order.  sig holds planes
+// [sig_lo, sig_hi) in the same arrangement.  Every level has fewer than
+// 2^31 cells, so all indices are 32-bit.
 template <typename T>
 struct LevelArgs {
-    int nx, ny, nz;
-    const T *cxy, *czm, *czp, *dg;   // per plane
+    int nx, ny, nz, rb;
+    const T *cxy, *czm, *czp, *dg;   // per-plane coefficients (scaled by h^2/eps0)
     T *e;
     T *r;
     T *sig;
     int sig_lo, sig_hi;
 };
 
-template <typename T> void launch_smooth(const LevelArgs<T> &L, int color, int zero_init, hipStream_t st);
-
+// Transfer tables between a level and the next coarser one.
 template <typename T>
-struct RestrictArgs {
-    LevelArgs<T> f;                  // fine level (e, r, sig read)
-    LevelArgs<T> c;                  // coarse level (r, sig written)
-    const int *fthick;               // fine plane thickness (finest-level planes)
-    const int *cthick;
+struct XferArgs {
     const int *cks, *ccnt;           // coarse plane K covers fine planes cks[K] .. cks[K]+ccnt[K]-1
-    int xy;                          // 1 if x and y are coarsened
+    const int *fthick, *cthick;      // plane thickness in finest planes
+    const int *pka, *pkb;            // coarse planes interpolated into each fine plane (pkb -1: contact)
+    const T *pwa, *pwb;
+    int xy;                          // x and y halved
 };
-template <typename T> void launch_restrict(const RestrictArgs<T> &a, hipStream_t st);
 
+// ------------------------------------------------- fine-level residual (FP64)
+// phi_out = phi_in + clip(e) (when e is given) or 2 phi_in - phi_prev (when
+// phi_prev is given: linear extrapolation in time), then r = s (f - N(phi_out))
+// on the device slab and sigma = s e (p + n) / VT on semiconductor planes;
+// s = h^2/eps0.  Per-tile partial sums of r^2 and (s f)^2.
 template <typename T>
-struct ProlongArgs {
-    LevelArgs<T> f;                  // fine level e updated
-    LevelArgs<T> c;                  // coarse level e read
-    const int *ka, *kb;              // coarse planes for each fine plane (kb = -1: boundary, value 0)
-    const T *wa, *wb;
-    int xy;
+struct ResArgs {
+    int nx, ny, nzd, kb;
+    double v_b, v_t;
+    double p_scale;              // h / eps0
+    double rho_scale;            // h^2 / eps0
+    double vt_inv;               // 1 / VT
+    double sig_scale;            // (h^2/eps0) / VT
+    double dmax;                 // Newton update clip on semiconductor planes
+    const double *cxy, *czm, *czp;   // scaled, per device plane
+    const double *wl, *wr;           // P face weights of the face above plane k
+    const double *p0e, *n0e;         // e * p0, e * n0 per device plane
+    const int *pflags;
+    const double *phi_in;            // full grid
+    const double *phi_prev;          // full grid or nullptr: evaluate at 2 phi_in - phi_prev
+    double *phi_out;                 // full grid (written when e or phi_prev is given)
+    const T *e;                      // level-0 correction or nullptr
+    const double *P;                 // full grid
+    LevelArgs<T> L0;                 // r and sig written
+    double *part;
+    const SolveCtrl *ctrl;
 };
-template <typename T> void launch_prolong(const ProlongArgs<T> &a, hipStream_t st);
+template <typename T> int launch_residual(const ResArgs<T> &a, hipStream_t st);
 
-template <typename T> void launch_bottom(const LevelArgs<T> &L, int sweeps, hipStream_t st);
+template <typename T> void launch_smooth(const LevelArgs<T> &L, int color, int zero_init, const SolveCtrl *ctrl,
+                                         hipStream_t st);
+template <typename T> void launch_restrict(const LevelArgs<T> &F, const LevelArgs<T> &C, const XferArgs<T> &X,
+                                           const SolveCtrl *ctrl, hipStream_t st);
+template <typename T> void launch_prolong(const LevelArgs<T> &F, const LevelArgs<T> &C, const XferArgs<T> &X,
+                                          const SolveCtrl *ctrl, hipStream_t st);
 
-// phi[kb*nxy + c] += clip(e[c]) on the device slab; clip to +-dmax on planes flagged PF_SC.
+// All levels from the first one handed over down to the coarsest, in one
+// workgroup with every level resident in LDS: lv[0] is the handed-over level
+// (its r and sig are copied in from r_in / sig_in, its correction copied out
+// to e_out), xf[l] links lv[l] and lv[l+1].  off_* are byte offsets of each
+// level's arrays in the dynamic LDS allocation of lds_bytes.
 template <typename T>
-void launch_update(double *phi, const T *e, int nx, int ny, int nzd, int kb, const int *pflags, double dmax,
-                   hipStream_t st);
+struct CoarseArgs {
+    int nlev, nu1, nu2, bottom_sweeps;
+    int lds_bytes;
+    LevelArgs<T> lv[kMaxLevels];
+    XferArgs<T> xf[kMaxLevels];
+    int off_e[kMaxLevels], off_r[kMaxLevels], off_s[kMaxLevels];
+    const T *r_in;
+    const T *sig_in;
+    T *e_out;
+};
+template <typename T> void launch_coarse(const CoarseArgs<T> *dev_args, int lds_bytes, const SolveCtrl *ctrl,
+                                         hipStream_t st);
+constexpr int kCoarseLdsBytes = 64 * 1024;
 
-void launch_reduce_norms(const double *part, int nblocks, double *out, hipStream_t st);
+void launch_reduce(const double *part, int nparts, SolveCtrl *ctrl, int count_cycle, hipStream_t st);
+void launch_ctrl_reset(SolveCtrl *ctrl, int max_cycles, double tol2, hipStream_t st);
 void launch_fill(double *x, size_t n, double v, hipStream_t st);
 
 }  // namespace fx

@@ -1,9 +1,13 @@
 // HIP kernels of the TDGL + Poisson time step (gfx950, wave64).
 //
-// Layout: every field is z-major, x fastest, so a wave of 64 lanes along x
-// reads 512 contiguous bytes (FP64).  Launches use 64x4 blocks (one wave per
-// x-row) over (x, y) and one grid layer per z-plane, so all per-plane
-// coefficients are wave-uniform scalar loads.
+// Layout: fields are z-major with x fastest.  Multigrid levels with an even
+// x-extent store their cells split by red/black colour (see LevelArgs), so
+// that each half-sweep of the Gauss-Seidel smoother streams two contiguous
+// arrays instead of touching every other element.  Workgroups are 64x4
+// threads (one wave per row); large launches use a 1D grid whose block
+// index is remapped so that each of the 8 XCDs walks one contiguous range of
+// tiles (consecutive planes and rows), keeping stencil neighbours in that
+// XCD's L2.
 #include "fx_internal.h"
 
 namespace fx {
@@ -16,24 +20,150 @@ constexpr int BY = 4;
 __device__ __forceinline__ int wrap_p(int i, int n) { return i + 1 == n ? 0 : i + 1; }
 __device__ __forceinline__ int wrap_m(int i, int n) { return i == 0 ? n - 1 : i - 1; }
 
-// Sum over a 256-thread block (4 waves); result valid in thread 0.
+struct Tile {
+    int tx, ty, k, id;
+    bool ok;
+};
+
+// Tile of a 1D launch whose block count is a multiple of 8: XCD x (= block
+// index mod 8 under round-robin dispatch) gets tiles [x*nb/8, (x+1)*nb/8).
+__device__ __forceinline__ Tile tile_of(int ntx, int nty, int nz) {
+    const int nb = gridDim.x, b = blockIdx.x;
+    const int t = (b & 7) * (nb >> 3) + (b >> 3);
+    Tile r;
+    r.id = t;
+    r.ok = t < ntx * nty * nz;
+    r.tx = t % ntx;
+    const int q = t / ntx;
+    r.ty = q % nty;
+    r.k = q / nty;
+    return r;
+}
+
+int tiles(int nxw, int ny, int nz) { return ((nxw + BX - 1) / BX) * ((ny + BY - 1) / BY) * nz; }
+dim3 tile_grid(int ntiles) { return dim3((ntiles + 7) / 8 * 8); }
+
+template <typename T>
+__device__ __forceinline__ int cidx(const LevelArgs<T> &L, int i, int j, int k) {
+    const int lin = (k * L.ny + j) * L.nx + i;
+    if (!L.rb) return lin;
+    return (((i + j + k) & 1) ? ((L.nx * L.ny * L.nz) >> 1) : 0) + (lin >> 1);
+}
+
+template <typename T>
+__device__ __forceinline__ bool has_sig(const LevelArgs<T> &L, int k) { return k >= L.sig_lo && k < L.sig_hi; }
+
+template <typename T>
+__device__ __forceinline__ int sidx(const LevelArgs<T> &L, int i, int j, int k) {
+    const int lin = ((k - L.sig_lo) * L.ny + j) * L.nx + i;
+    if (!L.rb) return lin;
+    return (((i + j + k) & 1) ? ((L.nx * L.ny * (L.sig_hi - L.sig_lo)) >> 1) : 0) + (lin >> 1);
+}
+
+// sum over the 6 neighbours of coefficient * e(neighbour); Dirichlet neighbours are zero
+template <typename T>
+__device__ __forceinline__ T nb_sum(const LevelArgs<T> &L, const T *e, int i, int j, int k) {
+    T s = 0;
+    const T cx = L.cxy[k];
+    if (L.nx > 1) s += cx * (e[cidx(L, wrap_p(i, L.nx), j, k)] + e[cidx(L, wrap_m(i, L.nx), j, k)]);
+    if (L.ny > 1) s += cx * (e[cidx(L, i, wrap_p(j, L.ny), k)] + e[cidx(L, i, wrap_m(j, L.ny), k)]);
+    if (k > 0) s += L.czm[k] * e[cidx(L, i, j, k - 1)];
+    if (k < L.nz - 1) s += L.czp[k] * e[cidx(L, i, j, k + 1)];
+    return s;
+}
+
+template <typename T>
+__device__ __forceinline__ T diag_of(const LevelArgs<T> &L, int i, int j, int k) {
+    T d = L.dg[k];
+    if (has_sig(L, k)) d += L.sig[sidx(L, i, j, k)];
+    return d;
+}
+
+// Gauss-Seidel update of one cell of (L + diag sigma) e = r.
+template <typename T>
+__device__ __forceinline__ void gs_cell(const LevelArgs<T> &L, int i, int j, int k, int zero_init) {
+    const int c = cidx(L, i, j, k);
+    const T d = diag_of(L, i, j, k);
+    L.e[c] = zero_init ? L.r[c] / d : (L.r[c] + nb_sum(L, L.e, i, j, k)) / d;
+}
+
+// Residual of the finer level restricted to one coarse cell: volume-weighted
+// mean over the children, likewise sigma.  On a red/black level the black
+// children are skipped: right after a black half-sweep their residual is
+// zero (each black equation has just been solved exactly).
+template <typename T>
+__device__ __forceinline__ void restrict_cell(const LevelArgs<T> &F, const LevelArgs<T> &C, const XferArgs<T> &X,
+                                              int I, int J, int K) {
+    const int nsub = X.xy ? 2 : 1;
+    double sr = 0.0, ss = 0.0;
+    const int ks = X.cks[K], cnt = X.ccnt[K];
+    for (int dz = 0; dz < cnt; ++dz) {
+        const int k = ks + dz;
+        const double wz = (double)X.fthick[k] / (double)X.cthick[K];
+        const bool hs = has_sig(F, k);
+        for (int dy = 0; dy < nsub; ++dy) {
+            const int j = X.xy ? 2 * J + dy : J;
+            for (int dx = 0; dx < nsub; ++dx) {
+                const int i = X.xy ? 2 * I + dx : I;
+                const T sg = hs ? F.sig[sidx(F, i, j, k)] : T(0);
+                ss += wz * (double)sg;
+                if (F.rb && ((i + j + k) & 1)) continue;
+                const int c = cidx(F, i, j, k);
+                const T res = F.r[c] - ((F.dg[k] + sg) * F.e[c] - nb_sum(F, F.e, i, j, k));
+                sr += wz * (double)res;
+            }
+        }
+    }
+    const double wxy = X.xy ? 0.25 : 1.0;
+    C.r[cidx(C, I, J, K)] = (T)(sr * wxy);
+    if (has_sig(C, K)) C.sig[sidx(C, I, J, K)] = (T)(ss * wxy);
+}
+
+// e_f += I e_c: bilinear in x,y (cell-centred 3/4, 1/4), linear in z between
+// coarse plane centres (zero on contact faces).  On a red/black level only
+// black cells are corrected: the red values are overwritten by the next red
+// half-sweep without being read.
+template <typename T>
+__device__ __forceinline__ void prolong_cell(const LevelArgs<T> &F, const LevelArgs<T> &C, const XferArgs<T> &X,
+                                             int i, int j, int k) {
+    if (F.rb && !((i + j + k) & 1)) return;
+    int ix[2], jy[2];
+    T wx[2], wy[2];
+    int ns = 1;
+    if (X.xy) {
+        const int I = i >> 1, J = j >> 1;
+        ix[0] = I; ix[1] = (i & 1) ? wrap_p(I, C.nx) : wrap_m(I, C.nx);
+        jy[0] = J; jy[1] = (j & 1) ? wrap_p(J, C.ny) : wrap_m(J, C.ny);
+        wx[0] = wy[0] = T(0.75);
+        wx[1] = wy[1] = T(0.25);
+        ns = 2;
+    } else {
+        ix[0] = i; jy[0] = j; wx[0] = wy[0] = T(1);
+    }
+    T v = 0;
+    const int kz[2] = {X.pka[k], X.pkb[k]};
+    const T wz[2] = {X.pwa[k], X.pwb[k]};
+    for (int q = 0; q < 2; ++q) {
+        if (kz[q] < 0) continue;
+        T s = 0;
+        for (int yy = 0; yy < ns; ++yy)
+            for (int xx = 0; xx < ns; ++xx) s += wx[xx] * wy[yy] * C.e[cidx(C, ix[xx], jy[yy], kz[q])];
+        v += wz[q] * s;
+    }
+    F.e[cidx(F, i, j, k)] += v;
+}
+
+// Sum over a 256-thread block; result valid in thread 0.
 __device__ __forceinline__ double block_sum(double v, double *lds) {
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
     const int tid = threadIdx.y * blockDim.x + threadIdx.x;
-    const int lane = tid & 63, w = tid >> 6;
-    if (lane == 0) lds[w] = v;
+    if ((tid & 63) == 0) lds[tid >> 6] = v;
     __syncthreads();
     double s = 0.0;
-    if (tid == 0) {
-        const int nw = (blockDim.x * blockDim.y + 63) >> 6;
-        for (int q = 0; q < nw; ++q) s += lds[q];
-    }
+    if (tid == 0)
+        for (int q = 0; q < (int)((blockDim.x * blockDim.y) >> 6); ++q) s += lds[q];
     return s;
-}
-
-dim3 plane_grid(int nx, int ny, int nz) {
-    return dim3((nx + BX - 1) / BX, (ny + BY - 1) / BY, nz);
 }
 
 // ------------------------------------------------------------------- TDGL
@@ -46,9 +176,11 @@ __device__ __forceinline__ double surface_value(int pbc, double lambda, double h
 }
 
 __global__ __launch_bounds__(256) void k_tdgl(TdglArgs a) {
-    const int i = blockIdx.x * BX + threadIdx.x;
-    const int j = blockIdx.y * BY + threadIdx.y;
-    const int k = a.f0 + blockIdx.z;
+    const Tile t = tile_of((a.nx + BX - 1) / BX, (a.ny + BY - 1) / BY, a.f1 - a.f0);
+    if (!t.ok) return;
+    const int i = t.tx * BX + threadIdx.x;
+    const int j = t.ty * BY + threadIdx.y;
+    const int k = a.f0 + t.k;
     if (i >= a.nx || j >= a.ny) return;
     const size_t nxy = (size_t)a.nx * a.ny;
     const size_t c = (size_t)k * nxy + (size_t)j * a.nx + i;
@@ -83,243 +215,297 @@ template <typename T>
 __global__ __launch_bounds__(256) void k_residual(ResArgs<T> a) {
     __shared__ double lds_r[4];
     __shared__ double lds_f[4];
-    const int i = blockIdx.x * BX + threadIdx.x;
-    const int j = blockIdx.y * BY + threadIdx.y;
-    const int k = blockIdx.z;                       // device plane
+    if (a.ctrl->done) return;
+    const int nx = a.nx, ny = a.ny, nzd = a.nzd;
+    const Tile t = tile_of((nx + BX - 1) / BX, (ny + BY - 1) / BY, nzd);
+    if (!t.ok) return;
+    const int i = t.tx * BX + threadIdx.x;
+    const int j = t.ty * BY + threadIdx.y;
+    const int k = t.k;                                  // device plane
     double rr = 0.0, ff = 0.0;
-    if (i < a.nx && j < a.ny) {
-        const size_t nxy = (size_t)a.nx * a.ny;
-        const size_t cl = (size_t)k * nxy + (size_t)j * a.nx + i;   // level-0 index
-        const size_t c = cl + (size_t)a.kb * nxy;                   // full-grid index
-        const double *phi = a.phi;
-        const double v = phi[c];
+    if (i < nx && j < ny) {
+        const int nxy = nx * ny;
+        const double *phi = a.phi_in + (size_t)a.kb * nxy;
+        const double *prev = a.phi_prev ? a.phi_prev + (size_t)a.kb * nxy : nullptr;
+        const T *e = a.e;
+        const int rb = a.L0.rb;
+        const int half = (nxy * nzd) >> 1;
+        const double dmax = a.dmax;
+        const int ip = wrap_p(i, nx), im = wrap_m(i, nx), jp = wrap_p(j, ny), jm = wrap_m(j, ny);
+        const int cl = (k * ny + j) * nx + i;
+        // phi + clip(e) at level-0 linear index c of a cell with colour parity par on plane flagged fl
+        auto val = [&](int c, int par, int fl) -> double {
+            double v = phi[c];
+            if (prev) v = 2.0 * v - prev[c];
+            if (e) {
+                double d = (double)e[rb ? (par ? half : 0) + (c >> 1) : c];
+                if (fl & PF_SC) d = fmin(fmax(d, -dmax), dmax);
+                v += d;
+            }
+            return v;
+        };
+        const int fl = a.pflags[k];
+        const int par = (i + j + k) & 1;
+        const int row = cl - i;
+        const double v = val(cl, par, fl);
         double nb = 0.0;
-        if (a.nx > 1) nb += phi[c - i + wrap_p(i, a.nx)] + phi[c - i + wrap_m(i, a.nx)] - 2.0 * v;
-        if (a.ny > 1) {
-            const size_t pl = c - (size_t)j * a.nx;
-            nb += phi[pl + (size_t)wrap_p(j, a.ny) * a.nx] + phi[pl + (size_t)wrap_m(j, a.ny) * a.nx] - 2.0 * v;
-        }
+        if (nx > 1) nb += val(row + ip, par ^ 1, fl) + val(row + im, par ^ 1, fl) - 2.0 * v;
+        if (ny > 1) nb += val(cl + (jp - j) * nx, par ^ 1, fl) + val(cl + (jm - j) * nx, par ^ 1, fl) - 2.0 * v;
         double Lphi = -a.cxy[k] * nb;
-        const double dn = k > 0 ? phi[c - nxy] : 0.0;
-        const double up = k < a.nzd - 1 ? phi[c + nxy] : 0.0;
+        const double dn = k > 0 ? val(cl - nxy, par ^ 1, a.pflags[k - 1]) : 0.0;
+        const double up = k < nzd - 1 ? val(cl + nxy, par ^ 1, a.pflags[k + 1]) : 0.0;
         Lphi += a.czm[k] * (v - dn) + a.czp[k] * (v - up);
+        if (e || prev) a.phi_out[(size_t)a.kb * nxy + cl] = v;
         double f = 0.0;
         if (k == 0) f += a.czm[k] * a.v_b;
-        if (k == a.nzd - 1) f += a.czp[k] * a.v_t;
-        const int fl = a.pflags[k];
+        if (k == nzd - 1) f += a.czp[k] * a.v_t;
         if (fl & PF_P) {
-            const double pc = a.P[c];
-            const double pup = k == a.nzd - 1 ? pc : a.wl[k] * pc + a.wr[k] * a.P[c + nxy];
-            const double pdn = k == 0 ? pc : a.wl[k - 1] * a.P[c - nxy] + a.wr[k - 1] * pc;
+            const double *P = a.P + (size_t)a.kb * nxy;
+            const double pc = P[cl];
+            const double pup = k == nzd - 1 ? pc : a.wl[k] * pc + a.wr[k] * P[cl + nxy];
+            const double pdn = k == 0 ? pc : a.wl[k - 1] * P[cl - nxy] + a.wr[k - 1] * pc;
             f -= (pup - pdn) * a.p_scale;
         }
         double res = f - Lphi;
+        const LevelArgs<T> &L = a.L0;
         if (fl & PF_SC) {
             const double u = v * a.vt_inv;
             const double em = expm1(-u), ep = expm1(u);
             const double p0e = a.p0e[k], n0e = a.n0e[k];
             res += (p0e * em - n0e * ep) * a.rho_scale;                       // + rho_c
-            a.sig[cl - (size_t)a.sig_lo * nxy] = (T)((p0e * (1.0 + em) + n0e * (1.0 + ep)) * a.sig_scale);
+            L.sig[sidx(L, i, j, k)] = (T)((p0e * (1.0 + em) + n0e * (1.0 + ep)) * a.sig_scale);
         }
-        a.r[cl] = (T)res;
+        L.r[rb ? (par ? half : 0) + (cl >> 1) : cl] = (T)res;
         rr = res * res;
         ff = f * f;
     }
     const double sr = block_sum(rr, lds_r);
     const double sf = block_sum(ff, lds_f);
     if (threadIdx.x == 0 && threadIdx.y == 0) {
-        const size_t b = ((size_t)blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
-        a.part[2 * b] = sr;
-        a.part[2 * b + 1] = sf;
+        a.part[2 * t.id] = sr;
+        a.part[2 * t.id + 1] = sf;
     }
 }
 
-// ----------------------------------------------------------------- smoother
-// One colour of red-black Gauss-Seidel on (L + diag sigma) e = r.
-template <typename T>
-__device__ __forceinline__ T diag_at(const LevelArgs<T> &L, int k, size_t c, size_t nxy) {
-    T d = L.dg[k];
-    if (k >= L.sig_lo && k < L.sig_hi) d += L.sig[c - (size_t)L.sig_lo * nxy];
-    return d;
-}
-
-template <typename T>
-__device__ __forceinline__ T offdiag_sum(const LevelArgs<T> &L, const T *e, int i, int j, int k, size_t c, size_t nxy) {
-    T s = 0;
-    if (L.nx > 1) s += L.cxy[k] * (e[c - i + wrap_p(i, L.nx)] + e[c - i + wrap_m(i, L.nx)]);
-    if (L.ny > 1) {
-        const size_t pl = c - (size_t)j * L.nx;
-        s += L.cxy[k] * (e[pl + (size_t)wrap_p(j, L.ny) * L.nx] + e[pl + (size_t)wrap_m(j, L.ny) * L.nx]);
-    }
-    if (k > 0) s += L.czm[k] * e[c - nxy];
-    if (k < L.nz - 1) s += L.czp[k] * e[c + nxy];
-    return s;
-}
-
-template <typename T>
-__global__ __launch_bounds__(256) void k_smooth(LevelArgs<T> L, int color, int zero_init) {
-    const int i = blockIdx.x * BX + threadIdx.x;
-    const int j = blockIdx.y * BY + threadIdx.y;
-    const int k = blockIdx.z;
-    if (i >= L.nx || j >= L.ny) return;
-    const size_t nxy = (size_t)L.nx * L.ny;
-    const size_t c = (size_t)k * nxy + (size_t)j * L.nx + i;
-    if (((i + j + k) & 1) != color) {
-        if (zero_init) L.e[c] = T(0);
-        return;
-    }
-    const T d = diag_at(L, k, c, nxy);
-    if (zero_init) {
-        L.e[c] = L.r[c] / d;
-        return;
-    }
-    L.e[c] = (L.r[c] + offdiag_sum(L, L.e, i, j, k, c, nxy)) / d;
-}
-
-// ------------------------------------------------- residual + restriction
-template <typename T>
-__global__ __launch_bounds__(256) void k_restrict(RestrictArgs<T> a) {
-    const int I = blockIdx.x * BX + threadIdx.x;
-    const int J = blockIdx.y * BY + threadIdx.y;
-    const int K = blockIdx.z;
-    if (I >= a.c.nx || J >= a.c.ny) return;
-    const LevelArgs<T> &F = a.f;
-    const size_t fnxy = (size_t)F.nx * F.ny;
-    const int nsub = a.xy ? 2 : 1;
-    double sr = 0.0, ss = 0.0;
-    const int ks = a.cks[K], cnt = a.ccnt[K];
-    for (int dz = 0; dz < cnt; ++dz) {
-        const int k = ks + dz;
-        const double wz = (double)a.fthick[k] / (double)a.cthick[K];
-        const bool has_sig = k >= F.sig_lo && k < F.sig_hi;
-        for (int dy = 0; dy < nsub; ++dy) {
-            const int j = a.xy ? 2 * J + dy : J;
-            for (int dx = 0; dx < nsub; ++dx) {
-                const int i = a.xy ? 2 * I + dx : I;
-                const size_t c = (size_t)k * fnxy + (size_t)j * F.nx + i;
-                T d = F.dg[k];
-                T sg = 0;
-                if (has_sig) { sg = F.sig[c - (size_t)F.sig_lo * fnxy]; d += sg; }
-                const T res = F.r[c] - (d * F.e[c] - offdiag_sum(F, F.e, i, j, k, c, fnxy));
-                sr += wz * (double)res;
-                ss += wz * (double)sg;
-            }
-        }
-    }
-    const double wxy = a.xy ? 0.25 : 1.0;
-    const size_t cc = ((size_t)K * a.c.ny + J) * a.c.nx + I;
-    a.c.r[cc] = (T)(sr * wxy);
-    if (K >= a.c.sig_lo && K < a.c.sig_hi)
-        a.c.sig[cc - (size_t)a.c.sig_lo * a.c.nx * a.c.ny] = (T)(ss * wxy);
-}
-
-// ----------------------------------------------- prolongation + correction
-template <typename T>
-__global__ __launch_bounds__(256) void k_prolong(ProlongArgs<T> a) {
-    const int i = blockIdx.x * BX + threadIdx.x;
-    const int j = blockIdx.y * BY + threadIdx.y;
-    const int k = blockIdx.z;
-    if (i >= a.f.nx || j >= a.f.ny) return;
-    const int cnx = a.c.nx, cny = a.c.ny;
-    int ix[2], jy[2];
-    T wx[2], wy[2];
-    int nxs = 1, nys = 1;
-    if (a.xy) {
-        const int I = i >> 1, J = j >> 1;
-        ix[0] = I; ix[1] = (i & 1) ? wrap_p(I, cnx) : wrap_m(I, cnx);
-        jy[0] = J; jy[1] = (j & 1) ? wrap_p(J, cny) : wrap_m(J, cny);
-        wx[0] = T(0.75); wx[1] = T(0.25); wy[0] = T(0.75); wy[1] = T(0.25);
-        nxs = 2; nys = 2;
-    } else {
-        ix[0] = i; jy[0] = j; wx[0] = T(1); wy[0] = T(1);
-    }
-    const size_t cnxy = (size_t)cnx * cny;
-    T v = 0;
-    const int kz[2] = {a.ka[k], a.kb[k]};
-    const T wz[2] = {a.wa[k], a.wb[k]};
-    for (int q = 0; q < 2; ++q) {
-        if (kz[q] < 0) continue;
-        const T *ec = a.c.e + (size_t)kz[q] * cnxy;
-        T s = 0;
-        for (int yy = 0; yy < nys; ++yy)
-            for (int xx = 0; xx < nxs; ++xx) s += wx[xx] * wy[yy] * ec[(size_t)jy[yy] * cnx + ix[xx]];
-        v += wz[q] * s;
-    }
-    const size_t c = ((size_t)k * a.f.ny + j) * a.f.nx + i;
-    a.f.e[c] += v;
-}
-
-// ------------------------------------------------------------ bottom solve
-// Coarsest level: LDS-resident red-black sweeps in one workgroup.
-constexpr int kBottomMax = 2048;
-
-template <typename T>
-__global__ __launch_bounds__(1024) void k_bottom(LevelArgs<T> L, int sweeps) {
-    __shared__ T se[kBottomMax];
-    __shared__ T sr[kBottomMax];
-    __shared__ T sd[kBottomMax];
-    const int n = L.nx * L.ny * L.nz;
-    const int nxy = L.nx * L.ny;
-    for (int c = threadIdx.x; c < n; c += blockDim.x) {
-        const int k = c / nxy;
-        T d = L.dg[k];
-        if (k >= L.sig_lo && k < L.sig_hi) d += L.sig[c - L.sig_lo * nxy];
-        sd[c] = d;
-        sr[c] = L.r[c];
-        se[c] = T(0);
-    }
-    __syncthreads();
-    for (int s = 0; s < sweeps; ++s) {
-        for (int color = 0; color < 2; ++color) {
-            for (int c = threadIdx.x; c < n; c += blockDim.x) {
-                const int k = c / nxy, rem = c - k * nxy, j = rem / L.nx, i = rem - j * L.nx;
-                if (((i + j + k) & 1) != color) continue;
-                T acc = sr[c];
-                if (L.nx > 1) acc += L.cxy[k] * (se[c - i + wrap_p(i, L.nx)] + se[c - i + wrap_m(i, L.nx)]);
-                if (L.ny > 1) {
-                    const int pl = c - j * L.nx;
-                    acc += L.cxy[k] * (se[pl + wrap_p(j, L.ny) * L.nx] + se[pl + wrap_m(j, L.ny) * L.nx]);
-                }
-                if (k > 0) acc += L.czm[k] * se[c - nxy];
-                if (k < L.nz - 1) acc += L.czp[k] * se[c + nxy];
-                se[c] = acc / sd[c];
-            }
-            __syncthreads();
-        }
-    }
-    for (int c = threadIdx.x; c < n; c += blockDim.x) L.e[c] = se[c];
-}
-
-// ------------------------------------------------------------------ update
-template <typename T>
-__global__ __launch_bounds__(256) void k_update(double *phi, const T *e, int nx, int ny, int kb, const int *pflags,
-                                                double dmax) {
-    const int i = blockIdx.x * BX + threadIdx.x;
-    const int j = blockIdx.y * BY + threadIdx.y;
-    const int k = blockIdx.z;
-    if (i >= nx || j >= ny) return;
-    const size_t nxy = (size_t)nx * ny;
-    const size_t cl = (size_t)k * nxy + (size_t)j * nx + i;
-    double d = (double)e[cl];
-    if (pflags[k] & PF_SC) d = fmin(fmax(d, -dmax), dmax);
-    phi[cl + (size_t)kb * nxy] += d;
-}
-
-__global__ __launch_bounds__(1024) void k_reduce_norms(const double *part, int nb, double *out) {
+// Deterministic final sum of the residual partials and the stop decision.
+__global__ __launch_bounds__(1024) void k_reduce(const double *part, int n, SolveCtrl *ctrl, int count_cycle) {
     __shared__ double lr[16];
     __shared__ double lf[16];
+    if (ctrl->done) return;
     double r = 0.0, f = 0.0;
-    for (int b = threadIdx.x; b < nb; b += blockDim.x) { r += part[2 * b]; f += part[2 * b + 1]; }
+    for (int b = threadIdx.x; b < n; b += blockDim.x) { r += part[2 * b]; f += part[2 * b + 1]; }
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) { r += __shfl_down(r, off, 64); f += __shfl_down(f, off, 64); }
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    if (lane == 0) { lr[w] = r; lf[w] = f; }
+    if ((threadIdx.x & 63) == 0) { lr[threadIdx.x >> 6] = r; lf[threadIdx.x >> 6] = f; }
     __syncthreads();
     if (threadIdx.x == 0) {
         double a = 0.0, b = 0.0;
         for (int q = 0; q < (int)(blockDim.x >> 6); ++q) { a += lr[q]; b += lf[q]; }
-        out[0] = a;
-        out[1] = b;
+        ctrl->rn2 = a;
+        ctrl->fn2 = b;
+        if (count_cycle) ctrl->cycles += 1;
+        if (!isfinite(a) || !isfinite(b)) ctrl->done = 2;
+        else if (a <= ctrl->tol2 * b || a == 0.0 || b == 0.0) ctrl->done = 1;   // b = 0: the host sets phi = 0
+        else if (ctrl->cycles >= ctrl->max_cycles) ctrl->done = 3;
+    }
+}
+
+__global__ void k_ctrl_reset(SolveCtrl *ctrl, int max_cycles, double tol2) {
+    ctrl->done = 0;
+    ctrl->cycles = 0;
+    ctrl->max_cycles = max_cycles;
+    ctrl->tol2 = tol2;
+    ctrl->rn2 = 0.0;
+    ctrl->fn2 = 0.0;
+}
+
+// ----------------------------------------------------------------- smoother
+// One colour of red-black Gauss-Seidel on a red/black-split level: a thread
+// per cell of that colour, all reads and writes contiguous along x.
+template <typename T>
+__global__ __launch_bounds__(256) void k_smooth_rb(LevelArgs<T> L, int color, int zero_init, const SolveCtrl *ctrl) {
+    if (ctrl->done) return;
+    const int hx = L.nx >> 1;
+    const Tile t = tile_of((hx + BX - 1) / BX, (L.ny + BY - 1) / BY, L.nz);
+    if (!t.ok) return;
+    const int m = t.tx * BX + threadIdx.x;
+    const int j = t.ty * BY + threadIdx.y;
+    const int k = t.k;
+    if (m >= hx || j >= L.ny) return;
+    const int i = 2 * m + ((color + j + k) & 1);
+    const int half = (L.nx * L.ny * L.nz) >> 1;
+    const int plane = L.ny * hx;
+    const int row = k * plane + j * hx;
+    const int q = row + m;
+    const T *eo = L.e + (color ? 0 : half);
+    T *es = L.e + (color ? half : 0);
+    T d = L.dg[k];
+    if (k >= L.sig_lo && k < L.sig_hi) {
+        const int hs = (L.nx * L.ny * (L.sig_hi - L.sig_lo)) >> 1;
+        d += L.sig[(color ? hs : 0) + (k - L.sig_lo) * plane + j * hx + m];
+    }
+    const T rr = L.r[(color ? half : 0) + q];
+    if (zero_init) {
+        es[q] = rr / d;
+        return;
+    }
+    const int ip = i + 1 == L.nx ? 0 : i + 1, im = i == 0 ? L.nx - 1 : i - 1;
+    const T cx = L.cxy[k];
+    T s = cx * (eo[row + (ip >> 1)] + eo[row + (im >> 1)]);
+    if (L.ny > 1) s += cx * (eo[q + (wrap_p(j, L.ny) - j) * hx] + eo[q + (wrap_m(j, L.ny) - j) * hx]);
+    if (k > 0) s += L.czm[k] * eo[q - plane];
+    if (k < L.nz - 1) s += L.czp[k] * eo[q + plane];
+    es[q] = (rr + s) / d;
+}
+
+// Colour of a cell on a plainly stored level (odd x or y extent).  With an
+// odd periodic extent the parity colouring makes the wrap neighbours equal
+// coloured, so the last column / row (for odd nx / ny) get colours 2 and 3:
+// no two cells of one colour are then neighbours, and a sweep is the four
+// colours in turn.
+template <typename T>
+__device__ __forceinline__ int nat_color(const LevelArgs<T> &L, int i, int j, int k) {
+    const int par = (i + j + k) & 1;
+    const bool edge = ((L.nx & 1) && i == L.nx - 1) || ((L.ny & 1) && j == L.ny - 1);
+    return edge ? 2 + par : par;
+}
+
+// One colour of the Gauss-Seidel sweep on a plainly stored level: a thread per cell.
+template <typename T>
+__global__ __launch_bounds__(256) void k_smooth_nat(LevelArgs<T> L, int color, int zero_init, const SolveCtrl *ctrl) {
+    if (ctrl->done) return;
+    const Tile t = tile_of((L.nx + BX - 1) / BX, (L.ny + BY - 1) / BY, L.nz);
+    if (!t.ok) return;
+    const int i = t.tx * BX + threadIdx.x;
+    const int j = t.ty * BY + threadIdx.y;
+    const int k = t.k;
+    if (i >= L.nx || j >= L.ny) return;
+    if (nat_color(L, i, j, k) != color) {
+        if (zero_init) L.e[cidx(L, i, j, k)] = T(0);
+        return;
+    }
+    gs_cell(L, i, j, k, zero_init);
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_restrict(LevelArgs<T> F, LevelArgs<T> C, XferArgs<T> X, const SolveCtrl *ctrl) {
+    if (ctrl->done) return;
+    const Tile t = tile_of((C.nx + BX - 1) / BX, (C.ny + BY - 1) / BY, C.nz);
+    if (!t.ok) return;
+    const int I = t.tx * BX + threadIdx.x;
+    const int J = t.ty * BY + threadIdx.y;
+    if (I >= C.nx || J >= C.ny) return;
+    restrict_cell(F, C, X, I, J, t.k);
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_prolong(LevelArgs<T> F, LevelArgs<T> C, XferArgs<T> X, const SolveCtrl *ctrl) {
+    if (ctrl->done) return;
+    int i, j, k;
+    if (F.rb) {                       // a thread per black cell
+        const int hx = F.nx >> 1;
+        const Tile t = tile_of((hx + BX - 1) / BX, (F.ny + BY - 1) / BY, F.nz);
+        if (!t.ok) return;
+        const int m = t.tx * BX + threadIdx.x;
+        j = t.ty * BY + threadIdx.y;
+        k = t.k;
+        if (m >= hx || j >= F.ny) return;
+        i = 2 * m + ((1 + j + k) & 1);
+    } else {
+        const Tile t = tile_of((F.nx + BX - 1) / BX, (F.ny + BY - 1) / BY, F.nz);
+        if (!t.ok) return;
+        i = t.tx * BX + threadIdx.x;
+        j = t.ty * BY + threadIdx.y;
+        k = t.k;
+        if (i >= F.nx || j >= F.ny) return;
+    }
+    prolong_cell(F, C, X, i, j, k);
+}
+
+// --------------------------------------------- coarse levels in one workgroup
+template <typename T>
+__device__ void smooth_color(const LevelArgs<T> &L, int color, int zero_init) {
+    if (L.rb) {
+        const int hx = L.nx >> 1;
+        const int n = hx * L.ny * L.nz;
+        for (int q = threadIdx.x; q < n; q += blockDim.x) {
+            const int m = q % hx, row = q / hx, j = row % L.ny, k = row / L.ny;
+            gs_cell(L, 2 * m + ((color + j + k) & 1), j, k, zero_init);
+        }
+    } else {
+        const int n = L.nx * L.ny * L.nz;
+        for (int c = threadIdx.x; c < n; c += blockDim.x) {
+            const int i = c % L.nx, row = c / L.nx, j = row % L.ny, k = row / L.ny;
+            if (nat_color(L, i, j, k) == color) gs_cell(L, i, j, k, zero_init);
+            else if (zero_init) L.e[cidx(L, i, j, k)] = T(0);
+        }
+    }
+}
+
+// One full Gauss-Seidel sweep (2 colours on split levels, 4 otherwise).
+template <typename T>
+__device__ void smooth_sweep(const LevelArgs<T> &L, int zero_init) {
+    const int ncol = L.rb ? 2 : 4;
+    for (int c = 0; c < ncol; ++c) {
+        smooth_color(L, c, zero_init && c == 0);
+        __syncthreads();
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(1024) void k_coarse(const CoarseArgs<T> *A, const SolveCtrl *ctrl) {
+    extern __shared__ double lds_raw[];
+    if (ctrl->done) return;
+    unsigned char *lds = (unsigned char *)lds_raw;
+    const int nl = A->nlev;
+    // level views with LDS-resident e, r, sig
+    auto lvl = [&](int l) {
+        LevelArgs<T> L = A->lv[l];
+        L.e = (T *)(lds + A->off_e[l]);
+        L.r = (T *)(lds + A->off_r[l]);
+        L.sig = (T *)(lds + A->off_s[l]);
+        return L;
+    };
+    {
+        const LevelArgs<T> L0 = lvl(0);
+        const int n = L0.nx * L0.ny * L0.nz;
+        const int ns = L0.nx * L0.ny * (L0.sig_hi - L0.sig_lo);
+        for (int c = threadIdx.x; c < n; c += blockDim.x) L0.r[c] = A->r_in[c];
+        for (int c = threadIdx.x; c < ns; c += blockDim.x) L0.sig[c] = A->sig_in[c];
+        __syncthreads();
+    }
+    for (int l = 0; l < nl - 1; ++l) {
+        const LevelArgs<T> L = lvl(l);
+        for (int s = 0; s < A->nu1; ++s) smooth_sweep(L, s == 0);
+        const LevelArgs<T> C = lvl(l + 1);
+        const XferArgs<T> X = A->xf[l];
+        const int n = C.nx * C.ny * C.nz;
+        for (int c = threadIdx.x; c < n; c += blockDim.x) {
+            const int I = c % C.nx, row = c / C.nx;
+            restrict_cell(L, C, X, I, row % C.ny, row / C.ny);
+        }
+        __syncthreads();
+    }
+    {
+        const LevelArgs<T> B = lvl(nl - 1);
+        for (int s = 0; s < A->bottom_sweeps; ++s) smooth_sweep(B, s == 0);
+    }
+    for (int l = nl - 2; l >= 0; --l) {
+        const LevelArgs<T> L = lvl(l);
+        const LevelArgs<T> C = lvl(l + 1);
+        const XferArgs<T> X = A->xf[l];
+        const int n = L.nx * L.ny * L.nz;
+        for (int c = threadIdx.x; c < n; c += blockDim.x) {
+            const int i = c % L.nx, row = c / L.nx;
+            prolong_cell(L, C, X, i, row % L.ny, row / L.ny);
+        }
+        __syncthreads();
+        for (int s = 0; s < A->nu2; ++s) smooth_sweep(L, 0);
+    }
+    {
+        const LevelArgs<T> L0 = lvl(0);
+        const int n = L0.nx * L0.ny * L0.nz;
+        for (int c = threadIdx.x; c < n; c += blockDim.x) A->e_out[c] = L0.e[c];
     }
 }
 
@@ -331,58 +517,65 @@ __global__ void k_fill(double *x, size_t n, double v) {
 
 // ------------------------------------------------------------------ launchers
 void launch_tdgl(const TdglArgs &a, hipStream_t st) {
-    hipLaunchKernelGGL(k_tdgl, plane_grid(a.nx, a.ny, a.f1 - a.f0), dim3(BX, BY), 0, st, a);
+    hipLaunchKernelGGL(k_tdgl, tile_grid(tiles(a.nx, a.ny, a.f1 - a.f0)), dim3(BX, BY), 0, st, a);
 }
 
 template <typename T>
-void launch_residual(const ResArgs<T> &a, hipStream_t st, int *nblocks) {
-    dim3 g = plane_grid(a.nx, a.ny, a.nzd);
-    *nblocks = (int)(g.x * g.y * g.z);
-    hipLaunchKernelGGL(k_residual<T>, g, dim3(BX, BY), 0, st, a);
+int launch_residual(const ResArgs<T> &a, hipStream_t st) {
+    const int n = tiles(a.nx, a.ny, a.nzd);
+    hipLaunchKernelGGL(k_residual<T>, tile_grid(n), dim3(BX, BY), 0, st, a);
+    return n;
 }
 
 template <typename T>
-void launch_smooth(const LevelArgs<T> &L, int color, int zero_init, hipStream_t st) {
-    hipLaunchKernelGGL(k_smooth<T>, plane_grid(L.nx, L.ny, L.nz), dim3(BX, BY), 0, st, L, color, zero_init);
+void launch_smooth(const LevelArgs<T> &L, int color, int zero_init, const SolveCtrl *ctrl, hipStream_t st) {
+    if (L.rb)
+        hipLaunchKernelGGL(k_smooth_rb<T>, tile_grid(tiles(L.nx / 2, L.ny, L.nz)), dim3(BX, BY), 0, st, L, color,
+                           zero_init, ctrl);
+    else
+        hipLaunchKernelGGL(k_smooth_nat<T>, tile_grid(tiles(L.nx, L.ny, L.nz)), dim3(BX, BY), 0, st, L, color,
+                           zero_init, ctrl);
 }
 
 template <typename T>
-void launch_restrict(const RestrictArgs<T> &a, hipStream_t st) {
-    hipLaunchKernelGGL(k_restrict<T>, plane_grid(a.c.nx, a.c.ny, a.c.nz), dim3(BX, BY), 0, st, a);
+void launch_restrict(const LevelArgs<T> &F, const LevelArgs<T> &C, const XferArgs<T> &X, const SolveCtrl *ctrl,
+                     hipStream_t st) {
+    hipLaunchKernelGGL(k_restrict<T>, tile_grid(tiles(C.nx, C.ny, C.nz)), dim3(BX, BY), 0, st, F, C, X, ctrl);
 }
 
 template <typename T>
-void launch_prolong(const ProlongArgs<T> &a, hipStream_t st) {
-    hipLaunchKernelGGL(k_prolong<T>, plane_grid(a.f.nx, a.f.ny, a.f.nz), dim3(BX, BY), 0, st, a);
+void launch_prolong(const LevelArgs<T> &F, const LevelArgs<T> &C, const XferArgs<T> &X, const SolveCtrl *ctrl,
+                    hipStream_t st) {
+    hipLaunchKernelGGL(k_prolong<T>, tile_grid(tiles(F.rb ? F.nx / 2 : F.nx, F.ny, F.nz)), dim3(BX, BY), 0, st, F, C, X,
+                       ctrl);
 }
 
 template <typename T>
-void launch_bottom(const LevelArgs<T> &L, int sweeps, hipStream_t st) {
-    hipLaunchKernelGGL(k_bottom<T>, dim3(1), dim3(1024), 0, st, L, sweeps);
+void launch_coarse(const CoarseArgs<T> *dev_args, int lds_bytes, const SolveCtrl *ctrl, hipStream_t st) {
+    hipLaunchKernelGGL(k_coarse<T>, dim3(1), dim3(1024), lds_bytes, st, dev_args, ctrl);
 }
 
-template <typename T>
-void launch_update(double *phi, const T *e, int nx, int ny, int nzd, int kb, const int *pflags, double dmax,
-                   hipStream_t st) {
-    hipLaunchKernelGGL(k_update<T>, plane_grid(nx, ny, nzd), dim3(BX, BY), 0, st, phi, e, nx, ny, kb, pflags, dmax);
+void launch_reduce(const double *part, int nparts, SolveCtrl *ctrl, int count_cycle, hipStream_t st) {
+    hipLaunchKernelGGL(k_reduce, dim3(1), dim3(1024), 0, st, part, nparts, ctrl, count_cycle);
 }
 
-void launch_reduce_norms(const double *part, int nblocks, double *out, hipStream_t st) {
-    hipLaunchKernelGGL(k_reduce_norms, dim3(1), dim3(1024), 0, st, part, nblocks, out);
+void launch_ctrl_reset(SolveCtrl *ctrl, int max_cycles, double tol2, hipStream_t st) {
+    hipLaunchKernelGGL(k_ctrl_reset, dim3(1), dim3(1), 0, st, ctrl, max_cycles, tol2);
 }
 
 void launch_fill(double *x, size_t n, double v, hipStream_t st) {
-    const int blocks = (int)((n + 255) / 256 < 4096 ? (n + 255) / 256 : 4096);
-    hipLaunchKernelGGL(k_fill, dim3(blocks > 0 ? blocks : 1), dim3(256), 0, st, x, n, v);
+    const size_t b = (n + 255) / 256;
+    hipLaunchKernelGGL(k_fill, dim3(b == 0 ? 1 : (b < 4096 ? (unsigned)b : 4096u)), dim3(256), 0, st, x, n, v);
 }
 
-#define FX_INST(T)                                                                                         \
-    template void launch_residual<T>(const ResArgs<T> &, hipStream_t, int *);                               \
-    template void launch_smooth<T>(const LevelArgs<T> &, int, int, hipStream_t);                            \
-    template void launch_restrict<T>(const RestrictArgs<T> &, hipStream_t);                                 \
-    template void launch_prolong<T>(const ProlongArgs<T> &, hipStream_t);                                   \
-    template void launch_bottom<T>(const LevelArgs<T> &, int, hipStream_t);                                 \
-    template void launch_update<T>(double *, const T *, int, int, int, int, const int *, double, hipStream_t);
+#define FX_INST(T)                                                                                              \
+    template int launch_residual<T>(const ResArgs<T> &, hipStream_t);                                            \
+    template void launch_smooth<T>(const LevelArgs<T> &, int, int, const SolveCtrl *, hipStream_t);              \
+    template void launch_restrict<T>(const LevelArgs<T> &, const LevelArgs<T> &, const XferArgs<T> &,            \
+                                     const SolveCtrl *, hipStream_t);                                            \
+    template void launch_prolong<T>(const LevelArgs<T> &, const LevelArgs<T> &, const XferArgs<T> &,             \
+                                    const SolveCtrl *, hipStream_t);                                             \
+    template void launch_coarse<T>(const CoarseArgs<T> *, int, const SolveCtrl *, hipStream_t);
 FX_INST(double)
 FX_INST(float)
 

@@ -19,8 +19,11 @@
 // thickness-mean permittivity over the covered finest planes, and each
 // z-face coefficient is the series conductance of the finest half-planes
 // between the two coarse cell centres.  Restriction is the volume-weighted
-// mean, prolongation is linear between cell centres (bilinear in x/y,
-// distance-weighted in z with a zero correction on contact faces).
+// mean.  Prolongation is bilinear in x/y and, in z, linear in the series
+// resistance between the two nearest coarse centres (or the contact face,
+// where the correction is zero) -- the flux-continuous interpolant of a
+// layered medium, which keeps the V-cycle contraction near 0.1 across the
+// permittivity jumps where distance-linear weights stall near 0.2.
 #include "fx_internal.h"
 #include "../../include/ferrox.h"
 
@@ -31,6 +34,8 @@
 #include <cstring>
 #include <string>
 #include <vector>
+#include <algorithm>
+#include <type_traits>
 
 using namespace fx;
 
@@ -56,8 +61,7 @@ fx_status fail(fx_status s, const char *fmt, ...) {
             return fail(FX_EDEVICE, "%s failed: %s", #call, hipGetErrorString(e_));          \
     } while (0)
 
-constexpr int kBottomMaxCells = 2048;   // must not exceed the bottom kernel's LDS arrays
-constexpr int kBottomTarget = 64;
+constexpr int kBottomTarget = 8;         // stop coarsening at this many cells
 
 // One multigrid level, host view.
 struct HostLevel {
@@ -70,12 +74,14 @@ struct HostLevel {
     std::vector<int> pka, pkb;          // prolongation map of the finer level's planes
     std::vector<double> pwa, pwb;
     int sig_lo = 0, sig_hi = 0;
+    int rb = 0;                         // red/black-split storage (nx even)
     size_t ncell() const { return (size_t)nx * ny * nz; }
     size_t nsig() const { return (size_t)nx * ny * (sig_hi - sig_lo); }
 };
 
 struct Plan {
     int nx, ny, nz, kb, kt, nzd, f0, f1, sc0, sc1;
+    int lc;                             // first level handled by the one-workgroup coarse kernel
     std::vector<HostLevel> lv;
 };
 
@@ -100,9 +106,17 @@ struct DevLevel {
     int *ks = nullptr, *cnt = nullptr, *thick = nullptr, *pka = nullptr, *pkb = nullptr;
 };
 
+template <typename T>
+struct DevSet {
+    std::vector<DevLevel<T>> lv;
+    CoarseArgs<T> *coarse = nullptr;    // device copy of the coarse-kernel arguments
+    int coarse_lds = 0;
+};
+
 fx_status validate(const fx_stack_desc *d, Plan *p) {
     if (!d) return fail(FX_EINVAL, "desc is NULL");
     if (d->nx < 1 || d->ny < 1 || d->nz < 1) return fail(FX_EINVAL, "grid sizes must be >= 1");
+    if ((double)d->nx * d->ny * d->nz >= 2147483647.0) return fail(FX_EINVAL, "grid must have < 2^31 cells");
     if (!(d->h > 0) || !(d->Gamma > 0) || !(d->gamma > 0))
         return fail(FX_EINVAL, "h, Gamma and gamma must be > 0");
     if (d->pbc < 0 || d->pbc > 2) return fail(FX_EINVAL, "unknown pbc %d", d->pbc);
@@ -188,11 +202,22 @@ void build_plan(const fx_stack_desc *d, Plan *p) {
             C.sig_hi = cz ? (F.sig_hi + 1) / 2 : F.sig_hi;
         }
         p->lv.push_back(C);
-        if (p->lv.size() > 40) break;
+        if ((int)p->lv.size() >= kMaxLevels) break;
     }
-    // If the coarsest level is still too big for the one-workgroup bottom
-    // solve, drop nothing: the driver smooths it with the general kernels.
     const int nlev = (int)p->lv.size();
+    // red/black split storage needs a proper 2-colouring under periodic wrap
+    for (int l = 0; l < nlev; ++l)
+        p->lv[l].rb = p->lv[l].nx % 2 == 0 && (p->lv[l].ny % 2 == 0 || p->lv[l].ny == 1);
+    // the coarse kernel keeps levels lc.. in LDS
+    const size_t w = d->prec == FX_PREC_MIXED ? sizeof(float) : sizeof(double);
+    p->lc = nlev - 1;
+    size_t tail = 0;
+    for (int l = nlev - 1; l >= 0; --l) {
+        const HostLevel &L = p->lv[l];
+        tail += (2 * L.ncell() + L.nsig()) * w + 48;
+        if (tail > (size_t)kCoarseLdsBytes) break;
+        p->lc = l;
+    }
     int xy_pow = 0;
     for (int l = 0; l < nlev; ++l) {
         HostLevel &L = p->lv[l];
@@ -225,7 +250,12 @@ void build_plan(const fx_stack_desc *d, Plan *p) {
                 int kn;
                 if (zf < zc[K]) { kn = K - 1; zn = kn >= 0 ? zc[kn] : 0.0; }
                 else { kn = K + 1 < L.nz ? K + 1 : -1; zn = kn >= 0 ? zc[kn] : (double)p->nzd; }
-                const double wa = (zf - zn) / (zc[K] - zn);
+                // operator-dependent weights: linear in the series resistance
+                // (potential of a constant D_z flux) between the two centres,
+                // exact for the layered 1D problem across permittivity jumps
+                const double ra = series_R(epsd, std::min(zf, zc[K]), std::max(zf, zc[K]));
+                const double rn = series_R(epsd, std::min(zf, zn), std::max(zf, zn));
+                const double wa = rn / (ra + rn);
                 F.pwa[k] = wa;
                 F.pwb[k] = 1.0 - wa;
                 F.pkb[k] = kn;
@@ -236,39 +266,49 @@ void build_plan(const fx_stack_desc *d, Plan *p) {
 
 }  // namespace
 
+
 struct fx_stack {
     fx_stack_desc d{};
     std::vector<int> mat;
     std::vector<double> eps_r, Na, Nd;
     Plan plan;
     hipStream_t st = nullptr;
+    // P: [0] the caller's array, [1] workspace; pcur holds P^n
     double *P[2] = {nullptr, nullptr};
     int pcur = 0;
-    double *phi = nullptr;
+    // phi: [0] the caller's array, [1..3] workspace; phicur holds phi^n and,
+    // when hist is set, phiprev holds phi^{n-1} of the previous time step.
+    // A solve writes its iterates into the two buffers that are neither, so
+    // the entry state survives a failed solve.
+    double *phi[4] = {nullptr, nullptr, nullptr, nullptr};
+    int phicur = 0, phiprev = 1;
+    int hist = 0;
     // finest-level FP64 tables
-    double *t_cxy, *t_czm, *t_czp, *t_wl, *t_wr, *t_p0e, *t_n0e;
-    int *t_flags;
-    std::vector<DevLevel<double>> L64;
-    std::vector<DevLevel<float>> L32;
+    double *t_cxy = nullptr, *t_czm = nullptr, *t_czp = nullptr, *t_wl = nullptr, *t_wr = nullptr;
+    double *t_p0e = nullptr, *t_n0e = nullptr;
+    int *t_flags = nullptr;
+    DevSet<double> D64;
+    DevSet<float> D32;
     double *part = nullptr;
     int part_n = 0;
-    double *norms_dev = nullptr;
-    double *norms_host = nullptr;     // pinned
-    double *phi_save = nullptr;
+    SolveCtrl *ctrl = nullptr;          // device
+    SolveCtrl *ctrl_host = nullptr;     // pinned
     double VT = 0.0, scale = 0.0;
     double dmax = 0.0;
-    int nu1 = 2, nu2 = 2, bottom_sweeps = 40;
+    int nu1 = 2, nu2 = 2, bottom_sweeps = 12;
+    int k_pred = 4;                     // cycles enqueued before the first convergence check
+    int trace = 0;
 };
 
 namespace {
 
-// Lay out (or size) the workspace.  With s->... pointers null it only counts.
+// Lay out (or, with ws == nullptr, only size) the workspace.
 size_t carve(fx_stack *s, void *ws) {
     Carver cv(ws);
     const Plan &p = s->plan;
     const size_t nfull = (size_t)p.nx * p.ny * p.nz;
     s->P[1] = (double *)cv.take(nfull * sizeof(double));
-    s->phi_save = (double *)cv.take(nfull * sizeof(double));
+    for (int b = 1; b < 4; ++b) s->phi[b] = (double *)cv.take(nfull * sizeof(double));
     const int nzd = p.nzd;
     s->t_cxy = (double *)cv.take(nzd * sizeof(double));
     s->t_czm = (double *)cv.take(nzd * sizeof(double));
@@ -280,34 +320,31 @@ size_t carve(fx_stack *s, void *ws) {
     s->t_flags = (int *)cv.take(nzd * sizeof(int));
     const int nlev = (int)p.lv.size();
     const bool mixed = s->d.prec == FX_PREC_MIXED;
-    s->L64.assign(nlev, DevLevel<double>());
-    s->L32.assign(nlev, DevLevel<float>());
-    for (int l = 0; l < nlev; ++l) {
-        const HostLevel &H = p.lv[l];
+    s->D64.lv.assign(mixed ? 0 : nlev, DevLevel<double>());
+    s->D32.lv.assign(mixed ? nlev : 0, DevLevel<float>());
+    auto lay = [&](auto &D, const HostLevel &H, size_t w) {
+        using TT = std::remove_pointer_t<decltype(D.e)>;
         const size_t n = H.ncell(), ns = H.nsig();
         const int nz = H.nz;
-        auto ints = [&](int **dst) { *dst = (int *)cv.take(nz * sizeof(int)); };
-        if (!mixed) {
-            DevLevel<double> &D = s->L64[l];
-            D.e = (double *)cv.take(n * 8); D.r = (double *)cv.take(n * 8); D.sig = (double *)cv.take(ns * 8);
-            D.cxy = (double *)cv.take(nz * 8); D.czm = (double *)cv.take(nz * 8);
-            D.czp = (double *)cv.take(nz * 8); D.dg = (double *)cv.take(nz * 8);
-            D.pwa = (double *)cv.take(nz * 8); D.pwb = (double *)cv.take(nz * 8);
-            ints(&D.ks); ints(&D.cnt); ints(&D.thick); ints(&D.pka); ints(&D.pkb);
-        } else {
-            DevLevel<float> &D = s->L32[l];
-            D.e = (float *)cv.take(n * 4); D.r = (float *)cv.take(n * 4); D.sig = (float *)cv.take(ns * 4);
-            D.cxy = (float *)cv.take(nz * 4); D.czm = (float *)cv.take(nz * 4);
-            D.czp = (float *)cv.take(nz * 4); D.dg = (float *)cv.take(nz * 4);
-            D.pwa = (float *)cv.take(nz * 4); D.pwb = (float *)cv.take(nz * 4);
-            ints(&D.ks); ints(&D.cnt); ints(&D.thick); ints(&D.pka); ints(&D.pkb);
-        }
+        D.e = (TT *)cv.take(n * w); D.r = (TT *)cv.take(n * w); D.sig = (TT *)cv.take(ns * w);
+        D.cxy = (TT *)cv.take(nz * w); D.czm = (TT *)cv.take(nz * w);
+        D.czp = (TT *)cv.take(nz * w); D.dg = (TT *)cv.take(nz * w);
+        D.pwa = (TT *)cv.take(nz * w); D.pwb = (TT *)cv.take(nz * w);
+        D.ks = (int *)cv.take(nz * sizeof(int)); D.cnt = (int *)cv.take(nz * sizeof(int));
+        D.thick = (int *)cv.take(nz * sizeof(int)); D.pka = (int *)cv.take(nz * sizeof(int));
+        D.pkb = (int *)cv.take(nz * sizeof(int));
+    };
+    for (int l = 0; l < nlev; ++l) {
+        if (mixed) lay(s->D32.lv[l], p.lv[l], 4);
+        else lay(s->D64.lv[l], p.lv[l], 8);
     }
-    // residual partial sums: one pair per 64x4 block of the finest level
+    if (mixed) s->D32.coarse = (CoarseArgs<float> *)cv.take(sizeof(CoarseArgs<float>));
+    else s->D64.coarse = (CoarseArgs<double> *)cv.take(sizeof(CoarseArgs<double>));
+    // residual partial sums: one pair per 64x4 tile of the finest level
     const size_t nb = (size_t)((p.nx + 63) / 64) * ((p.ny + 3) / 4) * nzd;
     s->part_n = (int)nb;
     s->part = (double *)cv.take(2 * nb * sizeof(double));
-    s->norms_dev = (double *)cv.take(4 * sizeof(double));
+    s->ctrl = (SolveCtrl *)cv.take(sizeof(SolveCtrl));
     return cv.off + 256;
 }
 
@@ -319,9 +356,8 @@ fx_status upload_level(const HostLevel &H, DevLevel<T> &D) {
         HIP_OK(hipMemcpy(dst, a.data(), H.nz * sizeof(T), hipMemcpyHostToDevice));
         return FX_OK;
     };
-    auto upi = [&](int *dst, const std::vector<int> &src) -> fx_status {
-        std::vector<int> v(src);
-        v.resize(H.nz, 0);
+    auto upi = [&](int *dst, std::vector<int> v, int fillv) -> fx_status {
+        v.resize(H.nz, fillv);
         HIP_OK(hipMemcpy(dst, v.data(), H.nz * sizeof(int), hipMemcpyHostToDevice));
         return FX_OK;
     };
@@ -333,62 +369,88 @@ fx_status upload_level(const HostLevel &H, DevLevel<T> &D) {
     if ((st = up(D.pwa, pwa)) || (st = up(D.pwb, pwb))) return st;
     std::vector<int> thick(H.nz);
     for (int K = 0; K < H.nz; ++K) thick[K] = H.e0[K] - H.s0[K];
-    std::vector<int> pkb(H.pkb);
-    pkb.resize(H.nz, -1);
-    if ((st = upi(D.ks, H.ks)) || (st = upi(D.cnt, H.cnt)) || (st = upi(D.thick, thick)) ||
-        (st = upi(D.pka, H.pka)) || (st = upi(D.pkb, pkb)))
+    if ((st = upi(D.ks, H.ks, 0)) || (st = upi(D.cnt, H.cnt, 1)) || (st = upi(D.thick, thick, 1)) ||
+        (st = upi(D.pka, H.pka, 0)) || (st = upi(D.pkb, H.pkb, -1)))
         return st;
     return FX_OK;
 }
 
 template <typename T>
-LevelArgs<T> level_args(const fx_stack *s, const std::vector<DevLevel<T>> &LV, int l) {
+LevelArgs<T> level_args(const fx_stack *s, const DevSet<T> &D, int l) {
     const HostLevel &H = s->plan.lv[l];
     LevelArgs<T> a;
-    a.nx = H.nx; a.ny = H.ny; a.nz = H.nz;
-    a.cxy = LV[l].cxy; a.czm = LV[l].czm; a.czp = LV[l].czp; a.dg = LV[l].dg;
-    a.e = LV[l].e; a.r = LV[l].r; a.sig = LV[l].sig;
+    a.nx = H.nx; a.ny = H.ny; a.nz = H.nz; a.rb = H.rb;
+    a.cxy = D.lv[l].cxy; a.czm = D.lv[l].czm; a.czp = D.lv[l].czp; a.dg = D.lv[l].dg;
+    a.e = D.lv[l].e; a.r = D.lv[l].r; a.sig = D.lv[l].sig;
     a.sig_lo = H.sig_lo; a.sig_hi = H.sig_hi;
     return a;
 }
 
+// Transfer tables between level l (fine) and l+1 (coarse).
 template <typename T>
-void vcycle(fx_stack *s, const std::vector<DevLevel<T>> &LV, int l) {
-    const int nlev = (int)s->plan.lv.size();
-    hipStream_t st = s->st;
-    LevelArgs<T> A = level_args(s, LV, l);
-    if (l == nlev - 1) {
-        if (s->plan.lv[l].ncell() <= (size_t)kBottomMaxCells) {
-            launch_bottom(A, s->bottom_sweeps, st);
-        } else {
-            launch_smooth(A, 0, 1, st);
-            launch_smooth(A, 1, 0, st);
-            for (int q = 1; q < 4 * s->bottom_sweeps; ++q) { launch_smooth(A, 0, 0, st); launch_smooth(A, 1, 0, st); }
-        }
-        return;
-    }
-    launch_smooth(A, 0, 1, st);
-    launch_smooth(A, 1, 0, st);
-    for (int q = 1; q < s->nu1; ++q) { launch_smooth(A, 0, 0, st); launch_smooth(A, 1, 0, st); }
-    RestrictArgs<T> R;
-    R.f = A;
-    R.c = level_args(s, LV, l + 1);
-    R.fthick = LV[l].thick; R.cthick = LV[l + 1].thick;
-    R.cks = LV[l + 1].ks; R.ccnt = LV[l + 1].cnt;
-    R.xy = s->plan.lv[l + 1].xy_from_finer;
-    launch_restrict(R, st);
-    vcycle(s, LV, l + 1);
-    ProlongArgs<T> Pg;
-    Pg.f = A;
-    Pg.c = R.c;
-    Pg.ka = LV[l].pka; Pg.kb = LV[l].pkb; Pg.wa = LV[l].pwa; Pg.wb = LV[l].pwb;
-    Pg.xy = R.xy;
-    launch_prolong(Pg, st);
-    for (int q = 0; q < s->nu2; ++q) { launch_smooth(A, 0, 0, st); launch_smooth(A, 1, 0, st); }
+XferArgs<T> xfer_args(const fx_stack *s, const DevSet<T> &D, int l) {
+    XferArgs<T> x;
+    x.cks = D.lv[l + 1].ks; x.ccnt = D.lv[l + 1].cnt;
+    x.fthick = D.lv[l].thick; x.cthick = D.lv[l + 1].thick;
+    x.pka = D.lv[l].pka; x.pkb = D.lv[l].pkb; x.pwa = D.lv[l].pwa; x.pwb = D.lv[l].pwb;
+    x.xy = s->plan.lv[l + 1].xy_from_finer;
+    return x;
 }
 
 template <typename T>
-void residual(fx_stack *s, T *r0, T *sig0) {
+fx_status upload_coarse(fx_stack *s, DevSet<T> &D) {
+    const Plan &p = s->plan;
+    CoarseArgs<T> A;
+    memset(&A, 0, sizeof A);
+    A.nlev = (int)p.lv.size() - p.lc;
+    A.nu1 = s->nu1; A.nu2 = s->nu2;
+    const HostLevel &B = p.lv.back();
+    A.bottom_sweeps = s->bottom_sweeps + 2 * std::max(B.nx, std::max(B.ny, B.nz));
+    int off = 0;
+    auto take = [&](size_t bytes) { const int o = off; off += (int)((bytes + 15) & ~(size_t)15); return o; };
+    for (int q = 0; q < A.nlev; ++q) {
+        const HostLevel &H = p.lv[p.lc + q];
+        A.lv[q] = level_args(s, D, p.lc + q);
+        A.off_e[q] = take(H.ncell() * sizeof(T));
+        A.off_r[q] = take(H.ncell() * sizeof(T));
+        A.off_s[q] = take(H.nsig() * sizeof(T));
+        if (q + 1 < A.nlev) A.xf[q] = xfer_args(s, D, p.lc + q);
+    }
+    A.lds_bytes = off;
+    A.r_in = D.lv[p.lc].r;
+    A.sig_in = D.lv[p.lc].sig;
+    A.e_out = D.lv[p.lc].e;
+    if (off > kCoarseLdsBytes) return fail(FX_EINVAL, "coarse levels need %d bytes of LDS", off);
+    D.coarse_lds = off;
+    HIP_OK(hipMemcpy(D.coarse, &A, sizeof A, hipMemcpyHostToDevice));
+    return FX_OK;
+}
+
+template <typename T>
+void vcycle(fx_stack *s, const DevSet<T> &D, int l) {
+    hipStream_t st = s->st;
+    if (l == s->plan.lc) {
+        launch_coarse(D.coarse, D.coarse_lds, s->ctrl, st);
+        return;
+    }
+    const LevelArgs<T> A = level_args(s, D, l);
+    const LevelArgs<T> C = level_args(s, D, l + 1);
+    const XferArgs<T> X = xfer_args(s, D, l);
+    const int ncol = A.rb ? 2 : 4;
+    for (int q = 0; q < s->nu1; ++q)
+        for (int c = 0; c < ncol; ++c) launch_smooth(A, c, q == 0 && c == 0, s->ctrl, st);
+    launch_restrict(A, C, X, s->ctrl, st);
+    vcycle(s, D, l + 1);
+    launch_prolong(A, C, X, s->ctrl, st);
+    for (int q = 0; q < s->nu2; ++q)
+        for (int c = 0; c < ncol; ++c) launch_smooth(A, c, 0, s->ctrl, st);
+}
+
+// Fine-level residual at phi_in (+ e when given, written to phi_out) and the
+// stop decision.
+template <typename T>
+void residual(fx_stack *s, const DevSet<T> &D, const double *phi_in, double *phi_out, bool with_e,
+              const double *phi_prev = nullptr) {
     const Plan &p = s->plan;
     ResArgs<T> a;
     a.nx = p.nx; a.ny = p.ny; a.nzd = p.nzd; a.kb = p.kb;
@@ -397,99 +459,145 @@ void residual(fx_stack *s, T *r0, T *sig0) {
     a.rho_scale = s->scale;
     a.vt_inv = s->VT > 0 ? 1.0 / s->VT : 0.0;
     a.sig_scale = s->VT > 0 ? s->scale / s->VT : 0.0;
+    a.dmax = s->dmax;
     a.cxy = s->t_cxy; a.czm = s->t_czm; a.czp = s->t_czp;
     a.wl = s->t_wl; a.wr = s->t_wr; a.p0e = s->t_p0e; a.n0e = s->t_n0e; a.pflags = s->t_flags;
-    a.phi = s->phi; a.P = s->P[s->pcur];
-    a.r = r0; a.sig = sig0;
-    a.sig_lo = p.lv[0].sig_lo; a.sig_hi = p.lv[0].sig_hi;
+    a.phi_in = phi_in;
+    a.phi_prev = phi_prev;
+    a.phi_out = phi_out;
+    a.e = with_e ? D.lv[0].e : nullptr;
+    a.P = s->P[s->pcur];
+    a.L0 = level_args(s, D, 0);
     a.part = s->part;
-    int nb = 0;
-    launch_residual(a, s->st, &nb);
-    launch_reduce_norms(s->part, nb, s->norms_dev, s->st);
+    a.ctrl = s->ctrl;
+    const int n = launch_residual(a, s->st);
+    launch_reduce(s->part, n, s->ctrl, with_e ? 1 : 0, s->st);
 }
 
-fx_status read_norms(fx_stack *s, double *rn, double *fn) {
-    HIP_OK(hipMemcpyAsync(s->norms_host, s->norms_dev, 2 * sizeof(double), hipMemcpyDeviceToHost, s->st));
+fx_status read_ctrl(fx_stack *s) {
+    HIP_OK(hipMemcpyAsync(s->ctrl_host, s->ctrl, sizeof(SolveCtrl), hipMemcpyDeviceToHost, s->st));
     HIP_OK(hipStreamSynchronize(s->st));
-    *rn = std::sqrt(s->norms_host[0]);
-    *fn = std::sqrt(s->norms_host[1]);
     return FX_OK;
 }
 
+// Newton-multigrid solve.  The iterate before cycle 0 is phi^n, or (with
+// extrapolate set and a previous time level available) 2 phi^n - phi^{n-1}
+// written to buffer other[1].  Cycle c writes other[c % 2] from the previous
+// iterate; kernels of cycles after the device has decided to stop return at
+// once, so a batch of cycles is enqueued before each host check.
 template <typename T>
-fx_status solve_impl(fx_stack *s, const std::vector<DevLevel<T>> &LV, fx_solve_info *info) {
+fx_status solve_impl(fx_stack *s, const DevSet<T> &D, fx_solve_info *info, bool extrapolate) {
     const Plan &p = s->plan;
     const size_t nxy = (size_t)p.nx * p.ny;
-    double rn = 0, fn = 0;
-    HIP_OK(hipMemcpyAsync(s->phi_save + p.kb * nxy, s->phi + p.kb * nxy, p.nzd * nxy * sizeof(double),
-                          hipMemcpyDeviceToDevice, s->st));
-    residual<T>(s, LV[0].r, LV[0].sig);
-    fx_status st = read_norms(s, &rn, &fn);
-    if (st) return st;
-    if (fn == 0.0 && std::isfinite(rn)) {
-        // N(0) = 0 exactly, so phi = 0 is the root of N(phi) = 0
-        launch_fill(s->phi + p.kb * nxy, p.nzd * nxy, 0.0, s->st);
-        residual<T>(s, LV[0].r, LV[0].sig);
-        if ((st = read_norms(s, &rn, &fn))) return st;
-    }
-    int cyc = 0;
-    fx_status res = FX_ENOCONV;
+    const int entry = s->phicur;
+    int other[2], no = 0;
+    for (int b = 0; b < 4 && no < 2; ++b)
+        if (b != entry && b != s->phiprev) other[no++] = b;
+    const bool ex = extrapolate && s->hist;
+    launch_ctrl_reset(s->ctrl, s->d.max_cycles, s->d.tol_rel * s->d.tol_rel, s->st);
+    const int start = ex ? other[1] : entry;     // buffer holding the iterate before cycle 0
+    if (ex) residual<T>(s, D, s->phi[entry], s->phi[start], false, s->phi[s->phiprev]);
+    else residual<T>(s, D, s->phi[entry], nullptr, false);
+    int enq = 0;                        // cycles enqueued so far
+    int batch = s->trace ? 0 : std::max(1, s->k_pred);
+    fx_status st;
     for (;;) {
-        if (!std::isfinite(rn) || !std::isfinite(fn)) { res = FX_ENONFINITE; break; }
-        if (rn <= s->d.tol_rel * fn || rn == 0.0) { res = FX_OK; break; }
-        if (cyc >= s->d.max_cycles) break;
-        vcycle<T>(s, LV, 0);
-        launch_update<T>(s->phi, LV[0].e, p.nx, p.ny, p.nzd, p.kb, s->t_flags, s->dmax, s->st);
-        residual<T>(s, LV[0].r, LV[0].sig);
-        if ((st = read_norms(s, &rn, &fn))) return st;
-        ++cyc;
+        for (int q = 0; q < batch && enq < s->d.max_cycles; ++q, ++enq) {
+            const double *src = s->phi[enq == 0 ? start : other[(enq - 1) % 2]];
+            vcycle<T>(s, D, 0);
+            residual<T>(s, D, src, s->phi[other[enq % 2]], true);
+        }
+        if ((st = read_ctrl(s))) return st;
+        const SolveCtrl &c = *s->ctrl_host;
+        if (s->trace)
+            fprintf(stderr, "[ferrox] cycle %d |r|/|f| = %.3e\n", c.cycles, c.fn2 > 0 ? std::sqrt(c.rn2 / c.fn2) : 0.0);
+        if (c.done || enq >= s->d.max_cycles) break;
+        batch = 1;
     }
-    if (res == FX_ENONFINITE)
-        HIP_OK(hipMemcpyAsync(s->phi + p.kb * nxy, s->phi_save + p.kb * nxy, p.nzd * nxy * sizeof(double),
-                              hipMemcpyDeviceToDevice, s->st));
-    if (info) { info->cycles = cyc; info->status = res; info->res_norm = rn; info->rhs_norm = fn; }
-    if (res == FX_ENOCONV) return fail(res, "no convergence in %d cycles: |r|/|f| = %.3e", cyc, rn / fn);
+    const SolveCtrl c = *s->ctrl_host;
+    const int ncyc = c.cycles;
+    const int final_buf = ncyc == 0 ? start : other[(ncyc - 1) % 2];
+    double rn = std::sqrt(c.rn2), fn = std::sqrt(c.fn2);
+    fx_status res = FX_OK;
+    int newcur = final_buf;
+    if (c.done == 2) {
+        res = FX_ENONFINITE;
+        newcur = entry;                 // the entry iterate is untouched
+    } else if (c.done == 1 && fn == 0.0 && rn != 0.0) {
+        // f = 0: N(0) = 0 exactly, so phi = 0 is the root
+        launch_fill(s->phi[final_buf] + (size_t)p.kb * nxy, (size_t)p.nzd * nxy, 0.0, s->st);
+        rn = 0.0;
+    } else if (c.done != 1) {
+        res = FX_ENOCONV;
+    }
+    // phi^{n-1} for the next extrapolation is this solve's entry iterate
+    s->hist = extrapolate && res == FX_OK && newcur != entry;
+    if (s->hist) s->phiprev = entry;
+    s->phicur = newcur;
+    if (res != FX_ENONFINITE) s->k_pred = std::max(1, ncyc);
+    if (info) { info->cycles = ncyc; info->status = res; info->res_norm = rn; info->rhs_norm = fn; }
+    if (res == FX_ENOCONV) return fail(res, "no convergence in %d cycles: |r|/|f| = %.3e", ncyc, rn / fn);
     if (res == FX_ENONFINITE) return fail(res, "non-finite residual");
     return FX_OK;
 }
 
-fx_status solve(fx_stack *s, fx_solve_info *info) {
-    if (s->d.prec == FX_PREC_MIXED) return solve_impl<float>(s, s->L32, info);
-    return solve_impl<double>(s, s->L64, info);
+// A solve inside the time loop may start from the extrapolated iterate; the
+// history is kept only across consecutive time steps.
+fx_status solve(fx_stack *s, fx_solve_info *info, bool time_step = false) {
+    return s->d.prec == FX_PREC_MIXED ? solve_impl<float>(s, s->D32, info, time_step)
+                                      : solve_impl<double>(s, s->D64, info, time_step);
 }
 
-fx_status set_contacts(fx_stack *s) {
+void set_contacts(fx_stack *s) {
     const Plan &p = s->plan;
     const size_t nxy = (size_t)p.nx * p.ny;
-    if (p.kb > 0) launch_fill(s->phi, (size_t)p.kb * nxy, s->d.v_bottom, s->st);
-    if (p.kt < p.nz) launch_fill(s->phi + (size_t)p.kt * nxy, (size_t)(p.nz - p.kt) * nxy, s->d.v_top, s->st);
-    return FX_OK;
+    if (p.kb > 0) launch_fill(s->phi[0], (size_t)p.kb * nxy, s->d.v_bottom, s->st);
+    if (p.kt < p.nz) launch_fill(s->phi[0] + (size_t)p.kt * nxy, (size_t)(p.nz - p.kt) * nxy, s->d.v_top, s->st);
 }
 
-fx_status tdgl_impl(fx_stack *s, double dt) {
+void tdgl_impl(fx_stack *s, double dt) {
     const Plan &p = s->plan;
-    if (p.f0 < 0) return FX_OK;
+    if (p.f0 < 0) return;
     TdglArgs a;
     a.nx = p.nx; a.ny = p.ny; a.f0 = p.f0; a.f1 = p.f1;
     a.h = s->d.h; a.dt = dt;
     a.alpha = s->d.alpha; a.beta = s->d.beta; a.gamma = s->d.gamma;
     a.g11 = s->d.g11; a.g44 = s->d.g44; a.Gamma = s->d.Gamma;
     a.pbc = s->d.pbc; a.lambda = s->d.lambda;
-    a.P = s->P[s->pcur]; a.phi = s->phi; a.Pn = s->P[1 - s->pcur];
+    a.P = s->P[s->pcur]; a.phi = s->phi[s->phicur]; a.Pn = s->P[1 - s->pcur];
     launch_tdgl(a, s->st);
     s->pcur = 1 - s->pcur;
+}
+
+// Make the caller's arrays hold the current P and phi.
+fx_status sync_to_caller(fx_stack *s) {
+    const Plan &p = s->plan;
+    const size_t nxy = (size_t)p.nx * p.ny;
+    if (s->pcur != 0) {
+        if (p.f0 >= 0)
+            HIP_OK(hipMemcpyAsync(s->P[0] + p.f0 * nxy, s->P[1] + p.f0 * nxy, (p.f1 - p.f0) * nxy * sizeof(double),
+                                  hipMemcpyDeviceToDevice, s->st));
+        s->pcur = 0;
+    }
+    if (s->phicur != 0) {
+        // buffer 0 is the caller's: if it holds phi^{n-1}, swap roles first
+        if (s->phiprev == 0) {
+            int spare = 1;
+            while (spare == s->phicur) ++spare;
+            HIP_OK(hipMemcpyAsync(s->phi[spare] + p.kb * nxy, s->phi[0] + p.kb * nxy,
+                                  (size_t)p.nzd * nxy * sizeof(double), hipMemcpyDeviceToDevice, s->st));
+            s->phiprev = spare;
+        }
+        HIP_OK(hipMemcpyAsync(s->phi[0] + p.kb * nxy, s->phi[s->phicur] + p.kb * nxy,
+                              (size_t)p.nzd * nxy * sizeof(double), hipMemcpyDeviceToDevice, s->st));
+        s->phicur = 0;
+    }
     return FX_OK;
 }
 
-fx_status sync_P_to_caller(fx_stack *s) {
-    if (s->pcur == 0) return FX_OK;
-    const Plan &p = s->plan;
-    const size_t nxy = (size_t)p.nx * p.ny;
-    if (p.f0 >= 0)
-        HIP_OK(hipMemcpyAsync(s->P[0] + p.f0 * nxy, s->P[1] + p.f0 * nxy, (p.f1 - p.f0) * nxy * sizeof(double),
-                              hipMemcpyDeviceToDevice, s->st));
-    s->pcur = 0;
-    return FX_OK;
+int env_int(const char *name, int dflt) {
+    const char *v = getenv(name);
+    return v && *v ? atoi(v) : dflt;
 }
 
 }  // namespace
@@ -497,6 +605,7 @@ fx_status sync_P_to_caller(fx_stack *s) {
 extern "C" {
 
 size_t stack_workspace_bytes(const fx_stack_desc *desc) {
+    g_err.clear();
     fx_stack tmp;
     if (validate(desc, &tmp.plan)) return 0;
     tmp.d = *desc;
@@ -528,11 +637,13 @@ fx_status init_stack(const fx_stack_desc *desc, double *d_P, double *d_phi, void
     carve(s, d_ws);
     s->st = (hipStream_t)stream;
     s->P[0] = d_P;
-    s->phi = d_phi;
-    s->pcur = 0;
+    s->phi[0] = d_phi;
     s->scale = desc->h * desc->h / kEps0;
     s->VT = kKb * desc->T / kQe;
     s->dmax = s->VT > 0 ? 40.0 * s->VT : 0.0;
+    s->nu1 = std::max(1, env_int("FERROX_NU1", 2));
+    s->nu2 = std::max(1, env_int("FERROX_NU2", 2));
+    s->trace = env_int("FERROX_TRACE", 0);
     const Plan &p = s->plan;
     const int nzd = p.nzd;
     // finest-level tables: scaled coefficients, P face weights, carrier densities
@@ -559,20 +670,26 @@ fx_status init_stack(const fx_stack_desc *desc, double *d_P, double *d_phi, void
         }
     }
     const HostLevel &H0 = p.lv[0];
-#define UP(dst, v, T) HIP_OK(hipMemcpy(dst, (v).data(), nzd * sizeof(T), hipMemcpyHostToDevice))
+#define UP(dst, v, T)                                                                            \
+    do {                                                                                         \
+        hipError_t e_ = hipMemcpy(dst, (v).data(), nzd * sizeof(T), hipMemcpyHostToDevice);      \
+        if (e_ != hipSuccess) { delete s; return fail(FX_EDEVICE, "table upload: %s", hipGetErrorString(e_)); } \
+    } while (0)
     UP(s->t_cxy, H0.cxy, double); UP(s->t_czm, H0.czm, double); UP(s->t_czp, H0.czp, double);
     UP(s->t_wl, wl, double); UP(s->t_wr, wr, double); UP(s->t_p0e, p0e, double); UP(s->t_n0e, n0e, double);
     UP(s->t_flags, fl, int);
 #undef UP
     for (size_t l = 0; l < p.lv.size(); ++l) {
-        st = s->d.prec == FX_PREC_MIXED ? upload_level(p.lv[l], s->L32[l]) : upload_level(p.lv[l], s->L64[l]);
+        st = s->d.prec == FX_PREC_MIXED ? upload_level(p.lv[l], s->D32.lv[l]) : upload_level(p.lv[l], s->D64.lv[l]);
         if (st) { delete s; return st; }
     }
-    if (hipHostMalloc((void **)&s->norms_host, 4 * sizeof(double), 0) != hipSuccess) {
+    st = s->d.prec == FX_PREC_MIXED ? upload_coarse(s, s->D32) : upload_coarse(s, s->D64);
+    if (st) { delete s; return st; }
+    if (hipHostMalloc((void **)&s->ctrl_host, sizeof(SolveCtrl), 0) != hipSuccess) {
         delete s;
         return fail(FX_EDEVICE, "hipHostMalloc failed");
     }
-    // P: ping-pong buffer starts as a copy with zeros off the ferroelectric
+    // P: zero off the ferroelectric in both buffers
     const size_t nfull = (size_t)p.nx * p.ny * p.nz, nxy = (size_t)p.nx * p.ny;
     launch_fill(s->P[1], nfull, 0.0, s->st);
     if (p.f0 >= 0) {
@@ -582,10 +699,12 @@ fx_status init_stack(const fx_stack_desc *desc, double *d_P, double *d_phi, void
         launch_fill(s->P[0], nfull, 0.0, s->st);
     }
     // Step 0: phi^{0,(0)} = 0, then solve
-    launch_fill(s->phi, nfull, 0.0, s->st);
+    for (int b = 0; b < 4; ++b) launch_fill(s->phi[b], nfull, 0.0, s->st);
     set_contacts(s);
     *out = s;
-    return solve(s, nullptr);
+    st = solve(s, nullptr);
+    fx_status st2 = sync_to_caller(s);
+    return st ? st : st2;
 }
 
 fx_status tdgl_step(fx_stack *s, double dt) {
@@ -593,7 +712,8 @@ fx_status tdgl_step(fx_stack *s, double dt) {
     if (!s) return fail(FX_EINVAL, "stack is NULL");
     if (!(dt > 0)) return fail(FX_EINVAL, "dt must be > 0");
     tdgl_impl(s, dt);
-    return sync_P_to_caller(s);
+    s->hist = 0;
+    return sync_to_caller(s);
 }
 
 fx_status poisson_solve(fx_stack *s, double v_top, fx_solve_info *info) {
@@ -602,7 +722,11 @@ fx_status poisson_solve(fx_stack *s, double v_top, fx_solve_info *info) {
     if (!std::isfinite(v_top)) return fail(FX_EINVAL, "v_top must be finite");
     s->d.v_top = v_top;
     set_contacts(s);
-    return solve(s, info);
+    fx_status st = solve(s, info);
+    std::string msg = g_err;
+    fx_status st2 = sync_to_caller(s);
+    g_err = msg;
+    return st ? st : st2;
 }
 
 fx_status run_steps(fx_stack *s, int nsteps, double dt, const double *h_v_top_sched, fx_run_info *info) {
@@ -615,14 +739,16 @@ fx_status run_steps(fx_stack *s, int nsteps, double dt, const double *h_v_top_sc
         tdgl_impl(s, dt);
         if (h_v_top_sched) { s->d.v_top = h_v_top_sched[n]; set_contacts(s); }
         fx_solve_info si{};
-        st = solve(s, &si);
+        st = solve(s, &si, true);
         ri.total_cycles += si.cycles;
         if (si.cycles > ri.max_cycles_step) ri.max_cycles_step = si.cycles;
         ri.last_res_rel = si.rhs_norm > 0 ? si.res_norm / si.rhs_norm : 0.0;
         if (st) break;
         ri.steps_done = n + 1;
     }
-    fx_status st2 = sync_P_to_caller(s);
+    std::string msg = g_err;
+    fx_status st2 = sync_to_caller(s);
+    g_err = msg;
     if (info) *info = ri;
     return st ? st : st2;
 }
@@ -630,10 +756,22 @@ fx_status run_steps(fx_stack *s, int nsteps, double dt, const double *h_v_top_sc
 fx_status get_field(fx_stack *s, int which, double *h_out) {
     g_err.clear();
     if (!s || !h_out) return fail(FX_EINVAL, "NULL argument");
-    const size_t n = (size_t)s->plan.nx * s->plan.ny * s->plan.nz;
-    const double *src = which == FX_FIELD_P ? s->P[s->pcur] : which == FX_FIELD_PHI ? s->phi : nullptr;
-    if (!src) return fail(FX_EINVAL, "unknown field %d", which);
-    HIP_OK(hipMemcpyAsync(h_out, src, n * sizeof(double), hipMemcpyDeviceToHost, s->st));
+    if (which != FX_FIELD_P && which != FX_FIELD_PHI && which != FX_FIELD_PHI_PREV)
+        return fail(FX_EINVAL, "unknown field %d", which);
+    fx_status st = sync_to_caller(s);
+    if (st) return st;
+    const Plan &p = s->plan;
+    const size_t nxy = (size_t)p.nx * p.ny, n = nxy * p.nz;
+    if (which == FX_FIELD_PHI_PREV) {
+        if (!s->hist) return fail(FX_ESTATE, "no previous time level is held");
+        // device planes from the history buffer, contacts from the caller's array
+        HIP_OK(hipMemcpyAsync(h_out, s->phi[0], n * sizeof(double), hipMemcpyDeviceToHost, s->st));
+        HIP_OK(hipMemcpyAsync(h_out + p.kb * nxy, s->phi[s->phiprev] + p.kb * nxy, (size_t)p.nzd * nxy * sizeof(double),
+                              hipMemcpyDeviceToHost, s->st));
+    } else {
+        HIP_OK(hipMemcpyAsync(h_out, which == FX_FIELD_P ? s->P[0] : s->phi[0], n * sizeof(double),
+                              hipMemcpyDeviceToHost, s->st));
+    }
     HIP_OK(hipStreamSynchronize(s->st));
     return FX_OK;
 }
@@ -641,11 +779,22 @@ fx_status get_field(fx_stack *s, int which, double *h_out) {
 fx_status set_field(fx_stack *s, int which, const double *h_in) {
     g_err.clear();
     if (!s || !h_in) return fail(FX_EINVAL, "NULL argument");
+    if (which != FX_FIELD_P && which != FX_FIELD_PHI && which != FX_FIELD_PHI_PREV)
+        return fail(FX_EINVAL, "unknown field %d", which);
+    fx_status st = sync_to_caller(s);
+    if (st) return st;
     const Plan &p = s->plan;
     const size_t nxy = (size_t)p.nx * p.ny, n = nxy * p.nz;
+    if (which == FX_FIELD_PHI_PREV) {
+        s->phiprev = 1;                 // phicur is 0 after sync_to_caller
+        HIP_OK(hipMemcpyAsync(s->phi[1] + p.kb * nxy, h_in + p.kb * nxy, (size_t)p.nzd * nxy * sizeof(double),
+                              hipMemcpyHostToDevice, s->st));
+        HIP_OK(hipStreamSynchronize(s->st));
+        s->hist = 1;
+        return FX_OK;
+    }
+    s->hist = 0;
     if (which == FX_FIELD_P) {
-        fx_status sp = sync_P_to_caller(s);
-        if (sp) return sp;
         HIP_OK(hipMemcpyAsync(s->P[0], h_in, n * sizeof(double), hipMemcpyHostToDevice, s->st));
         HIP_OK(hipStreamSynchronize(s->st));
         if (p.f0 >= 0) {
@@ -654,12 +803,10 @@ fx_status set_field(fx_stack *s, int which, const double *h_in) {
         } else {
             launch_fill(s->P[0], n, 0.0, s->st);
         }
-    } else if (which == FX_FIELD_PHI) {
-        HIP_OK(hipMemcpyAsync(s->phi, h_in, n * sizeof(double), hipMemcpyHostToDevice, s->st));
+    } else {
+        HIP_OK(hipMemcpyAsync(s->phi[0], h_in, n * sizeof(double), hipMemcpyHostToDevice, s->st));
         HIP_OK(hipStreamSynchronize(s->st));
         set_contacts(s);
-    } else {
-        return fail(FX_EINVAL, "unknown field %d", which);
     }
     return FX_OK;
 }
@@ -678,7 +825,7 @@ fx_status stack_level_shape(const fx_stack *s, int level, int *nx, int *ny, int 
 fx_status destroy_stack(fx_stack *s) {
     if (!s) return FX_OK;
     if (s->st) (void)hipStreamSynchronize(s->st); else (void)hipDeviceSynchronize();
-    if (s->norms_host) (void)hipHostFree(s->norms_host);
+    if (s->ctrl_host) (void)hipHostFree(s->ctrl_host);
     delete s;
     return FX_OK;
 }

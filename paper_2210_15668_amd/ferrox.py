@@ -19,7 +19,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libferrox.so")
 
 FX_OK, FX_EINVAL, FX_ENOMEM, FX_EDEVICE, FX_ENOCONV, FX_ENONFINITE, FX_ESTATE = range(7)
-FIELD_P, FIELD_PHI = 0, 1
+FIELD_P, FIELD_PHI, FIELD_PHI_PREV = 0, 1, 2
 _STATUS = {0: "FX_OK", 1: "FX_EINVAL", 2: "FX_ENOMEM", 3: "FX_EDEVICE", 4: "FX_ENOCONV",
            5: "FX_ENONFINITE", 6: "FX_ESTATE"}
 

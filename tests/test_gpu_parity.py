@@ -154,14 +154,23 @@ def test_resume_and_determinism(fx):
     b.run_steps(4, W.DT)
     assert np.array_equal(a.get(fx.FIELD_P), b.get(fx.FIELD_P))
     assert np.array_equal(a.get(fx.FIELD_PHI), b.get(fx.FIELD_PHI))
-    # checkpoint through get/set into a fresh stack
+    # checkpoint through get/set into a fresh stack (P, phi and the previous time level)
     c = make_stack(fx, spec, P0)
     c.set(fx.FIELD_P, b.get(fx.FIELD_P))
     c.set(fx.FIELD_PHI, b.get(fx.FIELD_PHI))
+    c.set(fx.FIELD_PHI_PREV, b.get(fx.FIELD_PHI_PREV))
     a.run_steps(3, W.DT)
     c.run_steps(3, W.DT)
     assert np.array_equal(a.get(fx.FIELD_P), c.get(fx.FIELD_P))
     assert np.array_equal(a.get(fx.FIELD_PHI), c.get(fx.FIELD_PHI))
+    # without the previous level the restart converges to the same root, not the same iterate
+    d = make_stack(fx, spec, P0)
+    d.set(fx.FIELD_P, b.get(fx.FIELD_P))
+    d.set(fx.FIELD_PHI, b.get(fx.FIELD_PHI))
+    with pytest.raises(fx.FerroxError):
+        d.get(fx.FIELD_PHI_PREV)
+    d.run_steps(3, W.DT)
+    assert rel(d.get(fx.FIELD_PHI), a.get(fx.FIELD_PHI)) <= 1e-8
 
 
 def test_error_paths(fx):
