@@ -115,7 +115,8 @@ size_t stack_workspace_bytes(const fx_stack_desc *desc);
  * Validate desc, lay out the multigrid hierarchy in d_ws, upload the
  * per-plane tables, and run Step 0: phi := 0 on the device, then solve the
  * Poisson problem for the P held in d_P (Numerical Approach, Step 0).
- *   d_P, d_phi : caller-owned device arrays of nx*ny*nz doubles.  d_P holds
+ *   d_P, d_phi : caller-owned device arrays of nx*ny*nz doubles, 16-byte
+ *                aligned.  d_P holds
  *                P^0 (read; entries off ferroelectric planes are ignored and
  *                treated as zero).  d_phi receives phi^0; metal planes hold
  *                their contact potential.  Both must outlive the stack, and
@@ -169,6 +170,22 @@ fx_status run_steps(fx_stack *s, int nsteps, double dt, const double *h_v_top_sc
  * FX_FIELD_PHI_PREV returns FX_ESTATE when no previous level is held. */
 fx_status get_field(fx_stack *s, int which, double *h_out);
 fx_status set_field(fx_stack *s, int which, const double *h_in);
+
+/* Kernel-duration probe (instrumentation for roofline measurement).
+ * While FX_PROBE_SMOOTH_FINE is on, each launch of the finest-level
+ * Gauss-Seidel half-sweep (the kernel that moves the most bytes per step) is
+ * timestamped by its own dispatch (hipExtLaunchKernelGGL start/stop events,
+ * no extra stream work), up to max_launches launches, and the algorithmic
+ * bytes of those launches are summed: one touch each of the other colour's
+ * correction, this colour's right-hand side, sigma and correction (FP64:
+ * 8 bytes, mixed: 4 bytes per value), plus 16 bytes per cell for the phi
+ * pair read and written when the Newton update is folded into the last
+ * half-sweep.  stack_probe resets the counters (and synchronises the
+ * stream); stack_probe_read synchronises and returns the summed duration in
+ * ms, the number of timed launches and the bytes. */
+enum { FX_PROBE_OFF = 0, FX_PROBE_SMOOTH_FINE = 1 };
+fx_status stack_probe(fx_stack *s, int kernel, int max_launches);
+fx_status stack_probe_read(fx_stack *s, double *total_ms, int *launches, double *bytes);
 
 /* Number of multigrid levels and the sizes of level l (for diagnostics). */
 int stack_num_levels(const fx_stack *s);

@@ -98,8 +98,20 @@ struct ResArgs {
 };
 template <typename T> int launch_residual(const ResArgs<T> &a, hipStream_t st);
 
+// Newton update folded into the last black half-sweep of the finest level:
+// phi_out = phi_in + clip(e) for each black cell and its red partner (the
+// pair 2m, 2m+1 of a row), pointers at the device slab.
+struct UpdArgs {
+    const double *phi_in;
+    double *phi_out;
+    const int *pflags;
+    double dmax;
+};
+
+// ev0/ev1 (optional): HIP events the dispatch itself timestamps.
 template <typename T> void launch_smooth(const LevelArgs<T> &L, int color, int zero_init, const SolveCtrl *ctrl,
-                                         hipStream_t st);
+                                         hipStream_t st, const UpdArgs *upd = nullptr, hipEvent_t ev0 = nullptr,
+                                         hipEvent_t ev1 = nullptr);
 template <typename T> void launch_restrict(const LevelArgs<T> &F, const LevelArgs<T> &C, const XferArgs<T> &X,
                                            const SolveCtrl *ctrl, hipStream_t st);
 template <typename T> void launch_prolong(const LevelArgs<T> &F, const LevelArgs<T> &C, const XferArgs<T> &X,
@@ -116,7 +128,7 @@ struct CoarseArgs {
     int lds_bytes;
     LevelArgs<T> lv[kMaxLevels];
     XferArgs<T> xf[kMaxLevels];
-    int off_e[kMaxLevels], off_r[kMaxLevels], off_s[kMaxLevels];
+    int off_e[kMaxLevels], off_r[kMaxLevels], off_s[kMaxLevels], off_t[kMaxLevels];
     const T *r_in;
     const T *sig_in;
     T *e_out;

@@ -10,6 +10,8 @@
 // XCD's L2.
 #include "fx_internal.h"
 
+#include <hip/hip_ext.h>
+
 namespace fx {
 
 namespace {
@@ -211,73 +213,111 @@ __global__ __launch_bounds__(256) void k_tdgl(TdglArgs a) {
 }
 
 // ------------------------------------------------------ fine-level residual
-template <typename T>
+// MODE 0: residual at phi_in; 1: at 2 phi_in - phi_prev; 2: at phi_in + clip(e).
+// Each thread owns a column of ZT planes.  All loads are issued before any
+// arithmetic (clamped indices instead of boundary branches; the z-neighbours
+// of the column's planes are loaded once) so a wave makes one memory round
+// trip for ZT cells.
+template <typename T, int MODE, int ZT>
 __global__ __launch_bounds__(256) void k_residual(ResArgs<T> a) {
     __shared__ double lds_r[4];
     __shared__ double lds_f[4];
     if (a.ctrl->done) return;
     const int nx = a.nx, ny = a.ny, nzd = a.nzd;
-    const Tile t = tile_of((nx + BX - 1) / BX, (ny + BY - 1) / BY, nzd);
+    const Tile t = tile_of((nx + BX - 1) / BX, (ny + BY - 1) / BY, (nzd + ZT - 1) / ZT);
     if (!t.ok) return;
-    const int i = t.tx * BX + threadIdx.x;
-    const int j = t.ty * BY + threadIdx.y;
-    const int k = t.k;                                  // device plane
+    const int ii = t.tx * BX + threadIdx.x;
+    const int jj = t.ty * BY + threadIdx.y;
+    const bool live = ii < nx && jj < ny;
+    const int i = live ? ii : 0, j = live ? jj : 0;
+    const int k0 = t.k * ZT;
+    const int nxy = nx * ny;
+    const size_t off = (size_t)a.kb * nxy;
+    const double *phi = a.phi_in + off;
+    const double *P = a.P + off;
+    const int col = j * nx + i;
+    const int ox0 = wrap_p(i, nx) - i, ox1 = wrap_m(i, nx) - i;
+    const int oy0 = (wrap_p(j, ny) - j) * nx, oy1 = (wrap_m(j, ny) - j) * nx;
+    const int rb = a.L0.rb;
+    const int half = (nxy * nzd) >> 1;
+    const double big = 1e300;
+    auto kcl = [&](int k) { return k < 0 ? 0 : (k >= nzd ? nzd - 1 : k); };
+    // ---- bound charge: P of the column's planes and their neighbours (ferroelectric tiles only)
+    double pz[ZT + 2];
+#pragma unroll
+    for (int z = 0; z < ZT + 2; ++z) pz[z] = 0.0;
+    bool anyP = false;
+#pragma unroll
+    for (int z = 0; z < ZT; ++z) anyP |= (k0 + z < nzd) && (a.pflags[kcl(k0 + z)] & PF_P);
+    if (anyP) {
+#pragma unroll
+        for (int z = 0; z < ZT + 2; ++z) pz[z] = P[kcl(k0 - 1 + z) * nxy + col];
+    }
+    // ---- potential at the column (planes k0-1 .. k0+ZT) and the x/y neighbours (k0 .. k0+ZT-1)
+    double vc[ZT + 2], vx0[ZT], vx1[ZT], vy0[ZT], vy1[ZT];
+    auto at = [&](int k, int o, int par, double *dst) {
+        const int c = k * nxy + col + o;
+        double v = phi[c];
+        if (MODE == 1) v = 2.0 * v - a.phi_prev[off + c];
+        if (MODE == 2) {
+            const double d = (double)a.e[rb ? (par ? half : 0) + (c >> 1) : c];
+            const double lim = (a.pflags[k] & PF_SC) ? a.dmax : big;
+            v += fmin(fmax(d, -lim), lim);
+        }
+        *dst = v;
+    };
+    const int par0 = (i + j) & 1;
+#pragma unroll
+    for (int z = 0; z < ZT + 2; ++z) {
+        const int k = kcl(k0 - 1 + z);
+        at(k, 0, par0 ^ (k & 1), &vc[z]);
+    }
+#pragma unroll
+    for (int z = 0; z < ZT; ++z) {
+        const int k = kcl(k0 + z);
+        const int pn = par0 ^ (k & 1) ^ 1;
+        at(k, ox0, pn, &vx0[z]);
+        at(k, ox1, pn, &vx1[z]);
+        at(k, oy0, pn, &vy0[z]);
+        at(k, oy1, pn, &vy1[z]);
+    }
+    // ---- residual, carriers and stores, plane by plane
     double rr = 0.0, ff = 0.0;
-    if (i < nx && j < ny) {
-        const int nxy = nx * ny;
-        const double *phi = a.phi_in + (size_t)a.kb * nxy;
-        const double *prev = a.phi_prev ? a.phi_prev + (size_t)a.kb * nxy : nullptr;
-        const T *e = a.e;
-        const int rb = a.L0.rb;
-        const int half = (nxy * nzd) >> 1;
-        const double dmax = a.dmax;
-        const int ip = wrap_p(i, nx), im = wrap_m(i, nx), jp = wrap_p(j, ny), jm = wrap_m(j, ny);
-        const int cl = (k * ny + j) * nx + i;
-        // phi + clip(e) at level-0 linear index c of a cell with colour parity par on plane flagged fl
-        auto val = [&](int c, int par, int fl) -> double {
-            double v = phi[c];
-            if (prev) v = 2.0 * v - prev[c];
-            if (e) {
-                double d = (double)e[rb ? (par ? half : 0) + (c >> 1) : c];
-                if (fl & PF_SC) d = fmin(fmax(d, -dmax), dmax);
-                v += d;
-            }
-            return v;
-        };
+    const LevelArgs<T> &L = a.L0;
+#pragma unroll
+    for (int z = 0; z < ZT; ++z) {
+        const int k = k0 + z;
+        if (k >= nzd) break;
         const int fl = a.pflags[k];
-        const int par = (i + j + k) & 1;
-        const int row = cl - i;
-        const double v = val(cl, par, fl);
-        double nb = 0.0;
-        if (nx > 1) nb += val(row + ip, par ^ 1, fl) + val(row + im, par ^ 1, fl) - 2.0 * v;
-        if (ny > 1) nb += val(cl + (jp - j) * nx, par ^ 1, fl) + val(cl + (jm - j) * nx, par ^ 1, fl) - 2.0 * v;
-        double Lphi = -a.cxy[k] * nb;
-        const double dn = k > 0 ? val(cl - nxy, par ^ 1, a.pflags[k - 1]) : 0.0;
-        const double up = k < nzd - 1 ? val(cl + nxy, par ^ 1, a.pflags[k + 1]) : 0.0;
-        Lphi += a.czm[k] * (v - dn) + a.czp[k] * (v - up);
-        if (e || prev) a.phi_out[(size_t)a.kb * nxy + cl] = v;
+        const double v0 = vc[z + 1];
+        const double nb = (vx0[z] + vx1[z] - 2.0 * v0) + (vy0[z] + vy1[z] - 2.0 * v0);
+        const double dn = k > 0 ? vc[z] : 0.0;
+        const double up = k < nzd - 1 ? vc[z + 2] : 0.0;
+        const double Lphi = -a.cxy[k] * nb + a.czm[k] * (v0 - dn) + a.czp[k] * (v0 - up);
         double f = 0.0;
+        if (fl & PF_P) {
+            const double pc = pz[z + 1];
+            const double pup = k == nzd - 1 ? pc : a.wl[k] * pc + a.wr[k] * pz[z + 2];
+            const double pdn = k == 0 ? pc : a.wl[k - 1] * pz[z] + a.wr[k - 1] * pc;
+            f = -(pup - pdn) * a.p_scale;
+        }
         if (k == 0) f += a.czm[k] * a.v_b;
         if (k == nzd - 1) f += a.czp[k] * a.v_t;
-        if (fl & PF_P) {
-            const double *P = a.P + (size_t)a.kb * nxy;
-            const double pc = P[cl];
-            const double pup = k == nzd - 1 ? pc : a.wl[k] * pc + a.wr[k] * P[cl + nxy];
-            const double pdn = k == 0 ? pc : a.wl[k - 1] * P[cl - nxy] + a.wr[k - 1] * pc;
-            f -= (pup - pdn) * a.p_scale;
-        }
         double res = f - Lphi;
-        const LevelArgs<T> &L = a.L0;
-        if (fl & PF_SC) {
-            const double u = v * a.vt_inv;
-            const double em = expm1(-u), ep = expm1(u);
-            const double p0e = a.p0e[k], n0e = a.n0e[k];
-            res += (p0e * em - n0e * ep) * a.rho_scale;                       // + rho_c
-            L.sig[sidx(L, i, j, k)] = (T)((p0e * (1.0 + em) + n0e * (1.0 + ep)) * a.sig_scale);
+        if (live) {
+            const int cl = k * nxy + col;
+            if (MODE != 0) a.phi_out[off + cl] = v0;
+            if (fl & PF_SC) {
+                const double u = v0 * a.vt_inv;
+                const double em = expm1(-u), ep = expm1(u);
+                const double p0e = a.p0e[k], n0e = a.n0e[k];
+                res += (p0e * em - n0e * ep) * a.rho_scale;                       // + rho_c
+                L.sig[sidx(L, i, j, k)] = (T)((p0e * (1.0 + em) + n0e * (1.0 + ep)) * a.sig_scale);
+            }
+            L.r[cidx(L, i, j, k)] = (T)res;
+            rr += res * res;
+            ff += f * f;
         }
-        L.r[rb ? (par ? half : 0) + (cl >> 1) : cl] = (T)res;
-        rr = res * res;
-        ff = f * f;
     }
     const double sr = block_sum(rr, lds_r);
     const double sf = block_sum(ff, lds_f);
@@ -322,40 +362,81 @@ __global__ void k_ctrl_reset(SolveCtrl *ctrl, int max_cycles, double tol2) {
 // ----------------------------------------------------------------- smoother
 // One colour of red-black Gauss-Seidel on a red/black-split level: a thread
 // per cell of that colour, all reads and writes contiguous along x.
-template <typename T>
-__global__ __launch_bounds__(256) void k_smooth_rb(LevelArgs<T> L, int color, int zero_init, const SolveCtrl *ctrl) {
+template <typename T, int ZI, int ZT, int UPD>
+__global__ __launch_bounds__(256) void k_smooth_rb(LevelArgs<T> L, int color, const SolveCtrl *ctrl, UpdArgs u) {
     if (ctrl->done) return;
     const int hx = L.nx >> 1;
-    const Tile t = tile_of((hx + BX - 1) / BX, (L.ny + BY - 1) / BY, L.nz);
+    const Tile t = tile_of((hx + BX - 1) / BX, (L.ny + BY - 1) / BY, (L.nz + ZT - 1) / ZT);
     if (!t.ok) return;
-    const int m = t.tx * BX + threadIdx.x;
-    const int j = t.ty * BY + threadIdx.y;
-    const int k = t.k;
-    if (m >= hx || j >= L.ny) return;
-    const int i = 2 * m + ((color + j + k) & 1);
+    const int mm = t.tx * BX + threadIdx.x;
+    const int jj = t.ty * BY + threadIdx.y;
+    const bool live = mm < hx && jj < L.ny;
+    const int m = live ? mm : 0, j = live ? jj : 0;
     const int half = (L.nx * L.ny * L.nz) >> 1;
     const int plane = L.ny * hx;
-    const int row = k * plane + j * hx;
-    const int q = row + m;
     const T *eo = L.e + (color ? 0 : half);
     T *es = L.e + (color ? half : 0);
-    T d = L.dg[k];
-    if (k >= L.sig_lo && k < L.sig_hi) {
-        const int hs = (L.nx * L.ny * (L.sig_hi - L.sig_lo)) >> 1;
-        d += L.sig[(color ? hs : 0) + (k - L.sig_lo) * plane + j * hx + m];
+    const T *rs = L.r + (color ? half : 0);
+    const int hsz = (L.nx * L.ny * (L.sig_hi - L.sig_lo)) >> 1;
+    const int oy0 = L.ny > 1 ? (wrap_p(j, L.ny) - j) * hx : 0;
+    const int oy1 = L.ny > 1 ? (wrap_m(j, L.ny) - j) * hx : 0;
+    T out[ZT];
+    // loads of all ZT planes first
+    T rr[ZT], sg[ZT], ex0[ZT], ex1[ZT], ey0[ZT], ey1[ZT], ez0[ZT], ez1[ZT], ep[ZT];
+    double2 ph[ZT];
+#pragma unroll
+    for (int z = 0; z < ZT; ++z) {
+        const int k = min(t.k * ZT + z, L.nz - 1);
+        const int row = k * plane + j * hx;
+        const int q = row + m;
+        const bool hs = k >= L.sig_lo && k < L.sig_hi;
+        rr[z] = rs[q];
+        sg[z] = L.sig[hs ? (color ? hsz : 0) + (k - L.sig_lo) * plane + j * hx + m : 0];
+        if (!ZI) {
+            const int i = 2 * m + ((color + j + k) & 1);
+            const int ip = i + 1 == L.nx ? 0 : i + 1, im = i == 0 ? L.nx - 1 : i - 1;
+            ex0[z] = eo[row + (ip >> 1)];
+            ex1[z] = eo[row + (im >> 1)];
+            ey0[z] = eo[q + oy0];
+            ey1[z] = eo[q + oy1];
+            ez0[z] = eo[k > 0 ? q - plane : q];
+            ez1[z] = eo[k < L.nz - 1 ? q + plane : q];
+        }
+        if (UPD) {
+            ep[z] = eo[q];                       // the red partner of this black cell's pair
+            ph[z] = *(const double2 *)(u.phi_in + (size_t)k * L.nx * L.ny + (size_t)j * L.nx + 2 * m);
+        }
     }
-    const T rr = L.r[(color ? half : 0) + q];
-    if (zero_init) {
-        es[q] = rr / d;
-        return;
+#pragma unroll
+    for (int z = 0; z < ZT; ++z) {
+        const int k = min(t.k * ZT + z, L.nz - 1);
+        const bool hs = k >= L.sig_lo && k < L.sig_hi;
+        T s = 0;
+        if (!ZI) {
+            const T cx = L.cxy[k];
+            const T cy = L.ny > 1 ? cx : T(0);
+            s = cx * (ex0[z] + ex1[z]) + cy * (ey0[z] + ey1[z]) + (k > 0 ? L.czm[k] : T(0)) * ez0[z] +
+                (k < L.nz - 1 ? L.czp[k] : T(0)) * ez1[z];
+        }
+        out[z] = (rr[z] + s) / (L.dg[k] + (hs ? sg[z] : T(0)));
     }
-    const int ip = i + 1 == L.nx ? 0 : i + 1, im = i == 0 ? L.nx - 1 : i - 1;
-    const T cx = L.cxy[k];
-    T s = cx * (eo[row + (ip >> 1)] + eo[row + (im >> 1)]);
-    if (L.ny > 1) s += cx * (eo[q + (wrap_p(j, L.ny) - j) * hx] + eo[q + (wrap_m(j, L.ny) - j) * hx]);
-    if (k > 0) s += L.czm[k] * eo[q - plane];
-    if (k < L.nz - 1) s += L.czp[k] * eo[q + plane];
-    es[q] = (rr + s) / d;
+#pragma unroll
+    for (int z = 0; z < ZT; ++z) {
+        const int k = t.k * ZT + z;
+        if (live && k < L.nz) {
+            es[k * plane + j * hx + m] = out[z];
+            if (UPD) {
+                const double lim = (u.pflags[k] & PF_SC) ? u.dmax : 1e300;
+                const double db = fmin(fmax((double)out[z], -lim), lim);
+                const double dr = fmin(fmax((double)ep[z], -lim), lim);
+                const bool odd = ((color + j + k) & 1) != 0;          // black cell at 2m+1
+                double2 o;
+                o.x = ph[z].x + (odd ? dr : db);
+                o.y = ph[z].y + (odd ? db : dr);
+                *(double2 *)(u.phi_out + (size_t)k * L.nx * L.ny + (size_t)j * L.nx + 2 * m) = o;
+            }
+        }
+    }
 }
 
 // Colour of a cell on a plainly stored level (odd x or y extent).  With an
@@ -453,7 +534,7 @@ __device__ void smooth_sweep(const LevelArgs<T> &L, int zero_init) {
 }
 
 template <typename T>
-__global__ __launch_bounds__(1024) void k_coarse(const CoarseArgs<T> *A, const SolveCtrl *ctrl) {
+__global__ __launch_bounds__(512) void k_coarse(const CoarseArgs<T> *A, const SolveCtrl *ctrl) {
     extern __shared__ double lds_raw[];
     if (ctrl->done) return;
     unsigned char *lds = (unsigned char *)lds_raw;
@@ -464,8 +545,23 @@ __global__ __launch_bounds__(1024) void k_coarse(const CoarseArgs<T> *A, const S
         L.e = (T *)(lds + A->off_e[l]);
         L.r = (T *)(lds + A->off_r[l]);
         L.sig = (T *)(lds + A->off_s[l]);
+        T *tab = (T *)(lds + A->off_t[l]);
+        L.cxy = tab;
+        L.czm = tab + L.nz;
+        L.czp = tab + 2 * L.nz;
+        L.dg = tab + 3 * L.nz;
         return L;
     };
+    for (int l = 0; l < nl; ++l) {        // per-plane coefficient tables into LDS
+        const LevelArgs<T> G = A->lv[l];
+        T *tab = (T *)(lds + A->off_t[l]);
+        for (int c = threadIdx.x; c < G.nz; c += blockDim.x) {
+            tab[c] = G.cxy[c];
+            tab[G.nz + c] = G.czm[c];
+            tab[2 * G.nz + c] = G.czp[c];
+            tab[3 * G.nz + c] = G.dg[c];
+        }
+    }
     {
         const LevelArgs<T> L0 = lvl(0);
         const int n = L0.nx * L0.ny * L0.nz;
@@ -520,21 +616,46 @@ void launch_tdgl(const TdglArgs &a, hipStream_t st) {
     hipLaunchKernelGGL(k_tdgl, tile_grid(tiles(a.nx, a.ny, a.f1 - a.f0)), dim3(BX, BY), 0, st, a);
 }
 
+constexpr int kResZ = 4;   // planes per thread in the fine-level residual
+
 template <typename T>
 int launch_residual(const ResArgs<T> &a, hipStream_t st) {
-    const int n = tiles(a.nx, a.ny, a.nzd);
-    hipLaunchKernelGGL(k_residual<T>, tile_grid(n), dim3(BX, BY), 0, st, a);
+    const int n = tiles(a.nx, a.ny, (a.nzd + kResZ - 1) / kResZ);
+    if (a.e)
+        hipLaunchKernelGGL((k_residual<T, 2, kResZ>), tile_grid(n), dim3(BX, BY), 0, st, a);
+    else if (a.phi_prev)
+        hipLaunchKernelGGL((k_residual<T, 1, kResZ>), tile_grid(n), dim3(BX, BY), 0, st, a);
+    else
+        hipLaunchKernelGGL((k_residual<T, 0, kResZ>), tile_grid(n), dim3(BX, BY), 0, st, a);
     return n;
 }
 
 template <typename T>
-void launch_smooth(const LevelArgs<T> &L, int color, int zero_init, const SolveCtrl *ctrl, hipStream_t st) {
-    if (L.rb)
-        hipLaunchKernelGGL(k_smooth_rb<T>, tile_grid(tiles(L.nx / 2, L.ny, L.nz)), dim3(BX, BY), 0, st, L, color,
-                           zero_init, ctrl);
-    else
+void launch_smooth(const LevelArgs<T> &L, int color, int zero_init, const SolveCtrl *ctrl, hipStream_t st,
+                   const UpdArgs *upd, hipEvent_t ev0, hipEvent_t ev1) {
+    if (!L.rb) {
         hipLaunchKernelGGL(k_smooth_nat<T>, tile_grid(tiles(L.nx, L.ny, L.nz)), dim3(BX, BY), 0, st, L, color,
                            zero_init, ctrl);
+        return;
+    }
+    // large levels: 4 planes per thread; small ones one plane per thread for parallelism
+    const bool deep = (size_t)L.nx * L.ny * L.nz >= (1u << 19) && L.nz >= 8;
+    const dim3 g = deep ? tile_grid(tiles(L.nx / 2, L.ny, (L.nz + 3) / 4)) : tile_grid(tiles(L.nx / 2, L.ny, L.nz));
+    const UpdArgs u = upd ? *upd : UpdArgs{nullptr, nullptr, nullptr, 0.0};
+    auto go = [&](auto kern) {
+        if (ev0) hipExtLaunchKernelGGL(kern, g, dim3(BX, BY), 0, st, ev0, ev1, 0, L, color, ctrl, u);
+        else hipLaunchKernelGGL(kern, g, dim3(BX, BY), 0, st, L, color, ctrl, u);
+    };
+    if (upd) {
+        if (deep) go(k_smooth_rb<T, 0, 4, 1>);
+        else go(k_smooth_rb<T, 0, 1, 1>);
+    } else if (zero_init) {
+        if (deep) go(k_smooth_rb<T, 1, 4, 0>);
+        else go(k_smooth_rb<T, 1, 1, 0>);
+    } else {
+        if (deep) go(k_smooth_rb<T, 0, 4, 0>);
+        else go(k_smooth_rb<T, 0, 1, 0>);
+    }
 }
 
 template <typename T>
@@ -552,7 +673,7 @@ void launch_prolong(const LevelArgs<T> &F, const LevelArgs<T> &C, const XferArgs
 
 template <typename T>
 void launch_coarse(const CoarseArgs<T> *dev_args, int lds_bytes, const SolveCtrl *ctrl, hipStream_t st) {
-    hipLaunchKernelGGL(k_coarse<T>, dim3(1), dim3(1024), lds_bytes, st, dev_args, ctrl);
+    hipLaunchKernelGGL(k_coarse<T>, dim3(1), dim3(512), lds_bytes, st, dev_args, ctrl);
 }
 
 void launch_reduce(const double *part, int nparts, SolveCtrl *ctrl, int count_cycle, hipStream_t st) {
@@ -570,7 +691,8 @@ void launch_fill(double *x, size_t n, double v, hipStream_t st) {
 
 #define FX_INST(T)                                                                                              \
     template int launch_residual<T>(const ResArgs<T> &, hipStream_t);                                            \
-    template void launch_smooth<T>(const LevelArgs<T> &, int, int, const SolveCtrl *, hipStream_t);              \
+    template void launch_smooth<T>(const LevelArgs<T> &, int, int, const SolveCtrl *, hipStream_t, const UpdArgs *, \
+                                   hipEvent_t, hipEvent_t);                                                      \
     template void launch_restrict<T>(const LevelArgs<T> &, const LevelArgs<T> &, const XferArgs<T> &,            \
                                      const SolveCtrl *, hipStream_t);                                            \
     template void launch_prolong<T>(const LevelArgs<T> &, const LevelArgs<T> &, const XferArgs<T> &,             \

@@ -214,7 +214,7 @@ void build_plan(const fx_stack_desc *d, Plan *p) {
     size_t tail = 0;
     for (int l = nlev - 1; l >= 0; --l) {
         const HostLevel &L = p->lv[l];
-        tail += (2 * L.ncell() + L.nsig()) * w + 48;
+        tail += (2 * L.ncell() + L.nsig() + 4 * L.nz) * w + 64;
         if (tail > (size_t)kCoarseLdsBytes) break;
         p->lc = l;
     }
@@ -298,6 +298,11 @@ struct fx_stack {
     int nu1 = 2, nu2 = 2, bottom_sweeps = 12;
     int k_pred = 4;                     // cycles enqueued before the first convergence check
     int trace = 0;
+    // kernel-duration probe of the finest-level smoother
+    int probe = 0;
+    std::vector<hipEvent_t> ev;         // pairs (start, stop)
+    int ev_used = 0;
+    double probe_bytes = 0.0;
 };
 
 namespace {
@@ -326,7 +331,7 @@ size_t carve(fx_stack *s, void *ws) {
         using TT = std::remove_pointer_t<decltype(D.e)>;
         const size_t n = H.ncell(), ns = H.nsig();
         const int nz = H.nz;
-        D.e = (TT *)cv.take(n * w); D.r = (TT *)cv.take(n * w); D.sig = (TT *)cv.take(ns * w);
+        D.e = (TT *)cv.take(n * w); D.r = (TT *)cv.take(n * w); D.sig = (TT *)cv.take(std::max<size_t>(ns, 1) * w);
         D.cxy = (TT *)cv.take(nz * w); D.czm = (TT *)cv.take(nz * w);
         D.czp = (TT *)cv.take(nz * w); D.dg = (TT *)cv.take(nz * w);
         D.pwa = (TT *)cv.take(nz * w); D.pwb = (TT *)cv.take(nz * w);
@@ -340,7 +345,8 @@ size_t carve(fx_stack *s, void *ws) {
     }
     if (mixed) s->D32.coarse = (CoarseArgs<float> *)cv.take(sizeof(CoarseArgs<float>));
     else s->D64.coarse = (CoarseArgs<double> *)cv.take(sizeof(CoarseArgs<double>));
-    // residual partial sums: one pair per 64x4 tile of the finest level
+    // residual partial sums: one pair per 64x4 tile of the finest level (an upper bound
+    // for tiles spanning several planes)
     const size_t nb = (size_t)((p.nx + 63) / 64) * ((p.ny + 3) / 4) * nzd;
     s->part_n = (int)nb;
     s->part = (double *)cv.take(2 * nb * sizeof(double));
@@ -405,7 +411,7 @@ fx_status upload_coarse(fx_stack *s, DevSet<T> &D) {
     A.nlev = (int)p.lv.size() - p.lc;
     A.nu1 = s->nu1; A.nu2 = s->nu2;
     const HostLevel &B = p.lv.back();
-    A.bottom_sweeps = s->bottom_sweeps + 2 * std::max(B.nx, std::max(B.ny, B.nz));
+    A.bottom_sweeps = std::max(4, 2 * std::max(B.nx, std::max(B.ny, B.nz)));
     int off = 0;
     auto take = [&](size_t bytes) { const int o = off; off += (int)((bytes + 15) & ~(size_t)15); return o; };
     for (int q = 0; q < A.nlev; ++q) {
@@ -414,6 +420,7 @@ fx_status upload_coarse(fx_stack *s, DevSet<T> &D) {
         A.off_e[q] = take(H.ncell() * sizeof(T));
         A.off_r[q] = take(H.ncell() * sizeof(T));
         A.off_s[q] = take(H.nsig() * sizeof(T));
+        A.off_t[q] = take(4 * H.nz * sizeof(T));
         if (q + 1 < A.nlev) A.xf[q] = xfer_args(s, D, p.lc + q);
     }
     A.lds_bytes = off;
@@ -426,8 +433,30 @@ fx_status upload_coarse(fx_stack *s, DevSet<T> &D) {
     return FX_OK;
 }
 
+// Launch one smoother colour; finest-level launches are timestamped while
+// the probe is on, and their algorithmic bytes accumulated (one touch of each
+// array: the other colour's e, this colour's r, sigma and e; plus the phi
+// pair read and write when the Newton update is folded in).
 template <typename T>
-void vcycle(fx_stack *s, const DevSet<T> &D, int l) {
+void smooth(fx_stack *s, const LevelArgs<T> &A, int l, int color, int zi, const UpdArgs *upd = nullptr) {
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (l == 0 && s->probe && s->ev_used + 2 <= (int)s->ev.size()) {
+        e0 = s->ev[s->ev_used];
+        e1 = s->ev[s->ev_used + 1];
+        s->ev_used += 2;
+        const double n = (double)A.nx * A.ny * A.nz, ns = (double)A.nx * A.ny * (A.sig_hi - A.sig_lo);
+        double b = sizeof(T) * (0.5 * n + 0.5 * ns + 0.5 * n);       // r, sigma, e of this colour
+        if (!zi) b += sizeof(T) * 0.5 * n;                            // the other colour's e
+        if (upd) b += 16.0 * n;                                       // phi read + write
+        s->probe_bytes += b;
+    }
+    launch_smooth(A, color, zi, s->ctrl, s->st, upd, e0, e1);
+}
+
+// V-cycle from level l.  On the finest level (l = 0) with red/black storage
+// the last black half-sweep also writes phi_out = phi_in + clip(e).
+template <typename T>
+void vcycle(fx_stack *s, const DevSet<T> &D, int l, const UpdArgs *upd = nullptr) {
     hipStream_t st = s->st;
     if (l == s->plan.lc) {
         launch_coarse(D.coarse, D.coarse_lds, s->ctrl, st);
@@ -438,19 +467,21 @@ void vcycle(fx_stack *s, const DevSet<T> &D, int l) {
     const XferArgs<T> X = xfer_args(s, D, l);
     const int ncol = A.rb ? 2 : 4;
     for (int q = 0; q < s->nu1; ++q)
-        for (int c = 0; c < ncol; ++c) launch_smooth(A, c, q == 0 && c == 0, s->ctrl, st);
+        for (int c = 0; c < ncol; ++c) smooth(s, A, l, c, q == 0 && c == 0);
     launch_restrict(A, C, X, s->ctrl, st);
     vcycle(s, D, l + 1);
     launch_prolong(A, C, X, s->ctrl, st);
     for (int q = 0; q < s->nu2; ++q)
-        for (int c = 0; c < ncol; ++c) launch_smooth(A, c, 0, s->ctrl, st);
+        for (int c = 0; c < ncol; ++c)
+            smooth(s, A, l, c, 0, (upd && A.rb && q == s->nu2 - 1 && c == ncol - 1) ? upd : nullptr);
 }
 
 // Fine-level residual at phi_in (+ e when given, written to phi_out) and the
 // stop decision.
+// count_cycle: this residual closes a multigrid cycle (the device counts it).
 template <typename T>
 void residual(fx_stack *s, const DevSet<T> &D, const double *phi_in, double *phi_out, bool with_e,
-              const double *phi_prev = nullptr) {
+              const double *phi_prev, bool count_cycle) {
     const Plan &p = s->plan;
     ResArgs<T> a;
     a.nx = p.nx; a.ny = p.ny; a.nzd = p.nzd; a.kb = p.kb;
@@ -471,7 +502,7 @@ void residual(fx_stack *s, const DevSet<T> &D, const double *phi_in, double *phi
     a.part = s->part;
     a.ctrl = s->ctrl;
     const int n = launch_residual(a, s->st);
-    launch_reduce(s->part, n, s->ctrl, with_e ? 1 : 0, s->st);
+    launch_reduce(s->part, n, s->ctrl, count_cycle ? 1 : 0, s->st);
 }
 
 fx_status read_ctrl(fx_stack *s) {
@@ -496,16 +527,24 @@ fx_status solve_impl(fx_stack *s, const DevSet<T> &D, fx_solve_info *info, bool 
     const bool ex = extrapolate && s->hist;
     launch_ctrl_reset(s->ctrl, s->d.max_cycles, s->d.tol_rel * s->d.tol_rel, s->st);
     const int start = ex ? other[1] : entry;     // buffer holding the iterate before cycle 0
-    if (ex) residual<T>(s, D, s->phi[entry], s->phi[start], false, s->phi[s->phiprev]);
-    else residual<T>(s, D, s->phi[entry], nullptr, false);
+    if (ex) residual<T>(s, D, s->phi[entry], s->phi[start], false, s->phi[s->phiprev], false);
+    else residual<T>(s, D, s->phi[entry], nullptr, false, nullptr, false);
     int enq = 0;                        // cycles enqueued so far
     int batch = s->trace ? 0 : std::max(1, s->k_pred);
     fx_status st;
     for (;;) {
+        const bool fold = p.lv[0].rb && p.lc > 0;
         for (int q = 0; q < batch && enq < s->d.max_cycles; ++q, ++enq) {
             const double *src = s->phi[enq == 0 ? start : other[(enq - 1) % 2]];
-            vcycle<T>(s, D, 0);
-            residual<T>(s, D, src, s->phi[other[enq % 2]], true);
+            double *dst = s->phi[other[enq % 2]];
+            if (fold) {
+                const UpdArgs u{src + (size_t)p.kb * nxy, dst + (size_t)p.kb * nxy, s->t_flags, s->dmax};
+                vcycle<T>(s, D, 0, &u);
+                residual<T>(s, D, dst, nullptr, false, nullptr, true);
+            } else {
+                vcycle<T>(s, D, 0);
+                residual<T>(s, D, src, dst, true, nullptr, true);
+            }
         }
         if ((st = read_ctrl(s))) return st;
         const SolveCtrl &c = *s->ctrl_host;
@@ -620,6 +659,8 @@ fx_status init_stack(const fx_stack_desc *desc, double *d_P, double *d_phi, void
     *out = nullptr;
     if (!d_P || !d_phi || !d_ws) return fail(FX_EINVAL, "device pointers must not be NULL");
     if (((uintptr_t)d_ws & 255) != 0) return fail(FX_EINVAL, "workspace must be 256-byte aligned");
+    if (((uintptr_t)d_P & 15) != 0 || ((uintptr_t)d_phi & 15) != 0)
+        return fail(FX_EINVAL, "d_P and d_phi must be 16-byte aligned");
     fx_stack *s = new (std::nothrow) fx_stack();
     if (!s) return fail(FX_ENOMEM, "host allocation failed");
     fx_status st = validate(desc, &s->plan);
@@ -811,6 +852,40 @@ fx_status set_field(fx_stack *s, int which, const double *h_in) {
     return FX_OK;
 }
 
+fx_status stack_probe(fx_stack *s, int kernel, int max_launches) {
+    g_err.clear();
+    if (!s) return fail(FX_EINVAL, "stack is NULL");
+    if (kernel != FX_PROBE_OFF && kernel != FX_PROBE_SMOOTH_FINE) return fail(FX_EINVAL, "unknown probe %d", kernel);
+    if (kernel == FX_PROBE_OFF) { s->probe = 0; return FX_OK; }
+    if (max_launches < 1) return fail(FX_EINVAL, "max_launches must be >= 1");
+    HIP_OK(hipStreamSynchronize(s->st));
+    while ((int)s->ev.size() < 2 * max_launches) {
+        hipEvent_t e;
+        HIP_OK(hipEventCreate(&e));
+        s->ev.push_back(e);
+    }
+    s->probe = kernel;
+    s->ev_used = 0;
+    s->probe_bytes = 0.0;
+    return FX_OK;
+}
+
+fx_status stack_probe_read(fx_stack *s, double *total_ms, int *launches, double *bytes) {
+    g_err.clear();
+    if (!s) return fail(FX_EINVAL, "stack is NULL");
+    HIP_OK(hipStreamSynchronize(s->st));
+    double tot = 0.0;
+    for (int q = 0; q + 1 < s->ev_used; q += 2) {
+        float ms = 0.0f;
+        HIP_OK(hipEventElapsedTime(&ms, s->ev[q], s->ev[q + 1]));
+        tot += ms;
+    }
+    if (total_ms) *total_ms = tot;
+    if (launches) *launches = s->ev_used / 2;
+    if (bytes) *bytes = s->probe_bytes;
+    return FX_OK;
+}
+
 int stack_num_levels(const fx_stack *s) { return s ? (int)s->plan.lv.size() : 0; }
 
 fx_status stack_level_shape(const fx_stack *s, int level, int *nx, int *ny, int *nz) {
@@ -826,6 +901,7 @@ fx_status destroy_stack(fx_stack *s) {
     if (!s) return FX_OK;
     if (s->st) (void)hipStreamSynchronize(s->st); else (void)hipDeviceSynchronize();
     if (s->ctrl_host) (void)hipHostFree(s->ctrl_host);
+    for (hipEvent_t e : s->ev) (void)hipEventDestroy(e);
     delete s;
     return FX_OK;
 }

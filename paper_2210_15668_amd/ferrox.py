@@ -20,6 +20,7 @@ LIB_PATH = os.path.join(_HERE, "libferrox.so")
 
 FX_OK, FX_EINVAL, FX_ENOMEM, FX_EDEVICE, FX_ENOCONV, FX_ENONFINITE, FX_ESTATE = range(7)
 FIELD_P, FIELD_PHI, FIELD_PHI_PREV = 0, 1, 2
+PROBE_OFF, PROBE_SMOOTH_FINE = 0, 1
 _STATUS = {0: "FX_OK", 1: "FX_EINVAL", 2: "FX_ENOMEM", 3: "FX_EDEVICE", 4: "FX_ENOCONV",
            5: "FX_ENONFINITE", 6: "FX_ESTATE"}
 
@@ -67,6 +68,8 @@ SIGNATURES = [
     ("run_steps", ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_double, _dp, ctypes.POINTER(RunInfo)]),
     ("get_field", ctypes.c_int, [_vp, ctypes.c_int, _dp]),
     ("set_field", ctypes.c_int, [_vp, ctypes.c_int, _dp]),
+    ("stack_probe", ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int]),
+    ("stack_probe_read", ctypes.c_int, [_vp, _dp, _ip, _dp]),
     ("stack_num_levels", ctypes.c_int, [_vp]),
     ("stack_level_shape", ctypes.c_int, [_vp, ctypes.c_int, _ip, _ip, _ip]),
     ("destroy_stack", ctypes.c_int, [_vp]),
@@ -184,6 +187,16 @@ class Stack:
     def set(self, which: int, arr: np.ndarray):
         a = np.ascontiguousarray(arr, np.float64)
         _check(lib().set_field(self._h, which, a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
+
+    def probe(self, kernel: int = PROBE_SMOOTH_FINE, max_launches: int = 4096):
+        """Start timestamping the finest-level smoother launches (see include/ferrox.h)."""
+        _check(lib().stack_probe(self._h, kernel, max_launches))
+
+    def probe_read(self):
+        """(total ms, launches, algorithmic bytes) of the probed launches."""
+        ms, n, b = ctypes.c_double(), ctypes.c_int(), ctypes.c_double()
+        _check(lib().stack_probe_read(self._h, ctypes.byref(ms), ctypes.byref(n), ctypes.byref(b)))
+        return ms.value, n.value, b.value
 
     def levels(self):
         out = []
