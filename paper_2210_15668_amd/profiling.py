@@ -1,0 +1,130 @@
+"""Turn rocprofv3 output into the short text summaries kept under profiles/.
+
+Run on the GPU host from the repository root (each rocprofv3 call on its own):
+
+  rocprofv3 --kernel-trace --stats -d OUT/trace -o run -- python3 bench.py
+  rocprofv3 --pmc FETCH_SIZE -d OUT/fetch -o run -- python3 bench.py --steps 20 --no-mixed --no-cpu-baseline
+  rocprofv3 --pmc WRITE_SIZE -d OUT/write -o run -- python3 bench.py --steps 20 --no-mixed --no-cpu-baseline
+  rocprofv3 --pmc FETCH_SIZE -d OUT/cfetch -o run -- python3 -m paper_2210_15668_amd.profiling copy
+  rocprofv3 --pmc WRITE_SIZE -d OUT/cwrite -o run -- python3 -m paper_2210_15668_amd.profiling copy
+  python3 -m paper_2210_15668_amd.profiling stats OUT/trace
+  python3 -m paper_2210_15668_amd.profiling traffic OUT
+
+`copy` runs one plain device-to-device copy of 1 GiB (larger than the 256 MB
+last-level cache, so every byte crosses HBM): FETCH_SIZE and WRITE_SIZE of that
+dispatch, divided by 1 GiB, are the factors that turn the counters into bytes.
+"""
+from __future__ import annotations
+
+import glob
+import hashlib
+import json
+import os
+import re
+import sqlite3
+import sys
+from collections import defaultdict
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+KERNEL_SRC = os.path.join(ROOT, "paper_2210_15668_amd", "csrc", "fx_kernels.hip")
+COPY_BYTES = 1 << 30
+DOMINANT = "k_smooth_rb<double"        # finest-level smoother launches have the largest grid
+
+
+def _db(d):
+    files = glob.glob(os.path.join(d, "**", "*.db"), recursive=True)
+    if not files:
+        raise FileNotFoundError(f"no rocprofv3 database under {d}")
+    return sqlite3.connect(files[0])
+
+
+def _short(name):
+    m = re.search(r"(k_\w+)(<[^(]*>)?", name or "")
+    return (m.group(1) + (m.group(2) or "")) if m else (name or "")[:48]
+
+
+def copy():
+    import torch
+    n = COPY_BYTES // 8
+    a = torch.ones(n, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    b.copy_(a)
+    torch.cuda.synchronize()
+    print(f"copied {COPY_BYTES} bytes", flush=True)
+
+
+def stats(trace_dir):
+    db = _db(trace_dir)
+    rows = db.execute("select name, grid_x, duration from kernels").fetchall()
+    agg = defaultdict(lambda: [0, 0.0])
+    for name, gx, d in rows:
+        key = (_short(name), gx)
+        agg[key][0] += 1
+        agg[key][1] += d
+    tot = sum(v[1] for v in agg.values())
+    fine = [k for k in agg if k[0].startswith(DOMINANT)]
+    if fine:
+        gmax = max(k[1] for k in fine)
+        c = sum(agg[k][0] for k in fine if k[1] == gmax)
+        t = sum(agg[k][1] for k in fine if k[1] == gmax)
+        print(f"Dominant kernel (finest-level FP64 smoother, all variants, grid {gmax}): "
+              f"{c} launches, average {t / c / 1e3:.2f} us\n")
+    print("| kernel | grid (threads) | calls | avg us | total ms | % |")
+    print("|---|---|---|---|---|---|")
+    for (k, gx), (c, t) in sorted(agg.items(), key=lambda x: -x[1][1])[:24]:
+        print(f"| `{k}` | {gx} | {c} | {t / c / 1e3:.2f} | {t / 1e6:.2f} | {100 * t / tot:.1f} |")
+
+
+def _counter(d, counter):
+    db = _db(d)
+    rows = db.execute("select kernel_name, grid_size, counter_name, value from counters_collection").fetchall()
+    out = defaultdict(list)
+    for name, grid, cname, v in rows:
+        if cname == counter:
+            out[(_short(name), grid)].append(v)
+    return out
+
+
+def traffic(base):
+    """Measured HBM bytes per launch of the finest-level FP64 smoother (all its variants,
+    weighted by their launch counts in the counter run)."""
+    cf = _counter(os.path.join(base, "cfetch"), "FETCH_SIZE")
+    cw = _counter(os.path.join(base, "cwrite"), "WRITE_SIZE")
+    big_f = max(max(v) for v in cf.values()) * 1024.0
+    big_w = max(max(v) for v in cw.values()) * 1024.0
+    f_fetch, f_write = big_f / COPY_BYTES, big_w / COPY_BYTES
+    fe = _counter(os.path.join(base, "fetch"), "FETCH_SIZE")
+    wr = _counter(os.path.join(base, "write"), "WRITE_SIZE")
+    # the finest level is the largest grid among the smoother launches
+    keys = [k for k in fe if k[0].startswith(DOMINANT)]
+    gmax = max(k[1] for k in keys)
+    fine = [k for k in keys if k[1] == gmax]
+    n = sum(len(fe[k]) for k in fine)
+    fetch = sum(sum(fe[k]) for k in fine) * 1024.0 / f_fetch / n
+    write = sum(sum(wr.get(k, [0])) for k in fine) * 1024.0 / f_write / max(1, sum(len(wr.get(k, [])) for k in fine))
+    with open(KERNEL_SRC, "rb") as f:
+        sha = hashlib.sha256(f.read()).hexdigest()
+    out = {
+        "kernel": "finest-level red/black Gauss-Seidel half-sweep (FP64), all variants",
+        "variants": {f"{k[0]} grid {k[1]}": len(fe[k]) for k in fine},
+        "copy_calibration": {"bytes": COPY_BYTES, "fetch_factor": f_fetch, "write_factor": f_write},
+        "fetch_bytes_per_launch": fetch,
+        "write_bytes_per_launch": write,
+        "per_launch_bytes": {"fp64": fetch + write},
+        "kernel_src_sha256": sha,
+    }
+    print(json.dumps(out, indent=1))
+
+
+if __name__ == "__main__":
+    cmd = sys.argv[1] if len(sys.argv) > 1 else ""
+    if cmd == "copy":
+        copy()
+    elif cmd == "stats":
+        stats(sys.argv[2])
+    elif cmd == "traffic":
+        traffic(sys.argv[2])
+    else:
+        print(__doc__)
+        sys.exit(1)
