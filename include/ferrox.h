@@ -65,10 +65,10 @@ typedef enum { FX_PBC_FREE = 0, FX_PBC_ZERO = 1, FX_PBC_LAMBDA = 2 } fx_pbc;
  * double-precision defect-correction loop (residual, carriers, update). */
 typedef enum { FX_PREC_FP64 = 0, FX_PREC_MIXED = 1 } fx_precision;
 
-/* FX_FIELD_PHI_PREV is phi at the previous time level, kept by run_steps to
- * start each solve from the linear extrapolation 2 phi^n - phi^{n-1}; it is
+/* FX_FIELD_PHI_PREV + m - 1 (m = 1..3) is phi at time level n - m, kept by
+ * run_steps for the extrapolated starting iterate (warm_start); these are
  * part of the state a bitwise-exact checkpoint must carry. */
-enum { FX_FIELD_P = 0, FX_FIELD_PHI = 1, FX_FIELD_PHI_PREV = 2 };
+enum { FX_FIELD_P = 0, FX_FIELD_PHI = 1, FX_FIELD_PHI_PREV = 2, FX_FIELD_PHI_PREV2 = 3, FX_FIELD_PHI_PREV3 = 4 };
 
 typedef struct fx_stack fx_stack;
 
@@ -91,7 +91,10 @@ typedef struct {
     double tol_rel;              /* stop when ||f - N(phi)||_2 <= tol_rel ||f||_2           */
     int max_cycles;              /* multigrid cycles allowed per Poisson solve              */
     int prec;                    /* fx_precision                                            */
-    int flags;                   /* reserved, must be 0                                     */
+    int warm_start;              /* starting iterate of each run_steps solve: the polynomial
+                                    extrapolation in time through phi^n and the previous
+                                    warm_start levels (0: phi^n itself, as in Step 1b;
+                                    1: 2 phi^n - phi^{n-1}; 2: quadratic; 3: cubic)      */
 } fx_stack_desc;
 
 typedef struct {
@@ -161,13 +164,14 @@ fx_status poisson_solve(fx_stack *s, double v_top, fx_solve_info *info);
 fx_status run_steps(fx_stack *s, int nsteps, double dt, const double *h_v_top_sched,
                     fx_run_info *info);
 
-/* Copy the current P, phi or previous-time-level phi (FX_FIELD_*) to / from
- * host memory of nx*ny*nz doubles.  get_field synchronises the stream.
+/* Copy the current P, phi or a previous time level of phi (FX_FIELD_*) to /
+ * from host memory of nx*ny*nz doubles.  get_field synchronises the stream.
  * set_field of P zeroes entries off ferroelectric planes; set_field of phi
  * rewrites the metal planes with their contact potentials.  Setting P or phi
- * discards the previous time level (the next run_steps step starts from
- * phi^n); setting FX_FIELD_PHI_PREV afterwards restores it.  get_field of
- * FX_FIELD_PHI_PREV returns FX_ESTATE when no previous level is held. */
+ * discards the stored time levels (the next run_steps step starts from
+ * phi^n); setting FX_FIELD_PHI_PREV, then _PREV2, then _PREV3 afterwards
+ * restores them in that order.  get_field of a level that is not held
+ * returns FX_ESTATE. */
 fx_status get_field(fx_stack *s, int which, double *h_out);
 fx_status set_field(fx_stack *s, int which, const double *h_in);
 

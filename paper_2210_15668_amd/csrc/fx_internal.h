@@ -70,8 +70,7 @@ struct XferArgs {
 };
 
 // ------------------------------------------------- fine-level residual (FP64)
-// phi_out = phi_in + clip(e) (when e is given) or 2 phi_in - phi_prev (when
-// phi_prev is given: linear extrapolation in time), then r = s (f - N(phi_out))
+// phi_out = phi_in + clip(e) (when e is given), then r = s (f - N(phi_out))
 // on the device slab and sigma = s e (p + n) / VT on semiconductor planes;
 // s = h^2/eps0.  Per-tile partial sums of r^2 and (s f)^2.
 template <typename T>
@@ -88,8 +87,7 @@ struct ResArgs {
     const double *p0e, *n0e;         // e * p0, e * n0 per device plane
     const int *pflags;
     const double *phi_in;            // full grid
-    const double *phi_prev;          // full grid or nullptr: evaluate at 2 phi_in - phi_prev
-    double *phi_out;                 // full grid (written when e or phi_prev is given)
+    double *phi_out;                 // full grid (written when e is given)
     const T *e;                      // level-0 correction or nullptr
     const double *P;                 // full grid
     LevelArgs<T> L0;                 // r and sig written
@@ -139,6 +137,12 @@ constexpr int kCoarseLdsBytes = 64 * 1024;
 
 void launch_reduce(const double *part, int nparts, SolveCtrl *ctrl, int count_cycle, hipStream_t st);
 void launch_ctrl_reset(SolveCtrl *ctrl, int max_cycles, double tol2, hipStream_t st);
+struct ExtrapArgs {
+    int nin;
+    double c[4];
+    const double *in[4];
+};
+void launch_extrap(double *out, const ExtrapArgs &a, size_t n, hipStream_t st);
 void launch_fill(double *x, size_t n, double v, hipStream_t st);
 
 }  // namespace fx

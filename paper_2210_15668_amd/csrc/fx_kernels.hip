@@ -213,7 +213,7 @@ __global__ __launch_bounds__(256) void k_tdgl(TdglArgs a) {
 }
 
 // ------------------------------------------------------ fine-level residual
-// MODE 0: residual at phi_in; 1: at 2 phi_in - phi_prev; 2: at phi_in + clip(e).
+// MODE 0: residual at phi_in; MODE 2: at phi_in + clip(e), written to phi_out.
 // Each thread owns a column of ZT planes.  All loads are issued before any
 // arithmetic (clamped indices instead of boundary branches; the z-neighbours
 // of the column's planes are loaded once) so a wave makes one memory round
@@ -258,7 +258,6 @@ __global__ __launch_bounds__(256) void k_residual(ResArgs<T> a) {
     auto at = [&](int k, int o, int par, double *dst) {
         const int c = k * nxy + col + o;
         double v = phi[c];
-        if (MODE == 1) v = 2.0 * v - a.phi_prev[off + c];
         if (MODE == 2) {
             const double d = (double)a.e[rb ? (par ? half : 0) + (c >> 1) : c];
             const double lim = (a.pflags[k] & PF_SC) ? a.dmax : big;
@@ -605,6 +604,15 @@ __global__ __launch_bounds__(512) void k_coarse(const CoarseArgs<T> *A, const So
     }
 }
 
+// out = sum_q c[q] in[q] over n contiguous values (polynomial extrapolation in time).
+__global__ __launch_bounds__(256) void k_extrap(double *out, ExtrapArgs a, size_t n) {
+    for (size_t c = blockIdx.x * (size_t)blockDim.x + threadIdx.x; c < n; c += (size_t)gridDim.x * blockDim.x) {
+        double v = a.c[0] * a.in[0][c];
+        for (int q = 1; q < a.nin; ++q) v += a.c[q] * a.in[q][c];
+        out[c] = v;
+    }
+}
+
 __global__ void k_fill(double *x, size_t n, double v) {
     for (size_t c = blockIdx.x * (size_t)blockDim.x + threadIdx.x; c < n; c += (size_t)gridDim.x * blockDim.x) x[c] = v;
 }
@@ -623,8 +631,6 @@ int launch_residual(const ResArgs<T> &a, hipStream_t st) {
     const int n = tiles(a.nx, a.ny, (a.nzd + kResZ - 1) / kResZ);
     if (a.e)
         hipLaunchKernelGGL((k_residual<T, 2, kResZ>), tile_grid(n), dim3(BX, BY), 0, st, a);
-    else if (a.phi_prev)
-        hipLaunchKernelGGL((k_residual<T, 1, kResZ>), tile_grid(n), dim3(BX, BY), 0, st, a);
     else
         hipLaunchKernelGGL((k_residual<T, 0, kResZ>), tile_grid(n), dim3(BX, BY), 0, st, a);
     return n;
@@ -682,6 +688,11 @@ void launch_reduce(const double *part, int nparts, SolveCtrl *ctrl, int count_cy
 
 void launch_ctrl_reset(SolveCtrl *ctrl, int max_cycles, double tol2, hipStream_t st) {
     hipLaunchKernelGGL(k_ctrl_reset, dim3(1), dim3(1), 0, st, ctrl, max_cycles, tol2);
+}
+
+void launch_extrap(double *out, const ExtrapArgs &a, size_t n, hipStream_t st) {
+    const size_t b = (n + 255) / 256;
+    hipLaunchKernelGGL(k_extrap, dim3(b < 8192 ? (unsigned)b : 8192u), dim3(256), 0, st, out, a, n);
 }
 
 void launch_fill(double *x, size_t n, double v, hipStream_t st) {

@@ -125,7 +125,7 @@ fx_status validate(const fx_stack_desc *d, Plan *p) {
         return fail(FX_EINVAL, "plane tables must not be NULL");
     if (d->prec != FX_PREC_FP64 && d->prec != FX_PREC_MIXED) return fail(FX_EINVAL, "unknown precision");
     if (!(d->tol_rel > 0) || d->max_cycles < 1) return fail(FX_EINVAL, "tol_rel > 0 and max_cycles >= 1 required");
-    if (d->flags != 0) return fail(FX_EINVAL, "flags must be 0");
+    if (d->warm_start < 0 || d->warm_start > 3) return fail(FX_EINVAL, "warm_start must be 0..3");
     p->nx = d->nx; p->ny = d->ny; p->nz = d->nz;
     p->kb = -1; p->kt = -1; p->f0 = -1; p->f1 = -1; p->sc0 = -1; p->sc1 = -1;
     bool any_sc = false;
@@ -276,12 +276,14 @@ struct fx_stack {
     // P: [0] the caller's array, [1] workspace; pcur holds P^n
     double *P[2] = {nullptr, nullptr};
     int pcur = 0;
-    // phi: [0] the caller's array, [1..3] workspace; phicur holds phi^n and,
-    // when hist is set, phiprev holds phi^{n-1} of the previous time step.
-    // A solve writes its iterates into the two buffers that are neither, so
-    // the entry state survives a failed solve.
-    double *phi[4] = {nullptr, nullptr, nullptr, nullptr};
-    int phicur = 0, phiprev = 1;
+    // phi: [0] the caller's array, [1..5] workspace; phicur holds phi^n and
+    // prev[0..hist-1] hold phi^{n-1}, phi^{n-2}, phi^{n-3} of the previous time
+    // steps.  A solve writes its iterates into two buffers that are none of
+    // these, so the entry state survives a failed solve.
+    static constexpr int kPhiBufs = 6, kMaxHist = 3;
+    double *phi[kPhiBufs] = {};
+    int phicur = 0;
+    int prev[kMaxHist] = {1, 2, 3};
     int hist = 0;
     // finest-level FP64 tables
     double *t_cxy = nullptr, *t_czm = nullptr, *t_czp = nullptr, *t_wl = nullptr, *t_wr = nullptr;
@@ -313,7 +315,7 @@ size_t carve(fx_stack *s, void *ws) {
     const Plan &p = s->plan;
     const size_t nfull = (size_t)p.nx * p.ny * p.nz;
     s->P[1] = (double *)cv.take(nfull * sizeof(double));
-    for (int b = 1; b < 4; ++b) s->phi[b] = (double *)cv.take(nfull * sizeof(double));
+    for (int b = 1; b < fx_stack::kPhiBufs; ++b) s->phi[b] = (double *)cv.take(nfull * sizeof(double));
     const int nzd = p.nzd;
     s->t_cxy = (double *)cv.take(nzd * sizeof(double));
     s->t_czm = (double *)cv.take(nzd * sizeof(double));
@@ -481,7 +483,7 @@ void vcycle(fx_stack *s, const DevSet<T> &D, int l, const UpdArgs *upd = nullptr
 // count_cycle: this residual closes a multigrid cycle (the device counts it).
 template <typename T>
 void residual(fx_stack *s, const DevSet<T> &D, const double *phi_in, double *phi_out, bool with_e,
-              const double *phi_prev, bool count_cycle) {
+              bool count_cycle) {
     const Plan &p = s->plan;
     ResArgs<T> a;
     a.nx = p.nx; a.ny = p.ny; a.nzd = p.nzd; a.kb = p.kb;
@@ -494,7 +496,6 @@ void residual(fx_stack *s, const DevSet<T> &D, const double *phi_in, double *phi
     a.cxy = s->t_cxy; a.czm = s->t_czm; a.czp = s->t_czp;
     a.wl = s->t_wl; a.wr = s->t_wr; a.p0e = s->t_p0e; a.n0e = s->t_n0e; a.pflags = s->t_flags;
     a.phi_in = phi_in;
-    a.phi_prev = phi_prev;
     a.phi_out = phi_out;
     a.e = with_e ? D.lv[0].e : nullptr;
     a.P = s->P[s->pcur];
@@ -511,24 +512,41 @@ fx_status read_ctrl(fx_stack *s) {
     return FX_OK;
 }
 
-// Newton-multigrid solve.  The iterate before cycle 0 is phi^n, or (with
-// extrapolate set and a previous time level available) 2 phi^n - phi^{n-1}
+bool holds_history(const fx_stack *s, int b) {
+    for (int m = 0; m < s->hist; ++m)
+        if (s->prev[m] == b) return true;
+    return false;
+}
+
+// Lagrange extrapolation to t^{n+1} through t^n, t^{n-1}, ... (equal steps).
+const double kExtrap[4][4] = {{1, 0, 0, 0}, {2, -1, 0, 0}, {3, -3, 1, 0}, {4, -6, 4, -1}};
+
+// Newton-multigrid solve.  The iterate before cycle 0 is phi^n, or (in the
+// time loop, with previous levels held) their polynomial extrapolation
 // written to buffer other[1].  Cycle c writes other[c % 2] from the previous
 // iterate; kernels of cycles after the device has decided to stop return at
 // once, so a batch of cycles is enqueued before each host check.
 template <typename T>
-fx_status solve_impl(fx_stack *s, const DevSet<T> &D, fx_solve_info *info, bool extrapolate) {
+fx_status solve_impl(fx_stack *s, const DevSet<T> &D, fx_solve_info *info, bool time_step) {
     const Plan &p = s->plan;
-    const size_t nxy = (size_t)p.nx * p.ny;
+    const size_t nxy = (size_t)p.nx * p.ny, off = (size_t)p.kb * nxy, nd = (size_t)p.nzd * nxy;
     const int entry = s->phicur;
     int other[2], no = 0;
-    for (int b = 0; b < 4 && no < 2; ++b)
-        if (b != entry && b != s->phiprev) other[no++] = b;
-    const bool ex = extrapolate && s->hist;
+    for (int b = 0; b < fx_stack::kPhiBufs && no < 2; ++b)
+        if (b != entry && !holds_history(s, b)) other[no++] = b;
+    const int order = time_step ? std::min(s->hist, std::max(0, std::min(s->d.warm_start, fx_stack::kMaxHist))) : 0;
     launch_ctrl_reset(s->ctrl, s->d.max_cycles, s->d.tol_rel * s->d.tol_rel, s->st);
-    const int start = ex ? other[1] : entry;     // buffer holding the iterate before cycle 0
-    if (ex) residual<T>(s, D, s->phi[entry], s->phi[start], false, s->phi[s->phiprev], false);
-    else residual<T>(s, D, s->phi[entry], nullptr, false, nullptr, false);
+    const int start = order > 0 ? other[1] : entry;   // buffer holding the iterate before cycle 0
+    if (order > 0) {
+        ExtrapArgs ea;
+        ea.nin = order + 1;
+        for (int q = 0; q <= order; ++q) {
+            ea.c[q] = kExtrap[order][q];
+            ea.in[q] = s->phi[q == 0 ? entry : s->prev[q - 1]] + off;
+        }
+        launch_extrap(s->phi[start] + off, ea, nd, s->st);
+    }
+    residual<T>(s, D, s->phi[start], nullptr, false, false);
     int enq = 0;                        // cycles enqueued so far
     int batch = s->trace ? 0 : std::max(1, s->k_pred);
     fx_status st;
@@ -538,12 +556,12 @@ fx_status solve_impl(fx_stack *s, const DevSet<T> &D, fx_solve_info *info, bool 
             const double *src = s->phi[enq == 0 ? start : other[(enq - 1) % 2]];
             double *dst = s->phi[other[enq % 2]];
             if (fold) {
-                const UpdArgs u{src + (size_t)p.kb * nxy, dst + (size_t)p.kb * nxy, s->t_flags, s->dmax};
+                const UpdArgs u{src + off, dst + off, s->t_flags, s->dmax};
                 vcycle<T>(s, D, 0, &u);
-                residual<T>(s, D, dst, nullptr, false, nullptr, true);
+                residual<T>(s, D, dst, nullptr, false, true);
             } else {
                 vcycle<T>(s, D, 0);
-                residual<T>(s, D, src, dst, true, nullptr, true);
+                residual<T>(s, D, src, dst, true, true);
             }
         }
         if ((st = read_ctrl(s))) return st;
@@ -564,14 +582,19 @@ fx_status solve_impl(fx_stack *s, const DevSet<T> &D, fx_solve_info *info, bool 
         newcur = entry;                 // the entry iterate is untouched
     } else if (c.done == 1 && fn == 0.0 && rn != 0.0) {
         // f = 0: N(0) = 0 exactly, so phi = 0 is the root
-        launch_fill(s->phi[final_buf] + (size_t)p.kb * nxy, (size_t)p.nzd * nxy, 0.0, s->st);
+        launch_fill(s->phi[final_buf] + off, nd, 0.0, s->st);
         rn = 0.0;
     } else if (c.done != 1) {
         res = FX_ENOCONV;
     }
-    // phi^{n-1} for the next extrapolation is this solve's entry iterate
-    s->hist = extrapolate && res == FX_OK && newcur != entry;
-    if (s->hist) s->phiprev = entry;
+    // the entry iterate phi^n becomes the newest stored level
+    if (time_step && res == FX_OK && newcur != entry) {
+        for (int m = fx_stack::kMaxHist - 1; m > 0; --m) s->prev[m] = s->prev[m - 1];
+        s->prev[0] = entry;
+        s->hist = std::min(s->hist + 1, fx_stack::kMaxHist);
+    } else {
+        s->hist = 0;
+    }
     s->phicur = newcur;
     if (res != FX_ENONFINITE) s->k_pred = std::max(1, ncyc);
     if (info) { info->cycles = ncyc; info->status = res; info->res_norm = rn; info->rhs_norm = fn; }
@@ -619,13 +642,14 @@ fx_status sync_to_caller(fx_stack *s) {
         s->pcur = 0;
     }
     if (s->phicur != 0) {
-        // buffer 0 is the caller's: if it holds phi^{n-1}, swap roles first
-        if (s->phiprev == 0) {
+        // buffer 0 is the caller's: if it holds a stored level, move that level first
+        for (int m = 0; m < s->hist; ++m) {
+            if (s->prev[m] != 0) continue;
             int spare = 1;
-            while (spare == s->phicur) ++spare;
+            while (spare == s->phicur || holds_history(s, spare)) ++spare;
             HIP_OK(hipMemcpyAsync(s->phi[spare] + p.kb * nxy, s->phi[0] + p.kb * nxy,
                                   (size_t)p.nzd * nxy * sizeof(double), hipMemcpyDeviceToDevice, s->st));
-            s->phiprev = spare;
+            s->prev[m] = spare;
         }
         HIP_OK(hipMemcpyAsync(s->phi[0] + p.kb * nxy, s->phi[s->phicur] + p.kb * nxy,
                               (size_t)p.nzd * nxy * sizeof(double), hipMemcpyDeviceToDevice, s->st));
@@ -740,7 +764,7 @@ fx_status init_stack(const fx_stack_desc *desc, double *d_P, double *d_phi, void
         launch_fill(s->P[0], nfull, 0.0, s->st);
     }
     // Step 0: phi^{0,(0)} = 0, then solve
-    for (int b = 0; b < 4; ++b) launch_fill(s->phi[b], nfull, 0.0, s->st);
+    for (int b = 0; b < fx_stack::kPhiBufs; ++b) launch_fill(s->phi[b], nfull, 0.0, s->st);
     set_contacts(s);
     *out = s;
     st = solve(s, nullptr);
@@ -797,17 +821,17 @@ fx_status run_steps(fx_stack *s, int nsteps, double dt, const double *h_v_top_sc
 fx_status get_field(fx_stack *s, int which, double *h_out) {
     g_err.clear();
     if (!s || !h_out) return fail(FX_EINVAL, "NULL argument");
-    if (which != FX_FIELD_P && which != FX_FIELD_PHI && which != FX_FIELD_PHI_PREV)
-        return fail(FX_EINVAL, "unknown field %d", which);
+    if (which < FX_FIELD_P || which > FX_FIELD_PHI_PREV3) return fail(FX_EINVAL, "unknown field %d", which);
     fx_status st = sync_to_caller(s);
     if (st) return st;
     const Plan &p = s->plan;
     const size_t nxy = (size_t)p.nx * p.ny, n = nxy * p.nz;
-    if (which == FX_FIELD_PHI_PREV) {
-        if (!s->hist) return fail(FX_ESTATE, "no previous time level is held");
+    if (which >= FX_FIELD_PHI_PREV) {
+        const int m = which - FX_FIELD_PHI_PREV;
+        if (m >= s->hist) return fail(FX_ESTATE, "time level n-%d is not held", m + 1);
         // device planes from the history buffer, contacts from the caller's array
         HIP_OK(hipMemcpyAsync(h_out, s->phi[0], n * sizeof(double), hipMemcpyDeviceToHost, s->st));
-        HIP_OK(hipMemcpyAsync(h_out + p.kb * nxy, s->phi[s->phiprev] + p.kb * nxy, (size_t)p.nzd * nxy * sizeof(double),
+        HIP_OK(hipMemcpyAsync(h_out + p.kb * nxy, s->phi[s->prev[m]] + p.kb * nxy, (size_t)p.nzd * nxy * sizeof(double),
                               hipMemcpyDeviceToHost, s->st));
     } else {
         HIP_OK(hipMemcpyAsync(h_out, which == FX_FIELD_P ? s->P[0] : s->phi[0], n * sizeof(double),
@@ -820,18 +844,21 @@ fx_status get_field(fx_stack *s, int which, double *h_out) {
 fx_status set_field(fx_stack *s, int which, const double *h_in) {
     g_err.clear();
     if (!s || !h_in) return fail(FX_EINVAL, "NULL argument");
-    if (which != FX_FIELD_P && which != FX_FIELD_PHI && which != FX_FIELD_PHI_PREV)
-        return fail(FX_EINVAL, "unknown field %d", which);
+    if (which < FX_FIELD_P || which > FX_FIELD_PHI_PREV3) return fail(FX_EINVAL, "unknown field %d", which);
     fx_status st = sync_to_caller(s);
     if (st) return st;
     const Plan &p = s->plan;
     const size_t nxy = (size_t)p.nx * p.ny, n = nxy * p.nz;
-    if (which == FX_FIELD_PHI_PREV) {
-        s->phiprev = 1;                 // phicur is 0 after sync_to_caller
-        HIP_OK(hipMemcpyAsync(s->phi[1] + p.kb * nxy, h_in + p.kb * nxy, (size_t)p.nzd * nxy * sizeof(double),
+    if (which >= FX_FIELD_PHI_PREV) {
+        const int m = which - FX_FIELD_PHI_PREV;
+        if (m != s->hist) return fail(FX_ESTATE, "set time level n-%d after n-1 .. n-%d", m + 1, m);
+        int b = 1;                      // phicur is 0 after sync_to_caller
+        while (holds_history(s, b)) ++b;
+        HIP_OK(hipMemcpyAsync(s->phi[b] + p.kb * nxy, h_in + p.kb * nxy, (size_t)p.nzd * nxy * sizeof(double),
                               hipMemcpyHostToDevice, s->st));
         HIP_OK(hipStreamSynchronize(s->st));
-        s->hist = 1;
+        s->prev[m] = b;
+        s->hist = m + 1;
         return FX_OK;
     }
     s->hist = 0;

@@ -19,7 +19,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libferrox.so")
 
 FX_OK, FX_EINVAL, FX_ENOMEM, FX_EDEVICE, FX_ENOCONV, FX_ENONFINITE, FX_ESTATE = range(7)
-FIELD_P, FIELD_PHI, FIELD_PHI_PREV = 0, 1, 2
+FIELD_P, FIELD_PHI, FIELD_PHI_PREV, FIELD_PHI_PREV2, FIELD_PHI_PREV3 = 0, 1, 2, 3, 4
 PROBE_OFF, PROBE_SMOOTH_FINE = 0, 1
 _STATUS = {0: "FX_OK", 1: "FX_EINVAL", 2: "FX_ENOMEM", 3: "FX_EDEVICE", 4: "FX_ENOCONV",
            5: "FX_ENONFINITE", 6: "FX_ESTATE"}
@@ -44,7 +44,7 @@ class StackDesc(ctypes.Structure):
                 ("ni", ctypes.c_double), ("T", ctypes.c_double),
                 ("v_bottom", ctypes.c_double), ("v_top", ctypes.c_double),
                 ("tol_rel", ctypes.c_double), ("max_cycles", ctypes.c_int),
-                ("prec", ctypes.c_int), ("flags", ctypes.c_int)]
+                ("prec", ctypes.c_int), ("warm_start", ctypes.c_int)]
 
 
 class SolveInfo(ctypes.Structure):
@@ -112,7 +112,7 @@ class _DescHolder:
                            dp(self.eps), dp(self.na), dp(self.nd),
                            spec.alpha, spec.beta, spec.gamma, spec.g11, spec.g44, spec.Gamma,
                            spec.pbc, spec.lam, spec.ni, spec.T, spec.v_bottom, spec.v_top,
-                           spec.tol_rel, spec.max_cycles, spec.prec, 0)
+                           spec.tol_rel, spec.max_cycles, spec.prec, spec.warm_start)
 
 
 def workspace_bytes(spec: W.StackSpec) -> int:

@@ -72,6 +72,7 @@ class StackSpec:
     tol_rel: float = 1e-10
     max_cycles: int = 60
     prec: int = PREC_FP64
+    warm_start: int = 3          # extrapolation order of each step's starting iterate
 
     @property
     def ncell(self) -> int:

@@ -145,7 +145,7 @@ def test_zero_rhs_gives_zero_phi(fx):
 
 def test_resume_and_determinism(fx):
     """N1 + N2 steps equal N steps bitwise, and two identical runs agree bitwise."""
-    spec = W.shrink_lateral(W.mfism_large(), 32, 32)
+    spec = W.shrink_lateral(W.mfism_large(), 32, 32).copy(tol_rel=1e-13)
     P0 = W.random_P(spec, 4)
     a = make_stack(fx, spec, P0)
     a.run_steps(6, W.DT)
@@ -158,7 +158,8 @@ def test_resume_and_determinism(fx):
     c = make_stack(fx, spec, P0)
     c.set(fx.FIELD_P, b.get(fx.FIELD_P))
     c.set(fx.FIELD_PHI, b.get(fx.FIELD_PHI))
-    c.set(fx.FIELD_PHI_PREV, b.get(fx.FIELD_PHI_PREV))
+    for f in (fx.FIELD_PHI_PREV, fx.FIELD_PHI_PREV2, fx.FIELD_PHI_PREV3):
+        c.set(f, b.get(f))
     a.run_steps(3, W.DT)
     c.run_steps(3, W.DT)
     assert np.array_equal(a.get(fx.FIELD_P), c.get(fx.FIELD_P))
@@ -170,7 +171,7 @@ def test_resume_and_determinism(fx):
     with pytest.raises(fx.FerroxError):
         d.get(fx.FIELD_PHI_PREV)
     d.run_steps(3, W.DT)
-    assert rel(d.get(fx.FIELD_PHI), a.get(fx.FIELD_PHI)) <= 1e-8
+    assert rel(d.get(fx.FIELD_PHI), a.get(fx.FIELD_PHI)) <= 1e-10
 
 
 def test_error_paths(fx):
@@ -191,3 +192,17 @@ def test_error_paths(fx):
     assert np.array_equal(s.get(fx.FIELD_PHI), phi_before)
     with pytest.raises(fx.FerroxError):
         s.tdgl_step(-1.0)
+
+
+@pytest.mark.parametrize("order", [0, 1, 2, 3])
+def test_warm_start_orders_reach_the_same_root(fx, orc, order):
+    """Starting each solve from phi^n (the paper's Step 1b) or from its linear, quadratic or
+    cubic extrapolation in time changes only the iterate count, not the answer."""
+    spec = W.shrink_lateral(W.mfism_large(), 32, 32).copy(tol_rel=1e-13, warm_start=order)
+    P0 = W.random_P(spec, 6)
+    s = make_stack(fx, spec, P0)
+    info = s.run_steps(6, W.DT)
+    P_o, phi_o, _ = orc.run(spec, P0, 6, W.DT, tol=1e-13)
+    say(f"  warm_start {order}: {info.total_cycles / 6:.2f} cycles/step")
+    assert rel(s.get(fx.FIELD_P), P_o) <= 1e-10
+    assert rel(s.get(fx.FIELD_PHI), phi_o) <= 1e-10
