@@ -25,15 +25,20 @@
  *    host pointers ("h_") are ordinary process memory.  All work is enqueued
  *    on the stream given to init_stack (a hipStream_t passed as void*;
  *    NULL = the null stream).  Calls return after enqueueing, except where a
- *    host-visible decision is needed (poisson_solve and run_steps read the
- *    residual norm back once per multigrid cycle and therefore synchronise
- *    the stream).
+ *    host-visible result is needed: init_stack, poisson_solve and run_steps
+ *    (and their batch forms) synchronise the stream.  Convergence is decided
+ *    on the device; the host reads the solver state back after a few
+ *    predicted cycles of a single solve, and every few time steps of a run,
+ *    only to learn whether the work it enqueued has finished.
  *  - Errors are reported by fx_status; no exception crosses the ABI.
  *    last_error() returns a message for the most recent failure on the
  *    calling thread.  A stack is not thread-safe: use it from one thread.
- *  - The library allocates no device memory after init_stack: the caller
- *    passes the fields and one workspace buffer.  init_stack allocates a
- *    small pinned host buffer for norm read-back and host-side tables.
+ *  - The library allocates no device memory: the caller passes the fields
+ *    and one workspace buffer.  init_stack allocates a small pinned host
+ *    buffer for reading the solver state back, and host-side tables.
+ *  - Batches (init_batch ...) hold many independent stacks of different
+ *    sizes that advance together: each launch covers the tiles of all
+ *    instances, and every instance stops its own solves.
  */
 #ifndef FERROX_H
 #define FERROX_H
@@ -71,6 +76,7 @@ typedef enum { FX_PREC_FP64 = 0, FX_PREC_MIXED = 1 } fx_precision;
 enum { FX_FIELD_P = 0, FX_FIELD_PHI = 1, FX_FIELD_PHI_PREV = 2, FX_FIELD_PHI_PREV2 = 3, FX_FIELD_PHI_PREV3 = 4 };
 
 typedef struct fx_stack fx_stack;
+typedef struct fx_batch fx_batch;
 
 /* Problem statement (Table 1 and Methods of the paper).  Host arrays are
  * read during init_stack only. */
@@ -176,20 +182,34 @@ fx_status get_field(fx_stack *s, int which, double *h_out);
 fx_status set_field(fx_stack *s, int which, const double *h_in);
 
 /* Kernel-duration probe (instrumentation for roofline measurement).
- * While FX_PROBE_SMOOTH_FINE is on, each launch of the finest-level
- * Gauss-Seidel half-sweep (the kernel that moves the most bytes per step) is
- * timestamped by its own dispatch (hipExtLaunchKernelGGL start/stop events,
- * no extra stream work), up to max_launches launches, and the algorithmic
- * bytes of those launches are summed: one touch each of the other colour's
- * correction, this colour's right-hand side, sigma and correction (FP64:
- * 8 bytes, mixed: 4 bytes per value), plus 16 bytes per cell for the phi
- * pair read and written when the Newton update is folded into the last
- * half-sweep.  stack_probe resets the counters (and synchronises the
- * stream); stack_probe_read synchronises and returns the summed duration in
- * ms, the number of timed launches and the bytes. */
+ * While FX_PROBE_SMOOTH_FINE is on, every stride-th launch of the
+ * finest-level Gauss-Seidel half-sweep (the kernel that moves the most bytes
+ * per step) is timestamped by its own dispatch (hipExtLaunchKernelGGL
+ * start/stop events, no extra stream work), up to max_launches (<= 4096)
+ * timed launches, and the kernel itself adds up the algorithmic bytes of the
+ * instances it worked on: one touch each of the other colour's correction,
+ * this colour's right-hand side, sigma and correction (FP64: 8 bytes, mixed:
+ * 4 bytes per value), plus 16 bytes per cell for the phi pair read and
+ * written when the Newton update is folded into the last half-sweep.
+ * Launches in which every solve had already stopped do no work and are not
+ * counted.  stack_probe resets the counters (and synchronises the stream);
+ * stack_probe_read synchronises and returns the summed duration in ms, the
+ * number of counted launches and their bytes.  Runs use kernel-by-kernel
+ * launches while the probe is on. */
 enum { FX_PROBE_OFF = 0, FX_PROBE_SMOOTH_FINE = 1 };
-fx_status stack_probe(fx_stack *s, int kernel, int max_launches);
+fx_status stack_probe(fx_stack *s, int kernel, int max_launches, int stride);
 fx_status stack_probe_read(fx_stack *s, double *total_ms, int *launches, double *bytes);
+
+/* How run_steps / run_batch enqueue their work.  STREAM: kernel by kernel.
+ * GRAPH: the repeating unit of a run (one multigrid cycle for every running
+ * solve, then the finalization of stopped solves and the start of the next
+ * time step where due) is captured once as a HIP graph (1, 2, 4, 8 and 16
+ * units) on a private stream and replayed on the caller's stream.  Results
+ * are identical.  Defaults: STREAM for stacks, GRAPH for batches (the
+ * environment variable FERROX_LAUNCH=0/1 overrides the default).  While a
+ * probe is on, runs use STREAM. */
+enum { FX_LAUNCH_STREAM = 0, FX_LAUNCH_GRAPH = 1 };
+fx_status stack_set_launch(fx_stack *s, int mode);
 
 /* Number of multigrid levels and the sizes of level l (for diagnostics). */
 int stack_num_levels(const fx_stack *s);
@@ -197,6 +217,43 @@ fx_status stack_level_shape(const fx_stack *s, int level, int *nx, int *ny, int 
 
 /* Release the stack handle (not the caller's device buffers). */
 fx_status destroy_stack(fx_stack *s);
+
+/* ---------------------------------------------------------------- batches
+ * n independent stacks (1 <= n <= 4096) of any sizes, one precision.  Each
+ * instance behaves as a stack of its own would: same Step 0, same time
+ * steps, same results; the instances only share launches.  Workspace:
+ * batch_workspace_bytes(descs, n), 256-byte aligned; d_P[i], d_phi[i] are
+ * caller-owned device arrays of instance i's nx*ny*nz doubles (16-byte
+ * aligned), holding P^0 on entry and the current P and phi after every call,
+ * as for init_stack.  init_batch returns the first failing instance's
+ * FX_ENOCONV / FX_ENONFINITE if a Step 0 solve fails (the batch is still
+ * created). */
+typedef struct {
+    int status;                  /* fx_status of the instance's last solve in this call     */
+    int steps_done;
+    int total_cycles;
+    int max_cycles_step;
+    double last_res_rel;
+} fx_batch_info;
+
+size_t batch_workspace_bytes(const fx_stack_desc *descs, int n);
+fx_status init_batch(const fx_stack_desc *descs, int n, double *const *d_P, double *const *d_phi, void *d_ws,
+                     size_t ws_bytes, void *stream, fx_batch **out);
+
+/* nsteps time steps of every instance.  h_v_top_sched: NULL, or n host
+ * arrays of nsteps gate potentials (entry m for the solve producing
+ * phi^{n+m+1}).  An instance whose solve fails stops there (its
+ * info[i].status says why) while the others go on; the call returns FX_OK
+ * when every instance completed, else the status of the first failed one.
+ * info: NULL or n entries. */
+fx_status run_batch(fx_batch *b, int nsteps, double dt, const double *const *h_v_top_sched,
+                    fx_batch_info *info);
+
+/* Copy instance inst's current P, phi or stored level (FX_FIELD_*) to host
+ * memory, as get_field. */
+fx_status batch_get_field(fx_batch *b, int inst, int which, double *h_out);
+fx_status batch_set_launch(fx_batch *b, int mode);
+fx_status destroy_batch(fx_batch *b);
 
 /* Message of the most recent failing call on this thread ("" if none). */
 const char *last_error(void);

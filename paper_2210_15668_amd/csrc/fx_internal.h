@@ -1,4 +1,12 @@
-// Internal declarations shared by the HIP kernels and the host driver.
+// Internal declarations shared by the HIP kernels and the host engine.
+//
+// Every kernel is multi-instance: one launch covers the tiles of all
+// instances of a batch (a single stack is a batch of one).  A launch gets the
+// instance array and a prefix table of per-instance tile counts, and decodes
+// its block into (instance, local tile).  All per-solve control -- which phi
+// buffer holds which iterate, the stop decision, the stored time levels --
+// lives in device memory (InstState), so a whole time step can be enqueued,
+// or captured in a HIP graph, without a host decision inside it.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -16,39 +24,47 @@ constexpr double kEps0 = 8.8541878128e-12;
 enum : int { PF_SC = 1, PF_P = 2 };
 
 constexpr int kMaxLevels = 24;
+constexpr int kPhiBufs = 6;       // phi^n, up to 3 stored levels, two iterate buffers
+constexpr int kMaxHist = 3;
+constexpr int kCoarseLdsBytes = 64 * 1024;
 
-// Device-side state of one Poisson solve.  done: 0 running, 1 converged,
-// 2 non-finite residual, 3 cycle budget exhausted.  Kernels of a cycle
-// return immediately once done != 0, so cycles can be enqueued ahead of the
-// host's convergence check.
-struct SolveCtrl {
-    int done;
-    int cycles;
-    int max_cycles;
-    int pad;
-    double tol2;       // tol_rel^2
-    double rn2, fn2;   // ||r||^2, ||f||^2 of the latest residual (scaled units)
+// Mutable per-instance state of the current solve and of the time history.
+// Every instance runs its own state machine, driven by two kinds of slots:
+//  - an advance slot finalizes a solve that has stopped (history, status,
+//    step count) and, in a run, starts the next time step of instances that
+//    have not reached their target: TDGL update, flip of the P buffers,
+//    starting iterate, first residual;
+//  - a cycle slot performs one multigrid cycle + residual for every
+//    instance whose solve is still running.
+// A run is then a fixed sequence of slots (one advance slot, then pairs of
+// cycle and advance slots) that needs no host decision between its kernels.
+// done: 0 running, 1 converged, 2 non-finite residual, 3 cycle budget used.
+struct InstState {
+    int done, cycles;
+    int cur, start, oth0, oth1;       // phi buffers: phi^n, iterate before cycle 0, cycle outputs
+    int prev[kMaxHist], hist;         // stored time levels phi^{n-1..n-3}
+    int order;                        // extrapolation order of this solve
+    int zpend;                        // right-hand side exactly zero with a nonzero residual
+    int zero_fix;                     // phi := 0 for the solve finalized in this slot
+    int status;                       // fx_status of the last finalized solve
+    int step, target, sched_base, sched_len;
+    int pcur;                         // P buffer holding the current P
+    int ts;                           // the running solve belongs to a time step
+    int fresh;                        // solve started in this slot (first residual pending)
+    int insolve;                      // a solve is running or awaits finalization
+    int adv;                          // starts a time step in this advance slot
+    int parked;                       // run target reached or a solve failed
+    int solves, failed, total_cycles, max_cycles_step;
+    double v_top;                     // gate potential of the current solve
+    double dt;                        // time step of the run
+    double rn2, fn2;                  // ||r||^2, ||f||^2 of the latest residual (scaled units)
 };
 
-// --------------------------------------------------------------------- TDGL
-struct TdglArgs {
-    int nx, ny, f0, f1;          // ferroelectric planes [f0, f1) of the full grid
-    double h, dt;
-    double alpha, beta, gamma, g11, g44, Gamma;
-    int pbc;
-    double lambda;
-    const double *P;
-    const double *phi;
-    double *Pn;
-};
-void launch_tdgl(const TdglArgs &a, hipStream_t st);
-
-// One multigrid level as the kernels see it.  Storage of e and r: with rb
-// set (nx even, ny even or 1: a proper red/black colouring under periodic
-// wrap) the cells of colour (i+j+k)&1 == 0 come first, then colour 1, each
-// in z-major row order; otherwise plain z-major order.  sig holds planes
-// [sig_lo, sig_hi) in the same arrangement.  Every level has fewer than
-// 2^31 cells, so all indices are 32-bit.
+// One multigrid level.  Storage of e and r: with rb set (nx even, ny even or
+// 1: a proper red/black colouring under periodic wrap) the cells of colour
+// (i+j+k)&1 == 0 come first, then colour 1, each in z-major row order;
+// otherwise plain z-major order.  sig holds planes [sig_lo, sig_hi) in the
+// same arrangement.  Every level has fewer than 2^31 cells (32-bit indices).
 template <typename T>
 struct LevelArgs {
     int nx, ny, nz, rb;
@@ -69,80 +85,76 @@ struct XferArgs {
     int xy;                          // x and y halved
 };
 
-// ------------------------------------------------- fine-level residual (FP64)
-// phi_out = phi_in + clip(e) (when e is given), then r = s (f - N(phi_out))
-// on the device slab and sigma = s e (p + n) / VT on semiconductor planes;
-// s = h^2/eps0.  Per-tile partial sums of r^2 and (s f)^2.
+// Constant description of one instance (device memory, read by every kernel).
 template <typename T>
-struct ResArgs {
-    int nx, ny, nzd, kb;
-    double v_b, v_t;
-    double p_scale;              // h / eps0
-    double rho_scale;            // h^2 / eps0
-    double vt_inv;               // 1 / VT
-    double sig_scale;            // (h^2/eps0) / VT
-    double dmax;                 // Newton update clip on semiconductor planes
-    const double *cxy, *czm, *czp;   // scaled, per device plane
-    const double *wl, *wr;           // P face weights of the face above plane k
-    const double *p0e, *n0e;         // e * p0, e * n0 per device plane
+struct Inst {
+    int nx, ny, nz, kb, nzd, f0, f1;   // full grid, device slab [kb, kb+nzd), ferroelectric [f0, f1)
+    int nlev, lc, fold;                // levels; first level of the coarse kernel; update folded into smoothing
+    int max_cycles, warm;
+    double tol2;
+    // TDGL
+    double h, alpha, beta, gamma, g11, g44, Gamma, lambda;
+    int pbc;
+    // residual (scaled by s = h^2/eps0)
+    double v_b, p_scale, rho_scale, vt_inv, sig_scale, dmax;
+    const double *cxy0, *czm0, *czp0, *wl, *wr, *p0e, *n0e;
     const int *pflags;
-    const double *phi_in;            // full grid
-    double *phi_out;                 // full grid (written when e is given)
-    const T *e;                      // level-0 correction or nullptr
-    const double *P;                 // full grid
-    LevelArgs<T> L0;                 // r and sig written
-    double *part;
-    const SolveCtrl *ctrl;
-};
-template <typename T> int launch_residual(const ResArgs<T> &a, hipStream_t st);
-
-// Newton update folded into the last black half-sweep of the finest level:
-// phi_out = phi_in + clip(e) for each black cell and its red partner (the
-// pair 2m, 2m+1 of a row), pointers at the device slab.
-struct UpdArgs {
-    const double *phi_in;
-    double *phi_out;
-    const int *pflags;
-    double dmax;
-};
-
-// ev0/ev1 (optional): HIP events the dispatch itself timestamps.
-template <typename T> void launch_smooth(const LevelArgs<T> &L, int color, int zero_init, const SolveCtrl *ctrl,
-                                         hipStream_t st, const UpdArgs *upd = nullptr, hipEvent_t ev0 = nullptr,
-                                         hipEvent_t ev1 = nullptr);
-template <typename T> void launch_restrict(const LevelArgs<T> &F, const LevelArgs<T> &C, const XferArgs<T> &X,
-                                           const SolveCtrl *ctrl, hipStream_t st);
-template <typename T> void launch_prolong(const LevelArgs<T> &F, const LevelArgs<T> &C, const XferArgs<T> &X,
-                                          const SolveCtrl *ctrl, hipStream_t st);
-
-// All levels from the first one handed over down to the coarsest, in one
-// workgroup with every level resident in LDS: lv[0] is the handed-over level
-// (its r and sig are copied in from r_in / sig_in, its correction copied out
-// to e_out), xf[l] links lv[l] and lv[l+1].  off_* are byte offsets of each
-// level's arrays in the dynamic LDS allocation of lds_bytes.
-template <typename T>
-struct CoarseArgs {
-    int nlev, nu1, nu2, bottom_sweeps;
-    int lds_bytes;
+    const double *vsched;              // gate potentials of the run's steps (sched_len entries)
+    double *phi[kPhiBufs];
+    double *P[2];
+    double *part;                      // residual partial sums, 2 per residual tile
+    InstState *st;
+    // multigrid
     LevelArgs<T> lv[kMaxLevels];
     XferArgs<T> xf[kMaxLevels];
+    int nu1, nu2, lds_bytes;
     int off_e[kMaxLevels], off_r[kMaxLevels], off_s[kMaxLevels], off_t[kMaxLevels];
-    const T *r_in;
-    const T *sig_in;
-    T *e_out;
+    // conjugate-gradient bottom solve: search direction, product, reduction scratch (LDS offsets)
+    int off_p, off_q, off_red;
+    int bottom_iters;
+    double bottom_tol2;
 };
-template <typename T> void launch_coarse(const CoarseArgs<T> *dev_args, int lds_bytes, const SolveCtrl *ctrl,
-                                         hipStream_t st);
-constexpr int kCoarseLdsBytes = 64 * 1024;
 
-void launch_reduce(const double *part, int nparts, SolveCtrl *ctrl, int count_cycle, hipStream_t st);
-void launch_ctrl_reset(SolveCtrl *ctrl, int max_cycles, double tol2, hipStream_t st);
-struct ExtrapArgs {
-    int nin;
-    double c[4];
-    const double *in[4];
+// A launch over all instances: prefix[i] .. prefix[i+1] are instance i's tiles.
+struct Work {
+    const int *prefix;
+    int ninst;
+    int total;
 };
-void launch_extrap(double *out, const ExtrapArgs &a, size_t n, hipStream_t st);
+
+// ------------------------------------------------------------------ launchers
+// sel = 1 restricts a launch to the instances starting a time step in the
+// current advance slot; sel = 0 covers every instance.
+template <typename T> void launch_tdgl(const Inst<T> *I, const Work &w, int sel, hipStream_t st);
+template <typename T> void launch_flip(const Inst<T> *I, int ninst, hipStream_t st);
+template <typename T> void launch_begin(const Inst<T> *I, int ninst, int sel, hipStream_t st);
+template <typename T> void launch_extrap(const Inst<T> *I, const Work &w, hipStream_t st);
+// after_cycle 0: residual at the starting iterate of freshly begun solves;
+// 1: at the output of the cycle just run (forming phi_in + clip(e) first
+// where the update is not folded into the smoother: any_unfolded says
+// whether some instance is of that kind).
+template <typename T> void launch_residual(const Inst<T> *I, const Work &w, int after_cycle, int any_unfolded,
+                                           hipStream_t st);
+template <typename T> void launch_reduce(const Inst<T> *I, int ninst, int count_cycle, hipStream_t st);
+template <typename T> void launch_smooth(const Inst<T> *I, const Work &w, int level, int color, int zero_init,
+                                         int upd, int zt, double *probe, hipStream_t st, hipEvent_t ev0 = nullptr,
+                                         hipEvent_t ev1 = nullptr);
+template <typename T> void launch_restrict(const Inst<T> *I, const Work &w, int level, hipStream_t st);
+template <typename T> void launch_prolong(const Inst<T> *I, const Work &w, int level, hipStream_t st);
+template <typename T> void launch_coarse(const Inst<T> *I, int ninst, int lds_bytes, hipStream_t st);
+template <typename T> void launch_head(const Inst<T> *I, int ninst, int advance, hipStream_t st);
+template <typename T> void launch_zero_fix(const Inst<T> *I, const Work &w, hipStream_t st);
+template <typename T> void launch_run_setup(const Inst<T> *I, int ninst, int nsteps, int has_sched, double dt,
+                                            int first, hipStream_t st);
+template <typename T> void launch_set_vtop(const Inst<T> *I, int ninst, double v, hipStream_t st);
+void launch_put_state(InstState *dst, const InstState &v, hipStream_t st);
 void launch_fill(double *x, size_t n, double v, hipStream_t st);
+
+// Host-side tile counts (must match the kernels' decoding).
+constexpr int BX = 64;
+constexpr int BY = 4;
+__host__ __device__ inline int tiles3(int nxw, int ny, int nz) { return ((nxw + BX - 1) / BX) * ((ny + BY - 1) / BY) * nz; }
+constexpr int kResZ = 4;            // planes per thread in the fine-level residual
+constexpr int kExtrapChunk = 1024;  // cells per extrapolation tile
 
 }  // namespace fx

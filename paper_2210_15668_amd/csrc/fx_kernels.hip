@@ -1,13 +1,13 @@
 // HIP kernels of the TDGL + Poisson time step (gfx950, wave64).
 //
-// Layout: fields are z-major with x fastest.  Multigrid levels with an even
-// x-extent store their cells split by red/black colour (see LevelArgs), so
-// that each half-sweep of the Gauss-Seidel smoother streams two contiguous
-// arrays instead of touching every other element.  Workgroups are 64x4
-// threads (one wave per row); large launches use a 1D grid whose block
-// index is remapped so that each of the 8 XCDs walks one contiguous range of
-// tiles (consecutive planes and rows), keeping stencil neighbours in that
-// XCD's L2.
+// Layout: fields are z-major with x fastest.  Multigrid levels with even x
+// and y extents store their cells split by red/black colour (LevelArgs), so a
+// Gauss-Seidel half-sweep streams contiguous arrays.  Workgroups are 64x4
+// threads (one wave per row).  Every launch covers all instances of a batch:
+// a block's global tile index is first remapped so that each of the 8 XCDs
+// walks one contiguous range of tiles (consecutive planes and rows, keeping
+// stencil neighbours in that XCD's L2), then split into (instance, tile) by a
+// binary search in the launch's prefix table.
 #include "fx_internal.h"
 
 #include <hip/hip_ext.h>
@@ -16,55 +16,118 @@ namespace fx {
 
 namespace {
 
-constexpr int BX = 64;
-constexpr int BY = 4;
-
 __device__ __forceinline__ int wrap_p(int i, int n) { return i + 1 == n ? 0 : i + 1; }
 __device__ __forceinline__ int wrap_m(int i, int n) { return i == 0 ? n - 1 : i - 1; }
 
-struct Tile {
-    int tx, ty, k, id;
+// Explicit address spaces.  Pointers read from the instance table are
+// generic; used as such they become flat instructions, which need 64-bit
+// per-lane addresses and make every wait for a scalar load also wait for the
+// vector loads in flight.  The kernels therefore view the arrays through
+// global (1) pointers, and the coarse kernel its LDS copies through LDS (3)
+// pointers.
+#define FX_AS(n) __attribute__((address_space(n)))
+template <int AS, typename T>
+__device__ __forceinline__ T FX_AS(AS) *asp(T *p) { return (T FX_AS(AS) *)p; }
+
+typedef InstState FX_AS(1) GState;
+typedef double dpair __attribute__((ext_vector_type(2)));   // a 16-byte phi pair
+
+template <typename T, int AS>
+struct Lv {
+    using value_type = T;
+    int nx, ny, nz, rb;
+    const T FX_AS(AS) *cxy, *czm, *czp, *dg;
+    T FX_AS(AS) *e, *r, *sig;
+    int sig_lo, sig_hi;
+};
+
+template <typename T>
+struct Xv {
+    const int FX_AS(1) *cks, *ccnt, *fthick, *cthick, *pka, *pkb;
+    const T FX_AS(1) *pwa, *pwb;
+    int xy;
+};
+
+template <typename T>
+__device__ __forceinline__ Lv<T, 1> gview(const LevelArgs<T> &L) {
+    Lv<T, 1> v;
+    v.nx = L.nx; v.ny = L.ny; v.nz = L.nz; v.rb = L.rb;
+    v.cxy = asp<1>(L.cxy); v.czm = asp<1>(L.czm); v.czp = asp<1>(L.czp); v.dg = asp<1>(L.dg);
+    v.e = asp<1>(L.e); v.r = asp<1>(L.r); v.sig = asp<1>(L.sig);
+    v.sig_lo = L.sig_lo; v.sig_hi = L.sig_hi;
+    return v;
+}
+
+template <typename T>
+__device__ __forceinline__ Xv<T> xview(const XferArgs<T> &X) {
+    Xv<T> v;
+    v.cks = asp<1>(X.cks); v.ccnt = asp<1>(X.ccnt); v.fthick = asp<1>(X.fthick); v.cthick = asp<1>(X.cthick);
+    v.pka = asp<1>(X.pka); v.pkb = asp<1>(X.pkb); v.pwa = asp<1>(X.pwa); v.pwb = asp<1>(X.pwb);
+    v.xy = X.xy;
+    return v;
+}
+
+struct Blk {
+    int inst, t;
     bool ok;
 };
 
-// Tile of a 1D launch whose block count is a multiple of 8: XCD x (= block
-// index mod 8 under round-robin dispatch) gets tiles [x*nb/8, (x+1)*nb/8).
-__device__ __forceinline__ Tile tile_of(int ntx, int nty, int nz) {
+__device__ __forceinline__ Blk find_block(const Work &w) {
     const int nb = gridDim.x, b = blockIdx.x;
-    const int t = (b & 7) * (nb >> 3) + (b >> 3);
-    Tile r;
-    r.id = t;
-    r.ok = t < ntx * nty * nz;
-    r.tx = t % ntx;
-    const int q = t / ntx;
-    r.ty = q % nty;
-    r.k = q / nty;
+    const int g = (b & 7) * (nb >> 3) + (b >> 3);
+    Blk r;
+    r.ok = g < w.total;
+    r.inst = 0;
+    r.t = 0;
+    if (!r.ok) return r;
+    const int FX_AS(1) *pre = asp<1>(w.prefix);
+    int lo = 0, hi = w.ninst;                 // largest lo with prefix[lo] <= g
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (pre[mid] <= g) lo = mid;
+        else hi = mid;
+    }
+    r.inst = __builtin_amdgcn_readfirstlane(lo);
+    r.t = g - pre[r.inst];
     return r;
 }
 
-int tiles(int nxw, int ny, int nz) { return ((nxw + BX - 1) / BX) * ((ny + BY - 1) / BY) * nz; }
-dim3 tile_grid(int ntiles) { return dim3((ntiles + 7) / 8 * 8); }
+struct T3 {
+    int tx, ty, tz;
+};
+__device__ __forceinline__ T3 split3(int t, int nxw, int ny) {
+    const int ntx = (nxw + BX - 1) / BX, nty = (ny + BY - 1) / BY;
+    T3 r;
+    r.tx = t % ntx;
+    const int q = t / ntx;
+    r.ty = q % nty;
+    r.tz = q / nty;
+    return r;
+}
 
-template <typename T>
-__device__ __forceinline__ int cidx(const LevelArgs<T> &L, int i, int j, int k) {
+dim3 grid_of(int total) { return dim3((total + 7) / 8 * 8); }
+
+template <typename V>
+__device__ __forceinline__ int cidx(const V &L, int i, int j, int k) {
     const int lin = (k * L.ny + j) * L.nx + i;
     if (!L.rb) return lin;
     return (((i + j + k) & 1) ? ((L.nx * L.ny * L.nz) >> 1) : 0) + (lin >> 1);
 }
 
-template <typename T>
-__device__ __forceinline__ bool has_sig(const LevelArgs<T> &L, int k) { return k >= L.sig_lo && k < L.sig_hi; }
+template <typename V>
+__device__ __forceinline__ bool has_sig(const V &L, int k) { return k >= L.sig_lo && k < L.sig_hi; }
 
-template <typename T>
-__device__ __forceinline__ int sidx(const LevelArgs<T> &L, int i, int j, int k) {
+template <typename V>
+__device__ __forceinline__ int sidx(const V &L, int i, int j, int k) {
     const int lin = ((k - L.sig_lo) * L.ny + j) * L.nx + i;
     if (!L.rb) return lin;
     return (((i + j + k) & 1) ? ((L.nx * L.ny * (L.sig_hi - L.sig_lo)) >> 1) : 0) + (lin >> 1);
 }
 
 // sum over the 6 neighbours of coefficient * e(neighbour); Dirichlet neighbours are zero
-template <typename T>
-__device__ __forceinline__ T nb_sum(const LevelArgs<T> &L, const T *e, int i, int j, int k) {
+template <typename V, typename P>
+__device__ __forceinline__ typename V::value_type nb_sum(const V &L, P e, int i, int j, int k) {
+    using T = typename V::value_type;
     T s = 0;
     const T cx = L.cxy[k];
     if (L.nx > 1) s += cx * (e[cidx(L, wrap_p(i, L.nx), j, k)] + e[cidx(L, wrap_m(i, L.nx), j, k)]);
@@ -74,39 +137,51 @@ __device__ __forceinline__ T nb_sum(const LevelArgs<T> &L, const T *e, int i, in
     return s;
 }
 
-template <typename T>
-__device__ __forceinline__ T diag_of(const LevelArgs<T> &L, int i, int j, int k) {
-    T d = L.dg[k];
+template <typename V>
+__device__ __forceinline__ typename V::value_type diag_of(const V &L, int i, int j, int k) {
+    typename V::value_type d = L.dg[k];
     if (has_sig(L, k)) d += L.sig[sidx(L, i, j, k)];
     return d;
 }
 
 // Gauss-Seidel update of one cell of (L + diag sigma) e = r.
-template <typename T>
-__device__ __forceinline__ void gs_cell(const LevelArgs<T> &L, int i, int j, int k, int zero_init) {
+template <typename V>
+__device__ __forceinline__ void gs_cell(const V &L, int i, int j, int k, int zero_init) {
     const int c = cidx(L, i, j, k);
-    const T d = diag_of(L, i, j, k);
+    const auto d = diag_of(L, i, j, k);
     L.e[c] = zero_init ? L.r[c] / d : (L.r[c] + nb_sum(L, L.e, i, j, k)) / d;
+}
+
+// Colour of a cell on a plainly stored level (odd x or y extent).  With an
+// odd periodic extent the parity colouring makes the wrap neighbours equal
+// coloured, so the last column / row (for odd nx / ny) get colours 2 and 3:
+// no two cells of one colour are then neighbours, and a sweep is the four
+// colours in turn.
+template <typename V>
+__device__ __forceinline__ int nat_color(const V &L, int i, int j, int k) {
+    const int par = (i + j + k) & 1;
+    const bool edge = ((L.nx & 1) && i == L.nx - 1) || ((L.ny & 1) && j == L.ny - 1);
+    return edge ? 2 + par : par;
 }
 
 // Residual of the finer level restricted to one coarse cell: volume-weighted
 // mean over the children, likewise sigma.  On a red/black level the black
 // children are skipped: right after a black half-sweep their residual is
 // zero (each black equation has just been solved exactly).
-template <typename T>
-__device__ __forceinline__ void restrict_cell(const LevelArgs<T> &F, const LevelArgs<T> &C, const XferArgs<T> &X,
-                                              int I, int J, int K) {
-    const int nsub = X.xy ? 2 : 1;
+template <typename V, typename X>
+__device__ __forceinline__ void restrict_cell(const V &F, const V &C, const X &Xf, int I, int J, int K) {
+    using T = typename V::value_type;
+    const int nsub = Xf.xy ? 2 : 1;
     double sr = 0.0, ss = 0.0;
-    const int ks = X.cks[K], cnt = X.ccnt[K];
+    const int ks = Xf.cks[K], cnt = Xf.ccnt[K];
     for (int dz = 0; dz < cnt; ++dz) {
         const int k = ks + dz;
-        const double wz = (double)X.fthick[k] / (double)X.cthick[K];
+        const double wz = (double)Xf.fthick[k] / (double)Xf.cthick[K];
         const bool hs = has_sig(F, k);
         for (int dy = 0; dy < nsub; ++dy) {
-            const int j = X.xy ? 2 * J + dy : J;
+            const int j = Xf.xy ? 2 * J + dy : J;
             for (int dx = 0; dx < nsub; ++dx) {
-                const int i = X.xy ? 2 * I + dx : I;
+                const int i = Xf.xy ? 2 * I + dx : I;
                 const T sg = hs ? F.sig[sidx(F, i, j, k)] : T(0);
                 ss += wz * (double)sg;
                 if (F.rb && ((i + j + k) & 1)) continue;
@@ -116,23 +191,23 @@ __device__ __forceinline__ void restrict_cell(const LevelArgs<T> &F, const Level
             }
         }
     }
-    const double wxy = X.xy ? 0.25 : 1.0;
+    const double wxy = Xf.xy ? 0.25 : 1.0;
     C.r[cidx(C, I, J, K)] = (T)(sr * wxy);
     if (has_sig(C, K)) C.sig[sidx(C, I, J, K)] = (T)(ss * wxy);
 }
 
-// e_f += I e_c: bilinear in x,y (cell-centred 3/4, 1/4), linear in z between
-// coarse plane centres (zero on contact faces).  On a red/black level only
-// black cells are corrected: the red values are overwritten by the next red
-// half-sweep without being read.
-template <typename T>
-__device__ __forceinline__ void prolong_cell(const LevelArgs<T> &F, const LevelArgs<T> &C, const XferArgs<T> &X,
-                                             int i, int j, int k) {
+// e_f += I e_c: bilinear in x,y (cell-centred 3/4, 1/4), in z linear in the
+// series resistance between coarse plane centres (zero on contact faces).  On
+// a red/black level only black cells are corrected: the red values are
+// overwritten by the next red half-sweep without being read.
+template <typename V, typename X>
+__device__ __forceinline__ void prolong_cell(const V &F, const V &C, const X &Xf, int i, int j, int k) {
+    using T = typename V::value_type;
     if (F.rb && !((i + j + k) & 1)) return;
     int ix[2], jy[2];
     T wx[2], wy[2];
     int ns = 1;
-    if (X.xy) {
+    if (Xf.xy) {
         const int I = i >> 1, J = j >> 1;
         ix[0] = I; ix[1] = (i & 1) ? wrap_p(I, C.nx) : wrap_m(I, C.nx);
         jy[0] = J; jy[1] = (j & 1) ? wrap_p(J, C.ny) : wrap_m(J, C.ny);
@@ -143,8 +218,8 @@ __device__ __forceinline__ void prolong_cell(const LevelArgs<T> &F, const LevelA
         ix[0] = i; jy[0] = j; wx[0] = wy[0] = T(1);
     }
     T v = 0;
-    const int kz[2] = {X.pka[k], X.pkb[k]};
-    const T wz[2] = {X.pwa[k], X.pwb[k]};
+    const int kz[2] = {Xf.pka[k], Xf.pkb[k]};
+    const T wz[2] = {Xf.pwa[k], Xf.pwb[k]};
     for (int q = 0; q < 2; ++q) {
         if (kz[q] < 0) continue;
         T s = 0;
@@ -168,6 +243,12 @@ __device__ __forceinline__ double block_sum(double v, double *lds) {
     return s;
 }
 
+// phi buffer holding the input / output of the cycle in progress (cycle c = cycles)
+__device__ __forceinline__ int cyc_src(const GState *s) {
+    return s->cycles == 0 ? s->start : ((s->cycles - 1) % 2 == 0 ? s->oth0 : s->oth1);
+}
+__device__ __forceinline__ int cyc_dst(const GState *s) { return s->cycles % 2 == 0 ? s->oth0 : s->oth1; }
+
 // ------------------------------------------------------------------- TDGL
 // eq. (TDGL2) with forward Euler (Step 1a); surface stencils of eqs. (Pbc),
 // (PbcFree), (PbcDir) on the two ferroelectric boundary planes.
@@ -177,16 +258,24 @@ __device__ __forceinline__ double surface_value(int pbc, double lambda, double h
     return lambda * (9.0 * p0 - p1) / (8.0 * lambda + 3.0 * h);
 }
 
-__global__ __launch_bounds__(256) void k_tdgl(TdglArgs a) {
-    const Tile t = tile_of((a.nx + BX - 1) / BX, (a.ny + BY - 1) / BY, a.f1 - a.f0);
-    if (!t.ok) return;
+template <typename T>
+__global__ __launch_bounds__(256) void k_tdgl(const Inst<T> *I, Work w, int sel) {
+    const Blk b = find_block(w);
+    if (!b.ok) return;
+    const Inst<T> &a = I[b.inst];
+    const GState *s = asp<1>(a.st);
+    if (sel && !s->adv) return;
+    const int pcur = s->pcur;
+    const double dt = s->dt;
+    const T3 t = split3(b.t, a.nx, a.ny);
     const int i = t.tx * BX + threadIdx.x;
     const int j = t.ty * BY + threadIdx.y;
-    const int k = a.f0 + t.k;
+    const int k = a.f0 + t.tz;
     if (i >= a.nx || j >= a.ny) return;
     const size_t nxy = (size_t)a.nx * a.ny;
     const size_t c = (size_t)k * nxy + (size_t)j * a.nx + i;
-    const double *P = a.P, *phi = a.phi;
+    const double FX_AS(1) *P = asp<1>(a.P[pcur]);
+    const double FX_AS(1) *phi = asp<1>(a.phi[s->cur]);
     const double h = a.h, ih2 = 1.0 / (h * h), i2h = 0.5 / h;
     const double p = P[c];
     const size_t row = c - i;
@@ -209,58 +298,203 @@ __global__ __launch_bounds__(256) void k_tdgl(TdglArgs a) {
     const double p2 = p * p;
     const double landau = p * (a.alpha + p2 * (a.beta + a.gamma * p2));
     const double dF = landau - a.g44 * (dxx + dyy) - a.g11 * dzz + dphi;
-    a.Pn[c] = p - a.dt * a.Gamma * dF;
+    asp<1>(a.P[1 - pcur])[c] = p - dt * a.Gamma * dF;
+}
+
+// ------------------------------------------------------- solve bookkeeping
+// After a stand-alone TDGL update: the new P is in the other buffer, and the
+// stored time levels no longer belong to one time series.
+template <typename T>
+__global__ void k_flip(const Inst<T> *I, int ninst) {
+    const int n = blockIdx.x * blockDim.x + threadIdx.x;
+    if (n >= ninst) return;
+    GState *s = asp<1>(I[n].st);
+    s->pcur ^= 1;
+    s->hist = 0;
+}
+
+// One thread per instance: start a solve.  sel = 1 (time step, instances
+// flagged by the advance slot): the TDGL update just written becomes the
+// current P, the gate potential comes from the run's schedule, and the
+// starting iterate may be extrapolated in time.  sel = 0: a plain solve of
+// every instance from its current phi.
+template <typename T>
+__global__ void k_begin(const Inst<T> *I, int ninst, int sel) {
+    const int n = blockIdx.x * blockDim.x + threadIdx.x;
+    if (n >= ninst) return;
+    const Inst<T> &a = I[n];
+    GState *s = asp<1>(a.st);
+    if (sel && !s->adv) return;
+    if (sel) {
+        s->pcur ^= 1;
+        const int q = s->step - s->sched_base;
+        if (q >= 0 && q < s->sched_len) s->v_top = asp<1>(a.vsched)[q];
+    }
+    const int order = sel ? min(s->hist, a.warm) : 0;
+    int oth[2] = {0, 0}, no = 0;
+    for (int q = 0; q < kPhiBufs && no < 2; ++q) {
+        bool used = q == s->cur;
+        for (int m = 0; m < s->hist; ++m) used |= s->prev[m] == q;
+        if (!used) oth[no++] = q;
+    }
+    s->oth0 = oth[0];
+    s->oth1 = oth[1];
+    s->order = order;
+    s->start = order > 0 ? oth[1] : s->cur;
+    s->ts = sel;
+    s->done = 0;
+    s->cycles = 0;
+    s->zpend = 0;
+    s->fresh = 1;
+    s->insolve = 1;
+}
+
+// Lagrange extrapolation to t^{n+1} through t^n, t^{n-1}, ... (equal steps).
+__constant__ double kExtrapC[4][4] = {{1, 0, 0, 0}, {2, -1, 0, 0}, {3, -3, 1, 0}, {4, -6, 4, -1}};
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_extrap(const Inst<T> *I, Work w) {
+    const Blk b = find_block(w);
+    if (!b.ok) return;
+    const Inst<T> &a = I[b.inst];
+    const GState *s = asp<1>(a.st);
+    const int order = s->order;
+    if (!s->fresh || order == 0) return;
+    const size_t nxy = (size_t)a.nx * a.ny, off = (size_t)a.kb * nxy, n = (size_t)a.nzd * nxy;
+    const double FX_AS(1) *in[4];
+    in[0] = asp<1>(a.phi[s->cur]) + off;
+    for (int q = 1; q <= order; ++q) in[q] = asp<1>(a.phi[s->prev[q - 1]]) + off;
+    double FX_AS(1) *out = asp<1>(a.phi[s->start]) + off;
+    const size_t base = (size_t)b.t * kExtrapChunk;
+    const int tid = threadIdx.y * BX + threadIdx.x;
+    for (int q = 0; q < kExtrapChunk / 256; ++q) {
+        const size_t c = base + (size_t)q * 256 + tid;
+        if (c >= n) break;
+        double v = kExtrapC[order][0] * in[0][c];
+        for (int m = 1; m <= order; ++m) v += kExtrapC[order][m] * in[m][c];
+        out[c] = v;
+    }
+}
+
+// One thread per instance, first kernel of an advance slot (advance = 1) or
+// after a plain solve (advance = 0).  A solve that has stopped is finalized:
+// its last iterate becomes phi^{n+1} and, after a successful time step, phi^n
+// the newest stored level; the statistics and the status are recorded.
+// With advance set, an instance that is idle and below its run target (and
+// whose last solve succeeded) is flagged to start the next time step in this
+// slot; one that has reached the target or failed is parked.
+template <typename T>
+__global__ void k_head(const Inst<T> *I, int ninst, int advance) {
+    const int n = blockIdx.x * blockDim.x + threadIdx.x;
+    if (n >= ninst) return;
+    GState *s = asp<1>(I[n].st);
+    int zf = 0;
+    if (s->insolve && s->done != 0) {
+        const int c = s->cycles;
+        s->solves += 1;
+        s->total_cycles += c;
+        s->max_cycles_step = max(s->max_cycles_step, c);
+        s->insolve = 0;
+        if (s->done == 2) {                   // non-finite: keep phi^n, drop the history
+            s->status = 5;
+            s->failed += 1;
+            s->hist = 0;
+        } else {
+            const int fin = c == 0 ? s->start : ((c - 1) % 2 == 0 ? s->oth0 : s->oth1);
+            s->status = s->done == 1 ? 0 : 4;
+            if (s->status != 0) s->failed += 1;
+            const bool ok_step = s->ts && s->status == 0;
+            if (ok_step && fin != s->cur) {
+                for (int m = kMaxHist - 1; m > 0; --m) s->prev[m] = s->prev[m - 1];
+                s->prev[0] = s->cur;
+                s->hist = min(s->hist + 1, kMaxHist);
+            } else {
+                s->hist = 0;
+            }
+            if (ok_step) s->step += 1;
+            s->cur = fin;
+            zf = s->done == 1 && s->zpend;
+        }
+    }
+    s->zero_fix = zf;
+    int adv = 0;
+    if (advance && !s->parked && !s->insolve) {
+        if (s->status != 0 || s->step >= s->target) s->parked = 1;
+        else adv = 1;
+    }
+    s->adv = adv;
+}
+
+// f = 0 exactly: N(0) = 0, so phi = 0 is the root (applied in the slot that
+// finalizes the solve).
+template <typename T>
+__global__ __launch_bounds__(256) void k_zero_fix(const Inst<T> *I, Work w) {
+    const Blk b = find_block(w);
+    if (!b.ok) return;
+    const Inst<T> &a = I[b.inst];
+    const GState *s = asp<1>(a.st);
+    if (!s->zero_fix) return;
+    const size_t nxy = (size_t)a.nx * a.ny, n = (size_t)a.nzd * nxy;
+    double FX_AS(1) *out = asp<1>(a.phi[s->cur]) + (size_t)a.kb * nxy;
+    const size_t base = (size_t)b.t * kExtrapChunk;
+    const int tid = threadIdx.y * BX + threadIdx.x;
+    for (int q = 0; q < kExtrapChunk / 256; ++q) {
+        const size_t c = base + (size_t)q * 256 + tid;
+        if (c < n) out[c] = 0.0;
+    }
 }
 
 // ------------------------------------------------------ fine-level residual
-// MODE 0: residual at phi_in; MODE 2: at phi_in + clip(e), written to phi_out.
-// Each thread owns a column of ZT planes.  All loads are issued before any
-// arithmetic (clamped indices instead of boundary branches; the z-neighbours
-// of the column's planes are loaded once) so a wave makes one memory round
-// trip for ZT cells.
-template <typename T, int MODE, int ZT>
-__global__ __launch_bounds__(256) void k_residual(ResArgs<T> a) {
-    __shared__ double lds_r[4];
-    __shared__ double lds_f[4];
-    if (a.ctrl->done) return;
+// Each thread owns a column of kResZ planes.  All loads are issued before any
+// arithmetic (clamped indices instead of boundary branches; the column's
+// z-neighbours are loaded once) so a wave makes one memory round trip for
+// kResZ cells.  Mode 0 evaluates the current iterate; mode 2 (update not
+// folded into the smoother) first forms phi_out = phi_in + clip(e).
+template <typename T, int MODE>
+__device__ __forceinline__ void residual_body(const Inst<T> &a, const GState *s, const T3 &t, int after_cycle,
+                                              double &rr, double &ff) {
+    const int ZT = kResZ;
     const int nx = a.nx, ny = a.ny, nzd = a.nzd;
-    const Tile t = tile_of((nx + BX - 1) / BX, (ny + BY - 1) / BY, (nzd + ZT - 1) / ZT);
-    if (!t.ok) return;
     const int ii = t.tx * BX + threadIdx.x;
     const int jj = t.ty * BY + threadIdx.y;
     const bool live = ii < nx && jj < ny;
     const int i = live ? ii : 0, j = live ? jj : 0;
-    const int k0 = t.k * ZT;
+    const int k0 = t.tz * ZT;
     const int nxy = nx * ny;
     const size_t off = (size_t)a.kb * nxy;
-    const double *phi = a.phi_in + off;
-    const double *P = a.P + off;
+    const int bin = MODE == 2 ? cyc_src(s) : (after_cycle ? cyc_dst(s) : s->start);
+    const double FX_AS(1) *phi = asp<1>(a.phi[bin]) + off;
+    double FX_AS(1) *phi_out = asp<1>(a.phi[cyc_dst(s)]) + off;
+    const double FX_AS(1) *P = asp<1>(a.P[s->pcur]) + off;
+    const Lv<T, 1> L = gview(a.lv[0]);
+    const int FX_AS(1) *pflags = asp<1>(a.pflags);
+    const double FX_AS(1) *cxy0 = asp<1>(a.cxy0), *czm0 = asp<1>(a.czm0), *czp0 = asp<1>(a.czp0);
+    const double FX_AS(1) *wl = asp<1>(a.wl), *wr = asp<1>(a.wr);
+    const double FX_AS(1) *p0ev = asp<1>(a.p0e), *n0ev = asp<1>(a.n0e);
     const int col = j * nx + i;
     const int ox0 = wrap_p(i, nx) - i, ox1 = wrap_m(i, nx) - i;
     const int oy0 = (wrap_p(j, ny) - j) * nx, oy1 = (wrap_m(j, ny) - j) * nx;
-    const int rb = a.L0.rb;
+    const int rb = L.rb;
     const int half = (nxy * nzd) >> 1;
     const double big = 1e300;
     auto kcl = [&](int k) { return k < 0 ? 0 : (k >= nzd ? nzd - 1 : k); };
-    // ---- bound charge: P of the column's planes and their neighbours (ferroelectric tiles only)
     double pz[ZT + 2];
 #pragma unroll
     for (int z = 0; z < ZT + 2; ++z) pz[z] = 0.0;
     bool anyP = false;
 #pragma unroll
-    for (int z = 0; z < ZT; ++z) anyP |= (k0 + z < nzd) && (a.pflags[kcl(k0 + z)] & PF_P);
+    for (int z = 0; z < ZT; ++z) anyP |= (k0 + z < nzd) && (pflags[kcl(k0 + z)] & PF_P);
     if (anyP) {
 #pragma unroll
         for (int z = 0; z < ZT + 2; ++z) pz[z] = P[kcl(k0 - 1 + z) * nxy + col];
     }
-    // ---- potential at the column (planes k0-1 .. k0+ZT) and the x/y neighbours (k0 .. k0+ZT-1)
     double vc[ZT + 2], vx0[ZT], vx1[ZT], vy0[ZT], vy1[ZT];
     auto at = [&](int k, int o, int par, double *dst) {
         const int c = k * nxy + col + o;
         double v = phi[c];
         if (MODE == 2) {
-            const double d = (double)a.e[rb ? (par ? half : 0) + (c >> 1) : c];
-            const double lim = (a.pflags[k] & PF_SC) ? a.dmax : big;
+            const double d = (double)L.e[rb ? (par ? half : 0) + (c >> 1) : c];
+            const double lim = (pflags[k] & PF_SC) ? a.dmax : big;
             v += fmin(fmax(d, -lim), lim);
         }
         *dst = v;
@@ -280,36 +514,34 @@ __global__ __launch_bounds__(256) void k_residual(ResArgs<T> a) {
         at(k, oy0, pn, &vy0[z]);
         at(k, oy1, pn, &vy1[z]);
     }
-    // ---- residual, carriers and stores, plane by plane
-    double rr = 0.0, ff = 0.0;
-    const LevelArgs<T> &L = a.L0;
+    const double v_b = a.v_b, v_t = s->v_top;
 #pragma unroll
     for (int z = 0; z < ZT; ++z) {
         const int k = k0 + z;
         if (k >= nzd) break;
-        const int fl = a.pflags[k];
+        const int fl = pflags[k];
         const double v0 = vc[z + 1];
         const double nb = (vx0[z] + vx1[z] - 2.0 * v0) + (vy0[z] + vy1[z] - 2.0 * v0);
         const double dn = k > 0 ? vc[z] : 0.0;
         const double up = k < nzd - 1 ? vc[z + 2] : 0.0;
-        const double Lphi = -a.cxy[k] * nb + a.czm[k] * (v0 - dn) + a.czp[k] * (v0 - up);
+        const double Lphi = -cxy0[k] * nb + czm0[k] * (v0 - dn) + czp0[k] * (v0 - up);
         double f = 0.0;
         if (fl & PF_P) {
             const double pc = pz[z + 1];
-            const double pup = k == nzd - 1 ? pc : a.wl[k] * pc + a.wr[k] * pz[z + 2];
-            const double pdn = k == 0 ? pc : a.wl[k - 1] * pz[z] + a.wr[k - 1] * pc;
+            const double pup = k == nzd - 1 ? pc : wl[k] * pc + wr[k] * pz[z + 2];
+            const double pdn = k == 0 ? pc : wl[k - 1] * pz[z] + wr[k - 1] * pc;
             f = -(pup - pdn) * a.p_scale;
         }
-        if (k == 0) f += a.czm[k] * a.v_b;
-        if (k == nzd - 1) f += a.czp[k] * a.v_t;
+        if (k == 0) f += czm0[k] * v_b;
+        if (k == nzd - 1) f += czp0[k] * v_t;
         double res = f - Lphi;
         if (live) {
             const int cl = k * nxy + col;
-            if (MODE != 0) a.phi_out[off + cl] = v0;
+            if (MODE == 2) phi_out[cl] = v0;
             if (fl & PF_SC) {
                 const double u = v0 * a.vt_inv;
                 const double em = expm1(-u), ep = expm1(u);
-                const double p0e = a.p0e[k], n0e = a.n0e[k];
+                const double p0e = p0ev[k], n0e = n0ev[k];
                 res += (p0e * em - n0e * ep) * a.rho_scale;                       // + rho_c
                 L.sig[sidx(L, i, j, k)] = (T)((p0e * (1.0 + em) + n0e * (1.0 + ep)) * a.sig_scale);
             }
@@ -318,74 +550,103 @@ __global__ __launch_bounds__(256) void k_residual(ResArgs<T> a) {
             ff += f * f;
         }
     }
+}
+
+// MODE 0 covers every instance except, after a cycle, those whose update is
+// not folded into the smoother; MODE 2 covers exactly those (two kernels
+// rather than one branch: each keeps its own, smaller register budget).
+template <typename T, int MODE>
+__global__ __launch_bounds__(256) void k_residual(const Inst<T> *I, Work w, int after_cycle) {
+    __shared__ double lds_r[4];
+    __shared__ double lds_f[4];
+    const Blk b = find_block(w);
+    if (!b.ok) return;
+    const Inst<T> &a = I[b.inst];
+    const GState *s = asp<1>(a.st);
+    if (after_cycle ? s->done != 0 : !s->fresh) return;
+    if ((MODE == 2) != (after_cycle && !a.fold)) return;
+    const T3 t = split3(b.t, a.nx, a.ny);
+    double rr = 0.0, ff = 0.0;
+    residual_body<T, MODE>(a, s, t, after_cycle, rr, ff);
     const double sr = block_sum(rr, lds_r);
     const double sf = block_sum(ff, lds_f);
     if (threadIdx.x == 0 && threadIdx.y == 0) {
-        a.part[2 * t.id] = sr;
-        a.part[2 * t.id + 1] = sf;
+        double FX_AS(1) *part = asp<1>(a.part);
+        part[2 * b.t] = sr;
+        part[2 * b.t + 1] = sf;
     }
 }
 
-// Deterministic final sum of the residual partials and the stop decision.
-__global__ __launch_bounds__(1024) void k_reduce(const double *part, int n, SolveCtrl *ctrl, int count_cycle) {
+// Deterministic final sum of one instance's residual partials (a block per
+// instance) and its stop decision.
+template <typename T>
+__global__ __launch_bounds__(1024) void k_reduce(const Inst<T> *I, int count_cycle) {
     __shared__ double lr[16];
     __shared__ double lf[16];
-    if (ctrl->done) return;
+    const Inst<T> &a = I[blockIdx.x];
+    GState *s = asp<1>(a.st);
+    if (count_cycle ? s->done != 0 : !s->fresh) return;
+    const int n = tiles3(a.nx, a.ny, (a.nzd + kResZ - 1) / kResZ);
+    const double FX_AS(1) *part = asp<1>(a.part);
     double r = 0.0, f = 0.0;
-    for (int b = threadIdx.x; b < n; b += blockDim.x) { r += part[2 * b]; f += part[2 * b + 1]; }
+    for (int q = threadIdx.x; q < n; q += blockDim.x) { r += part[2 * q]; f += part[2 * q + 1]; }
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) { r += __shfl_down(r, off, 64); f += __shfl_down(f, off, 64); }
     if ((threadIdx.x & 63) == 0) { lr[threadIdx.x >> 6] = r; lf[threadIdx.x >> 6] = f; }
     __syncthreads();
     if (threadIdx.x == 0) {
-        double a = 0.0, b = 0.0;
-        for (int q = 0; q < (int)(blockDim.x >> 6); ++q) { a += lr[q]; b += lf[q]; }
-        ctrl->rn2 = a;
-        ctrl->fn2 = b;
-        if (count_cycle) ctrl->cycles += 1;
-        if (!isfinite(a) || !isfinite(b)) ctrl->done = 2;
-        else if (a <= ctrl->tol2 * b || a == 0.0 || b == 0.0) ctrl->done = 1;   // b = 0: the host sets phi = 0
-        else if (ctrl->cycles >= ctrl->max_cycles) ctrl->done = 3;
+        double x = 0.0, y = 0.0;
+        for (int q = 0; q < (int)(blockDim.x >> 6); ++q) { x += lr[q]; y += lf[q]; }
+        s->rn2 = x;
+        s->fn2 = y;
+        s->fresh = 0;
+        if (count_cycle) s->cycles += 1;
+        if (!isfinite(x) || !isfinite(y)) s->done = 2;
+        else if (y == 0.0) { s->done = 1; s->zpend = x != 0.0; }
+        else if (x <= a.tol2 * y || x == 0.0) s->done = 1;
+        else if (s->cycles >= a.max_cycles) s->done = 3;
     }
 }
 
-__global__ void k_ctrl_reset(SolveCtrl *ctrl, int max_cycles, double tol2) {
-    ctrl->done = 0;
-    ctrl->cycles = 0;
-    ctrl->max_cycles = max_cycles;
-    ctrl->tol2 = tol2;
-    ctrl->rn2 = 0.0;
-    ctrl->fn2 = 0.0;
-}
-
 // ----------------------------------------------------------------- smoother
-// One colour of red-black Gauss-Seidel on a red/black-split level: a thread
-// per cell of that colour, all reads and writes contiguous along x.
+// One colour of red-black Gauss-Seidel on (L + diag sigma) e = r.  Split
+// storage: a thread per cell of that colour, ZT planes per thread with all
+// loads issued first; plainly stored levels: a thread per cell and plane of
+// a 64x4xZT tile.  UPD (finest level, last black half-sweep, instances whose
+// update is folded in) also writes phi_out = phi_in + clip(e) for each black
+// cell and its red partner (the pair 2m, 2m+1 of a row).
 template <typename T, int ZI, int ZT, int UPD>
-__global__ __launch_bounds__(256) void k_smooth_rb(LevelArgs<T> L, int color, const SolveCtrl *ctrl, UpdArgs u) {
-    if (ctrl->done) return;
+__device__ __forceinline__ void smooth_rb_body(const Inst<T> &a, const Lv<T, 1> &L, int t, int color) {
     const int hx = L.nx >> 1;
-    const Tile t = tile_of((hx + BX - 1) / BX, (L.ny + BY - 1) / BY, (L.nz + ZT - 1) / ZT);
-    if (!t.ok) return;
-    const int mm = t.tx * BX + threadIdx.x;
-    const int jj = t.ty * BY + threadIdx.y;
+    const T3 tt = split3(t, hx, L.ny);
+    const int mm = tt.tx * BX + threadIdx.x;
+    const int jj = tt.ty * BY + threadIdx.y;
     const bool live = mm < hx && jj < L.ny;
     const int m = live ? mm : 0, j = live ? jj : 0;
     const int half = (L.nx * L.ny * L.nz) >> 1;
     const int plane = L.ny * hx;
-    const T *eo = L.e + (color ? 0 : half);
-    T *es = L.e + (color ? half : 0);
-    const T *rs = L.r + (color ? half : 0);
+    const T FX_AS(1) *eo = L.e + (color ? 0 : half);
+    T FX_AS(1) *es = L.e + (color ? half : 0);
+    const T FX_AS(1) *rs = L.r + (color ? half : 0);
     const int hsz = (L.nx * L.ny * (L.sig_hi - L.sig_lo)) >> 1;
     const int oy0 = L.ny > 1 ? (wrap_p(j, L.ny) - j) * hx : 0;
     const int oy1 = L.ny > 1 ? (wrap_m(j, L.ny) - j) * hx : 0;
+    const bool upd = UPD && a.fold;
+    const double FX_AS(1) *phi_in = nullptr;
+    double FX_AS(1) *phi_out = nullptr;
+    const int FX_AS(1) *pflags = asp<1>(a.pflags);
+    if (upd) {
+        const GState *s = asp<1>(a.st);
+        const size_t off = (size_t)a.kb * a.nx * a.ny;
+        phi_in = asp<1>(a.phi[cyc_src(s)]) + off;
+        phi_out = asp<1>(a.phi[cyc_dst(s)]) + off;
+    }
     T out[ZT];
-    // loads of all ZT planes first
     T rr[ZT], sg[ZT], ex0[ZT], ex1[ZT], ey0[ZT], ey1[ZT], ez0[ZT], ez1[ZT], ep[ZT];
-    double2 ph[ZT];
+    dpair ph[ZT];
 #pragma unroll
     for (int z = 0; z < ZT; ++z) {
-        const int k = min(t.k * ZT + z, L.nz - 1);
+        const int k = min(tt.tz * ZT + z, L.nz - 1);
         const int row = k * plane + j * hx;
         const int q = row + m;
         const bool hs = k >= L.sig_lo && k < L.sig_hi;
@@ -401,110 +662,132 @@ __global__ __launch_bounds__(256) void k_smooth_rb(LevelArgs<T> L, int color, co
             ez0[z] = eo[k > 0 ? q - plane : q];
             ez1[z] = eo[k < L.nz - 1 ? q + plane : q];
         }
-        if (UPD) {
+        if (upd) {
             ep[z] = eo[q];                       // the red partner of this black cell's pair
-            ph[z] = *(const double2 *)(u.phi_in + (size_t)k * L.nx * L.ny + (size_t)j * L.nx + 2 * m);
+            ph[z] = *(const dpair FX_AS(1) *)(phi_in + (size_t)k * L.nx * L.ny + (size_t)j * L.nx + 2 * m);
         }
     }
 #pragma unroll
     for (int z = 0; z < ZT; ++z) {
-        const int k = min(t.k * ZT + z, L.nz - 1);
+        const int k = min(tt.tz * ZT + z, L.nz - 1);
         const bool hs = k >= L.sig_lo && k < L.sig_hi;
-        T s = 0;
+        T acc = 0;
         if (!ZI) {
             const T cx = L.cxy[k];
             const T cy = L.ny > 1 ? cx : T(0);
-            s = cx * (ex0[z] + ex1[z]) + cy * (ey0[z] + ey1[z]) + (k > 0 ? L.czm[k] : T(0)) * ez0[z] +
-                (k < L.nz - 1 ? L.czp[k] : T(0)) * ez1[z];
+            acc = cx * (ex0[z] + ex1[z]) + cy * (ey0[z] + ey1[z]) + (k > 0 ? L.czm[k] : T(0)) * ez0[z] +
+                  (k < L.nz - 1 ? L.czp[k] : T(0)) * ez1[z];
         }
-        out[z] = (rr[z] + s) / (L.dg[k] + (hs ? sg[z] : T(0)));
+        out[z] = (rr[z] + acc) / (L.dg[k] + (hs ? sg[z] : T(0)));
     }
 #pragma unroll
     for (int z = 0; z < ZT; ++z) {
-        const int k = t.k * ZT + z;
+        const int k = tt.tz * ZT + z;
         if (live && k < L.nz) {
             es[k * plane + j * hx + m] = out[z];
-            if (UPD) {
-                const double lim = (u.pflags[k] & PF_SC) ? u.dmax : 1e300;
+            if (upd) {
+                const double lim = (pflags[k] & PF_SC) ? a.dmax : 1e300;
                 const double db = fmin(fmax((double)out[z], -lim), lim);
                 const double dr = fmin(fmax((double)ep[z], -lim), lim);
                 const bool odd = ((color + j + k) & 1) != 0;          // black cell at 2m+1
-                double2 o;
+                dpair o;
                 o.x = ph[z].x + (odd ? dr : db);
                 o.y = ph[z].y + (odd ? db : dr);
-                *(double2 *)(u.phi_out + (size_t)k * L.nx * L.ny + (size_t)j * L.nx + 2 * m) = o;
+                *(dpair FX_AS(1) *)(phi_out + (size_t)k * L.nx * L.ny + (size_t)j * L.nx + 2 * m) = o;
             }
         }
     }
 }
 
-// Colour of a cell on a plainly stored level (odd x or y extent).  With an
-// odd periodic extent the parity colouring makes the wrap neighbours equal
-// coloured, so the last column / row (for odd nx / ny) get colours 2 and 3:
-// no two cells of one colour are then neighbours, and a sweep is the four
-// colours in turn.
-template <typename T>
-__device__ __forceinline__ int nat_color(const LevelArgs<T> &L, int i, int j, int k) {
-    const int par = (i + j + k) & 1;
-    const bool edge = ((L.nx & 1) && i == L.nx - 1) || ((L.ny & 1) && j == L.ny - 1);
-    return edge ? 2 + par : par;
-}
-
-// One colour of the Gauss-Seidel sweep on a plainly stored level: a thread per cell.
-template <typename T>
-__global__ __launch_bounds__(256) void k_smooth_nat(LevelArgs<T> L, int color, int zero_init, const SolveCtrl *ctrl) {
-    if (ctrl->done) return;
-    const Tile t = tile_of((L.nx + BX - 1) / BX, (L.ny + BY - 1) / BY, L.nz);
-    if (!t.ok) return;
-    const int i = t.tx * BX + threadIdx.x;
-    const int j = t.ty * BY + threadIdx.y;
-    const int k = t.k;
+template <typename T, int ZT>
+__device__ __forceinline__ void smooth_nat_body(const Lv<T, 1> &L, int t, int color, int zero_init) {
+    const T3 tt = split3(t, L.nx, L.ny);
+    const int i = tt.tx * BX + threadIdx.x;
+    const int j = tt.ty * BY + threadIdx.y;
     if (i >= L.nx || j >= L.ny) return;
-    if (nat_color(L, i, j, k) != color) {
-        if (zero_init) L.e[cidx(L, i, j, k)] = T(0);
-        return;
+    for (int z = 0; z < ZT; ++z) {
+        const int k = tt.tz * ZT + z;
+        if (k >= L.nz) break;
+        if (nat_color(L, i, j, k) != color) {
+            if (zero_init) L.e[cidx(L, i, j, k)] = T(0);
+            continue;
+        }
+        gs_cell(L, i, j, k, zero_init);
     }
-    gs_cell(L, i, j, k, zero_init);
+}
+
+// probe (instrumentation): the first tile of each instance that works adds
+// the launch's algorithmic bytes for that instance -- one touch each of this
+// colour's r, sigma and e, the other colour's e (not read when zero_init),
+// and the phi pair read and written where the update is folded in.
+template <typename T, int ZI, int ZT, int UPD>
+__global__ __launch_bounds__(256) void k_smooth(const Inst<T> *I, Work w, int level, int color, double *probe) {
+    const Blk b = find_block(w);
+    if (!b.ok) return;
+    const Inst<T> &a = I[b.inst];
+    if (asp<1>(a.st)->done) return;
+    const Lv<T, 1> L = gview(a.lv[level]);
+    if (L.rb) {
+        if (color > 1) return;
+        smooth_rb_body<T, ZI, ZT, UPD>(a, L, b.t, color);
+    } else {
+        smooth_nat_body<T, ZT>(L, b.t, color, ZI);
+    }
+    // after the sweep: an atomic ahead of it would stop the per-plane tables
+    // from being read through the scalar cache
+    if (probe && b.t == 0 && threadIdx.x == 0 && threadIdx.y == 0 && (L.rb ? color < 2 : true)) {
+        const double n = (double)L.nx * L.ny * L.nz, ns = (double)L.nx * L.ny * (L.sig_hi - L.sig_lo);
+        double by = sizeof(T) * (0.5 * n + 0.5 * ns + 0.5 * n);
+        if (!ZI) by += sizeof(T) * 0.5 * n;
+        if (UPD && a.fold && L.rb) by += 16.0 * n;
+        atomicAdd(probe, by);
+    }
 }
 
 template <typename T>
-__global__ __launch_bounds__(256) void k_restrict(LevelArgs<T> F, LevelArgs<T> C, XferArgs<T> X, const SolveCtrl *ctrl) {
-    if (ctrl->done) return;
-    const Tile t = tile_of((C.nx + BX - 1) / BX, (C.ny + BY - 1) / BY, C.nz);
-    if (!t.ok) return;
-    const int I = t.tx * BX + threadIdx.x;
-    const int J = t.ty * BY + threadIdx.y;
-    if (I >= C.nx || J >= C.ny) return;
-    restrict_cell(F, C, X, I, J, t.k);
+__global__ __launch_bounds__(256) void k_restrict(const Inst<T> *I, Work w, int level) {
+    const Blk b = find_block(w);
+    if (!b.ok) return;
+    const Inst<T> &a = I[b.inst];
+    if (asp<1>(a.st)->done) return;
+    const Lv<T, 1> C = gview(a.lv[level + 1]);
+    const T3 t = split3(b.t, C.nx, C.ny);
+    const int I0 = t.tx * BX + threadIdx.x;
+    const int J0 = t.ty * BY + threadIdx.y;
+    if (I0 >= C.nx || J0 >= C.ny) return;
+    restrict_cell(gview(a.lv[level]), C, xview(a.xf[level]), I0, J0, t.tz);
 }
 
 template <typename T>
-__global__ __launch_bounds__(256) void k_prolong(LevelArgs<T> F, LevelArgs<T> C, XferArgs<T> X, const SolveCtrl *ctrl) {
-    if (ctrl->done) return;
+__global__ __launch_bounds__(256) void k_prolong(const Inst<T> *I, Work w, int level) {
+    const Blk b = find_block(w);
+    if (!b.ok) return;
+    const Inst<T> &a = I[b.inst];
+    if (asp<1>(a.st)->done) return;
+    const Lv<T, 1> F = gview(a.lv[level]);
     int i, j, k;
     if (F.rb) {                       // a thread per black cell
         const int hx = F.nx >> 1;
-        const Tile t = tile_of((hx + BX - 1) / BX, (F.ny + BY - 1) / BY, F.nz);
-        if (!t.ok) return;
+        const T3 t = split3(b.t, hx, F.ny);
         const int m = t.tx * BX + threadIdx.x;
         j = t.ty * BY + threadIdx.y;
-        k = t.k;
+        k = t.tz;
         if (m >= hx || j >= F.ny) return;
         i = 2 * m + ((1 + j + k) & 1);
     } else {
-        const Tile t = tile_of((F.nx + BX - 1) / BX, (F.ny + BY - 1) / BY, F.nz);
-        if (!t.ok) return;
+        const T3 t = split3(b.t, F.nx, F.ny);
         i = t.tx * BX + threadIdx.x;
         j = t.ty * BY + threadIdx.y;
-        k = t.k;
+        k = t.tz;
         if (i >= F.nx || j >= F.ny) return;
     }
-    prolong_cell(F, C, X, i, j, k);
+    prolong_cell(F, gview(a.lv[level + 1]), xview(a.xf[level]), i, j, k);
 }
 
 // --------------------------------------------- coarse levels in one workgroup
-template <typename T>
-__device__ void smooth_color(const LevelArgs<T> &L, int color, int zero_init) {
+template <typename V>
+__device__ void smooth_color(const V &L, int color, int zero_init) {
+    using T = typename V::value_type;
     if (L.rb) {
         const int hx = L.nx >> 1;
         const int n = hx * L.ny * L.nz;
@@ -523,8 +806,8 @@ __device__ void smooth_color(const LevelArgs<T> &L, int color, int zero_init) {
 }
 
 // One full Gauss-Seidel sweep (2 colours on split levels, 4 otherwise).
-template <typename T>
-__device__ void smooth_sweep(const LevelArgs<T> &L, int zero_init) {
+template <typename V>
+__device__ void smooth_sweep(const V &L, int zero_init) {
     const int ncol = L.rb ? 2 : 4;
     for (int c = 0; c < ncol; ++c) {
         smooth_color(L, c, zero_init && c == 0);
@@ -532,28 +815,92 @@ __device__ void smooth_sweep(const LevelArgs<T> &L, int zero_init) {
     }
 }
 
+// Dot product over a whole workgroup, accumulated in double in a fixed order
+// (deterministic); every thread returns the total.
+template <typename P>
+__device__ double block_dot(P x, P y, int n, double FX_AS(3) *red) {
+    const int tid = threadIdx.x;
+    double s = 0.0;
+    for (int c = tid; c < n; c += blockDim.x) s += (double)x[c] * (double)y[c];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
+    if ((tid & 63) == 0) red[tid >> 6] = s;
+    __syncthreads();
+    double t = 0.0;
+    for (int q = 0; q < (int)(blockDim.x >> 6); ++q) t += red[q];
+    __syncthreads();
+    return t;
+}
+
+// Bottom solve on the coarsest level: conjugate gradients on the symmetric
+// positive definite (L + diag sigma) e = r from e = 0, until the residual has
+// dropped by sqrt(tol2) or after iters steps.  r is overwritten by the
+// residual.  Unlike a fixed number of Gauss-Seidel sweeps this also solves
+// coarsest levels that keep many cells in x and y (odd lateral sizes stop the
+// x-y coarsening early).
 template <typename T>
-__global__ __launch_bounds__(512) void k_coarse(const CoarseArgs<T> *A, const SolveCtrl *ctrl) {
+__device__ void bottom_cg(const Lv<T, 3> &B, T FX_AS(3) *p, T FX_AS(3) *q, double FX_AS(3) *red, int iters,
+                          double tol2) {
+    const int n = B.nx * B.ny * B.nz;
+    T FX_AS(3) *e = B.e;
+    T FX_AS(3) *r = B.r;
+    for (int c = threadIdx.x; c < n; c += blockDim.x) {
+        e[c] = T(0);
+        p[c] = r[c];
+    }
+    __syncthreads();
+    double rr = block_dot(r, r, n, red);
+    const double stop = tol2 * rr;
+    for (int it = 0; it < iters && rr > stop; ++it) {
+        for (int c = threadIdx.x; c < n; c += blockDim.x) {
+            const int i = c % B.nx, row = c / B.nx, j = row % B.ny, k = row / B.ny;
+            const int ci = cidx(B, i, j, k);
+            q[ci] = diag_of(B, i, j, k) * p[ci] - nb_sum(B, p, i, j, k);
+        }
+        __syncthreads();
+        const double pq = block_dot(p, q, n, red);
+        if (!(pq > 0.0)) break;
+        const double alpha = rr / pq;
+        for (int c = threadIdx.x; c < n; c += blockDim.x) {
+            e[c] += (T)(alpha * (double)p[c]);
+            r[c] -= (T)(alpha * (double)q[c]);
+        }
+        __syncthreads();
+        const double rn = block_dot(r, r, n, red);
+        const double beta = rn / rr;
+        rr = rn;
+        for (int c = threadIdx.x; c < n; c += blockDim.x) p[c] = r[c] + (T)(beta * (double)p[c]);
+        __syncthreads();
+    }
+}
+
+// A block per instance: the V-cycle from level lc down to the coarsest with
+// every level's e, r, sigma and coefficient tables resident in LDS.
+template <typename T>
+__global__ __launch_bounds__(512) void k_coarse(const Inst<T> *I) {
     extern __shared__ double lds_raw[];
-    if (ctrl->done) return;
-    unsigned char *lds = (unsigned char *)lds_raw;
-    const int nl = A->nlev;
-    // level views with LDS-resident e, r, sig
-    auto lvl = [&](int l) {
-        LevelArgs<T> L = A->lv[l];
-        L.e = (T *)(lds + A->off_e[l]);
-        L.r = (T *)(lds + A->off_r[l]);
-        L.sig = (T *)(lds + A->off_s[l]);
-        T *tab = (T *)(lds + A->off_t[l]);
+    const Inst<T> &A = I[blockIdx.x];
+    if (asp<1>(A.st)->done) return;
+    unsigned char FX_AS(3) *lds = asp<3>((unsigned char *)lds_raw);
+    const int l0 = A.lc, nl = A.nlev - A.lc;
+    auto lvl = [&](int q) {
+        const LevelArgs<T> &G = A.lv[l0 + q];
+        Lv<T, 3> L;
+        L.nx = G.nx; L.ny = G.ny; L.nz = G.nz; L.rb = G.rb;
+        L.sig_lo = G.sig_lo; L.sig_hi = G.sig_hi;
+        L.e = (T FX_AS(3) *)(lds + A.off_e[q]);
+        L.r = (T FX_AS(3) *)(lds + A.off_r[q]);
+        L.sig = (T FX_AS(3) *)(lds + A.off_s[q]);
+        T FX_AS(3) *tab = (T FX_AS(3) *)(lds + A.off_t[q]);
         L.cxy = tab;
         L.czm = tab + L.nz;
         L.czp = tab + 2 * L.nz;
         L.dg = tab + 3 * L.nz;
         return L;
     };
-    for (int l = 0; l < nl; ++l) {        // per-plane coefficient tables into LDS
-        const LevelArgs<T> G = A->lv[l];
-        T *tab = (T *)(lds + A->off_t[l]);
+    for (int q = 0; q < nl; ++q) {        // per-plane coefficient tables into LDS
+        const Lv<T, 1> G = gview(A.lv[l0 + q]);
+        T FX_AS(3) *tab = (T FX_AS(3) *)(lds + A.off_t[q]);
         for (int c = threadIdx.x; c < G.nz; c += blockDim.x) {
             tab[c] = G.cxy[c];
             tab[G.nz + c] = G.czm[c];
@@ -562,55 +909,73 @@ __global__ __launch_bounds__(512) void k_coarse(const CoarseArgs<T> *A, const So
         }
     }
     {
-        const LevelArgs<T> L0 = lvl(0);
-        const int n = L0.nx * L0.ny * L0.nz;
-        const int ns = L0.nx * L0.ny * (L0.sig_hi - L0.sig_lo);
-        for (int c = threadIdx.x; c < n; c += blockDim.x) L0.r[c] = A->r_in[c];
-        for (int c = threadIdx.x; c < ns; c += blockDim.x) L0.sig[c] = A->sig_in[c];
+        const Lv<T, 1> G = gview(A.lv[l0]);
+        const Lv<T, 3> L0 = lvl(0);
+        const int n = G.nx * G.ny * G.nz;
+        const int ns = G.nx * G.ny * (G.sig_hi - G.sig_lo);
+        for (int c = threadIdx.x; c < n; c += blockDim.x) L0.r[c] = G.r[c];
+        for (int c = threadIdx.x; c < ns; c += blockDim.x) L0.sig[c] = G.sig[c];
         __syncthreads();
     }
-    for (int l = 0; l < nl - 1; ++l) {
-        const LevelArgs<T> L = lvl(l);
-        for (int s = 0; s < A->nu1; ++s) smooth_sweep(L, s == 0);
-        const LevelArgs<T> C = lvl(l + 1);
-        const XferArgs<T> X = A->xf[l];
+    for (int q = 0; q < nl - 1; ++q) {
+        const Lv<T, 3> L = lvl(q);
+        for (int s = 0; s < A.nu1; ++s) smooth_sweep(L, s == 0);
+        const Lv<T, 3> C = lvl(q + 1);
+        const Xv<T> X = xview(A.xf[l0 + q]);
         const int n = C.nx * C.ny * C.nz;
         for (int c = threadIdx.x; c < n; c += blockDim.x) {
-            const int I = c % C.nx, row = c / C.nx;
-            restrict_cell(L, C, X, I, row % C.ny, row / C.ny);
+            const int I0 = c % C.nx, row = c / C.nx;
+            restrict_cell(L, C, X, I0, row % C.ny, row / C.ny);
         }
         __syncthreads();
     }
-    {
-        const LevelArgs<T> B = lvl(nl - 1);
-        for (int s = 0; s < A->bottom_sweeps; ++s) smooth_sweep(B, s == 0);
-    }
-    for (int l = nl - 2; l >= 0; --l) {
-        const LevelArgs<T> L = lvl(l);
-        const LevelArgs<T> C = lvl(l + 1);
-        const XferArgs<T> X = A->xf[l];
+    bottom_cg<T>(lvl(nl - 1), (T FX_AS(3) *)(lds + A.off_p), (T FX_AS(3) *)(lds + A.off_q),
+                 (double FX_AS(3) *)(lds + A.off_red), A.bottom_iters, A.bottom_tol2);
+    for (int q = nl - 2; q >= 0; --q) {
+        const Lv<T, 3> L = lvl(q);
+        const Lv<T, 3> C = lvl(q + 1);
+        const Xv<T> X = xview(A.xf[l0 + q]);
         const int n = L.nx * L.ny * L.nz;
         for (int c = threadIdx.x; c < n; c += blockDim.x) {
             const int i = c % L.nx, row = c / L.nx;
             prolong_cell(L, C, X, i, row % L.ny, row / L.ny);
         }
         __syncthreads();
-        for (int s = 0; s < A->nu2; ++s) smooth_sweep(L, 0);
+        for (int s = 0; s < A.nu2; ++s) smooth_sweep(L, 0);
     }
     {
-        const LevelArgs<T> L0 = lvl(0);
-        const int n = L0.nx * L0.ny * L0.nz;
-        for (int c = threadIdx.x; c < n; c += blockDim.x) A->e_out[c] = L0.e[c];
+        const Lv<T, 1> G = gview(A.lv[l0]);
+        const Lv<T, 3> L0 = lvl(0);
+        const int n = G.nx * G.ny * G.nz;
+        for (int c = threadIdx.x; c < n; c += blockDim.x) G.e[c] = L0.e[c];
     }
 }
 
-// out = sum_q c[q] in[q] over n contiguous values (polynomial extrapolation in time).
-__global__ __launch_bounds__(256) void k_extrap(double *out, ExtrapArgs a, size_t n) {
-    for (size_t c = blockIdx.x * (size_t)blockDim.x + threadIdx.x; c < n; c += (size_t)gridDim.x * blockDim.x) {
-        double v = a.c[0] * a.in[0][c];
-        for (int q = 1; q < a.nin; ++q) v += a.c[q] * a.in[q][c];
-        out[c] = v;
-    }
+// Start of a run (or of one chunk of its schedule): nsteps more time steps.
+// first = 0 keeps instances whose solve failed in an earlier chunk parked.
+template <typename T>
+__global__ void k_run_setup(const Inst<T> *I, int ninst, int nsteps, int has_sched, double dt, int first) {
+    const int n = blockIdx.x * blockDim.x + threadIdx.x;
+    if (n >= ninst) return;
+    GState *s = asp<1>(I[n].st);
+    const bool failed = !first && s->status != 0;
+    if (first) { s->status = 0; s->max_cycles_step = 0; }
+    s->target = s->step + nsteps;
+    s->sched_base = s->step;
+    s->sched_len = has_sched ? nsteps : 0;
+    s->dt = dt;
+    s->parked = nsteps == 0 || failed;
+    s->adv = 0;
+}
+
+template <typename T>
+__global__ void k_set_vtop(const Inst<T> *I, int ninst, double v) {
+    const int n = blockIdx.x * blockDim.x + threadIdx.x;
+    if (n < ninst) asp<1>(I[n].st)->v_top = v;
+}
+
+__global__ void k_put_state(InstState *dst, InstState v) {
+    if (threadIdx.x == 0) *dst = v;
 }
 
 __global__ void k_fill(double *x, size_t n, double v) {
@@ -620,79 +985,103 @@ __global__ void k_fill(double *x, size_t n, double v) {
 }  // namespace
 
 // ------------------------------------------------------------------ launchers
-void launch_tdgl(const TdglArgs &a, hipStream_t st) {
-    hipLaunchKernelGGL(k_tdgl, tile_grid(tiles(a.nx, a.ny, a.f1 - a.f0)), dim3(BX, BY), 0, st, a);
-}
-
-constexpr int kResZ = 4;   // planes per thread in the fine-level residual
-
-template <typename T>
-int launch_residual(const ResArgs<T> &a, hipStream_t st) {
-    const int n = tiles(a.nx, a.ny, (a.nzd + kResZ - 1) / kResZ);
-    if (a.e)
-        hipLaunchKernelGGL((k_residual<T, 2, kResZ>), tile_grid(n), dim3(BX, BY), 0, st, a);
-    else
-        hipLaunchKernelGGL((k_residual<T, 0, kResZ>), tile_grid(n), dim3(BX, BY), 0, st, a);
-    return n;
-}
+#define FX_LAUNCH(kern, w, ...)                                                                            \
+    do {                                                                                                   \
+        if ((w).total > 0) hipLaunchKernelGGL(kern, grid_of((w).total), dim3(BX, BY), 0, st, __VA_ARGS__); \
+    } while (0)
 
 template <typename T>
-void launch_smooth(const LevelArgs<T> &L, int color, int zero_init, const SolveCtrl *ctrl, hipStream_t st,
-                   const UpdArgs *upd, hipEvent_t ev0, hipEvent_t ev1) {
-    if (!L.rb) {
-        hipLaunchKernelGGL(k_smooth_nat<T>, tile_grid(tiles(L.nx, L.ny, L.nz)), dim3(BX, BY), 0, st, L, color,
-                           zero_init, ctrl);
-        return;
-    }
-    // large levels: 4 planes per thread; small ones one plane per thread for parallelism
-    const bool deep = (size_t)L.nx * L.ny * L.nz >= (1u << 19) && L.nz >= 8;
-    const dim3 g = deep ? tile_grid(tiles(L.nx / 2, L.ny, (L.nz + 3) / 4)) : tile_grid(tiles(L.nx / 2, L.ny, L.nz));
-    const UpdArgs u = upd ? *upd : UpdArgs{nullptr, nullptr, nullptr, 0.0};
+void launch_tdgl(const Inst<T> *I, const Work &w, int sel, hipStream_t st) {
+    FX_LAUNCH(k_tdgl<T>, w, I, w, sel);
+}
+
+inline dim3 per_inst(int ninst) { return dim3((ninst + 63) / 64); }
+
+template <typename T>
+void launch_flip(const Inst<T> *I, int ninst, hipStream_t st) {
+    hipLaunchKernelGGL(k_flip<T>, per_inst(ninst), dim3(64), 0, st, I, ninst);
+}
+
+template <typename T>
+void launch_begin(const Inst<T> *I, int ninst, int sel, hipStream_t st) {
+    hipLaunchKernelGGL(k_begin<T>, per_inst(ninst), dim3(64), 0, st, I, ninst, sel);
+}
+
+template <typename T>
+void launch_extrap(const Inst<T> *I, const Work &w, hipStream_t st) {
+    FX_LAUNCH(k_extrap<T>, w, I, w);
+}
+
+template <typename T>
+void launch_residual(const Inst<T> *I, const Work &w, int after_cycle, int any_unfolded, hipStream_t st) {
+    auto *k0 = &k_residual<T, 0>;
+    auto *k2 = &k_residual<T, 2>;
+    FX_LAUNCH(k0, w, I, w, after_cycle);
+    if (after_cycle && any_unfolded) FX_LAUNCH(k2, w, I, w, after_cycle);
+}
+
+template <typename T>
+void launch_reduce(const Inst<T> *I, int ninst, int count_cycle, hipStream_t st) {
+    hipLaunchKernelGGL(k_reduce<T>, dim3(ninst), dim3(1024), 0, st, I, count_cycle);
+}
+
+template <typename T>
+void launch_smooth(const Inst<T> *I, const Work &w, int level, int color, int zero_init, int upd, int zt,
+                   double *probe, hipStream_t st, hipEvent_t ev0, hipEvent_t ev1) {
+    if (w.total <= 0) return;
+    const dim3 g = grid_of(w.total);
     auto go = [&](auto kern) {
-        if (ev0) hipExtLaunchKernelGGL(kern, g, dim3(BX, BY), 0, st, ev0, ev1, 0, L, color, ctrl, u);
-        else hipLaunchKernelGGL(kern, g, dim3(BX, BY), 0, st, L, color, ctrl, u);
+        if (ev0) hipExtLaunchKernelGGL(kern, g, dim3(BX, BY), 0, st, ev0, ev1, 0, I, w, level, color, probe);
+        else hipLaunchKernelGGL(kern, g, dim3(BX, BY), 0, st, I, w, level, color, probe);
     };
-    if (upd) {
-        if (deep) go(k_smooth_rb<T, 0, 4, 1>);
-        else go(k_smooth_rb<T, 0, 1, 1>);
-    } else if (zero_init) {
-        if (deep) go(k_smooth_rb<T, 1, 4, 0>);
-        else go(k_smooth_rb<T, 1, 1, 0>);
+    if (zt == 4) {
+        if (upd) go(k_smooth<T, 0, 4, 1>);
+        else if (zero_init) go(k_smooth<T, 1, 4, 0>);
+        else go(k_smooth<T, 0, 4, 0>);
     } else {
-        if (deep) go(k_smooth_rb<T, 0, 4, 0>);
-        else go(k_smooth_rb<T, 0, 1, 0>);
+        if (upd) go(k_smooth<T, 0, 1, 1>);
+        else if (zero_init) go(k_smooth<T, 1, 1, 0>);
+        else go(k_smooth<T, 0, 1, 0>);
     }
 }
 
 template <typename T>
-void launch_restrict(const LevelArgs<T> &F, const LevelArgs<T> &C, const XferArgs<T> &X, const SolveCtrl *ctrl,
-                     hipStream_t st) {
-    hipLaunchKernelGGL(k_restrict<T>, tile_grid(tiles(C.nx, C.ny, C.nz)), dim3(BX, BY), 0, st, F, C, X, ctrl);
+void launch_restrict(const Inst<T> *I, const Work &w, int level, hipStream_t st) {
+    FX_LAUNCH(k_restrict<T>, w, I, w, level);
 }
 
 template <typename T>
-void launch_prolong(const LevelArgs<T> &F, const LevelArgs<T> &C, const XferArgs<T> &X, const SolveCtrl *ctrl,
-                    hipStream_t st) {
-    hipLaunchKernelGGL(k_prolong<T>, tile_grid(tiles(F.rb ? F.nx / 2 : F.nx, F.ny, F.nz)), dim3(BX, BY), 0, st, F, C, X,
-                       ctrl);
+void launch_prolong(const Inst<T> *I, const Work &w, int level, hipStream_t st) {
+    FX_LAUNCH(k_prolong<T>, w, I, w, level);
 }
 
 template <typename T>
-void launch_coarse(const CoarseArgs<T> *dev_args, int lds_bytes, const SolveCtrl *ctrl, hipStream_t st) {
-    hipLaunchKernelGGL(k_coarse<T>, dim3(1), dim3(512), lds_bytes, st, dev_args, ctrl);
+void launch_coarse(const Inst<T> *I, int ninst, int lds_bytes, hipStream_t st) {
+    hipLaunchKernelGGL(k_coarse<T>, dim3(ninst), dim3(512), lds_bytes, st, I);
 }
 
-void launch_reduce(const double *part, int nparts, SolveCtrl *ctrl, int count_cycle, hipStream_t st) {
-    hipLaunchKernelGGL(k_reduce, dim3(1), dim3(1024), 0, st, part, nparts, ctrl, count_cycle);
+template <typename T>
+void launch_head(const Inst<T> *I, int ninst, int advance, hipStream_t st) {
+    hipLaunchKernelGGL(k_head<T>, per_inst(ninst), dim3(64), 0, st, I, ninst, advance);
 }
 
-void launch_ctrl_reset(SolveCtrl *ctrl, int max_cycles, double tol2, hipStream_t st) {
-    hipLaunchKernelGGL(k_ctrl_reset, dim3(1), dim3(1), 0, st, ctrl, max_cycles, tol2);
+template <typename T>
+void launch_zero_fix(const Inst<T> *I, const Work &w, hipStream_t st) {
+    FX_LAUNCH(k_zero_fix<T>, w, I, w);
 }
 
-void launch_extrap(double *out, const ExtrapArgs &a, size_t n, hipStream_t st) {
-    const size_t b = (n + 255) / 256;
-    hipLaunchKernelGGL(k_extrap, dim3(b < 8192 ? (unsigned)b : 8192u), dim3(256), 0, st, out, a, n);
+template <typename T>
+void launch_run_setup(const Inst<T> *I, int ninst, int nsteps, int has_sched, double dt, int first, hipStream_t st) {
+    hipLaunchKernelGGL(k_run_setup<T>, per_inst(ninst), dim3(64), 0, st, I, ninst, nsteps, has_sched, dt, first);
+}
+
+template <typename T>
+void launch_set_vtop(const Inst<T> *I, int ninst, double v, hipStream_t st) {
+    hipLaunchKernelGGL(k_set_vtop<T>, per_inst(ninst), dim3(64), 0, st, I, ninst, v);
+}
+
+void launch_put_state(InstState *dst, const InstState &v, hipStream_t st) {
+    hipLaunchKernelGGL(k_put_state, dim3(1), dim3(64), 0, st, dst, v);
 }
 
 void launch_fill(double *x, size_t n, double v, hipStream_t st) {
@@ -700,15 +1089,22 @@ void launch_fill(double *x, size_t n, double v, hipStream_t st) {
     hipLaunchKernelGGL(k_fill, dim3(b == 0 ? 1 : (b < 4096 ? (unsigned)b : 4096u)), dim3(256), 0, st, x, n, v);
 }
 
-#define FX_INST(T)                                                                                              \
-    template int launch_residual<T>(const ResArgs<T> &, hipStream_t);                                            \
-    template void launch_smooth<T>(const LevelArgs<T> &, int, int, const SolveCtrl *, hipStream_t, const UpdArgs *, \
-                                   hipEvent_t, hipEvent_t);                                                      \
-    template void launch_restrict<T>(const LevelArgs<T> &, const LevelArgs<T> &, const XferArgs<T> &,            \
-                                     const SolveCtrl *, hipStream_t);                                            \
-    template void launch_prolong<T>(const LevelArgs<T> &, const LevelArgs<T> &, const XferArgs<T> &,             \
-                                    const SolveCtrl *, hipStream_t);                                             \
-    template void launch_coarse<T>(const CoarseArgs<T> *, int, const SolveCtrl *, hipStream_t);
+#define FX_INST(T)                                                                                           \
+    template void launch_tdgl<T>(const Inst<T> *, const Work &, int, hipStream_t);                           \
+    template void launch_flip<T>(const Inst<T> *, int, hipStream_t);                                        \
+    template void launch_begin<T>(const Inst<T> *, int, int, hipStream_t);                                  \
+    template void launch_extrap<T>(const Inst<T> *, const Work &, hipStream_t);                              \
+    template void launch_residual<T>(const Inst<T> *, const Work &, int, int, hipStream_t);                  \
+    template void launch_reduce<T>(const Inst<T> *, int, int, hipStream_t);                                  \
+    template void launch_smooth<T>(const Inst<T> *, const Work &, int, int, int, int, int, double *,         \
+                                   hipStream_t, hipEvent_t, hipEvent_t);                                     \
+    template void launch_restrict<T>(const Inst<T> *, const Work &, int, hipStream_t);                       \
+    template void launch_prolong<T>(const Inst<T> *, const Work &, int, hipStream_t);                        \
+    template void launch_coarse<T>(const Inst<T> *, int, int, hipStream_t);                                  \
+    template void launch_head<T>(const Inst<T> *, int, int, hipStream_t);                                    \
+    template void launch_zero_fix<T>(const Inst<T> *, const Work &, hipStream_t);                            \
+    template void launch_run_setup<T>(const Inst<T> *, int, int, int, double, int, hipStream_t);             \
+    template void launch_set_vtop<T>(const Inst<T> *, int, double, hipStream_t);
 FX_INST(double)
 FX_INST(float)
 

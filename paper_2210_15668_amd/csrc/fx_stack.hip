@@ -27,15 +27,16 @@
 #include "fx_internal.h"
 #include "../../include/ferrox.h"
 
+#include <algorithm>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <new>
 #include <string>
-#include <vector>
-#include <algorithm>
 #include <type_traits>
+#include <vector>
 
 using namespace fx;
 
@@ -60,6 +61,11 @@ fx_status fail(fx_status s, const char *fmt, ...) {
         if (e_ != hipSuccess)                                                                \
             return fail(FX_EDEVICE, "%s failed: %s", #call, hipGetErrorString(e_));          \
     } while (0)
+
+int env_int(const char *name, int dflt) {
+    const char *v = getenv(name);
+    return v && *v ? atoi(v) : dflt;
+}
 
 constexpr int kBottomTarget = 8;         // stop coarsening at this many cells
 
@@ -106,12 +112,6 @@ struct DevLevel {
     int *ks = nullptr, *cnt = nullptr, *thick = nullptr, *pka = nullptr, *pkb = nullptr;
 };
 
-template <typename T>
-struct DevSet {
-    std::vector<DevLevel<T>> lv;
-    CoarseArgs<T> *coarse = nullptr;    // device copy of the coarse-kernel arguments
-    int coarse_lds = 0;
-};
 
 fx_status validate(const fx_stack_desc *d, Plan *p) {
     if (!d) return fail(FX_EINVAL, "desc is NULL");
@@ -215,6 +215,7 @@ void build_plan(const fx_stack_desc *d, Plan *p) {
     for (int l = nlev - 1; l >= 0; --l) {
         const HostLevel &L = p->lv[l];
         tail += (2 * L.ncell() + L.nsig() + 4 * L.nz) * w + 64;
+        if (l == nlev - 1) tail += 2 * L.ncell() * w + 16 * sizeof(double) + 64;   // bottom-solve vectors
         if (tail > (size_t)kCoarseLdsBytes) break;
         p->lc = l;
     }
@@ -264,96 +265,253 @@ void build_plan(const fx_stack_desc *d, Plan *p) {
     }
 }
 
-}  // namespace
 
-
-struct fx_stack {
+// ---------------------------------------------------------------- instances
+// Host view of one instance: its plan, scaled constants and the device
+// addresses carved from its region of the workspace.
+struct InstHost {
     fx_stack_desc d{};
     std::vector<int> mat;
     std::vector<double> eps_r, Na, Nd;
-    Plan plan;
-    hipStream_t st = nullptr;
-    // P: [0] the caller's array, [1] workspace; pcur holds P^n
+    Plan plan{};
+    double VT = 0.0, scale = 0.0, dmax = 0.0;
+    // P: [0] the caller's array, [1] workspace.  phi: [0] the caller's array,
+    // [1..5] workspace; which buffer holds phi^n and the stored time levels is
+    // device state (InstState).
     double *P[2] = {nullptr, nullptr};
-    int pcur = 0;
-    // phi: [0] the caller's array, [1..5] workspace; phicur holds phi^n and
-    // prev[0..hist-1] hold phi^{n-1}, phi^{n-2}, phi^{n-3} of the previous time
-    // steps.  A solve writes its iterates into two buffers that are none of
-    // these, so the entry state survives a failed solve.
-    static constexpr int kPhiBufs = 6, kMaxHist = 3;
     double *phi[kPhiBufs] = {};
-    int phicur = 0;
-    int prev[kMaxHist] = {1, 2, 3};
-    int hist = 0;
-    // finest-level FP64 tables
     double *t_cxy = nullptr, *t_czm = nullptr, *t_czp = nullptr, *t_wl = nullptr, *t_wr = nullptr;
     double *t_p0e = nullptr, *t_n0e = nullptr;
     int *t_flags = nullptr;
-    DevSet<double> D64;
-    DevSet<float> D32;
+    std::vector<DevLevel<double>> L64;
+    std::vector<DevLevel<float>> L32;
     double *part = nullptr;
-    int part_n = 0;
-    SolveCtrl *ctrl = nullptr;          // device
-    SolveCtrl *ctrl_host = nullptr;     // pinned
-    double VT = 0.0, scale = 0.0;
-    double dmax = 0.0;
-    int nu1 = 2, nu2 = 2, bottom_sweeps = 12;
-    int k_pred = 4;                     // cycles enqueued before the first convergence check
-    int trace = 0;
-    // kernel-duration probe of the finest-level smoother
-    int probe = 0;
-    std::vector<hipEvent_t> ev;         // pairs (start, stop)
-    int ev_used = 0;
-    double probe_bytes = 0.0;
+    int lds = 0;                        // LDS bytes of this instance's coarse levels
+    double filled_top = NAN;            // contact value last written into the caller's top metal planes
 };
 
-namespace {
+constexpr int kSchedChunk = 1024;       // schedule entries per instance held on the device
+constexpr int kProbeMax = 4096;         // timed launches per probe
+constexpr int kMaxBatch = 4096;
+constexpr int kUnitPow = 5;             // captured unit graphs: 1, 2, 4, 8, 16 units
 
-// Lay out (or, with ws == nullptr, only size) the workspace.
-size_t carve(fx_stack *s, void *ws) {
-    Carver cv(ws);
-    const Plan &p = s->plan;
-    const size_t nfull = (size_t)p.nx * p.ny * p.nz;
-    s->P[1] = (double *)cv.take(nfull * sizeof(double));
-    for (int b = 1; b < fx_stack::kPhiBufs; ++b) s->phi[b] = (double *)cv.take(nfull * sizeof(double));
-    const int nzd = p.nzd;
-    s->t_cxy = (double *)cv.take(nzd * sizeof(double));
-    s->t_czm = (double *)cv.take(nzd * sizeof(double));
-    s->t_czp = (double *)cv.take(nzd * sizeof(double));
-    s->t_wl = (double *)cv.take(nzd * sizeof(double));
-    s->t_wr = (double *)cv.take(nzd * sizeof(double));
-    s->t_p0e = (double *)cv.take(nzd * sizeof(double));
-    s->t_n0e = (double *)cv.take(nzd * sizeof(double));
-    s->t_flags = (int *)cv.take(nzd * sizeof(int));
-    const int nlev = (int)p.lv.size();
-    const bool mixed = s->d.prec == FX_PREC_MIXED;
-    s->D64.lv.assign(mixed ? 0 : nlev, DevLevel<double>());
-    s->D32.lv.assign(mixed ? nlev : 0, DevLevel<float>());
-    auto lay = [&](auto &D, const HostLevel &H, size_t w) {
-        using TT = std::remove_pointer_t<decltype(D.e)>;
-        const size_t n = H.ncell(), ns = H.nsig();
-        const int nz = H.nz;
-        D.e = (TT *)cv.take(n * w); D.r = (TT *)cv.take(n * w); D.sig = (TT *)cv.take(std::max<size_t>(ns, 1) * w);
-        D.cxy = (TT *)cv.take(nz * w); D.czm = (TT *)cv.take(nz * w);
-        D.czp = (TT *)cv.take(nz * w); D.dg = (TT *)cv.take(nz * w);
-        D.pwa = (TT *)cv.take(nz * w); D.pwb = (TT *)cv.take(nz * w);
-        D.ks = (int *)cv.take(nz * sizeof(int)); D.cnt = (int *)cv.take(nz * sizeof(int));
-        D.thick = (int *)cv.take(nz * sizeof(int)); D.pka = (int *)cv.take(nz * sizeof(int));
-        D.pkb = (int *)cv.take(nz * sizeof(int));
-    };
-    for (int l = 0; l < nlev; ++l) {
-        if (mixed) lay(s->D32.lv[l], p.lv[l], 4);
-        else lay(s->D64.lv[l], p.lv[l], 8);
+// A batch of instances (a single stack is a batch of one) sharing one
+// precision, one stream and one launch sequence.
+struct Engine {
+    int n = 0;
+    int prec = FX_PREC_FP64;
+    hipStream_t st = nullptr;
+    std::vector<InstHost> in;
+    void *inst_dev = nullptr;           // Inst<T>[n]
+    InstState *st_dev = nullptr;        // InstState[n]
+    InstState *mir = nullptr;           // pinned host mirror, valid between calls
+    int *prefix_dev = nullptr;
+    double *sched_dev = nullptr;        // n x kSchedChunk gate potentials
+    double *probe_dev = nullptr;        // kProbeMax byte counters
+    std::vector<int> prefix_host;
+    Work w_tdgl{}, w_ext{}, w_res{};
+    std::vector<Work> w_sm, w_rs, w_pr;
+    std::vector<int> zt, ncol;
+    int max_lc = 0, lds_max = 0, max_cycles = 1;
+    int any_unfolded = 0;               // some instance forms phi + clip(e) in the residual kernel
+    int nu1 = 2, nu2 = 2;
+    int k_pred = 4;                     // cycles enqueued before the first check of a plain solve
+    int trace = 0;
+    int ucap = 16;                      // units enqueued between host checks of a run
+    int mode = FX_LAUNCH_STREAM;
+    // kernel-duration probe of the finest-level smoother
+    int probe = 0;
+    int probe_stride = 1, probe_seen = 0;
+    std::vector<hipEvent_t> ev;         // pairs (start, stop)
+    int ev_used = 0;
+    // unit graphs (2^q units each) captured on a private stream
+    hipStream_t cap = nullptr;
+    hipGraphExec_t unit_exec[kUnitPow] = {};
+};
+
+fx_status validate_all(const fx_stack_desc *descs, int n, Engine *e) {
+    if (!descs) return fail(FX_EINVAL, "desc is NULL");
+    if (n < 1 || n > kMaxBatch) return fail(FX_EINVAL, "instance count %d outside 1..%d", n, kMaxBatch);
+    e->n = n;
+    e->in.assign(n, InstHost());
+    e->prec = descs[0].prec;
+    for (int i = 0; i < n; ++i) {
+        InstHost &h = e->in[i];
+        fx_status st = validate(&descs[i], &h.plan);
+        if (st) {
+            if (n > 1) g_err = "instance " + std::to_string(i) + ": " + g_err;
+            return st;
+        }
+        if (descs[i].prec != e->prec) return fail(FX_EINVAL, "instance %d: all instances need one precision", i);
+        h.d = descs[i];
+        const int nz = descs[i].nz;
+        h.mat.assign(descs[i].plane_mat, descs[i].plane_mat + nz);
+        h.eps_r.assign(descs[i].plane_eps_r, descs[i].plane_eps_r + nz);
+        h.Na.assign(descs[i].plane_Na, descs[i].plane_Na + nz);
+        h.Nd.assign(descs[i].plane_Nd, descs[i].plane_Nd + nz);
+        h.d.plane_mat = h.mat.data();
+        h.d.plane_eps_r = h.eps_r.data();
+        h.d.plane_Na = h.Na.data();
+        h.d.plane_Nd = h.Nd.data();
+        build_plan(&h.d, &h.plan);
+        h.scale = h.d.h * h.d.h / kEps0;
+        h.VT = kKb * h.d.T / kQe;
+        h.dmax = h.VT > 0 ? 40.0 * h.VT : 0.0;
     }
-    if (mixed) s->D32.coarse = (CoarseArgs<float> *)cv.take(sizeof(CoarseArgs<float>));
-    else s->D64.coarse = (CoarseArgs<double> *)cv.take(sizeof(CoarseArgs<double>));
-    // residual partial sums: one pair per 64x4 tile of the finest level (an upper bound
-    // for tiles spanning several planes)
-    const size_t nb = (size_t)((p.nx + 63) / 64) * ((p.ny + 3) / 4) * nzd;
-    s->part_n = (int)nb;
-    s->part = (double *)cv.take(2 * nb * sizeof(double));
-    s->ctrl = (SolveCtrl *)cv.take(sizeof(SolveCtrl));
+    return FX_OK;
+}
+
+// Coarse-kernel LDS layout of levels lc.. of one instance (16-byte slots).
+template <typename T>
+int coarse_layout(const Plan &p, Inst<T> *a) {
+    int off = 0;
+    auto take = [&](size_t bytes) { const int o = off; off += (int)((bytes + 15) & ~(size_t)15); return o; };
+    const int nl = (int)p.lv.size() - p.lc;
+    for (int q = 0; q < nl; ++q) {
+        const HostLevel &H = p.lv[p.lc + q];
+        const int oe = take(H.ncell() * sizeof(T)), orr = take(H.ncell() * sizeof(T));
+        const int os = take(H.nsig() * sizeof(T)), ot = take(4 * H.nz * sizeof(T));
+        if (a) { a->off_e[q] = oe; a->off_r[q] = orr; a->off_s[q] = os; a->off_t[q] = ot; }
+    }
+    const HostLevel &B = p.lv.back();
+    const int op = take(B.ncell() * sizeof(T)), oq = take(B.ncell() * sizeof(T));
+    const int ored = take(16 * sizeof(double));
+    if (a) { a->off_p = op; a->off_q = oq; a->off_red = ored; }
+    return off;
+}
+
+int tiles_smooth(const HostLevel &H, int zt) {
+    const int nzt = (H.nz + zt - 1) / zt;
+    return H.rb ? tiles3(H.nx / 2, H.ny, nzt) : tiles3(H.nx, H.ny, nzt);
+}
+
+// Launch shapes that depend on all instances: levels with their own
+// kernels, planes per smoother thread, colours per sweep.
+void plan_launches(Engine *e) {
+    e->max_lc = 0;
+    e->max_cycles = 1;
+    e->any_unfolded = 0;
+    for (const InstHost &h : e->in) {
+        e->max_lc = std::max(e->max_lc, h.plan.lc);
+        e->max_cycles = std::max(e->max_cycles, h.d.max_cycles);
+        if (!(h.plan.lv[0].rb && h.plan.lc > 0)) e->any_unfolded = 1;
+    }
+    e->zt.assign(e->max_lc, 1);
+    e->ncol.assign(e->max_lc, 2);
+    const int zt_env = env_int("FERROX_ZT", 0);
+    for (int l = 0; l < e->max_lc; ++l) {
+        size_t cells = 0;
+        int min_nz = 1 << 30;
+        for (const InstHost &h : e->in) {
+            if (l >= h.plan.lc) continue;
+            const HostLevel &H = h.plan.lv[l];
+            cells += H.ncell();
+            min_nz = std::min(min_nz, H.nz);
+            if (!H.rb) e->ncol[l] = 4;
+        }
+        // large levels: 4 planes per thread; small ones one plane per thread for parallelism
+        e->zt[l] = cells >= ((size_t)1 << 19) && min_nz >= 8 ? 4 : 1;
+        if (zt_env == 1 || zt_env == 4) e->zt[l] = zt_env;
+    }
+}
+
+// Lay out (or, with ws == nullptr, only size) the workspace: one region per
+// instance, then the shared tables.
+size_t carve(Engine *e, void *ws) {
+    Carver cv(ws);
+    const bool mixed = e->prec == FX_PREC_MIXED;
+    for (InstHost &h : e->in) {
+        const Plan &p = h.plan;
+        const size_t nfull = (size_t)p.nx * p.ny * p.nz;
+        h.P[1] = (double *)cv.take(nfull * sizeof(double));
+        for (int b = 1; b < kPhiBufs; ++b) h.phi[b] = (double *)cv.take(nfull * sizeof(double));
+        const int nzd = p.nzd;
+        h.t_cxy = (double *)cv.take(nzd * sizeof(double));
+        h.t_czm = (double *)cv.take(nzd * sizeof(double));
+        h.t_czp = (double *)cv.take(nzd * sizeof(double));
+        h.t_wl = (double *)cv.take(nzd * sizeof(double));
+        h.t_wr = (double *)cv.take(nzd * sizeof(double));
+        h.t_p0e = (double *)cv.take(nzd * sizeof(double));
+        h.t_n0e = (double *)cv.take(nzd * sizeof(double));
+        h.t_flags = (int *)cv.take(nzd * sizeof(int));
+        const int nlev = (int)p.lv.size();
+        h.L64.assign(mixed ? 0 : nlev, DevLevel<double>());
+        h.L32.assign(mixed ? nlev : 0, DevLevel<float>());
+        auto lay = [&](auto &D, const HostLevel &H, size_t w) {
+            using TT = std::remove_pointer_t<decltype(D.e)>;
+            const size_t nc = H.ncell(), ns = H.nsig();
+            const int nz = H.nz;
+            D.e = (TT *)cv.take(nc * w); D.r = (TT *)cv.take(nc * w); D.sig = (TT *)cv.take(std::max<size_t>(ns, 1) * w);
+            D.cxy = (TT *)cv.take(nz * w); D.czm = (TT *)cv.take(nz * w);
+            D.czp = (TT *)cv.take(nz * w); D.dg = (TT *)cv.take(nz * w);
+            D.pwa = (TT *)cv.take(nz * w); D.pwb = (TT *)cv.take(nz * w);
+            D.ks = (int *)cv.take(nz * sizeof(int)); D.cnt = (int *)cv.take(nz * sizeof(int));
+            D.thick = (int *)cv.take(nz * sizeof(int)); D.pka = (int *)cv.take(nz * sizeof(int));
+            D.pkb = (int *)cv.take(nz * sizeof(int));
+        };
+        for (int l = 0; l < nlev; ++l) {
+            if (mixed) lay(h.L32[l], p.lv[l], 4);
+            else lay(h.L64[l], p.lv[l], 8);
+        }
+        // residual partial sums: one pair per residual tile
+        const size_t nres = (size_t)tiles3(p.nx, p.ny, (p.nzd + kResZ - 1) / kResZ);
+        h.part = (double *)cv.take(2 * nres * sizeof(double));
+    }
+    const size_t inst_bytes = mixed ? sizeof(Inst<float>) : sizeof(Inst<double>);
+    e->inst_dev = cv.take((size_t)e->n * inst_bytes);
+    e->st_dev = (InstState *)cv.take((size_t)e->n * sizeof(InstState));
+    const size_t ntab = 3 + 3 * (size_t)e->max_lc;
+    e->prefix_dev = (int *)cv.take(ntab * (e->n + 1) * sizeof(int));
+    e->sched_dev = (double *)cv.take((size_t)e->n * kSchedChunk * sizeof(double));
+    e->probe_dev = (double *)cv.take(kProbeMax * sizeof(double));
     return cv.off + 256;
+}
+
+// Prefix tables of per-instance tile counts, one per launch kind.
+fx_status build_work(Engine *e) {
+    const int n = e->n;
+    e->prefix_host.clear();
+    int tab = 0;
+    fx_status bad = FX_OK;
+    auto mk = [&](auto count) -> Work {
+        Work w;
+        w.prefix = e->prefix_dev + (size_t)tab * (n + 1);
+        w.ninst = n;
+        long long tot = 0;
+        e->prefix_host.push_back(0);
+        for (int i = 0; i < n; ++i) {
+            tot += count(e->in[i]);
+            if (tot > (1LL << 30)) bad = FX_EINVAL;
+            e->prefix_host.push_back((int)std::min<long long>(tot, 1LL << 30));
+        }
+        w.total = (int)std::min<long long>(tot, 1LL << 30);
+        ++tab;
+        return w;
+    };
+    e->w_tdgl = mk([](const InstHost &h) { const Plan &p = h.plan; return p.f0 >= 0 ? tiles3(p.nx, p.ny, p.f1 - p.f0) : 0; });
+    e->w_ext = mk([](const InstHost &h) {
+        const Plan &p = h.plan;
+        return (int)(((size_t)p.nx * p.ny * p.nzd + kExtrapChunk - 1) / kExtrapChunk);
+    });
+    e->w_res = mk([](const InstHost &h) { const Plan &p = h.plan; return tiles3(p.nx, p.ny, (p.nzd + kResZ - 1) / kResZ); });
+    e->w_sm.clear(); e->w_rs.clear(); e->w_pr.clear();
+    for (int l = 0; l < e->max_lc; ++l) {
+        const int zt = e->zt[l];
+        e->w_sm.push_back(mk([&](const InstHost &h) { return l < h.plan.lc ? tiles_smooth(h.plan.lv[l], zt) : 0; }));
+        e->w_rs.push_back(mk([&](const InstHost &h) {
+            if (l >= h.plan.lc) return 0;
+            const HostLevel &C = h.plan.lv[l + 1];
+            return tiles3(C.nx, C.ny, C.nz);
+        }));
+        e->w_pr.push_back(mk([&](const InstHost &h) {
+            if (l >= h.plan.lc) return 0;
+            const HostLevel &F = h.plan.lv[l];
+            return F.rb ? tiles3(F.nx / 2, F.ny, F.nz) : tiles3(F.nx, F.ny, F.nz);
+        }));
+    }
+    if (bad) return fail(FX_EINVAL, "a launch would exceed 2^30 tiles");
+    HIP_OK(hipMemcpy(e->prefix_dev, e->prefix_host.data(), e->prefix_host.size() * sizeof(int), hipMemcpyHostToDevice));
+    return FX_OK;
 }
 
 template <typename T>
@@ -384,295 +542,580 @@ fx_status upload_level(const HostLevel &H, DevLevel<T> &D) {
 }
 
 template <typename T>
-LevelArgs<T> level_args(const fx_stack *s, const DevSet<T> &D, int l) {
-    const HostLevel &H = s->plan.lv[l];
-    LevelArgs<T> a;
-    a.nx = H.nx; a.ny = H.ny; a.nz = H.nz; a.rb = H.rb;
-    a.cxy = D.lv[l].cxy; a.czm = D.lv[l].czm; a.czp = D.lv[l].czp; a.dg = D.lv[l].dg;
-    a.e = D.lv[l].e; a.r = D.lv[l].r; a.sig = D.lv[l].sig;
-    a.sig_lo = H.sig_lo; a.sig_hi = H.sig_hi;
+const std::vector<DevLevel<T>> &levels(const InstHost &h) {
+    if constexpr (std::is_same<T, float>::value) return h.L32;
+    else return h.L64;
+}
+
+template <typename T>
+Inst<T> make_inst(const Engine *e, int i) {
+    const InstHost &h = e->in[i];
+    const Plan &p = h.plan;
+    const fx_stack_desc &d = h.d;
+    const std::vector<DevLevel<T>> &D = levels<T>(h);
+    Inst<T> a;
+    memset(&a, 0, sizeof a);
+    a.nx = p.nx; a.ny = p.ny; a.nz = p.nz; a.kb = p.kb; a.nzd = p.nzd;
+    a.f0 = p.f0 >= 0 ? p.f0 : 0;
+    a.f1 = p.f0 >= 0 ? p.f1 : 0;
+    a.nlev = (int)p.lv.size();
+    a.lc = p.lc;
+    a.fold = p.lv[0].rb && p.lc > 0;
+    a.max_cycles = d.max_cycles;
+    a.warm = d.warm_start;
+    a.tol2 = d.tol_rel * d.tol_rel;
+    a.h = d.h; a.alpha = d.alpha; a.beta = d.beta; a.gamma = d.gamma;
+    a.g11 = d.g11; a.g44 = d.g44; a.Gamma = d.Gamma; a.lambda = d.lambda; a.pbc = d.pbc;
+    a.v_b = d.v_bottom;
+    a.p_scale = d.h / kEps0;
+    a.rho_scale = h.scale;
+    a.vt_inv = h.VT > 0 ? 1.0 / h.VT : 0.0;
+    a.sig_scale = h.VT > 0 ? h.scale / h.VT : 0.0;
+    a.dmax = h.dmax;
+    a.cxy0 = h.t_cxy; a.czm0 = h.t_czm; a.czp0 = h.t_czp; a.wl = h.t_wl; a.wr = h.t_wr;
+    a.p0e = h.t_p0e; a.n0e = h.t_n0e; a.pflags = h.t_flags;
+    a.vsched = e->sched_dev + (size_t)i * kSchedChunk;
+    for (int b = 0; b < kPhiBufs; ++b) a.phi[b] = h.phi[b];
+    a.P[0] = h.P[0]; a.P[1] = h.P[1];
+    a.part = h.part;
+    a.st = e->st_dev + i;
+    for (int l = 0; l < a.nlev; ++l) {
+        const HostLevel &H = p.lv[l];
+        LevelArgs<T> &L = a.lv[l];
+        L.nx = H.nx; L.ny = H.ny; L.nz = H.nz; L.rb = H.rb;
+        L.cxy = D[l].cxy; L.czm = D[l].czm; L.czp = D[l].czp; L.dg = D[l].dg;
+        L.e = D[l].e; L.r = D[l].r; L.sig = D[l].sig;
+        L.sig_lo = H.sig_lo; L.sig_hi = H.sig_hi;
+        if (l + 1 < a.nlev) {
+            XferArgs<T> &X = a.xf[l];
+            X.cks = D[l + 1].ks; X.ccnt = D[l + 1].cnt;
+            X.fthick = D[l].thick; X.cthick = D[l + 1].thick;
+            X.pka = D[l].pka; X.pkb = D[l].pkb; X.pwa = D[l].pwa; X.pwb = D[l].pwb;
+            X.xy = p.lv[l + 1].xy_from_finer;
+        }
+    }
+    a.nu1 = e->nu1;
+    a.nu2 = e->nu2;
+    // CG in exact arithmetic ends within ncell steps; the cap only guards rounding
+    a.bottom_iters = (int)std::min<size_t>(2 * p.lv.back().ncell() + 8, 512);
+    a.bottom_tol2 = std::is_same<T, float>::value ? 1e-10 : 1e-14;
+    a.lds_bytes = coarse_layout<T>(p, &a);
     return a;
 }
 
-// Transfer tables between level l (fine) and l+1 (coarse).
+// Per-plane tables of the finest level and of every multigrid level, the
+// instance array and the initial states.
 template <typename T>
-XferArgs<T> xfer_args(const fx_stack *s, const DevSet<T> &D, int l) {
-    XferArgs<T> x;
-    x.cks = D.lv[l + 1].ks; x.ccnt = D.lv[l + 1].cnt;
-    x.fthick = D.lv[l].thick; x.cthick = D.lv[l + 1].thick;
-    x.pka = D.lv[l].pka; x.pkb = D.lv[l].pkb; x.pwa = D.lv[l].pwa; x.pwb = D.lv[l].pwb;
-    x.xy = s->plan.lv[l + 1].xy_from_finer;
-    return x;
-}
-
-template <typename T>
-fx_status upload_coarse(fx_stack *s, DevSet<T> &D) {
-    const Plan &p = s->plan;
-    CoarseArgs<T> A;
-    memset(&A, 0, sizeof A);
-    A.nlev = (int)p.lv.size() - p.lc;
-    A.nu1 = s->nu1; A.nu2 = s->nu2;
-    const HostLevel &B = p.lv.back();
-    A.bottom_sweeps = std::max(4, 2 * std::max(B.nx, std::max(B.ny, B.nz)));
-    int off = 0;
-    auto take = [&](size_t bytes) { const int o = off; off += (int)((bytes + 15) & ~(size_t)15); return o; };
-    for (int q = 0; q < A.nlev; ++q) {
-        const HostLevel &H = p.lv[p.lc + q];
-        A.lv[q] = level_args(s, D, p.lc + q);
-        A.off_e[q] = take(H.ncell() * sizeof(T));
-        A.off_r[q] = take(H.ncell() * sizeof(T));
-        A.off_s[q] = take(H.nsig() * sizeof(T));
-        A.off_t[q] = take(4 * H.nz * sizeof(T));
-        if (q + 1 < A.nlev) A.xf[q] = xfer_args(s, D, p.lc + q);
+fx_status upload_all(Engine *e) {
+    std::vector<Inst<T>> host(e->n);
+    for (int i = 0; i < e->n; ++i) {
+        InstHost &h = e->in[i];
+        const Plan &p = h.plan;
+        const fx_stack_desc &d = h.d;
+        const int nzd = p.nzd;
+        // finest-level tables: scaled coefficients, P face weights, carrier densities
+        std::vector<double> wl(nzd, 1.0), wr(nzd, 0.0), p0e(nzd, 0.0), n0e(nzd, 0.0);
+        std::vector<int> fl(nzd, 0);
+        for (int k = 0; k < nzd; ++k) {
+            const int K = p.kb + k;
+            if (k + 1 < nzd) {
+                const double eL = d.plane_eps_r[K], eR = d.plane_eps_r[K + 1];
+                wl[k] = eR / (eL + eR);
+                wr[k] = eL / (eL + eR);
+            }
+            const bool fe_near = d.plane_mat[K] == FX_MAT_FE || (k > 0 && d.plane_mat[K - 1] == FX_MAT_FE) ||
+                                 (k + 1 < nzd && d.plane_mat[K + 1] == FX_MAT_FE);
+            if (fe_near) fl[k] |= PF_P;
+            if (d.plane_mat[K] == FX_MAT_SC) {
+                fl[k] |= PF_SC;
+                const double net = d.plane_Nd[K] - d.plane_Na[K], ni = d.ni;
+                double pp, nn;
+                if (net >= 0) { nn = 0.5 * net + std::sqrt(0.25 * net * net + ni * ni); pp = ni * ni / nn; }
+                else { pp = -0.5 * net + std::sqrt(0.25 * net * net + ni * ni); nn = ni * ni / pp; }
+                p0e[k] = kQe * pp;
+                n0e[k] = kQe * nn;
+            }
+        }
+        const HostLevel &H0 = p.lv[0];
+        HIP_OK(hipMemcpy(h.t_cxy, H0.cxy.data(), nzd * sizeof(double), hipMemcpyHostToDevice));
+        HIP_OK(hipMemcpy(h.t_czm, H0.czm.data(), nzd * sizeof(double), hipMemcpyHostToDevice));
+        HIP_OK(hipMemcpy(h.t_czp, H0.czp.data(), nzd * sizeof(double), hipMemcpyHostToDevice));
+        HIP_OK(hipMemcpy(h.t_wl, wl.data(), nzd * sizeof(double), hipMemcpyHostToDevice));
+        HIP_OK(hipMemcpy(h.t_wr, wr.data(), nzd * sizeof(double), hipMemcpyHostToDevice));
+        HIP_OK(hipMemcpy(h.t_p0e, p0e.data(), nzd * sizeof(double), hipMemcpyHostToDevice));
+        HIP_OK(hipMemcpy(h.t_n0e, n0e.data(), nzd * sizeof(double), hipMemcpyHostToDevice));
+        HIP_OK(hipMemcpy(h.t_flags, fl.data(), nzd * sizeof(int), hipMemcpyHostToDevice));
+        const std::vector<DevLevel<T>> &D = levels<T>(h);
+        for (size_t l = 0; l < p.lv.size(); ++l) {
+            fx_status st = upload_level(p.lv[l], const_cast<DevLevel<T> &>(D[l]));
+            if (st) return st;
+        }
+        host[i] = make_inst<T>(e, i);
+        h.lds = host[i].lds_bytes;
+        if (h.lds > kCoarseLdsBytes) return fail(FX_EINVAL, "coarse levels need %d bytes of LDS", h.lds);
+        e->lds_max = std::max(e->lds_max, h.lds);
     }
-    A.lds_bytes = off;
-    A.r_in = D.lv[p.lc].r;
-    A.sig_in = D.lv[p.lc].sig;
-    A.e_out = D.lv[p.lc].e;
-    if (off > kCoarseLdsBytes) return fail(FX_EINVAL, "coarse levels need %d bytes of LDS", off);
-    D.coarse_lds = off;
-    HIP_OK(hipMemcpy(D.coarse, &A, sizeof A, hipMemcpyHostToDevice));
+    HIP_OK(hipMemcpy(e->inst_dev, host.data(), (size_t)e->n * sizeof(Inst<T>), hipMemcpyHostToDevice));
+    for (int i = 0; i < e->n; ++i) {
+        InstState &s = e->mir[i];
+        memset(&s, 0, sizeof s);
+        s.done = 1;                     // idle: no solve running
+        s.cur = 0;
+        for (int m = 0; m < kMaxHist; ++m) s.prev[m] = m + 1;
+        s.parked = 1;
+        s.v_top = e->in[i].d.v_top;
+    }
+    HIP_OK(hipMemcpy(e->st_dev, e->mir, (size_t)e->n * sizeof(InstState), hipMemcpyHostToDevice));
     return FX_OK;
 }
 
-// Launch one smoother colour; finest-level launches are timestamped while
-// the probe is on, and their algorithmic bytes accumulated (one touch of each
-// array: the other colour's e, this colour's r, sigma and e; plus the phi
-// pair read and write when the Newton update is folded in).
+// ------------------------------------------------------------ launch slots
 template <typename T>
-void smooth(fx_stack *s, const LevelArgs<T> &A, int l, int color, int zi, const UpdArgs *upd = nullptr) {
+const Inst<T> *idev(const Engine *e) { return (const Inst<T> *)e->inst_dev; }
+
+// One smoother colour at level l; finest-level launches are timed while the
+// probe is on.
+template <typename T>
+void smooth_l(Engine *e, int l, int color, int zi, int upd) {
+    const Work &w = e->w_sm[l];
+    if (w.total <= 0) return;
     hipEvent_t e0 = nullptr, e1 = nullptr;
-    if (l == 0 && s->probe && s->ev_used + 2 <= (int)s->ev.size()) {
-        e0 = s->ev[s->ev_used];
-        e1 = s->ev[s->ev_used + 1];
-        s->ev_used += 2;
-        const double n = (double)A.nx * A.ny * A.nz, ns = (double)A.nx * A.ny * (A.sig_hi - A.sig_lo);
-        double b = sizeof(T) * (0.5 * n + 0.5 * ns + 0.5 * n);       // r, sigma, e of this colour
-        if (!zi) b += sizeof(T) * 0.5 * n;                            // the other colour's e
-        if (upd) b += 16.0 * n;                                       // phi read + write
-        s->probe_bytes += b;
+    double *pb = nullptr;
+    if (l == 0 && e->probe && e->ev_used + 2 <= (int)e->ev.size() && (e->probe_seen++ % e->probe_stride) == 0) {
+        e0 = e->ev[e->ev_used];
+        e1 = e->ev[e->ev_used + 1];
+        pb = e->probe_dev + e->ev_used / 2;
+        e->ev_used += 2;
     }
-    launch_smooth(A, color, zi, s->ctrl, s->st, upd, e0, e1);
+    launch_smooth(idev<T>(e), w, l, color, zi, upd, e->zt[l], pb, e->st, e0, e1);
 }
 
-// V-cycle from level l.  On the finest level (l = 0) with red/black storage
-// the last black half-sweep also writes phi_out = phi_in + clip(e).
+// One V(nu1, nu2) cycle over every running instance.  Levels 0 .. lc-1 of an
+// instance have their own launches; the coarse kernel takes the rest.  On
+// the finest level the last black half-sweep also forms phi_out = phi_in +
+// clip(e) where the update is folded in.
 template <typename T>
-void vcycle(fx_stack *s, const DevSet<T> &D, int l, const UpdArgs *upd = nullptr) {
-    hipStream_t st = s->st;
-    if (l == s->plan.lc) {
-        launch_coarse(D.coarse, D.coarse_lds, s->ctrl, st);
-        return;
+void enq_vcycle(Engine *e) {
+    const Inst<T> *I = idev<T>(e);
+    for (int l = 0; l < e->max_lc; ++l) {
+        for (int q = 0; q < e->nu1; ++q)
+            for (int c = 0; c < e->ncol[l]; ++c) smooth_l<T>(e, l, c, q == 0 && c == 0, 0);
+        launch_restrict(I, e->w_rs[l], l, e->st);
     }
-    const LevelArgs<T> A = level_args(s, D, l);
-    const LevelArgs<T> C = level_args(s, D, l + 1);
-    const XferArgs<T> X = xfer_args(s, D, l);
-    const int ncol = A.rb ? 2 : 4;
-    for (int q = 0; q < s->nu1; ++q)
-        for (int c = 0; c < ncol; ++c) smooth(s, A, l, c, q == 0 && c == 0);
-    launch_restrict(A, C, X, s->ctrl, st);
-    vcycle(s, D, l + 1);
-    launch_prolong(A, C, X, s->ctrl, st);
-    for (int q = 0; q < s->nu2; ++q)
-        for (int c = 0; c < ncol; ++c)
-            smooth(s, A, l, c, 0, (upd && A.rb && q == s->nu2 - 1 && c == ncol - 1) ? upd : nullptr);
+    launch_coarse(I, e->n, e->lds_max, e->st);
+    for (int l = e->max_lc - 1; l >= 0; --l) {
+        launch_prolong(I, e->w_pr[l], l, e->st);
+        for (int q = 0; q < e->nu2; ++q)
+            for (int c = 0; c < e->ncol[l]; ++c) smooth_l<T>(e, l, c, 0, l == 0 && q == e->nu2 - 1 && c == 1);
+    }
 }
 
-// Fine-level residual at phi_in (+ e when given, written to phi_out) and the
-// stop decision.
-// count_cycle: this residual closes a multigrid cycle (the device counts it).
+// Cycle slot: one cycle and its residual for every running solve.
 template <typename T>
-void residual(fx_stack *s, const DevSet<T> &D, const double *phi_in, double *phi_out, bool with_e,
-              bool count_cycle) {
-    const Plan &p = s->plan;
-    ResArgs<T> a;
-    a.nx = p.nx; a.ny = p.ny; a.nzd = p.nzd; a.kb = p.kb;
-    a.v_b = s->d.v_bottom; a.v_t = s->d.v_top;
-    a.p_scale = s->d.h / kEps0;
-    a.rho_scale = s->scale;
-    a.vt_inv = s->VT > 0 ? 1.0 / s->VT : 0.0;
-    a.sig_scale = s->VT > 0 ? s->scale / s->VT : 0.0;
-    a.dmax = s->dmax;
-    a.cxy = s->t_cxy; a.czm = s->t_czm; a.czp = s->t_czp;
-    a.wl = s->t_wl; a.wr = s->t_wr; a.p0e = s->t_p0e; a.n0e = s->t_n0e; a.pflags = s->t_flags;
-    a.phi_in = phi_in;
-    a.phi_out = phi_out;
-    a.e = with_e ? D.lv[0].e : nullptr;
-    a.P = s->P[s->pcur];
-    a.L0 = level_args(s, D, 0);
-    a.part = s->part;
-    a.ctrl = s->ctrl;
-    const int n = launch_residual(a, s->st);
-    launch_reduce(s->part, n, s->ctrl, count_cycle ? 1 : 0, s->st);
+void enq_cycle(Engine *e) {
+    enq_vcycle<T>(e);
+    launch_residual(idev<T>(e), e->w_res, 1, e->any_unfolded, e->st);
+    launch_reduce(idev<T>(e), e->n, 1, e->st);
 }
 
-fx_status read_ctrl(fx_stack *s) {
-    HIP_OK(hipMemcpyAsync(s->ctrl_host, s->ctrl, sizeof(SolveCtrl), hipMemcpyDeviceToHost, s->st));
-    HIP_OK(hipStreamSynchronize(s->st));
+// Advance slot: finalize stopped solves, start the next time step where due.
+template <typename T>
+void enq_advance(Engine *e) {
+    const Inst<T> *I = idev<T>(e);
+    launch_head(I, e->n, 1, e->st);
+    launch_zero_fix(I, e->w_ext, e->st);
+    launch_tdgl(I, e->w_tdgl, 1, e->st);
+    launch_begin(I, e->n, 1, e->st);
+    launch_extrap(I, e->w_ext, e->st);
+    launch_residual(I, e->w_res, 0, 0, e->st);
+    launch_reduce(I, e->n, 0, e->st);
+}
+
+template <typename T>
+void enq_units(Engine *e, int units) {
+    for (int u = 0; u < units; ++u) {
+        enq_cycle<T>(e);
+        enq_advance<T>(e);
+    }
+}
+
+// Capture the unit sequences as graphs (once; a private stream records them).
+template <typename T>
+fx_status capture_units(Engine *e) {
+    if (e->unit_exec[0]) return FX_OK;
+    if (!e->cap) HIP_OK(hipStreamCreateWithFlags(&e->cap, hipStreamNonBlocking));
+    hipStream_t user = e->st;
+    for (int q = 0; q < kUnitPow; ++q) {
+        hipGraph_t g = nullptr;
+        e->st = e->cap;
+        hipError_t err = hipStreamBeginCapture(e->cap, hipStreamCaptureModeThreadLocal);
+        if (err == hipSuccess) {
+            enq_units<T>(e, 1 << q);
+            err = hipStreamEndCapture(e->cap, &g);
+        }
+        e->st = user;
+        if (err != hipSuccess) return fail(FX_EDEVICE, "graph capture failed: %s", hipGetErrorString(err));
+        err = hipGraphInstantiate(&e->unit_exec[q], g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        if (err != hipSuccess) return fail(FX_EDEVICE, "graph instantiation failed: %s", hipGetErrorString(err));
+    }
     return FX_OK;
 }
 
-bool holds_history(const fx_stack *s, int b) {
-    for (int m = 0; m < s->hist; ++m)
-        if (s->prev[m] == b) return true;
+template <typename T>
+fx_status launch_units(Engine *e, int units) {
+    if (e->mode == FX_LAUNCH_GRAPH && !e->probe) {
+        fx_status st = capture_units<T>(e);
+        if (st) return st;
+        for (int q = kUnitPow - 1; q >= 0; --q)
+            while (units >= (1 << q)) {
+                HIP_OK(hipGraphLaunch(e->unit_exec[q], e->st));
+                units -= 1 << q;
+            }
+        return FX_OK;
+    }
+    enq_units<T>(e, units);
+    return FX_OK;
+}
+
+fx_status read_states(Engine *e) {
+    HIP_OK(hipGetLastError());
+    HIP_OK(hipMemcpyAsync(e->mir, e->st_dev, (size_t)e->n * sizeof(InstState), hipMemcpyDeviceToHost, e->st));
+    HIP_OK(hipStreamSynchronize(e->st));
+    return FX_OK;
+}
+
+// Plain solve of every instance from its current phi (Step 0, poisson_solve).
+template <typename T>
+fx_status solve_plain_t(Engine *e) {
+    const Inst<T> *I = idev<T>(e);
+    launch_begin(I, e->n, 0, e->st);
+    launch_residual(I, e->w_res, 0, 0, e->st);
+    launch_reduce(I, e->n, 0, e->st);
+    int enq = 0;
+    int batch = e->trace ? 0 : std::max(1, e->k_pred);
+    fx_status st;
+    for (;;) {
+        for (int q = 0; q < batch && enq < e->max_cycles; ++q, ++enq) enq_cycle<T>(e);
+        if ((st = read_states(e))) return st;
+        bool all = true;
+        for (int i = 0; i < e->n; ++i) all &= e->mir[i].done != 0;
+        if (e->trace) {
+            const InstState &c = e->mir[0];
+            fprintf(stderr, "[ferrox] cycle %d |r|/|f| = %.3e\n", c.cycles, c.fn2 > 0 ? std::sqrt(c.rn2 / c.fn2) : 0.0);
+        }
+        if (all) break;
+        if (enq >= e->max_cycles) return fail(FX_EDEVICE, "solver state did not stop after %d cycles", enq);
+        batch = 1;
+    }
+    launch_head(I, e->n, 0, e->st);
+    launch_zero_fix(I, e->w_ext, e->st);
+    if ((st = read_states(e))) return st;
+    int kmax = 1;
+    for (int i = 0; i < e->n; ++i)
+        if (e->mir[i].status != FX_ENONFINITE) kmax = std::max(kmax, e->mir[i].cycles);
+    e->k_pred = kmax;
+    return FX_OK;
+}
+
+fx_status solve_plain(Engine *e) { return e->prec == FX_PREC_MIXED ? solve_plain_t<float>(e) : solve_plain_t<double>(e); }
+
+// nsteps time steps of every instance (Step 1a + Step 1b each).  The
+// schedule (host arrays of nsteps gate potentials per instance, or NULL)
+// is staged through the device in chunks; inside a chunk the host only
+// checks, every few units, whether all instances have parked.
+template <typename T>
+fx_status run_t(Engine *e, int nsteps, double dt, const double *const *sched) {
+    const Inst<T> *I = idev<T>(e);
+    fx_status st;
+    for (int done = 0, first = 1; done < nsteps; first = 0) {
+        const int chunk = std::min(kSchedChunk, nsteps - done);
+        if (sched) {
+            HIP_OK(hipStreamSynchronize(e->st));
+            for (int i = 0; i < e->n; ++i)
+                HIP_OK(hipMemcpyAsync(e->sched_dev + (size_t)i * kSchedChunk, sched[i] + done, chunk * sizeof(double),
+                                      hipMemcpyHostToDevice, e->st));
+        }
+        launch_run_setup(I, e->n, chunk, sched ? 1 : 0, dt, first, e->st);
+        enq_advance<T>(e);
+        long long budget = (long long)chunk * (e->max_cycles + 1) + 1;
+        int units = std::min(e->ucap, chunk);
+        for (;;) {
+            if ((st = launch_units<T>(e, units))) return st;
+            budget -= units;
+            if ((st = read_states(e))) return st;
+            int rem = 0;
+            bool all = true;
+            for (int i = 0; i < e->n; ++i) {
+                const InstState &s = e->mir[i];
+                if (s.parked) continue;
+                all = false;
+                rem = std::max(rem, s.target - s.step);
+            }
+            if (all) break;
+            if (budget <= 0) return fail(FX_EDEVICE, "time steps did not finish within the cycle budget");
+            units = std::max(1, std::min(e->ucap, rem));
+        }
+        done += chunk;
+        bool any_ok = false;
+        for (int i = 0; i < e->n; ++i) any_ok |= e->mir[i].status == FX_OK;
+        if (!any_ok) break;
+    }
+    return FX_OK;
+}
+
+fx_status run(Engine *e, int nsteps, double dt, const double *const *sched) {
+    return e->prec == FX_PREC_MIXED ? run_t<float>(e, nsteps, dt, sched) : run_t<double>(e, nsteps, dt, sched);
+}
+
+// Write the host mirror of instance i back to the device (stream-ordered).
+void put_state(Engine *e, int i) { launch_put_state(e->st_dev + i, e->mir[i], e->st); }
+
+bool holds_history(const InstState &s, int b) {
+    for (int m = 0; m < s.hist; ++m)
+        if (s.prev[m] == b) return true;
     return false;
 }
 
-// Lagrange extrapolation to t^{n+1} through t^n, t^{n-1}, ... (equal steps).
-const double kExtrap[4][4] = {{1, 0, 0, 0}, {2, -1, 0, 0}, {3, -3, 1, 0}, {4, -6, 4, -1}};
+void fill_contacts(Engine *e, int i, bool force) {
+    InstHost &h = e->in[i];
+    const Plan &p = h.plan;
+    const size_t nxy = (size_t)p.nx * p.ny;
+    const double vt = e->mir[i].v_top;
+    if (force && p.kb > 0) launch_fill(h.phi[0], (size_t)p.kb * nxy, h.d.v_bottom, e->st);
+    if (p.kt < p.nz && (force || !(h.filled_top == vt)))
+        launch_fill(h.phi[0] + (size_t)p.kt * nxy, (size_t)(p.nz - p.kt) * nxy, vt, e->st);
+    h.filled_top = vt;
+}
 
-// Newton-multigrid solve.  The iterate before cycle 0 is phi^n, or (in the
-// time loop, with previous levels held) their polynomial extrapolation
-// written to buffer other[1].  Cycle c writes other[c % 2] from the previous
-// iterate; kernels of cycles after the device has decided to stop return at
-// once, so a batch of cycles is enqueued before each host check.
-template <typename T>
-fx_status solve_impl(fx_stack *s, const DevSet<T> &D, fx_solve_info *info, bool time_step) {
-    const Plan &p = s->plan;
-    const size_t nxy = (size_t)p.nx * p.ny, off = (size_t)p.kb * nxy, nd = (size_t)p.nzd * nxy;
-    const int entry = s->phicur;
-    int other[2], no = 0;
-    for (int b = 0; b < fx_stack::kPhiBufs && no < 2; ++b)
-        if (b != entry && !holds_history(s, b)) other[no++] = b;
-    const int order = time_step ? std::min(s->hist, std::max(0, std::min(s->d.warm_start, fx_stack::kMaxHist))) : 0;
-    launch_ctrl_reset(s->ctrl, s->d.max_cycles, s->d.tol_rel * s->d.tol_rel, s->st);
-    const int start = order > 0 ? other[1] : entry;   // buffer holding the iterate before cycle 0
-    if (order > 0) {
-        ExtrapArgs ea;
-        ea.nin = order + 1;
-        for (int q = 0; q <= order; ++q) {
-            ea.c[q] = kExtrap[order][q];
-            ea.in[q] = s->phi[q == 0 ? entry : s->prev[q - 1]] + off;
+// Make the caller's arrays hold the current P and phi (mirror must be valid).
+fx_status sync_to_caller(Engine *e) {
+    for (int i = 0; i < e->n; ++i) {
+        InstHost &h = e->in[i];
+        InstState &s = e->mir[i];
+        const Plan &p = h.plan;
+        const size_t nxy = (size_t)p.nx * p.ny;
+        bool changed = false;
+        if (s.pcur != 0) {
+            if (p.f0 >= 0)
+                HIP_OK(hipMemcpyAsync(h.P[0] + p.f0 * nxy, h.P[1] + p.f0 * nxy, (p.f1 - p.f0) * nxy * sizeof(double),
+                                      hipMemcpyDeviceToDevice, e->st));
+            s.pcur = 0;
+            changed = true;
         }
-        launch_extrap(s->phi[start] + off, ea, nd, s->st);
-    }
-    residual<T>(s, D, s->phi[start], nullptr, false, false);
-    int enq = 0;                        // cycles enqueued so far
-    int batch = s->trace ? 0 : std::max(1, s->k_pred);
-    fx_status st;
-    for (;;) {
-        const bool fold = p.lv[0].rb && p.lc > 0;
-        for (int q = 0; q < batch && enq < s->d.max_cycles; ++q, ++enq) {
-            const double *src = s->phi[enq == 0 ? start : other[(enq - 1) % 2]];
-            double *dst = s->phi[other[enq % 2]];
-            if (fold) {
-                const UpdArgs u{src + off, dst + off, s->t_flags, s->dmax};
-                vcycle<T>(s, D, 0, &u);
-                residual<T>(s, D, dst, nullptr, false, true);
-            } else {
-                vcycle<T>(s, D, 0);
-                residual<T>(s, D, src, dst, true, true);
+        if (s.cur != 0) {
+            // buffer 0 is the caller's: if it holds a stored level, move that level first
+            for (int m = 0; m < s.hist; ++m) {
+                if (s.prev[m] != 0) continue;
+                int spare = 1;
+                while (spare == s.cur || holds_history(s, spare)) ++spare;
+                HIP_OK(hipMemcpyAsync(h.phi[spare] + p.kb * nxy, h.phi[0] + p.kb * nxy,
+                                      (size_t)p.nzd * nxy * sizeof(double), hipMemcpyDeviceToDevice, e->st));
+                s.prev[m] = spare;
             }
+            HIP_OK(hipMemcpyAsync(h.phi[0] + p.kb * nxy, h.phi[s.cur] + p.kb * nxy,
+                                  (size_t)p.nzd * nxy * sizeof(double), hipMemcpyDeviceToDevice, e->st));
+            s.cur = 0;
+            changed = true;
         }
-        if ((st = read_ctrl(s))) return st;
-        const SolveCtrl &c = *s->ctrl_host;
-        if (s->trace)
-            fprintf(stderr, "[ferrox] cycle %d |r|/|f| = %.3e\n", c.cycles, c.fn2 > 0 ? std::sqrt(c.rn2 / c.fn2) : 0.0);
-        if (c.done || enq >= s->d.max_cycles) break;
-        batch = 1;
+        if (changed) put_state(e, i);
+        fill_contacts(e, i, false);
     }
-    const SolveCtrl c = *s->ctrl_host;
-    const int ncyc = c.cycles;
-    const int final_buf = ncyc == 0 ? start : other[(ncyc - 1) % 2];
-    double rn = std::sqrt(c.rn2), fn = std::sqrt(c.fn2);
-    fx_status res = FX_OK;
-    int newcur = final_buf;
-    if (c.done == 2) {
-        res = FX_ENONFINITE;
-        newcur = entry;                 // the entry iterate is untouched
-    } else if (c.done == 1 && fn == 0.0 && rn != 0.0) {
-        // f = 0: N(0) = 0 exactly, so phi = 0 is the root
-        launch_fill(s->phi[final_buf] + off, nd, 0.0, s->st);
-        rn = 0.0;
-    } else if (c.done != 1) {
-        res = FX_ENOCONV;
+    HIP_OK(hipGetLastError());
+    return FX_OK;
+}
+
+int env_mode(int dflt) {
+    const int m = env_int("FERROX_LAUNCH", dflt);
+    return m == FX_LAUNCH_GRAPH ? FX_LAUNCH_GRAPH : FX_LAUNCH_STREAM;
+}
+
+// Common set-up of stacks and batches, then Step 0 for every instance.
+fx_status engine_init(Engine *e, double *const *d_P, double *const *d_phi, void *d_ws, size_t ws_bytes,
+                      void *stream) {
+    const size_t need = carve(e, nullptr);
+    if (ws_bytes < need) return fail(FX_ENOMEM, "workspace %zu bytes < %zu needed", ws_bytes, need);
+    carve(e, d_ws);
+    e->st = (hipStream_t)stream;
+    e->nu1 = std::max(1, env_int("FERROX_NU1", 2));
+    e->nu2 = std::max(1, env_int("FERROX_NU2", 2));
+    e->trace = env_int("FERROX_TRACE", 0);
+    e->ucap = std::max(1, std::min(1 << (kUnitPow - 1), env_int("FERROX_UNITS", 16)));
+    for (int i = 0; i < e->n; ++i) {
+        e->in[i].P[0] = d_P[i];
+        e->in[i].phi[0] = d_phi[i];
     }
-    // the entry iterate phi^n becomes the newest stored level
-    if (time_step && res == FX_OK && newcur != entry) {
-        for (int m = fx_stack::kMaxHist - 1; m > 0; --m) s->prev[m] = s->prev[m - 1];
-        s->prev[0] = entry;
-        s->hist = std::min(s->hist + 1, fx_stack::kMaxHist);
+    if (hipHostMalloc((void **)&e->mir, (size_t)e->n * sizeof(InstState), 0) != hipSuccess)
+        return fail(FX_EDEVICE, "hipHostMalloc failed");
+    fx_status st = build_work(e);
+    if (st) return st;
+    st = e->prec == FX_PREC_MIXED ? upload_all<float>(e) : upload_all<double>(e);
+    if (st) return st;
+    for (int i = 0; i < e->n; ++i) {
+        InstHost &h = e->in[i];
+        const Plan &p = h.plan;
+        // P: zero off the ferroelectric in both buffers
+        const size_t nfull = (size_t)p.nx * p.ny * p.nz, nxy = (size_t)p.nx * p.ny;
+        launch_fill(h.P[1], nfull, 0.0, e->st);
+        if (p.f0 >= 0) {
+            if (p.f0 > 0) launch_fill(h.P[0], (size_t)p.f0 * nxy, 0.0, e->st);
+            if (p.f1 < p.nz) launch_fill(h.P[0] + (size_t)p.f1 * nxy, (size_t)(p.nz - p.f1) * nxy, 0.0, e->st);
+        } else {
+            launch_fill(h.P[0], nfull, 0.0, e->st);
+        }
+        // Step 0: phi^{0,(0)} = 0, then solve
+        for (int b = 0; b < kPhiBufs; ++b) launch_fill(h.phi[b], nfull, 0.0, e->st);
+        fill_contacts(e, i, true);
+    }
+    launch_fill(e->probe_dev, kProbeMax, 0.0, e->st);
+    return solve_plain(e);
+}
+
+void engine_release(Engine *e) {
+    if (e->st) (void)hipStreamSynchronize(e->st); else (void)hipDeviceSynchronize();
+    for (int q = 0; q < kUnitPow; ++q)
+        if (e->unit_exec[q]) (void)hipGraphExecDestroy(e->unit_exec[q]);
+    if (e->cap) (void)hipStreamDestroy(e->cap);
+    if (e->mir) (void)hipHostFree(e->mir);
+    for (hipEvent_t ev : e->ev) (void)hipEventDestroy(ev);
+}
+
+fx_status status_message(const InstState &s, int inst) {
+    const char *who = inst >= 0 ? "instance " : "";
+    char idx[32] = "";
+    if (inst >= 0) snprintf(idx, sizeof idx, "%d: ", inst);
+    if (s.status == FX_ENOCONV)
+        return fail(FX_ENOCONV, "%s%sno convergence in %d cycles: |r|/|f| = %.3e", who, idx, s.cycles,
+                    s.fn2 > 0 ? std::sqrt(s.rn2 / s.fn2) : 0.0);
+    if (s.status == FX_ENONFINITE) return fail(FX_ENONFINITE, "%s%snon-finite residual", who, idx);
+    return FX_OK;
+}
+
+fx_status get_field_impl(Engine *e, int i, int which, double *h_out) {
+    if (which < FX_FIELD_P || which > FX_FIELD_PHI_PREV3) return fail(FX_EINVAL, "unknown field %d", which);
+    fx_status st = sync_to_caller(e);
+    if (st) return st;
+    const InstHost &h = e->in[i];
+    const InstState &s = e->mir[i];
+    const Plan &p = h.plan;
+    const size_t nxy = (size_t)p.nx * p.ny, n = nxy * p.nz;
+    if (which >= FX_FIELD_PHI_PREV) {
+        const int m = which - FX_FIELD_PHI_PREV;
+        if (m >= s.hist) return fail(FX_ESTATE, "time level n-%d is not held", m + 1);
+        // device planes from the history buffer, contacts from the caller's array
+        HIP_OK(hipMemcpyAsync(h_out, h.phi[0], n * sizeof(double), hipMemcpyDeviceToHost, e->st));
+        HIP_OK(hipMemcpyAsync(h_out + p.kb * nxy, h.phi[s.prev[m]] + p.kb * nxy, (size_t)p.nzd * nxy * sizeof(double),
+                              hipMemcpyDeviceToHost, e->st));
     } else {
-        s->hist = 0;
+        HIP_OK(hipMemcpyAsync(h_out, which == FX_FIELD_P ? h.P[0] : h.phi[0], n * sizeof(double),
+                              hipMemcpyDeviceToHost, e->st));
     }
-    s->phicur = newcur;
-    if (res != FX_ENONFINITE) s->k_pred = std::max(1, ncyc);
-    if (info) { info->cycles = ncyc; info->status = res; info->res_norm = rn; info->rhs_norm = fn; }
-    if (res == FX_ENOCONV) return fail(res, "no convergence in %d cycles: |r|/|f| = %.3e", ncyc, rn / fn);
-    if (res == FX_ENONFINITE) return fail(res, "non-finite residual");
+    HIP_OK(hipStreamSynchronize(e->st));
     return FX_OK;
 }
 
-// A solve inside the time loop may start from the extrapolated iterate; the
-// history is kept only across consecutive time steps.
-fx_status solve(fx_stack *s, fx_solve_info *info, bool time_step = false) {
-    return s->d.prec == FX_PREC_MIXED ? solve_impl<float>(s, s->D32, info, time_step)
-                                      : solve_impl<double>(s, s->D64, info, time_step);
-}
-
-void set_contacts(fx_stack *s) {
-    const Plan &p = s->plan;
-    const size_t nxy = (size_t)p.nx * p.ny;
-    if (p.kb > 0) launch_fill(s->phi[0], (size_t)p.kb * nxy, s->d.v_bottom, s->st);
-    if (p.kt < p.nz) launch_fill(s->phi[0] + (size_t)p.kt * nxy, (size_t)(p.nz - p.kt) * nxy, s->d.v_top, s->st);
-}
-
-void tdgl_impl(fx_stack *s, double dt) {
-    const Plan &p = s->plan;
-    if (p.f0 < 0) return;
-    TdglArgs a;
-    a.nx = p.nx; a.ny = p.ny; a.f0 = p.f0; a.f1 = p.f1;
-    a.h = s->d.h; a.dt = dt;
-    a.alpha = s->d.alpha; a.beta = s->d.beta; a.gamma = s->d.gamma;
-    a.g11 = s->d.g11; a.g44 = s->d.g44; a.Gamma = s->d.Gamma;
-    a.pbc = s->d.pbc; a.lambda = s->d.lambda;
-    a.P = s->P[s->pcur]; a.phi = s->phi[s->phicur]; a.Pn = s->P[1 - s->pcur];
-    launch_tdgl(a, s->st);
-    s->pcur = 1 - s->pcur;
-}
-
-// Make the caller's arrays hold the current P and phi.
-fx_status sync_to_caller(fx_stack *s) {
-    const Plan &p = s->plan;
-    const size_t nxy = (size_t)p.nx * p.ny;
-    if (s->pcur != 0) {
-        if (p.f0 >= 0)
-            HIP_OK(hipMemcpyAsync(s->P[0] + p.f0 * nxy, s->P[1] + p.f0 * nxy, (p.f1 - p.f0) * nxy * sizeof(double),
-                                  hipMemcpyDeviceToDevice, s->st));
-        s->pcur = 0;
+fx_status set_field_impl(Engine *e, int i, int which, const double *h_in) {
+    if (which < FX_FIELD_P || which > FX_FIELD_PHI_PREV3) return fail(FX_EINVAL, "unknown field %d", which);
+    fx_status st = sync_to_caller(e);
+    if (st) return st;
+    InstHost &h = e->in[i];
+    InstState &s = e->mir[i];
+    const Plan &p = h.plan;
+    const size_t nxy = (size_t)p.nx * p.ny, n = nxy * p.nz;
+    if (which >= FX_FIELD_PHI_PREV) {
+        const int m = which - FX_FIELD_PHI_PREV;
+        if (m != s.hist) return fail(FX_ESTATE, "set time level n-%d after n-1 .. n-%d", m + 1, m);
+        int b = 1;                      // cur is 0 after sync_to_caller
+        while (holds_history(s, b)) ++b;
+        HIP_OK(hipMemcpyAsync(h.phi[b] + p.kb * nxy, h_in + p.kb * nxy, (size_t)p.nzd * nxy * sizeof(double),
+                              hipMemcpyHostToDevice, e->st));
+        HIP_OK(hipStreamSynchronize(e->st));
+        s.prev[m] = b;
+        s.hist = m + 1;
+        put_state(e, i);
+        return FX_OK;
     }
-    if (s->phicur != 0) {
-        // buffer 0 is the caller's: if it holds a stored level, move that level first
-        for (int m = 0; m < s->hist; ++m) {
-            if (s->prev[m] != 0) continue;
-            int spare = 1;
-            while (spare == s->phicur || holds_history(s, spare)) ++spare;
-            HIP_OK(hipMemcpyAsync(s->phi[spare] + p.kb * nxy, s->phi[0] + p.kb * nxy,
-                                  (size_t)p.nzd * nxy * sizeof(double), hipMemcpyDeviceToDevice, s->st));
-            s->prev[m] = spare;
+    s.hist = 0;
+    put_state(e, i);
+    if (which == FX_FIELD_P) {
+        HIP_OK(hipMemcpyAsync(h.P[0], h_in, n * sizeof(double), hipMemcpyHostToDevice, e->st));
+        HIP_OK(hipStreamSynchronize(e->st));
+        if (p.f0 >= 0) {
+            if (p.f0 > 0) launch_fill(h.P[0], (size_t)p.f0 * nxy, 0.0, e->st);
+            if (p.f1 < p.nz) launch_fill(h.P[0] + (size_t)p.f1 * nxy, (size_t)(p.nz - p.f1) * nxy, 0.0, e->st);
+        } else {
+            launch_fill(h.P[0], n, 0.0, e->st);
         }
-        HIP_OK(hipMemcpyAsync(s->phi[0] + p.kb * nxy, s->phi[s->phicur] + p.kb * nxy,
-                              (size_t)p.nzd * nxy * sizeof(double), hipMemcpyDeviceToDevice, s->st));
-        s->phicur = 0;
+    } else {
+        HIP_OK(hipMemcpyAsync(h.phi[0], h_in, n * sizeof(double), hipMemcpyHostToDevice, e->st));
+        HIP_OK(hipStreamSynchronize(e->st));
+        fill_contacts(e, i, true);
     }
     return FX_OK;
 }
 
-int env_int(const char *name, int dflt) {
-    const char *v = getenv(name);
-    return v && *v ? atoi(v) : dflt;
+fx_status probe_on(Engine *e, int kernel, int max_launches, int stride) {
+    if (kernel != FX_PROBE_OFF && kernel != FX_PROBE_SMOOTH_FINE) return fail(FX_EINVAL, "unknown probe %d", kernel);
+    if (kernel == FX_PROBE_OFF) { e->probe = 0; return FX_OK; }
+    if (max_launches < 1 || max_launches > kProbeMax)
+        return fail(FX_EINVAL, "max_launches must be in 1..%d", kProbeMax);
+    if (stride < 1) return fail(FX_EINVAL, "stride must be >= 1");
+    HIP_OK(hipStreamSynchronize(e->st));
+    while ((int)e->ev.size() < 2 * max_launches) {
+        hipEvent_t ev;
+        HIP_OK(hipEventCreate(&ev));
+        e->ev.push_back(ev);
+    }
+    e->ev.resize(2 * max_launches);
+    launch_fill(e->probe_dev, kProbeMax, 0.0, e->st);
+    HIP_OK(hipStreamSynchronize(e->st));
+    e->probe = kernel;
+    e->probe_stride = stride;
+    e->probe_seen = 0;
+    e->ev_used = 0;
+    return FX_OK;
+}
+
+// Launches in which no instance worked (all solves stopped) carry no bytes
+// and are left out.
+fx_status probe_read(Engine *e, double *total_ms, int *launches, double *bytes) {
+    HIP_OK(hipStreamSynchronize(e->st));
+    const int nl = e->ev_used / 2;
+    std::vector<double> b(std::max(nl, 1));
+    if (nl > 0) HIP_OK(hipMemcpy(b.data(), e->probe_dev, nl * sizeof(double), hipMemcpyDeviceToHost));
+    double tot = 0.0, by = 0.0;
+    int cnt = 0;
+    for (int q = 0; q < nl; ++q) {
+        if (!(b[q] > 0)) continue;
+        float ms = 0.0f;
+        HIP_OK(hipEventElapsedTime(&ms, e->ev[2 * q], e->ev[2 * q + 1]));
+        tot += ms;
+        by += b[q];
+        ++cnt;
+    }
+    if (total_ms) *total_ms = tot;
+    if (launches) *launches = cnt;
+    if (bytes) *bytes = by;
+    return FX_OK;
 }
 
 }  // namespace
+
+struct fx_stack {
+    Engine e;
+};
+
+struct fx_batch {
+    Engine e;
+};
 
 extern "C" {
 
 size_t stack_workspace_bytes(const fx_stack_desc *desc) {
     g_err.clear();
-    fx_stack tmp;
-    if (validate(desc, &tmp.plan)) return 0;
-    tmp.d = *desc;
-    build_plan(desc, &tmp.plan);
+    Engine tmp;
+    if (validate_all(desc, 1, &tmp)) return 0;
+    plan_launches(&tmp);
     return carve(&tmp, nullptr);
 }
 
@@ -687,237 +1130,123 @@ fx_status init_stack(const fx_stack_desc *desc, double *d_P, double *d_phi, void
         return fail(FX_EINVAL, "d_P and d_phi must be 16-byte aligned");
     fx_stack *s = new (std::nothrow) fx_stack();
     if (!s) return fail(FX_ENOMEM, "host allocation failed");
-    fx_status st = validate(desc, &s->plan);
+    Engine *e = &s->e;
+    fx_status st = validate_all(desc, 1, e);
     if (st) { delete s; return st; }
-    s->d = *desc;
-    s->mat.assign(desc->plane_mat, desc->plane_mat + desc->nz);
-    s->eps_r.assign(desc->plane_eps_r, desc->plane_eps_r + desc->nz);
-    s->Na.assign(desc->plane_Na, desc->plane_Na + desc->nz);
-    s->Nd.assign(desc->plane_Nd, desc->plane_Nd + desc->nz);
-    s->d.plane_mat = s->mat.data(); s->d.plane_eps_r = s->eps_r.data();
-    s->d.plane_Na = s->Na.data(); s->d.plane_Nd = s->Nd.data();
-    build_plan(&s->d, &s->plan);
-    const size_t need = carve(s, nullptr);
-    if (ws_bytes < need) { delete s; return fail(FX_ENOMEM, "workspace %zu bytes < %zu needed", ws_bytes, need); }
-    carve(s, d_ws);
-    s->st = (hipStream_t)stream;
-    s->P[0] = d_P;
-    s->phi[0] = d_phi;
-    s->scale = desc->h * desc->h / kEps0;
-    s->VT = kKb * desc->T / kQe;
-    s->dmax = s->VT > 0 ? 40.0 * s->VT : 0.0;
-    s->nu1 = std::max(1, env_int("FERROX_NU1", 2));
-    s->nu2 = std::max(1, env_int("FERROX_NU2", 2));
-    s->trace = env_int("FERROX_TRACE", 0);
-    const Plan &p = s->plan;
-    const int nzd = p.nzd;
-    // finest-level tables: scaled coefficients, P face weights, carrier densities
-    std::vector<double> wl(nzd, 1.0), wr(nzd, 0.0), p0e(nzd, 0.0), n0e(nzd, 0.0);
-    std::vector<int> fl(nzd, 0);
-    for (int k = 0; k < nzd; ++k) {
-        const int K = p.kb + k;
-        if (k + 1 < nzd) {
-            const double eL = desc->plane_eps_r[K], eR = desc->plane_eps_r[K + 1];
-            wl[k] = eR / (eL + eR);
-            wr[k] = eL / (eL + eR);
-        }
-        const bool fe_near = desc->plane_mat[K] == FX_MAT_FE || (k > 0 && desc->plane_mat[K - 1] == FX_MAT_FE) ||
-                             (k + 1 < nzd && desc->plane_mat[K + 1] == FX_MAT_FE);
-        if (fe_near) fl[k] |= PF_P;
-        if (desc->plane_mat[K] == FX_MAT_SC) {
-            fl[k] |= PF_SC;
-            const double net = desc->plane_Nd[K] - desc->plane_Na[K], ni = desc->ni;
-            double pp, nn;
-            if (net >= 0) { nn = 0.5 * net + std::sqrt(0.25 * net * net + ni * ni); pp = ni * ni / nn; }
-            else { pp = -0.5 * net + std::sqrt(0.25 * net * net + ni * ni); nn = ni * ni / pp; }
-            p0e[k] = kQe * pp;
-            n0e[k] = kQe * nn;
-        }
-    }
-    const HostLevel &H0 = p.lv[0];
-#define UP(dst, v, T)                                                                            \
-    do {                                                                                         \
-        hipError_t e_ = hipMemcpy(dst, (v).data(), nzd * sizeof(T), hipMemcpyHostToDevice);      \
-        if (e_ != hipSuccess) { delete s; return fail(FX_EDEVICE, "table upload: %s", hipGetErrorString(e_)); } \
-    } while (0)
-    UP(s->t_cxy, H0.cxy, double); UP(s->t_czm, H0.czm, double); UP(s->t_czp, H0.czp, double);
-    UP(s->t_wl, wl, double); UP(s->t_wr, wr, double); UP(s->t_p0e, p0e, double); UP(s->t_n0e, n0e, double);
-    UP(s->t_flags, fl, int);
-#undef UP
-    for (size_t l = 0; l < p.lv.size(); ++l) {
-        st = s->d.prec == FX_PREC_MIXED ? upload_level(p.lv[l], s->D32.lv[l]) : upload_level(p.lv[l], s->D64.lv[l]);
-        if (st) { delete s; return st; }
-    }
-    st = s->d.prec == FX_PREC_MIXED ? upload_coarse(s, s->D32) : upload_coarse(s, s->D64);
-    if (st) { delete s; return st; }
-    if (hipHostMalloc((void **)&s->ctrl_host, sizeof(SolveCtrl), 0) != hipSuccess) {
+    plan_launches(e);
+    e->mode = env_mode(FX_LAUNCH_STREAM);
+    st = engine_init(e, &d_P, &d_phi, d_ws, ws_bytes, stream);
+    if (st == FX_ENOMEM || st == FX_EINVAL || (st == FX_EDEVICE && !e->mir)) {
+        engine_release(e);
         delete s;
-        return fail(FX_EDEVICE, "hipHostMalloc failed");
+        return st;
     }
-    // P: zero off the ferroelectric in both buffers
-    const size_t nfull = (size_t)p.nx * p.ny * p.nz, nxy = (size_t)p.nx * p.ny;
-    launch_fill(s->P[1], nfull, 0.0, s->st);
-    if (p.f0 >= 0) {
-        if (p.f0 > 0) launch_fill(s->P[0], (size_t)p.f0 * nxy, 0.0, s->st);
-        if (p.f1 < p.nz) launch_fill(s->P[0] + (size_t)p.f1 * nxy, (size_t)(p.nz - p.f1) * nxy, 0.0, s->st);
-    } else {
-        launch_fill(s->P[0], nfull, 0.0, s->st);
-    }
-    // Step 0: phi^{0,(0)} = 0, then solve
-    for (int b = 0; b < fx_stack::kPhiBufs; ++b) launch_fill(s->phi[b], nfull, 0.0, s->st);
-    set_contacts(s);
     *out = s;
-    st = solve(s, nullptr);
-    fx_status st2 = sync_to_caller(s);
-    return st ? st : st2;
+    if (st) return st;
+    fx_status st2 = sync_to_caller(e);
+    if (!st2) st2 = status_message(e->mir[0], -1);
+    return st2;
 }
 
 fx_status tdgl_step(fx_stack *s, double dt) {
     g_err.clear();
     if (!s) return fail(FX_EINVAL, "stack is NULL");
     if (!(dt > 0)) return fail(FX_EINVAL, "dt must be > 0");
-    tdgl_impl(s, dt);
-    s->hist = 0;
-    return sync_to_caller(s);
+    Engine *e = &s->e;
+    e->mir[0].dt = dt;
+    put_state(e, 0);
+    if (e->prec == FX_PREC_MIXED) {
+        launch_tdgl(idev<float>(e), e->w_tdgl, 0, e->st);
+        launch_flip(idev<float>(e), 1, e->st);
+    } else {
+        launch_tdgl(idev<double>(e), e->w_tdgl, 0, e->st);
+        launch_flip(idev<double>(e), 1, e->st);
+    }
+    e->mir[0].pcur ^= 1;
+    e->mir[0].hist = 0;
+    return sync_to_caller(e);
 }
 
 fx_status poisson_solve(fx_stack *s, double v_top, fx_solve_info *info) {
     g_err.clear();
     if (!s) return fail(FX_EINVAL, "stack is NULL");
     if (!std::isfinite(v_top)) return fail(FX_EINVAL, "v_top must be finite");
-    s->d.v_top = v_top;
-    set_contacts(s);
-    fx_status st = solve(s, info);
-    std::string msg = g_err;
-    fx_status st2 = sync_to_caller(s);
-    g_err = msg;
-    return st ? st : st2;
+    Engine *e = &s->e;
+    e->mir[0].v_top = v_top;
+    put_state(e, 0);
+    fx_status st = solve_plain(e);
+    if (st) return st;
+    const InstState c = e->mir[0];
+    if (info) {
+        info->cycles = c.cycles;
+        info->status = c.status;
+        info->res_norm = c.status == FX_OK && c.zero_fix ? 0.0 : std::sqrt(c.rn2);
+        info->rhs_norm = std::sqrt(c.fn2);
+    }
+    st = sync_to_caller(e);
+    if (st) return st;
+    return status_message(c, -1);
 }
 
 fx_status run_steps(fx_stack *s, int nsteps, double dt, const double *h_v_top_sched, fx_run_info *info) {
     g_err.clear();
     if (!s) return fail(FX_EINVAL, "stack is NULL");
     if (nsteps < 0 || !(dt > 0)) return fail(FX_EINVAL, "nsteps >= 0 and dt > 0 required");
+    Engine *e = &s->e;
+    const InstState before = e->mir[0];
+    fx_status st = run(e, nsteps, dt, h_v_top_sched ? &h_v_top_sched : nullptr);
+    if (st) return st;
+    const InstState c = e->mir[0];
     fx_run_info ri{};
-    fx_status st = FX_OK;
-    for (int n = 0; n < nsteps; ++n) {
-        tdgl_impl(s, dt);
-        if (h_v_top_sched) { s->d.v_top = h_v_top_sched[n]; set_contacts(s); }
-        fx_solve_info si{};
-        st = solve(s, &si, true);
-        ri.total_cycles += si.cycles;
-        if (si.cycles > ri.max_cycles_step) ri.max_cycles_step = si.cycles;
-        ri.last_res_rel = si.rhs_norm > 0 ? si.res_norm / si.rhs_norm : 0.0;
-        if (st) break;
-        ri.steps_done = n + 1;
+    if (nsteps > 0) {
+        ri.steps_done = c.step - before.step;
+        ri.total_cycles = c.total_cycles - before.total_cycles;
+        ri.max_cycles_step = c.max_cycles_step;
+        ri.last_res_rel = c.fn2 > 0 && !(c.status == FX_OK && c.zero_fix) ? std::sqrt(c.rn2 / c.fn2) : 0.0;
     }
-    std::string msg = g_err;
-    fx_status st2 = sync_to_caller(s);
-    g_err = msg;
     if (info) *info = ri;
-    return st ? st : st2;
+    st = sync_to_caller(e);
+    if (st) return st;
+    return nsteps > 0 ? status_message(c, -1) : FX_OK;
 }
 
 fx_status get_field(fx_stack *s, int which, double *h_out) {
     g_err.clear();
     if (!s || !h_out) return fail(FX_EINVAL, "NULL argument");
-    if (which < FX_FIELD_P || which > FX_FIELD_PHI_PREV3) return fail(FX_EINVAL, "unknown field %d", which);
-    fx_status st = sync_to_caller(s);
-    if (st) return st;
-    const Plan &p = s->plan;
-    const size_t nxy = (size_t)p.nx * p.ny, n = nxy * p.nz;
-    if (which >= FX_FIELD_PHI_PREV) {
-        const int m = which - FX_FIELD_PHI_PREV;
-        if (m >= s->hist) return fail(FX_ESTATE, "time level n-%d is not held", m + 1);
-        // device planes from the history buffer, contacts from the caller's array
-        HIP_OK(hipMemcpyAsync(h_out, s->phi[0], n * sizeof(double), hipMemcpyDeviceToHost, s->st));
-        HIP_OK(hipMemcpyAsync(h_out + p.kb * nxy, s->phi[s->prev[m]] + p.kb * nxy, (size_t)p.nzd * nxy * sizeof(double),
-                              hipMemcpyDeviceToHost, s->st));
-    } else {
-        HIP_OK(hipMemcpyAsync(h_out, which == FX_FIELD_P ? s->P[0] : s->phi[0], n * sizeof(double),
-                              hipMemcpyDeviceToHost, s->st));
-    }
-    HIP_OK(hipStreamSynchronize(s->st));
-    return FX_OK;
+    return get_field_impl(&s->e, 0, which, h_out);
 }
 
 fx_status set_field(fx_stack *s, int which, const double *h_in) {
     g_err.clear();
     if (!s || !h_in) return fail(FX_EINVAL, "NULL argument");
-    if (which < FX_FIELD_P || which > FX_FIELD_PHI_PREV3) return fail(FX_EINVAL, "unknown field %d", which);
-    fx_status st = sync_to_caller(s);
-    if (st) return st;
-    const Plan &p = s->plan;
-    const size_t nxy = (size_t)p.nx * p.ny, n = nxy * p.nz;
-    if (which >= FX_FIELD_PHI_PREV) {
-        const int m = which - FX_FIELD_PHI_PREV;
-        if (m != s->hist) return fail(FX_ESTATE, "set time level n-%d after n-1 .. n-%d", m + 1, m);
-        int b = 1;                      // phicur is 0 after sync_to_caller
-        while (holds_history(s, b)) ++b;
-        HIP_OK(hipMemcpyAsync(s->phi[b] + p.kb * nxy, h_in + p.kb * nxy, (size_t)p.nzd * nxy * sizeof(double),
-                              hipMemcpyHostToDevice, s->st));
-        HIP_OK(hipStreamSynchronize(s->st));
-        s->prev[m] = b;
-        s->hist = m + 1;
-        return FX_OK;
-    }
-    s->hist = 0;
-    if (which == FX_FIELD_P) {
-        HIP_OK(hipMemcpyAsync(s->P[0], h_in, n * sizeof(double), hipMemcpyHostToDevice, s->st));
-        HIP_OK(hipStreamSynchronize(s->st));
-        if (p.f0 >= 0) {
-            if (p.f0 > 0) launch_fill(s->P[0], (size_t)p.f0 * nxy, 0.0, s->st);
-            if (p.f1 < p.nz) launch_fill(s->P[0] + (size_t)p.f1 * nxy, (size_t)(p.nz - p.f1) * nxy, 0.0, s->st);
-        } else {
-            launch_fill(s->P[0], n, 0.0, s->st);
-        }
-    } else {
-        HIP_OK(hipMemcpyAsync(s->phi[0], h_in, n * sizeof(double), hipMemcpyHostToDevice, s->st));
-        HIP_OK(hipStreamSynchronize(s->st));
-        set_contacts(s);
-    }
+    return set_field_impl(&s->e, 0, which, h_in);
+}
+
+fx_status stack_set_launch(fx_stack *s, int mode) {
+    g_err.clear();
+    if (!s) return fail(FX_EINVAL, "stack is NULL");
+    if (mode != FX_LAUNCH_STREAM && mode != FX_LAUNCH_GRAPH) return fail(FX_EINVAL, "unknown launch mode %d", mode);
+    s->e.mode = mode;
     return FX_OK;
 }
 
-fx_status stack_probe(fx_stack *s, int kernel, int max_launches) {
+fx_status stack_probe(fx_stack *s, int kernel, int max_launches, int stride) {
     g_err.clear();
     if (!s) return fail(FX_EINVAL, "stack is NULL");
-    if (kernel != FX_PROBE_OFF && kernel != FX_PROBE_SMOOTH_FINE) return fail(FX_EINVAL, "unknown probe %d", kernel);
-    if (kernel == FX_PROBE_OFF) { s->probe = 0; return FX_OK; }
-    if (max_launches < 1) return fail(FX_EINVAL, "max_launches must be >= 1");
-    HIP_OK(hipStreamSynchronize(s->st));
-    while ((int)s->ev.size() < 2 * max_launches) {
-        hipEvent_t e;
-        HIP_OK(hipEventCreate(&e));
-        s->ev.push_back(e);
-    }
-    s->probe = kernel;
-    s->ev_used = 0;
-    s->probe_bytes = 0.0;
-    return FX_OK;
+    return probe_on(&s->e, kernel, max_launches, stride);
 }
 
 fx_status stack_probe_read(fx_stack *s, double *total_ms, int *launches, double *bytes) {
     g_err.clear();
     if (!s) return fail(FX_EINVAL, "stack is NULL");
-    HIP_OK(hipStreamSynchronize(s->st));
-    double tot = 0.0;
-    for (int q = 0; q + 1 < s->ev_used; q += 2) {
-        float ms = 0.0f;
-        HIP_OK(hipEventElapsedTime(&ms, s->ev[q], s->ev[q + 1]));
-        tot += ms;
-    }
-    if (total_ms) *total_ms = tot;
-    if (launches) *launches = s->ev_used / 2;
-    if (bytes) *bytes = s->probe_bytes;
-    return FX_OK;
+    return probe_read(&s->e, total_ms, launches, bytes);
 }
 
-int stack_num_levels(const fx_stack *s) { return s ? (int)s->plan.lv.size() : 0; }
+int stack_num_levels(const fx_stack *s) { return s ? (int)s->e.in[0].plan.lv.size() : 0; }
 
 fx_status stack_level_shape(const fx_stack *s, int level, int *nx, int *ny, int *nz) {
-    if (!s || level < 0 || level >= (int)s->plan.lv.size()) return fail(FX_EINVAL, "bad level");
-    const HostLevel &H = s->plan.lv[level];
+    if (!s || level < 0 || level >= (int)s->e.in[0].plan.lv.size()) return fail(FX_EINVAL, "bad level");
+    const HostLevel &H = s->e.in[0].plan.lv[level];
     if (nx) *nx = H.nx;
     if (ny) *ny = H.ny;
     if (nz) *nz = H.nz;
@@ -926,10 +1255,104 @@ fx_status stack_level_shape(const fx_stack *s, int level, int *nx, int *ny, int 
 
 fx_status destroy_stack(fx_stack *s) {
     if (!s) return FX_OK;
-    if (s->st) (void)hipStreamSynchronize(s->st); else (void)hipDeviceSynchronize();
-    if (s->ctrl_host) (void)hipHostFree(s->ctrl_host);
-    for (hipEvent_t e : s->ev) (void)hipEventDestroy(e);
+    engine_release(&s->e);
     delete s;
+    return FX_OK;
+}
+
+// ------------------------------------------------------------------ batches
+size_t batch_workspace_bytes(const fx_stack_desc *descs, int n) {
+    g_err.clear();
+    Engine tmp;
+    if (validate_all(descs, n, &tmp)) return 0;
+    plan_launches(&tmp);
+    return carve(&tmp, nullptr);
+}
+
+fx_status init_batch(const fx_stack_desc *descs, int n, double *const *d_P, double *const *d_phi, void *d_ws,
+                     size_t ws_bytes, void *stream, fx_batch **out) {
+    g_err.clear();
+    if (!out) return fail(FX_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!d_P || !d_phi || !d_ws) return fail(FX_EINVAL, "pointers must not be NULL");
+    if (((uintptr_t)d_ws & 255) != 0) return fail(FX_EINVAL, "workspace must be 256-byte aligned");
+    if (n >= 1 && n <= kMaxBatch)
+        for (int i = 0; i < n; ++i) {
+            if (!d_P[i] || !d_phi[i]) return fail(FX_EINVAL, "instance %d: device pointers must not be NULL", i);
+            if (((uintptr_t)d_P[i] & 15) != 0 || ((uintptr_t)d_phi[i] & 15) != 0)
+                return fail(FX_EINVAL, "instance %d: P and phi must be 16-byte aligned", i);
+        }
+    fx_batch *b = new (std::nothrow) fx_batch();
+    if (!b) return fail(FX_ENOMEM, "host allocation failed");
+    Engine *e = &b->e;
+    fx_status st = validate_all(descs, n, e);
+    if (st) { delete b; return st; }
+    plan_launches(e);
+    e->mode = env_mode(FX_LAUNCH_GRAPH);
+    st = engine_init(e, d_P, d_phi, d_ws, ws_bytes, stream);
+    if (st == FX_ENOMEM || st == FX_EINVAL || (st == FX_EDEVICE && !e->mir)) {
+        engine_release(e);
+        delete b;
+        return st;
+    }
+    *out = b;
+    if (st) return st;
+    st = sync_to_caller(e);
+    if (st) return st;
+    for (int i = 0; i < n; ++i)
+        if (e->mir[i].status != FX_OK) return status_message(e->mir[i], i);
+    return FX_OK;
+}
+
+fx_status run_batch(fx_batch *b, int nsteps, double dt, const double *const *h_v_top_sched, fx_batch_info *info) {
+    g_err.clear();
+    if (!b) return fail(FX_EINVAL, "batch is NULL");
+    if (nsteps < 0 || !(dt > 0)) return fail(FX_EINVAL, "nsteps >= 0 and dt > 0 required");
+    Engine *e = &b->e;
+    if (h_v_top_sched)
+        for (int i = 0; i < e->n; ++i)
+            if (!h_v_top_sched[i]) return fail(FX_EINVAL, "instance %d: schedule is NULL", i);
+    std::vector<InstState> before(e->mir, e->mir + e->n);
+    fx_status st = run(e, nsteps, dt, h_v_top_sched);
+    if (st) return st;
+    if (info)
+        for (int i = 0; i < e->n; ++i) {
+            const InstState &c = e->mir[i];
+            fx_batch_info &r = info[i];
+            r.status = nsteps > 0 ? c.status : FX_OK;
+            r.steps_done = c.step - before[i].step;
+            r.total_cycles = c.total_cycles - before[i].total_cycles;
+            r.max_cycles_step = nsteps > 0 ? c.max_cycles_step : 0;
+            r.last_res_rel = nsteps > 0 && c.fn2 > 0 && !(c.status == FX_OK && c.zero_fix) ? std::sqrt(c.rn2 / c.fn2) : 0.0;
+        }
+    std::vector<InstState> after(e->mir, e->mir + e->n);
+    st = sync_to_caller(e);
+    if (st) return st;
+    if (nsteps > 0)
+        for (int i = 0; i < e->n; ++i)
+            if (after[i].status != FX_OK) return status_message(after[i], i);
+    return FX_OK;
+}
+
+fx_status batch_get_field(fx_batch *b, int inst, int which, double *h_out) {
+    g_err.clear();
+    if (!b || !h_out) return fail(FX_EINVAL, "NULL argument");
+    if (inst < 0 || inst >= b->e.n) return fail(FX_EINVAL, "instance %d outside 0..%d", inst, b->e.n - 1);
+    return get_field_impl(&b->e, inst, which, h_out);
+}
+
+fx_status batch_set_launch(fx_batch *b, int mode) {
+    g_err.clear();
+    if (!b) return fail(FX_EINVAL, "batch is NULL");
+    if (mode != FX_LAUNCH_STREAM && mode != FX_LAUNCH_GRAPH) return fail(FX_EINVAL, "unknown launch mode %d", mode);
+    b->e.mode = mode;
+    return FX_OK;
+}
+
+fx_status destroy_batch(fx_batch *b) {
+    if (!b) return FX_OK;
+    engine_release(&b->e);
+    delete b;
     return FX_OK;
 }
 

@@ -21,6 +21,7 @@ LIB_PATH = os.path.join(_HERE, "libferrox.so")
 FX_OK, FX_EINVAL, FX_ENOMEM, FX_EDEVICE, FX_ENOCONV, FX_ENONFINITE, FX_ESTATE = range(7)
 FIELD_P, FIELD_PHI, FIELD_PHI_PREV, FIELD_PHI_PREV2, FIELD_PHI_PREV3 = 0, 1, 2, 3, 4
 PROBE_OFF, PROBE_SMOOTH_FINE = 0, 1
+LAUNCH_STREAM, LAUNCH_GRAPH = 0, 1
 _STATUS = {0: "FX_OK", 1: "FX_EINVAL", 2: "FX_ENOMEM", 3: "FX_EDEVICE", 4: "FX_ENOCONV",
            5: "FX_ENONFINITE", 6: "FX_ESTATE"}
 
@@ -57,6 +58,11 @@ class RunInfo(ctypes.Structure):
                 ("max_cycles_step", ctypes.c_int), ("last_res_rel", ctypes.c_double)]
 
 
+class BatchInfo(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int), ("steps_done", ctypes.c_int), ("total_cycles", ctypes.c_int),
+                ("max_cycles_step", ctypes.c_int), ("last_res_rel", ctypes.c_double)]
+
+
 # (name, restype, argtypes) of every entry point declared in include/ferrox.h
 _vp, _dp, _ip = ctypes.c_void_p, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int)
 _D = ctypes.POINTER(StackDesc)
@@ -68,11 +74,20 @@ SIGNATURES = [
     ("run_steps", ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_double, _dp, ctypes.POINTER(RunInfo)]),
     ("get_field", ctypes.c_int, [_vp, ctypes.c_int, _dp]),
     ("set_field", ctypes.c_int, [_vp, ctypes.c_int, _dp]),
-    ("stack_probe", ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int]),
+    ("stack_probe", ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int, ctypes.c_int]),
     ("stack_probe_read", ctypes.c_int, [_vp, _dp, _ip, _dp]),
     ("stack_num_levels", ctypes.c_int, [_vp]),
     ("stack_level_shape", ctypes.c_int, [_vp, ctypes.c_int, _ip, _ip, _ip]),
     ("destroy_stack", ctypes.c_int, [_vp]),
+    ("stack_set_launch", ctypes.c_int, [_vp, ctypes.c_int]),
+    ("batch_workspace_bytes", ctypes.c_size_t, [_D, ctypes.c_int]),
+    ("init_batch", ctypes.c_int, [_D, ctypes.c_int, ctypes.POINTER(_vp), ctypes.POINTER(_vp), _vp,
+                                  ctypes.c_size_t, _vp, ctypes.POINTER(_vp)]),
+    ("run_batch", ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_double, ctypes.POINTER(_dp),
+                                 ctypes.POINTER(BatchInfo)]),
+    ("batch_get_field", ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int, _dp]),
+    ("batch_set_launch", ctypes.c_int, [_vp, ctypes.c_int]),
+    ("destroy_batch", ctypes.c_int, [_vp]),
     ("last_error", ctypes.c_char_p, []),
 ]
 
@@ -188,9 +203,13 @@ class Stack:
         a = np.ascontiguousarray(arr, np.float64)
         _check(lib().set_field(self._h, which, a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
 
-    def probe(self, kernel: int = PROBE_SMOOTH_FINE, max_launches: int = 4096):
-        """Start timestamping the finest-level smoother launches (see include/ferrox.h)."""
-        _check(lib().stack_probe(self._h, kernel, max_launches))
+    def set_launch(self, mode: int):
+        """LAUNCH_STREAM or LAUNCH_GRAPH for run_steps (see include/ferrox.h)."""
+        _check(lib().stack_set_launch(self._h, mode))
+
+    def probe(self, kernel: int = PROBE_SMOOTH_FINE, max_launches: int = 4096, stride: int = 1):
+        """Start timestamping every stride-th finest-level smoother launch (see include/ferrox.h)."""
+        _check(lib().stack_probe(self._h, kernel, max_launches, stride))
 
     def probe_read(self):
         """(total ms, launches, algorithmic bytes) of the probed launches."""
@@ -209,6 +228,86 @@ class Stack:
     def close(self):
         if getattr(self, "_h", None) is not None and self._h.value:
             lib().destroy_stack(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def batch_workspace_bytes(specs: Sequence[W.StackSpec]) -> int:
+    hs = [_DescHolder(sp) for sp in specs]
+    arr = (StackDesc * len(hs))(*[h.d for h in hs])
+    return int(lib().batch_workspace_bytes(arr, len(hs)))
+
+
+class Batch:
+    """Independent stacks of different sizes advanced together (one launch per
+    kernel for all of them).  ``P[i]`` and ``phi[i]`` are the instances'
+    float64 tensors of shape (nz, ny, nx), holding the current state after
+    every call.  Construction runs Step 0 for every instance."""
+
+    def __init__(self, specs: Sequence[W.StackSpec], P0s, device: str = "cuda:0", stream=None,
+                 check_init: bool = True):
+        import torch
+        self.specs = list(specs)
+        self.n = len(self.specs)
+        self.device = torch.device(device)
+        self.P, self.phi = [], []
+        for sp, P0 in zip(self.specs, P0s):
+            shape = (sp.nz, sp.ny, sp.nx)
+            if isinstance(P0, np.ndarray):
+                P = torch.from_numpy(np.ascontiguousarray(P0, np.float64)).to(self.device)
+            else:
+                P = P0.to(device=self.device, dtype=torch.float64).contiguous()
+            assert tuple(P.shape) == shape, (P.shape, shape)
+            self.P.append(P)
+            self.phi.append(torch.zeros(shape, dtype=torch.float64, device=self.device))
+        self._hs = [_DescHolder(sp) for sp in self.specs]
+        self._descs = (StackDesc * self.n)(*[h.d for h in self._hs])
+        nbytes = int(lib().batch_workspace_bytes(self._descs, self.n))
+        if nbytes == 0:
+            raise FerroxError(FX_EINVAL, lib().last_error().decode())
+        self.ws = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        pP = (_vp * self.n)(*[t.data_ptr() for t in self.P])
+        pphi = (_vp * self.n)(*[t.data_ptr() for t in self.phi])
+        self._h = ctypes.c_void_p()
+        st = lib().init_batch(self._descs, self.n, pP, pphi, self.ws.data_ptr(), nbytes,
+                              self.stream.cuda_stream, ctypes.byref(self._h))
+        if not self._h.value:
+            _check(st)
+        self.init_status = st
+        if check_init:
+            _check(st)
+
+    def run(self, nsteps: int, dt: float, v_scheds=None, check: bool = True):
+        """nsteps time steps of every instance; returns a list of BatchInfo."""
+        info = (BatchInfo * self.n)()
+        vs = None
+        if v_scheds is not None:
+            self._vs = [np.ascontiguousarray(v, np.float64) for v in v_scheds]
+            assert len(self._vs) == self.n and all(len(v) >= nsteps for v in self._vs)
+            vs = (_dp * self.n)(*[v.ctypes.data_as(_dp) for v in self._vs])
+        st = lib().run_batch(self._h, nsteps, dt, vs, info)
+        if check:
+            _check(st)
+        return list(info)
+
+    def get(self, inst: int, which: int) -> np.ndarray:
+        sp = self.specs[inst]
+        out = np.empty((sp.nz, sp.ny, sp.nx), np.float64)
+        _check(lib().batch_get_field(self._h, inst, which, out.ctypes.data_as(_dp)))
+        return out
+
+    def set_launch(self, mode: int):
+        _check(lib().batch_set_launch(self._h, mode))
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib().destroy_batch(self._h)
             self._h = ctypes.c_void_p()
 
     def __del__(self):

@@ -28,7 +28,7 @@ from collections import defaultdict
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 KERNEL_SRC = os.path.join(ROOT, "paper_2210_15668_amd", "csrc", "fx_kernels.hip")
 COPY_BYTES = 1 << 30
-DOMINANT = "k_smooth_rb<double"        # finest-level smoother launches have the largest grid
+DOMINANT = "k_smooth<double"           # finest-level smoother launches have the largest grid
 
 
 def _db(d):
