@@ -59,9 +59,10 @@ def run_gpu(prec_name, steps, warmup):
     if warmup:
         s.run_steps(warmup, W.DT)
     torch.cuda.synchronize()
-    # every 8th finest-level smoother launch of the timed region is timed by its own
-    # dispatch events (timing every launch would slow the region by a few per cent)
-    s.probe(ferrox.PROBE_SMOOTH_FINE, max_launches=min(4096, max(64, steps * 2)), stride=8)
+    # every 7th finest-level smoother launch of the timed region is timed by its own
+    # dispatch events (timing every launch would slow the region by a few per cent);
+    # 7 is prime to the 8 such launches of a V-cycle, so all variants are sampled
+    s.probe(ferrox.PROBE_SMOOTH_FINE, max_launches=min(4096, max(64, steps * 2)), stride=7)
     t0 = time.perf_counter()
     info = s.run_steps(steps, W.DT)
     torch.cuda.synchronize()
@@ -79,6 +80,31 @@ def run_gpu(prec_name, steps, warmup):
     out["phi"] = s.phi.detach().cpu().numpy()
     s.close()
     return out
+
+
+def run_batch64(prec_name, steps, warmup):
+    """The 64 uneven MFIM instances advanced together (one launch per kernel for all of
+    them, graph replay): time steps of the whole batch per second."""
+    import torch
+    from paper_2210_15668_amd import ferrox
+    from paper_2210_15668_amd import workloads as W
+    prec = W.PREC_FP64 if prec_name == "fp64" else W.PREC_MIXED
+    inst = W.batch_instances(64)
+    specs = [sp.copy(prec=prec) for sp, _ in inst]
+    b = ferrox.Batch(specs, [P for _, P in inst], device="cuda:0")      # Step 0, untimed
+    b.set_launch(ferrox.LAUNCH_GRAPH)
+    if warmup:
+        b.run(warmup, W.DT)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    info = b.run(steps, W.DT)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    b.close()
+    cells = sum(sp.ncell for sp in specs)
+    return {"batch_steps_per_s": steps / dt, "instance_steps_per_s": 64 * steps / dt,
+            "cells_total": cells, "vcycles_per_step_mean": sum(i.total_cycles for i in info) / (64.0 * steps),
+            "vcycles_per_step_max": max(i.max_cycles_step for i in info)}
 
 
 def cpu_baseline(sample_steps):
@@ -109,6 +135,8 @@ def main():
     ap.add_argument("--cpu-sample-steps", type=int, default=16)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
+    ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--batch-steps", type=int, default=100)
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -132,9 +160,17 @@ def main():
     traffic = measured_traffic("fp64")
     roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                "kernel": "k_smooth_rb (finest-level red/black Gauss-Seidel half-sweep, FP64)",
+                "kernel": "k_smooth<double,*,4,*> (finest-level red/black Gauss-Seidel half-sweep, FP64, all variants)",
                 "avg_launch_us": avg_us, "algorithmic_bytes_per_launch": per_launch,
                 "launches_timed": r64["probe_launches"]}
+    batch = None
+    if not args.no_batch:
+        b64 = run_batch64("fp64", args.batch_steps, 5)
+        bmx = run_batch64("mixed", args.batch_steps, 5)
+        batch = {"workload": "64 uneven MFIM instances: x, y in {32, 48, 64, 96}, z in {32, 48}, FE 16..32 / DE 4, "
+                             "gates uniform in [-2, 2] V (seeds 100..163)",
+                 "launch": "one launch per kernel for all instances, graph replay", "steps": args.batch_steps,
+                 "fp64": b64, "mixed": bmx}
     cpu = None if args.no_cpu_baseline else cpu_baseline(args.cpu_sample_steps)
     line = {
         "metric": "TDGL+Poisson steps/s at 1e-10 residual, 256\u00b2\u00d7128 MFISM; plain MG vs learned",
@@ -147,6 +183,7 @@ def main():
                    "vcycles_per_step": r64["vcycles_per_step"],
                    "last_rel_residual": r64["last_rel_residual"]},
         "mixed_precision": mixed,
+        "batch64": batch,
         "roofline": roofline,
         "cpu_baseline": cpu,
         "paper_context": "paper: ~15x node-by-node GPU vs multicore (4x A100 vs 32 Haswell cores, NERSC); "
