@@ -48,7 +48,7 @@ def measured_traffic(prec):
     return float(v) if v is not None else None
 
 
-def run_gpu(prec_name, steps, warmup):
+def run_gpu(prec_name, steps, warmup, tune=True):
     import torch
     from paper_2210_15668_amd import ferrox
     from paper_2210_15668_amd import workloads as W
@@ -56,6 +56,13 @@ def run_gpu(prec_name, steps, warmup):
     spec = W.mfism_large(prec)
     P0 = W.random_P(spec, 2)
     s = ferrox.Stack(spec, P0, device="cuda:0")          # Step 0, untimed
+    tuned = None
+    if tune:                                             # launch-shape search, untimed
+        ti = s.autotune()
+        tuned = {"levels": ti.levels, "configs_timed": ti.configs_timed,
+                 "half_sweep_us_default": ti.default_us, "half_sweep_us_tuned": ti.tuned_us,
+                 "shapes": [dict(zip(("tile_x", "planes_per_thread", "waves8"), s.tune_config(l)))
+                            for l in range(ti.levels)]}
     if warmup:
         s.run_steps(warmup, W.DT)
     torch.cuda.synchronize()
@@ -75,14 +82,14 @@ def run_gpu(prec_name, steps, warmup):
         "ms_per_step": 1e3 * elapsed / steps,
         "vcycles_per_step": info.total_cycles / max(1, steps),
         "last_rel_residual": info.last_res_rel,
-        "probe_ms": ms, "probe_launches": launches, "probe_bytes": nbytes,
+        "probe_ms": ms, "probe_launches": launches, "probe_bytes": nbytes, "autotune": tuned,
     }
     out["phi"] = s.phi.detach().cpu().numpy()
     s.close()
     return out
 
 
-def run_batch64(prec_name, steps, warmup):
+def run_batch64(prec_name, steps, warmup, tune=True):
     """The 64 uneven MFIM instances advanced together (one launch per kernel for all of
     them, graph replay): time steps of the whole batch per second."""
     import torch
@@ -93,6 +100,7 @@ def run_batch64(prec_name, steps, warmup):
     specs = [sp.copy(prec=prec) for sp, _ in inst]
     b = ferrox.Batch(specs, [P for _, P in inst], device="cuda:0")      # Step 0, untimed
     b.set_launch(ferrox.LAUNCH_GRAPH)
+    ti = b.autotune() if tune else None
     if warmup:
         b.run(warmup, W.DT)
     torch.cuda.synchronize()
@@ -104,7 +112,8 @@ def run_batch64(prec_name, steps, warmup):
     cells = sum(sp.ncell for sp in specs)
     return {"batch_steps_per_s": steps / dt, "instance_steps_per_s": 64 * steps / dt,
             "cells_total": cells, "vcycles_per_step_mean": sum(i.total_cycles for i in info) / (64.0 * steps),
-            "vcycles_per_step_max": max(i.max_cycles_step for i in info)}
+            "vcycles_per_step_max": max(i.max_cycles_step for i in info),
+            "autotune_half_sweep_us": None if ti is None else [ti.default_us, ti.tuned_us]}
 
 
 def cpu_baseline(sample_steps):
@@ -136,6 +145,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--no-tune", action="store_true", help="keep the default smoother launch shapes")
     ap.add_argument("--batch-steps", type=int, default=100)
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -145,10 +155,10 @@ def main():
     import numpy as np
     import oracle  # noqa: F401  (only for the cpu_baseline leg)
 
-    r64 = run_gpu("fp64", args.steps, args.warmup)
+    r64 = run_gpu("fp64", args.steps, args.warmup, not args.no_tune)
     mixed = None
     if not args.no_mixed:
-        rmx = run_gpu("mixed", args.steps, args.warmup)
+        rmx = run_gpu("mixed", args.steps, args.warmup, not args.no_tune)
         diff = float(np.linalg.norm(rmx["phi"] - r64["phi"]) / np.linalg.norm(r64["phi"]))
         mixed = {"value": rmx["steps_per_s"], "ms_per_step": rmx["ms_per_step"],
                  "vcycles_per_step": rmx["vcycles_per_step"], "dtype": "f32 multigrid in f64 defect correction",
@@ -165,8 +175,8 @@ def main():
                 "launches_timed": r64["probe_launches"]}
     batch = None
     if not args.no_batch:
-        b64 = run_batch64("fp64", args.batch_steps, 5)
-        bmx = run_batch64("mixed", args.batch_steps, 5)
+        b64 = run_batch64("fp64", args.batch_steps, 5, not args.no_tune)
+        bmx = run_batch64("mixed", args.batch_steps, 5, not args.no_tune)
         batch = {"workload": "64 uneven MFIM instances: x, y in {32, 48, 64, 96}, z in {32, 48}, FE 16..32 / DE 4, "
                              "gates uniform in [-2, 2] V (seeds 100..163)",
                  "launch": "one launch per kernel for all instances, graph replay", "steps": args.batch_steps,
@@ -181,6 +191,7 @@ def main():
                                "Boltzmann carriers, dt 1e-13 s, 1 V gate, ||r||/||f|| <= 1e-10",
                    "solver": "Newton-multigrid V(2,2), extrapolated warm start",
                    "vcycles_per_step": r64["vcycles_per_step"],
+                   "autotune": r64["autotune"],
                    "last_rel_residual": r64["last_rel_residual"]},
         "mixed_precision": mixed,
         "batch64": batch,

@@ -211,6 +211,31 @@ fx_status stack_probe_read(fx_stack *s, double *total_ms, int *launches, double 
 enum { FX_LAUNCH_STREAM = 0, FX_LAUNCH_GRAPH = 1 };
 fx_status stack_set_launch(fx_stack *s, int mode);
 
+/* Autotuner.  For every multigrid level with its own smoother launches,
+ * times the candidate launch shapes of the Gauss-Seidel half-sweep on the
+ * stack's own level arrays -- tiles of 32x8, 64x4 or 128x2 threads, 1, 2, 4
+ * or 8 planes per thread (z-march length), and the compiler's register
+ * budget or one that keeps 8 waves per SIMD resident -- and keeps the
+ * fastest.  Only the division of the work changes, so results are bitwise
+ * identical with any choice.  cache_path (NULL: none) names a text file of
+ * earlier choices keyed by GPU architecture, precision and the shapes of the
+ * level's instances: a level found there is not timed again unless
+ * FX_TUNE_FORCE is set; new choices are appended.  Synchronises the stream;
+ * call between runs (not while a probe is on).  info may be NULL. */
+typedef struct {
+    int levels;                  /* levels with their own smoother launches                  */
+    int from_cache;              /* of those, shapes taken from the cache file               */
+    int configs_timed;           /* candidate shapes timed                                   */
+    int cache_written;           /* 1 if new lines were appended to the cache file           */
+    double default_us;           /* one half-sweep per searched level, default shapes, summed */
+    double tuned_us;             /* the same with the chosen shapes                           */
+} fx_tune_info;
+enum { FX_TUNE_FORCE = 1 };
+fx_status stack_autotune(fx_stack *s, const char *cache_path, int flags, fx_tune_info *info);
+/* The shape in use at level l: tile width in threads, planes per thread,
+ * 8-wave register budget (0/1). */
+fx_status stack_tune_config(const fx_stack *s, int level, int *tile_x, int *zt, int *waves8);
+
 /* Number of multigrid levels and the sizes of level l (for diagnostics). */
 int stack_num_levels(const fx_stack *s);
 fx_status stack_level_shape(const fx_stack *s, int level, int *nx, int *ny, int *nz);
@@ -253,6 +278,7 @@ fx_status run_batch(fx_batch *b, int nsteps, double dt, const double *const *h_v
  * memory, as get_field. */
 fx_status batch_get_field(fx_batch *b, int inst, int which, double *h_out);
 fx_status batch_set_launch(fx_batch *b, int mode);
+fx_status batch_autotune(fx_batch *b, const char *cache_path, int flags, fx_tune_info *info);
 fx_status destroy_batch(fx_batch *b);
 
 /* Message of the most recent failing call on this thread ("" if none). */

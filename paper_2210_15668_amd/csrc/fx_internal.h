@@ -136,9 +136,15 @@ template <typename T> void launch_extrap(const Inst<T> *I, const Work &w, hipStr
 template <typename T> void launch_residual(const Inst<T> *I, const Work &w, int after_cycle, int any_unfolded,
                                            hipStream_t st);
 template <typename T> void launch_reduce(const Inst<T> *I, int ninst, int count_cycle, hipStream_t st);
+// Launch shape of one level's smoother: tile of 2^lbx x 2^(8-lbx) threads,
+// zt planes per thread, w8: register budget for 8 waves per SIMD.  Only the
+// division of the work changes, never a cell's arithmetic.
+struct SmoothCfg {
+    int lbx, zt, w8;
+};
 template <typename T> void launch_smooth(const Inst<T> *I, const Work &w, int level, int color, int zero_init,
-                                         int upd, int zt, double *probe, hipStream_t st, hipEvent_t ev0 = nullptr,
-                                         hipEvent_t ev1 = nullptr);
+                                         int upd, const SmoothCfg &c, double *probe, hipStream_t st,
+                                         hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
 template <typename T> void launch_restrict(const Inst<T> *I, const Work &w, int level, hipStream_t st);
 template <typename T> void launch_prolong(const Inst<T> *I, const Work &w, int level, hipStream_t st);
 template <typename T> void launch_coarse(const Inst<T> *I, int ninst, int lds_bytes, hipStream_t st);
@@ -149,11 +155,16 @@ template <typename T> void launch_run_setup(const Inst<T> *I, int ninst, int nst
 template <typename T> void launch_set_vtop(const Inst<T> *I, int ninst, double v, hipStream_t st);
 void launch_put_state(InstState *dst, const InstState &v, hipStream_t st);
 void launch_fill(double *x, size_t n, double v, hipStream_t st);
+void launch_zero(void *x, size_t bytes, hipStream_t st);          // bytes: a multiple of 4
 
 // Host-side tile counts (must match the kernels' decoding).
 constexpr int BX = 64;
 constexpr int BY = 4;
 __host__ __device__ inline int tiles3(int nxw, int ny, int nz) { return ((nxw + BX - 1) / BX) * ((ny + BY - 1) / BY) * nz; }
+inline int tiles_cfg(int nxw, int ny, int nz, const SmoothCfg &c) {
+    const int bx = 1 << c.lbx, by = 256 >> c.lbx;
+    return ((nxw + bx - 1) / bx) * ((ny + by - 1) / by) * ((nz + c.zt - 1) / c.zt);
+}
 constexpr int kResZ = 4;            // planes per thread in the fine-level residual
 constexpr int kExtrapChunk = 1024;  // cells per extrapolation tile
 

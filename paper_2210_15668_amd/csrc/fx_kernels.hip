@@ -105,6 +105,18 @@ __device__ __forceinline__ T3 split3(int t, int nxw, int ny) {
     return r;
 }
 
+// Tile of 2^lbx x 2^(8-lbx) threads (a 256-thread block, x fastest); the
+// smoother's tile shape is chosen per level at run time.
+__device__ __forceinline__ T3 split3r(int t, int nxw, int ny, int lbx) {
+    const int ntx = (nxw + (1 << lbx) - 1) >> lbx, nty = (ny + (256 >> lbx) - 1) >> (8 - lbx);
+    T3 r;
+    r.tx = t % ntx;
+    const int q = t / ntx;
+    r.ty = q % nty;
+    r.tz = q / nty;
+    return r;
+}
+
 dim3 grid_of(int total) { return dim3((total + 7) / 8 * 8); }
 
 template <typename V>
@@ -611,16 +623,16 @@ __global__ __launch_bounds__(1024) void k_reduce(const Inst<T> *I, int count_cyc
 // ----------------------------------------------------------------- smoother
 // One colour of red-black Gauss-Seidel on (L + diag sigma) e = r.  Split
 // storage: a thread per cell of that colour, ZT planes per thread with all
-// loads issued first; plainly stored levels: a thread per cell and plane of
-// a 64x4xZT tile.  UPD (finest level, last black half-sweep, instances whose
+// loads issued first; plainly stored levels: a thread per cell and ZT planes
+// of a tile.  UPD (finest level, last black half-sweep, instances whose
 // update is folded in) also writes phi_out = phi_in + clip(e) for each black
 // cell and its red partner (the pair 2m, 2m+1 of a row).
 template <typename T, int ZI, int ZT, int UPD>
-__device__ __forceinline__ void smooth_rb_body(const Inst<T> &a, const Lv<T, 1> &L, int t, int color) {
+__device__ __forceinline__ void smooth_rb_body(const Inst<T> &a, const Lv<T, 1> &L, int t, int color, int lbx) {
     const int hx = L.nx >> 1;
-    const T3 tt = split3(t, hx, L.ny);
-    const int mm = tt.tx * BX + threadIdx.x;
-    const int jj = tt.ty * BY + threadIdx.y;
+    const T3 tt = split3r(t, hx, L.ny, lbx);
+    const int mm = (tt.tx << lbx) + (threadIdx.x & ((1 << lbx) - 1));
+    const int jj = (tt.ty << (8 - lbx)) + (threadIdx.x >> lbx);
     const bool live = mm < hx && jj < L.ny;
     const int m = live ? mm : 0, j = live ? jj : 0;
     const int half = (L.nx * L.ny * L.nz) >> 1;
@@ -700,10 +712,10 @@ __device__ __forceinline__ void smooth_rb_body(const Inst<T> &a, const Lv<T, 1> 
 }
 
 template <typename T, int ZT>
-__device__ __forceinline__ void smooth_nat_body(const Lv<T, 1> &L, int t, int color, int zero_init) {
-    const T3 tt = split3(t, L.nx, L.ny);
-    const int i = tt.tx * BX + threadIdx.x;
-    const int j = tt.ty * BY + threadIdx.y;
+__device__ __forceinline__ void smooth_nat_body(const Lv<T, 1> &L, int t, int color, int zero_init, int lbx) {
+    const T3 tt = split3r(t, L.nx, L.ny, lbx);
+    const int i = (tt.tx << lbx) + (threadIdx.x & ((1 << lbx) - 1));
+    const int j = (tt.ty << (8 - lbx)) + (threadIdx.x >> lbx);
     if (i >= L.nx || j >= L.ny) return;
     for (int z = 0; z < ZT; ++z) {
         const int k = tt.tz * ZT + z;
@@ -721,7 +733,8 @@ __device__ __forceinline__ void smooth_nat_body(const Lv<T, 1> &L, int t, int co
 // colour's r, sigma and e, the other colour's e (not read when zero_init),
 // and the phi pair read and written where the update is folded in.
 template <typename T, int ZI, int ZT, int UPD>
-__global__ __launch_bounds__(256) void k_smooth(const Inst<T> *I, Work w, int level, int color, double *probe) {
+__device__ __forceinline__ void smooth_kernel(const Inst<T> *I, const Work &w, int level, int color, int lbx,
+                                              double *probe) {
     const Blk b = find_block(w);
     if (!b.ok) return;
     const Inst<T> &a = I[b.inst];
@@ -729,19 +742,33 @@ __global__ __launch_bounds__(256) void k_smooth(const Inst<T> *I, Work w, int le
     const Lv<T, 1> L = gview(a.lv[level]);
     if (L.rb) {
         if (color > 1) return;
-        smooth_rb_body<T, ZI, ZT, UPD>(a, L, b.t, color);
+        smooth_rb_body<T, ZI, ZT, UPD>(a, L, b.t, color, lbx);
     } else {
-        smooth_nat_body<T, ZT>(L, b.t, color, ZI);
+        smooth_nat_body<T, ZT>(L, b.t, color, ZI, lbx);
     }
     // after the sweep: an atomic ahead of it would stop the per-plane tables
     // from being read through the scalar cache
-    if (probe && b.t == 0 && threadIdx.x == 0 && threadIdx.y == 0 && (L.rb ? color < 2 : true)) {
+    if (probe && b.t == 0 && threadIdx.x == 0 && (L.rb ? color < 2 : true)) {
         const double n = (double)L.nx * L.ny * L.nz, ns = (double)L.nx * L.ny * (L.sig_hi - L.sig_lo);
         double by = sizeof(T) * (0.5 * n + 0.5 * ns + 0.5 * n);
         if (!ZI) by += sizeof(T) * 0.5 * n;
         if (UPD && a.fold && L.rb) by += 16.0 * n;
         atomicAdd(probe, by);
     }
+}
+
+// Two register budgets: the compiler's own, and one that keeps at least 8
+// waves per SIMD resident (64 VGPRs); the autotuner picks per level.
+template <typename T, int ZI, int ZT, int UPD>
+__global__ __launch_bounds__(256) void k_smooth(const Inst<T> *I, Work w, int level, int color, int lbx,
+                                                double *probe) {
+    smooth_kernel<T, ZI, ZT, UPD>(I, w, level, color, lbx, probe);
+}
+
+template <typename T, int ZI, int ZT, int UPD>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void k_smooth_w8(
+    const Inst<T> *I, Work w, int level, int color, int lbx, double *probe) {
+    smooth_kernel<T, ZI, ZT, UPD>(I, w, level, color, lbx, probe);
 }
 
 template <typename T>
@@ -978,6 +1005,10 @@ __global__ void k_put_state(InstState *dst, InstState v) {
     if (threadIdx.x == 0) *dst = v;
 }
 
+__global__ void k_zero32(unsigned *x, size_t n) {
+    for (size_t c = blockIdx.x * (size_t)blockDim.x + threadIdx.x; c < n; c += (size_t)gridDim.x * blockDim.x) x[c] = 0u;
+}
+
 __global__ void k_fill(double *x, size_t n, double v) {
     for (size_t c = blockIdx.x * (size_t)blockDim.x + threadIdx.x; c < n; c += (size_t)gridDim.x * blockDim.x) x[c] = v;
 }
@@ -1025,23 +1056,37 @@ void launch_reduce(const Inst<T> *I, int ninst, int count_cycle, hipStream_t st)
     hipLaunchKernelGGL(k_reduce<T>, dim3(ninst), dim3(1024), 0, st, I, count_cycle);
 }
 
+template <typename T, int ZT>
+struct SmoothSet {
+    template <typename F>
+    static void pick(int upd, int zero_init, int w8, F go) {
+        if (w8) {
+            if (upd) go(k_smooth_w8<T, 0, ZT, 1>);
+            else if (zero_init) go(k_smooth_w8<T, 1, ZT, 0>);
+            else go(k_smooth_w8<T, 0, ZT, 0>);
+        } else {
+            if (upd) go(k_smooth<T, 0, ZT, 1>);
+            else if (zero_init) go(k_smooth<T, 1, ZT, 0>);
+            else go(k_smooth<T, 0, ZT, 0>);
+        }
+    }
+};
+
 template <typename T>
-void launch_smooth(const Inst<T> *I, const Work &w, int level, int color, int zero_init, int upd, int zt,
+void launch_smooth(const Inst<T> *I, const Work &w, int level, int color, int zero_init, int upd, const SmoothCfg &c,
                    double *probe, hipStream_t st, hipEvent_t ev0, hipEvent_t ev1) {
     if (w.total <= 0) return;
     const dim3 g = grid_of(w.total);
+    const int lbx = c.lbx;
     auto go = [&](auto kern) {
-        if (ev0) hipExtLaunchKernelGGL(kern, g, dim3(BX, BY), 0, st, ev0, ev1, 0, I, w, level, color, probe);
-        else hipLaunchKernelGGL(kern, g, dim3(BX, BY), 0, st, I, w, level, color, probe);
+        if (ev0) hipExtLaunchKernelGGL(kern, g, dim3(256), 0, st, ev0, ev1, 0, I, w, level, color, lbx, probe);
+        else hipLaunchKernelGGL(kern, g, dim3(256), 0, st, I, w, level, color, lbx, probe);
     };
-    if (zt == 4) {
-        if (upd) go(k_smooth<T, 0, 4, 1>);
-        else if (zero_init) go(k_smooth<T, 1, 4, 0>);
-        else go(k_smooth<T, 0, 4, 0>);
-    } else {
-        if (upd) go(k_smooth<T, 0, 1, 1>);
-        else if (zero_init) go(k_smooth<T, 1, 1, 0>);
-        else go(k_smooth<T, 0, 1, 0>);
+    switch (c.zt) {
+        case 8: SmoothSet<T, 8>::pick(upd, zero_init, c.w8, go); break;
+        case 4: SmoothSet<T, 4>::pick(upd, zero_init, c.w8, go); break;
+        case 2: SmoothSet<T, 2>::pick(upd, zero_init, c.w8, go); break;
+        default: SmoothSet<T, 1>::pick(upd, zero_init, c.w8, go); break;
     }
 }
 
@@ -1084,6 +1129,11 @@ void launch_put_state(InstState *dst, const InstState &v, hipStream_t st) {
     hipLaunchKernelGGL(k_put_state, dim3(1), dim3(64), 0, st, dst, v);
 }
 
+void launch_zero(void *x, size_t bytes, hipStream_t st) {
+    const size_t n = bytes / 4, b = (n + 255) / 256;
+    hipLaunchKernelGGL(k_zero32, dim3(b == 0 ? 1 : (b < 4096 ? (unsigned)b : 4096u)), dim3(256), 0, st, (unsigned *)x, n);
+}
+
 void launch_fill(double *x, size_t n, double v, hipStream_t st) {
     const size_t b = (n + 255) / 256;
     hipLaunchKernelGGL(k_fill, dim3(b == 0 ? 1 : (b < 4096 ? (unsigned)b : 4096u)), dim3(256), 0, st, x, n, v);
@@ -1096,8 +1146,8 @@ void launch_fill(double *x, size_t n, double v, hipStream_t st) {
     template void launch_extrap<T>(const Inst<T> *, const Work &, hipStream_t);                              \
     template void launch_residual<T>(const Inst<T> *, const Work &, int, int, hipStream_t);                  \
     template void launch_reduce<T>(const Inst<T> *, int, int, hipStream_t);                                  \
-    template void launch_smooth<T>(const Inst<T> *, const Work &, int, int, int, int, int, double *,         \
-                                   hipStream_t, hipEvent_t, hipEvent_t);                                     \
+    template void launch_smooth<T>(const Inst<T> *, const Work &, int, int, int, int, const SmoothCfg &,     \
+                                   double *, hipStream_t, hipEvent_t, hipEvent_t);                           \
     template void launch_restrict<T>(const Inst<T> *, const Work &, int, hipStream_t);                       \
     template void launch_prolong<T>(const Inst<T> *, const Work &, int, hipStream_t);                        \
     template void launch_coarse<T>(const Inst<T> *, int, int, hipStream_t);                                  \

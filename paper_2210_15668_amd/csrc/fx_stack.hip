@@ -311,7 +311,8 @@ struct Engine {
     std::vector<int> prefix_host;
     Work w_tdgl{}, w_ext{}, w_res{};
     std::vector<Work> w_sm, w_rs, w_pr;
-    std::vector<int> zt, ncol;
+    std::vector<SmoothCfg> scfg;        // smoother launch shape per level
+    std::vector<int> ncol;
     int max_lc = 0, lds_max = 0, max_cycles = 1;
     int any_unfolded = 0;               // some instance forms phi + clip(e) in the residual kernel
     int nu1 = 2, nu2 = 2;
@@ -380,10 +381,7 @@ int coarse_layout(const Plan &p, Inst<T> *a) {
     return off;
 }
 
-int tiles_smooth(const HostLevel &H, int zt) {
-    const int nzt = (H.nz + zt - 1) / zt;
-    return H.rb ? tiles3(H.nx / 2, H.ny, nzt) : tiles3(H.nx, H.ny, nzt);
-}
+int tiles_smooth(const HostLevel &H, const SmoothCfg &c) { return tiles_cfg(H.rb ? H.nx / 2 : H.nx, H.ny, H.nz, c); }
 
 // Launch shapes that depend on all instances: levels with their own
 // kernels, planes per smoother thread, colours per sweep.
@@ -396,7 +394,7 @@ void plan_launches(Engine *e) {
         e->max_cycles = std::max(e->max_cycles, h.d.max_cycles);
         if (!(h.plan.lv[0].rb && h.plan.lc > 0)) e->any_unfolded = 1;
     }
-    e->zt.assign(e->max_lc, 1);
+    e->scfg.assign(e->max_lc, SmoothCfg{6, 1, 0});
     e->ncol.assign(e->max_lc, 2);
     const int zt_env = env_int("FERROX_ZT", 0);
     for (int l = 0; l < e->max_lc; ++l) {
@@ -409,9 +407,10 @@ void plan_launches(Engine *e) {
             min_nz = std::min(min_nz, H.nz);
             if (!H.rb) e->ncol[l] = 4;
         }
-        // large levels: 4 planes per thread; small ones one plane per thread for parallelism
-        e->zt[l] = cells >= ((size_t)1 << 19) && min_nz >= 8 ? 4 : 1;
-        if (zt_env == 1 || zt_env == 4) e->zt[l] = zt_env;
+        // before tuning: large levels 4 planes per thread, small ones one plane per
+        // thread for parallelism, 64 x 4 tiles
+        e->scfg[l].zt = cells >= ((size_t)1 << 19) && min_nz >= 8 ? 4 : 1;
+        if (zt_env == 1 || zt_env == 2 || zt_env == 4 || zt_env == 8) e->scfg[l].zt = zt_env;
     }
 }
 
@@ -496,8 +495,8 @@ fx_status build_work(Engine *e) {
     e->w_res = mk([](const InstHost &h) { const Plan &p = h.plan; return tiles3(p.nx, p.ny, (p.nzd + kResZ - 1) / kResZ); });
     e->w_sm.clear(); e->w_rs.clear(); e->w_pr.clear();
     for (int l = 0; l < e->max_lc; ++l) {
-        const int zt = e->zt[l];
-        e->w_sm.push_back(mk([&](const InstHost &h) { return l < h.plan.lc ? tiles_smooth(h.plan.lv[l], zt) : 0; }));
+        const SmoothCfg c = e->scfg[l];
+        e->w_sm.push_back(mk([&](const InstHost &h) { return l < h.plan.lc ? tiles_smooth(h.plan.lv[l], c) : 0; }));
         e->w_rs.push_back(mk([&](const InstHost &h) {
             if (l >= h.plan.lc) return 0;
             const HostLevel &C = h.plan.lv[l + 1];
@@ -687,7 +686,7 @@ void smooth_l(Engine *e, int l, int color, int zi, int upd) {
         pb = e->probe_dev + e->ev_used / 2;
         e->ev_used += 2;
     }
-    launch_smooth(idev<T>(e), w, l, color, zi, upd, e->zt[l], pb, e->st, e0, e1);
+    launch_smooth(idev<T>(e), w, l, color, zi, upd, e->scfg[l], pb, e->st, e0, e1);
 }
 
 // One V(nu1, nu2) cycle over every running instance.  Levels 0 .. lc-1 of an
@@ -965,6 +964,17 @@ fx_status engine_init(Engine *e, double *const *d_P, double *const *d_phi, void 
         }
         // Step 0: phi^{0,(0)} = 0, then solve
         for (int b = 0; b < kPhiBufs; ++b) launch_fill(h.phi[b], nfull, 0.0, e->st);
+        // level arrays start defined (the autotuner may sweep them before any solve)
+        const size_t w = e->prec == FX_PREC_MIXED ? sizeof(float) : sizeof(double);
+        for (size_t l = 0; l < p.lv.size(); ++l) {
+            const HostLevel &H = p.lv[l];
+            void *ee = e->prec == FX_PREC_MIXED ? (void *)h.L32[l].e : (void *)h.L64[l].e;
+            void *rr = e->prec == FX_PREC_MIXED ? (void *)h.L32[l].r : (void *)h.L64[l].r;
+            void *ss = e->prec == FX_PREC_MIXED ? (void *)h.L32[l].sig : (void *)h.L64[l].sig;
+            launch_zero(ee, H.ncell() * w, e->st);
+            launch_zero(rr, H.ncell() * w, e->st);
+            launch_zero(ss, std::max<size_t>(H.nsig(), 1) * w, e->st);
+        }
         fill_contacts(e, i, true);
     }
     launch_fill(e->probe_dev, kProbeMax, 0.0, e->st);
@@ -975,6 +985,7 @@ void engine_release(Engine *e) {
     if (e->st) (void)hipStreamSynchronize(e->st); else (void)hipDeviceSynchronize();
     for (int q = 0; q < kUnitPow; ++q)
         if (e->unit_exec[q]) (void)hipGraphExecDestroy(e->unit_exec[q]);
+    for (int q = 0; q < kUnitPow; ++q) e->unit_exec[q] = nullptr;
     if (e->cap) (void)hipStreamDestroy(e->cap);
     if (e->mir) (void)hipHostFree(e->mir);
     for (hipEvent_t ev : e->ev) (void)hipEventDestroy(ev);
@@ -1097,6 +1108,196 @@ fx_status probe_read(Engine *e, double *total_ms, int *launches, double *bytes) 
     if (launches) *launches = cnt;
     if (bytes) *bytes = by;
     return FX_OK;
+}
+
+// ---------------------------------------------------------------- autotuner
+// For every level with its own smoother launches, the candidate launch shapes
+// (tile 32x8, 64x4 or 128x2 threads; 1, 2, 4 or 8 planes per thread; the
+// compiler's register budget or one for 8 waves per SIMD) are timed on the
+// live level arrays, and the fastest is kept.  The arithmetic of a cell does
+// not depend on the shape, so results are bitwise unchanged.  Choices are
+// cached in a text file, one line per (device, precision, level composition):
+//   <key> -> <log2 tile x> <planes per thread> <8-wave budget> <us per half-sweep>
+constexpr int kTuneVersion = 1;
+constexpr int kTuneReps = 10;
+
+uint64_t fnv1a(const std::string &t) {
+    uint64_t h = 1469598103934665603ULL;
+    for (unsigned char c : t) { h ^= c; h *= 1099511628211ULL; }
+    return h;
+}
+
+std::string device_tag() {
+    int dev = 0;
+    hipDeviceProp_t pr;
+    if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&pr, dev) != hipSuccess) return "unknown";
+    std::string a = pr.gcnArchName;
+    for (char &c : a)
+        if (c == ' ') c = '_';
+    return a + "/" + std::to_string(pr.multiProcessorCount);
+}
+
+std::string tune_key(const Engine *e, int l, const std::string &dev) {
+    std::string sig;
+    size_t cells = 0;
+    for (const InstHost &h : e->in) {
+        if (l >= h.plan.lc) continue;
+        const HostLevel &H = h.plan.lv[l];
+        sig += std::to_string(H.nx) + "x" + std::to_string(H.ny) + "x" + std::to_string(H.nz) + (H.rb ? "r" : "n") +
+               std::to_string(H.sig_hi - H.sig_lo) + ";";
+        cells += H.ncell();
+    }
+    char buf[256];
+    snprintf(buf, sizeof buf, "v%d %s %s smooth %016llx %zu", kTuneVersion, dev.c_str(),
+             e->prec == FX_PREC_MIXED ? "f32" : "f64", (unsigned long long)fnv1a(sig), cells);
+    return buf;
+}
+
+struct TuneEntry {
+    SmoothCfg c;
+    double us;
+};
+
+std::vector<std::pair<std::string, TuneEntry>> read_tune_cache(const char *path) {
+    std::vector<std::pair<std::string, TuneEntry>> out;
+    FILE *f = path ? fopen(path, "r") : nullptr;
+    if (!f) return out;
+    char line[1024];
+    while (fgets(line, sizeof line, f)) {
+        std::string t(line);
+        const size_t arrow = t.find(" -> ");
+        if (arrow == std::string::npos) continue;
+        TuneEntry te;
+        if (sscanf(t.c_str() + arrow + 4, "%d %d %d %lf", &te.c.lbx, &te.c.zt, &te.c.w8, &te.us) != 4) continue;
+        const bool ok = te.c.lbx >= 5 && te.c.lbx <= 7 && (te.c.zt == 1 || te.c.zt == 2 || te.c.zt == 4 || te.c.zt == 8) &&
+                        (te.c.w8 == 0 || te.c.w8 == 1);
+        if (ok) out.emplace_back(t.substr(0, arrow), te);
+    }
+    fclose(f);
+    return out;
+}
+
+// Prefix table of level l's smoother launches for launch shape c.
+fx_status set_smooth_work(Engine *e, int l, const SmoothCfg &c) {
+    const int n = e->n, tab = 3 + 3 * l;
+    int *hp = e->prefix_host.data() + (size_t)tab * (n + 1);
+    long long tot = 0;
+    hp[0] = 0;
+    for (int i = 0; i < n; ++i) {
+        const InstHost &h = e->in[i];
+        tot += l < h.plan.lc ? tiles_smooth(h.plan.lv[l], c) : 0;
+        if (tot > (1LL << 30)) return fail(FX_EINVAL, "a launch would exceed 2^30 tiles");
+        hp[i + 1] = (int)tot;
+    }
+    HIP_OK(hipStreamSynchronize(e->st));
+    HIP_OK(hipMemcpy(e->prefix_dev + (size_t)tab * (n + 1), hp, (n + 1) * sizeof(int), hipMemcpyHostToDevice));
+    e->w_sm[l].total = (int)tot;
+    return FX_OK;
+}
+
+template <typename T>
+fx_status time_smooth(Engine *e, int l, const SmoothCfg &c, hipEvent_t ev0, hipEvent_t ev1, double *us) {
+    fx_status st = set_smooth_work(e, l, c);
+    if (st) return st;
+    const Inst<T> *I = idev<T>(e);
+    double best = 1e300;
+    for (int rep = 0; rep < 2; ++rep) {
+        for (int q = 0; q < 2; ++q) launch_smooth(I, e->w_sm[l], l, q & 1, 0, 0, c, nullptr, e->st);
+        HIP_OK(hipEventRecord(ev0, e->st));
+        for (int q = 0; q < kTuneReps; ++q) launch_smooth(I, e->w_sm[l], l, q & 1, 0, 0, c, nullptr, e->st);
+        HIP_OK(hipEventRecord(ev1, e->st));
+        HIP_OK(hipEventSynchronize(ev1));
+        float ms = 0.0f;
+        HIP_OK(hipEventElapsedTime(&ms, ev0, ev1));
+        best = std::min(best, 1e3 * ms / kTuneReps);
+    }
+    *us = best;
+    return FX_OK;
+}
+
+void drop_graphs(Engine *e) {
+    for (int q = 0; q < kUnitPow; ++q)
+        if (e->unit_exec[q]) {
+            (void)hipGraphExecDestroy(e->unit_exec[q]);
+            e->unit_exec[q] = nullptr;
+        }
+}
+
+template <typename T>
+fx_status autotune_t(Engine *e, const char *path, int flags, fx_tune_info *info) {
+    fx_tune_info ti{};
+    HIP_OK(hipStreamSynchronize(e->st));
+    // every instance's kernels must run while timing: done = 0, restored after
+    std::vector<InstState> saved(e->mir, e->mir + e->n);
+    for (int i = 0; i < e->n; ++i) {
+        InstState t = saved[i];
+        t.done = 0;
+        launch_put_state(e->st_dev + i, t, e->st);
+    }
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    HIP_OK(hipEventCreate(&ev0));
+    HIP_OK(hipEventCreate(&ev1));
+    const std::string dev = device_tag();
+    const auto cache = read_tune_cache(path);
+    FILE *out = nullptr;
+    fx_status st = FX_OK;
+    for (int l = 0; l < e->max_lc && !st; ++l) {
+        ++ti.levels;
+        const std::string key = tune_key(e, l, dev);
+        const TuneEntry *hit = nullptr;
+        for (const auto &kv : cache)
+            if (kv.first == key) hit = &kv.second;          // the last entry wins
+        SmoothCfg pick = e->scfg[l];
+        if (hit && !(flags & FX_TUNE_FORCE)) {
+            pick = hit->c;
+            ++ti.from_cache;
+        } else {
+            int min_nz = 1 << 30;
+            for (const InstHost &h : e->in)
+                if (l < h.plan.lc) min_nz = std::min(min_nz, h.plan.lv[l].nz);
+            double def_us = 0.0, best_us;
+            if ((st = time_smooth<T>(e, l, pick, ev0, ev1, &def_us))) break;
+            best_us = def_us;
+            ++ti.configs_timed;
+            for (int lbx = 5; lbx <= 7 && !st; ++lbx)
+                for (int zt : {1, 2, 4, 8})
+                    for (int w8 = 0; w8 <= 1; ++w8) {
+                        if (zt > 1 && zt > min_nz) continue;
+                        const SmoothCfg c{lbx, zt, w8};
+                        if (c.lbx == pick.lbx && c.zt == pick.zt && c.w8 == pick.w8) continue;
+                        double us = 0.0;
+                        if ((st = time_smooth<T>(e, l, c, ev0, ev1, &us))) break;
+                        ++ti.configs_timed;
+                        if (us < 0.98 * best_us) { best_us = us; pick = c; }
+                    }
+            if (st) break;
+            ti.default_us += def_us;
+            ti.tuned_us += best_us;
+            if (path) {
+                if (!out) out = fopen(path, "a");
+                if (out) {
+                    fprintf(out, "%s -> %d %d %d %.3f\n", key.c_str(), pick.lbx, pick.zt, pick.w8, best_us);
+                    ti.cache_written = 1;
+                }
+            }
+        }
+        e->scfg[l] = pick;
+        if (!st) st = set_smooth_work(e, l, pick);
+    }
+    if (out) fclose(out);
+    for (int i = 0; i < e->n; ++i) launch_put_state(e->st_dev + i, saved[i], e->st);
+    hipError_t er = hipStreamSynchronize(e->st);
+    (void)hipEventDestroy(ev0);
+    (void)hipEventDestroy(ev1);
+    drop_graphs(e);
+    if (st) return st;
+    if (er != hipSuccess) return fail(FX_EDEVICE, "autotune: %s", hipGetErrorString(er));
+    if (info) *info = ti;
+    return FX_OK;
+}
+
+fx_status autotune(Engine *e, const char *path, int flags, fx_tune_info *info) {
+    return e->prec == FX_PREC_MIXED ? autotune_t<float>(e, path, flags, info) : autotune_t<double>(e, path, flags, info);
 }
 
 }  // namespace
@@ -1230,6 +1431,24 @@ fx_status stack_set_launch(fx_stack *s, int mode) {
     return FX_OK;
 }
 
+fx_status stack_autotune(fx_stack *s, const char *cache_path, int flags, fx_tune_info *info) {
+    g_err.clear();
+    if (!s) return fail(FX_EINVAL, "stack is NULL");
+    if (flags & ~FX_TUNE_FORCE) return fail(FX_EINVAL, "unknown flags %d", flags);
+    return autotune(&s->e, cache_path, flags, info);
+}
+
+fx_status stack_tune_config(const fx_stack *s, int level, int *tile_x, int *zt, int *waves8) {
+    g_err.clear();
+    if (!s) return fail(FX_EINVAL, "stack is NULL");
+    if (level < 0 || level >= s->e.max_lc) return fail(FX_EINVAL, "level %d has no smoother launches", level);
+    const SmoothCfg &c = s->e.scfg[level];
+    if (tile_x) *tile_x = 1 << c.lbx;
+    if (zt) *zt = c.zt;
+    if (waves8) *waves8 = c.w8;
+    return FX_OK;
+}
+
 fx_status stack_probe(fx_stack *s, int kernel, int max_launches, int stride) {
     g_err.clear();
     if (!s) return fail(FX_EINVAL, "stack is NULL");
@@ -1339,6 +1558,13 @@ fx_status batch_get_field(fx_batch *b, int inst, int which, double *h_out) {
     if (!b || !h_out) return fail(FX_EINVAL, "NULL argument");
     if (inst < 0 || inst >= b->e.n) return fail(FX_EINVAL, "instance %d outside 0..%d", inst, b->e.n - 1);
     return get_field_impl(&b->e, inst, which, h_out);
+}
+
+fx_status batch_autotune(fx_batch *b, const char *cache_path, int flags, fx_tune_info *info) {
+    g_err.clear();
+    if (!b) return fail(FX_EINVAL, "batch is NULL");
+    if (flags & ~FX_TUNE_FORCE) return fail(FX_EINVAL, "unknown flags %d", flags);
+    return autotune(&b->e, cache_path, flags, info);
 }
 
 fx_status batch_set_launch(fx_batch *b, int mode) {

@@ -22,6 +22,7 @@ FX_OK, FX_EINVAL, FX_ENOMEM, FX_EDEVICE, FX_ENOCONV, FX_ENONFINITE, FX_ESTATE = 
 FIELD_P, FIELD_PHI, FIELD_PHI_PREV, FIELD_PHI_PREV2, FIELD_PHI_PREV3 = 0, 1, 2, 3, 4
 PROBE_OFF, PROBE_SMOOTH_FINE = 0, 1
 LAUNCH_STREAM, LAUNCH_GRAPH = 0, 1
+TUNE_FORCE = 1
 _STATUS = {0: "FX_OK", 1: "FX_EINVAL", 2: "FX_ENOMEM", 3: "FX_EDEVICE", 4: "FX_ENOCONV",
            5: "FX_ENONFINITE", 6: "FX_ESTATE"}
 
@@ -63,6 +64,11 @@ class BatchInfo(ctypes.Structure):
                 ("max_cycles_step", ctypes.c_int), ("last_res_rel", ctypes.c_double)]
 
 
+class TuneInfo(ctypes.Structure):
+    _fields_ = [("levels", ctypes.c_int), ("from_cache", ctypes.c_int), ("configs_timed", ctypes.c_int),
+                ("cache_written", ctypes.c_int), ("default_us", ctypes.c_double), ("tuned_us", ctypes.c_double)]
+
+
 # (name, restype, argtypes) of every entry point declared in include/ferrox.h
 _vp, _dp, _ip = ctypes.c_void_p, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int)
 _D = ctypes.POINTER(StackDesc)
@@ -80,6 +86,9 @@ SIGNATURES = [
     ("stack_level_shape", ctypes.c_int, [_vp, ctypes.c_int, _ip, _ip, _ip]),
     ("destroy_stack", ctypes.c_int, [_vp]),
     ("stack_set_launch", ctypes.c_int, [_vp, ctypes.c_int]),
+    ("stack_autotune", ctypes.c_int, [_vp, ctypes.c_char_p, ctypes.c_int, ctypes.POINTER(TuneInfo)]),
+    ("stack_tune_config", ctypes.c_int, [_vp, ctypes.c_int, _ip, _ip, _ip]),
+    ("batch_autotune", ctypes.c_int, [_vp, ctypes.c_char_p, ctypes.c_int, ctypes.POINTER(TuneInfo)]),
     ("batch_workspace_bytes", ctypes.c_size_t, [_D, ctypes.c_int]),
     ("init_batch", ctypes.c_int, [_D, ctypes.c_int, ctypes.POINTER(_vp), ctypes.POINTER(_vp), _vp,
                                   ctypes.c_size_t, _vp, ctypes.POINTER(_vp)]),
@@ -207,6 +216,19 @@ class Stack:
         """LAUNCH_STREAM or LAUNCH_GRAPH for run_steps (see include/ferrox.h)."""
         _check(lib().stack_set_launch(self._h, mode))
 
+    def autotune(self, cache_path: Optional[str] = None, force: bool = False) -> TuneInfo:
+        """Time the smoother's launch shapes per level and keep the fastest (see include/ferrox.h)."""
+        info = TuneInfo()
+        path = cache_path.encode() if cache_path else None
+        _check(lib().stack_autotune(self._h, path, TUNE_FORCE if force else 0, ctypes.byref(info)))
+        return info
+
+    def tune_config(self, level: int):
+        """(tile width in threads, planes per thread, 8-wave register budget) in use at a level."""
+        a, b, c = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+        _check(lib().stack_tune_config(self._h, level, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)))
+        return a.value, b.value, c.value
+
     def probe(self, kernel: int = PROBE_SMOOTH_FINE, max_launches: int = 4096, stride: int = 1):
         """Start timestamping every stride-th finest-level smoother launch (see include/ferrox.h)."""
         _check(lib().stack_probe(self._h, kernel, max_launches, stride))
@@ -304,6 +326,12 @@ class Batch:
 
     def set_launch(self, mode: int):
         _check(lib().batch_set_launch(self._h, mode))
+
+    def autotune(self, cache_path: Optional[str] = None, force: bool = False) -> TuneInfo:
+        info = TuneInfo()
+        path = cache_path.encode() if cache_path else None
+        _check(lib().batch_autotune(self._h, path, TUNE_FORCE if force else 0, ctypes.byref(info)))
+        return info
 
     def close(self):
         if getattr(self, "_h", None) is not None and self._h.value:

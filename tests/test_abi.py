@@ -48,6 +48,8 @@ def test_binding_struct_matches_header_layout(fx):
     assert ctypes.sizeof(fx.StackDesc) == 176
     assert ctypes.sizeof(fx.SolveInfo) == 24
     assert ctypes.sizeof(fx.RunInfo) == 24
+    assert ctypes.sizeof(fx.BatchInfo) == 24
+    assert ctypes.sizeof(fx.TuneInfo) == 32
 
 
 def test_workspace_sizing_and_validation(fx):
