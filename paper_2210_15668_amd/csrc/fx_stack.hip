@@ -25,6 +25,7 @@
 // layered medium, which keeps the V-cycle contraction near 0.1 across the
 // permittivity jumps where distance-linear weights stall near 0.2.
 #include "fx_internal.h"
+#include "fx_unet_internal.h"
 #include "../../include/ferrox.h"
 
 #include <algorithm>
@@ -61,6 +62,12 @@ fx_status fail(fx_status s, const char *fmt, ...) {
         if (e_ != hipSuccess)                                                                \
             return fail(FX_EDEVICE, "%s failed: %s", #call, hipGetErrorString(e_));          \
     } while (0)
+
+}  // namespace
+
+void fx::set_error(const char *msg) { g_err = msg; }
+
+namespace {
 
 int env_int(const char *name, int dflt) {
     const char *v = getenv(name);
@@ -1310,6 +1317,38 @@ struct fx_batch {
     Engine e;
 };
 
+// ------------------------------------------------- learned start helpers
+namespace {
+
+fx_status check_unet(const Engine *e, fx_unet *u) {
+    if (!u) return fail(FX_EINVAL, "network is NULL");
+    int nx, ny, nz;
+    hipStream_t ust;
+    unet_geometry(u, &nx, &ny, &nz, &ust);
+    const Plan &p = e->in[0].plan;
+    if (nx != p.nx || ny != p.ny || nz != p.nzd)
+        return fail(FX_EINVAL, "network slab %dx%dx%d differs from the stack's device slab %dx%dx%d", nx, ny, nz, p.nx,
+                    p.ny, p.nzd);
+    return FX_OK;
+}
+
+// Per-plane tables of the stack's device planes for the network.
+fx_status unet_tables(const Engine *e, fx_unet *u, double v_top, bool doping) {
+    const InstHost &h = e->in[0];
+    const Plan &p = h.plan;
+    std::vector<double> eps(p.nzd), dop(p.nzd);
+    for (int k = 0; k < p.nzd; ++k) {
+        eps[k] = h.eps_r[p.kb + k];
+        dop[k] = h.mat[p.kb + k] == FX_MAT_SC ? h.Nd[p.kb + k] - h.Na[p.kb + k] : 0.0;
+    }
+    fx_status st = unet_upload_lin(u, eps.data(), h.d.v_bottom, v_top);
+    if (!st && doping) st = unet_upload_doping(u, dop.data());
+    return st;
+}
+
+}  // namespace
+
+
 extern "C" {
 
 size_t stack_workspace_bytes(const fx_stack_desc *desc) {
@@ -1580,6 +1619,64 @@ fx_status destroy_batch(fx_batch *b) {
     engine_release(&b->e);
     delete b;
     return FX_OK;
+}
+
+fx_status stack_unet_input(fx_stack *s, fx_unet *u, double v_top) {
+    g_err.clear();
+    if (!s) return fail(FX_EINVAL, "stack is NULL");
+    fx_status st = check_unet(&s->e, u);
+    if (st) return st;
+    if (!std::isfinite(v_top)) return fail(FX_EINVAL, "v_top must be finite");
+    HIP_OK(hipStreamSynchronize(s->e.st));
+    if ((st = unet_tables(&s->e, u, v_top, true))) return st;
+    const InstHost &h = s->e.in[0];
+    const size_t nxy = (size_t)h.plan.nx * h.plan.ny;
+    unet_pack_from_f64(u, h.P[0] + h.plan.kb * nxy, v_top);
+    HIP_OK(hipGetLastError());
+    return FX_OK;
+}
+
+fx_status stack_unet_target(fx_stack *s, fx_unet *u, double v_top, float *d_target) {
+    g_err.clear();
+    if (!s || !d_target) return fail(FX_EINVAL, "NULL argument");
+    fx_status st = check_unet(&s->e, u);
+    if (st) return st;
+    if (!std::isfinite(v_top)) return fail(FX_EINVAL, "v_top must be finite");
+    HIP_OK(hipStreamSynchronize(s->e.st));
+    if ((st = unet_tables(&s->e, u, v_top, false))) return st;
+    const InstHost &h = s->e.in[0];
+    const size_t nxy = (size_t)h.plan.nx * h.plan.ny;
+    unet_make_target(u, h.phi[0] + h.plan.kb * nxy, d_target);
+    int nx, ny, nz;
+    hipStream_t ust;
+    unet_geometry(u, &nx, &ny, &nz, &ust);
+    HIP_OK(hipStreamSynchronize(ust));
+    return FX_OK;
+}
+
+fx_status stack_learned_solve(fx_stack *s, fx_unet *u, double v_top, fx_solve_info *info) {
+    g_err.clear();
+    if (!s) return fail(FX_EINVAL, "stack is NULL");
+    Engine *e = &s->e;
+    fx_status st = check_unet(e, u);
+    if (st) return st;
+    if (!std::isfinite(v_top)) return fail(FX_EINVAL, "v_top must be finite");
+    HIP_OK(hipStreamSynchronize(e->st));
+    if ((st = unet_tables(e, u, v_top, true))) return st;
+    InstHost &h = e->in[0];
+    const size_t nxy = (size_t)h.plan.nx * h.plan.ny;
+    unet_pack_from_f64(u, h.P[0] + h.plan.kb * nxy, v_top);
+    unet_forward_enqueue(u);
+    unet_apply(u, h.phi[0] + h.plan.kb * nxy);
+    int nx, ny, nz;
+    hipStream_t ust;
+    unet_geometry(u, &nx, &ny, &nz, &ust);
+    HIP_OK(hipStreamSynchronize(ust));
+    HIP_OK(hipGetLastError());
+    // phi^n was replaced: the stored time levels no longer precede it
+    e->mir[0].hist = 0;
+    put_state(e, 0);
+    return poisson_solve(s, v_top, info);
 }
 
 const char *last_error(void) { return g_err.c_str(); }

@@ -1,0 +1,990 @@
+// Learned warm start: a 3D convolutional U-Net on the device slab of a stack,
+// forward and backward on the matrix cores (gfx950, BF16 operands, FP32
+// accumulation), and its Adam training step.
+//
+// Tensors are (z, y, x, channel), channel fastest, stored as BF16 bit
+// patterns.  A 3x3x3 convolution is an implicit GEMM per output voxel block:
+// M = output channels, N = voxels, K = 27 taps x input channels, fed to
+// v_mfma_f32_16x16x16_bf16 in 16-channel K chunks.  Lane layout of that
+// instruction (wave64): lane l holds A[l%16][4(l/16)+j], B[4(l/16)+j][l%16]
+// and D[4(l/16)+r][l%16], j, r = 0..3; with A = weights W[tap][cout][cin] and
+// B = input channels of one neighbour voxel per lane, both operands are one
+// 8-byte load per lane and each lane stores 4 consecutive output channels.
+//
+// The input gradient of a convolution is the same convolution of the output
+// gradient with the weights flipped in all three directions and transposed
+// (cin <-> cout): the adjoint of "read x at v + d" is "write to v + d", and
+// the periodic x-y wrap and the zeros beyond the z-ends are their own adjoints
+// under the flip.  The weight gradient sums dZ[v][cout] x[v + d][cin] over all
+// voxels: blocks stage 64 voxels of both in LDS and accumulate on the matrix
+// cores; per-block partial sums are added in a fixed order (deterministic).
+#include "fx_internal.h"
+#include "fx_unet_internal.h"
+#include "../../include/ferrox_unet.h"
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+namespace fx {
+
+namespace {
+
+typedef short s4 __attribute__((ext_vector_type(4)));
+typedef float f4 __attribute__((ext_vector_type(4)));
+
+constexpr float kPScale = 0.2f;          // C/m^2
+constexpr double kDopingScale = 1e24;    // m^-3
+constexpr double kVScale = 2.0;          // V
+constexpr double kPhiScale = 1.0;        // V
+constexpr int kInC = 16;
+
+__device__ __forceinline__ float bf2f(bf16_t h) { return __uint_as_float((unsigned)h << 16); }
+
+// round to nearest even (NaN stays NaN)
+__device__ __forceinline__ bf16_t f2bf(float f) {
+    const unsigned u = __float_as_uint(f);
+    if ((u & 0x7fffffffu) > 0x7f800000u) return (bf16_t)((u >> 16) | 0x40u);
+    return (bf16_t)((u + 0x7fffu + ((u >> 16) & 1u)) >> 16);
+}
+
+// ------------------------------------------------------------ convolution
+// OUT 0: Y (BF16) = relu(conv + bias); OUT 1: Y (FP32) = conv; OUT 2: Y (FP32) += conv.
+// Block: 4 waves, each 16 x NTW consecutive voxels and all COUT channels.
+template <int CIN, int COUT, int NTW, int OUT>
+__global__ __launch_bounds__(256) void k_conv3(const bf16_t *__restrict__ X, int ldx, const bf16_t *__restrict__ Wt,
+                                               const float *__restrict__ bias, void *Yv, int ldy, int nx, int ny,
+                                               int nz) {
+    constexpr int MT = COUT / 16, KC = CIN / 16;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int n = nx * ny * nz;
+    const int v0 = (blockIdx.x * 4 + wave) * (16 * NTW);
+    if (v0 >= n) return;
+    const int col = lane & 15, kq = lane >> 4;
+    int px[NTW], py[NTW], pz[NTW];
+    bool ok[NTW];
+#pragma unroll
+    for (int t = 0; t < NTW; ++t) {
+        const int v = v0 + 16 * t + col;
+        ok[t] = v < n;
+        const int vv = ok[t] ? v : 0;
+        px[t] = vv % nx;
+        const int q = vv / nx;
+        py[t] = q % ny;
+        pz[t] = q / ny;
+    }
+    f4 acc[MT][NTW];
+#pragma unroll
+    for (int m = 0; m < MT; ++m)
+#pragma unroll
+        for (int t = 0; t < NTW; ++t) acc[m][t] = f4{0.f, 0.f, 0.f, 0.f};
+    const s4 zero4 = {0, 0, 0, 0};
+    for (int dz = -1; dz <= 1; ++dz)
+        for (int dy = -1; dy <= 1; ++dy)
+            for (int dx = -1; dx <= 1; ++dx) {
+                const int tap = (dz + 1) * 9 + (dy + 1) * 3 + (dx + 1);
+                int nb[NTW];
+#pragma unroll
+                for (int t = 0; t < NTW; ++t) {
+                    const int z2 = pz[t] + dz;
+                    int y2 = py[t] + dy, x2 = px[t] + dx;
+                    y2 = y2 < 0 ? y2 + ny : (y2 >= ny ? y2 - ny : y2);
+                    x2 = x2 < 0 ? x2 + nx : (x2 >= nx ? x2 - nx : x2);
+                    nb[t] = (ok[t] && z2 >= 0 && z2 < nz) ? (z2 * ny + y2) * nx + x2 : -1;
+                }
+                const bf16_t *wtap = Wt + (size_t)tap * COUT * CIN;
+#pragma unroll
+                for (int kc = 0; kc < KC; ++kc) {
+                    s4 b[NTW];
+#pragma unroll
+                    for (int t = 0; t < NTW; ++t)
+                        b[t] = nb[t] >= 0 ? *(const s4 *)(X + (size_t)nb[t] * ldx + kc * 16 + 4 * kq) : zero4;
+#pragma unroll
+                    for (int m = 0; m < MT; ++m) {
+                        const s4 a = *(const s4 *)(wtap + (size_t)(m * 16 + col) * CIN + kc * 16 + 4 * kq);
+#pragma unroll
+                        for (int t = 0; t < NTW; ++t)
+                            acc[m][t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b[t], acc[m][t], 0, 0, 0);
+                    }
+                }
+            }
+#pragma unroll
+    for (int t = 0; t < NTW; ++t) {
+        if (!ok[t]) continue;
+        const size_t v = (size_t)(v0 + 16 * t + col);
+#pragma unroll
+        for (int m = 0; m < MT; ++m) {
+            const int co = m * 16 + 4 * kq;
+            if (OUT == 0) {
+                s4 o;
+#pragma unroll
+                for (int r = 0; r < 4; ++r) o[r] = (short)f2bf(fmaxf(acc[m][t][r] + bias[co + r], 0.f));
+                *(s4 *)((bf16_t *)Yv + v * ldy + co) = o;
+            } else {
+                f4 *dst = (f4 *)((float *)Yv + v * ldy + co);
+                if (OUT == 2) *dst = *dst + acc[m][t];
+                else *dst = acc[m][t];
+            }
+        }
+    }
+}
+
+// Weight gradient of one tap (blockIdx.y): part[bx][tap][cout][cin] =
+// sum over the block's voxels of G[v][cout] X[v + d_tap][cin].
+template <int CIN, int COUT>
+__global__ __launch_bounds__(256) void k_wgrad(const bf16_t *__restrict__ X, int ldx, const bf16_t *__restrict__ G,
+                                               int nx, int ny, int nz, float *__restrict__ part) {
+    __shared__ bf16_t gz[64 * COUT];
+    __shared__ bf16_t xs[64 * CIN];
+    constexpr int MT = COUT / 16, NC = CIN / 16, T = MT * NC, TPW = (T + 3) / 4;
+    const int tap = blockIdx.y;
+    const int dz = tap / 9 - 1, dy = (tap / 3) % 3 - 1, dx = tap % 3 - 1;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int col = lane & 15, kq = lane >> 4;
+    const int n = nx * ny * nz, nchunks = (n + 63) / 64;
+    f4 acc[TPW];
+#pragma unroll
+    for (int q = 0; q < TPW; ++q) acc[q] = f4{0.f, 0.f, 0.f, 0.f};
+    for (int ch = blockIdx.x; ch < nchunks; ch += gridDim.x) {
+        const int v0 = ch * 64;
+        for (int e = threadIdx.x; e < 64 * COUT; e += 256) {
+            const int v = v0 + e / COUT;
+            gz[e] = v < n ? G[(size_t)v * COUT + e % COUT] : (bf16_t)0;
+        }
+        for (int e = threadIdx.x; e < 64 * CIN; e += 256) {
+            const int v = v0 + e / CIN;
+            bf16_t val = 0;
+            if (v < n) {
+                const int x = v % nx, q = v / nx, y = q % ny, z = q / ny;
+                const int z2 = z + dz;
+                if (z2 >= 0 && z2 < nz) {
+                    int y2 = y + dy, x2 = x + dx;
+                    y2 = y2 < 0 ? y2 + ny : (y2 >= ny ? y2 - ny : y2);
+                    x2 = x2 < 0 ? x2 + nx : (x2 >= nx ? x2 - nx : x2);
+                    val = X[(size_t)((z2 * ny + y2) * nx + x2) * ldx + e % CIN];
+                }
+            }
+            xs[e] = val;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int kk = 0; kk < 4; ++kk) {
+#pragma unroll
+            for (int q = 0; q < TPW; ++q) {
+                const int tile = wave + 4 * q;
+                if (tile >= T) break;
+                const int mt = tile / NC, nt = tile % NC;
+                s4 a, b;
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    const int r = kk * 16 + 4 * kq + j;
+                    a[j] = (short)gz[r * COUT + mt * 16 + col];
+                    b[j] = (short)xs[r * CIN + nt * 16 + col];
+                }
+                acc[q] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc[q], 0, 0, 0);
+            }
+        }
+        __syncthreads();
+    }
+    float *out = part + ((size_t)blockIdx.x * 27 + tap) * COUT * CIN;
+#pragma unroll
+    for (int q = 0; q < TPW; ++q) {
+        const int tile = wave + 4 * q;
+        if (tile >= T) break;
+        const int mt = tile / NC, nt = tile % NC;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) out[(size_t)(mt * 16 + 4 * kq + r) * CIN + nt * 16 + col] = acc[q][r];
+    }
+}
+
+// dst[i] (+)= sum over p of part[p][i], p in a fixed order.
+__global__ void k_part_sum(const float *__restrict__ part, int nparts, int m, float *__restrict__ dst, int add) {
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < m; i += gridDim.x * blockDim.x) {
+        float s = 0.f;
+        for (int p = 0; p < nparts; ++p) s += part[(size_t)p * m + i];
+        dst[i] = add ? dst[i] + s : s;
+    }
+}
+
+// ------------------------------------------------------ elementwise parts
+// Average of the 2x2x2 children (low grid nx, ny, nz).
+__global__ void k_pool(const bf16_t *__restrict__ X, int ldx, bf16_t *__restrict__ Y, int C, int nx, int ny, int nz) {
+    const size_t total = (size_t)nx * ny * nz * C;
+    for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < total; e += (size_t)gridDim.x * blockDim.x) {
+        const int c = (int)(e % C);
+        const size_t v = e / C;
+        const int x = (int)(v % nx), q = (int)(v / nx), y = q % ny, z = q / ny;
+        const int NX = 2 * nx, NY = 2 * ny;
+        float s = 0.f;
+        for (int a = 0; a < 2; ++a)
+            for (int b = 0; b < 2; ++b)
+                for (int d = 0; d < 2; ++d)
+                    s += bf2f(X[(size_t)(((2 * z + a) * NY + 2 * y + b) * NX + 2 * x + d) * ldx + c]);
+        Y[e] = f2bf(s * 0.125f);
+    }
+}
+
+// D[child][c] += G[parent][c] / 8 (high grid nx, ny, nz).
+__global__ void k_pool_bwd(const float *__restrict__ G, float *__restrict__ D, int ldd, int C, int nx, int ny, int nz) {
+    const size_t total = (size_t)nx * ny * nz * C;
+    for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < total; e += (size_t)gridDim.x * blockDim.x) {
+        const int c = (int)(e % C);
+        const size_t v = e / C;
+        const int x = (int)(v % nx), q = (int)(v / nx), y = q % ny, z = q / ny;
+        const size_t p = ((size_t)(z / 2) * (ny / 2) + y / 2) * (nx / 2) + x / 2;
+        D[v * ldd + c] += 0.125f * G[p * C + c];
+    }
+}
+
+// Y[child] = X[parent] (high grid nx, ny, nz).
+__global__ void k_up(const bf16_t *__restrict__ X, bf16_t *__restrict__ Y, int ldy, int C, int nx, int ny, int nz) {
+    const size_t total = (size_t)nx * ny * nz * C;
+    for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < total; e += (size_t)gridDim.x * blockDim.x) {
+        const int c = (int)(e % C);
+        const size_t v = e / C;
+        const int x = (int)(v % nx), q = (int)(v / nx), y = q % ny, z = q / ny;
+        const size_t p = ((size_t)(z / 2) * (ny / 2) + y / 2) * (nx / 2) + x / 2;
+        Y[v * ldy + c] = X[p * C + c];
+    }
+}
+
+// D[parent][c] = sum of G[child][c] over the 8 children (low grid nx, ny, nz).
+__global__ void k_up_bwd(const float *__restrict__ G, int ldg, float *__restrict__ D, int C, int nx, int ny, int nz) {
+    const size_t total = (size_t)nx * ny * nz * C;
+    for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < total; e += (size_t)gridDim.x * blockDim.x) {
+        const int c = (int)(e % C);
+        const size_t v = e / C;
+        const int x = (int)(v % nx), q = (int)(v / nx), y = q % ny, z = q / ny;
+        const int NX = 2 * nx, NY = 2 * ny;
+        float s = 0.f;
+        for (int a = 0; a < 2; ++a)
+            for (int b = 0; b < 2; ++b)
+                for (int d = 0; d < 2; ++d) s += G[(size_t)(((2 * z + a) * NY + 2 * y + b) * NX + 2 * x + d) * ldg + c];
+        D[e] = s;
+    }
+}
+
+// Z = G * [Y > 0] (gradient through a ReLU whose output is Y), as BF16.
+__global__ void k_mask(const float *__restrict__ G, int ldg, const bf16_t *__restrict__ Y, int ldy,
+                       bf16_t *__restrict__ Z, int C, size_t n) {
+    const size_t total = n * C;
+    for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < total; e += (size_t)gridDim.x * blockDim.x) {
+        const int c = (int)(e % C);
+        const size_t v = e / C;
+        Z[e] = bf2f(Y[v * ldy + c]) > 0.f ? f2bf(G[v * ldg + c]) : (bf16_t)0;
+    }
+}
+
+// Per-block column sums of a BF16 [n][C] tensor: part[block][c].
+__global__ __launch_bounds__(256) void k_colsum(const bf16_t *__restrict__ Z, int C, size_t n, float *__restrict__ part) {
+    __shared__ float red[256];
+    const int c = threadIdx.x % C, lanes = 256 / C * C;
+    float s = 0.f;
+    if ((int)threadIdx.x < lanes)
+        for (size_t v = blockIdx.x * (size_t)(256 / C) + threadIdx.x / C; v < n; v += (size_t)gridDim.x * (256 / C))
+            s += bf2f(Z[v * C + c]);
+    red[threadIdx.x] = s;
+    __syncthreads();
+    if ((int)threadIdx.x < C) {
+        float t = 0.f;
+        for (int q = threadIdx.x; q < lanes; q += C) t += red[q];
+        part[(size_t)blockIdx.x * C + threadIdx.x] = t;
+    }
+}
+
+// Head: out[v] = b + sum_c w[c] X[v][c] (X: [n][16]).
+__global__ void k_head(const bf16_t *__restrict__ X, const float *__restrict__ wb, float *__restrict__ out, size_t n) {
+    for (size_t v = blockIdx.x * (size_t)blockDim.x + threadIdx.x; v < n; v += (size_t)gridDim.x * blockDim.x) {
+        float s = wb[16];
+        const s4 *p = (const s4 *)(X + v * 16);
+        for (int q = 0; q < 4; ++q) {
+            const s4 a = p[q];
+            for (int j = 0; j < 4; ++j) s += wb[4 * q + j] * bf2f((bf16_t)a[j]);
+        }
+        out[v] = s;
+    }
+}
+
+// Loss pieces: d[v] = 2 (out - t) / n and per-block sums of (out - t)^2.
+__global__ __launch_bounds__(256) void k_loss(const float *__restrict__ out, const float *__restrict__ tg,
+                                              float *__restrict__ d, double *__restrict__ part, size_t n) {
+    __shared__ double red[256];
+    double s = 0.0;
+    const float sc = 2.0f / (float)n;
+    for (size_t v = blockIdx.x * (size_t)blockDim.x + threadIdx.x; v < n; v += (size_t)gridDim.x * blockDim.x) {
+        const float e = out[v] - tg[v];
+        d[v] = sc * e;
+        s += (double)e * e;
+    }
+    red[threadIdx.x] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double t = 0.0;
+        for (int q = 0; q < 256; ++q) t += red[q];
+        part[blockIdx.x] = t;
+    }
+}
+
+__global__ void k_sum_d(const double *__restrict__ part, int n, double scale, double *__restrict__ dst) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        double t = 0.0;
+        for (int q = 0; q < n; ++q) t += part[q];
+        *dst = t * scale;
+    }
+}
+
+// Head backward: Z[v][c] = d[v] w[c] [Y > 0]; per-block sums of d[v] Y[v][c] (c < 16) and d[v] (c = 16).
+__global__ __launch_bounds__(256) void k_head_bwd(const float *__restrict__ d, const bf16_t *__restrict__ Y,
+                                                  const float *__restrict__ wb, bf16_t *__restrict__ Z,
+                                                  float *__restrict__ part, size_t n) {
+    __shared__ float red[17][256];
+    float s[17];
+    for (int c = 0; c < 17; ++c) s[c] = 0.f;
+    for (size_t v = blockIdx.x * (size_t)blockDim.x + threadIdx.x; v < n; v += (size_t)gridDim.x * blockDim.x) {
+        const float g = d[v];
+        for (int c = 0; c < 16; ++c) {
+            const float y = bf2f(Y[v * 16 + c]);
+            s[c] += g * y;
+            Z[v * 16 + c] = y > 0.f ? f2bf(g * wb[c]) : (bf16_t)0;
+        }
+        s[16] += g;
+    }
+    for (int c = 0; c < 17; ++c) red[c][threadIdx.x] = s[c];
+    __syncthreads();
+    if (threadIdx.x < 17) {
+        float t = 0.f;
+        for (int q = 0; q < 256; ++q) t += red[threadIdx.x][q];
+        part[(size_t)blockIdx.x * 17 + threadIdx.x] = t;
+    }
+}
+
+// Adam on the flat parameter vector.
+__global__ void k_adam(float *__restrict__ th, const float *__restrict__ g, float *__restrict__ m, float *__restrict__ v,
+                       size_t n, float lr, float c1, float c2) {
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+        const float gi = g[i];
+        const float mi = 0.9f * m[i] + 0.1f * gi;
+        const float vi = 0.999f * v[i] + 0.001f * gi * gi;
+        m[i] = mi;
+        v[i] = vi;
+        th[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + 1e-8f);
+    }
+}
+
+// BF16 copies of one layer's weights: wt[t][co][ci] and the flipped,
+// transposed wf[26 - t][ci][co] used by the input gradient.
+__global__ void k_prep(const float *__restrict__ th, int cin, int cout, bf16_t *__restrict__ wt, bf16_t *__restrict__ wf) {
+    const int total = 27 * cin * cout;
+    for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < total; e += gridDim.x * blockDim.x) {
+        const int ci = e % cin, q = e / cin, co = q % cout, t = q / cout;
+        const bf16_t h = f2bf(th[e]);
+        wt[e] = h;
+        wf[((size_t)(26 - t) * cin + ci) * cout + co] = h;
+    }
+}
+
+// Network input from P over the device planes (z-major), doping per plane and V.
+template <typename T>
+__global__ void k_pack(const T *__restrict__ P, const float *__restrict__ dop, float vs, bf16_t *__restrict__ in,
+                       int nxy, size_t n) {
+    for (size_t v = blockIdx.x * (size_t)blockDim.x + threadIdx.x; v < n; v += (size_t)gridDim.x * blockDim.x) {
+        s4 q0, q1 = {0, 0, 0, 0};
+        q0[0] = (short)f2bf((float)P[v] / kPScale);
+        q0[1] = (short)f2bf(dop[v / nxy]);
+        q0[2] = (short)f2bf(vs);
+        q0[3] = 0;
+        s4 *dst = (s4 *)(in + v * kInC);
+        dst[0] = q0;
+        dst[1] = q1;
+        dst[2] = q1;
+        dst[3] = q1;
+    }
+}
+
+__global__ void k_bf_to_f(const bf16_t *__restrict__ a, float *__restrict__ b, size_t n) {
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) b[i] = bf2f(a[i]);
+}
+
+__global__ void k_f_to_bf(const float *__restrict__ a, bf16_t *__restrict__ b, size_t n) {
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) b[i] = f2bf(a[i]);
+}
+
+// phi (device planes) := phi_lin[z] + scale * out.
+__global__ void k_apply(const float *__restrict__ out, const double *__restrict__ lin, double *__restrict__ phi, int nxy,
+                        size_t n) {
+    for (size_t v = blockIdx.x * (size_t)blockDim.x + threadIdx.x; v < n; v += (size_t)gridDim.x * blockDim.x)
+        phi[v] = lin[v / nxy] + kPhiScale * (double)out[v];
+}
+
+// target := (phi - phi_lin[z]) / scale.
+__global__ void k_target(const double *__restrict__ phi, const double *__restrict__ lin, float *__restrict__ tg, int nxy,
+                         size_t n) {
+    for (size_t v = blockIdx.x * (size_t)blockDim.x + threadIdx.x; v < n; v += (size_t)gridDim.x * blockDim.x)
+        tg[v] = (float)((phi[v] - lin[v / nxy]) / kPhiScale);
+}
+
+dim3 grid_for(size_t work) {
+    const size_t b = (work + 255) / 256;
+    return dim3((unsigned)(b == 0 ? 1 : (b < 8192 ? b : 8192)));
+}
+
+// -------------------------------------------------------- host dispatch
+typedef void (*ConvFn)(const bf16_t *, int, const bf16_t *, const float *, void *, int, int, int, int);
+
+template <int CIN, int COUT, int NTW, int OUT>
+void conv_launch(const bf16_t *X, int ldx, const bf16_t *W, const float *b, void *Y, int ldy, int nx, int ny, int nz,
+                 hipStream_t st) {
+    const int n = nx * ny * nz, per = 64 * NTW;
+    hipLaunchKernelGGL((k_conv3<CIN, COUT, NTW, OUT>), dim3((n + per - 1) / per), dim3(256), 0, st, X, ldx, W, b, Y, ldy,
+                       nx, ny, nz);
+}
+
+// (cin, cout) pairs of the forward layers and of their input gradients
+#define FX_CONV_PAIRS(F) \
+    F(16, 16) F(16, 32) F(32, 32) F(32, 64) F(64, 64) F(96, 32) F(48, 16) F(32, 16) F(64, 32) F(32, 96) F(16, 48)
+
+// Convolution dispatch: NTW = 4 on large grids, 1 on small ones (more blocks).
+bool conv_any(int cin, int cout, int out, const bf16_t *X, int ldx, const bf16_t *W, const float *b, void *Y, int ldy,
+              int nx, int ny, int nz, hipStream_t st) {
+    const bool big = (size_t)nx * ny * nz >= (size_t)256 * 64 * 4;
+#define FX_CONV_CASE(ci, co)                                                                               \
+    if (cin == ci && cout == co) {                                                                         \
+        if (out == 0) {                                                                                    \
+            if (big) conv_launch<ci, co, 4, 0>(X, ldx, W, b, Y, ldy, nx, ny, nz, st);                       \
+            else conv_launch<ci, co, 1, 0>(X, ldx, W, b, Y, ldy, nx, ny, nz, st);                           \
+        } else if (out == 1) {                                                                             \
+            if (big) conv_launch<ci, co, 4, 1>(X, ldx, W, b, Y, ldy, nx, ny, nz, st);                       \
+            else conv_launch<ci, co, 1, 1>(X, ldx, W, b, Y, ldy, nx, ny, nz, st);                           \
+        } else {                                                                                           \
+            if (big) conv_launch<ci, co, 4, 2>(X, ldx, W, b, Y, ldy, nx, ny, nz, st);                       \
+            else conv_launch<ci, co, 1, 2>(X, ldx, W, b, Y, ldy, nx, ny, nz, st);                           \
+        }                                                                                                  \
+        return true;                                                                                       \
+    }
+    FX_CONV_PAIRS(FX_CONV_CASE)
+#undef FX_CONV_CASE
+    return false;
+}
+
+bool wgrad_any(int cin, int cout, const bf16_t *X, int ldx, const bf16_t *G, int nx, int ny, int nz, float *part,
+               int nparts, hipStream_t st) {
+#define FX_WG_CASE(ci, co)                                                                                        \
+    if (cin == ci && cout == co) {                                                                                \
+        hipLaunchKernelGGL((k_wgrad<ci, co>), dim3(nparts, 27), dim3(256), 0, st, X, ldx, G, nx, ny, nz, part);  \
+        return true;                                                                                              \
+    }
+    FX_CONV_PAIRS(FX_WG_CASE)
+#undef FX_WG_CASE
+    return false;
+}
+
+}  // namespace
+
+// ------------------------------------------------------------- the network
+struct Layer {
+    const char *name;
+    int cin, cout, level;
+    size_t woff, boff;                  // offsets in the parameter vector
+    size_t bf_off;                      // offset of this layer in the BF16 weight arrays
+};
+
+static const Layer kLayerTemplate[10] = {
+    {"e0a", 16, 16, 0, 0, 0, 0}, {"e0b", 16, 16, 0, 0, 0, 0}, {"e1a", 16, 32, 1, 0, 0, 0}, {"e1b", 32, 32, 1, 0, 0, 0},
+    {"b2a", 32, 64, 2, 0, 0, 0}, {"b2b", 64, 64, 2, 0, 0, 0}, {"d1a", 96, 32, 1, 0, 0, 0}, {"d1b", 32, 32, 1, 0, 0, 0},
+    {"d0a", 48, 16, 0, 0, 0, 0}, {"d0b", 16, 16, 0, 0, 0, 0}};
+enum { E0A, E0B, E1A, E1B, B2A, B2B, D1A, D1B, D0A, D0B, NLAYER };
+
+struct UnetLayout {
+    Layer L[NLAYER];
+    size_t nparams = 0, head_off = 0, nbf = 0;
+    UnetLayout() {
+        size_t o = 0, bo = 0;
+        for (int i = 0; i < NLAYER; ++i) {
+            L[i] = kLayerTemplate[i];
+            L[i].woff = o;
+            o += (size_t)27 * L[i].cin * L[i].cout;
+            L[i].boff = o;
+            o += L[i].cout;
+            L[i].bf_off = bo;
+            bo += (size_t)27 * L[i].cin * L[i].cout;
+        }
+        head_off = o;
+        nparams = o + 17;
+        nbf = bo;
+    }
+};
+
+static const UnetLayout &layout() {
+    static const UnetLayout lay;
+    return lay;
+}
+
+}  // namespace fx
+
+using namespace fx;
+
+struct fx_unet {
+    int nx, ny, nz, train;
+    hipStream_t st;
+    size_t n0, n1, n2;                  // voxels per level
+    // parameters and optimiser
+    float *theta, *grad, *m, *v;
+    bf16_t *wt, *wf;
+    int adam_t;
+    // activations (BF16)
+    bf16_t *in, *a_e0a, *cat0, *p0, *a_e1a, *cat1, *p1, *a_b2a, *a_b2b, *a_d1a, *a_d1b, *a_d0a, *a_d0b;
+    float *out;
+    // gradients (training)
+    float *dout, *g0_16, *g0_48, *g1_32a, *g1_32b, *g1_96, *g1_16, *g2_64a, *g2_64b, *g2_32;
+    bf16_t *z0, *z1, *z2;
+    float *part;                        // weight-gradient partial sums
+    size_t part_floats;
+    double *dpart, *dscal;
+    float *dop;                         // doping per plane (network units)
+    double *lin;                        // phi_lin per plane
+    double *h_scal;                     // pinned read-back
+};
+
+namespace {
+
+fx_status ufail(fx_status s, const char *fmt, ...) __attribute__((format(printf, 2, 3)));
+fx_status ufail(fx_status s, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    fx::set_error(buf);
+    return s;
+}
+
+#define UHIP(call)                                                                                 \
+    do {                                                                                           \
+        hipError_t e_ = (call);                                                                    \
+        if (e_ != hipSuccess) return ufail(FX_EDEVICE, "%s failed: %s", #call, hipGetErrorString(e_)); \
+    } while (0)
+
+constexpr int kWgradParts0 = 128;       // weight-gradient partitions on the finest level
+
+int wgrad_parts(size_t n) {
+    const size_t chunks = (n + 63) / 64;
+    const size_t p = chunks / 32;       // at least 32 chunks per block
+    return (int)(p < 1 ? 1 : (p > kWgradParts0 ? kWgradParts0 : p));
+}
+
+struct Carve {
+    char *base;
+    size_t off = 0;
+    explicit Carve(void *b) : base((char *)b) {}
+    template <typename T>
+    T *take(size_t count) {
+        off = (off + 255) & ~(size_t)255;
+        T *p = base ? (T *)(base + off) : nullptr;
+        off += count * sizeof(T);
+        return p;
+    }
+};
+
+bool valid_dims(int nx, int ny, int nz) {
+    return nx >= 4 && ny >= 4 && nz >= 4 && nx % 4 == 0 && ny % 4 == 0 && nz % 4 == 0 &&
+           (double)nx * ny * nz * 48 < 2147483647.0;
+}
+
+size_t carve_unet(fx_unet *u, void *ws) {
+    Carve cv(ws);
+    const UnetLayout &lay = layout();
+    const size_t n0 = u->n0, n1 = u->n1, n2 = u->n2;
+    u->theta = cv.take<float>(lay.nparams);
+    u->wt = cv.take<bf16_t>(lay.nbf);
+    u->wf = cv.take<bf16_t>(lay.nbf);
+    u->in = cv.take<bf16_t>(n0 * kInC);
+    u->a_e0a = cv.take<bf16_t>(n0 * 16);
+    u->cat0 = cv.take<bf16_t>(n0 * 48);
+    u->p0 = cv.take<bf16_t>(n1 * 16);
+    u->a_e1a = cv.take<bf16_t>(n1 * 32);
+    u->cat1 = cv.take<bf16_t>(n1 * 96);
+    u->p1 = cv.take<bf16_t>(n2 * 32);
+    u->a_b2a = cv.take<bf16_t>(n2 * 64);
+    u->a_b2b = cv.take<bf16_t>(n2 * 64);
+    u->a_d1a = cv.take<bf16_t>(n1 * 32);
+    u->a_d1b = cv.take<bf16_t>(n1 * 32);
+    u->a_d0a = cv.take<bf16_t>(n0 * 16);
+    u->a_d0b = cv.take<bf16_t>(n0 * 16);
+    u->out = cv.take<float>(n0);
+    u->dop = cv.take<float>(u->nz);
+    u->lin = cv.take<double>(u->nz);
+    u->dpart = cv.take<double>(8192);
+    u->dscal = cv.take<double>(4);
+    if (u->train) {
+        u->grad = cv.take<float>(lay.nparams);
+        u->m = cv.take<float>(lay.nparams);
+        u->v = cv.take<float>(lay.nparams);
+        u->dout = cv.take<float>(n0);
+        u->g0_16 = cv.take<float>(n0 * 16);
+        u->g0_48 = cv.take<float>(n0 * 48);
+        u->g1_32a = cv.take<float>(n1 * 32);
+        u->g1_32b = cv.take<float>(n1 * 32);
+        u->g1_96 = cv.take<float>(n1 * 96);
+        u->g1_16 = cv.take<float>(n1 * 16);
+        u->g2_64a = cv.take<float>(n2 * 64);
+        u->g2_64b = cv.take<float>(n2 * 64);
+        u->g2_32 = cv.take<float>(n2 * 32);
+        u->z0 = cv.take<bf16_t>(n0 * 16);
+        u->z1 = cv.take<bf16_t>(n1 * 32);
+        u->z2 = cv.take<bf16_t>(n2 * 64);
+        size_t pf = 0;
+        for (int i = 0; i < NLAYER; ++i) {
+            const Layer &L = lay.L[i];
+            const size_t n = L.level == 0 ? n0 : (L.level == 1 ? n1 : n2);
+            pf = std::max(pf, (size_t)wgrad_parts(n) * 27 * L.cin * L.cout);
+        }
+        pf = std::max(pf, (size_t)8192 * 64);           // column-sum partials
+        u->part_floats = pf;
+        u->part = cv.take<float>(pf);
+    } else {
+        u->grad = u->m = u->v = u->dout = nullptr;
+        u->g0_16 = u->g0_48 = u->g1_32a = u->g1_32b = u->g1_96 = u->g1_16 = u->g2_64a = u->g2_64b = u->g2_32 = nullptr;
+        u->z0 = u->z1 = u->z2 = nullptr;
+        u->part = nullptr;
+        u->part_floats = 0;
+    }
+    return cv.off + 256;
+}
+
+struct Dims {
+    int nx, ny, nz;
+};
+
+Dims dims_of(const fx_unet *u, int level) {
+    return Dims{u->nx >> level, u->ny >> level, u->nz >> level};
+}
+
+const bf16_t *wt_of(const fx_unet *u, int l) { return u->wt + layout().L[l].bf_off; }
+const bf16_t *wf_of(const fx_unet *u, int l) { return u->wf + layout().L[l].bf_off; }
+const float *bias_of(const fx_unet *u, int l) { return u->theta + layout().L[l].boff; }
+
+void conv_fwd(fx_unet *u, int l, const bf16_t *X, int ldx, bf16_t *Y, int ldy) {
+    const Layer &L = layout().L[l];
+    const Dims d = dims_of(u, L.level);
+    conv_any(L.cin, L.cout, 0, X, ldx, wt_of(u, l), bias_of(u, l), Y, ldy, d.nx, d.ny, d.nz, u->st);
+}
+
+void prep_weights(fx_unet *u) {
+    const UnetLayout &lay = layout();
+    for (int i = 0; i < NLAYER; ++i) {
+        const Layer &L = lay.L[i];
+        hipLaunchKernelGGL(k_prep, grid_for((size_t)27 * L.cin * L.cout), dim3(256), 0, u->st, u->theta + L.woff, L.cin,
+                           L.cout, u->wt + L.bf_off, u->wf + L.bf_off);
+    }
+}
+
+void enqueue_forward(fx_unet *u) {
+    const Dims d0 = dims_of(u, 0), d1 = dims_of(u, 1), d2 = dims_of(u, 2);
+    hipStream_t st = u->st;
+    conv_fwd(u, E0A, u->in, kInC, u->a_e0a, 16);
+    conv_fwd(u, E0B, u->a_e0a, 16, u->cat0 + 32, 48);
+    hipLaunchKernelGGL(k_pool, grid_for(u->n1 * 16), dim3(256), 0, st, u->cat0 + 32, 48, u->p0, 16, d1.nx, d1.ny, d1.nz);
+    conv_fwd(u, E1A, u->p0, 16, u->a_e1a, 32);
+    conv_fwd(u, E1B, u->a_e1a, 32, u->cat1 + 64, 96);
+    hipLaunchKernelGGL(k_pool, grid_for(u->n2 * 32), dim3(256), 0, st, u->cat1 + 64, 96, u->p1, 32, d2.nx, d2.ny, d2.nz);
+    conv_fwd(u, B2A, u->p1, 32, u->a_b2a, 64);
+    conv_fwd(u, B2B, u->a_b2a, 64, u->a_b2b, 64);
+    hipLaunchKernelGGL(k_up, grid_for(u->n1 * 64), dim3(256), 0, st, u->a_b2b, u->cat1, 96, 64, d1.nx, d1.ny, d1.nz);
+    conv_fwd(u, D1A, u->cat1, 96, u->a_d1a, 32);
+    conv_fwd(u, D1B, u->a_d1a, 32, u->a_d1b, 32);
+    hipLaunchKernelGGL(k_up, grid_for(u->n0 * 32), dim3(256), 0, st, u->a_d1b, u->cat0, 48, 32, d0.nx, d0.ny, d0.nz);
+    conv_fwd(u, D0A, u->cat0, 48, u->a_d0a, 16);
+    conv_fwd(u, D0B, u->a_d0a, 16, u->a_d0b, 16);
+    hipLaunchKernelGGL(k_head, grid_for(u->n0), dim3(256), 0, st, u->a_d0b, u->theta + layout().head_off, u->out, u->n0);
+}
+
+// Bias gradient of layer l from its BF16 output gradient Z ([n][cout]).
+void bias_grad(fx_unet *u, int l, const bf16_t *Z, size_t n) {
+    const Layer &L = layout().L[l];
+    const int nb = (int)std::min<size_t>(1024, (n + 255) / 256);
+    hipLaunchKernelGGL(k_colsum, dim3(nb), dim3(256), 0, u->st, Z, L.cout, n, u->part);
+    hipLaunchKernelGGL(k_part_sum, dim3(1), dim3(64), 0, u->st, u->part, nb, L.cout, u->grad + L.boff, 0);
+}
+
+// Weight and bias gradient of layer l (input X, ld ldx; output gradient Z),
+// and optionally its input gradient into G (FP32, ld ldg; add = accumulate).
+void layer_backward(fx_unet *u, int l, const bf16_t *X, int ldx, const bf16_t *Z, float *G, int ldg, int add) {
+    const Layer &L = layout().L[l];
+    const Dims d = dims_of(u, L.level);
+    const size_t n = (size_t)d.nx * d.ny * d.nz;
+    const int np = wgrad_parts(n);
+    wgrad_any(L.cin, L.cout, X, ldx, Z, d.nx, d.ny, d.nz, u->part, np, u->st);
+    const int m = 27 * L.cin * L.cout;
+    hipLaunchKernelGGL(k_part_sum, grid_for(m), dim3(256), 0, u->st, u->part, np, m, u->grad + L.woff, 0);
+    bias_grad(u, l, Z, n);
+    if (G) conv_any(L.cout, L.cin, add ? 2 : 1, Z, L.cout, wf_of(u, l), nullptr, G, ldg, d.nx, d.ny, d.nz, u->st);
+}
+
+void mask(fx_unet *u, const float *G, int ldg, const bf16_t *Y, int ldy, bf16_t *Z, int C, size_t n) {
+    hipLaunchKernelGGL(k_mask, grid_for(n * C), dim3(256), 0, u->st, G, ldg, Y, ldy, Z, C, n);
+}
+
+// Loss against tg and the full gradient (into u->grad); the loss is left in dscal[0].
+void enqueue_backward(fx_unet *u, const float *tg) {
+    const Dims d0 = dims_of(u, 0), d1 = dims_of(u, 1), d2 = dims_of(u, 2);
+    hipStream_t st = u->st;
+    const UnetLayout &lay = layout();
+    const size_t n0 = u->n0, n1 = u->n1, n2 = u->n2;
+    const int nbl = 1024;
+    hipLaunchKernelGGL(k_loss, dim3(nbl), dim3(256), 0, st, u->out, tg, u->dout, u->dpart, n0);
+    hipLaunchKernelGGL(k_sum_d, dim3(1), dim3(64), 0, st, u->dpart, nbl, 1.0 / (double)n0, u->dscal);
+    // head
+    hipLaunchKernelGGL(k_head_bwd, dim3(nbl), dim3(256), 0, st, u->dout, u->a_d0b, u->theta + lay.head_off, u->z0,
+                       u->part, n0);
+    hipLaunchKernelGGL(k_part_sum, dim3(1), dim3(64), 0, st, u->part, nbl, 17, u->grad + lay.head_off, 0);
+    // level 0, up
+    layer_backward(u, D0B, u->a_d0a, 16, u->z0, u->g0_16, 16, 0);
+    mask(u, u->g0_16, 16, u->a_d0a, 16, u->z0, 16, n0);
+    layer_backward(u, D0A, u->cat0, 48, u->z0, u->g0_48, 48, 0);
+    hipLaunchKernelGGL(k_up_bwd, grid_for(n1 * 32), dim3(256), 0, st, u->g0_48, 48, u->g1_32a, 32, d1.nx, d1.ny, d1.nz);
+    // level 1, up
+    mask(u, u->g1_32a, 32, u->a_d1b, 32, u->z1, 32, n1);
+    layer_backward(u, D1B, u->a_d1a, 32, u->z1, u->g1_32b, 32, 0);
+    mask(u, u->g1_32b, 32, u->a_d1a, 32, u->z1, 32, n1);
+    layer_backward(u, D1A, u->cat1, 96, u->z1, u->g1_96, 96, 0);
+    hipLaunchKernelGGL(k_up_bwd, grid_for(n2 * 64), dim3(256), 0, st, u->g1_96, 96, u->g2_64a, 64, d2.nx, d2.ny, d2.nz);
+    // level 2
+    mask(u, u->g2_64a, 64, u->a_b2b, 64, u->z2, 64, n2);
+    layer_backward(u, B2B, u->a_b2a, 64, u->z2, u->g2_64b, 64, 0);
+    mask(u, u->g2_64b, 64, u->a_b2a, 64, u->z2, 64, n2);
+    layer_backward(u, B2A, u->p1, 32, u->z2, u->g2_32, 32, 0);
+    hipLaunchKernelGGL(k_pool_bwd, grid_for(n1 * 32), dim3(256), 0, st, u->g2_32, u->g1_96 + 64, 96, 32, d1.nx, d1.ny,
+                       d1.nz);
+    // level 1, down (skip 1 gradient = channels 64..95 of g1_96)
+    mask(u, u->g1_96 + 64, 96, u->cat1 + 64, 96, u->z1, 32, n1);
+    layer_backward(u, E1B, u->a_e1a, 32, u->z1, u->g1_32b, 32, 0);
+    mask(u, u->g1_32b, 32, u->a_e1a, 32, u->z1, 32, n1);
+    layer_backward(u, E1A, u->p0, 16, u->z1, u->g1_16, 16, 0);
+    hipLaunchKernelGGL(k_pool_bwd, grid_for(n0 * 16), dim3(256), 0, st, u->g1_16, u->g0_48 + 32, 48, 16, d0.nx, d0.ny,
+                       d0.nz);
+    // level 0, down (skip 0 gradient = channels 32..47 of g0_48)
+    mask(u, u->g0_48 + 32, 48, u->cat0 + 32, 48, u->z0, 16, n0);
+    layer_backward(u, E0B, u->a_e0a, 16, u->z0, u->g0_16, 16, 0);
+    mask(u, u->g0_16, 16, u->a_e0a, 16, u->z0, 16, n0);
+    layer_backward(u, E0A, u->in, kInC, u->z0, nullptr, 0, 0);
+}
+
+// phi_lin per device plane: the P = 0, carrier-free layered stack between the contacts.
+void phi_lin_planes(const double *eps, int nz, double vb, double vt, double *out) {
+    double Rtot = 0.0;
+    for (int k = 0; k < nz; ++k) Rtot += 1.0 / eps[k];
+    double R = 0.0;
+    for (int k = 0; k < nz; ++k) {
+        const double half = 0.5 / eps[k];
+        out[k] = vb + (vt - vb) * (R + half) / Rtot;
+        R += 2.0 * half;
+    }
+}
+
+}  // namespace
+
+namespace fx {
+
+fx_status unet_upload_doping(fx_unet *u, const double *h_doping) {
+    std::vector<float> d(u->nz);
+    for (int k = 0; k < u->nz; ++k) d[k] = (float)(h_doping[k] / kDopingScale);
+    UHIP(hipMemcpyAsync(u->dop, d.data(), u->nz * sizeof(float), hipMemcpyHostToDevice, u->st));
+    UHIP(hipStreamSynchronize(u->st));
+    return FX_OK;
+}
+
+fx_status unet_upload_lin(fx_unet *u, const double *eps, double vb, double vt) {
+    std::vector<double> l(u->nz);
+    phi_lin_planes(eps, u->nz, vb, vt, l.data());
+    UHIP(hipMemcpyAsync(u->lin, l.data(), u->nz * sizeof(double), hipMemcpyHostToDevice, u->st));
+    UHIP(hipStreamSynchronize(u->st));
+    return FX_OK;
+}
+
+void unet_geometry(const fx_unet *u, int *nx, int *ny, int *nz, hipStream_t *st) {
+    *nx = u->nx;
+    *ny = u->ny;
+    *nz = u->nz;
+    *st = u->st;
+}
+
+void unet_pack_from_f64(fx_unet *u, const double *P_slab, double v_top) {
+    hipLaunchKernelGGL(k_pack<double>, grid_for(u->n0), dim3(256), 0, u->st, P_slab, u->dop, (float)(v_top / kVScale),
+                       u->in, u->nx * u->ny, u->n0);
+}
+
+void unet_forward_enqueue(fx_unet *u) { enqueue_forward(u); }
+
+void unet_apply(fx_unet *u, double *phi_slab) {
+    hipLaunchKernelGGL(k_apply, grid_for(u->n0), dim3(256), 0, u->st, u->out, u->lin, phi_slab, u->nx * u->ny, u->n0);
+}
+
+void unet_make_target(fx_unet *u, const double *phi_slab, float *tg) {
+    hipLaunchKernelGGL(k_target, grid_for(u->n0), dim3(256), 0, u->st, phi_slab, u->lin, tg, u->nx * u->ny, u->n0);
+}
+
+}  // namespace fx
+
+extern "C" {
+
+size_t unet_num_params(void) { return layout().nparams; }
+
+size_t unet_workspace_bytes(int nx, int ny, int nzd, int train) {
+    fx::set_error("");
+    if (!valid_dims(nx, ny, nzd)) {
+        ufail(FX_EINVAL, "network slab %dx%dx%d: each size must be a multiple of 4 and >= 4", nx, ny, nzd);
+        return 0;
+    }
+    fx_unet u{};
+    u.nx = nx; u.ny = ny; u.nz = nzd; u.train = train ? 1 : 0;
+    u.n0 = (size_t)nx * ny * nzd;
+    u.n1 = u.n0 / 8;
+    u.n2 = u.n1 / 8;
+    return carve_unet(&u, nullptr);
+}
+
+fx_status unet_init(int nx, int ny, int nzd, int train, void *d_ws, size_t ws_bytes, void *stream, fx_unet **out) {
+    fx::set_error("");
+    if (!out) return ufail(FX_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!valid_dims(nx, ny, nzd)) return ufail(FX_EINVAL, "network slab %dx%dx%d: each size must be a multiple of 4 and >= 4", nx, ny, nzd);
+    if (!d_ws || ((uintptr_t)d_ws & 255) != 0) return ufail(FX_EINVAL, "workspace must be non-NULL and 256-byte aligned");
+    fx_unet *u = new (std::nothrow) fx_unet();
+    if (!u) return ufail(FX_ENOMEM, "host allocation failed");
+    u->nx = nx; u->ny = ny; u->nz = nzd; u->train = train ? 1 : 0;
+    u->n0 = (size_t)nx * ny * nzd;
+    u->n1 = u->n0 / 8;
+    u->n2 = u->n1 / 8;
+    u->st = (hipStream_t)stream;
+    const size_t need = carve_unet(u, nullptr);
+    if (ws_bytes < need) { delete u; return ufail(FX_ENOMEM, "workspace %zu bytes < %zu needed", ws_bytes, need); }
+    carve_unet(u, d_ws);
+    if (hipHostMalloc((void **)&u->h_scal, 4 * sizeof(double), 0) != hipSuccess) {
+        delete u;
+        return ufail(FX_EDEVICE, "hipHostMalloc failed");
+    }
+    // everything defined before first use: zero the whole workspace
+    launch_zero(d_ws, (need - 256) & ~(size_t)3, u->st);
+    u->adam_t = 0;
+    if (hipStreamSynchronize(u->st) != hipSuccess) {
+        (void)hipHostFree(u->h_scal);
+        delete u;
+        return ufail(FX_EDEVICE, "workspace clear failed");
+    }
+    *out = u;
+    return FX_OK;
+}
+
+fx_status unet_set_params(fx_unet *u, const float *h_params) {
+    fx::set_error("");
+    if (!u || !h_params) return ufail(FX_EINVAL, "NULL argument");
+    const size_t n = layout().nparams;
+    UHIP(hipMemcpyAsync(u->theta, h_params, n * sizeof(float), hipMemcpyHostToDevice, u->st));
+    if (u->train) {
+        launch_zero(u->m, n * sizeof(float), u->st);
+        launch_zero(u->v, n * sizeof(float), u->st);
+    }
+    u->adam_t = 0;
+    prep_weights(u);
+    UHIP(hipStreamSynchronize(u->st));
+    return FX_OK;
+}
+
+fx_status unet_get_params(fx_unet *u, float *h_params) {
+    fx::set_error("");
+    if (!u || !h_params) return ufail(FX_EINVAL, "NULL argument");
+    UHIP(hipMemcpyAsync(h_params, u->theta, layout().nparams * sizeof(float), hipMemcpyDeviceToHost, u->st));
+    UHIP(hipStreamSynchronize(u->st));
+    return FX_OK;
+}
+
+fx_status unet_pack_input(fx_unet *u, const float *d_P, const double *h_doping, double v_top) {
+    fx::set_error("");
+    if (!u || !d_P || !h_doping) return ufail(FX_EINVAL, "NULL argument");
+    if (!std::isfinite(v_top)) return ufail(FX_EINVAL, "v_top must be finite");
+    fx_status st = unet_upload_doping(u, h_doping);
+    if (st) return st;
+    hipLaunchKernelGGL(k_pack<float>, grid_for(u->n0), dim3(256), 0, u->st, d_P, u->dop, (float)(v_top / kVScale), u->in,
+                       u->nx * u->ny, u->n0);
+    return FX_OK;
+}
+
+fx_status unet_set_input(fx_unet *u, const float *h_in) {
+    fx::set_error("");
+    if (!u || !h_in) return ufail(FX_EINVAL, "NULL argument");
+    // stage through the output-gradient buffer or the activations: a float copy of n0*16 values
+    const size_t n = u->n0 * kInC;
+    float *tmp = (float *)u->cat0;      // n0*48 BF16 = n0*24 floats >= n0*16
+    UHIP(hipMemcpyAsync(tmp, h_in, n * sizeof(float), hipMemcpyHostToDevice, u->st));
+    hipLaunchKernelGGL(k_f_to_bf, grid_for(n), dim3(256), 0, u->st, tmp, u->in, n);
+    UHIP(hipStreamSynchronize(u->st));
+    return FX_OK;
+}
+
+fx_status unet_get_input(fx_unet *u, float *h_in) {
+    fx::set_error("");
+    if (!u || !h_in) return ufail(FX_EINVAL, "NULL argument");
+    const size_t n = u->n0 * kInC;
+    float *tmp = (float *)u->cat0;
+    hipLaunchKernelGGL(k_bf_to_f, grid_for(n), dim3(256), 0, u->st, u->in, tmp, n);
+    UHIP(hipMemcpyAsync(h_in, tmp, n * sizeof(float), hipMemcpyDeviceToHost, u->st));
+    UHIP(hipStreamSynchronize(u->st));
+    return FX_OK;
+}
+
+fx_status unet_forward(fx_unet *u, float *d_out) {
+    fx::set_error("");
+    if (!u) return ufail(FX_EINVAL, "network is NULL");
+    enqueue_forward(u);
+    if (d_out) UHIP(hipMemcpyAsync(d_out, u->out, u->n0 * sizeof(float), hipMemcpyDeviceToDevice, u->st));
+    UHIP(hipGetLastError());
+    return FX_OK;
+}
+
+fx_status unet_loss_grad(fx_unet *u, const float *d_target, double *h_loss, float *h_grad) {
+    fx::set_error("");
+    if (!u || !d_target) return ufail(FX_EINVAL, "NULL argument");
+    if (!u->train) return ufail(FX_ESTATE, "network was created without training buffers");
+    enqueue_forward(u);
+    enqueue_backward(u, d_target);
+    UHIP(hipMemcpyAsync(u->h_scal, u->dscal, sizeof(double), hipMemcpyDeviceToHost, u->st));
+    if (h_grad) UHIP(hipMemcpyAsync(h_grad, u->grad, layout().nparams * sizeof(float), hipMemcpyDeviceToHost, u->st));
+    UHIP(hipStreamSynchronize(u->st));
+    if (h_loss) *h_loss = u->h_scal[0];
+    return FX_OK;
+}
+
+fx_status unet_train_step(fx_unet *u, const float *d_target, float lr, double *h_loss) {
+    fx::set_error("");
+    if (!u || !d_target) return ufail(FX_EINVAL, "NULL argument");
+    if (!u->train) return ufail(FX_ESTATE, "network was created without training buffers");
+    if (!(lr > 0)) return ufail(FX_EINVAL, "lr must be > 0");
+    enqueue_forward(u);
+    enqueue_backward(u, d_target);
+    u->adam_t += 1;
+    const float c1 = 1.0f - powf(0.9f, (float)u->adam_t), c2 = 1.0f - powf(0.999f, (float)u->adam_t);
+    const size_t n = layout().nparams;
+    hipLaunchKernelGGL(k_adam, grid_for(n), dim3(256), 0, u->st, u->theta, u->grad, u->m, u->v, n, lr, c1, c2);
+    prep_weights(u);
+    if (h_loss) {
+        UHIP(hipMemcpyAsync(u->h_scal, u->dscal, sizeof(double), hipMemcpyDeviceToHost, u->st));
+        UHIP(hipStreamSynchronize(u->st));
+        *h_loss = u->h_scal[0];
+    }
+    UHIP(hipGetLastError());
+    return FX_OK;
+}
+
+fx_status unet_destroy(fx_unet *u) {
+    if (!u) return FX_OK;
+    if (u->st) (void)hipStreamSynchronize(u->st); else (void)hipDeviceSynchronize();
+    if (u->h_scal) (void)hipHostFree(u->h_scal);
+    delete u;
+    return FX_OK;
+}
+
+}  // extern "C"

@@ -71,6 +71,7 @@ class TuneInfo(ctypes.Structure):
 
 # (name, restype, argtypes) of every entry point declared in include/ferrox.h
 _vp, _dp, _ip = ctypes.c_void_p, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int)
+_fp = ctypes.POINTER(ctypes.c_float)
 _D = ctypes.POINTER(StackDesc)
 SIGNATURES = [
     ("stack_workspace_bytes", ctypes.c_size_t, [_D]),
@@ -89,6 +90,23 @@ SIGNATURES = [
     ("stack_autotune", ctypes.c_int, [_vp, ctypes.c_char_p, ctypes.c_int, ctypes.POINTER(TuneInfo)]),
     ("stack_tune_config", ctypes.c_int, [_vp, ctypes.c_int, _ip, _ip, _ip]),
     ("batch_autotune", ctypes.c_int, [_vp, ctypes.c_char_p, ctypes.c_int, ctypes.POINTER(TuneInfo)]),
+    # include/ferrox_unet.h
+    ("unet_num_params", ctypes.c_size_t, []),
+    ("unet_workspace_bytes", ctypes.c_size_t, [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int]),
+    ("unet_init", ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, _vp, ctypes.c_size_t, _vp,
+                                 ctypes.POINTER(_vp)]),
+    ("unet_set_params", ctypes.c_int, [_vp, _fp]),
+    ("unet_get_params", ctypes.c_int, [_vp, _fp]),
+    ("unet_pack_input", ctypes.c_int, [_vp, _vp, _dp, ctypes.c_double]),
+    ("unet_set_input", ctypes.c_int, [_vp, _fp]),
+    ("unet_get_input", ctypes.c_int, [_vp, _fp]),
+    ("unet_forward", ctypes.c_int, [_vp, _vp]),
+    ("unet_loss_grad", ctypes.c_int, [_vp, _vp, _dp, _fp]),
+    ("unet_train_step", ctypes.c_int, [_vp, _vp, ctypes.c_float, _dp]),
+    ("unet_destroy", ctypes.c_int, [_vp]),
+    ("stack_unet_input", ctypes.c_int, [_vp, _vp, ctypes.c_double]),
+    ("stack_unet_target", ctypes.c_int, [_vp, _vp, ctypes.c_double, _vp]),
+    ("stack_learned_solve", ctypes.c_int, [_vp, _vp, ctypes.c_double, ctypes.POINTER(SolveInfo)]),
     ("batch_workspace_bytes", ctypes.c_size_t, [_D, ctypes.c_int]),
     ("init_batch", ctypes.c_int, [_D, ctypes.c_int, ctypes.POINTER(_vp), ctypes.POINTER(_vp), _vp,
                                   ctypes.c_size_t, _vp, ctypes.POINTER(_vp)]),
@@ -336,6 +354,102 @@ class Batch:
     def close(self):
         if getattr(self, "_h", None) is not None and self._h.value:
             lib().destroy_batch(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class UNet:
+    """The learned warm start's network (include/ferrox_unet.h) over a stack's device slab
+    of nzd x ny x nx cells.  Parameters are a flat float32 vector (unet_num_params())."""
+
+    def __init__(self, nx: int, ny: int, nzd: int, train: bool = False, device: str = "cuda:0", stream=None):
+        import torch
+        self.shape = (nzd, ny, nx)
+        self.device = torch.device(device)
+        nbytes = int(lib().unet_workspace_bytes(nx, ny, nzd, 1 if train else 0))
+        if nbytes == 0:
+            raise FerroxError(FX_EINVAL, lib().last_error().decode())
+        self.ws = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        self._h = ctypes.c_void_p()
+        _check(lib().unet_init(nx, ny, nzd, 1 if train else 0, self.ws.data_ptr(), nbytes, self.stream.cuda_stream,
+                               ctypes.byref(self._h)))
+        self.nparams = int(lib().unet_num_params())
+
+    @staticmethod
+    def num_params() -> int:
+        return int(lib().unet_num_params())
+
+    def set_params(self, theta: np.ndarray):
+        a = np.ascontiguousarray(theta, np.float32)
+        assert a.size == self.nparams
+        _check(lib().unet_set_params(self._h, a.ctypes.data_as(_fp)))
+
+    def get_params(self) -> np.ndarray:
+        a = np.empty(self.nparams, np.float32)
+        _check(lib().unet_get_params(self._h, a.ctypes.data_as(_fp)))
+        return a
+
+    def set_input(self, x: np.ndarray):
+        a = np.ascontiguousarray(x, np.float32)
+        assert a.shape == self.shape + (16,)
+        _check(lib().unet_set_input(self._h, a.ctypes.data_as(_fp)))
+
+    def get_input(self) -> np.ndarray:
+        a = np.empty(self.shape + (16,), np.float32)
+        _check(lib().unet_get_input(self._h, a.ctypes.data_as(_fp)))
+        return a
+
+    def pack_input(self, P_slab, doping_planes, v_top: float):
+        """P_slab: float32 device tensor (nzd, ny, nx); doping_planes: nzd values of Nd - Na."""
+        self._dop = np.ascontiguousarray(doping_planes, np.float64)
+        _check(lib().unet_pack_input(self._h, P_slab.data_ptr(), self._dop.ctypes.data_as(_dp), float(v_top)))
+
+    def forward(self, out=None):
+        """Runs the network on its current input; returns a float32 tensor (nzd, ny, nx)."""
+        import torch
+        if out is None:
+            out = torch.empty(self.shape, dtype=torch.float32, device=self.device)
+        _check(lib().unet_forward(self._h, out.data_ptr()))
+        return out
+
+    def loss_grad(self, target, want_grad: bool = True):
+        loss = ctypes.c_double()
+        g = np.empty(self.nparams, np.float32) if want_grad else None
+        _check(lib().unet_loss_grad(self._h, target.data_ptr(), ctypes.byref(loss),
+                                    g.ctypes.data_as(_fp) if g is not None else None))
+        return loss.value, g
+
+    def train_step(self, target, lr: float, want_loss: bool = False):
+        loss = ctypes.c_double()
+        _check(lib().unet_train_step(self._h, target.data_ptr(), float(lr), ctypes.byref(loss) if want_loss else None))
+        return loss.value if want_loss else None
+
+    def input_from_stack(self, stack: "Stack", v_top: float):
+        _check(lib().stack_unet_input(stack._h, self._h, float(v_top)))
+
+    def target_from_stack(self, stack: "Stack", v_top: float, out=None):
+        import torch
+        if out is None:
+            out = torch.empty(self.shape, dtype=torch.float32, device=self.device)
+        _check(lib().stack_unet_target(stack._h, self._h, float(v_top), out.data_ptr()))
+        return out
+
+    def learned_solve(self, stack: "Stack", v_top: float, check: bool = True) -> SolveInfo:
+        info = SolveInfo()
+        st = lib().stack_learned_solve(stack._h, self._h, float(v_top), ctypes.byref(info))
+        if check:
+            _check(st)
+        return info
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib().unet_destroy(self._h)
             self._h = ctypes.c_void_p()
 
     def __del__(self):

@@ -10,11 +10,12 @@ import pytest
 from paper_2210_15668_amd import workloads as W
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-HEADER = os.path.join(ROOT, "include", "ferrox.h")
+HEADERS = [os.path.join(ROOT, "include", h) for h in sorted(os.listdir(os.path.join(ROOT, "include")))
+           if h.endswith(".h")]
 
 
 def declared_functions():
-    text = open(HEADER).read()
+    text = "\n".join(open(h).read() for h in HEADERS)
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
     names = re.findall(r"^[A-Za-z_][\w \*]*?\b(\w+)\s*\([^;]*\)\s*;", text, flags=re.M)
     return sorted(set(n for n in names if n not in ("if", "while")))
@@ -41,6 +42,17 @@ def test_library_exports_every_declared_symbol(fx):
         assert hasattr(lib, n), n
     bound = {s[0] for s in fx.SIGNATURES}
     assert set(declared_functions()) == bound
+
+
+def test_unet_sizes_are_host_only_and_validated(fx):
+    lib = fx.lib()
+    from oracle import unet_ref
+    assert lib.unet_num_params() == unet_ref.num_params()
+    assert lib.unet_workspace_bytes(128, 128, 60, 0) > 0
+    assert lib.unet_workspace_bytes(128, 128, 60, 1) > lib.unet_workspace_bytes(128, 128, 60, 0)
+    for bad in [(126, 128, 60), (128, 128, 62), (0, 4, 4), (4, 4, 2)]:
+        assert lib.unet_workspace_bytes(*bad, 0) == 0
+        assert fx.lib().last_error().decode() != ""
 
 
 def test_binding_struct_matches_header_layout(fx):
