@@ -116,6 +116,23 @@ def run_batch64(prec_name, steps, warmup, tune=True):
             "autotune_half_sweep_us": None if ti is None else [ti.default_us, ti.tuned_us]}
 
 
+def run_learned():
+    """The learned warm start on the 128 x 128 x 64 MFISM stack with the committed trained
+    weights, against plain multigrid on held-out states (both solved to 1e-10): cold starts,
+    gate jumps and the time loop, plus the network's inference rate on the matrix cores."""
+    import numpy as np
+    from paper_2210_15668_amd import ferrox, learn
+    spec = learn.spec_c4()
+    kb, kt = spec.device_range()
+    net = ferrox.UNet(spec.nx, spec.ny, kt - kb)
+    net.set_params(np.load(learn.WEIGHTS))
+    res = learn.evaluate(net, spec, n_cold=8, n_steps=50)
+    res["inference"] = learn.inference_rate(net)
+    net.close()
+    res["workload"] = "MFISM 128x128x64 (metal 2 | FE 24 | SiO2 4 | p-Si 32 | metal 2), held-out seeds >= 10000"
+    return res
+
+
 def cpu_baseline(sample_steps):
     """The oracle, as it stands, on the same z-stack with a 64 x 64 footprint (1/16 of
     the cells): Step 0 untimed, then `sample_steps` timed steps at the same tolerance;
@@ -146,6 +163,7 @@ def main():
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-tune", action="store_true", help="keep the default smoother launch shapes")
+    ap.add_argument("--no-learned", action="store_true")
     ap.add_argument("--batch-steps", type=int, default=100)
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -181,6 +199,7 @@ def main():
                              "gates uniform in [-2, 2] V (seeds 100..163)",
                  "launch": "one launch per kernel for all instances, graph replay", "steps": args.batch_steps,
                  "fp64": b64, "mixed": bmx}
+    learned = None if args.no_learned else run_learned()
     cpu = None if args.no_cpu_baseline else cpu_baseline(args.cpu_sample_steps)
     line = {
         "metric": "TDGL+Poisson steps/s at 1e-10 residual, 256\u00b2\u00d7128 MFISM; plain MG vs learned",
@@ -195,6 +214,7 @@ def main():
                    "last_rel_residual": r64["last_rel_residual"]},
         "mixed_precision": mixed,
         "batch64": batch,
+        "learned": learned,
         "roofline": roofline,
         "cpu_baseline": cpu,
         "paper_context": "paper: ~15x node-by-node GPU vs multicore (4x A100 vs 32 Haswell cores, NERSC); "

@@ -705,7 +705,7 @@ void enqueue_forward(fx_unet *u) {
 // Bias gradient of layer l from its BF16 output gradient Z ([n][cout]).
 void bias_grad(fx_unet *u, int l, const bf16_t *Z, size_t n) {
     const Layer &L = layout().L[l];
-    const int nb = (int)std::min<size_t>(1024, (n + 255) / 256);
+    const int nb = (int)std::min<size_t>(128, (n + 255) / 256);
     hipLaunchKernelGGL(k_colsum, dim3(nb), dim3(256), 0, u->st, Z, L.cout, n, u->part);
     hipLaunchKernelGGL(k_part_sum, dim3(1), dim3(64), 0, u->st, u->part, nb, L.cout, u->grad + L.boff, 0);
 }
@@ -734,7 +734,7 @@ void enqueue_backward(fx_unet *u, const float *tg) {
     hipStream_t st = u->st;
     const UnetLayout &lay = layout();
     const size_t n0 = u->n0, n1 = u->n1, n2 = u->n2;
-    const int nbl = 1024;
+    const int nbl = 256;
     hipLaunchKernelGGL(k_loss, dim3(nbl), dim3(256), 0, st, u->out, tg, u->dout, u->dpart, n0);
     hipLaunchKernelGGL(k_sum_d, dim3(1), dim3(64), 0, st, u->dpart, nbl, 1.0 / (double)n0, u->dscal);
     // head

@@ -3,8 +3,8 @@
 Run on the GPU host from the repository root (each rocprofv3 call on its own):
 
   rocprofv3 --kernel-trace --stats -d OUT/trace -o run -- python3 bench.py
-  rocprofv3 --pmc FETCH_SIZE -d OUT/fetch -o run -- python3 bench.py --steps 20 --no-mixed --no-batch --no-cpu-baseline
-  rocprofv3 --pmc WRITE_SIZE -d OUT/write -o run -- python3 bench.py --steps 20 --no-mixed --no-batch --no-cpu-baseline
+  rocprofv3 --pmc FETCH_SIZE -d OUT/fetch -o run -- python3 bench.py --steps 20 --no-mixed --no-batch --no-learned --no-cpu-baseline
+  rocprofv3 --pmc WRITE_SIZE -d OUT/write -o run -- python3 bench.py --steps 20 --no-mixed --no-batch --no-learned --no-cpu-baseline
   rocprofv3 --pmc FETCH_SIZE -d OUT/cfetch -o run -- python3 -m paper_2210_15668_amd.profiling copy
   rocprofv3 --pmc WRITE_SIZE -d OUT/cwrite -o run -- python3 -m paper_2210_15668_amd.profiling copy
   python3 -m paper_2210_15668_amd.profiling stats OUT/trace
