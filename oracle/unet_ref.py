@@ -155,30 +155,21 @@ def relu(z):
 
 
 # ----------------------------------------------------------------- the network
-# Optional rounding hooks state a reduced-precision evaluation of the same
-# network: `rnd` is applied to every stored activation (each convolution's
-# ReLU output and each pooled tensor), `grnd` to every back-propagated signal
-# entering a convolution's backward pass.  Both default to no rounding.
-def _id(v):
-    return v
-
-
-def forward(theta: np.ndarray, x: np.ndarray, keep: bool = False, rnd=None):
+def forward(theta: np.ndarray, x: np.ndarray, keep: bool = False):
     """Network output (D, H, W) for input x (D, H, W, 16); with keep, also the activations."""
-    rnd = rnd or _id
     p = unpack(theta)
     a = {}
 
     def layer(name, inp):
         W, b = p[name]
-        out = rnd(relu(conv3(inp, W, b)))
+        out = relu(conv3(inp, W, b))
         a[name + ".in"] = inp
         a[name] = out
         return out
 
     s0 = layer("e0b", layer("e0a", x))
-    s1 = layer("e1b", layer("e1a", rnd(pool(s0))))
-    bt = layer("b2b", layer("b2a", rnd(pool(s1))))
+    s1 = layer("e1b", layer("e1a", pool(s0)))
+    bt = layer("b2b", layer("b2a", pool(s1)))
     c1 = np.concatenate([up(bt), s1], axis=3)
     u1 = layer("d1b", layer("d1a", c1))
     c0 = np.concatenate([up(u1), s0], axis=3)
@@ -194,10 +185,9 @@ def loss(theta: np.ndarray, x: np.ndarray, target: np.ndarray) -> float:
     return float(np.mean(d * d))
 
 
-def gradient(theta: np.ndarray, x: np.ndarray, target: np.ndarray, rnd=None, grnd=None):
+def gradient(theta: np.ndarray, x: np.ndarray, target: np.ndarray):
     """(loss, d loss / d theta) by the chain rule through the layers above."""
-    grnd = grnd or _id
-    out, a = forward(theta, x, keep=True, rnd=rnd)
+    out, a = forward(theta, x, keep=True)
     p = unpack(theta)
     g = np.zeros_like(theta)
     gp = unpack(g)
@@ -213,7 +203,7 @@ def gradient(theta: np.ndarray, x: np.ndarray, target: np.ndarray, rnd=None, grn
     def back(name, dy):
         W, _ = p[name]
         gW, gbb = gp[name]
-        dz = grnd(dy * (a[name] > 0))
+        dz = dy * (a[name] > 0)
         dx, dW, db = conv3_backward(a[name + ".in"], W, dz)
         gW += dW
         gbb += db

@@ -25,6 +25,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 #include <string>
@@ -83,39 +84,117 @@ __global__ __launch_bounds__(256) void k_conv3(const bf16_t *__restrict__ X, int
 #pragma unroll
         for (int t = 0; t < NTW; ++t) acc[m][t] = f4{0.f, 0.f, 0.f, 0.f};
     const s4 zero4 = {0, 0, 0, 0};
-    for (int dz = -1; dz <= 1; ++dz)
-        for (int dy = -1; dy <= 1; ++dy)
-            for (int dx = -1; dx <= 1; ++dx) {
-                const int tap = (dz + 1) * 9 + (dy + 1) * 3 + (dx + 1);
-                int nb[NTW];
+    // 16-channel chunks outer, taps inner: the accumulation order of k_conv3s,
+    // so both kernels give bitwise the same result
+    for (int kc = 0; kc < KC; ++kc)
+        for (int dz = -1; dz <= 1; ++dz)
+            for (int dy = -1; dy <= 1; ++dy)
 #pragma unroll
-                for (int t = 0; t < NTW; ++t) {
-                    const int z2 = pz[t] + dz;
-                    int y2 = py[t] + dy, x2 = px[t] + dx;
-                    y2 = y2 < 0 ? y2 + ny : (y2 >= ny ? y2 - ny : y2);
-                    x2 = x2 < 0 ? x2 + nx : (x2 >= nx ? x2 - nx : x2);
-                    nb[t] = (ok[t] && z2 >= 0 && z2 < nz) ? (z2 * ny + y2) * nx + x2 : -1;
-                }
-                const bf16_t *wtap = Wt + (size_t)tap * COUT * CIN;
-#pragma unroll
-                for (int kc = 0; kc < KC; ++kc) {
+                for (int dx = -1; dx <= 1; ++dx) {
+                    const int tap = (dz + 1) * 9 + (dy + 1) * 3 + (dx + 1);
                     s4 b[NTW];
 #pragma unroll
-                    for (int t = 0; t < NTW; ++t)
-                        b[t] = nb[t] >= 0 ? *(const s4 *)(X + (size_t)nb[t] * ldx + kc * 16 + 4 * kq) : zero4;
+                    for (int t = 0; t < NTW; ++t) {
+                        const int z2 = pz[t] + dz;
+                        int y2 = py[t] + dy, x2 = px[t] + dx;
+                        y2 = y2 < 0 ? y2 + ny : (y2 >= ny ? y2 - ny : y2);
+                        x2 = x2 < 0 ? x2 + nx : (x2 >= nx ? x2 - nx : x2);
+                        const int nb = (ok[t] && z2 >= 0 && z2 < nz) ? (z2 * ny + y2) * nx + x2 : -1;
+                        b[t] = nb >= 0 ? *(const s4 *)(X + (size_t)nb * ldx + kc * 16 + 4 * kq) : zero4;
+                    }
+                    const bf16_t *wtap = Wt + (size_t)tap * COUT * CIN + kc * 16 + 4 * kq;
 #pragma unroll
                     for (int m = 0; m < MT; ++m) {
-                        const s4 a = *(const s4 *)(wtap + (size_t)(m * 16 + col) * CIN + kc * 16 + 4 * kq);
+                        const s4 a = *(const s4 *)(wtap + (size_t)(m * 16 + col) * CIN);
 #pragma unroll
                         for (int t = 0; t < NTW; ++t)
                             acc[m][t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b[t], acc[m][t], 0, 0, 0);
                     }
                 }
-            }
 #pragma unroll
     for (int t = 0; t < NTW; ++t) {
         if (!ok[t]) continue;
         const size_t v = (size_t)(v0 + 16 * t + col);
+#pragma unroll
+        for (int m = 0; m < MT; ++m) {
+            const int co = m * 16 + 4 * kq;
+            if (OUT == 0) {
+                s4 o;
+#pragma unroll
+                for (int r = 0; r < 4; ++r) o[r] = (short)f2bf(fmaxf(acc[m][t][r] + bias[co + r], 0.f));
+                *(s4 *)((bf16_t *)Yv + v * ldy + co) = o;
+            } else {
+                f4 *dst = (f4 *)((float *)Yv + v * ldy + co);
+                if (OUT == 2) *dst = *dst + acc[m][t];
+                else *dst = acc[m][t];
+            }
+        }
+    }
+}
+
+// The same convolution with the input staged in LDS: a block computes 64
+// consecutive x by 4 rows of one plane (a wave per row, 4 column tiles of 16
+// voxels); for each 16-channel chunk the 3 x 6 x 66 halo tile is loaded once
+// (16-byte loads) and all 27 taps read their B fragments from LDS (each wave
+// reads 512 contiguous bytes per fragment: no bank conflicts).  Needs nx a
+// multiple of 64 and ny a multiple of 4.
+template <int CIN, int COUT, int OUT>
+__global__ __launch_bounds__(256) void k_conv3s(const bf16_t *__restrict__ X, int ldx, const bf16_t *__restrict__ Wt,
+                                                const float *__restrict__ bias, void *Yv, int ldy, int nx, int ny,
+                                                int nz) {
+    constexpr int MT = COUT / 16, KC = CIN / 16, HX = 66, HY = 6;
+    __shared__ bf16_t halo[3 * HY * HX * 16];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int col = lane & 15, kq = lane >> 4;
+    const int ntx = nx >> 6, nty = ny >> 2;
+    const int tx = blockIdx.x % ntx, q0 = blockIdx.x / ntx, ty = q0 % nty, z = q0 / nty;
+    const int x0 = tx * 64, y0 = ty * 4;
+    f4 acc[MT][4];
+#pragma unroll
+    for (int m = 0; m < MT; ++m)
+#pragma unroll
+        for (int t = 0; t < 4; ++t) acc[m][t] = f4{0.f, 0.f, 0.f, 0.f};
+    typedef int i4 __attribute__((ext_vector_type(4)));
+    for (int kc = 0; kc < KC; ++kc) {
+        // stage: 3*6*66 voxels x 32 bytes, 16 bytes per thread and step
+        for (int u = threadIdx.x; u < 3 * HY * HX * 2; u += 256) {
+            const int vi = u >> 1, half = u & 1;
+            const int xx = vi % HX, r = vi / HX, dyh = r % HY, dzh = r / HY;
+            const int z2 = z + dzh - 1;
+            i4 val = {0, 0, 0, 0};
+            if (z2 >= 0 && z2 < nz) {
+                int y2 = y0 + dyh - 1, x2 = x0 + xx - 1;
+                y2 = y2 < 0 ? y2 + ny : (y2 >= ny ? y2 - ny : y2);
+                x2 = x2 < 0 ? x2 + nx : (x2 >= nx ? x2 - nx : x2);
+                val = *(const i4 *)(X + (size_t)((z2 * ny + y2) * nx + x2) * ldx + kc * 16 + half * 8);
+            }
+            *(i4 *)(halo + vi * 16 + half * 8) = val;
+        }
+        __syncthreads();
+        for (int dz = 0; dz < 3; ++dz)
+            for (int dy = 0; dy < 3; ++dy) {
+                const bf16_t *hrow = halo + ((dz * HY + wave + dy) * HX) * 16;
+#pragma unroll
+                for (int dx = 0; dx < 3; ++dx) {
+                    const int tap = dz * 9 + dy * 3 + dx;
+                    s4 b[4];
+#pragma unroll
+                    for (int t = 0; t < 4; ++t) b[t] = *(const s4 *)(hrow + (16 * t + col + dx) * 16 + 4 * kq);
+                    const bf16_t *wtap = Wt + (size_t)tap * COUT * CIN + kc * 16 + 4 * kq;
+#pragma unroll
+                    for (int m = 0; m < MT; ++m) {
+                        const s4 a = *(const s4 *)(wtap + (size_t)(m * 16 + col) * CIN);
+#pragma unroll
+                        for (int t = 0; t < 4; ++t)
+                            acc[m][t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b[t], acc[m][t], 0, 0, 0);
+                    }
+                }
+            }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+        const size_t v = ((size_t)z * ny + y0 + wave) * nx + x0 + 16 * t + col;
 #pragma unroll
         for (int m = 0; m < MT; ++m) {
             const int co = m * 16 + 4 * kq;
@@ -211,71 +290,98 @@ __global__ void k_part_sum(const float *__restrict__ part, int nparts, int m, fl
 }
 
 // ------------------------------------------------------ elementwise parts
-// Average of the 2x2x2 children (low grid nx, ny, nz).
+// One thread per (coarse voxel, group of 4 channels): the 8 children of a
+// coarse voxel (low grid nx, ny, nz) are decoded once and moved as 8-byte
+// (BF16) or 16-byte (FP32) vectors.
+struct Kids {
+    size_t v[8];
+};
+
+__device__ __forceinline__ Kids kids_of(size_t p, int nx, int ny) {
+    const int x = (int)(p % nx), q = (int)(p / nx), y = q % ny, z = q / ny;
+    const size_t NX = 2 * (size_t)nx, NY = 2 * (size_t)ny;
+    Kids k;
+    for (int a = 0; a < 2; ++a)
+        for (int b = 0; b < 2; ++b)
+            for (int d = 0; d < 2; ++d) k.v[a * 4 + b * 2 + d] = ((size_t)(2 * z + a) * NY + 2 * y + b) * NX + 2 * x + d;
+    return k;
+}
+
+// Y[parent][c] = mean of X[children][c].
 __global__ void k_pool(const bf16_t *__restrict__ X, int ldx, bf16_t *__restrict__ Y, int C, int nx, int ny, int nz) {
-    const size_t total = (size_t)nx * ny * nz * C;
+    const int G = C / 4;
+    const size_t total = (size_t)nx * ny * nz * G;
     for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < total; e += (size_t)gridDim.x * blockDim.x) {
-        const int c = (int)(e % C);
-        const size_t v = e / C;
-        const int x = (int)(v % nx), q = (int)(v / nx), y = q % ny, z = q / ny;
-        const int NX = 2 * nx, NY = 2 * ny;
-        float s = 0.f;
-        for (int a = 0; a < 2; ++a)
-            for (int b = 0; b < 2; ++b)
-                for (int d = 0; d < 2; ++d)
-                    s += bf2f(X[(size_t)(((2 * z + a) * NY + 2 * y + b) * NX + 2 * x + d) * ldx + c]);
-        Y[e] = f2bf(s * 0.125f);
+        const int g = (int)(e % G);
+        const size_t p = e / G;
+        const Kids k = kids_of(p, nx, ny);
+        float s[4] = {0.f, 0.f, 0.f, 0.f};
+        for (int q = 0; q < 8; ++q) {
+            const s4 a = *(const s4 *)(X + k.v[q] * ldx + 4 * g);
+            for (int j = 0; j < 4; ++j) s[j] += bf2f((bf16_t)a[j]);
+        }
+        s4 o;
+        for (int j = 0; j < 4; ++j) o[j] = (short)f2bf(s[j] * 0.125f);
+        *(s4 *)(Y + p * C + 4 * g) = o;
     }
 }
 
-// D[child][c] += G[parent][c] / 8 (high grid nx, ny, nz).
-__global__ void k_pool_bwd(const float *__restrict__ G, float *__restrict__ D, int ldd, int C, int nx, int ny, int nz) {
-    const size_t total = (size_t)nx * ny * nz * C;
+// D[children][c] += G[parent][c] / 8.
+__global__ void k_pool_bwd(const float *__restrict__ Gr, float *__restrict__ D, int ldd, int C, int nx, int ny, int nz) {
+    const int G = C / 4;
+    const size_t total = (size_t)nx * ny * nz * G;
     for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < total; e += (size_t)gridDim.x * blockDim.x) {
-        const int c = (int)(e % C);
-        const size_t v = e / C;
-        const int x = (int)(v % nx), q = (int)(v / nx), y = q % ny, z = q / ny;
-        const size_t p = ((size_t)(z / 2) * (ny / 2) + y / 2) * (nx / 2) + x / 2;
-        D[v * ldd + c] += 0.125f * G[p * C + c];
+        const int g = (int)(e % G);
+        const size_t p = e / G;
+        const Kids k = kids_of(p, nx, ny);
+        const f4 a = 0.125f * *(const f4 *)(Gr + p * C + 4 * g);
+        for (int q = 0; q < 8; ++q) {
+            f4 *d = (f4 *)(D + k.v[q] * ldd + 4 * g);
+            *d = *d + a;
+        }
     }
 }
 
-// Y[child] = X[parent] (high grid nx, ny, nz).
+// Y[children][c] = X[parent][c].
 __global__ void k_up(const bf16_t *__restrict__ X, bf16_t *__restrict__ Y, int ldy, int C, int nx, int ny, int nz) {
-    const size_t total = (size_t)nx * ny * nz * C;
+    const int G = C / 4;
+    const size_t total = (size_t)nx * ny * nz * G;
     for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < total; e += (size_t)gridDim.x * blockDim.x) {
-        const int c = (int)(e % C);
-        const size_t v = e / C;
-        const int x = (int)(v % nx), q = (int)(v / nx), y = q % ny, z = q / ny;
-        const size_t p = ((size_t)(z / 2) * (ny / 2) + y / 2) * (nx / 2) + x / 2;
-        Y[v * ldy + c] = X[p * C + c];
+        const int g = (int)(e % G);
+        const size_t p = e / G;
+        const Kids k = kids_of(p, nx, ny);
+        const s4 a = *(const s4 *)(X + p * C + 4 * g);
+        for (int q = 0; q < 8; ++q) *(s4 *)(Y + k.v[q] * ldy + 4 * g) = a;
     }
 }
 
-// D[parent][c] = sum of G[child][c] over the 8 children (low grid nx, ny, nz).
-__global__ void k_up_bwd(const float *__restrict__ G, int ldg, float *__restrict__ D, int C, int nx, int ny, int nz) {
-    const size_t total = (size_t)nx * ny * nz * C;
+// D[parent][c] = sum of G[children][c].
+__global__ void k_up_bwd(const float *__restrict__ Gr, int ldg, float *__restrict__ D, int C, int nx, int ny, int nz) {
+    const int G = C / 4;
+    const size_t total = (size_t)nx * ny * nz * G;
     for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < total; e += (size_t)gridDim.x * blockDim.x) {
-        const int c = (int)(e % C);
-        const size_t v = e / C;
-        const int x = (int)(v % nx), q = (int)(v / nx), y = q % ny, z = q / ny;
-        const int NX = 2 * nx, NY = 2 * ny;
-        float s = 0.f;
-        for (int a = 0; a < 2; ++a)
-            for (int b = 0; b < 2; ++b)
-                for (int d = 0; d < 2; ++d) s += G[(size_t)(((2 * z + a) * NY + 2 * y + b) * NX + 2 * x + d) * ldg + c];
-        D[e] = s;
+        const int g = (int)(e % G);
+        const size_t p = e / G;
+        const Kids k = kids_of(p, nx, ny);
+        f4 s = {0.f, 0.f, 0.f, 0.f};
+        for (int q = 0; q < 8; ++q) s = s + *(const f4 *)(Gr + k.v[q] * ldg + 4 * g);
+        *(f4 *)(D + p * C + 4 * g) = s;
     }
 }
 
 // Z = G * [Y > 0] (gradient through a ReLU whose output is Y), as BF16.
 __global__ void k_mask(const float *__restrict__ G, int ldg, const bf16_t *__restrict__ Y, int ldy,
                        bf16_t *__restrict__ Z, int C, size_t n) {
-    const size_t total = n * C;
+    const int Gq = C / 4;
+    const size_t total = n * Gq;
     for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < total; e += (size_t)gridDim.x * blockDim.x) {
-        const int c = (int)(e % C);
-        const size_t v = e / C;
-        Z[e] = bf2f(Y[v * ldy + c]) > 0.f ? f2bf(G[v * ldg + c]) : (bf16_t)0;
+        const int g = (int)(e % Gq);
+        const size_t v = e / Gq;
+        const f4 gv = *(const f4 *)(G + v * ldg + 4 * g);
+        const s4 y = *(const s4 *)(Y + v * ldy + 4 * g);
+        s4 o;
+        for (int j = 0; j < 4; ++j) o[j] = bf2f((bf16_t)y[j]) > 0.f ? (short)f2bf(gv[j]) : (short)0;
+        *(s4 *)(Z + v * C + 4 * g) = o;
     }
 }
 
@@ -437,7 +543,12 @@ typedef void (*ConvFn)(const bf16_t *, int, const bf16_t *, const float *, void 
 
 template <int CIN, int COUT, int NTW, int OUT>
 void conv_launch(const bf16_t *X, int ldx, const bf16_t *W, const float *b, void *Y, int ldy, int nx, int ny, int nz,
-                 hipStream_t st) {
+                 bool staged, hipStream_t st) {
+    if (staged && nx % 64 == 0 && ny % 4 == 0) {        // LDS-staged input
+        hipLaunchKernelGGL((k_conv3s<CIN, COUT, OUT>), dim3((nx / 64) * (ny / 4) * nz), dim3(256), 0, st, X, ldx, W, b,
+                           Y, ldy, nx, ny, nz);
+        return;
+    }
     const int n = nx * ny * nz, per = 64 * NTW;
     hipLaunchKernelGGL((k_conv3<CIN, COUT, NTW, OUT>), dim3((n + per - 1) / per), dim3(256), 0, st, X, ldx, W, b, Y, ldy,
                        nx, ny, nz);
@@ -449,19 +560,19 @@ void conv_launch(const bf16_t *X, int ldx, const bf16_t *W, const float *b, void
 
 // Convolution dispatch: NTW = 4 on large grids, 1 on small ones (more blocks).
 bool conv_any(int cin, int cout, int out, const bf16_t *X, int ldx, const bf16_t *W, const float *b, void *Y, int ldy,
-              int nx, int ny, int nz, hipStream_t st) {
+              int nx, int ny, int nz, bool staged, hipStream_t st) {
     const bool big = (size_t)nx * ny * nz >= (size_t)256 * 64 * 4;
 #define FX_CONV_CASE(ci, co)                                                                               \
     if (cin == ci && cout == co) {                                                                         \
         if (out == 0) {                                                                                    \
-            if (big) conv_launch<ci, co, 4, 0>(X, ldx, W, b, Y, ldy, nx, ny, nz, st);                       \
-            else conv_launch<ci, co, 1, 0>(X, ldx, W, b, Y, ldy, nx, ny, nz, st);                           \
+            if (big) conv_launch<ci, co, 4, 0>(X, ldx, W, b, Y, ldy, nx, ny, nz, staged, st);                       \
+            else conv_launch<ci, co, 1, 0>(X, ldx, W, b, Y, ldy, nx, ny, nz, staged, st);                           \
         } else if (out == 1) {                                                                             \
-            if (big) conv_launch<ci, co, 4, 1>(X, ldx, W, b, Y, ldy, nx, ny, nz, st);                       \
-            else conv_launch<ci, co, 1, 1>(X, ldx, W, b, Y, ldy, nx, ny, nz, st);                           \
+            if (big) conv_launch<ci, co, 4, 1>(X, ldx, W, b, Y, ldy, nx, ny, nz, staged, st);                       \
+            else conv_launch<ci, co, 1, 1>(X, ldx, W, b, Y, ldy, nx, ny, nz, staged, st);                           \
         } else {                                                                                           \
-            if (big) conv_launch<ci, co, 4, 2>(X, ldx, W, b, Y, ldy, nx, ny, nz, st);                       \
-            else conv_launch<ci, co, 1, 2>(X, ldx, W, b, Y, ldy, nx, ny, nz, st);                           \
+            if (big) conv_launch<ci, co, 4, 2>(X, ldx, W, b, Y, ldy, nx, ny, nz, staged, st);                       \
+            else conv_launch<ci, co, 1, 2>(X, ldx, W, b, Y, ldy, nx, ny, nz, staged, st);                           \
         }                                                                                                  \
         return true;                                                                                       \
     }
@@ -529,6 +640,7 @@ using namespace fx;
 
 struct fx_unet {
     int nx, ny, nz, train;
+    bool staged;                        // LDS-staged convolutions where the x-y extents allow
     hipStream_t st;
     size_t n0, n1, n2;                  // voxels per level
     // parameters and optimiser
@@ -670,7 +782,7 @@ const float *bias_of(const fx_unet *u, int l) { return u->theta + layout().L[l].
 void conv_fwd(fx_unet *u, int l, const bf16_t *X, int ldx, bf16_t *Y, int ldy) {
     const Layer &L = layout().L[l];
     const Dims d = dims_of(u, L.level);
-    conv_any(L.cin, L.cout, 0, X, ldx, wt_of(u, l), bias_of(u, l), Y, ldy, d.nx, d.ny, d.nz, u->st);
+    conv_any(L.cin, L.cout, 0, X, ldx, wt_of(u, l), bias_of(u, l), Y, ldy, d.nx, d.ny, d.nz, u->staged, u->st);
 }
 
 void prep_weights(fx_unet *u) {
@@ -687,16 +799,16 @@ void enqueue_forward(fx_unet *u) {
     hipStream_t st = u->st;
     conv_fwd(u, E0A, u->in, kInC, u->a_e0a, 16);
     conv_fwd(u, E0B, u->a_e0a, 16, u->cat0 + 32, 48);
-    hipLaunchKernelGGL(k_pool, grid_for(u->n1 * 16), dim3(256), 0, st, u->cat0 + 32, 48, u->p0, 16, d1.nx, d1.ny, d1.nz);
+    hipLaunchKernelGGL(k_pool, grid_for(u->n1 * 4), dim3(256), 0, st, u->cat0 + 32, 48, u->p0, 16, d1.nx, d1.ny, d1.nz);
     conv_fwd(u, E1A, u->p0, 16, u->a_e1a, 32);
     conv_fwd(u, E1B, u->a_e1a, 32, u->cat1 + 64, 96);
-    hipLaunchKernelGGL(k_pool, grid_for(u->n2 * 32), dim3(256), 0, st, u->cat1 + 64, 96, u->p1, 32, d2.nx, d2.ny, d2.nz);
+    hipLaunchKernelGGL(k_pool, grid_for(u->n2 * 8), dim3(256), 0, st, u->cat1 + 64, 96, u->p1, 32, d2.nx, d2.ny, d2.nz);
     conv_fwd(u, B2A, u->p1, 32, u->a_b2a, 64);
     conv_fwd(u, B2B, u->a_b2a, 64, u->a_b2b, 64);
-    hipLaunchKernelGGL(k_up, grid_for(u->n1 * 64), dim3(256), 0, st, u->a_b2b, u->cat1, 96, 64, d1.nx, d1.ny, d1.nz);
+    hipLaunchKernelGGL(k_up, grid_for(u->n2 * 16), dim3(256), 0, st, u->a_b2b, u->cat1, 96, 64, d2.nx, d2.ny, d2.nz);
     conv_fwd(u, D1A, u->cat1, 96, u->a_d1a, 32);
     conv_fwd(u, D1B, u->a_d1a, 32, u->a_d1b, 32);
-    hipLaunchKernelGGL(k_up, grid_for(u->n0 * 32), dim3(256), 0, st, u->a_d1b, u->cat0, 48, 32, d0.nx, d0.ny, d0.nz);
+    hipLaunchKernelGGL(k_up, grid_for(u->n1 * 8), dim3(256), 0, st, u->a_d1b, u->cat0, 48, 32, d1.nx, d1.ny, d1.nz);
     conv_fwd(u, D0A, u->cat0, 48, u->a_d0a, 16);
     conv_fwd(u, D0B, u->a_d0a, 16, u->a_d0b, 16);
     hipLaunchKernelGGL(k_head, grid_for(u->n0), dim3(256), 0, st, u->a_d0b, u->theta + layout().head_off, u->out, u->n0);
@@ -721,11 +833,12 @@ void layer_backward(fx_unet *u, int l, const bf16_t *X, int ldx, const bf16_t *Z
     const int m = 27 * L.cin * L.cout;
     hipLaunchKernelGGL(k_part_sum, grid_for(m), dim3(256), 0, u->st, u->part, np, m, u->grad + L.woff, 0);
     bias_grad(u, l, Z, n);
-    if (G) conv_any(L.cout, L.cin, add ? 2 : 1, Z, L.cout, wf_of(u, l), nullptr, G, ldg, d.nx, d.ny, d.nz, u->st);
+    if (G)
+        conv_any(L.cout, L.cin, add ? 2 : 1, Z, L.cout, wf_of(u, l), nullptr, G, ldg, d.nx, d.ny, d.nz, u->staged, u->st);
 }
 
 void mask(fx_unet *u, const float *G, int ldg, const bf16_t *Y, int ldy, bf16_t *Z, int C, size_t n) {
-    hipLaunchKernelGGL(k_mask, grid_for(n * C), dim3(256), 0, u->st, G, ldg, Y, ldy, Z, C, n);
+    hipLaunchKernelGGL(k_mask, grid_for(n * (C / 4)), dim3(256), 0, u->st, G, ldg, Y, ldy, Z, C, n);
 }
 
 // Loss against tg and the full gradient (into u->grad); the loss is left in dscal[0].
@@ -745,27 +858,27 @@ void enqueue_backward(fx_unet *u, const float *tg) {
     layer_backward(u, D0B, u->a_d0a, 16, u->z0, u->g0_16, 16, 0);
     mask(u, u->g0_16, 16, u->a_d0a, 16, u->z0, 16, n0);
     layer_backward(u, D0A, u->cat0, 48, u->z0, u->g0_48, 48, 0);
-    hipLaunchKernelGGL(k_up_bwd, grid_for(n1 * 32), dim3(256), 0, st, u->g0_48, 48, u->g1_32a, 32, d1.nx, d1.ny, d1.nz);
+    hipLaunchKernelGGL(k_up_bwd, grid_for(n1 * 8), dim3(256), 0, st, u->g0_48, 48, u->g1_32a, 32, d1.nx, d1.ny, d1.nz);
     // level 1, up
     mask(u, u->g1_32a, 32, u->a_d1b, 32, u->z1, 32, n1);
     layer_backward(u, D1B, u->a_d1a, 32, u->z1, u->g1_32b, 32, 0);
     mask(u, u->g1_32b, 32, u->a_d1a, 32, u->z1, 32, n1);
     layer_backward(u, D1A, u->cat1, 96, u->z1, u->g1_96, 96, 0);
-    hipLaunchKernelGGL(k_up_bwd, grid_for(n2 * 64), dim3(256), 0, st, u->g1_96, 96, u->g2_64a, 64, d2.nx, d2.ny, d2.nz);
+    hipLaunchKernelGGL(k_up_bwd, grid_for(n2 * 16), dim3(256), 0, st, u->g1_96, 96, u->g2_64a, 64, d2.nx, d2.ny, d2.nz);
     // level 2
     mask(u, u->g2_64a, 64, u->a_b2b, 64, u->z2, 64, n2);
     layer_backward(u, B2B, u->a_b2a, 64, u->z2, u->g2_64b, 64, 0);
     mask(u, u->g2_64b, 64, u->a_b2a, 64, u->z2, 64, n2);
     layer_backward(u, B2A, u->p1, 32, u->z2, u->g2_32, 32, 0);
-    hipLaunchKernelGGL(k_pool_bwd, grid_for(n1 * 32), dim3(256), 0, st, u->g2_32, u->g1_96 + 64, 96, 32, d1.nx, d1.ny,
-                       d1.nz);
+    hipLaunchKernelGGL(k_pool_bwd, grid_for(n2 * 8), dim3(256), 0, st, u->g2_32, u->g1_96 + 64, 96, 32, d2.nx, d2.ny,
+                       d2.nz);
     // level 1, down (skip 1 gradient = channels 64..95 of g1_96)
     mask(u, u->g1_96 + 64, 96, u->cat1 + 64, 96, u->z1, 32, n1);
     layer_backward(u, E1B, u->a_e1a, 32, u->z1, u->g1_32b, 32, 0);
     mask(u, u->g1_32b, 32, u->a_e1a, 32, u->z1, 32, n1);
     layer_backward(u, E1A, u->p0, 16, u->z1, u->g1_16, 16, 0);
-    hipLaunchKernelGGL(k_pool_bwd, grid_for(n0 * 16), dim3(256), 0, st, u->g1_16, u->g0_48 + 32, 48, 16, d0.nx, d0.ny,
-                       d0.nz);
+    hipLaunchKernelGGL(k_pool_bwd, grid_for(n1 * 4), dim3(256), 0, st, u->g1_16, u->g0_48 + 32, 48, 16, d1.nx, d1.ny,
+                       d1.nz);
     // level 0, down (skip 0 gradient = channels 32..47 of g0_48)
     mask(u, u->g0_48 + 32, 48, u->cat0 + 32, 48, u->z0, 16, n0);
     layer_backward(u, E0B, u->a_e0a, 16, u->z0, u->g0_16, 16, 0);
@@ -860,6 +973,10 @@ fx_status unet_init(int nx, int ny, int nzd, int train, void *d_ws, size_t ws_by
     u->n1 = u->n0 / 8;
     u->n2 = u->n1 / 8;
     u->st = (hipStream_t)stream;
+    {   // FERROX_UNET_STAGED=0 keeps every convolution on the unstaged kernel (same results)
+        const char *e = getenv("FERROX_UNET_STAGED");
+        u->staged = !(e && *e == '0');
+    }
     const size_t need = carve_unet(u, nullptr);
     if (ws_bytes < need) { delete u; return ufail(FX_ENOMEM, "workspace %zu bytes < %zu needed", ws_bytes, need); }
     carve_unet(u, d_ws);

@@ -149,13 +149,3 @@ def test_pack_and_unpack_round_trip():
     t = U.pack_target(spec, phi, -1.5)
     assert np.allclose(U.unpack_prediction(spec, t, -1.5), phi[kb:kt], rtol=0, atol=1e-14)
 
-
-def test_rounding_hooks_default_to_the_float64_network():
-    theta = U.init_params(21)
-    x = rnd((8, 8, 8, 16), 22)
-    t = rnd((8, 8, 8), 23)
-    L0, g0 = U.gradient(theta, x, t)
-    L1, g1 = U.gradient(theta, x, t, rnd=lambda v: v, grnd=lambda v: v)
-    assert L0 == L1 and np.array_equal(g0, g1)
-    # a rounding hook is applied where stated: rounding activations to integers changes the output
-    assert not np.allclose(U.forward(theta, x, rnd=np.round), U.forward(theta, x))
