@@ -72,6 +72,8 @@ def _load():
         lib.orc_residual_norms.argtypes = [D, dp, dp, dp, dp]
         lib.orc_run.argtypes = [D, dp, dp, ctypes.c_int, ctypes.c_double, dp, ctypes.c_double,
                                 ctypes.c_int, ctypes.POINTER(Info)]
+        lib.orc_run_pc.argtypes = [D, dp, dp, ctypes.c_int, ctypes.c_double, dp, ctypes.c_double,
+                                ctypes.c_int, ctypes.POINTER(Info)]
         _lib = lib
     return _lib
 
@@ -172,8 +174,9 @@ def residual_norms(spec, P: np.ndarray, phi: np.ndarray, v_top: Optional[float] 
 
 def run(spec, P0: np.ndarray, nsteps: int, dt: float, v_sched: Optional[Sequence[float]] = None,
         tol: float = 1e-13, phi0: Optional[np.ndarray] = None, max_newton: int = 200,
-        init: bool = True):
-    """Step 0 (if ``init``) then ``nsteps`` Euler steps; returns (P, phi, Info of the last solve)."""
+        init: bool = True, order: int = 1):
+    """Step 0 (if ``init``) then ``nsteps`` steps of the forward-Euler scheme (order 1) or the
+    predictor-corrector (order 2); returns (P, phi, Info of the last solve)."""
     lib = _load()
     P = np.array(P0, dtype=np.float64, copy=True)
     if init:
@@ -183,7 +186,8 @@ def run(spec, P0: np.ndarray, nsteps: int, dt: float, v_sched: Optional[Sequence
     h = _DescHolder(spec)
     vs = None if v_sched is None else np.ascontiguousarray(v_sched, np.float64)
     info = Info()
-    s = lib.orc_run(h.ref, _ptr(P), _ptr(phi), nsteps, dt, _ptr(vs), tol, max_newton, ctypes.byref(info))
+    fn = lib.orc_run_pc if order == 2 else lib.orc_run
+    s = fn(h.ref, _ptr(P), _ptr(phi), nsteps, dt, _ptr(vs), tol, max_newton, ctypes.byref(info))
     if s:
         raise RuntimeError(f"oracle run failed: status {s}")
     return P, phi, info

@@ -481,3 +481,37 @@ int orc_run(const orc_desc *d_in, double *P, double *phi, int nsteps, double dt,
     free(Pn);
     return s;
 }
+
+/*
+ * Second-order time loop, the predictor-corrector of the Numerical Approach:
+ *   predictor  P* = P^n + dt f(P^n, phi^n)                         (Step 1a)
+ *              phi* solved for P*, warm-started from phi^n          (Step 1b)
+ *   corrector  P^{n+1} = P^n + dt/2 f(P^n, phi^n) + dt/2 f(P*, phi*) (Step 2a)
+ *              phi^{n+1} solved for P^{n+1}, warm-started from phi* (Step 2b)
+ * with the gate v_sched[n] (or d->v_top) for both solves of step n.
+ */
+int orc_run_pc(const orc_desc *d_in, double *P, double *phi, int nsteps, double dt,
+               const double *v_sched, double tol, int max_newton, orc_info *last)
+{
+    orc_desc d = *d_in;
+    size_t n = (size_t)d.nx * d.ny * d.nz;
+    double *f0 = calloc(n, sizeof(double)), *f1 = calloc(n, sizeof(double));
+    double *Ps = calloc(n, sizeof(double));
+    int s = 0;
+    for (int step = 0; step < nsteps && !s; step++) {
+        if (v_sched) d.v_top = v_sched[step];
+        s = orc_tdgl_rhs(&d, P, phi, f0);
+        if (s) break;
+        for (size_t c = 0; c < n; c++) Ps[c] = P[c] + dt * f0[c];
+        s = orc_solve(&d, Ps, phi, tol, max_newton, last);          /* phi := phi* */
+        if (s) break;
+        s = orc_tdgl_rhs(&d, Ps, phi, f1);
+        if (s) break;
+        for (size_t c = 0; c < n; c++) P[c] = P[c] + 0.5 * dt * f0[c] + 0.5 * dt * f1[c];
+        s = orc_solve(&d, P, phi, tol, max_newton, last);           /* phi := phi^{n+1} */
+    }
+    free(f0);
+    free(f1);
+    free(Ps);
+    return s;
+}

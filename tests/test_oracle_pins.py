@@ -68,6 +68,45 @@ def test_T1b_scalar_euler_recursion(orc):
     assert np.allclose(P[f0:f1], p, rtol=1e-14, atol=0)
 
 
+def test_T1c_time_order_of_euler_and_predictor_corrector(orc):
+    """Uniform P with phi = 0 follows the scalar Landau ODE dP/dt = -Gamma (a P + b P^3 + g P^5).
+    Against scipy's solution (rtol 1e-12), halving dt divides the error at t = 4 ps by 2 for
+    the forward-Euler scheme and by 4 for the predictor-corrector (Numerical Approach): the
+    convergence orders 1 and 2 the paper states (Table 2)."""
+    from scipy.integrate import solve_ivp
+    spec = one_d([(W.FE, 5, W.EPS_FE, 0.0)], v_top=0.0)
+    f0, f1 = spec.fe_range()
+    p0, T = 0.05, 4e-12
+    rate = lambda t, p: -W.MOBILITY * (W.ALPHA * p + W.BETA * p ** 3 + W.GAMMA_L * p ** 5)
+    exact = solve_ivp(rate, (0.0, T), [p0], method="DOP853", rtol=1e-13, atol=1e-16).y[0, -1]
+    for order, ratio in ((1, 2.0), (2, 4.0)):
+        errs = []
+        for dt in (2e-13, 1e-13, 5e-14):
+            P = np.zeros((spec.nz, spec.ny, spec.nx))
+            P[f0:f1] = p0
+            P, phi, _ = orc.run(spec, P, int(round(T / dt)), dt, tol=1e-14, order=order)
+            assert np.abs(phi).max() < 1e-12
+            errs.append(abs(P[f0:f1].mean() - exact))
+        assert errs[0] / errs[1] == pytest.approx(ratio, rel=0.08), (order, errs)
+        assert errs[1] / errs[2] == pytest.approx(ratio, rel=0.04), (order, errs)
+
+
+def test_predictor_corrector_reduces_to_heun_on_the_coupled_stack(orc):
+    """One predictor-corrector step equals its definition built from the oracle's own
+    single-step pieces: two right-hand sides and two solves (Steps 1a, 1b, 2a, 2b)."""
+    spec = W.mfim_small().copy(tol_rel=1e-13)
+    P0 = W.random_P(spec, 3, amp=0.05)
+    phi0, _ = orc.solve(spec, P0, tol=1e-14)
+    dt = 1e-13
+    Ps = P0 + dt * orc.tdgl_rhs(spec, P0, phi0)
+    phis, _ = orc.solve(spec, Ps, phi0, tol=1e-14)
+    P1 = P0 + 0.5 * dt * orc.tdgl_rhs(spec, P0, phi0) + 0.5 * dt * orc.tdgl_rhs(spec, Ps, phis)
+    phi1, _ = orc.solve(spec, P1, phis, tol=1e-14)
+    P, phi, _ = orc.run(spec, P0, 1, dt, tol=1e-14, phi0=phi0, init=False, order=2)
+    assert np.allclose(P, P1, rtol=0, atol=1e-15)
+    assert np.allclose(phi, phi1, rtol=1e-12, atol=1e-14)
+
+
 def _dzz_from_rhs(orc, spec, P):
     """Recover g11 * Dzz from f(P, 0) with the Landau terms switched off."""
     s = spec.copy(alpha=0.0, beta=0.0, gamma=0.0)
