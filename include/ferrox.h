@@ -101,6 +101,10 @@ typedef struct {
                                     extrapolation in time through phi^n and the previous
                                     warm_start levels (0: phi^n itself, as in Step 1b;
                                     1: 2 phi^n - phi^{n-1}; 2: quadratic; 3: cubic)      */
+    int time_order;              /* run_steps' time scheme (Numerical Approach): 0 or 1 the
+                                    forward-Euler Steps 1a + 1b; 2 the predictor-corrector
+                                    Steps 1a, 1b, 2a, 2b (two solves per step; the
+                                    corrector's solve starts from the predictor's phi)   */
 } fx_stack_desc;
 
 typedef struct {

@@ -50,6 +50,8 @@ struct InstState {
     int step, target, sched_base, sched_len;
     int pcur;                         // P buffer holding the current P
     int ts;                           // the running solve belongs to a time step
+    int phase;                        // second-order steps: 0 predictor (or Euler), 1 corrector
+    int corr;                         // runs the corrector update in this advance slot
     int fresh;                        // solve started in this slot (first residual pending)
     int insolve;                      // a solve is running or awaits finalization
     int adv;                          // starts a time step in this advance slot
@@ -91,6 +93,7 @@ struct Inst {
     int nx, ny, nz, kb, nzd, f0, f1;   // full grid, device slab [kb, kb+nzd), ferroelectric [f0, f1)
     int nlev, lc, fold;                // levels; first level of the coarse kernel; update folded into smoothing
     int max_cycles, warm;
+    int order2;                        // predictor-corrector time steps
     double tol2;
     // TDGL
     double h, alpha, beta, gamma, g11, g44, Gamma, lambda;
@@ -126,6 +129,9 @@ struct Work {
 // sel = 1 restricts a launch to the instances starting a time step in the
 // current advance slot; sel = 0 covers every instance.
 template <typename T> void launch_tdgl(const Inst<T> *I, const Work &w, int sel, hipStream_t st);
+// corrector of a second-order step, for the instances flagged in this advance slot:
+// P^n := (P^n + P*)/2 + dt/2 f(P*, phi*), in the buffer that holds P^n
+template <typename T> void launch_tdgl_corr(const Inst<T> *I, const Work &w, hipStream_t st);
 template <typename T> void launch_flip(const Inst<T> *I, int ninst, hipStream_t st);
 template <typename T> void launch_begin(const Inst<T> *I, int ninst, int sel, hipStream_t st);
 template <typename T> void launch_extrap(const Inst<T> *I, const Work &w, hipStream_t st);

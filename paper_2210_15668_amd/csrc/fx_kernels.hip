@@ -270,24 +270,12 @@ __device__ __forceinline__ double surface_value(int pbc, double lambda, double h
     return lambda * (9.0 * p0 - p1) / (8.0 * lambda + 3.0 * h);
 }
 
+// The variational force dF/dP of eq. (TDGL2) at cell (i, j, k), c its index;
+// the time derivative is -Gamma times it.
 template <typename T>
-__global__ __launch_bounds__(256) void k_tdgl(const Inst<T> *I, Work w, int sel) {
-    const Blk b = find_block(w);
-    if (!b.ok) return;
-    const Inst<T> &a = I[b.inst];
-    const GState *s = asp<1>(a.st);
-    if (sel && !s->adv) return;
-    const int pcur = s->pcur;
-    const double dt = s->dt;
-    const T3 t = split3(b.t, a.nx, a.ny);
-    const int i = t.tx * BX + threadIdx.x;
-    const int j = t.ty * BY + threadIdx.y;
-    const int k = a.f0 + t.tz;
-    if (i >= a.nx || j >= a.ny) return;
+__device__ __forceinline__ double tdgl_force(const Inst<T> &a, const double FX_AS(1) *P,
+                                             const double FX_AS(1) *phi, int i, int j, int k, size_t c) {
     const size_t nxy = (size_t)a.nx * a.ny;
-    const size_t c = (size_t)k * nxy + (size_t)j * a.nx + i;
-    const double FX_AS(1) *P = asp<1>(a.P[pcur]);
-    const double FX_AS(1) *phi = asp<1>(a.phi[s->cur]);
     const double h = a.h, ih2 = 1.0 / (h * h), i2h = 0.5 / h;
     const double p = P[c];
     const size_t row = c - i;
@@ -309,8 +297,49 @@ __global__ __launch_bounds__(256) void k_tdgl(const Inst<T> *I, Work w, int sel)
     }
     const double p2 = p * p;
     const double landau = p * (a.alpha + p2 * (a.beta + a.gamma * p2));
-    const double dF = landau - a.g44 * (dxx + dyy) - a.g11 * dzz + dphi;
-    asp<1>(a.P[1 - pcur])[c] = p - dt * a.Gamma * dF;
+    return landau - a.g44 * (dxx + dyy) - a.g11 * dzz + dphi;
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_tdgl(const Inst<T> *I, Work w, int sel) {
+    const Blk b = find_block(w);
+    if (!b.ok) return;
+    const Inst<T> &a = I[b.inst];
+    const GState *s = asp<1>(a.st);
+    if (sel && !s->adv) return;
+    const int pcur = s->pcur;
+    const T3 t = split3(b.t, a.nx, a.ny);
+    const int i = t.tx * BX + threadIdx.x;
+    const int j = t.ty * BY + threadIdx.y;
+    const int k = a.f0 + t.tz;
+    if (i >= a.nx || j >= a.ny) return;
+    const size_t c = ((size_t)k * a.ny + j) * a.nx + i;
+    const double FX_AS(1) *P = asp<1>(a.P[pcur]);
+    const double dF = tdgl_force(a, P, asp<1>(a.phi[s->cur]), i, j, k, c);
+    asp<1>(a.P[1 - pcur])[c] = P[c] - s->dt * a.Gamma * dF;
+}
+
+// Corrector (Step 2a): P^{n+1} = P^n + dt/2 f(P^n, phi^n) + dt/2 f(P*, phi*); with
+// P* = P^n + dt f(P^n, phi^n) this is (P^n + P*)/2 + dt/2 f(P*, phi*).  P^n is
+// the other P buffer and is overwritten in place (each cell reads only its own).
+template <typename T>
+__global__ __launch_bounds__(256) void k_tdgl_corr(const Inst<T> *I, Work w) {
+    const Blk b = find_block(w);
+    if (!b.ok) return;
+    const Inst<T> &a = I[b.inst];
+    const GState *s = asp<1>(a.st);
+    if (!s->corr) return;
+    const int pcur = s->pcur;
+    const T3 t = split3(b.t, a.nx, a.ny);
+    const int i = t.tx * BX + threadIdx.x;
+    const int j = t.ty * BY + threadIdx.y;
+    const int k = a.f0 + t.tz;
+    if (i >= a.nx || j >= a.ny) return;
+    const size_t c = ((size_t)k * a.ny + j) * a.nx + i;
+    const double FX_AS(1) *Ps = asp<1>(a.P[pcur]);
+    double FX_AS(1) *Pn = asp<1>(a.P[1 - pcur]);
+    const double dF = tdgl_force(a, Ps, asp<1>(a.phi[s->cur]), i, j, k, c);
+    Pn[c] = 0.5 * (Pn[c] + Ps[c]) - 0.5 * s->dt * a.Gamma * dF;
 }
 
 // ------------------------------------------------------- solve bookkeeping
@@ -336,13 +365,16 @@ __global__ void k_begin(const Inst<T> *I, int ninst, int sel) {
     if (n >= ninst) return;
     const Inst<T> &a = I[n];
     GState *s = asp<1>(a.st);
-    if (sel && !s->adv) return;
+    if (sel && !s->adv && !s->corr) return;
     if (sel) {
         s->pcur ^= 1;
         const int q = s->step - s->sched_base;
-        if (q >= 0 && q < s->sched_len) s->v_top = asp<1>(a.vsched)[q];
+        if (s->adv && q >= 0 && q < s->sched_len) s->v_top = asp<1>(a.vsched)[q];
+    } else {
+        s->phase = 0;
     }
-    const int order = sel ? min(s->hist, a.warm) : 0;
+    // a corrector's solve starts from the predictor's phi (the current iterate)
+    const int order = sel && s->adv ? min(s->hist, a.warm) : 0;
     int oth[2] = {0, 0}, no = 0;
     for (int q = 0; q < kPhiBufs && no < 2; ++q) {
         bool used = q == s->cur;
@@ -400,7 +432,7 @@ __global__ void k_head(const Inst<T> *I, int ninst, int advance) {
     const int n = blockIdx.x * blockDim.x + threadIdx.x;
     if (n >= ninst) return;
     GState *s = asp<1>(I[n].st);
-    int zf = 0;
+    int zf = 0, corr = 0;
     if (s->insolve && s->done != 0) {
         const int c = s->cycles;
         s->solves += 1;
@@ -416,25 +448,39 @@ __global__ void k_head(const Inst<T> *I, int ninst, int advance) {
             s->status = s->done == 1 ? 0 : 4;
             if (s->status != 0) s->failed += 1;
             const bool ok_step = s->ts && s->status == 0;
-            if (ok_step && fin != s->cur) {
-                for (int m = kMaxHist - 1; m > 0; --m) s->prev[m] = s->prev[m - 1];
-                s->prev[0] = s->cur;
-                s->hist = min(s->hist + 1, kMaxHist);
+            if (ok_step && s->phase == 1) {
+                // corrector done: phi^{n+1}; the predictor's phi is dropped, phi^n
+                // stays the newest stored level
+                s->step += 1;
+                s->phase = 0;
+            } else if (ok_step) {
+                // Euler step, or the predictor of a second-order step: phi^n
+                // becomes the newest stored level
+                if (fin != s->cur) {
+                    for (int m = kMaxHist - 1; m > 0; --m) s->prev[m] = s->prev[m - 1];
+                    s->prev[0] = s->cur;
+                    s->hist = min(s->hist + 1, kMaxHist);
+                } else {
+                    s->hist = 0;
+                }
+                if (I[n].order2) { s->phase = 1; corr = 1; }
+                else s->step += 1;
             } else {
                 s->hist = 0;
+                s->phase = 0;
             }
-            if (ok_step) s->step += 1;
             s->cur = fin;
             zf = s->done == 1 && s->zpend;
         }
     }
     s->zero_fix = zf;
     int adv = 0;
-    if (advance && !s->parked && !s->insolve) {
+    if (advance && !s->parked && !s->insolve && !corr) {
         if (s->status != 0 || s->step >= s->target) s->parked = 1;
         else adv = 1;
     }
     s->adv = adv;
+    s->corr = corr;
 }
 
 // f = 0 exactly: N(0) = 0, so phi = 0 is the root (applied in the slot that
@@ -1025,6 +1071,10 @@ template <typename T>
 void launch_tdgl(const Inst<T> *I, const Work &w, int sel, hipStream_t st) {
     FX_LAUNCH(k_tdgl<T>, w, I, w, sel);
 }
+template <typename T>
+void launch_tdgl_corr(const Inst<T> *I, const Work &w, hipStream_t st) {
+    FX_LAUNCH(k_tdgl_corr<T>, w, I, w);
+}
 
 inline dim3 per_inst(int ninst) { return dim3((ninst + 63) / 64); }
 
@@ -1141,6 +1191,7 @@ void launch_fill(double *x, size_t n, double v, hipStream_t st) {
 
 #define FX_INST(T)                                                                                           \
     template void launch_tdgl<T>(const Inst<T> *, const Work &, int, hipStream_t);                           \
+    template void launch_tdgl_corr<T>(const Inst<T> *, const Work &, hipStream_t);                           \
     template void launch_flip<T>(const Inst<T> *, int, hipStream_t);                                        \
     template void launch_begin<T>(const Inst<T> *, int, int, hipStream_t);                                  \
     template void launch_extrap<T>(const Inst<T> *, const Work &, hipStream_t);                              \

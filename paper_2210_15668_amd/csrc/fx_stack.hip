@@ -133,6 +133,7 @@ fx_status validate(const fx_stack_desc *d, Plan *p) {
     if (d->prec != FX_PREC_FP64 && d->prec != FX_PREC_MIXED) return fail(FX_EINVAL, "unknown precision");
     if (!(d->tol_rel > 0) || d->max_cycles < 1) return fail(FX_EINVAL, "tol_rel > 0 and max_cycles >= 1 required");
     if (d->warm_start < 0 || d->warm_start > 3) return fail(FX_EINVAL, "warm_start must be 0..3");
+    if (d->time_order < 0 || d->time_order > 2) return fail(FX_EINVAL, "time_order must be 0, 1 or 2");
     p->nx = d->nx; p->ny = d->ny; p->nz = d->nz;
     p->kb = -1; p->kt = -1; p->f0 = -1; p->f1 = -1; p->sc0 = -1; p->sc1 = -1;
     bool any_sc = false;
@@ -322,6 +323,7 @@ struct Engine {
     std::vector<int> ncol;
     int max_lc = 0, lds_max = 0, max_cycles = 1;
     int any_unfolded = 0;               // some instance forms phi + clip(e) in the residual kernel
+    int any_order2 = 0;                 // some instance takes predictor-corrector steps
     int nu1 = 2, nu2 = 2;
     int k_pred = 4;                     // cycles enqueued before the first check of a plain solve
     int trace = 0;
@@ -396,10 +398,12 @@ void plan_launches(Engine *e) {
     e->max_lc = 0;
     e->max_cycles = 1;
     e->any_unfolded = 0;
+    e->any_order2 = 0;
     for (const InstHost &h : e->in) {
         e->max_lc = std::max(e->max_lc, h.plan.lc);
         e->max_cycles = std::max(e->max_cycles, h.d.max_cycles);
         if (!(h.plan.lv[0].rb && h.plan.lc > 0)) e->any_unfolded = 1;
+        if (h.d.time_order == 2) e->any_order2 = 1;
     }
     e->scfg.assign(e->max_lc, SmoothCfg{6, 1, 0});
     e->ncol.assign(e->max_lc, 2);
@@ -569,6 +573,7 @@ Inst<T> make_inst(const Engine *e, int i) {
     a.fold = p.lv[0].rb && p.lc > 0;
     a.max_cycles = d.max_cycles;
     a.warm = d.warm_start;
+    a.order2 = d.time_order == 2;
     a.tol2 = d.tol_rel * d.tol_rel;
     a.h = d.h; a.alpha = d.alpha; a.beta = d.beta; a.gamma = d.gamma;
     a.g11 = d.g11; a.g44 = d.g44; a.Gamma = d.Gamma; a.lambda = d.lambda; a.pbc = d.pbc;
@@ -731,6 +736,7 @@ void enq_advance(Engine *e) {
     launch_head(I, e->n, 1, e->st);
     launch_zero_fix(I, e->w_ext, e->st);
     launch_tdgl(I, e->w_tdgl, 1, e->st);
+    if (e->any_order2) launch_tdgl_corr(I, e->w_tdgl, e->st);
     launch_begin(I, e->n, 1, e->st);
     launch_extrap(I, e->w_ext, e->st);
     launch_residual(I, e->w_res, 0, 0, e->st);
@@ -826,7 +832,8 @@ fx_status solve_plain_t(Engine *e) {
 
 fx_status solve_plain(Engine *e) { return e->prec == FX_PREC_MIXED ? solve_plain_t<float>(e) : solve_plain_t<double>(e); }
 
-// nsteps time steps of every instance (Step 1a + Step 1b each).  The
+// nsteps time steps of every instance (Steps 1a + 1b each, and 2a + 2b for
+// predictor-corrector instances, whose steps take two solves).  The
 // schedule (host arrays of nsteps gate potentials per instance, or NULL)
 // is staged through the device in chunks; inside a chunk the host only
 // checks, every few units, whether all instances have parked.
@@ -844,7 +851,7 @@ fx_status run_t(Engine *e, int nsteps, double dt, const double *const *sched) {
         }
         launch_run_setup(I, e->n, chunk, sched ? 1 : 0, dt, first, e->st);
         enq_advance<T>(e);
-        long long budget = (long long)chunk * (e->max_cycles + 1) + 1;
+        long long budget = (long long)chunk * (e->any_order2 ? 2 : 1) * (e->max_cycles + 1) + 1;
         int units = std::min(e->ucap, chunk);
         for (;;) {
             if ((st = launch_units<T>(e, units))) return st;
@@ -856,7 +863,9 @@ fx_status run_t(Engine *e, int nsteps, double dt, const double *const *sched) {
                 const InstState &s = e->mir[i];
                 if (s.parked) continue;
                 all = false;
-                rem = std::max(rem, s.target - s.step);
+                const int solves = e->in[i].d.time_order == 2 ? 2 * (s.target - s.step) - s.phase
+                                                              : s.target - s.step;
+                rem = std::max(rem, solves);
             }
             if (all) break;
             if (budget <= 0) return fail(FX_EDEVICE, "time steps did not finish within the cycle budget");

@@ -795,7 +795,7 @@ void prep_weights(fx_unet *u) {
 }
 
 void enqueue_forward(fx_unet *u) {
-    const Dims d0 = dims_of(u, 0), d1 = dims_of(u, 1), d2 = dims_of(u, 2);
+    const Dims d1 = dims_of(u, 1), d2 = dims_of(u, 2);
     hipStream_t st = u->st;
     conv_fwd(u, E0A, u->in, kInC, u->a_e0a, 16);
     conv_fwd(u, E0B, u->a_e0a, 16, u->cat0 + 32, 48);
@@ -843,7 +843,7 @@ void mask(fx_unet *u, const float *G, int ldg, const bf16_t *Y, int ldy, bf16_t 
 
 // Loss against tg and the full gradient (into u->grad); the loss is left in dscal[0].
 void enqueue_backward(fx_unet *u, const float *tg) {
-    const Dims d0 = dims_of(u, 0), d1 = dims_of(u, 1), d2 = dims_of(u, 2);
+    const Dims d1 = dims_of(u, 1), d2 = dims_of(u, 2);
     hipStream_t st = u->st;
     const UnetLayout &lay = layout();
     const size_t n0 = u->n0, n1 = u->n1, n2 = u->n2;

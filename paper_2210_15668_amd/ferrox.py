@@ -46,7 +46,8 @@ class StackDesc(ctypes.Structure):
                 ("ni", ctypes.c_double), ("T", ctypes.c_double),
                 ("v_bottom", ctypes.c_double), ("v_top", ctypes.c_double),
                 ("tol_rel", ctypes.c_double), ("max_cycles", ctypes.c_int),
-                ("prec", ctypes.c_int), ("warm_start", ctypes.c_int)]
+                ("prec", ctypes.c_int), ("warm_start", ctypes.c_int),
+                ("time_order", ctypes.c_int)]
 
 
 class SolveInfo(ctypes.Structure):
@@ -154,7 +155,8 @@ class _DescHolder:
                            dp(self.eps), dp(self.na), dp(self.nd),
                            spec.alpha, spec.beta, spec.gamma, spec.g11, spec.g44, spec.Gamma,
                            spec.pbc, spec.lam, spec.ni, spec.T, spec.v_bottom, spec.v_top,
-                           spec.tol_rel, spec.max_cycles, spec.prec, spec.warm_start)
+                           spec.tol_rel, spec.max_cycles, spec.prec, spec.warm_start,
+                           spec.time_order)
 
 
 def workspace_bytes(spec: W.StackSpec) -> int:

@@ -73,6 +73,7 @@ class StackSpec:
     max_cycles: int = 60
     prec: int = PREC_FP64
     warm_start: int = 3          # extrapolation order of each step's starting iterate
+    time_order: int = 1          # 1 forward Euler, 2 predictor-corrector (two solves per step)
 
     @property
     def ncell(self) -> int:
