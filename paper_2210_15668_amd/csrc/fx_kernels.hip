@@ -373,8 +373,12 @@ __global__ void k_begin(const Inst<T> *I, int ninst, int sel) {
     } else {
         s->phase = 0;
     }
-    // a corrector's solve starts from the predictor's phi (the current iterate)
-    const int order = sel && s->adv ? min(s->hist, a.warm) : 0;
+    // A corrector's solve starts from the predictor's phi*, O(dt^2) away from phi^{n+1},
+    // unless the history through phi^n supports an extrapolation of order >= 2, which is
+    // O(dt^3) away or closer.
+    int order = 0;
+    if (sel && s->adv) order = min(s->hist, a.warm);
+    else if (sel) order = min(s->hist - 1, a.warm) >= 2 ? min(s->hist - 1, a.warm) : 0;
     int oth[2] = {0, 0}, no = 0;
     for (int q = 0; q < kPhiBufs && no < 2; ++q) {
         bool used = q == s->cur;
@@ -406,8 +410,10 @@ __global__ __launch_bounds__(256) void k_extrap(const Inst<T> *I, Work w) {
     if (!s->fresh || order == 0) return;
     const size_t nxy = (size_t)a.nx * a.ny, off = (size_t)a.kb * nxy, n = (size_t)a.nzd * nxy;
     const double FX_AS(1) *in[4];
-    in[0] = asp<1>(a.phi[s->cur]) + off;
-    for (int q = 1; q <= order; ++q) in[q] = asp<1>(a.phi[s->prev[q - 1]]) + off;
+    // newest level phi^n: the current iterate, or for a corrector the last stored level
+    const int sh = s->phase == 1 ? 1 : 0;
+    in[0] = asp<1>(a.phi[sh ? s->prev[0] : s->cur]) + off;
+    for (int q = 1; q <= order; ++q) in[q] = asp<1>(a.phi[s->prev[q - 1 + sh]]) + off;
     double FX_AS(1) *out = asp<1>(a.phi[s->start]) + off;
     const size_t base = (size_t)b.t * kExtrapChunk;
     const int tid = threadIdx.y * BX + threadIdx.x;

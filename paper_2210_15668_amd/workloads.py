@@ -174,6 +174,41 @@ def mfism_medium(prec: int = PREC_FP64) -> StackSpec:
                    v_top=1.0, ni=1.0e16, T=300.0, tol_rel=1e-10, prec=prec)
 
 
+def convergence_mfism(n: int = 128, prec: int = PREC_FP64) -> StackSpec:
+    """The MFISM cube of the paper's convergence study (Methods, numerical validation;
+    Table 2): 32 nm on each side in n^3 cells, the bottom quarter undoped Si, the next
+    quarter SiO2, the upper half ferroelectric; phi = 0 on both z-faces; the lambda = 3 nm
+    surface condition; Table 1's gradient coefficient g11 = g44 = 1e-9 V m^3/C."""
+    if n % 4:
+        raise ValueError("n must be a multiple of 4")
+    q = n // 4
+    return layered(n, n, n, [(FE, 2 * q, EPS_FE, 0.0), (DE, q, EPS_SIO2, 0.0), (SC, q, EPS_SI, 0.0)],
+                   h=32e-9 / n, g11=1.0e-9, g44=1.0e-9, v_top=0.0, v_bottom=0.0,
+                   ni=1.0e16, T=300.0, tol_rel=1e-13, prec=prec)
+
+
+def gaussian_bump_P(spec: StackSpec, amp: float = 0.002, sigma_xy: float = 5e-9,
+                    sigma_z: float = 2e-9, z0: float = 24e-9) -> np.ndarray:
+    """The convergence study's initial P: amp exp(-(x^2 + y^2)/(2 sigma_xy^2)
+    - (z - z0)^2/(2 sigma_z^2)) on the ferroelectric planes, zero elsewhere.  z is the
+    height of the cell centre above the bottom face; x and y are measured from the centre
+    of the periodic footprint."""
+    h = spec.h
+    x = (np.arange(spec.nx) + 0.5) * h - 0.5 * spec.nx * h
+    y = (np.arange(spec.ny) + 0.5) * h - 0.5 * spec.ny * h
+    z = (np.arange(spec.nz) + 0.5) * h
+    P = amp * np.exp(-(x[None, None, :] ** 2 + y[None, :, None] ** 2) / (2 * sigma_xy ** 2)
+                     - (z[:, None, None] - z0) ** 2 / (2 * sigma_z ** 2))
+    f0, f1 = spec.fe_range()
+    P[:f0] = 0.0
+    P[f1:] = 0.0
+    return P
+
+
+CONVERGENCE_DT = (50e-15, 25e-15, 12.5e-15)   # s: coarse, medium, fine time steps
+CONVERGENCE_T_END = 400e-15                    # s
+
+
 def shrink_lateral(spec: StackSpec, nx: int, ny: int) -> StackSpec:
     """Same z-stack on a smaller periodic x-y footprint (for oracle-sized parity cases)."""
     return spec.copy(nx=nx, ny=ny)

@@ -107,6 +107,26 @@ def test_predictor_corrector_reduces_to_heun_on_the_coupled_stack(orc):
     assert np.allclose(phi, phi1, rtol=1e-12, atol=1e-14)
 
 
+def test_T2_convergence_study_rates_of_both_schemes(orc):
+    """Table 2, Tests 1 and 2: the MFISM cube with the Gaussian P bump, refined in time
+    only (50, 25, 12.5 fs to 400 fs); Rate = log2(E_c^m / E_m^f) with E the RMS difference
+    of successive resolutions.  The paper reports rates 1.00 (P) and 1.01 (phi) for the
+    first-order scheme and 2.02 and 2.07 for the second-order scheme; the coupled oracle
+    must show orders 1 and 2 for both fields (here on 32^3 cells, 1 nm, for speed)."""
+    spec = W.convergence_mfism(32)
+    P0 = W.gaussian_bump_P(spec)
+    for order in (1, 2):
+        res = []
+        for dt in W.CONVERGENCE_DT:
+            n = int(round(W.CONVERGENCE_T_END / dt))
+            P, phi, _ = orc.run(spec, P0, n, dt, tol=1e-13, order=order)
+            res.append((P, phi))
+        for f in (0, 1):
+            e_cm = np.sqrt(np.mean((res[1][f] - res[0][f]) ** 2))
+            e_mf = np.sqrt(np.mean((res[2][f] - res[1][f]) ** 2))
+            assert np.log2(e_cm / e_mf) == pytest.approx(order, abs=0.05), (order, f, e_cm, e_mf)
+
+
 def _dzz_from_rhs(orc, spec, P):
     """Recover g11 * Dzz from f(P, 0) with the Landau terms switched off."""
     s = spec.copy(alpha=0.0, beta=0.0, gamma=0.0)
