@@ -74,6 +74,7 @@ def _load():
                                 ctypes.c_int, ctypes.POINTER(Info)]
         lib.orc_run_pc.argtypes = [D, dp, dp, ctypes.c_int, ctypes.c_double, dp, ctypes.c_double,
                                 ctypes.c_int, ctypes.POINTER(Info)]
+        lib.orc_qv.argtypes = [D, dp, dp, dp, dp]
         _lib = lib
     return _lib
 
@@ -170,6 +171,18 @@ def residual_norms(spec, P: np.ndarray, phi: np.ndarray, v_top: Optional[float] 
     if lib.orc_residual_norms(h.ref, _ptr(P), _ptr(phi), ctypes.byref(rn), ctypes.byref(fn)):
         raise ValueError("invalid stack")
     return rn.value, fn.value
+
+
+def qv(spec, P: np.ndarray, phi: np.ndarray):
+    """(Q, V_fe^avg) of the Q-V characteristics for the given fields (see orc_qv)."""
+    lib = _load()
+    h = _DescHolder(spec)
+    Pc = np.ascontiguousarray(P, np.float64)
+    pc = np.ascontiguousarray(phi, np.float64)
+    q, v = ctypes.c_double(), ctypes.c_double()
+    if lib.orc_qv(h.ref, _ptr(Pc), _ptr(pc), ctypes.byref(q), ctypes.byref(v)):
+        raise ValueError("no ferroelectric/dielectric interface")
+    return q.value, v.value
 
 
 def run(spec, P0: np.ndarray, nsteps: int, dt: float, v_sched: Optional[Sequence[float]] = None,

@@ -459,6 +459,50 @@ int orc_residual_norms(const orc_desc *d, const double *P, const double *phi, do
 }
 
 /*
+ * Q and V_fe^avg of the Q-V characteristics (Results, MFIM).
+ *
+ * z_int is the face between the ferroelectric run and a dielectric plane next
+ * to it: the ferroelectric's bottom face if the plane below is dielectric, else
+ * its top face if the plane above is.  Across that face, take the lower cell L
+ * and the upper cell R, each half cell with constant eps and P (z upward,
+ * D_z = -eps dphi/dz + P).  The face potential phi_int and the flux D are the
+ * solution of the two half-cell relations
+ *     D = -eps_L (phi_int - phi_L) / (h/2) + P_L
+ *     D = -eps_R (phi_R - phi_int) / (h/2) + P_R.
+ * In the dielectric half cell P = 0, so D = eps0 eps_DE E_z there, the paper's
+ * integrand.  Q is the lateral mean of -D: the charge density counted from the
+ * gate (top) into the stack, positive for a positive gate over a
+ * series capacitor.  V_fe = v_top - (lateral mean of phi_int).
+ * Returns 2 if the layout is invalid or the ferroelectric has no dielectric
+ * neighbour.
+ */
+int orc_qv(const orc_desc *d, const double *P, const double *phi, double *Q, double *V_fe)
+{
+    int kb, kt, f0, f1, kl, kr;
+    if (find_layout(d, &kb, &kt, &f0, &f1) || f0 < 0) return 2;
+    if (f0 - 1 >= kb && d->mat[f0 - 1] == MAT_DE) { kl = f0 - 1; kr = f0; }
+    else if (f1 < kt && d->mat[f1] == MAT_DE) { kl = f1 - 1; kr = f1; }
+    else return 2;
+    const double eL = EPS0 * d->eps_r[kl], eR = EPS0 * d->eps_r[kr], hh = 0.5 * d->h;
+    double sumD = 0.0, sumphi = 0.0;
+    for (int j = 0; j < d->ny; j++)
+        for (int i = 0; i < d->nx; i++) {
+            const double pL = d->mat[kl] == MAT_FE ? P[IDX(d, i, j, kl)] : 0.0;
+            const double pR = d->mat[kr] == MAT_FE ? P[IDX(d, i, j, kr)] : 0.0;
+            const double phiL = phi[IDX(d, i, j, kl)], phiR = phi[IDX(d, i, j, kr)];
+            /* eliminate D: eps_L (phi_int - phi_L) + eps_R (phi_int - phi_R) = (P_L - P_R) h/2 */
+            const double phi_int = (eL * phiL + eR * phiR + (pL - pR) * hh) / (eL + eR);
+            const double D = -eL * (phi_int - phiL) / hh + pL;
+            sumD += D;
+            sumphi += phi_int;
+        }
+    const double area = (double)d->nx * d->ny;
+    *Q = -sumD / area;
+    *V_fe = d->v_top - sumphi / area;
+    return 0;
+}
+
+/*
  * Time loop: for n = 0..nsteps-1:  P^{n+1} = P^n + dt f(P^n, phi^n) (Step 1a);
  * phi^{n+1} solved for P^{n+1} with gate v_sched[n] (or d->v_top when NULL),
  * warm-started from phi^n (Step 1b).  P and phi are in/out.

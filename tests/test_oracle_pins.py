@@ -127,6 +127,73 @@ def test_T2_convergence_study_rates_of_both_schemes(orc):
             assert np.log2(e_cm / e_mf) == pytest.approx(order, abs=0.05), (order, f, e_cm, e_mf)
 
 
+# ---------------------------------------------------------------- Q-V diagnostics
+
+def _mfim_1d(v_top, eps_de=W.EPS_SIO2, n_fe=12, n_de=5):
+    return one_d([(W.FE, n_fe, W.EPS_FE, 0.0), (W.DE, n_de, eps_de, 0.0)], v_top=v_top)
+
+
+@pytest.mark.parametrize("eps_de", [W.EPS_SIO2, W.EPS_AL2O3])
+def test_qv_of_a_series_capacitor(orc, eps_de):
+    """P = 0: Q = eps0 V / (t_fe/eps_fe + t_de/eps_de) and V_fe = V (t_fe/eps_fe) / (sum)."""
+    spec = _mfim_1d(1.3, eps_de)
+    P = np.zeros((spec.nz, spec.ny, spec.nx))
+    phi, _ = orc.solve(spec, P, tol=1e-14)
+    Q, V = orc.qv(spec, P, phi)
+    t_fe, t_de = 12 * spec.h, 5 * spec.h
+    R = t_fe / W.EPS_FE + t_de / eps_de
+    assert Q == pytest.approx(EPS0 * 1.3 / R, rel=1e-11)
+    assert V == pytest.approx(1.3 * (t_fe / W.EPS_FE) / R, rel=1e-11)
+
+
+def test_qv_of_a_uniform_polarisation_at_zero_bias(orc):
+    """Results, MFIM: at V_app = 0 the ferroelectric sees E_dep = -P / (eps0 (eps_fe +
+    eps_DE t_fe / t_DE)); the dielectric carries E_de = -E_dep t_fe / t_DE, so
+    Q = -eps0 eps_DE E_de and V_fe = -E_dep t_fe."""
+    spec = _mfim_1d(0.0)
+    f0, f1 = spec.fe_range()
+    P = np.zeros((spec.nz, spec.ny, spec.nx))
+    P[f0:f1] = 0.15
+    phi, _ = orc.solve(spec, P, tol=1e-14)
+    Q, V = orc.qv(spec, P, phi)
+    t_fe, t_de = 12 * spec.h, 5 * spec.h
+    E_dep = -0.15 / (EPS0 * (W.EPS_FE + W.EPS_SIO2 * t_fe / t_de))
+    E_de = -E_dep * t_fe / t_de
+    assert Q == pytest.approx(-EPS0 * W.EPS_SIO2 * E_de, rel=1e-11)
+    assert V == pytest.approx(-E_dep * t_fe, rel=1e-11)
+
+
+def test_qv_obeys_gauss_law_in_3d(orc):
+    """Any P in 3D: the dielectric holds no charge and is periodic laterally, so the plane
+    mean of D_z is the same on all its faces (Q is also the back electrode's charge, read
+    off the contact face) and the plane-mean potential is linear across it:
+    V_fe = v_top - v_bottom - Q t_de / (eps0 eps_DE).  Reading the interface face one plane off, or
+    with the wrong half-cell permittivity or polarisation, breaks both."""
+    spec = W.mfim_small().copy(v_top=0.7, v_bottom=0.2)
+    P = W.random_P(spec, 21, amp=0.2)
+    phi, _ = orc.solve(spec, P, tol=1e-14)
+    Q, V = orc.qv(spec, P, phi)
+    kb, _ = spec.device_range()
+    f0, _ = spec.fe_range()
+    assert spec.plane_mat[kb] == W.DE and f0 - kb == 4
+    D_contact = -EPS0 * W.EPS_SIO2 * (phi[kb] - 0.2) / (0.5 * spec.h)
+    assert Q == pytest.approx(-D_contact.mean(), rel=1e-9)
+    t_de = 4 * spec.h
+    assert V == pytest.approx(0.7 - 0.2 - Q * t_de / (EPS0 * W.EPS_SIO2), rel=1e-9)
+    # P-odd and V-odd: (P, V) -> (-P, -V) flips both
+    s2 = spec.copy(v_top=-0.7, v_bottom=-0.2)
+    phi2, _ = orc.solve(s2, -P, tol=1e-14)
+    Q2, V2 = orc.qv(s2, -P, phi2)
+    assert Q2 == pytest.approx(-Q, rel=1e-10) and V2 == pytest.approx(-V, rel=1e-10)
+
+
+def test_qv_needs_a_dielectric_next_to_the_ferroelectric(orc):
+    spec = one_d([(W.FE, 6, W.EPS_FE, 0.0)])
+    P = np.zeros((spec.nz, spec.ny, spec.nx))
+    with pytest.raises(ValueError):
+        orc.qv(spec, P, P)
+
+
 def _dzz_from_rhs(orc, spec, P):
     """Recover g11 * Dzz from f(P, 0) with the Landau terms switched off."""
     s = spec.copy(alpha=0.0, beta=0.0, gamma=0.0)
