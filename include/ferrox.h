@@ -174,6 +174,32 @@ fx_status poisson_solve(fx_stack *s, double v_top, fx_solve_info *info);
 fx_status run_steps(fx_stack *s, int nsteps, double dt, const double *h_v_top_sched,
                     fx_run_info *info);
 
+/*
+ * Q-V characteristics (Results, MFIM: the interface charge density Q and the
+ * average ferroelectric voltage V_fe^avg of the Q-V_fe and Q-V_app curves).
+ * z_int is the face between the ferroelectric and a dielectric plane next to
+ * it: below the ferroelectric if that plane is dielectric, else above it.
+ * With L the plane below and R the plane above that face, D is the face flux
+ * of the Poisson operator, D = -eps0 eps_f (phi_R - phi_L)/h + P_f
+ * (eps_f = 2 eps_L eps_R/(eps_L + eps_R), P_f = (eps_R P_L + eps_L P_R)/
+ * (eps_L + eps_R)), which in the dielectric half cell is eps0 eps_DE E_z;
+ * phi_int is the face value of that half-cell profile.  Then
+ *     Q    = -(lateral mean of D)          [C/m^2]
+ *     V_fe = v_top - (lateral mean of phi_int)   [V]
+ * (z points to the gate, so Q > 0 for a positive gate over a series
+ * capacitor, the first quadrant of the paper's Q-V_app loops).
+ * stack_qv: of the current state (synchronises the stream).  run_steps_qv:
+ * run_steps that also writes Q and V_fe after every completed step n into
+ * h_Q[n], h_V_fe[n] (host arrays of nsteps doubles; entries of steps not
+ * completed are left as they were); the values are reduced on the device
+ * inside the run, two small kernels per step, in a fixed order (repeatable
+ * bit for bit).  Both return FX_EINVAL if the ferroelectric has no
+ * dielectric neighbour.
+ */
+fx_status stack_qv(fx_stack *s, double *h_Q, double *h_V_fe);
+fx_status run_steps_qv(fx_stack *s, int nsteps, double dt, const double *h_v_top_sched, double *h_Q,
+                       double *h_V_fe, fx_run_info *info);
+
 /* Copy the current P, phi or a previous time level of phi (FX_FIELD_*) to /
  * from host memory of nx*ny*nz doubles.  get_field synchronises the stream.
  * set_field of P zeroes entries off ferroelectric planes; set_field of phi
@@ -277,6 +303,14 @@ fx_status init_batch(const fx_stack_desc *descs, int n, double *const *d_P, doub
  * info: NULL or n entries. */
 fx_status run_batch(fx_batch *b, int nsteps, double dt, const double *const *h_v_top_sched,
                     fx_batch_info *info);
+
+/* Q and V_fe as stack_qv / run_steps_qv, per instance: batch_qv fills n
+ * entries (NaN for an instance whose ferroelectric has no dielectric
+ * neighbour); run_batch_qv records into n host arrays h_Q[i], h_V_fe[i] of
+ * nsteps doubles (left as they were for such instances). */
+fx_status batch_qv(fx_batch *b, double *h_Q, double *h_V_fe);
+fx_status run_batch_qv(fx_batch *b, int nsteps, double dt, const double *const *h_v_top_sched,
+                       double *const *h_Q, double *const *h_V_fe, fx_batch_info *info);
 
 /* Copy instance inst's current P, phi or stored level (FX_FIELD_*) to host
  * memory, as get_field. */

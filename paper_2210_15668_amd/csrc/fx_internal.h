@@ -27,6 +27,8 @@ constexpr int kMaxLevels = 24;
 constexpr int kPhiBufs = 6;       // phi^n, up to 3 stored levels, two iterate buffers
 constexpr int kMaxHist = 3;
 constexpr int kCoarseLdsBytes = 64 * 1024;
+constexpr int kQvBlocks = 8;      // blocks per instance of the interface-plane reductions
+constexpr int kRecSteps = 1024;   // recorded steps per instance held on the device
 
 // Mutable per-instance state of the current solve and of the time history.
 // Every instance runs its own state machine, driven by two kinds of slots:
@@ -52,6 +54,7 @@ struct InstState {
     int ts;                           // the running solve belongs to a time step
     int phase;                        // second-order steps: 0 predictor (or Euler), 1 corrector
     int corr;                         // runs the corrector update in this advance slot
+    int stepped;                      // a time step was completed in this advance slot
     int fresh;                        // solve started in this slot (first residual pending)
     int insolve;                      // a solve is running or awaits finalization
     int adv;                          // starts a time step in this advance slot
@@ -106,6 +109,13 @@ struct Inst {
     double *phi[kPhiBufs];
     double *P[2];
     double *part;                      // residual partial sums, 2 per residual tile
+    // Q-V diagnostics: the ferroelectric/dielectric face between planes qv_kl and qv_kl + 1
+    // (qv_kl < 0: none), the ferroelectric on its upper side if qv_fe_up; eps0 eps_r of
+    // both planes; partial sums (2 per block) and the per-step record (Q, V_fe pairs)
+    int qv_kl, qv_fe_up;
+    double qv_el, qv_er;
+    double *qv_part;
+    double *qv_rec;
     InstState *st;
     // multigrid
     LevelArgs<T> lv[kMaxLevels];
@@ -133,6 +143,10 @@ template <typename T> void launch_tdgl(const Inst<T> *I, const Work &w, int sel,
 // P^n := (P^n + P*)/2 + dt/2 f(P*, phi*), in the buffer that holds P^n
 template <typename T> void launch_tdgl_corr(const Inst<T> *I, const Work &w, hipStream_t st);
 template <typename T> void launch_flip(const Inst<T> *I, int ninst, hipStream_t st);
+// Interface charge Q and average ferroelectric voltage V_fe.  record 0: every instance's
+// current state into out[2 i], out[2 i + 1] (NaN without an interface); record 1: the
+// instances that completed a time step in this advance slot, into their per-step record.
+template <typename T> void launch_qv(const Inst<T> *I, int ninst, int record, double *out, hipStream_t st);
 template <typename T> void launch_begin(const Inst<T> *I, int ninst, int sel, hipStream_t st);
 template <typename T> void launch_extrap(const Inst<T> *I, const Work &w, hipStream_t st);
 // after_cycle 0: residual at the starting iterate of freshly begun solves;

@@ -438,7 +438,7 @@ __global__ void k_head(const Inst<T> *I, int ninst, int advance) {
     const int n = blockIdx.x * blockDim.x + threadIdx.x;
     if (n >= ninst) return;
     GState *s = asp<1>(I[n].st);
-    int zf = 0, corr = 0;
+    int zf = 0, corr = 0, stepped = 0;
     if (s->insolve && s->done != 0) {
         const int c = s->cycles;
         s->solves += 1;
@@ -459,6 +459,7 @@ __global__ void k_head(const Inst<T> *I, int ninst, int advance) {
                 // stays the newest stored level
                 s->step += 1;
                 s->phase = 0;
+                stepped = 1;
             } else if (ok_step) {
                 // Euler step, or the predictor of a second-order step: phi^n
                 // becomes the newest stored level
@@ -470,7 +471,7 @@ __global__ void k_head(const Inst<T> *I, int ninst, int advance) {
                     s->hist = 0;
                 }
                 if (I[n].order2) { s->phase = 1; corr = 1; }
-                else s->step += 1;
+                else { s->step += 1; stepped = 1; }
             } else {
                 s->hist = 0;
                 s->phase = 0;
@@ -487,6 +488,82 @@ __global__ void k_head(const Inst<T> *I, int ninst, int advance) {
     }
     s->adv = adv;
     s->corr = corr;
+    s->stepped = stepped;
+}
+
+// Q-V diagnostics (Results, MFIM).  Across the ferroelectric/dielectric face, with L
+// the lower and R the upper plane, the Poisson operator's flux is
+// D = -eps_f (phi_R - phi_L)/h + P_f (harmonic-mean eps_f, P_f = (eps_R P_L + eps_L P_R)
+// / (eps_L + eps_R)), equal to eps0 eps_DE E_z in the dielectric half cell.  The face
+// potential follows from the lower half cell, D = -eps_L (phi_int - phi_L)/(h/2) + P_L.
+// Each block sums D and phi_int over a strided share of the face (fixed order), then
+// a tree in LDS; the finishing kernel adds the blocks' sums in block order.
+template <typename T>
+__global__ __launch_bounds__(256) void k_qv_part(const Inst<T> *I, int record) {
+    const int inst = blockIdx.x / kQvBlocks, blk = blockIdx.x % kQvBlocks;
+    const Inst<T> &a = I[inst];
+    const GState *s = asp<1>(a.st);
+    if (a.qv_kl < 0 || (record && !s->stepped)) return;
+    const size_t nxy = (size_t)a.nx * a.ny;
+    const double FX_AS(1) *phL = asp<1>(a.phi[s->cur]) + (size_t)a.qv_kl * nxy;
+    const double FX_AS(1) *phR = phL + nxy;
+    const double FX_AS(1) *Pfe = asp<1>(a.P[s->pcur]) + (size_t)(a.qv_kl + a.qv_fe_up) * nxy;
+    const double eL = a.qv_el, eR = a.qv_er, ih = 1.0 / a.h;
+    const double ef = 2.0 * eL * eR / (eL + eR), wL = eR / (eL + eR), wR = eL / (eL + eR);
+    const double hh_eL = 0.5 * a.h / eL;
+    double sd = 0.0, sp = 0.0;
+    for (size_t c = (size_t)blk * 256 + threadIdx.x; c < nxy; c += (size_t)kQvBlocks * 256) {
+        const double p = Pfe[c];
+        const double pL = a.qv_fe_up ? 0.0 : p, pR = a.qv_fe_up ? p : 0.0;
+        const double D = -ef * (phR[c] - phL[c]) * ih + wL * pL + wR * pR;
+        sd += D;
+        sp += phL[c] - (D - pL) * hh_eL;
+    }
+    __shared__ double red[2][256];
+    red[0][threadIdx.x] = sd;
+    red[1][threadIdx.x] = sp;
+    __syncthreads();
+    for (int m = 128; m > 0; m >>= 1) {
+        if ((int)threadIdx.x < m) {
+            red[0][threadIdx.x] += red[0][threadIdx.x + m];
+            red[1][threadIdx.x] += red[1][threadIdx.x + m];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        double FX_AS(1) *o = asp<1>(a.qv_part) + 2 * blk;
+        o[0] = red[0][0];
+        o[1] = red[1][0];
+    }
+}
+
+template <typename T>
+__global__ void k_qv_fin(const Inst<T> *I, int ninst, int record, double *out) {
+    const int n = blockIdx.x * blockDim.x + threadIdx.x;
+    if (n >= ninst) return;
+    const Inst<T> &a = I[n];
+    const GState *s = asp<1>(a.st);
+    if (record && (a.qv_kl < 0 || !s->stepped)) return;
+    double Q = __builtin_nan(""), V = __builtin_nan("");
+    if (a.qv_kl >= 0) {
+        double sd = 0.0, sp = 0.0;
+        const double FX_AS(1) *p = asp<1>(a.qv_part);
+        for (int b = 0; b < kQvBlocks; ++b) { sd += p[2 * b]; sp += p[2 * b + 1]; }
+        const double area = (double)a.nx * a.ny;
+        Q = -sd / area;
+        V = s->v_top - sp / area;
+    }
+    if (record) {
+        const int q = s->step - 1 - s->sched_base;
+        if (q >= 0 && q < kRecSteps) {
+            double FX_AS(1) *r = asp<1>(a.qv_rec) + 2 * q;
+            r[0] = Q;
+            r[1] = V;
+        }
+    } else {
+        asp<1>(out)[2 * n] = Q;
+        asp<1>(out)[2 * n + 1] = V;
+    }
 }
 
 // f = 0 exactly: N(0) = 0, so phi = 0 is the root (applied in the slot that
@@ -1085,6 +1162,12 @@ void launch_tdgl_corr(const Inst<T> *I, const Work &w, hipStream_t st) {
 inline dim3 per_inst(int ninst) { return dim3((ninst + 63) / 64); }
 
 template <typename T>
+void launch_qv(const Inst<T> *I, int ninst, int record, double *out, hipStream_t st) {
+    hipLaunchKernelGGL(k_qv_part<T>, dim3(ninst * kQvBlocks), dim3(256), 0, st, I, record);
+    hipLaunchKernelGGL(k_qv_fin<T>, per_inst(ninst), dim3(64), 0, st, I, ninst, record, out);
+}
+
+template <typename T>
 void launch_flip(const Inst<T> *I, int ninst, hipStream_t st) {
     hipLaunchKernelGGL(k_flip<T>, per_inst(ninst), dim3(64), 0, st, I, ninst);
 }
@@ -1199,6 +1282,7 @@ void launch_fill(double *x, size_t n, double v, hipStream_t st) {
     template void launch_tdgl<T>(const Inst<T> *, const Work &, int, hipStream_t);                           \
     template void launch_tdgl_corr<T>(const Inst<T> *, const Work &, hipStream_t);                           \
     template void launch_flip<T>(const Inst<T> *, int, hipStream_t);                                        \
+    template void launch_qv<T>(const Inst<T> *, int, int, double *, hipStream_t);                            \
     template void launch_begin<T>(const Inst<T> *, int, int, hipStream_t);                                  \
     template void launch_extrap<T>(const Inst<T> *, const Work &, hipStream_t);                              \
     template void launch_residual<T>(const Inst<T> *, const Work &, int, int, hipStream_t);                  \

@@ -294,11 +294,13 @@ struct InstHost {
     std::vector<DevLevel<double>> L64;
     std::vector<DevLevel<float>> L32;
     double *part = nullptr;
+    double *qv_part = nullptr, *qv_rec = nullptr;
     int lds = 0;                        // LDS bytes of this instance's coarse levels
     double filled_top = NAN;            // contact value last written into the caller's top metal planes
 };
 
 constexpr int kSchedChunk = 1024;       // schedule entries per instance held on the device
+static_assert(kRecSteps == kSchedChunk, "the Q-V record covers one schedule chunk");
 constexpr int kProbeMax = 4096;         // timed launches per probe
 constexpr int kMaxBatch = 4096;
 constexpr int kUnitPow = 5;             // captured unit graphs: 1, 2, 4, 8, 16 units
@@ -316,6 +318,9 @@ struct Engine {
     int *prefix_dev = nullptr;
     double *sched_dev = nullptr;        // n x kSchedChunk gate potentials
     double *probe_dev = nullptr;        // kProbeMax byte counters
+    double *qv_out = nullptr;           // n x (Q, V_fe) of the current state
+    int rec = 0;                        // advance slots record Q and V_fe of completed steps
+    int graphs_rec = 0;                 // the captured unit graphs include the recording
     std::vector<int> prefix_host;
     Work w_tdgl{}, w_ext{}, w_res{};
     std::vector<Work> w_sm, w_rs, w_pr;
@@ -466,6 +471,8 @@ size_t carve(Engine *e, void *ws) {
         // residual partial sums: one pair per residual tile
         const size_t nres = (size_t)tiles3(p.nx, p.ny, (p.nzd + kResZ - 1) / kResZ);
         h.part = (double *)cv.take(2 * nres * sizeof(double));
+        h.qv_part = (double *)cv.take(2 * kQvBlocks * sizeof(double));
+        h.qv_rec = (double *)cv.take(2 * (size_t)kRecSteps * sizeof(double));
     }
     const size_t inst_bytes = mixed ? sizeof(Inst<float>) : sizeof(Inst<double>);
     e->inst_dev = cv.take((size_t)e->n * inst_bytes);
@@ -474,6 +481,7 @@ size_t carve(Engine *e, void *ws) {
     e->prefix_dev = (int *)cv.take(ntab * (e->n + 1) * sizeof(int));
     e->sched_dev = (double *)cv.take((size_t)e->n * kSchedChunk * sizeof(double));
     e->probe_dev = (double *)cv.take(kProbeMax * sizeof(double));
+    e->qv_out = (double *)cv.take(2 * (size_t)e->n * sizeof(double));
     return cv.off + 256;
 }
 
@@ -590,6 +598,20 @@ Inst<T> make_inst(const Engine *e, int i) {
     a.P[0] = h.P[0]; a.P[1] = h.P[1];
     a.part = h.part;
     a.st = e->st_dev + i;
+    // the ferroelectric/dielectric face: below the ferroelectric if that plane is
+    // dielectric, else above it
+    a.qv_kl = -1;
+    a.qv_fe_up = 0;
+    if (p.f0 >= 0) {
+        if (p.f0 - 1 >= p.kb && h.mat[p.f0 - 1] == FX_MAT_DE) { a.qv_kl = p.f0 - 1; a.qv_fe_up = 1; }
+        else if (p.f1 < p.kt && h.mat[p.f1] == FX_MAT_DE) { a.qv_kl = p.f1 - 1; a.qv_fe_up = 0; }
+    }
+    if (a.qv_kl >= 0) {
+        a.qv_el = kEps0 * h.eps_r[a.qv_kl];
+        a.qv_er = kEps0 * h.eps_r[a.qv_kl + 1];
+    }
+    a.qv_part = h.qv_part;
+    a.qv_rec = h.qv_rec;
     for (int l = 0; l < a.nlev; ++l) {
         const HostLevel &H = p.lv[l];
         LevelArgs<T> &L = a.lv[l];
@@ -735,6 +757,7 @@ void enq_advance(Engine *e) {
     const Inst<T> *I = idev<T>(e);
     launch_head(I, e->n, 1, e->st);
     launch_zero_fix(I, e->w_ext, e->st);
+    if (e->rec) launch_qv(I, e->n, 1, nullptr, e->st);
     launch_tdgl(I, e->w_tdgl, 1, e->st);
     if (e->any_order2) launch_tdgl_corr(I, e->w_tdgl, e->st);
     launch_begin(I, e->n, 1, e->st);
@@ -752,9 +775,13 @@ void enq_units(Engine *e, int units) {
 }
 
 // Capture the unit sequences as graphs (once; a private stream records them).
+void drop_graphs(Engine *e);
+
 template <typename T>
 fx_status capture_units(Engine *e) {
-    if (e->unit_exec[0]) return FX_OK;
+    if (e->unit_exec[0] && e->graphs_rec == e->rec) return FX_OK;
+    drop_graphs(e);
+    e->graphs_rec = e->rec;
     if (!e->cap) HIP_OK(hipStreamCreateWithFlags(&e->cap, hipStreamNonBlocking));
     hipStream_t user = e->st;
     for (int q = 0; q < kUnitPow; ++q) {
@@ -838,11 +865,20 @@ fx_status solve_plain(Engine *e) { return e->prec == FX_PREC_MIXED ? solve_plain
 // is staged through the device in chunks; inside a chunk the host only
 // checks, every few units, whether all instances have parked.
 template <typename T>
-fx_status run_t(Engine *e, int nsteps, double dt, const double *const *sched) {
+fx_status run_t(Engine *e, int nsteps, double dt, const double *const *sched, double *const *q_out,
+                double *const *v_out) {
     const Inst<T> *I = idev<T>(e);
     fx_status st;
+    e->rec = q_out != nullptr;
+    std::vector<int> step0(e->n);
+    std::vector<double> stage;
     for (int done = 0, first = 1; done < nsteps; first = 0) {
         const int chunk = std::min(kSchedChunk, nsteps - done);
+        if (e->rec)
+            for (int i = 0; i < e->n; ++i) {
+                step0[i] = e->mir[i].step;
+                launch_fill(e->in[i].qv_rec, 2 * (size_t)kRecSteps, NAN, e->st);
+            }
         if (sched) {
             HIP_OK(hipStreamSynchronize(e->st));
             for (int i = 0; i < e->n; ++i)
@@ -871,6 +907,20 @@ fx_status run_t(Engine *e, int nsteps, double dt, const double *const *sched) {
             if (budget <= 0) return fail(FX_EDEVICE, "time steps did not finish within the cycle budget");
             units = std::max(1, std::min(e->ucap, rem));
         }
+        if (e->rec) {
+            stage.resize(2 * (size_t)kRecSteps);
+            for (int i = 0; i < e->n; ++i) {
+                const int got = std::min(e->mir[i].step - step0[i], chunk);
+                if (got <= 0) continue;
+                HIP_OK(hipMemcpyAsync(stage.data(), e->in[i].qv_rec, 2 * (size_t)got * sizeof(double),
+                                      hipMemcpyDeviceToHost, e->st));
+                HIP_OK(hipStreamSynchronize(e->st));
+                for (int q = 0; q < got; ++q) {
+                    q_out[i][done + q] = stage[2 * q];
+                    v_out[i][done + q] = stage[2 * q + 1];
+                }
+            }
+        }
         done += chunk;
         bool any_ok = false;
         for (int i = 0; i < e->n; ++i) any_ok |= e->mir[i].status == FX_OK;
@@ -879,8 +929,31 @@ fx_status run_t(Engine *e, int nsteps, double dt, const double *const *sched) {
     return FX_OK;
 }
 
-fx_status run(Engine *e, int nsteps, double dt, const double *const *sched) {
-    return e->prec == FX_PREC_MIXED ? run_t<float>(e, nsteps, dt, sched) : run_t<double>(e, nsteps, dt, sched);
+fx_status run(Engine *e, int nsteps, double dt, const double *const *sched, double *const *q_out = nullptr,
+              double *const *v_out = nullptr) {
+    return e->prec == FX_PREC_MIXED ? run_t<float>(e, nsteps, dt, sched, q_out, v_out)
+                                    : run_t<double>(e, nsteps, dt, sched, q_out, v_out);
+}
+
+// The ferroelectric has a dielectric plane next to it (the face Q and V_fe are read on).
+bool has_interface(const InstHost &h) {
+    const Plan &p = h.plan;
+    if (p.f0 < 0) return false;
+    return (p.f0 - 1 >= p.kb && h.mat[p.f0 - 1] == FX_MAT_DE) || (p.f1 < p.kt && h.mat[p.f1] == FX_MAT_DE);
+}
+
+// Q and V_fe of every instance's current state into host arrays of n entries.
+fx_status qv_now(Engine *e, double *h_Q, double *h_V) {
+    if (e->prec == FX_PREC_MIXED) launch_qv(idev<float>(e), e->n, 0, e->qv_out, e->st);
+    else launch_qv(idev<double>(e), e->n, 0, e->qv_out, e->st);
+    std::vector<double> b(2 * (size_t)e->n);
+    HIP_OK(hipMemcpyAsync(b.data(), e->qv_out, b.size() * sizeof(double), hipMemcpyDeviceToHost, e->st));
+    HIP_OK(hipStreamSynchronize(e->st));
+    for (int i = 0; i < e->n; ++i) {
+        h_Q[i] = b[2 * i];
+        h_V[i] = b[2 * i + 1];
+    }
+    return FX_OK;
 }
 
 // Write the host mirror of instance i back to the device (stream-ordered).
@@ -1437,13 +1510,15 @@ fx_status poisson_solve(fx_stack *s, double v_top, fx_solve_info *info) {
     return status_message(c, -1);
 }
 
-fx_status run_steps(fx_stack *s, int nsteps, double dt, const double *h_v_top_sched, fx_run_info *info) {
+static fx_status run_steps_impl(fx_stack *s, int nsteps, double dt, const double *h_v_top_sched, double *h_Q,
+                                double *h_V_fe, fx_run_info *info) {
     g_err.clear();
     if (!s) return fail(FX_EINVAL, "stack is NULL");
     if (nsteps < 0 || !(dt > 0)) return fail(FX_EINVAL, "nsteps >= 0 and dt > 0 required");
     Engine *e = &s->e;
     const InstState before = e->mir[0];
-    fx_status st = run(e, nsteps, dt, h_v_top_sched ? &h_v_top_sched : nullptr);
+    fx_status st = run(e, nsteps, dt, h_v_top_sched ? &h_v_top_sched : nullptr, h_Q ? &h_Q : nullptr,
+                       h_V_fe ? &h_V_fe : nullptr);
     if (st) return st;
     const InstState c = e->mir[0];
     fx_run_info ri{};
@@ -1457,6 +1532,25 @@ fx_status run_steps(fx_stack *s, int nsteps, double dt, const double *h_v_top_sc
     st = sync_to_caller(e);
     if (st) return st;
     return nsteps > 0 ? status_message(c, -1) : FX_OK;
+}
+
+fx_status run_steps(fx_stack *s, int nsteps, double dt, const double *h_v_top_sched, fx_run_info *info) {
+    return run_steps_impl(s, nsteps, dt, h_v_top_sched, nullptr, nullptr, info);
+}
+
+fx_status run_steps_qv(fx_stack *s, int nsteps, double dt, const double *h_v_top_sched, double *h_Q,
+                       double *h_V_fe, fx_run_info *info) {
+    if (!h_Q || !h_V_fe) return fail(FX_EINVAL, "Q and V_fe arrays are required");
+    if (s && !has_interface(s->e.in[0]))
+        return fail(FX_EINVAL, "the ferroelectric has no dielectric neighbour");
+    return run_steps_impl(s, nsteps, dt, h_v_top_sched, h_Q, h_V_fe, info);
+}
+
+fx_status stack_qv(fx_stack *s, double *h_Q, double *h_V_fe) {
+    g_err.clear();
+    if (!s || !h_Q || !h_V_fe) return fail(FX_EINVAL, "NULL argument");
+    if (!has_interface(s->e.in[0])) return fail(FX_EINVAL, "the ferroelectric has no dielectric neighbour");
+    return qv_now(&s->e, h_Q, h_V_fe);
 }
 
 fx_status get_field(fx_stack *s, int which, double *h_out) {
@@ -1571,7 +1665,8 @@ fx_status init_batch(const fx_stack_desc *descs, int n, double *const *d_P, doub
     return FX_OK;
 }
 
-fx_status run_batch(fx_batch *b, int nsteps, double dt, const double *const *h_v_top_sched, fx_batch_info *info) {
+static fx_status run_batch_impl(fx_batch *b, int nsteps, double dt, const double *const *h_v_top_sched,
+                                double *const *h_Q, double *const *h_V_fe, fx_batch_info *info) {
     g_err.clear();
     if (!b) return fail(FX_EINVAL, "batch is NULL");
     if (nsteps < 0 || !(dt > 0)) return fail(FX_EINVAL, "nsteps >= 0 and dt > 0 required");
@@ -1579,8 +1674,11 @@ fx_status run_batch(fx_batch *b, int nsteps, double dt, const double *const *h_v
     if (h_v_top_sched)
         for (int i = 0; i < e->n; ++i)
             if (!h_v_top_sched[i]) return fail(FX_EINVAL, "instance %d: schedule is NULL", i);
+    if (h_Q)
+        for (int i = 0; i < e->n; ++i)
+            if (!h_Q[i] || !h_V_fe[i]) return fail(FX_EINVAL, "instance %d: Q or V_fe array is NULL", i);
     std::vector<InstState> before(e->mir, e->mir + e->n);
-    fx_status st = run(e, nsteps, dt, h_v_top_sched);
+    fx_status st = run(e, nsteps, dt, h_v_top_sched, h_Q, h_V_fe);
     if (st) return st;
     if (info)
         for (int i = 0; i < e->n; ++i) {
@@ -1599,6 +1697,22 @@ fx_status run_batch(fx_batch *b, int nsteps, double dt, const double *const *h_v
         for (int i = 0; i < e->n; ++i)
             if (after[i].status != FX_OK) return status_message(after[i], i);
     return FX_OK;
+}
+
+fx_status run_batch(fx_batch *b, int nsteps, double dt, const double *const *h_v_top_sched, fx_batch_info *info) {
+    return run_batch_impl(b, nsteps, dt, h_v_top_sched, nullptr, nullptr, info);
+}
+
+fx_status run_batch_qv(fx_batch *b, int nsteps, double dt, const double *const *h_v_top_sched,
+                       double *const *h_Q, double *const *h_V_fe, fx_batch_info *info) {
+    if (!h_Q || !h_V_fe) return fail(FX_EINVAL, "Q and V_fe arrays are required");
+    return run_batch_impl(b, nsteps, dt, h_v_top_sched, h_Q, h_V_fe, info);
+}
+
+fx_status batch_qv(fx_batch *b, double *h_Q, double *h_V_fe) {
+    g_err.clear();
+    if (!b || !h_Q || !h_V_fe) return fail(FX_EINVAL, "NULL argument");
+    return qv_now(&b->e, h_Q, h_V_fe);
 }
 
 fx_status batch_get_field(fx_batch *b, int inst, int which, double *h_out) {

@@ -80,6 +80,8 @@ SIGNATURES = [
     ("tdgl_step", ctypes.c_int, [_vp, ctypes.c_double]),
     ("poisson_solve", ctypes.c_int, [_vp, ctypes.c_double, ctypes.POINTER(SolveInfo)]),
     ("run_steps", ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_double, _dp, ctypes.POINTER(RunInfo)]),
+    ("run_steps_qv", ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_double, _dp, _dp, _dp, ctypes.POINTER(RunInfo)]),
+    ("stack_qv", ctypes.c_int, [_vp, _dp, _dp]),
     ("get_field", ctypes.c_int, [_vp, ctypes.c_int, _dp]),
     ("set_field", ctypes.c_int, [_vp, ctypes.c_int, _dp]),
     ("stack_probe", ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int, ctypes.c_int]),
@@ -113,6 +115,9 @@ SIGNATURES = [
                                   ctypes.c_size_t, _vp, ctypes.POINTER(_vp)]),
     ("run_batch", ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_double, ctypes.POINTER(_dp),
                                  ctypes.POINTER(BatchInfo)]),
+    ("run_batch_qv", ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_double, ctypes.POINTER(_dp), ctypes.POINTER(_dp),
+                                    ctypes.POINTER(_dp), ctypes.POINTER(BatchInfo)]),
+    ("batch_qv", ctypes.c_int, [_vp, _dp, _dp]),
     ("batch_get_field", ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int, _dp]),
     ("batch_set_launch", ctypes.c_int, [_vp, ctypes.c_int]),
     ("destroy_batch", ctypes.c_int, [_vp]),
@@ -222,6 +227,29 @@ class Stack:
         if check:
             _check(st)
         return info
+
+    def run_steps_qv(self, nsteps: int, dt: float, v_sched: Optional[Sequence[float]] = None,
+                     check: bool = True):
+        """run_steps that also returns Q [C/m^2] and V_fe [V] after every step: (info, Q, V_fe)."""
+        info = RunInfo()
+        vs = None
+        if v_sched is not None:
+            self._vs = np.ascontiguousarray(v_sched, np.float64)
+            assert len(self._vs) >= nsteps
+            vs = self._vs.ctypes.data_as(_dp)
+        q = np.full(nsteps, np.nan)
+        v = np.full(nsteps, np.nan)
+        st = lib().run_steps_qv(self._h, nsteps, dt, vs, q.ctypes.data_as(_dp), v.ctypes.data_as(_dp),
+                                ctypes.byref(info))
+        if check:
+            _check(st)
+        return info, q, v
+
+    def qv(self):
+        """(Q [C/m^2], V_fe [V]) of the current state."""
+        q, v = ctypes.c_double(), ctypes.c_double()
+        _check(lib().stack_qv(self._h, ctypes.byref(q), ctypes.byref(v)))
+        return q.value, v.value
 
     def get(self, which: int) -> np.ndarray:
         out = np.empty((self.spec.nz, self.spec.ny, self.spec.nx), np.float64)
@@ -337,6 +365,30 @@ class Batch:
         if check:
             _check(st)
         return list(info)
+
+    def run_qv(self, nsteps: int, dt: float, v_scheds=None, check: bool = True):
+        """run that also records Q and V_fe after every step: (infos, Q[n][nsteps], V_fe[n][nsteps])."""
+        info = (BatchInfo * self.n)()
+        vs = None
+        if v_scheds is not None:
+            self._vs = [np.ascontiguousarray(v, np.float64) for v in v_scheds]
+            assert len(self._vs) == self.n and all(len(v) >= nsteps for v in self._vs)
+            vs = (_dp * self.n)(*[v.ctypes.data_as(_dp) for v in self._vs])
+        q = [np.full(nsteps, np.nan) for _ in range(self.n)]
+        v = [np.full(nsteps, np.nan) for _ in range(self.n)]
+        pq = (_dp * self.n)(*[a.ctypes.data_as(_dp) for a in q])
+        pv = (_dp * self.n)(*[a.ctypes.data_as(_dp) for a in v])
+        st = lib().run_batch_qv(self._h, nsteps, dt, vs, pq, pv, info)
+        if check:
+            _check(st)
+        return list(info), q, v
+
+    def qv(self):
+        """Arrays (Q, V_fe) of every instance's current state (NaN without an interface)."""
+        q = np.empty(self.n)
+        v = np.empty(self.n)
+        _check(lib().batch_qv(self._h, q.ctypes.data_as(_dp), v.ctypes.data_as(_dp)))
+        return q, v
 
     def get(self, inst: int, which: int) -> np.ndarray:
         sp = self.specs[inst]

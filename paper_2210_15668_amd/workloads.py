@@ -220,6 +220,26 @@ def ramp_schedule(nsteps: int, v_final: float = 1.5, n_ramp: int = 2000) -> np.n
     return v_final * np.minimum(n, n_ramp) / n_ramp
 
 
+def triangle_schedule(nsteps: int, v_max: float, period: int, v0: float = 0.0) -> np.ndarray:
+    """Triangular gate wave for the solves producing phi^n, n = 1..nsteps: from v0 up to
+    v0 + v_max at a quarter period, down to v0 - v_max at three quarters, back at a full
+    period (the Q-V sweeps of the Results section)."""
+    t = (np.arange(1, nsteps + 1, dtype=np.float64) / period) % 1.0
+    w = np.where(t < 0.25, 4 * t, np.where(t < 0.75, 2 - 4 * t, 4 * t - 4))
+    return v0 + v_max * w
+
+
+def mfim_fig3(n_lateral: int = 64, prec: int = PREC_FP64) -> StackSpec:
+    """The 3D MFIM of the Results (Q-V loops): 5 nm ferroelectric over 4 nm Al2O3, 32 nm
+    lateral at h = 0.5 nm (64 x 64 cells; n_lateral shrinks the footprint), one metal plane
+    at each end; Table 1's g11 = g44 = 1e-9 V m^3/C."""
+    return layered(n_lateral, n_lateral, 20, [(FE, 10, EPS_FE, 0.0), (DE, 8, EPS_AL2O3, 0.0)],
+                   g11=1.0e-9, g44=1.0e-9, v_top=0.0, tol_rel=1e-10, prec=prec)
+
+
+DT_TABLE1 = 4.0e-13      # s, Table 1's time step (with g = 1e-9 and h = 0.5 nm)
+
+
 def batch_instances(count: int = 64, seed0: int = 100) -> List[Tuple[StackSpec, np.ndarray]]:
     """Uneven MFIM instances: x,y from {32,48,64,96}, z from {32,48}, FE 16..min(32,nz-4), DE 4.
 
