@@ -123,3 +123,23 @@ def test_records_span_schedule_chunks(fx, orc):
     Qo, Vo = orc.qv(spec.copy(v_top=vs[-1]), s.get(fx.FIELD_P), s.get(fx.FIELD_PHI))
     assert close(Q[-1], Qo) and close(V[-1], Vo)
     assert Q[1023] != Q[1024]
+
+
+def test_double_hysteresis_of_the_mfim(fx):
+    """Results, MFIM (qualitative; the paper's numbers belong to its own sweep rate): the
+    32 nm 3D MFIM relaxed at 0 V into domains and swept by a +-4 V triangle shows the
+    double hysteresis -- one loop in the first quadrant, its mirror in the third, none
+    around the origin -- and a negative dQ/dV_fe in the multidomain state."""
+    from paper_2210_15668_amd import sweep as S
+    spec = W.mfim_fig3()
+    period = 16000
+    r = S.run_sweep(spec, W.random_P(spec, 1, amp=0.01), 3000, 4.0, period)
+    f = S.loop_features(r["v"], r["Q"], r["V_fe"], period)
+    say(f"  {r['steps'] / r['seconds']:.0f} steps/s; {f}")
+    assert f["Q_max"] > 0.05
+    assert 1.0 < f["V_SD"] < 3.5 and f["V_MD"] < f["V_SD"] - 0.5
+    assert f["loop_max_dQ"] > 0.05 * f["Q_max"]
+    assert abs(f["Q_at_0V_up"]) < 0.01 * f["Q_max"]
+    assert f["dQ_dVfe_multidomain"] < 0
+    Q = r["Q"]
+    assert Q[3 * period // 4 - 1] == pytest.approx(-Q[period // 4 - 1], rel=0.05)
