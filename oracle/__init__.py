@@ -45,7 +45,9 @@ class _Desc(ctypes.Structure):
                 ("g11", ctypes.c_double), ("g44", ctypes.c_double), ("Gamma", ctypes.c_double),
                 ("pbc", ctypes.c_int), ("lam", ctypes.c_double),
                 ("ni", ctypes.c_double), ("T", ctypes.c_double),
-                ("v_bottom", ctypes.c_double), ("v_top", ctypes.c_double)]
+                ("v_bottom", ctypes.c_double), ("v_top", ctypes.c_double),
+                ("carriers", ctypes.c_int), ("me", ctypes.c_double), ("mp", ctypes.c_double),
+                ("Eg", ctypes.c_double)]
 
 
 class Info(ctypes.Structure):
@@ -75,6 +77,9 @@ def _load():
         lib.orc_run_pc.argtypes = [D, dp, dp, ctypes.c_int, ctypes.c_double, dp, ctypes.c_double,
                                 ctypes.c_int, ctypes.POINTER(Info)]
         lib.orc_qv.argtypes = [D, dp, dp, dp, dp]
+        lib.orc_fd_half.argtypes = [ctypes.c_double, dp, dp]
+        lib.orc_fd_half.restype = None
+        lib.orc_plane_densities.argtypes = [D, ctypes.c_int, dp, dp]
         _lib = lib
     return _lib
 
@@ -99,7 +104,8 @@ class _DescHolder:
                        _ptr(self.eps), _ptr(self.na), _ptr(self.nd),
                        spec.alpha, spec.beta, spec.gamma, spec.g11, spec.g44, spec.Gamma,
                        spec.pbc, spec.lam, spec.ni, spec.T, spec.v_bottom,
-                       spec.v_top if v_top is None else v_top)
+                       spec.v_top if v_top is None else v_top,
+                       spec.carriers, spec.m_e, spec.m_p, spec.Eg)
 
     @property
     def ref(self):
@@ -171,6 +177,24 @@ def residual_norms(spec, P: np.ndarray, phi: np.ndarray, v_top: Optional[float] 
     if lib.orc_residual_norms(h.ref, _ptr(P), _ptr(phi), ctypes.byref(rn), ctypes.byref(fn)):
         raise ValueError("invalid stack")
     return rn.value, fn.value
+
+
+def fd_half(eta: float):
+    """(F, dF/deta) of the Fermi-Dirac integral of order 1/2 as the oracle evaluates it."""
+    lib = _load()
+    F, dF = ctypes.c_double(), ctypes.c_double()
+    lib.orc_fd_half(float(eta), ctypes.byref(F), ctypes.byref(dF))
+    return F.value, dF.value
+
+
+def plane_densities(spec, k: int):
+    """(p0, n0): the neutral-bulk hole and electron densities of semiconductor plane k."""
+    lib = _load()
+    h = _DescHolder(spec)
+    p0, n0 = ctypes.c_double(), ctypes.c_double()
+    if lib.orc_plane_densities(h.ref, k, ctypes.byref(p0), ctypes.byref(n0)):
+        raise ValueError("not a semiconductor plane")
+    return p0.value, n0.value
 
 
 def qv(spec, P: np.ndarray, phi: np.ndarray):

@@ -71,9 +71,13 @@
 #define Q_E   1.602176634e-19
 #define K_B   1.380649e-23
 #define EPS0  8.8541878128e-12
+#define HBAR  1.054571817e-34
+#define M_E0  9.1093837015e-31
+#define PI    3.14159265358979323846
 
 enum { MAT_METAL = 0, MAT_FE = 1, MAT_DE = 2, MAT_SC = 3 };
 enum { BC_FREE = 0, BC_ZERO = 1, BC_LAMBDA = 2 };
+enum { CARRIERS_BOLTZMANN = 0, CARRIERS_FD = 1 };
 
 typedef struct {
     int nx, ny, nz;
@@ -85,6 +89,9 @@ typedef struct {
     double lambda;
     double ni, T;
     double v_bottom, v_top;
+    int carriers;        /* CARRIERS_BOLTZMANN (densities from ni) or CARRIERS_FD */
+    double me, mp;       /* effective masses / free-electron mass (Fermi-Dirac only) */
+    double Eg;           /* band gap [eV] (Fermi-Dirac only) */
 } orc_desc;
 
 typedef struct {
@@ -185,8 +192,58 @@ typedef struct {
     double *cxy;      /* per plane: eps_k / h^2 */
     double *czm, *czp;/* per plane: face coefficient / h^2 (contact faces 2 eps / h^2) */
     double *p0, *n0;  /* per plane neutral-bulk densities (semiconductor planes) */
+    double *etn, *etp;/* Fermi-Dirac: (E_F - E_c)/kT and (E_v - E_F)/kT at phi = 0 */
+    double Nc, Nv;    /* Fermi-Dirac: effective densities of states */
     double VT;
 } orc_tables;
+
+/*
+ * Fermi-Dirac integral of order 1/2 in the normalisation that tends to e^eta
+ * for eta -> -inf: F(eta) = (2/sqrt(pi)) int_0^inf sqrt(x) / (1 + e^(x - eta)) dx.
+ * Then eq. (ne) reads n_e = Nc F((E_F - E_c)/kT) with Nc = 2 (m kT / (2 pi hbar^2))^(3/2),
+ * and eq. (np) likewise for holes.  As the paper does (Methods, Poisson solve),
+ * F is taken from the closed-form approximation of Bednarczyk and Bednarczyk
+ * (1978):  F(eta) = 1 / (e^-eta + xi),  xi = (3 sqrt(pi) / 4) nu^(-3/8),
+ * nu = eta^4 + 50 + 33.6 eta (1 - 0.68 exp(-0.17 (eta + 1)^2)).
+ * dF is the derivative of that expression, so that the Newton Jacobian is the
+ * derivative of the charge actually used.
+ */
+void orc_fd_half(double eta, double *F, double *dF)
+{
+    const double a = eta + 1.0;
+    const double g = exp(-0.17 * a * a);
+    const double s = 1.0 - 0.68 * g;
+    const double nu = pow(eta, 4.0) + 50.0 + 33.6 * eta * s;
+    const double dnu = 4.0 * pow(eta, 3.0) + 33.6 * s + 33.6 * eta * 0.68 * 0.34 * a * g;
+    const double xi = 0.75 * sqrt(PI) * pow(nu, -0.375);
+    const double dxi = -0.375 * xi * dnu / nu;
+    const double em = exp(-eta);
+    const double D = em + xi;
+    *F = 1.0 / D;
+    *dF = (em - dxi) / (D * D);
+}
+
+static double fd_F(double eta)
+{
+    double F, dF;
+    orc_fd_half(eta, &F, &dF);
+    return F;
+}
+
+/* Fermi-Dirac neutrality at phi = 0: the x = (E_F - E_c)/kT with
+ * Nv F(-x - Eg/kT) - Nc F(x) + Nd - Na = 0 (eq. rho with no field), by
+ * bisection (the left side falls monotonically in x). */
+static double fd_neutral_eta(double Nc, double Nv, double egkt, double Na, double Nd)
+{
+    double lo = -egkt - 100.0, hi = 100.0;
+    for (int it = 0; it < 400; it++) {
+        const double mid = 0.5 * (lo + hi);
+        if (mid <= lo || mid >= hi) break;
+        const double g = Nv * fd_F(-mid - egkt) - Nc * fd_F(mid) + Nd - Na;
+        if (g > 0.0) lo = mid; else hi = mid;
+    }
+    return 0.5 * (lo + hi);
+}
 
 static void neutral_densities(double Na, double Nd, double ni, double *p0, double *n0)
 {
@@ -208,8 +265,12 @@ static int build_tables(const orc_desc *d, orc_tables *t)
     t->eps = calloc(nz, sizeof(double)); t->cxy = calloc(nz, sizeof(double));
     t->czm = calloc(nz, sizeof(double)); t->czp = calloc(nz, sizeof(double));
     t->p0 = calloc(nz, sizeof(double));  t->n0 = calloc(nz, sizeof(double));
+    t->etn = calloc(nz, sizeof(double)); t->etp = calloc(nz, sizeof(double));
     const double h2 = d->h * d->h;
     t->VT = K_B * d->T / Q_E;
+    const double kT = K_B * d->T;
+    t->Nc = 2.0 * pow(d->me * M_E0 * kT / (2.0 * PI * HBAR * HBAR), 1.5);
+    t->Nv = 2.0 * pow(d->mp * M_E0 * kT / (2.0 * PI * HBAR * HBAR), 1.5);
     for (int k = 0; k < nz; k++) t->eps[k] = EPS0 * d->eps_r[k];
     for (int k = t->kb; k < t->kt; k++) {
         t->cxy[k] = t->eps[k] / h2;
@@ -217,7 +278,13 @@ static int build_tables(const orc_desc *d, orc_tables *t)
         else t->czm[k] = 2.0 * t->eps[k - 1] * t->eps[k] / (t->eps[k - 1] + t->eps[k]) / h2;
         if (k == t->kt - 1) t->czp[k] = 2.0 * t->eps[k] / h2;
         else t->czp[k] = 2.0 * t->eps[k] * t->eps[k + 1] / (t->eps[k] + t->eps[k + 1]) / h2;
-        if (d->mat[k] == MAT_SC) neutral_densities(d->Na[k], d->Nd[k], d->ni, &t->p0[k], &t->n0[k]);
+        if (d->mat[k] == MAT_SC && d->carriers == CARRIERS_FD) {
+            const double egkt = d->Eg / t->VT;
+            t->etn[k] = fd_neutral_eta(t->Nc, t->Nv, egkt, d->Na[k], d->Nd[k]);
+            t->etp[k] = -t->etn[k] - egkt;
+        } else if (d->mat[k] == MAT_SC) {
+            neutral_densities(d->Na[k], d->Nd[k], d->ni, &t->p0[k], &t->n0[k]);
+        }
     }
     return 0;
 }
@@ -225,6 +292,7 @@ static int build_tables(const orc_desc *d, orc_tables *t)
 static void free_tables(orc_tables *t)
 {
     free(t->eps); free(t->cxy); free(t->czm); free(t->czp); free(t->p0); free(t->n0);
+    free(t->etn); free(t->etp);
 }
 
 /* Face value of P between planes k (below) and k+1 (above) at (i,j). */
@@ -261,8 +329,35 @@ static void carriers(const orc_desc *d, const orc_tables *t, int k, double phi, 
 {
     if (d->mat[k] != MAT_SC) { *rho = 0.0; *sig = 0.0; return; }
     const double u = phi / t->VT;
+    if (d->carriers == CARRIERS_FD) {
+        /* eq. (rho) with n_e = Nc F(eta_n), n_p = Nv F(eta_p); the potential
+         * lowers the conduction band by e phi: eta_n = eta_n0 + u, eta_p = eta_p0 - u */
+        double Fn, dFn, Fp, dFp;
+        orc_fd_half(t->etn[k] + u, &Fn, &dFn);
+        orc_fd_half(t->etp[k] - u, &Fp, &dFp);
+        *rho = Q_E * (t->Nv * Fp - t->Nc * Fn + d->Nd[k] - d->Na[k]);
+        *sig = Q_E * (t->Nv * dFp + t->Nc * dFn) / t->VT;
+        return;
+    }
     *rho = Q_E * (t->p0[k] * expm1(-u) - t->n0[k] * expm1(u));
     *sig = Q_E * (t->p0[k] * exp(-u) + t->n0[k] * exp(u)) / t->VT;
+}
+
+/* Neutral-bulk carrier densities of plane k as the oracle uses them (for tests). */
+int orc_plane_densities(const orc_desc *d, int k, double *p0, double *n0)
+{
+    orc_tables t;
+    if (build_tables(d, &t)) return 2;
+    if (k < 0 || k >= d->nz || d->mat[k] != MAT_SC) { free_tables(&t); return 2; }
+    if (d->carriers == CARRIERS_FD) {
+        *p0 = t.Nv * fd_F(t.etp[k]);
+        *n0 = t.Nc * fd_F(t.etn[k]);
+    } else {
+        *p0 = t.p0[k];
+        *n0 = t.n0[k];
+    }
+    free_tables(&t);
+    return 0;
 }
 
 /* out = N(phi) = L phi - rho_c(phi) on device cells (Dirichlet neighbours zero). */

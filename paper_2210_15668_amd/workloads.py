@@ -29,6 +29,7 @@ import numpy as np
 METAL, FE, DE, SC = 0, 1, 2, 3
 PBC_FREE, PBC_ZERO, PBC_LAMBDA = 0, 1, 2
 PREC_FP64, PREC_MIXED = 0, 1
+CARRIERS_BOLTZMANN, CARRIERS_FD = 0, 1
 
 # Table 1 of the paper (SI units)
 ALPHA = -2.5e9          # V m / C
@@ -74,6 +75,10 @@ class StackSpec:
     prec: int = PREC_FP64
     warm_start: int = 3          # extrapolation order of each step's starting iterate
     time_order: int = 1          # 1 forward Euler, 2 predictor-corrector (two solves per step)
+    carriers: int = CARRIERS_BOLTZMANN
+    m_e: float = 1.08            # Table 1: effective masses / free-electron mass (Fermi-Dirac)
+    m_p: float = 0.81
+    Eg: float = 1.12             # eV, silicon at 300 K (Fermi-Dirac)
 
     @property
     def ncell(self) -> int:

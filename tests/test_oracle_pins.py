@@ -194,6 +194,110 @@ def test_qv_needs_a_dielectric_next_to_the_ferroelectric(orc):
         orc.qv(spec, P, P)
 
 
+# ---------------------------------------------------------------- Fermi-Dirac carriers
+
+HBAR = 1.054571817e-34
+ME0 = 9.1093837015e-31
+
+
+def _fd_half_exact(eta):
+    """(2/sqrt(pi)) int_0^inf sqrt(x) / (1 + e^(x - eta)) dx by adaptive quadrature."""
+    from scipy.integrate import quad
+    f = lambda x: np.sqrt(x) / (1.0 + np.exp(x - eta)) if x - eta < 700 else 0.0
+    v, _ = quad(f, 0.0, max(eta, 0.0) + 80.0, limit=400, points=[eta] if eta > 0 else None,
+                epsabs=0.0, epsrel=1e-12)
+    return 2.0 / np.sqrt(np.pi) * v
+
+
+def _effective_dos(m, T):
+    """Nc (or Nv) = 2 (m kT / (2 pi hbar^2))^(3/2): eq. (density_state) integrated against the
+    Boltzmann tail."""
+    return 2.0 * (m * ME0 * KB * T / (2.0 * np.pi * HBAR ** 2)) ** 1.5
+
+
+def test_fd_half_within_the_approximations_accuracy(orc):
+    """Methods (Poisson solve): the Fermi-Dirac integral of order 1/2 by Bednarczyk's closed
+    form must stay within that approximation's published accuracy (0.4 %) of the integral
+    itself, tend to e^eta (eq. MaxBolt_ne_np) and to the degenerate limit
+    (4 / (3 sqrt(pi))) eta^(3/2), and its derivative must be the derivative of F."""
+    worst = 0.0
+    for eta in np.linspace(-15.0, 60.0, 76):
+        F, _ = orc.fd_half(eta)
+        worst = max(worst, abs(F / _fd_half_exact(eta) - 1.0))
+    assert worst < 4e-3, worst
+    F, dF = orc.fd_half(-40.0)
+    assert F == pytest.approx(np.exp(-40.0), rel=1e-12) and dF == pytest.approx(np.exp(-40.0), rel=1e-12)
+    F, _ = orc.fd_half(1000.0)
+    assert F == pytest.approx(4.0 / (3.0 * np.sqrt(np.pi)) * 1000.0 ** 1.5, rel=1e-5)
+    for eta in (-8.0, -1.0, 0.0, 2.5, 12.0, 40.0):
+        d = 1e-5
+        fd = (orc.fd_half(eta + d)[0] - orc.fd_half(eta - d)[0]) / (2 * d)
+        assert orc.fd_half(eta)[1] == pytest.approx(fd, rel=1e-7), eta
+
+
+@pytest.mark.parametrize("Na,Nd", [(0.0, 0.0), (1e24, 0.0), (0.0, 1e26)])
+def test_fd_neutral_bulk(orc, Na, Nd):
+    """eq. (rho) at phi = 0: p0 - n0 + Nd - Na = 0.  Undoped, both equal
+    sqrt(Nc Nv) exp(-Eg / 2kT) (Nc, Nv from Table 1's effective masses); n-type 1e26 m^-3
+    is degenerate, so n0 p0 falls below the Boltzmann value Nc Nv exp(-Eg/kT)."""
+    spec = W.layered(1, 1, 6, [(W.SC, 4, W.EPS_SI, Na)], carriers=W.CARRIERS_FD)
+    spec.plane_Nd[1:5] = Nd
+    p0, n0 = orc.plane_densities(spec, 2)
+    Nc, Nv = _effective_dos(spec.m_e, spec.T), _effective_dos(spec.m_p, spec.T)
+    VT = KB * spec.T / QE
+    nv2 = Nc * Nv * np.exp(-spec.Eg / VT)
+    if Na == 0 and Nd == 0:
+        assert p0 == pytest.approx(np.sqrt(nv2), rel=1e-6) and n0 == pytest.approx(np.sqrt(nv2), rel=1e-6)
+    else:
+        assert p0 - n0 + Nd - Na == pytest.approx(0.0, abs=1e-12 * max(Na, Nd))
+        if Nd > 0:
+            assert n0 * p0 < 0.5 * nv2
+        else:
+            assert n0 * p0 == pytest.approx(nv2, rel=0.03)     # p0 = 1e24 is mildly degenerate
+
+
+@pytest.mark.parametrize("vg", [0.2, 0.5, -0.3])
+def test_fd_reduces_to_boltzmann_when_nondegenerate(orc, vg):
+    """1D metal / SiO2 / p-Si (1e21 m^-3) / metal: in depletion every carrier is far from
+    degenerate and the Fermi-Dirac solve equals the Maxwell-Boltzmann one (eq. MaxBolt_ne_np,
+    with ni = sqrt(Nc Nv) exp(-Eg/2kT)); in accumulation the surface holes are degenerate,
+    F(eta) < e^eta packs fewer of them per volt, and the surface potential must be larger."""
+    T = 300.0
+    VT = KB * T / QE
+    ni = np.sqrt(_effective_dos(1.08, T) * _effective_dos(0.81, T)) * np.exp(-1.12 / (2 * VT))
+    h = 0.5e-9
+    nsc, nde = 800, 4
+    spec = W.layered(1, 1, nsc + nde + 2, [(W.DE, nde, W.EPS_SIO2, 0.0), (W.SC, nsc, W.EPS_SI, 1e21)],
+                     h=h, v_top=vg, ni=ni, T=T)
+    P = np.zeros((spec.nz, 1, 1))
+    pb, _ = orc.solve(spec, P, tol=1e-14)
+    pf, _ = orc.solve(spec.copy(carriers=W.CARRIERS_FD), P, tol=1e-14)
+    r = np.linalg.norm(pf - pb) / np.linalg.norm(pb)
+    ks = spec.device_range()[0] + nsc - 1                    # top semiconductor plane
+    if vg > 0:
+        assert r < 1e-6, r
+    else:
+        assert r > 5e-4 and pf[ks, 0, 0] < pb[ks, 0, 0] < 0, (r, pf[ks, 0, 0], pb[ks, 0, 0])
+
+
+def test_fd_newton_jacobian(orc):
+    """With Fermi-Dirac carriers sigma must still be -d rho / d phi (checked by central
+    differences at the root of a 3D MFISM with undoped and doped silicon planes)."""
+    spec = W.layered(2, 2, 14, [(W.FE, 4, W.EPS_FE, 0.0), (W.DE, 2, W.EPS_SIO2, 0.0),
+                                (W.SC, 6, W.EPS_SI, 0.0)], v_top=0.9, carriers=W.CARRIERS_FD)
+    spec.plane_Na[1:4] = 1e25
+    P = W.random_P(spec, 6, amp=0.2)
+    phi, _ = orc.solve(spec, P, tol=1e-14)
+    kb, kt = spec.device_range()
+    f, N0, rho, sig = orc.poisson_parts(spec, P, phi)
+    dv = 1e-7
+    _, _, rp, _ = orc.poisson_parts(spec, P, phi + dv)
+    _, _, rm, _ = orc.poisson_parts(spec, P, phi - dv)
+    sc = spec.plane_mat == W.SC
+    assert np.allclose(-(rp - rm)[sc] / (2 * dv), sig[sc], rtol=1e-6)
+    assert np.abs((f - N0)[kb:kt]).max() <= 1e-12 * np.abs(f[kb:kt]).max()
+
+
 def _dzz_from_rhs(orc, spec, P):
     """Recover g11 * Dzz from f(P, 0) with the Landau terms switched off."""
     s = spec.copy(alpha=0.0, beta=0.0, gamma=0.0)
