@@ -61,6 +61,19 @@ typedef enum {
 
 typedef enum { FX_MAT_METAL = 0, FX_MAT_FE = 1, FX_MAT_DE = 2, FX_MAT_SC = 3 } fx_material;
 
+/* Carrier statistics of semiconductor planes (eq. rho).  Both measure phi
+ * from the neutral bulk of the plane's doping (phi = 0 carries no charge).
+ *  BOLTZMANN: eq. (MaxBolt_ne_np) with the intrinsic density ni:
+ *      n = n0 e^(phi/VT), p = p0 e^(-phi/VT), p0 n0 = ni^2.
+ *  FD: eqs. (FD), (density_state), (ne), (np): n = Nc F(eta_n0 + phi/VT),
+ *      p = Nv F(eta_p0 - phi/VT), Nc = 2 (m_e kT/(2 pi hbar^2))^(3/2) (Nv with
+ *      m_p), eta_n0 + eta_p0 = -Eg/kT and eta_n0 fixed by neutrality at
+ *      phi = 0; F is the Fermi-Dirac integral of order 1/2 (normalised to
+ *      e^eta for eta -> -inf) in the closed-form approximation of Bednarczyk
+ *      and Bednarczyk (1978), as in the paper's Methods (Poisson solve); ni
+ *      is not used. */
+typedef enum { FX_CARRIERS_BOLTZMANN = 0, FX_CARRIERS_FD = 1 } fx_carriers;
+
 /* Polarisation surface condition at both ferroelectric faces, eqs. (Pbc),
  * (PbcFree), (PbcDir): lambda dP/dn + P = 0 with outward normal n. */
 typedef enum { FX_PBC_FREE = 0, FX_PBC_ZERO = 1, FX_PBC_LAMBDA = 2 } fx_pbc;
@@ -105,6 +118,10 @@ typedef struct {
                                     forward-Euler Steps 1a + 1b; 2 the predictor-corrector
                                     Steps 1a, 1b, 2a, 2b (two solves per step; the
                                     corrector's solve starts from the predictor's phi)   */
+    int carriers;                /* fx_carriers: semiconductor carrier statistics           */
+    double m_e, m_p;             /* effective masses / free-electron mass (FX_CARRIERS_FD;
+                                    Table 1: 1.08 and 0.81)                                 */
+    double Eg;                   /* band gap [eV] (FX_CARRIERS_FD)                          */
 } fx_stack_desc;
 
 typedef struct {

@@ -19,6 +19,28 @@ namespace fx {
 constexpr double kQe = 1.602176634e-19;
 constexpr double kKb = 1.380649e-23;
 constexpr double kEps0 = 8.8541878128e-12;
+constexpr double kHbar = 1.054571817e-34;
+constexpr double kMe0 = 9.1093837015e-31;
+
+// Fermi-Dirac integral of order 1/2, normalised to e^eta for eta -> -inf, in the
+// closed form of Bednarczyk and Bednarczyk (1978): F = 1/(e^-eta + xi),
+// xi = (3 sqrt(pi)/4) nu^(-3/8), nu = eta^4 + 50 + 33.6 eta (1 - 0.68 e^(-0.17 (eta+1)^2)),
+// and dF/deta of that expression (written so that nothing overflows for eta >= -700).
+__host__ __device__ inline void fd_half(double eta, double &F, double &dF) {
+    eta = fmax(eta, -700.0);
+    const double a = eta + 1.0;
+    const double g = exp(-0.17 * a * a);
+    const double s = 1.0 - 0.68 * g;
+    const double e2 = eta * eta;
+    const double nu = e2 * e2 + 50.0 + 33.6 * eta * s;
+    const double dnu = 4.0 * e2 * eta + 33.6 * s + 7.76832 * eta * a * g;
+    const double xi = 1.329340388179137 * exp(-0.375 * log(nu));
+    const double dxi = -0.375 * xi * dnu / nu;
+    const double em = exp(-eta);
+    const double f = 1.0 / (em + xi);
+    F = f;
+    dF = (em * f - dxi * f) * f;
+}
 
 // Per-plane flag bits of the finest (device) level.
 enum : int { PF_SC = 1, PF_P = 2 };
@@ -104,6 +126,10 @@ struct Inst {
     // residual (scaled by s = h^2/eps0)
     double v_b, p_scale, rho_scale, vt_inv, sig_scale, dmax;
     const double *cxy0, *czm0, *czp0, *wl, *wr, *p0e, *n0e;
+    // Fermi-Dirac carriers (fd): p0e, n0e hold e Nv, e Nc; fdt holds per plane
+    // eta_p0, eta_n0, F(eta_p0), F(eta_n0)
+    int fd;
+    const double *fdt;
     const int *pflags;
     const double *vsched;              // gate potentials of the run's steps (sched_len entries)
     double *phi[kPhiBufs];

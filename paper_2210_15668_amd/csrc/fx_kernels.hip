@@ -681,10 +681,20 @@ __device__ __forceinline__ void residual_body(const Inst<T> &a, const GState *s,
             if (MODE == 2) phi_out[cl] = v0;
             if (fl & PF_SC) {
                 const double u = v0 * a.vt_inv;
-                const double em = expm1(-u), ep = expm1(u);
                 const double p0e = p0ev[k], n0e = n0ev[k];
-                res += (p0e * em - n0e * ep) * a.rho_scale;                       // + rho_c
-                L.sig[sidx(L, i, j, k)] = (T)((p0e * (1.0 + em) + n0e * (1.0 + ep)) * a.sig_scale);
+                if (a.fd) {
+                    // differences from the neutral state: rho_c(0) = 0 exactly
+                    const double FX_AS(1) *ft = asp<1>(a.fdt) + 4 * k;
+                    double Fp, dFp, Fn, dFn;
+                    fd_half(ft[0] - u, Fp, dFp);
+                    fd_half(ft[1] + u, Fn, dFn);
+                    res += (p0e * (Fp - ft[2]) - n0e * (Fn - ft[3])) * a.rho_scale;
+                    L.sig[sidx(L, i, j, k)] = (T)((p0e * dFp + n0e * dFn) * a.sig_scale);
+                } else {
+                    const double em = expm1(-u), ep = expm1(u);
+                    res += (p0e * em - n0e * ep) * a.rho_scale;                   // + rho_c
+                    L.sig[sidx(L, i, j, k)] = (T)((p0e * (1.0 + em) + n0e * (1.0 + ep)) * a.sig_scale);
+                }
             }
             L.r[cidx(L, i, j, k)] = (T)res;
             rr += res * res;

@@ -134,6 +134,10 @@ fx_status validate(const fx_stack_desc *d, Plan *p) {
     if (!(d->tol_rel > 0) || d->max_cycles < 1) return fail(FX_EINVAL, "tol_rel > 0 and max_cycles >= 1 required");
     if (d->warm_start < 0 || d->warm_start > 3) return fail(FX_EINVAL, "warm_start must be 0..3");
     if (d->time_order < 0 || d->time_order > 2) return fail(FX_EINVAL, "time_order must be 0, 1 or 2");
+    if (d->carriers != FX_CARRIERS_BOLTZMANN && d->carriers != FX_CARRIERS_FD)
+        return fail(FX_EINVAL, "carriers must be FX_CARRIERS_BOLTZMANN or FX_CARRIERS_FD");
+    if (d->carriers == FX_CARRIERS_FD && !(d->m_e > 0 && d->m_p > 0 && d->Eg > 0))
+        return fail(FX_EINVAL, "Fermi-Dirac carriers need m_e, m_p, Eg > 0");
     p->nx = d->nx; p->ny = d->ny; p->nz = d->nz;
     p->kb = -1; p->kt = -1; p->f0 = -1; p->f1 = -1; p->sc0 = -1; p->sc1 = -1;
     bool any_sc = false;
@@ -160,7 +164,8 @@ fx_status validate(const fx_stack_desc *d, Plan *p) {
         if (p->f1 - p->f0 < 3) return fail(FX_EINVAL, "ferroelectric needs >= 3 planes");
     }
     if (any_sc) {
-        if (!(d->T > 0) || !(d->ni > 0)) return fail(FX_EINVAL, "T and ni must be > 0 with a semiconductor");
+        if (!(d->T > 0) || (d->carriers != FX_CARRIERS_FD && !(d->ni > 0)))
+            return fail(FX_EINVAL, "T (and ni, for Boltzmann carriers) must be > 0 with a semiconductor");
         for (int k = p->sc0; k < p->sc1; ++k)
             if (d->plane_mat[k] != FX_MAT_SC) return fail(FX_EINVAL, "semiconductor planes must be contiguous");
     }
@@ -290,6 +295,7 @@ struct InstHost {
     double *phi[kPhiBufs] = {};
     double *t_cxy = nullptr, *t_czm = nullptr, *t_czp = nullptr, *t_wl = nullptr, *t_wr = nullptr;
     double *t_p0e = nullptr, *t_n0e = nullptr;
+    double *t_fd = nullptr;             // Fermi-Dirac: 4 values per device plane
     int *t_flags = nullptr;
     std::vector<DevLevel<double>> L64;
     std::vector<DevLevel<float>> L32;
@@ -430,6 +436,23 @@ void plan_launches(Engine *e) {
     }
 }
 
+// (E_F - E_c)/kT of a semiconductor plane at phi = 0 under Fermi-Dirac statistics:
+// the root of Nv F(-x - Eg/kT) - Nc F(x) + Nd - Na = 0 (falling in x), by bisection
+// down to adjacent doubles.
+double fd_neutral_eta(double Nc, double Nv, double egkt, double Na, double Nd) {
+    double lo = -egkt - 100.0, hi = 100.0;
+    for (int it = 0; it < 400; ++it) {
+        const double mid = 0.5 * (lo + hi);
+        if (mid <= lo || mid >= hi) break;
+        double Fp, Fn, d;
+        fd_half(-mid - egkt, Fp, d);
+        fd_half(mid, Fn, d);
+        if (Nv * Fp - Nc * Fn + Nd - Na > 0.0) lo = mid;
+        else hi = mid;
+    }
+    return 0.5 * (lo + hi);
+}
+
 // Lay out (or, with ws == nullptr, only size) the workspace: one region per
 // instance, then the shared tables.
 size_t carve(Engine *e, void *ws) {
@@ -448,6 +471,7 @@ size_t carve(Engine *e, void *ws) {
         h.t_wr = (double *)cv.take(nzd * sizeof(double));
         h.t_p0e = (double *)cv.take(nzd * sizeof(double));
         h.t_n0e = (double *)cv.take(nzd * sizeof(double));
+        h.t_fd = (double *)cv.take(4 * (size_t)nzd * sizeof(double));
         h.t_flags = (int *)cv.take(nzd * sizeof(int));
         const int nlev = (int)p.lv.size();
         h.L64.assign(mixed ? 0 : nlev, DevLevel<double>());
@@ -593,6 +617,8 @@ Inst<T> make_inst(const Engine *e, int i) {
     a.dmax = h.dmax;
     a.cxy0 = h.t_cxy; a.czm0 = h.t_czm; a.czp0 = h.t_czp; a.wl = h.t_wl; a.wr = h.t_wr;
     a.p0e = h.t_p0e; a.n0e = h.t_n0e; a.pflags = h.t_flags;
+    a.fd = d.carriers == FX_CARRIERS_FD;
+    a.fdt = h.t_fd;
     a.vsched = e->sched_dev + (size_t)i * kSchedChunk;
     for (int b = 0; b < kPhiBufs; ++b) a.phi[b] = h.phi[b];
     a.P[0] = h.P[0]; a.P[1] = h.P[1];
@@ -647,7 +673,7 @@ fx_status upload_all(Engine *e) {
         const fx_stack_desc &d = h.d;
         const int nzd = p.nzd;
         // finest-level tables: scaled coefficients, P face weights, carrier densities
-        std::vector<double> wl(nzd, 1.0), wr(nzd, 0.0), p0e(nzd, 0.0), n0e(nzd, 0.0);
+        std::vector<double> wl(nzd, 1.0), wr(nzd, 0.0), p0e(nzd, 0.0), n0e(nzd, 0.0), fdt(4 * (size_t)nzd, 0.0);
         std::vector<int> fl(nzd, 0);
         for (int k = 0; k < nzd; ++k) {
             const int K = p.kb + k;
@@ -661,12 +687,29 @@ fx_status upload_all(Engine *e) {
             if (fe_near) fl[k] |= PF_P;
             if (d.plane_mat[K] == FX_MAT_SC) {
                 fl[k] |= PF_SC;
-                const double net = d.plane_Nd[K] - d.plane_Na[K], ni = d.ni;
-                double pp, nn;
-                if (net >= 0) { nn = 0.5 * net + std::sqrt(0.25 * net * net + ni * ni); pp = ni * ni / nn; }
-                else { pp = -0.5 * net + std::sqrt(0.25 * net * net + ni * ni); nn = ni * ni / pp; }
-                p0e[k] = kQe * pp;
-                n0e[k] = kQe * nn;
+                if (d.carriers == FX_CARRIERS_FD) {
+                    const double kT = kKb * d.T;
+                    const double Nc = 2.0 * std::pow(d.m_e * kMe0 * kT / (2.0 * M_PI * kHbar * kHbar), 1.5);
+                    const double Nv = 2.0 * std::pow(d.m_p * kMe0 * kT / (2.0 * M_PI * kHbar * kHbar), 1.5);
+                    const double egkt = d.Eg / h.VT;
+                    const double etn = fd_neutral_eta(Nc, Nv, egkt, d.plane_Na[K], d.plane_Nd[K]);
+                    double F, dF;
+                    fdt[4 * k + 0] = -etn - egkt;
+                    fdt[4 * k + 1] = etn;
+                    fd_half(-etn - egkt, F, dF);
+                    fdt[4 * k + 2] = F;
+                    fd_half(etn, F, dF);
+                    fdt[4 * k + 3] = F;
+                    p0e[k] = kQe * Nv;
+                    n0e[k] = kQe * Nc;
+                } else {
+                    const double net = d.plane_Nd[K] - d.plane_Na[K], ni = d.ni;
+                    double pp, nn;
+                    if (net >= 0) { nn = 0.5 * net + std::sqrt(0.25 * net * net + ni * ni); pp = ni * ni / nn; }
+                    else { pp = -0.5 * net + std::sqrt(0.25 * net * net + ni * ni); nn = ni * ni / pp; }
+                    p0e[k] = kQe * pp;
+                    n0e[k] = kQe * nn;
+                }
             }
         }
         const HostLevel &H0 = p.lv[0];
@@ -677,6 +720,7 @@ fx_status upload_all(Engine *e) {
         HIP_OK(hipMemcpy(h.t_wr, wr.data(), nzd * sizeof(double), hipMemcpyHostToDevice));
         HIP_OK(hipMemcpy(h.t_p0e, p0e.data(), nzd * sizeof(double), hipMemcpyHostToDevice));
         HIP_OK(hipMemcpy(h.t_n0e, n0e.data(), nzd * sizeof(double), hipMemcpyHostToDevice));
+        HIP_OK(hipMemcpy(h.t_fd, fdt.data(), fdt.size() * sizeof(double), hipMemcpyHostToDevice));
         HIP_OK(hipMemcpy(h.t_flags, fl.data(), nzd * sizeof(int), hipMemcpyHostToDevice));
         const std::vector<DevLevel<T>> &D = levels<T>(h);
         for (size_t l = 0; l < p.lv.size(); ++l) {

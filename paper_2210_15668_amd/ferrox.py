@@ -47,7 +47,8 @@ class StackDesc(ctypes.Structure):
                 ("v_bottom", ctypes.c_double), ("v_top", ctypes.c_double),
                 ("tol_rel", ctypes.c_double), ("max_cycles", ctypes.c_int),
                 ("prec", ctypes.c_int), ("warm_start", ctypes.c_int),
-                ("time_order", ctypes.c_int)]
+                ("time_order", ctypes.c_int), ("carriers", ctypes.c_int),
+                ("m_e", ctypes.c_double), ("m_p", ctypes.c_double), ("Eg", ctypes.c_double)]
 
 
 class SolveInfo(ctypes.Structure):
@@ -161,7 +162,7 @@ class _DescHolder:
                            spec.alpha, spec.beta, spec.gamma, spec.g11, spec.g44, spec.Gamma,
                            spec.pbc, spec.lam, spec.ni, spec.T, spec.v_bottom, spec.v_top,
                            spec.tol_rel, spec.max_cycles, spec.prec, spec.warm_start,
-                           spec.time_order)
+                           spec.time_order, spec.carriers, spec.m_e, spec.m_p, spec.Eg)
 
 
 def workspace_bytes(spec: W.StackSpec) -> int:

@@ -245,6 +245,17 @@ def mfim_fig3(n_lateral: int = 64, prec: int = PREC_FP64) -> StackSpec:
 DT_TABLE1 = 4.0e-13      # s, Table 1's time step (with g = 1e-9 and h = 0.5 nm)
 
 
+def mfism_fig4(n_lateral: int = 64, prec: int = PREC_FP64) -> StackSpec:
+    """The 3D MFISM of the Results (FeFET gate stack): 5 nm ferroelectric, 1 nm SiO2, 10 nm
+    undoped silicon with Fermi-Dirac carriers (Table 1's effective masses), 32 nm lateral at
+    h = 0.5 nm (64 x 64 cells; n_lateral shrinks the footprint), one metal plane at each end,
+    0 V gate; Table 1's g11 = g44 = 1e-9 V m^3/C."""
+    return layered(n_lateral, n_lateral, 34, [(FE, 10, EPS_FE, 0.0), (DE, 2, EPS_SIO2, 0.0),
+                                              (SC, 20, EPS_SI, 0.0)],
+                   g11=1.0e-9, g44=1.0e-9, v_top=0.0, T=300.0, carriers=CARRIERS_FD,
+                   tol_rel=1e-10, prec=prec)
+
+
 def batch_instances(count: int = 64, seed0: int = 100) -> List[Tuple[StackSpec, np.ndarray]]:
     """Uneven MFIM instances: x,y from {32,48,64,96}, z from {32,48}, FE 16..min(32,nz-4), DE 4.
 

@@ -55,13 +55,30 @@ def test_unet_sizes_are_host_only_and_validated(fx):
         assert fx.lib().last_error().decode() != ""
 
 
-def test_binding_struct_matches_header_layout(fx):
-    # fx_stack_desc: 3 ints, double, 4 pointers, 6 doubles, int, 3 doubles, 2 doubles, double, 3 ints
-    assert ctypes.sizeof(fx.StackDesc) == 176
-    assert ctypes.sizeof(fx.SolveInfo) == 24
-    assert ctypes.sizeof(fx.RunInfo) == 24
-    assert ctypes.sizeof(fx.BatchInfo) == 24
-    assert ctypes.sizeof(fx.TuneInfo) == 32
+def test_binding_struct_matches_header_layout(fx, tmp_path):
+    """Every binding struct has the C struct's size and every field its offset, as the C
+    compiler lays out include/ferrox.h."""
+    import subprocess
+    pairs = [("fx_stack_desc", fx.StackDesc), ("fx_solve_info", fx.SolveInfo), ("fx_run_info", fx.RunInfo),
+             ("fx_batch_info", fx.BatchInfo), ("fx_tune_info", fx.TuneInfo)]
+    cname = {"lam": "lambda"}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "ferrox.h"', 'int main(void) {']
+    for ct, py in pairs:
+        lines.append(f'printf("{ct} sizeof %zu\\n", sizeof({ct}));')
+        for f, _ in py._fields_:
+            c = cname.get(f, f)
+            lines.append(f'printf("{ct} {f} %zu\\n", offsetof({ct}, {c}));')
+    lines += ['return 0;', '}']
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.check_call(["gcc", "-std=c11", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)])
+    out = subprocess.check_output([str(exe)]).decode().split("\n")
+    got = {tuple(l.split()[:2]): int(l.split()[2]) for l in out if l.strip()}
+    for ct, py in pairs:
+        assert got[(ct, "sizeof")] == ctypes.sizeof(py), ct
+        for f, _ in py._fields_:
+            assert got[(ct, f)] == getattr(py, f).offset, (ct, f)
 
 
 def test_workspace_sizing_and_validation(fx):

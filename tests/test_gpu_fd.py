@@ -1,0 +1,100 @@
+"""Fermi-Dirac carriers on the GPU (eqs. FD, density_state, ne, np, rho with the F_1/2
+approximation the paper names) against the oracle, whose carrier model is pinned on the CPU
+(quadrature within the approximation's accuracy, both limits, neutrality, the Boltzmann
+reduction, the Newton Jacobian).  Fields agree to the same 1e-10 as with Boltzmann carriers."""
+import sys
+
+import numpy as np
+import pytest
+
+from paper_2210_15668_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def rel(a, b):
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def fx():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2210_15668_amd import ferrox
+    ferrox.lib()
+    return ferrox
+
+
+@pytest.mark.parametrize("prec", [W.PREC_FP64, W.PREC_MIXED])
+def test_fig4_mfism_parity(fx, orc, prec):
+    """The FeFET gate stack (undoped Si) on a 16x16 footprint: Step 0 and 6 time steps at
+    Table 1's dt with a gate ramp into inversion."""
+    spec = W.mfism_fig4(16, prec).copy(tol_rel=1e-13)
+    P0 = W.random_P(spec, 41, amp=0.2)
+    s = fx.Stack(spec, P0)
+    phi_o, _ = orc.solve(spec, P0, tol=1e-13)
+    r0 = rel(s.get(fx.FIELD_PHI), phi_o)
+    n = 6
+    vs = np.linspace(0.5, 3.0, n)
+    info = s.run_steps(n, W.DT_TABLE1, vs)
+    P_o, phi_o, _ = orc.run(spec, P0, n, W.DT_TABLE1, v_sched=vs, tol=1e-13, phi0=phi_o, init=False)
+    rp, rf = rel(s.get(fx.FIELD_P), P_o), rel(s.get(fx.FIELD_PHI), phi_o)
+    say(f"  step 0 rel {r0:.2e}; cycles/step {info.total_cycles / n:.2f} relP {rp:.2e} relphi {rf:.2e}")
+    assert r0 <= 1e-10 and rp <= 1e-10 and rf <= 1e-10
+
+
+@pytest.mark.parametrize("Na,Nd,v", [(1e24, 0.0, -2.0), (0.0, 1e26, 1.5), (1e25, 0.0, 2.5)])
+def test_doped_and_degenerate_silicon(fx, orc, Na, Nd, v):
+    """Degenerate accumulation of p-Si, degenerate n+ Si, and strong inversion: the regimes
+    where Fermi-Dirac and Boltzmann statistics part."""
+    spec = W.layered(16, 16, 40, [(W.FE, 12, W.EPS_FE, 0.0), (W.DE, 4, W.EPS_SIO2, 0.0),
+                                  (W.SC, 20, W.EPS_SI, Na)], v_top=v, T=300.0,
+                     carriers=W.CARRIERS_FD, tol_rel=1e-13)
+    kb, kt = spec.device_range()
+    spec.plane_Nd[kb:kb + 20] = Nd
+    P0 = W.random_P(spec, 42, amp=0.1)
+    s = fx.Stack(spec, P0)
+    phi_o, _ = orc.solve(spec, P0, tol=1e-13)
+    s.run_steps(3, W.DT)
+    P_o, phi_o, _ = orc.run(spec, P0, 3, W.DT, tol=1e-13, phi0=phi_o, init=False)
+    rp, rf = rel(s.get(fx.FIELD_P), P_o), rel(s.get(fx.FIELD_PHI), phi_o)
+    # the same stack with Boltzmann carriers lands measurably elsewhere
+    sb = spec.copy(carriers=W.CARRIERS_BOLTZMANN, ni=1.0e16)
+    phi_b, _ = orc.solve(sb, P0, tol=1e-13)
+    _, phi_b, _ = orc.run(sb, P0, 3, W.DT, tol=1e-13, phi0=phi_b, init=False)
+    say(f"  Na {Na:.0e} Nd {Nd:.0e} V {v}: relP {rp:.2e} relphi {rf:.2e}; Boltzmann differs by "
+        f"{rel(phi_b, phi_o):.2e}")
+    assert rp <= 1e-10 and rf <= 1e-10
+    assert rel(phi_b, phi_o) > 1e-4
+
+
+def test_batch_mixes_carrier_models(fx, orc):
+    """Boltzmann and Fermi-Dirac instances in one batch, graph replay."""
+    a = W.shrink_lateral(W.mfism_large(), 16, 16).copy(tol_rel=1e-13)
+    b = a.copy(carriers=W.CARRIERS_FD)
+    c = W.mfism_fig4(16).copy(tol_rel=1e-13, v_top=1.0)
+    specs = [a, b, c]
+    Ps = [W.random_P(sp, 50 + q, amp=0.05) for q, sp in enumerate(specs)]
+    bt = fx.Batch(specs, Ps)
+    bt.set_launch(fx.LAUNCH_GRAPH)
+    n = 4
+    info = bt.run(n, W.DT)
+    for q, sp in enumerate(specs):
+        assert info[q].status == fx.FX_OK and info[q].steps_done == n
+        P_o, phi_o, _ = orc.run(sp, Ps[q], n, W.DT, tol=1e-13)
+        rp, rf = rel(bt.get(q, fx.FIELD_P), P_o), rel(bt.get(q, fx.FIELD_PHI), phi_o)
+        say(f"  inst {q} carriers {sp.carriers}: relP {rp:.2e} relphi {rf:.2e}")
+        assert rp <= 1e-10 and rf <= 1e-10, q
+
+
+def test_fd_descriptor_is_validated(fx):
+    spec = W.mfism_fig4(16)
+    for bad in (spec.copy(carriers=2), spec.copy(m_e=0.0), spec.copy(Eg=-1.0)):
+        with pytest.raises(fx.FerroxError):
+            fx.Stack(bad, W.random_P(bad, 0))
