@@ -148,6 +148,7 @@ struct Inst {
     XferArgs<T> xf[kMaxLevels];
     int nu1, nu2, lds_bytes;
     int off_e[kMaxLevels], off_r[kMaxLevels], off_s[kMaxLevels], off_t[kMaxLevels];
+    int off_x[kMaxLevels];             // transfer tables between coarse-kernel levels q and q+1
     // conjugate-gradient bottom solve: search direction, product, reduction scratch (LDS offsets)
     int off_p, off_q, off_red;
     int bottom_iters;

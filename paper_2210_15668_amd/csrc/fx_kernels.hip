@@ -41,10 +41,10 @@ struct Lv {
     int sig_lo, sig_hi;
 };
 
-template <typename T>
+template <typename T, int AS = 1>
 struct Xv {
-    const int FX_AS(1) *cks, *ccnt, *fthick, *cthick, *pka, *pkb;
-    const T FX_AS(1) *pwa, *pwb;
+    const int FX_AS(AS) *cks, *ccnt, *fthick, *cthick, *pka, *pkb;
+    const T FX_AS(AS) *pwa, *pwb;
     int xy;
 };
 
@@ -691,7 +691,11 @@ __device__ __forceinline__ void residual_body(const Inst<T> &a, const GState *s,
                     res += (p0e * (Fp - ft[2]) - n0e * (Fn - ft[3])) * a.rho_scale;
                     L.sig[sidx(L, i, j, k)] = (T)((p0e * dFp + n0e * dFn) * a.sig_scale);
                 } else {
-                    const double em = expm1(-u), ep = expm1(u);
+                    // e^u - 1 and e^-u - 1 from one expm1: with t = e^|u| - 1 the other
+                    // is -t / (1 + t), free of cancellation for either sign of u
+                    const double t1 = expm1(fabs(u));
+                    const double t2 = -t1 / (1.0 + t1);
+                    const double ep = u >= 0.0 ? t1 : t2, em = u >= 0.0 ? t2 : t1;
                     res += (p0e * em - n0e * ep) * a.rho_scale;                   // + rho_c
                     L.sig[sidx(L, i, j, k)] = (T)((p0e * (1.0 + em) + n0e * (1.0 + ep)) * a.sig_scale);
                 }
@@ -951,20 +955,63 @@ __global__ __launch_bounds__(256) void k_prolong(const Inst<T> *I, Work w, int l
 }
 
 // --------------------------------------------- coarse levels in one workgroup
-template <typename V>
+// Quotient q / d for 0 <= q < 2^31 and 1 <= d < 2^16 without an integer division:
+// (q + 1/2) / d lies at least 1/(2d) >= 2^-17 from the next integer, while the
+// product with the rounded reciprocal is off by at most 2^-52 q/d < 2^-21.
+struct FDiv {
+    int d;
+    double inv;
+};
+__device__ __forceinline__ FDiv fdiv_of(int d) { return {d, 1.0 / (double)d}; }
+__device__ __forceinline__ int fquo(int q, const FDiv &f) { return (int)(((double)q + 0.5) * f.inv); }
+
+// (i, j, k) of natural index c on an nx x ny x nz level
+struct Split3 {
+    FDiv fx, fy;
+};
+__device__ __forceinline__ void split_c(int c, const Split3 &s, int &i, int &j, int &k) {
+    const int row = fquo(c, s.fx);
+    i = c - row * s.fx.d;
+    k = fquo(row, s.fy);
+    j = row - k * s.fy.d;
+}
+
+// Work split of a coarse-kernel phase: the whole workgroup (stride blockDim.x,
+// separated by workgroup barriers) or, on the smallest levels, the first wave
+// alone (stride 64).  One wave's LDS operations complete in program order, so
+// its phases only need the compiler kept from moving memory operations across
+// the boundary.
+template <bool WAVE>
+__device__ __forceinline__ void phase_sync() {
+    if (WAVE) {
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+    } else {
+        __syncthreads();
+    }
+}
+template <bool WAVE>
+__device__ __forceinline__ int phase_stride() { return WAVE ? 64 : (int)blockDim.x; }
+
+template <bool WAVE, typename V>
 __device__ void smooth_color(const V &L, int color, int zero_init) {
     using T = typename V::value_type;
+    const int st = phase_stride<WAVE>();
     if (L.rb) {
         const int hx = L.nx >> 1;
         const int n = hx * L.ny * L.nz;
-        for (int q = threadIdx.x; q < n; q += blockDim.x) {
-            const int m = q % hx, row = q / hx, j = row % L.ny, k = row / L.ny;
+        const Split3 sp{fdiv_of(hx), fdiv_of(L.ny)};
+        for (int q = threadIdx.x; q < n; q += st) {
+            int m, j, k;
+            split_c(q, sp, m, j, k);
             gs_cell(L, 2 * m + ((color + j + k) & 1), j, k, zero_init);
         }
     } else {
         const int n = L.nx * L.ny * L.nz;
-        for (int c = threadIdx.x; c < n; c += blockDim.x) {
-            const int i = c % L.nx, row = c / L.nx, j = row % L.ny, k = row / L.ny;
+        const Split3 sp{fdiv_of(L.nx), fdiv_of(L.ny)};
+        for (int c = threadIdx.x; c < n; c += st) {
+            int i, j, k;
+            split_c(c, sp, i, j, k);
             if (nat_color(L, i, j, k) == color) gs_cell(L, i, j, k, zero_init);
             else if (zero_init) L.e[cidx(L, i, j, k)] = T(0);
         }
@@ -972,13 +1019,37 @@ __device__ void smooth_color(const V &L, int color, int zero_init) {
 }
 
 // One full Gauss-Seidel sweep (2 colours on split levels, 4 otherwise).
-template <typename V>
+template <bool WAVE, typename V>
 __device__ void smooth_sweep(const V &L, int zero_init) {
     const int ncol = L.rb ? 2 : 4;
     for (int c = 0; c < ncol; ++c) {
-        smooth_color(L, c, zero_init && c == 0);
-        __syncthreads();
+        smooth_color<WAVE>(L, c, zero_init && c == 0);
+        phase_sync<WAVE>();
     }
+}
+
+// Restriction into level C and prolongation from it, as one phase each.
+template <bool WAVE, typename T, typename X_>
+__device__ void restrict_phase(const Lv<T, 3> &L, const Lv<T, 3> &C, const X_ &X) {
+    const int n = C.nx * C.ny * C.nz;
+    const Split3 sp{fdiv_of(C.nx), fdiv_of(C.ny)};
+    for (int c = threadIdx.x; c < n; c += phase_stride<WAVE>()) {
+        int I0, J0, K0;
+        split_c(c, sp, I0, J0, K0);
+        restrict_cell(L, C, X, I0, J0, K0);
+    }
+    phase_sync<WAVE>();
+}
+template <bool WAVE, typename T, typename X_>
+__device__ void prolong_phase(const Lv<T, 3> &L, const Lv<T, 3> &C, const X_ &X) {
+    const int n = L.nx * L.ny * L.nz;
+    const Split3 sp{fdiv_of(L.nx), fdiv_of(L.ny)};
+    for (int c = threadIdx.x; c < n; c += phase_stride<WAVE>()) {
+        int i, j, k;
+        split_c(c, sp, i, j, k);
+        prolong_cell(L, C, X, i, j, k);
+    }
+    phase_sync<WAVE>();
 }
 
 // Dot product over a whole workgroup, accumulated in double in a fixed order
@@ -1004,12 +1075,81 @@ __device__ double block_dot(P x, P y, int n, double FX_AS(3) *red) {
 // residual.  Unlike a fixed number of Gauss-Seidel sweeps this also solves
 // coarsest levels that keep many cells in x and y (odd lateral sizes stop the
 // x-y coarsening early).
+// Sum over the 64 lanes of a wave, formed in lane 0 in a fixed order and
+// broadcast (every lane gets the same bits).
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+    return __shfl(v, 0, 64);
+}
+
+// The same conjugate gradients for a bottom level of at most 64 cells, run by
+// the first wave alone with one cell per lane: the operator's neighbours are
+// read from other lanes' registers, the dot products are wave sums, and no
+// workgroup barrier is needed inside the iteration.
+template <typename T>
+__device__ void bottom_cg_wave(const Lv<T, 3> &B, int iters, double tol2) {
+    const int n = B.nx * B.ny * B.nz;
+    const int c = threadIdx.x;
+    const bool on = c < n;
+    int i = 0, j = 0, k = 0;
+    if (on) {
+        const Split3 sp{fdiv_of(B.nx), fdiv_of(B.ny)};
+        split_c(c, sp, i, j, k);
+    }
+    // neighbour lanes (natural order) and coefficients; absent neighbours weigh 0
+    int nl[6];
+    double w[6];
+    const double cx = on ? (double)B.cxy[k] : 0.0;
+    nl[0] = (k * B.ny + j) * B.nx + wrap_p(i, B.nx);
+    nl[1] = (k * B.ny + j) * B.nx + wrap_m(i, B.nx);
+    w[0] = w[1] = B.nx > 1 ? cx : 0.0;
+    nl[2] = (k * B.ny + wrap_p(j, B.ny)) * B.nx + i;
+    nl[3] = (k * B.ny + wrap_m(j, B.ny)) * B.nx + i;
+    w[2] = w[3] = B.ny > 1 ? cx : 0.0;
+    nl[4] = k > 0 ? c - B.nx * B.ny : c;
+    w[4] = on && k > 0 ? (double)B.czm[k] : 0.0;
+    nl[5] = k < B.nz - 1 ? c + B.nx * B.ny : c;
+    w[5] = on && k < B.nz - 1 ? (double)B.czp[k] : 0.0;
+    const int ci = on ? cidx(B, i, j, k) : 0;
+    const double d = on ? (double)diag_of(B, i, j, k) : 1.0;
+    double r = on ? (double)B.r[ci] : 0.0;
+    double x = 0.0, p = r;
+    double rr = wave_sum(r * r);
+    const double stop = tol2 * rr;
+    for (int it = 0; it < iters && rr > stop; ++it) {
+        double q = d * p;
+#pragma unroll
+        for (int m = 0; m < 6; ++m) q -= w[m] * __shfl(p, nl[m], 64);
+        if (!on) q = 0.0;
+        const double pq = wave_sum(p * q);
+        if (!(pq > 0.0)) break;
+        const double alpha = rr / pq;
+        x += alpha * p;
+        r -= alpha * q;
+        const double rn = wave_sum(r * r);
+        const double beta = rn / rr;
+        rr = rn;
+        p = r + beta * p;
+    }
+    if (on) {
+        B.e[ci] = (T)x;
+        B.r[ci] = (T)r;
+    }
+}
+
 template <typename T>
 __device__ void bottom_cg(const Lv<T, 3> &B, T FX_AS(3) *p, T FX_AS(3) *q, double FX_AS(3) *red, int iters,
                           double tol2) {
     const int n = B.nx * B.ny * B.nz;
+    if (n <= 64) {
+        if (threadIdx.x < 64) bottom_cg_wave(B, iters, tol2);
+        __syncthreads();
+        return;
+    }
     T FX_AS(3) *e = B.e;
     T FX_AS(3) *r = B.r;
+    const Split3 sp{fdiv_of(B.nx), fdiv_of(B.ny)};
     for (int c = threadIdx.x; c < n; c += blockDim.x) {
         e[c] = T(0);
         p[c] = r[c];
@@ -1019,7 +1159,8 @@ __device__ void bottom_cg(const Lv<T, 3> &B, T FX_AS(3) *p, T FX_AS(3) *q, doubl
     const double stop = tol2 * rr;
     for (int it = 0; it < iters && rr > stop; ++it) {
         for (int c = threadIdx.x; c < n; c += blockDim.x) {
-            const int i = c % B.nx, row = c / B.nx, j = row % B.ny, k = row / B.ny;
+            int i, j, k;
+            split_c(c, sp, i, j, k);
             const int ci = cidx(B, i, j, k);
             q[ci] = diag_of(B, i, j, k) * p[ci] - nb_sum(B, p, i, j, k);
         }
@@ -1074,6 +1215,44 @@ __global__ __launch_bounds__(512) void k_coarse(const Inst<T> *I) {
             tab[3 * G.nz + c] = G.dg[c];
         }
     }
+    // transfer tables into LDS: restriction and prolongation then wait on no
+    // global load
+    auto xlds = [&](int q) {
+        const int nf = A.lv[l0 + q].nz, nc = A.lv[l0 + q + 1].nz;
+        int FX_AS(3) *ib = (int FX_AS(3) *)(lds + A.off_x[q]);
+        Xv<T, 3> X;
+        X.cks = ib;
+        X.ccnt = ib + nc;
+        X.cthick = ib + 2 * nc;
+        X.fthick = ib + 3 * nc;
+        X.pka = ib + 3 * nc + nf;
+        X.pkb = ib + 3 * nc + 2 * nf;
+        const T FX_AS(3) *wb =
+            (const T FX_AS(3) *)(lds + ((A.off_x[q] + (3 * nc + 3 * nf) * (int)sizeof(int) + 15) & ~15));
+        X.pwa = wb;
+        X.pwb = wb + nf;
+        X.xy = A.xf[l0 + q].xy;
+        return X;
+    };
+    for (int q = 0; q + 1 < nl; ++q) {
+        const Xv<T> G = xview(A.xf[l0 + q]);
+        const int nf = A.lv[l0 + q].nz, nc = A.lv[l0 + q + 1].nz;
+        const Xv<T, 3> X = xlds(q);
+        int FX_AS(3) *ib = (int FX_AS(3) *)X.cks;
+        T FX_AS(3) *wb = (T FX_AS(3) *)X.pwa;
+        for (int c = threadIdx.x; c < nc; c += blockDim.x) {
+            ib[c] = G.cks[c];
+            ib[nc + c] = G.ccnt[c];
+            ib[2 * nc + c] = G.cthick[c];
+        }
+        for (int c = threadIdx.x; c < nf; c += blockDim.x) {
+            ib[3 * nc + c] = G.fthick[c];
+            ib[3 * nc + nf + c] = G.pka[c];
+            ib[3 * nc + 2 * nf + c] = G.pkb[c];
+            wb[c] = G.pwa[c];
+            wb[nf + c] = G.pwb[c];
+        }
+    }
     {
         const Lv<T, 1> G = gview(A.lv[l0]);
         const Lv<T, 3> L0 = lvl(0);
@@ -1085,29 +1264,15 @@ __global__ __launch_bounds__(512) void k_coarse(const Inst<T> *I) {
     }
     for (int q = 0; q < nl - 1; ++q) {
         const Lv<T, 3> L = lvl(q);
-        for (int s = 0; s < A.nu1; ++s) smooth_sweep(L, s == 0);
-        const Lv<T, 3> C = lvl(q + 1);
-        const Xv<T> X = xview(A.xf[l0 + q]);
-        const int n = C.nx * C.ny * C.nz;
-        for (int c = threadIdx.x; c < n; c += blockDim.x) {
-            const int I0 = c % C.nx, row = c / C.nx;
-            restrict_cell(L, C, X, I0, row % C.ny, row / C.ny);
-        }
-        __syncthreads();
+        for (int s = 0; s < A.nu1; ++s) smooth_sweep<false>(L, s == 0);
+        restrict_phase<false>(L, lvl(q + 1), xlds(q));
     }
     bottom_cg<T>(lvl(nl - 1), (T FX_AS(3) *)(lds + A.off_p), (T FX_AS(3) *)(lds + A.off_q),
                  (double FX_AS(3) *)(lds + A.off_red), A.bottom_iters, A.bottom_tol2);
     for (int q = nl - 2; q >= 0; --q) {
         const Lv<T, 3> L = lvl(q);
-        const Lv<T, 3> C = lvl(q + 1);
-        const Xv<T> X = xview(A.xf[l0 + q]);
-        const int n = L.nx * L.ny * L.nz;
-        for (int c = threadIdx.x; c < n; c += blockDim.x) {
-            const int i = c % L.nx, row = c / L.nx;
-            prolong_cell(L, C, X, i, row % L.ny, row / L.ny);
-        }
-        __syncthreads();
-        for (int s = 0; s < A.nu2; ++s) smooth_sweep(L, 0);
+        prolong_phase<false>(L, lvl(q + 1), xlds(q));
+        for (int s = 0; s < A.nu2; ++s) smooth_sweep<false>(L, 0);
     }
     {
         const Lv<T, 1> G = gview(A.lv[l0]);

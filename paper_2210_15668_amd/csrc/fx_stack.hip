@@ -132,7 +132,8 @@ fx_status validate(const fx_stack_desc *d, Plan *p) {
         return fail(FX_EINVAL, "plane tables must not be NULL");
     if (d->prec != FX_PREC_FP64 && d->prec != FX_PREC_MIXED) return fail(FX_EINVAL, "unknown precision");
     if (!(d->tol_rel > 0) || d->max_cycles < 1) return fail(FX_EINVAL, "tol_rel > 0 and max_cycles >= 1 required");
-    if (d->warm_start < 0 || d->warm_start > 3) return fail(FX_EINVAL, "warm_start must be 0..3");
+    if (d->warm_start < 0 || d->warm_start > kMaxHist)
+        return fail(FX_EINVAL, "warm_start must be 0..%d", kMaxHist);
     if (d->time_order < 0 || d->time_order > 2) return fail(FX_EINVAL, "time_order must be 0, 1 or 2");
     if (d->carriers != FX_CARRIERS_BOLTZMANN && d->carriers != FX_CARRIERS_FD)
         return fail(FX_EINVAL, "carriers must be FX_CARRIERS_BOLTZMANN or FX_CARRIERS_FD");
@@ -229,6 +230,7 @@ void build_plan(const fx_stack_desc *d, Plan *p) {
         const HostLevel &L = p->lv[l];
         tail += (2 * L.ncell() + L.nsig() + 4 * L.nz) * w + 64;
         if (l == nlev - 1) tail += 2 * L.ncell() * w + 16 * sizeof(double) + 64;   // bottom-solve vectors
+        else tail += 3 * (L.nz + p->lv[l + 1].nz) * sizeof(int) + 2 * L.nz * w + 48;  // transfer tables
         if (tail > (size_t)kCoarseLdsBytes) break;
         p->lc = l;
     }
@@ -393,6 +395,13 @@ int coarse_layout(const Plan &p, Inst<T> *a) {
         const int oe = take(H.ncell() * sizeof(T)), orr = take(H.ncell() * sizeof(T));
         const int os = take(H.nsig() * sizeof(T)), ot = take(4 * H.nz * sizeof(T));
         if (a) { a->off_e[q] = oe; a->off_r[q] = orr; a->off_s[q] = os; a->off_t[q] = ot; }
+    }
+    // transfer tables: 3 ints per coarse plane (cks, ccnt, cthick), 3 ints and
+    // 2 values per fine plane (fthick, pka, pkb; pwa, pwb)
+    for (int q = 0; q + 1 < nl; ++q) {
+        const int nf = p.lv[p.lc + q].nz, nc = p.lv[p.lc + q + 1].nz;
+        const int ox = take(3 * nc * sizeof(int) + 3 * nf * sizeof(int) + 2 * nf * sizeof(T) + 16);
+        if (a) a->off_x[q] = ox;
     }
     const HostLevel &B = p.lv.back();
     const int op = take(B.ncell() * sizeof(T)), oq = take(B.ncell() * sizeof(T));
@@ -657,7 +666,12 @@ Inst<T> make_inst(const Engine *e, int i) {
     a.nu2 = e->nu2;
     // CG in exact arithmetic ends within ncell steps; the cap only guards rounding
     a.bottom_iters = (int)std::min<size_t>(2 * p.lv.back().ncell() + 8, 512);
-    a.bottom_tol2 = std::is_same<T, float>::value ? 1e-10 : 1e-14;
+    {
+        // relative residual the bottom solve reaches (FERROX_BOTTOM_RTOL overrides)
+        const char *v = getenv("FERROX_BOTTOM_RTOL");
+        const double rt = v && *v ? atof(v) : (std::is_same<T, float>::value ? 1e-5 : 1e-7);
+        a.bottom_tol2 = rt * rt;
+    }
     a.lds_bytes = coarse_layout<T>(p, &a);
     return a;
 }
