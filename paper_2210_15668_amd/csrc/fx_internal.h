@@ -213,6 +213,7 @@ inline int tiles_cfg(int nxw, int ny, int nz, const SmoothCfg &c) {
     return ((nxw + bx - 1) / bx) * ((ny + by - 1) / by) * ((nz + c.zt - 1) / c.zt);
 }
 constexpr int kResZ = 4;            // planes per thread in the fine-level residual
+constexpr int kProZ = 4;            // planes per thread in the prolongation kernel
 constexpr int kExtrapChunk = 1024;  // cells per extrapolation tile
 
 }  // namespace fx

@@ -180,20 +180,26 @@ __device__ __forceinline__ int nat_color(const V &L, int i, int j, int k) {
 // mean over the children, likewise sigma.  On a red/black level the black
 // children are skipped: right after a black half-sweep their residual is
 // zero (each black equation has just been solved exactly).
-template <typename V, typename X>
-__device__ __forceinline__ void restrict_cell(const V &F, const V &C, const X &Xf, int I, int J, int K) {
+// The child loops are unrolled (XY fixes their extent, a coarse plane has one
+// or two children) so that a thread issues all its loads together.
+template <bool XY, typename V, typename X>
+__device__ __forceinline__ void restrict_cell_t(const V &F, const V &C, const X &Xf, int I, int J, int K) {
     using T = typename V::value_type;
-    const int nsub = Xf.xy ? 2 : 1;
+    constexpr int nsub = XY ? 2 : 1;
     double sr = 0.0, ss = 0.0;
     const int ks = Xf.cks[K], cnt = Xf.ccnt[K];
-    for (int dz = 0; dz < cnt; ++dz) {
+#pragma unroll
+    for (int dz = 0; dz < 2; ++dz) {
+        if (dz >= cnt) break;
         const int k = ks + dz;
         const double wz = (double)Xf.fthick[k] / (double)Xf.cthick[K];
         const bool hs = has_sig(F, k);
+#pragma unroll
         for (int dy = 0; dy < nsub; ++dy) {
-            const int j = Xf.xy ? 2 * J + dy : J;
+            const int j = XY ? 2 * J + dy : J;
+#pragma unroll
             for (int dx = 0; dx < nsub; ++dx) {
-                const int i = Xf.xy ? 2 * I + dx : I;
+                const int i = XY ? 2 * I + dx : I;
                 const T sg = hs ? F.sig[sidx(F, i, j, k)] : T(0);
                 ss += wz * (double)sg;
                 if (F.rb && ((i + j + k) & 1)) continue;
@@ -203,43 +209,58 @@ __device__ __forceinline__ void restrict_cell(const V &F, const V &C, const X &X
             }
         }
     }
-    const double wxy = Xf.xy ? 0.25 : 1.0;
+    const double wxy = XY ? 0.25 : 1.0;
     C.r[cidx(C, I, J, K)] = (T)(sr * wxy);
     if (has_sig(C, K)) C.sig[sidx(C, I, J, K)] = (T)(ss * wxy);
+}
+template <typename V, typename X>
+__device__ __forceinline__ void restrict_cell(const V &F, const V &C, const X &Xf, int I, int J, int K) {
+    if (Xf.xy) restrict_cell_t<true>(F, C, Xf, I, J, K);
+    else restrict_cell_t<false>(F, C, Xf, I, J, K);
 }
 
 // e_f += I e_c: bilinear in x,y (cell-centred 3/4, 1/4), in z linear in the
 // series resistance between coarse plane centres (zero on contact faces).  On
 // a red/black level only black cells are corrected: the red values are
 // overwritten by the next red half-sweep without being read.
-template <typename V, typename X>
-__device__ __forceinline__ void prolong_cell(const V &F, const V &C, const X &Xf, int i, int j, int k) {
+// Unrolled like the restriction: all coarse values are loaded together; a
+// missing second plane (contact side) reads the first with weight zero.
+// prolong_value returns the interpolated correction of fine cell (i, j, k).
+template <bool XY, typename V, typename X>
+__device__ __forceinline__ typename V::value_type prolong_value(const V &C, const X &Xf, int i, int j, int k) {
     using T = typename V::value_type;
-    if (F.rb && !((i + j + k) & 1)) return;
+    constexpr int ns = XY ? 2 : 1;
     int ix[2], jy[2];
     T wx[2], wy[2];
-    int ns = 1;
-    if (Xf.xy) {
+    if (XY) {
         const int I = i >> 1, J = j >> 1;
         ix[0] = I; ix[1] = (i & 1) ? wrap_p(I, C.nx) : wrap_m(I, C.nx);
         jy[0] = J; jy[1] = (j & 1) ? wrap_p(J, C.ny) : wrap_m(J, C.ny);
         wx[0] = wy[0] = T(0.75);
         wx[1] = wy[1] = T(0.25);
-        ns = 2;
     } else {
-        ix[0] = i; jy[0] = j; wx[0] = wy[0] = T(1);
+        ix[0] = ix[1] = i; jy[0] = jy[1] = j; wx[0] = wy[0] = T(1);
+        wx[1] = wy[1] = T(0);
     }
+    const int ka = Xf.pka[k], kb = Xf.pkb[k];
+    const int kz[2] = {ka, kb >= 0 ? kb : ka};
+    const T wz[2] = {Xf.pwa[k], kb >= 0 ? Xf.pwb[k] : T(0)};
     T v = 0;
-    const int kz[2] = {Xf.pka[k], Xf.pkb[k]};
-    const T wz[2] = {Xf.pwa[k], Xf.pwb[k]};
+#pragma unroll
     for (int q = 0; q < 2; ++q) {
-        if (kz[q] < 0) continue;
         T s = 0;
+#pragma unroll
         for (int yy = 0; yy < ns; ++yy)
+#pragma unroll
             for (int xx = 0; xx < ns; ++xx) s += wx[xx] * wy[yy] * C.e[cidx(C, ix[xx], jy[yy], kz[q])];
         v += wz[q] * s;
     }
-    F.e[cidx(F, i, j, k)] += v;
+    return v;
+}
+template <typename V, typename X>
+__device__ __forceinline__ void prolong_cell(const V &F, const V &C, const X &Xf, int i, int j, int k) {
+    if (F.rb && !((i + j + k) & 1)) return;
+    F.e[cidx(F, i, j, k)] += Xf.xy ? prolong_value<true>(C, Xf, i, j, k) : prolong_value<false>(C, Xf, i, j, k);
 }
 
 // Sum over a 256-thread block; result valid in thread 0.
@@ -928,6 +949,26 @@ __global__ __launch_bounds__(256) void k_restrict(const Inst<T> *I, Work w, int 
     restrict_cell(gview(a.lv[level]), C, xview(a.xf[level]), I0, J0, t.tz);
 }
 
+// A thread per column of kProZ planes (black cells only on a red/black
+// level): every correction is formed before any cell is updated, so the
+// column's loads are all in flight together.
+template <bool XY, typename T>
+__device__ __forceinline__ void prolong_column(const Lv<T, 1> &F, const Lv<T, 1> &C, const Xv<T> &X, int m, int j,
+                                               int k0) {
+    T v[kProZ];
+    int c[kProZ];
+#pragma unroll
+    for (int z = 0; z < kProZ; ++z) {
+        const int k = min(k0 + z, F.nz - 1);
+        const int i = F.rb ? 2 * m + ((1 + j + k) & 1) : m;
+        v[z] = prolong_value<XY>(C, X, i, j, k);
+        c[z] = cidx(F, i, j, k);
+    }
+#pragma unroll
+    for (int z = 0; z < kProZ; ++z)
+        if (k0 + z < F.nz) F.e[c[z]] += v[z];
+}
+
 template <typename T>
 __global__ __launch_bounds__(256) void k_prolong(const Inst<T> *I, Work w, int level) {
     const Blk b = find_block(w);
@@ -935,23 +976,15 @@ __global__ __launch_bounds__(256) void k_prolong(const Inst<T> *I, Work w, int l
     const Inst<T> &a = I[b.inst];
     if (asp<1>(a.st)->done) return;
     const Lv<T, 1> F = gview(a.lv[level]);
-    int i, j, k;
-    if (F.rb) {                       // a thread per black cell
-        const int hx = F.nx >> 1;
-        const T3 t = split3(b.t, hx, F.ny);
-        const int m = t.tx * BX + threadIdx.x;
-        j = t.ty * BY + threadIdx.y;
-        k = t.tz;
-        if (m >= hx || j >= F.ny) return;
-        i = 2 * m + ((1 + j + k) & 1);
-    } else {
-        const T3 t = split3(b.t, F.nx, F.ny);
-        i = t.tx * BX + threadIdx.x;
-        j = t.ty * BY + threadIdx.y;
-        k = t.tz;
-        if (i >= F.nx || j >= F.ny) return;
-    }
-    prolong_cell(F, gview(a.lv[level + 1]), xview(a.xf[level]), i, j, k);
+    const int nxe = F.rb ? F.nx >> 1 : F.nx;      // black cells per row on a red/black level
+    const T3 t = split3(b.t, nxe, F.ny);
+    const int m = t.tx * BX + threadIdx.x;
+    const int j = t.ty * BY + threadIdx.y;
+    if (m >= nxe || j >= F.ny) return;
+    const Lv<T, 1> C = gview(a.lv[level + 1]);
+    const Xv<T> X = xview(a.xf[level]);
+    if (X.xy) prolong_column<true>(F, C, X, m, j, t.tz * kProZ);
+    else prolong_column<false>(F, C, X, m, j, t.tz * kProZ);
 }
 
 // --------------------------------------------- coarse levels in one workgroup

@@ -557,7 +557,8 @@ fx_status build_work(Engine *e) {
         e->w_pr.push_back(mk([&](const InstHost &h) {
             if (l >= h.plan.lc) return 0;
             const HostLevel &F = h.plan.lv[l];
-            return F.rb ? tiles3(F.nx / 2, F.ny, F.nz) : tiles3(F.nx, F.ny, F.nz);
+            const int zt = (F.nz + kProZ - 1) / kProZ;
+            return F.rb ? tiles3(F.nx / 2, F.ny, zt) : tiles3(F.nx, F.ny, zt);
         }));
     }
     if (bad) return fail(FX_EINVAL, "a launch would exceed 2^30 tiles");
