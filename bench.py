@@ -12,7 +12,9 @@ the warm-up steps are outside the timed region; fields are resident in HBM.
 Prints one JSON line: FP64 steps/s (headline), the mixed-precision variant, the
 roofline of the dominant kernel (the finest-level Gauss-Seidel half-sweep, timed
 by its own dispatch events inside the timed region) and the CPU oracle's rate on
-a bounded sample of the same stack.
+a bounded sample of the same stack.  Beside them: the batch of 64 uneven instances, the
+learned warm start, and the same stack with the predictor-corrector time scheme and with
+Fermi-Dirac carriers, plus a recorded Q-V sweep of the 3D MFIM of the Results.
 """
 import argparse
 import hashlib
@@ -48,7 +50,7 @@ def measured_traffic(prec):
     return float(v) if v is not None else None
 
 
-def run_gpu(prec_name, steps, warmup, tune=True):
+def run_gpu(prec_name, steps, warmup, tune=True, tune_cache=None):
     import torch
     from paper_2210_15668_amd import ferrox
     from paper_2210_15668_amd import workloads as W
@@ -58,7 +60,7 @@ def run_gpu(prec_name, steps, warmup, tune=True):
     s = ferrox.Stack(spec, P0, device="cuda:0")          # Step 0, untimed
     tuned = None
     if tune:                                             # launch-shape search, untimed
-        ti = s.autotune()
+        ti = s.autotune(tune_cache)
         tuned = {"levels": ti.levels, "configs_timed": ti.configs_timed,
                  "half_sweep_us_default": ti.default_us, "half_sweep_us_tuned": ti.tuned_us,
                  "shapes": [dict(zip(("tile_x", "planes_per_thread", "waves8"), s.tune_config(l)))
@@ -89,7 +91,7 @@ def run_gpu(prec_name, steps, warmup, tune=True):
     return out
 
 
-def run_batch64(prec_name, steps, warmup, tune=True):
+def run_batch64(prec_name, steps, warmup, tune=True, tune_cache=None):
     """The 64 uneven MFIM instances advanced together (one launch per kernel for all of
     them, graph replay): time steps of the whole batch per second."""
     import torch
@@ -100,7 +102,7 @@ def run_batch64(prec_name, steps, warmup, tune=True):
     specs = [sp.copy(prec=prec) for sp, _ in inst]
     b = ferrox.Batch(specs, [P for _, P in inst], device="cuda:0")      # Step 0, untimed
     b.set_launch(ferrox.LAUNCH_GRAPH)
-    ti = b.autotune() if tune else None
+    ti = b.autotune(tune_cache) if tune else None
     if warmup:
         b.run(warmup, W.DT)
     torch.cuda.synchronize()
@@ -133,6 +135,33 @@ def run_learned():
     return res
 
 
+def run_variants(steps):
+    """The same 256 x 256 x 128 stack with the predictor-corrector (two solves per step)
+    and with Fermi-Dirac carriers, and a recorded Q-V sweep of the 3D MFIM (Results)."""
+    import torch
+    from paper_2210_15668_amd import ferrox, sweep
+    from paper_2210_15668_amd import workloads as W
+    out = {}
+    for name, spec in (("predictor_corrector", W.mfism_large().copy(time_order=2)),
+                       ("fermi_dirac", W.mfism_large().copy(carriers=W.CARRIERS_FD))):
+        s = ferrox.Stack(spec, W.random_P(spec, 2), device="cuda:0")
+        s.run_steps(10, W.DT)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        info = s.run_steps(steps, W.DT)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        s.close()
+        out[name] = {"steps_per_s": steps / dt, "vcycles_per_step": info.total_cycles / steps, "steps": steps}
+    spec = W.mfim_fig3()
+    period = 4000
+    r = sweep.run_sweep(spec, W.random_P(spec, 1, amp=0.01), 1000, 4.0, period)
+    out["qv_sweep"] = {"workload": "3D MFIM 64x64x20 (5 nm FE / 4 nm Al2O3), +-4 V triangle, dt 4e-13 s, "
+                                   "Q and V_fe recorded every step", "steps": r["steps"],
+                       "steps_per_s": r["steps"] / r["seconds"], "vcycles_per_step": r["cycles"] / r["steps"]}
+    return out
+
+
 def cpu_baseline(sample_steps):
     """The oracle, as it stands, on the same z-stack with a 64 x 64 footprint (1/16 of
     the cells): Step 0 untimed, then `sample_steps` timed steps at the same tolerance;
@@ -163,7 +192,10 @@ def main():
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-tune", action="store_true", help="keep the default smoother launch shapes")
+    ap.add_argument("--tune-cache", default=None,
+                    help="file of tuned launch shapes: read if it holds this workload, else written")
     ap.add_argument("--no-learned", action="store_true")
+    ap.add_argument("--no-variants", action="store_true", help="skip the predictor-corrector, Fermi-Dirac and Q-V lines")
     ap.add_argument("--batch-steps", type=int, default=100)
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -173,10 +205,10 @@ def main():
     import numpy as np
     import oracle  # noqa: F401  (only for the cpu_baseline leg)
 
-    r64 = run_gpu("fp64", args.steps, args.warmup, not args.no_tune)
+    r64 = run_gpu("fp64", args.steps, args.warmup, not args.no_tune, args.tune_cache)
     mixed = None
     if not args.no_mixed:
-        rmx = run_gpu("mixed", args.steps, args.warmup, not args.no_tune)
+        rmx = run_gpu("mixed", args.steps, args.warmup, not args.no_tune, args.tune_cache)
         diff = float(np.linalg.norm(rmx["phi"] - r64["phi"]) / np.linalg.norm(r64["phi"]))
         mixed = {"value": rmx["steps_per_s"], "ms_per_step": rmx["ms_per_step"],
                  "vcycles_per_step": rmx["vcycles_per_step"], "dtype": "f32 multigrid in f64 defect correction",
@@ -193,13 +225,14 @@ def main():
                 "launches_timed": r64["probe_launches"]}
     batch = None
     if not args.no_batch:
-        b64 = run_batch64("fp64", args.batch_steps, 5, not args.no_tune)
-        bmx = run_batch64("mixed", args.batch_steps, 5, not args.no_tune)
+        b64 = run_batch64("fp64", args.batch_steps, 5, not args.no_tune, args.tune_cache)
+        bmx = run_batch64("mixed", args.batch_steps, 5, not args.no_tune, args.tune_cache)
         batch = {"workload": "64 uneven MFIM instances: x, y in {32, 48, 64, 96}, z in {32, 48}, FE 16..32 / DE 4, "
                              "gates uniform in [-2, 2] V (seeds 100..163)",
                  "launch": "one launch per kernel for all instances, graph replay", "steps": args.batch_steps,
                  "fp64": b64, "mixed": bmx}
     learned = None if args.no_learned else run_learned()
+    variants = None if args.no_variants else run_variants(100)
     cpu = None if args.no_cpu_baseline else cpu_baseline(args.cpu_sample_steps)
     line = {
         "metric": "TDGL+Poisson steps/s at 1e-10 residual, 256\u00b2\u00d7128 MFISM; plain MG vs learned",
@@ -215,6 +248,7 @@ def main():
         "mixed_precision": mixed,
         "batch64": batch,
         "learned": learned,
+        "variants": variants,
         "roofline": roofline,
         "cpu_baseline": cpu,
         "paper_context": "paper: ~15x node-by-node GPU vs multicore (4x A100 vs 32 Haswell cores, NERSC); "

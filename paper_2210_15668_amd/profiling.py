@@ -1,10 +1,13 @@
 """Turn rocprofv3 output into the short text summaries kept under profiles/.
 
-Run on the GPU host from the repository root (each rocprofv3 call on its own):
+Run on the GPU host from the repository root (each rocprofv3 call on its own); the
+first, unprofiled bench run stores the tuned launch shapes in TUNE, so that the profiled
+runs use the same shapes without the tuner's own timing launches:
 
-  rocprofv3 --kernel-trace --stats -d OUT/trace -o run -- python3 bench.py
-  rocprofv3 --pmc FETCH_SIZE -d OUT/fetch -o run -- python3 bench.py --steps 20 --no-mixed --no-batch --no-learned --no-cpu-baseline
-  rocprofv3 --pmc WRITE_SIZE -d OUT/write -o run -- python3 bench.py --steps 20 --no-mixed --no-batch --no-learned --no-cpu-baseline
+  python3 bench.py --tune-cache TUNE
+  rocprofv3 --kernel-trace --stats -d OUT/trace -o run -- python3 bench.py --no-batch --no-learned --no-variants --no-cpu-baseline --tune-cache TUNE
+  rocprofv3 --pmc FETCH_SIZE -d OUT/fetch -o run -- python3 bench.py --steps 20 --no-mixed --no-batch --no-learned --no-cpu-baseline --no-variants --tune-cache TUNE
+  rocprofv3 --pmc WRITE_SIZE -d OUT/write -o run -- python3 bench.py --steps 20 --no-mixed --no-batch --no-learned --no-cpu-baseline --no-variants --tune-cache TUNE
   rocprofv3 --pmc FETCH_SIZE -d OUT/cfetch -o run -- python3 -m paper_2210_15668_amd.profiling copy
   rocprofv3 --pmc WRITE_SIZE -d OUT/cwrite -o run -- python3 -m paper_2210_15668_amd.profiling copy
   python3 -m paper_2210_15668_amd.profiling stats OUT/trace
@@ -28,7 +31,23 @@ from collections import defaultdict
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 KERNEL_SRC = os.path.join(ROOT, "paper_2210_15668_amd", "csrc", "fx_kernels.hip")
 COPY_BYTES = 1 << 30
-DOMINANT = "k_smooth<double"           # finest-level smoother launches have the largest grid
+# The dominant kernel: the FP64 Gauss-Seidel half-sweep on the finest level.  Its
+# launches (all variants: zero start, plain, folded Newton update; either register
+# budget) are those covering the most cells: grid x planes per thread (the third
+# template argument).
+SMOOTH64 = ("k_smooth<double", "k_smooth_w8<double")
+
+
+def _cells(name, grid):
+    if not name.startswith(SMOOTH64):
+        return 0
+    args = name[name.index("<") + 1:name.index(">")].split(",")
+    return grid * int(args[2])
+
+
+def _finest(keys):
+    top = max(_cells(*k) for k in keys)
+    return [k for k in keys if top > 0 and _cells(*k) == top]
 
 
 def _db(d):
@@ -63,12 +82,11 @@ def stats(trace_dir):
         agg[key][0] += 1
         agg[key][1] += d
     tot = sum(v[1] for v in agg.values())
-    fine = [k for k in agg if k[0].startswith(DOMINANT)]
+    fine = _finest(list(agg))
     if fine:
-        gmax = max(k[1] for k in fine)
-        c = sum(agg[k][0] for k in fine if k[1] == gmax)
-        t = sum(agg[k][1] for k in fine if k[1] == gmax)
-        print(f"Dominant kernel (finest-level FP64 smoother, all variants, grid {gmax}): "
+        c = sum(agg[k][0] for k in fine)
+        t = sum(agg[k][1] for k in fine)
+        print(f"Dominant kernel (finest-level FP64 smoother, {', '.join(f'`{k[0]}`' for k in fine)}): "
               f"{c} launches, average {t / c / 1e3:.2f} us\n")
     print("| kernel | grid (threads) | calls | avg us | total ms | % |")
     print("|---|---|---|---|---|---|")
@@ -96,10 +114,7 @@ def traffic(base):
     f_fetch, f_write = big_f / COPY_BYTES, big_w / COPY_BYTES
     fe = _counter(os.path.join(base, "fetch"), "FETCH_SIZE")
     wr = _counter(os.path.join(base, "write"), "WRITE_SIZE")
-    # the finest level is the largest grid among the smoother launches
-    keys = [k for k in fe if k[0].startswith(DOMINANT)]
-    gmax = max(k[1] for k in keys)
-    fine = [k for k in keys if k[1] == gmax]
+    fine = _finest(list(fe))
     n = sum(len(fe[k]) for k in fine)
     fetch = sum(sum(fe[k]) for k in fine) * 1024.0 / f_fetch / n
     write = sum(sum(wr.get(k, [0])) for k in fine) * 1024.0 / f_write / max(1, sum(len(wr.get(k, [])) for k in fine))
