@@ -116,8 +116,12 @@ typedef struct {
                                     1: 2 phi^n - phi^{n-1}; 2: quadratic; 3: cubic)      */
     int time_order;              /* run_steps' time scheme (Numerical Approach): 0 or 1 the
                                     forward-Euler Steps 1a + 1b; 2 the predictor-corrector
-                                    Steps 1a, 1b, 2a, 2b (two solves per step; the
-                                    corrector's solve starts from the predictor's phi)   */
+                                    Steps 1a, 1b, 2a, 2b (two solves per step; each
+                                    predictor solve starts from the extrapolation plus the
+                                    last step's phi* - phi^n, which takes one more full
+                                    grid of workspace and, unlike the stored levels, is not
+                                    part of a field checkpoint: a restarted run reaches the
+                                    same roots, not the same bits)                        */
     int carriers;                /* fx_carriers: semiconductor carrier statistics           */
     double m_e, m_p;             /* effective masses / free-electron mass (FX_CARRIERS_FD;
                                     Table 1: 1.08 and 0.81)                                 */

@@ -46,7 +46,8 @@ __host__ __device__ inline void fd_half(double eta, double &F, double &dF) {
 enum : int { PF_SC = 1, PF_P = 2 };
 
 constexpr int kMaxLevels = 24;
-constexpr int kPhiBufs = 6;       // phi^n, up to 3 stored levels, two iterate buffers
+constexpr int kPhiBufs = 7;       // phi^n, up to 3 stored levels, two iterate buffers, and for
+                                  // predictor-corrector instances the last predictor's phi*
 constexpr int kMaxHist = 3;
 constexpr int kCoarseLdsBytes = 64 * 1024;
 constexpr int kQvBlocks = 8;      // blocks per instance of the interface-plane reductions
@@ -76,6 +77,8 @@ struct InstState {
     int ts;                           // the running solve belongs to a time step
     int phase;                        // second-order steps: 0 predictor (or Euler), 1 corrector
     int corr;                         // runs the corrector update in this advance slot
+    int pstar;                        // buffer of the last step's predictor phi* (-1: none)
+    int usestar;                      // this solve starts from the extrapolation + phi* - phi^n
     int stepped;                      // a time step was completed in this advance slot
     int fresh;                        // solve started in this slot (first residual pending)
     int insolve;                      // a solve is running or awaits finalization
@@ -119,6 +122,7 @@ struct Inst {
     int nlev, lc, fold;                // levels; first level of the coarse kernel; update folded into smoothing
     int max_cycles, warm;
     int order2;                        // predictor-corrector time steps
+    int nbuf;                          // phi buffers in use (kPhiBufs - 1 without order2)
     double tol2;
     // TDGL
     double h, alpha, beta, gamma, g11, g44, Gamma, lambda;

@@ -393,23 +393,29 @@ __global__ void k_begin(const Inst<T> *I, int ninst, int sel) {
         if (s->adv && q >= 0 && q < s->sched_len) s->v_top = asp<1>(a.vsched)[q];
     } else {
         s->phase = 0;
+        s->pstar = -1;
     }
     // A corrector's solve starts from the predictor's phi*, O(dt^2) away from phi^{n+1},
     // unless the history through phi^n supports an extrapolation of order >= 2, which is
-    // O(dt^3) away or closer.
+    // O(dt^3) away or closer.  A predictor's target phi* differs from phi^{n+1} by a
+    // smooth O(dt^2) offset: with the last step's phi* kept, it starts from the
+    // extrapolation plus that step's offset phi*_n - phi^n, O(dt^3) away.
     int order = 0;
     if (sel && s->adv) order = min(s->hist, a.warm);
     else if (sel) order = min(s->hist - 1, a.warm) >= 2 ? min(s->hist - 1, a.warm) : 0;
+    const int usestar = sel && s->adv && a.order2 && s->pstar >= 0;
+    if (!usestar) s->pstar = -1;
     int oth[2] = {0, 0}, no = 0;
-    for (int q = 0; q < kPhiBufs && no < 2; ++q) {
-        bool used = q == s->cur;
+    for (int q = 0; q < a.nbuf && no < 2; ++q) {
+        bool used = q == s->cur || q == s->pstar;
         for (int m = 0; m < s->hist; ++m) used |= s->prev[m] == q;
         if (!used) oth[no++] = q;
     }
     s->oth0 = oth[0];
     s->oth1 = oth[1];
     s->order = order;
-    s->start = order > 0 ? oth[1] : s->cur;
+    s->usestar = usestar;
+    s->start = order > 0 || usestar ? oth[1] : s->cur;
     s->ts = sel;
     s->done = 0;
     s->cycles = 0;
@@ -428,7 +434,7 @@ __global__ __launch_bounds__(256) void k_extrap(const Inst<T> *I, Work w) {
     const Inst<T> &a = I[b.inst];
     const GState *s = asp<1>(a.st);
     const int order = s->order;
-    if (!s->fresh || order == 0) return;
+    if (!s->fresh || (order == 0 && !s->usestar)) return;
     const size_t nxy = (size_t)a.nx * a.ny, off = (size_t)a.kb * nxy, n = (size_t)a.nzd * nxy;
     const double FX_AS(1) *in[4];
     // newest level phi^n: the current iterate, or for a corrector the last stored level
@@ -436,6 +442,7 @@ __global__ __launch_bounds__(256) void k_extrap(const Inst<T> *I, Work w) {
     in[0] = asp<1>(a.phi[sh ? s->prev[0] : s->cur]) + off;
     for (int q = 1; q <= order; ++q) in[q] = asp<1>(a.phi[s->prev[q - 1 + sh]]) + off;
     double FX_AS(1) *out = asp<1>(a.phi[s->start]) + off;
+    const double FX_AS(1) *star = asp<1>(a.phi[s->usestar ? s->pstar : s->cur]) + off;
     const size_t base = (size_t)b.t * kExtrapChunk;
     const int tid = threadIdx.y * BX + threadIdx.x;
     for (int q = 0; q < kExtrapChunk / 256; ++q) {
@@ -443,6 +450,7 @@ __global__ __launch_bounds__(256) void k_extrap(const Inst<T> *I, Work w) {
         if (c >= n) break;
         double v = kExtrapC[order][0] * in[0][c];
         for (int m = 1; m <= order; ++m) v += kExtrapC[order][m] * in[m][c];
+        if (s->usestar) v += star[c] - in[0][c];
         out[c] = v;
     }
 }
@@ -476,11 +484,12 @@ __global__ void k_head(const Inst<T> *I, int ninst, int advance) {
             if (s->status != 0) s->failed += 1;
             const bool ok_step = s->ts && s->status == 0;
             if (ok_step && s->phase == 1) {
-                // corrector done: phi^{n+1}; the predictor's phi is dropped, phi^n
-                // stays the newest stored level
+                // corrector done: phi^{n+1}; the predictor's phi* is kept for the next
+                // predictor's start, phi^n stays the newest stored level
                 s->step += 1;
                 s->phase = 0;
                 stepped = 1;
+                s->pstar = s->cur;
             } else if (ok_step) {
                 // Euler step, or the predictor of a second-order step: phi^n
                 // becomes the newest stored level
@@ -493,9 +502,11 @@ __global__ void k_head(const Inst<T> *I, int ninst, int advance) {
                 }
                 if (I[n].order2) { s->phase = 1; corr = 1; }
                 else { s->step += 1; stepped = 1; }
+                s->pstar = -1;
             } else {
                 s->hist = 0;
                 s->phase = 0;
+                s->pstar = -1;
             }
             s->cur = fin;
             zf = s->done == 1 && s->zpend;

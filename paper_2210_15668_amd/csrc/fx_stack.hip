@@ -471,7 +471,8 @@ size_t carve(Engine *e, void *ws) {
         const Plan &p = h.plan;
         const size_t nfull = (size_t)p.nx * p.ny * p.nz;
         h.P[1] = (double *)cv.take(nfull * sizeof(double));
-        for (int b = 1; b < kPhiBufs; ++b) h.phi[b] = (double *)cv.take(nfull * sizeof(double));
+        const int nbuf = h.d.time_order == 2 ? kPhiBufs : kPhiBufs - 1;
+        for (int b = 1; b < nbuf; ++b) h.phi[b] = (double *)cv.take(nfull * sizeof(double));
         const int nzd = p.nzd;
         h.t_cxy = (double *)cv.take(nzd * sizeof(double));
         h.t_czm = (double *)cv.take(nzd * sizeof(double));
@@ -616,6 +617,7 @@ Inst<T> make_inst(const Engine *e, int i) {
     a.max_cycles = d.max_cycles;
     a.warm = d.warm_start;
     a.order2 = d.time_order == 2;
+    a.nbuf = a.order2 ? kPhiBufs : kPhiBufs - 1;
     a.tol2 = d.tol_rel * d.tol_rel;
     a.h = d.h; a.alpha = d.alpha; a.beta = d.beta; a.gamma = d.gamma;
     a.g11 = d.g11; a.g44 = d.g44; a.Gamma = d.Gamma; a.lambda = d.lambda; a.pbc = d.pbc;
@@ -754,6 +756,7 @@ fx_status upload_all(Engine *e) {
         s.done = 1;                     // idle: no solve running
         s.cur = 0;
         for (int m = 0; m < kMaxHist; ++m) s.prev[m] = m + 1;
+        s.pstar = -1;
         s.parked = 1;
         s.v_top = e->in[i].d.v_top;
     }
@@ -1018,10 +1021,11 @@ fx_status qv_now(Engine *e, double *h_Q, double *h_V) {
 // Write the host mirror of instance i back to the device (stream-ordered).
 void put_state(Engine *e, int i) { launch_put_state(e->st_dev + i, e->mir[i], e->st); }
 
+// Buffer b holds a stored time level or the last predictor's phi*.
 bool holds_history(const InstState &s, int b) {
     for (int m = 0; m < s.hist; ++m)
         if (s.prev[m] == b) return true;
-    return false;
+    return s.pstar == b;
 }
 
 void fill_contacts(Engine *e, int i, bool force) {
@@ -1051,14 +1055,16 @@ fx_status sync_to_caller(Engine *e) {
             changed = true;
         }
         if (s.cur != 0) {
-            // buffer 0 is the caller's: if it holds a stored level, move that level first
-            for (int m = 0; m < s.hist; ++m) {
-                if (s.prev[m] != 0) continue;
+            // buffer 0 is the caller's: if it holds a stored level (or the last
+            // predictor's phi*), move that first
+            for (int m = -1; m < s.hist; ++m) {
+                int &slot = m < 0 ? s.pstar : s.prev[m];
+                if (slot != 0) continue;
                 int spare = 1;
                 while (spare == s.cur || holds_history(s, spare)) ++spare;
                 HIP_OK(hipMemcpyAsync(h.phi[spare] + p.kb * nxy, h.phi[0] + p.kb * nxy,
                                       (size_t)p.nzd * nxy * sizeof(double), hipMemcpyDeviceToDevice, e->st));
-                s.prev[m] = spare;
+                slot = spare;
             }
             HIP_OK(hipMemcpyAsync(h.phi[0] + p.kb * nxy, h.phi[s.cur] + p.kb * nxy,
                                   (size_t)p.nzd * nxy * sizeof(double), hipMemcpyDeviceToDevice, e->st));
@@ -1111,7 +1117,8 @@ fx_status engine_init(Engine *e, double *const *d_P, double *const *d_phi, void 
             launch_fill(h.P[0], nfull, 0.0, e->st);
         }
         // Step 0: phi^{0,(0)} = 0, then solve
-        for (int b = 0; b < kPhiBufs; ++b) launch_fill(h.phi[b], nfull, 0.0, e->st);
+        for (int b = 0; b < kPhiBufs; ++b)
+            if (h.phi[b]) launch_fill(h.phi[b], nfull, 0.0, e->st);
         // level arrays start defined (the autotuner may sweep them before any solve)
         const size_t w = e->prec == FX_PREC_MIXED ? sizeof(float) : sizeof(double);
         for (size_t l = 0; l < p.lv.size(); ++l) {
@@ -1195,6 +1202,7 @@ fx_status set_field_impl(Engine *e, int i, int which, const double *h_in) {
         return FX_OK;
     }
     s.hist = 0;
+    s.pstar = -1;
     put_state(e, i);
     if (which == FX_FIELD_P) {
         HIP_OK(hipMemcpyAsync(h.P[0], h_in, n * sizeof(double), hipMemcpyHostToDevice, e->st));
@@ -1545,6 +1553,7 @@ fx_status tdgl_step(fx_stack *s, double dt) {
     }
     e->mir[0].pcur ^= 1;
     e->mir[0].hist = 0;
+    e->mir[0].pstar = -1;
     return sync_to_caller(e);
 }
 
@@ -1857,6 +1866,7 @@ fx_status stack_learned_solve(fx_stack *s, fx_unet *u, double v_top, fx_solve_in
     HIP_OK(hipGetLastError());
     // phi^n was replaced: the stored time levels no longer precede it
     e->mir[0].hist = 0;
+    e->mir[0].pstar = -1;
     put_state(e, 0);
     return poisson_solve(s, v_top, info);
 }
