@@ -337,7 +337,8 @@ struct Engine {
     int max_lc = 0, lds_max = 0, max_cycles = 1;
     int any_unfolded = 0;               // some instance forms phi + clip(e) in the residual kernel
     int any_order2 = 0;                 // some instance takes predictor-corrector steps
-    int nu1 = 2, nu2 = 2;
+    int nu1 = 2, nu2 = 2;               // sweeps before / after the coarse correction, finest level
+    int nu1c = 2, nu2c = 2;             // the same on every coarser level
     int k_pred = 4;                     // cycles enqueued before the first check of a plain solve
     int trace = 0;
     int ucap = 16;                      // units enqueued between host checks of a run
@@ -665,8 +666,8 @@ Inst<T> make_inst(const Engine *e, int i) {
             X.xy = p.lv[l + 1].xy_from_finer;
         }
     }
-    a.nu1 = e->nu1;
-    a.nu2 = e->nu2;
+    a.nu1 = e->nu1c;
+    a.nu2 = e->nu2c;
     // CG in exact arithmetic ends within ncell steps; the cap only guards rounding
     a.bottom_iters = (int)std::min<size_t>(2 * p.lv.back().ncell() + 8, 512);
     {
@@ -793,15 +794,17 @@ template <typename T>
 void enq_vcycle(Engine *e) {
     const Inst<T> *I = idev<T>(e);
     for (int l = 0; l < e->max_lc; ++l) {
-        for (int q = 0; q < e->nu1; ++q)
+        const int nu1 = l == 0 ? e->nu1 : e->nu1c;
+        for (int q = 0; q < nu1; ++q)
             for (int c = 0; c < e->ncol[l]; ++c) smooth_l<T>(e, l, c, q == 0 && c == 0, 0);
         launch_restrict(I, e->w_rs[l], l, e->st);
     }
     launch_coarse(I, e->n, e->lds_max, e->st);
     for (int l = e->max_lc - 1; l >= 0; --l) {
         launch_prolong(I, e->w_pr[l], l, e->st);
-        for (int q = 0; q < e->nu2; ++q)
-            for (int c = 0; c < e->ncol[l]; ++c) smooth_l<T>(e, l, c, 0, l == 0 && q == e->nu2 - 1 && c == 1);
+        const int nu2 = l == 0 ? e->nu2 : e->nu2c;
+        for (int q = 0; q < nu2; ++q)
+            for (int c = 0; c < e->ncol[l]; ++c) smooth_l<T>(e, l, c, 0, l == 0 && q == nu2 - 1 && c == 1);
     }
 }
 
@@ -1092,6 +1095,8 @@ fx_status engine_init(Engine *e, double *const *d_P, double *const *d_phi, void 
     e->st = (hipStream_t)stream;
     e->nu1 = std::max(1, env_int("FERROX_NU1", 2));
     e->nu2 = std::max(1, env_int("FERROX_NU2", 2));
+    e->nu1c = std::max(1, env_int("FERROX_NU1C", e->nu1));
+    e->nu2c = std::max(1, env_int("FERROX_NU2C", e->nu2));
     e->trace = env_int("FERROX_TRACE", 0);
     e->ucap = std::max(1, std::min(1 << (kUnitPow - 1), env_int("FERROX_UNITS", 16)));
     for (int i = 0; i < e->n; ++i) {
