@@ -138,6 +138,27 @@ __global__ __launch_bounds__(256) void k_conv3(const bf16_t *__restrict__ X, int
 // (16-byte loads) and all 27 taps read their B fragments from LDS (each wave
 // reads 512 contiguous bytes per fragment: no bank conflicts).  Needs nx a
 // multiple of 64 and ny a multiple of 4.
+// Move a 4 x bf16 fragment between lanes of a 16-lane row with DPP (register only).
+template <int CTRL>
+__device__ __forceinline__ s4 dpp_s4(s4 v) {
+    union {
+        s4 s;
+        int i[2];
+    } u;
+    u.s = v;
+    u.i[0] = __builtin_amdgcn_update_dpp(0, u.i[0], CTRL, 0xF, 0xF, true);
+    u.i[1] = __builtin_amdgcn_update_dpp(0, u.i[1], CTRL, 0xF, 0xF, true);
+    return u.s;
+}
+// The fragment of voxel (col + DX) of a 16-voxel tile: lane col + DX of the same row,
+// or, past the row's end, lane col + DX - 16 of the next tile's fragment.
+template <int DX>
+__device__ __forceinline__ s4 shift_frag(s4 cur, s4 next, int col) {
+    const s4 a = dpp_s4<0x100 + DX>(cur);         // row_shl: lane i reads lane i + DX
+    const s4 b = dpp_s4<0x110 + 16 - DX>(next);   // row_shr: lane i reads lane i - (16 - DX)
+    return col + DX < 16 ? a : b;
+}
+
 template <int CIN, int COUT, int OUT>
 __global__ __launch_bounds__(256) void k_conv3s(const bf16_t *__restrict__ X, int ldx, const bf16_t *__restrict__ Wt,
                                                 const float *__restrict__ bias, void *Yv, int ldy, int nx, int ny,
@@ -174,12 +195,19 @@ __global__ __launch_bounds__(256) void k_conv3s(const bf16_t *__restrict__ X, in
         for (int dz = 0; dz < 3; ++dz)
             for (int dy = 0; dy < 3; ++dy) {
                 const bf16_t *hrow = halo + ((dz * HY + wave + dy) * HX) * 16;
+                // the row's fragments at dx = 0 (and the two voxels past the 64);
+                // dx = 1, 2 are the same voxels shifted along each 16-lane row
+                s4 b0[5];
+#pragma unroll
+                for (int t = 0; t < 5; ++t) b0[t] = *(const s4 *)(hrow + min(16 * t + col, HX - 1) * 16 + 4 * kq);
 #pragma unroll
                 for (int dx = 0; dx < 3; ++dx) {
                     const int tap = dz * 9 + dy * 3 + dx;
                     s4 b[4];
 #pragma unroll
-                    for (int t = 0; t < 4; ++t) b[t] = *(const s4 *)(hrow + (16 * t + col + dx) * 16 + 4 * kq);
+                    for (int t = 0; t < 4; ++t)
+                        b[t] = dx == 0 ? b0[t] : (dx == 1 ? shift_frag<1>(b0[t], b0[t + 1], col)
+                                                          : shift_frag<2>(b0[t], b0[t + 1], col));
                     const bf16_t *wtap = Wt + (size_t)tap * COUT * CIN + kc * 16 + 4 * kq;
 #pragma unroll
                     for (int m = 0; m < MT; ++m) {
