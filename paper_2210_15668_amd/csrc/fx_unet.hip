@@ -60,7 +60,11 @@ template <int CIN, int COUT, int NTW, int OUT>
 __global__ __launch_bounds__(256) void k_conv3(const bf16_t *__restrict__ X, int ldx, const bf16_t *__restrict__ Wt,
                                                const float *__restrict__ bias, void *Yv, int ldy, int nx, int ny,
                                                int nz) {
-    constexpr int MT = COUT / 16, KC = CIN / 16;
+    // with few input channels blockIdx.y picks one 16-channel output tile (more waves in
+    // flight on small levels for little extra input traffic); otherwise a wave does all
+    constexpr bool MSPLIT = CIN <= 32;
+    constexpr int MT = MSPLIT ? 1 : COUT / 16, KC = CIN / 16;
+    const int mo = MSPLIT ? blockIdx.y * 16 : 0;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int n = nx * ny * nz;
     const int v0 = (blockIdx.x * 4 + wave) * (16 * NTW);
@@ -105,7 +109,7 @@ __global__ __launch_bounds__(256) void k_conv3(const bf16_t *__restrict__ X, int
                     const bf16_t *wtap = Wt + (size_t)tap * COUT * CIN + kc * 16 + 4 * kq;
 #pragma unroll
                     for (int m = 0; m < MT; ++m) {
-                        const s4 a = *(const s4 *)(wtap + (size_t)(m * 16 + col) * CIN);
+                        const s4 a = *(const s4 *)(wtap + (size_t)(mo + m * 16 + col) * CIN);
 #pragma unroll
                         for (int t = 0; t < NTW; ++t)
                             acc[m][t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b[t], acc[m][t], 0, 0, 0);
@@ -117,7 +121,7 @@ __global__ __launch_bounds__(256) void k_conv3(const bf16_t *__restrict__ X, int
         const size_t v = (size_t)(v0 + 16 * t + col);
 #pragma unroll
         for (int m = 0; m < MT; ++m) {
-            const int co = m * 16 + 4 * kq;
+            const int co = mo + m * 16 + 4 * kq;
             if (OUT == 0) {
                 s4 o;
 #pragma unroll
@@ -578,8 +582,8 @@ void conv_launch(const bf16_t *X, int ldx, const bf16_t *W, const float *b, void
         return;
     }
     const int n = nx * ny * nz, per = 64 * NTW;
-    hipLaunchKernelGGL((k_conv3<CIN, COUT, NTW, OUT>), dim3((n + per - 1) / per), dim3(256), 0, st, X, ldx, W, b, Y, ldy,
-                       nx, ny, nz);
+    hipLaunchKernelGGL((k_conv3<CIN, COUT, NTW, OUT>), dim3((n + per - 1) / per, CIN <= 32 ? COUT / 16 : 1), dim3(256),
+                       0, st, X, ldx, W, b, Y, ldy, nx, ny, nz);
 }
 
 // (cin, cout) pairs of the forward layers and of their input gradients
