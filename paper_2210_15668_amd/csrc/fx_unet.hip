@@ -245,30 +245,48 @@ __global__ __launch_bounds__(256) void k_conv3s(const bf16_t *__restrict__ X, in
 }
 
 // Weight gradient of one tap (blockIdx.y): part[bx][tap][cout][cin] =
-// sum over the block's voxels of G[v][cout] X[v + d_tap][cin].
+// sum over the block's voxels of G[v][cout] X[v + d_tap][cin].  Each round stages
+// 128 voxels of both operands in LDS, transposed ([channel][voxel]) so that every
+// matrix-core fragment is one 8-byte read; staging moves 8 channels (16 bytes) of one
+// voxel per load, its neighbour index worked out once per such piece.
 template <int CIN, int COUT>
 __global__ __launch_bounds__(256) void k_wgrad(const bf16_t *__restrict__ X, int ldx, const bf16_t *__restrict__ G,
                                                int nx, int ny, int nz, float *__restrict__ part) {
-    __shared__ bf16_t gz[64 * COUT];
-    __shared__ bf16_t xs[64 * CIN];
+    constexpr int VB = 128;
+    __shared__ bf16_t gt[COUT * VB];
+    __shared__ bf16_t xt[CIN * VB];
     constexpr int MT = COUT / 16, NC = CIN / 16, T = MT * NC, TPW = (T + 3) / 4;
+    typedef int i4 __attribute__((ext_vector_type(4)));
     const int tap = blockIdx.y;
     const int dz = tap / 9 - 1, dy = (tap / 3) % 3 - 1, dx = tap % 3 - 1;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int col = lane & 15, kq = lane >> 4;
-    const int n = nx * ny * nz, nchunks = (n + 63) / 64;
+    const int n = nx * ny * nz, nchunks = (n + VB - 1) / VB;
     f4 acc[TPW];
 #pragma unroll
     for (int q = 0; q < TPW; ++q) acc[q] = f4{0.f, 0.f, 0.f, 0.f};
     for (int ch = blockIdx.x; ch < nchunks; ch += gridDim.x) {
-        const int v0 = ch * 64;
-        for (int e = threadIdx.x; e < 64 * COUT; e += 256) {
-            const int v = v0 + e / COUT;
-            gz[e] = v < n ? G[(size_t)v * COUT + e % COUT] : (bf16_t)0;
+        const int v0 = ch * VB;
+        for (int u = threadIdx.x; u < VB * (COUT / 8); u += 256) {
+            const int vl = u / (COUT / 8), c8 = (u % (COUT / 8)) * 8;
+            const int v = v0 + vl;
+            union {
+                i4 w;
+                bf16_t h[8];
+            } val;
+            val.w = i4{0, 0, 0, 0};
+            if (v < n) val.w = *(const i4 *)(G + (size_t)v * COUT + c8);
+#pragma unroll
+            for (int j2 = 0; j2 < 8; ++j2) gt[(c8 + j2) * VB + vl] = val.h[j2];
         }
-        for (int e = threadIdx.x; e < 64 * CIN; e += 256) {
-            const int v = v0 + e / CIN;
-            bf16_t val = 0;
+        for (int u = threadIdx.x; u < VB * (CIN / 8); u += 256) {
+            const int vl = u / (CIN / 8), c8 = (u % (CIN / 8)) * 8;
+            const int v = v0 + vl;
+            union {
+                i4 w;
+                bf16_t h[8];
+            } val;
+            val.w = i4{0, 0, 0, 0};
             if (v < n) {
                 const int x = v % nx, q = v / nx, y = q % ny, z = q / ny;
                 const int z2 = z + dz;
@@ -276,26 +294,22 @@ __global__ __launch_bounds__(256) void k_wgrad(const bf16_t *__restrict__ X, int
                     int y2 = y + dy, x2 = x + dx;
                     y2 = y2 < 0 ? y2 + ny : (y2 >= ny ? y2 - ny : y2);
                     x2 = x2 < 0 ? x2 + nx : (x2 >= nx ? x2 - nx : x2);
-                    val = X[(size_t)((z2 * ny + y2) * nx + x2) * ldx + e % CIN];
+                    val.w = *(const i4 *)(X + (size_t)((z2 * ny + y2) * nx + x2) * ldx + c8);
                 }
             }
-            xs[e] = val;
+#pragma unroll
+            for (int j2 = 0; j2 < 8; ++j2) xt[(c8 + j2) * VB + vl] = val.h[j2];
         }
         __syncthreads();
 #pragma unroll
-        for (int kk = 0; kk < 4; ++kk) {
+        for (int kk = 0; kk < VB / 16; ++kk) {
 #pragma unroll
             for (int q = 0; q < TPW; ++q) {
                 const int tile = wave + 4 * q;
                 if (tile >= T) break;
                 const int mt = tile / NC, nt = tile % NC;
-                s4 a, b;
-#pragma unroll
-                for (int j = 0; j < 4; ++j) {
-                    const int r = kk * 16 + 4 * kq + j;
-                    a[j] = (short)gz[r * COUT + mt * 16 + col];
-                    b[j] = (short)xs[r * CIN + nt * 16 + col];
-                }
+                const s4 a = *(const s4 *)(gt + (mt * 16 + col) * VB + kk * 16 + 4 * kq);
+                const s4 b = *(const s4 *)(xt + (nt * 16 + col) * VB + kk * 16 + 4 * kq);
                 acc[q] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc[q], 0, 0, 0);
             }
         }
