@@ -195,6 +195,17 @@ __global__ __launch_bounds__(256) void k_conv3s(const bf16_t *__restrict__ X, in
             }
             *(i4 *)(halo + vi * 16 + half * 8) = val;
         }
+        // with two output tiles the chunk's weight fragments of all taps are loaded into
+        // registers before the taps (measured: helps there, not with one tile or more)
+        constexpr bool WREG = MT == 2;
+        s4 wr[WREG ? 27 : 1][WREG ? MT : 1];
+        if (WREG)
+#pragma unroll
+            for (int tp = 0; tp < 27; ++tp)
+#pragma unroll
+                for (int m = 0; m < MT; ++m)
+                    wr[tp][m] = *(const s4 *)(Wt + (size_t)tp * COUT * CIN + kc * 16 + 4 * kq +
+                                              (size_t)(m * 16 + col) * CIN);
         __syncthreads();
         for (int dz = 0; dz < 3; ++dz)
             for (int dy = 0; dy < 3; ++dy) {
@@ -215,7 +226,8 @@ __global__ __launch_bounds__(256) void k_conv3s(const bf16_t *__restrict__ X, in
                     const bf16_t *wtap = Wt + (size_t)tap * COUT * CIN + kc * 16 + 4 * kq;
 #pragma unroll
                     for (int m = 0; m < MT; ++m) {
-                        const s4 a = *(const s4 *)(wtap + (size_t)(m * 16 + col) * CIN);
+                        const s4 a = WREG ? wr[WREG ? tap : 0][WREG ? m : 0]
+                                          : *(const s4 *)(wtap + (size_t)(m * 16 + col) * CIN);
 #pragma unroll
                         for (int t = 0; t < 4; ++t)
                             acc[m][t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b[t], acc[m][t], 0, 0, 0);
