@@ -196,7 +196,7 @@ def main():
                     help="file of tuned launch shapes: read if it holds this workload, else written")
     ap.add_argument("--no-learned", action="store_true")
     ap.add_argument("--no-variants", action="store_true", help="skip the predictor-corrector, Fermi-Dirac and Q-V lines")
-    ap.add_argument("--batch-steps", type=int, default=100)
+    ap.add_argument("--batch-steps", type=int, default=500)
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
