@@ -219,6 +219,76 @@ __device__ __forceinline__ void restrict_cell(const V &F, const V &C, const X &X
     else restrict_cell_t<false>(F, C, Xf, I, J, K);
 }
 
+// The same restriction for a red/black level halved in x and y, in global
+// memory, with every load issued before any arithmetic: in each child row the
+// red child is the one with dx = (dy + k) & 1, a coarse plane with a single
+// child reads that plane twice (the copy is skipped below), and sigma outside
+// the semiconductor planes is read from the cell's own residual and ignored.
+// Without conditional loads the compiler keeps all 40 loads in flight at
+// once instead of waiting on each child's stencil in turn.
+template <typename V, typename X>
+__device__ __forceinline__ void restrict_cell_rbxy(const V &F, const V &C, const X &Xf, int I, int J, int K) {
+    using T = typename V::value_type;
+    const int ks = Xf.cks[K], cnt = Xf.ccnt[K];
+    T sg[2][2][2], rv[2][2], ev[2][2], nb[2][2][6], cx[2], czm[2], czp[2], dg[2];
+#pragma unroll
+    for (int dz = 0; dz < 2; ++dz) {
+        const int k = ks + (dz < cnt ? dz : 0);
+        const bool hs = has_sig(F, k);
+        const int km = k > 0 ? k - 1 : k, kp = k < F.nz - 1 ? k + 1 : k;
+        cx[dz] = F.cxy[k];
+        czm[dz] = F.czm[k];
+        czp[dz] = F.czp[k];
+        dg[dz] = F.dg[k];
+#pragma unroll
+        for (int dy = 0; dy < 2; ++dy) {
+            const int j = 2 * J + dy;
+#pragma unroll
+            for (int dx = 0; dx < 2; ++dx) {
+                const int i = 2 * I + dx;
+                const T FX_AS(1) *sp = hs ? F.sig + sidx(F, i, j, k) : F.r + cidx(F, i, j, k);
+                sg[dz][dy][dx] = *sp;
+            }
+            const int i = 2 * I + ((dy + k) & 1);
+            const int c = cidx(F, i, j, k);
+            rv[dz][dy] = F.r[c];
+            ev[dz][dy] = F.e[c];
+            nb[dz][dy][0] = F.e[cidx(F, wrap_p(i, F.nx), j, k)];
+            nb[dz][dy][1] = F.e[cidx(F, wrap_m(i, F.nx), j, k)];
+            nb[dz][dy][2] = F.e[cidx(F, i, wrap_p(j, F.ny), k)];
+            nb[dz][dy][3] = F.e[cidx(F, i, wrap_m(j, F.ny), k)];
+            nb[dz][dy][4] = F.e[cidx(F, i, j, km)];
+            nb[dz][dy][5] = F.e[cidx(F, i, j, kp)];
+        }
+    }
+    double sr = 0.0, ss = 0.0;
+#pragma unroll
+    for (int dz = 0; dz < 2; ++dz) {
+        if (dz >= cnt) break;
+        const int k = ks + dz;
+        const double wz = (double)Xf.fthick[k] / (double)Xf.cthick[K];
+        const bool hs = has_sig(F, k);
+#pragma unroll
+        for (int dy = 0; dy < 2; ++dy) {
+#pragma unroll
+            for (int dx = 0; dx < 2; ++dx) {
+                const T sgc = hs ? sg[dz][dy][dx] : T(0);
+                ss += wz * (double)sgc;
+                if (dx != ((dy + k) & 1)) continue;
+                T nbs = 0;
+                nbs += cx[dz] * (nb[dz][dy][0] + nb[dz][dy][1]);
+                nbs += cx[dz] * (nb[dz][dy][2] + nb[dz][dy][3]);
+                if (k > 0) nbs += czm[dz] * nb[dz][dy][4];
+                if (k < F.nz - 1) nbs += czp[dz] * nb[dz][dy][5];
+                const T res = rv[dz][dy] - ((dg[dz] + sgc) * ev[dz][dy] - nbs);
+                sr += wz * (double)res;
+            }
+        }
+    }
+    C.r[cidx(C, I, J, K)] = (T)(sr * 0.25);
+    if (has_sig(C, K)) C.sig[sidx(C, I, J, K)] = (T)(ss * 0.25);
+}
+
 // e_f += I e_c: bilinear in x,y (cell-centred 3/4, 1/4), in z linear in the
 // series resistance between coarse plane centres (zero on contact faces).  On
 // a red/black level only black cells are corrected: the red values are
@@ -620,8 +690,8 @@ __global__ __launch_bounds__(256) void k_zero_fix(const Inst<T> *I, Work w) {
 // ------------------------------------------------------ fine-level residual
 // Each thread owns a column of kResZ planes.  All loads are issued before any
 // arithmetic (clamped indices instead of boundary branches; the column's
-// z-neighbours are loaded once) so a wave makes one memory round trip for
-// kResZ cells.  Mode 0 evaluates the current iterate; mode 2 (update not
+// z-neighbours are loaded once) and all stores follow it, so a wave makes one
+// memory round trip for kResZ cells.  Mode 0 evaluates the current iterate; mode 2 (update not
 // folded into the smoother) first forms phi_out = phi_in + clip(e).
 template <typename T, int MODE>
 __device__ __forceinline__ void residual_body(const Inst<T> &a, const GState *s, const T3 &t, int after_cycle,
@@ -651,16 +721,19 @@ __device__ __forceinline__ void residual_body(const Inst<T> &a, const GState *s,
     const int half = (nxy * nzd) >> 1;
     const double big = 1e300;
     auto kcl = [&](int k) { return k < 0 ? 0 : (k >= nzd ? nzd - 1 : k); };
-    double pz[ZT + 2];
+    int fl[ZT];
 #pragma unroll
-    for (int z = 0; z < ZT + 2; ++z) pz[z] = 0.0;
+    for (int z = 0; z < ZT; ++z) fl[z] = pflags[kcl(k0 + z)];
     bool anyP = false;
 #pragma unroll
-    for (int z = 0; z < ZT; ++z) anyP |= (k0 + z < nzd) && (pflags[kcl(k0 + z)] & PF_P);
-    if (anyP) {
+    for (int z = 0; z < ZT; ++z) anyP |= (k0 + z < nzd) && (fl[z] & PF_P);
+    // P is read only by columns that hold a polarised plane; the others load
+    // the phi cells they read anyway (cache hits, values unused), so that no
+    // branch joins ahead of the phi loads and every load is in flight at once.
+    const double FX_AS(1) *Psrc = anyP ? P : phi;
+    double pz[ZT + 2];
 #pragma unroll
-        for (int z = 0; z < ZT + 2; ++z) pz[z] = P[kcl(k0 - 1 + z) * nxy + col];
-    }
+    for (int z = 0; z < ZT + 2; ++z) pz[z] = Psrc[kcl(k0 - 1 + z) * nxy + col];
     double vc[ZT + 2], vx0[ZT], vx1[ZT], vy0[ZT], vy1[ZT];
     auto at = [&](int k, int o, int par, double *dst) {
         const int c = k * nxy + col + o;
@@ -688,18 +761,20 @@ __device__ __forceinline__ void residual_body(const Inst<T> &a, const GState *s,
         at(k, oy1, pn, &vy1[z]);
     }
     const double v_b = a.v_b, v_t = s->v_top;
+    double res[ZT], sg[ZT];
 #pragma unroll
     for (int z = 0; z < ZT; ++z) {
         const int k = k0 + z;
+        res[z] = 0.0;
+        sg[z] = 0.0;
         if (k >= nzd) break;
-        const int fl = pflags[k];
         const double v0 = vc[z + 1];
         const double nb = (vx0[z] + vx1[z] - 2.0 * v0) + (vy0[z] + vy1[z] - 2.0 * v0);
         const double dn = k > 0 ? vc[z] : 0.0;
         const double up = k < nzd - 1 ? vc[z + 2] : 0.0;
         const double Lphi = -cxy0[k] * nb + czm0[k] * (v0 - dn) + czp0[k] * (v0 - up);
         double f = 0.0;
-        if (fl & PF_P) {
+        if (fl[z] & PF_P) {
             const double pc = pz[z + 1];
             const double pup = k == nzd - 1 ? pc : wl[k] * pc + wr[k] * pz[z + 2];
             const double pdn = k == 0 ? pc : wl[k - 1] * pz[z] + wr[k - 1] * pc;
@@ -707,35 +782,42 @@ __device__ __forceinline__ void residual_body(const Inst<T> &a, const GState *s,
         }
         if (k == 0) f += czm0[k] * v_b;
         if (k == nzd - 1) f += czp0[k] * v_t;
-        double res = f - Lphi;
-        if (live) {
-            const int cl = k * nxy + col;
-            if (MODE == 2) phi_out[cl] = v0;
-            if (fl & PF_SC) {
-                const double u = v0 * a.vt_inv;
-                const double p0e = p0ev[k], n0e = n0ev[k];
-                if (a.fd) {
-                    // differences from the neutral state: rho_c(0) = 0 exactly
-                    const double FX_AS(1) *ft = asp<1>(a.fdt) + 4 * k;
-                    double Fp, dFp, Fn, dFn;
-                    fd_half(ft[0] - u, Fp, dFp);
-                    fd_half(ft[1] + u, Fn, dFn);
-                    res += (p0e * (Fp - ft[2]) - n0e * (Fn - ft[3])) * a.rho_scale;
-                    L.sig[sidx(L, i, j, k)] = (T)((p0e * dFp + n0e * dFn) * a.sig_scale);
-                } else {
-                    // e^u - 1 and e^-u - 1 from one expm1: with t = e^|u| - 1 the other
-                    // is -t / (1 + t), free of cancellation for either sign of u
-                    const double t1 = expm1(fabs(u));
-                    const double t2 = -t1 / (1.0 + t1);
-                    const double ep = u >= 0.0 ? t1 : t2, em = u >= 0.0 ? t2 : t1;
-                    res += (p0e * em - n0e * ep) * a.rho_scale;                   // + rho_c
-                    L.sig[sidx(L, i, j, k)] = (T)((p0e * (1.0 + em) + n0e * (1.0 + ep)) * a.sig_scale);
-                }
+        double r = f - Lphi;
+        if (fl[z] & PF_SC) {
+            const double u = v0 * a.vt_inv;
+            const double p0e = p0ev[k], n0e = n0ev[k];
+            if (a.fd) {
+                // differences from the neutral state: rho_c(0) = 0 exactly
+                const double FX_AS(1) *ft = asp<1>(a.fdt) + 4 * k;
+                double Fp, dFp, Fn, dFn;
+                fd_half(ft[0] - u, Fp, dFp);
+                fd_half(ft[1] + u, Fn, dFn);
+                r += (p0e * (Fp - ft[2]) - n0e * (Fn - ft[3])) * a.rho_scale;
+                sg[z] = (p0e * dFp + n0e * dFn) * a.sig_scale;
+            } else {
+                // e^u - 1 and e^-u - 1 from one expm1: with t = e^|u| - 1 the other
+                // is -t / (1 + t), free of cancellation for either sign of u
+                const double t1 = expm1(fabs(u));
+                const double t2 = -t1 / (1.0 + t1);
+                const double ep = u >= 0.0 ? t1 : t2, em = u >= 0.0 ? t2 : t1;
+                r += (p0e * em - n0e * ep) * a.rho_scale;                         // + rho_c
+                sg[z] = (p0e * (1.0 + em) + n0e * (1.0 + ep)) * a.sig_scale;
             }
-            L.r[cidx(L, i, j, k)] = (T)res;
-            rr += res * res;
+        }
+        res[z] = r;
+        if (live) {
+            rr += r * r;
             ff += f * f;
         }
+    }
+    if (!live) return;
+#pragma unroll
+    for (int z = 0; z < ZT; ++z) {
+        const int k = k0 + z;
+        if (k >= nzd) break;
+        if (MODE == 2) phi_out[k * nxy + col] = vc[z + 1];
+        if (fl[z] & PF_SC) L.sig[sidx(L, i, j, k)] = (T)sg[z];
+        L.r[cidx(L, i, j, k)] = (T)res[z];
     }
 }
 
@@ -957,16 +1039,19 @@ __global__ __launch_bounds__(256) void k_restrict(const Inst<T> *I, Work w, int 
     const int I0 = t.tx * BX + threadIdx.x;
     const int J0 = t.ty * BY + threadIdx.y;
     if (I0 >= C.nx || J0 >= C.ny) return;
-    restrict_cell(gview(a.lv[level]), C, xview(a.xf[level]), I0, J0, t.tz);
+    const Lv<T, 1> F = gview(a.lv[level]);
+    const Xv<T> X = xview(a.xf[level]);
+    if (F.rb && X.xy) restrict_cell_rbxy(F, C, X, I0, J0, t.tz);
+    else restrict_cell(F, C, X, I0, J0, t.tz);
 }
 
 // A thread per column of kProZ planes (black cells only on a red/black
-// level): every correction is formed before any cell is updated, so the
-// column's loads are all in flight together.
+// level): every correction is formed, and every corrected cell read, before
+// any cell is updated, so the column's loads are all in flight together.
 template <bool XY, typename T>
 __device__ __forceinline__ void prolong_column(const Lv<T, 1> &F, const Lv<T, 1> &C, const Xv<T> &X, int m, int j,
                                                int k0) {
-    T v[kProZ];
+    T v[kProZ], e[kProZ];
     int c[kProZ];
 #pragma unroll
     for (int z = 0; z < kProZ; ++z) {
@@ -974,10 +1059,11 @@ __device__ __forceinline__ void prolong_column(const Lv<T, 1> &F, const Lv<T, 1>
         const int i = F.rb ? 2 * m + ((1 + j + k) & 1) : m;
         v[z] = prolong_value<XY>(C, X, i, j, k);
         c[z] = cidx(F, i, j, k);
+        e[z] = F.e[c[z]];          // read before any store: a store could alias it
     }
 #pragma unroll
     for (int z = 0; z < kProZ; ++z)
-        if (k0 + z < F.nz) F.e[c[z]] += v[z];
+        if (k0 + z < F.nz) F.e[c[z]] = e[z] + v[z];
 }
 
 template <typename T>
