@@ -80,6 +80,10 @@ __device__ __forceinline__ Blk find_block(const Work &w) {
     r.inst = 0;
     r.t = 0;
     if (!r.ok) return r;
+    if (w.ninst == 1) {                       // prefix[0] = 0: no table lookup
+        r.t = g;
+        return r;
+    }
     const int FX_AS(1) *pre = asp<1>(w.prefix);
     int lo = 0, hi = w.ninst;                 // largest lo with prefix[lo] <= g
     while (hi - lo > 1) {
