@@ -196,6 +196,11 @@ struct SmoothCfg {
 template <typename T> void launch_smooth(const Inst<T> *I, const Work &w, int level, int color, int zero_init,
                                          int upd, const SmoothCfg &c, double *probe, hipStream_t st,
                                          hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
+// the first two half-sweeps of a cycle on a level stored red/black at every
+// instance (zero start, red then black) as one launch; the same values as the
+// two separate launches
+template <typename T> void launch_smooth_zpair(const Inst<T> *I, const Work &w, int level, const SmoothCfg &c,
+                                               hipStream_t st);
 template <typename T> void launch_restrict(const Inst<T> *I, const Work &w, int level, hipStream_t st);
 template <typename T> void launch_prolong(const Inst<T> *I, const Work &w, int level, hipStream_t st);
 template <typename T> void launch_coarse(const Inst<T> *I, int ninst, int lds_bytes, hipStream_t st);

@@ -882,6 +882,17 @@ __global__ __launch_bounds__(1024) void k_reduce(const Inst<T> *I, int count_cyc
 }
 
 // ----------------------------------------------------------------- smoother
+// Neighbour sum of a red/black cell from the other colour's six values (the
+// z terms vanish on the contact planes); one expression shared by every kernel
+// that updates a cell, so that they round alike.
+template <typename T>
+__device__ __forceinline__ T rb_nb_sum(const Lv<T, 1> &L, int k, T ex0, T ex1, T ey0, T ey1, T ez0, T ez1) {
+    const T cx = L.cxy[k];
+    const T cy = L.ny > 1 ? cx : T(0);
+    return cx * (ex0 + ex1) + cy * (ey0 + ey1) + (k > 0 ? L.czm[k] : T(0)) * ez0 +
+           (k < L.nz - 1 ? L.czp[k] : T(0)) * ez1;
+}
+
 // One colour of red-black Gauss-Seidel on (L + diag sigma) e = r.  Split
 // storage: a thread per cell of that colour, ZT planes per thread with all
 // loads issued first; plainly stored levels: a thread per cell and ZT planes
@@ -945,12 +956,7 @@ __device__ __forceinline__ void smooth_rb_body(const Inst<T> &a, const Lv<T, 1> 
         const int k = min(tt.tz * ZT + z, L.nz - 1);
         const bool hs = k >= L.sig_lo && k < L.sig_hi;
         T acc = 0;
-        if (!ZI) {
-            const T cx = L.cxy[k];
-            const T cy = L.ny > 1 ? cx : T(0);
-            acc = cx * (ex0[z] + ex1[z]) + cy * (ey0[z] + ey1[z]) + (k > 0 ? L.czm[k] : T(0)) * ez0[z] +
-                  (k < L.nz - 1 ? L.czp[k] : T(0)) * ez1[z];
-        }
+        if (!ZI) acc = rb_nb_sum(L, k, ex0[z], ex1[z], ey0[z], ey1[z], ez0[z], ez1[z]);
         out[z] = (rr[z] + acc) / (L.dg[k] + (hs ? sg[z] : T(0)));
     }
 #pragma unroll
@@ -987,6 +993,66 @@ __device__ __forceinline__ void smooth_nat_body(const Lv<T, 1> &L, int t, int co
         }
         gs_cell(L, i, j, k, zero_init);
     }
+}
+
+// Zero-start pair on a red/black level: the first red half-sweep of a cycle
+// (the correction starts at zero, so a red value is r / diag) and the black
+// half-sweep after it, in one launch.  A thread per black cell forms the six red
+// neighbour values itself, exactly as the red sweep computes them, and also
+// stores the red cell of its own (2m, 2m+1) pair, which is one of its two x
+// neighbours: the pairs tile each row, so every red cell is written once, with
+// the value the red launch would have written.
+template <typename T, int ZT>
+__device__ __forceinline__ void smooth_zpair_body(const Lv<T, 1> &L, int t, int lbx) {
+    const int hx = L.nx >> 1;
+    const T3 tt = split3r(t, hx, L.ny, lbx);
+    const int m = (tt.tx << lbx) + (threadIdx.x & ((1 << lbx) - 1));
+    const int j = (tt.ty << (8 - lbx)) + (threadIdx.x >> lbx);
+    if (m >= hx || j >= L.ny) return;
+    const int half = (L.nx * L.ny * L.nz) >> 1;
+    const int plane = L.ny * hx;
+    const int hsz = (L.nx * L.ny * (L.sig_hi - L.sig_lo)) >> 1;
+    T FX_AS(1) *e_red = L.e;
+    T FX_AS(1) *e_blk = L.e + half;
+    const T FX_AS(1) *r_red = L.r, *r_blk = L.r + half;
+    const int oy0 = L.ny > 1 ? (wrap_p(j, L.ny) - j) * hx : 0;
+    const int oy1 = L.ny > 1 ? (wrap_m(j, L.ny) - j) * hx : 0;
+    // red value at red index c of plane kk after a zero-start red half-sweep
+    auto red = [&](int c, int kk) {
+        const bool hs = kk >= L.sig_lo && kk < L.sig_hi;
+        const T sg = L.sig[hs ? (kk - L.sig_lo) * plane + (c - kk * plane) : 0];
+        return (r_red[c] + T(0)) / (L.dg[kk] + (hs ? sg : T(0)));
+    };
+#pragma unroll
+    for (int z = 0; z < ZT; ++z) {
+        const int k = tt.tz * ZT + z;
+        if (k >= L.nz) break;
+        const int row = k * plane + j * hx;
+        const int q = row + m;
+        const int i = 2 * m + ((1 + j + k) & 1);
+        const int ip = i + 1 == L.nx ? 0 : i + 1, im = i == 0 ? L.nx - 1 : i - 1;
+        const bool hs = k >= L.sig_lo && k < L.sig_hi;
+        const T rb = r_blk[q];
+        const T sb = L.sig[hs ? hsz + (k - L.sig_lo) * plane + j * hx + m : 0];
+        const T ex0 = red(row + (ip >> 1), k), ex1 = red(row + (im >> 1), k);
+        const T ey0 = red(q + oy0, k), ey1 = red(q + oy1, k);
+        const T ez0 = k > 0 ? red(q - plane, k - 1) : red(q, k);
+        const T ez1 = k < L.nz - 1 ? red(q + plane, k + 1) : red(q, k);
+        const T acc = rb_nb_sum(L, k, ex0, ex1, ey0, ey1, ez0, ez1);
+        e_blk[q] = (rb + acc) / (L.dg[k] + (hs ? sb : T(0)));
+        e_red[q] = (i & 1) ? ex1 : ex0;                  // the pair's red cell: x - 1 or x + 1
+    }
+}
+
+template <typename T, int ZT>
+__global__ __launch_bounds__(256) void k_smooth_zpair(const Inst<T> *I, Work w, int level, int lbx) {
+    const Blk b = find_block(w);
+    if (!b.ok) return;
+    const Inst<T> &a = I[b.inst];
+    if (asp<1>(a.st)->done) return;
+    const Lv<T, 1> L = gview(a.lv[level]);
+    if (!L.rb) return;                               // the host fuses only all-red/black levels
+    smooth_zpair_body<T, ZT>(L, b.t, lbx);
 }
 
 // probe (instrumentation): the first tile of each instance that works adds
@@ -1539,6 +1605,18 @@ void launch_smooth(const Inst<T> *I, const Work &w, int level, int color, int ze
 }
 
 template <typename T>
+void launch_smooth_zpair(const Inst<T> *I, const Work &w, int level, const SmoothCfg &c, hipStream_t st) {
+    if (w.total <= 0) return;
+    const dim3 g = grid_of(w.total);
+    switch (c.zt) {
+        case 8: hipLaunchKernelGGL((k_smooth_zpair<T, 8>), g, dim3(256), 0, st, I, w, level, c.lbx); break;
+        case 4: hipLaunchKernelGGL((k_smooth_zpair<T, 4>), g, dim3(256), 0, st, I, w, level, c.lbx); break;
+        case 2: hipLaunchKernelGGL((k_smooth_zpair<T, 2>), g, dim3(256), 0, st, I, w, level, c.lbx); break;
+        default: hipLaunchKernelGGL((k_smooth_zpair<T, 1>), g, dim3(256), 0, st, I, w, level, c.lbx); break;
+    }
+}
+
+template <typename T>
 void launch_restrict(const Inst<T> *I, const Work &w, int level, hipStream_t st) {
     FX_LAUNCH(k_restrict<T>, w, I, w, level);
 }
@@ -1598,6 +1676,7 @@ void launch_fill(double *x, size_t n, double v, hipStream_t st) {
     template void launch_reduce<T>(const Inst<T> *, int, int, hipStream_t);                                  \
     template void launch_smooth<T>(const Inst<T> *, const Work &, int, int, int, int, const SmoothCfg &,     \
                                    double *, hipStream_t, hipEvent_t, hipEvent_t);                           \
+    template void launch_smooth_zpair<T>(const Inst<T> *, const Work &, int, const SmoothCfg &, hipStream_t); \
     template void launch_restrict<T>(const Inst<T> *, const Work &, int, hipStream_t);                       \
     template void launch_prolong<T>(const Inst<T> *, const Work &, int, hipStream_t);                        \
     template void launch_coarse<T>(const Inst<T> *, int, int, hipStream_t);                                  \

@@ -795,8 +795,16 @@ void enq_vcycle(Engine *e) {
     const Inst<T> *I = idev<T>(e);
     for (int l = 0; l < e->max_lc; ++l) {
         const int nu1 = l == 0 ? e->nu1 : e->nu1c;
-        for (int q = 0; q < nu1; ++q)
+        // below the finest level (whose launches the probe times one by one) the
+        // zero-start red and black half-sweeps of a red/black level are one launch
+        const bool zpair = l > 0 && e->ncol[l] == 2 && e->w_sm[l].total > 0;
+        for (int q = 0; q < nu1; ++q) {
+            if (q == 0 && zpair) {
+                launch_smooth_zpair(I, e->w_sm[l], l, e->scfg[l], e->st);
+                continue;
+            }
             for (int c = 0; c < e->ncol[l]; ++c) smooth_l<T>(e, l, c, q == 0 && c == 0, 0);
+        }
         launch_restrict(I, e->w_rs[l], l, e->st);
     }
     launch_coarse(I, e->n, e->lds_max, e->st);
