@@ -201,6 +201,11 @@ template <typename T> void launch_smooth(const Inst<T> *I, const Work &w, int le
 // two separate launches
 template <typename T> void launch_smooth_zpair(const Inst<T> *I, const Work &w, int level, const SmoothCfg &c,
                                                hipStream_t st);
+// prolongation into a level stored red/black at every instance fused with the
+// red half-sweep after it (the corrected black values are not stored: the
+// black half-sweep that follows overwrites them without reading them)
+template <typename T> void launch_prolong_red(const Inst<T> *I, const Work &w, int level, const SmoothCfg &c,
+                                              hipStream_t st);
 template <typename T> void launch_restrict(const Inst<T> *I, const Work &w, int level, hipStream_t st);
 template <typename T> void launch_prolong(const Inst<T> *I, const Work &w, int level, hipStream_t st);
 template <typename T> void launch_coarse(const Inst<T> *I, int ninst, int lds_bytes, hipStream_t st);

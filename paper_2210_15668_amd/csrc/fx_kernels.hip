@@ -1136,6 +1136,66 @@ __device__ __forceinline__ void prolong_column(const Lv<T, 1> &F, const Lv<T, 1>
         if (k0 + z < F.nz) F.e[c[z]] = e[z] + v[z];
 }
 
+// Prolongation fused with the red half-sweep after it, on a red/black level:
+// the correction touches only black cells, and the black half-sweep that
+// follows recomputes every black cell without reading it, so the corrected
+// black values are needed by this red half-sweep alone.  A thread per red cell
+// corrects its six black neighbours in registers (same operands, same order as
+// prolong_column) and updates itself from them (same expression as the red
+// half-sweep); nothing but the red cells is stored.
+template <bool XY, typename T, int ZT>
+__device__ __forceinline__ void prolong_red_body(const Lv<T, 1> &F, const Lv<T, 1> &C, const Xv<T> &X, int t,
+                                                 int lbx) {
+    const int hx = F.nx >> 1;
+    const T3 tt = split3r(t, hx, F.ny, lbx);
+    const int m = (tt.tx << lbx) + (threadIdx.x & ((1 << lbx) - 1));
+    const int j = (tt.ty << (8 - lbx)) + (threadIdx.x >> lbx);
+    if (m >= hx || j >= F.ny) return;
+    const int half = (F.nx * F.ny * F.nz) >> 1;
+    const int plane = F.ny * hx;
+    const T FX_AS(1) *eb = F.e + half;                 // black values before the correction
+    T FX_AS(1) *er = F.e;
+    const int jp = wrap_p(j, F.ny), jm = wrap_m(j, F.ny);
+    const int oy0 = (jp - j) * hx, oy1 = (jm - j) * hx;
+    // corrected black value at black index c, fine cell (i, jj, kk)
+    auto blk = [&](int c, int i, int jj, int kk) { return eb[c] + prolong_value<XY>(C, X, i, jj, kk); };
+#pragma unroll
+    for (int z = 0; z < ZT; ++z) {
+        const int k = tt.tz * ZT + z;
+        if (k >= F.nz) break;
+        const int row = k * plane + j * hx;
+        const int q = row + m;
+        const int i = 2 * m + ((j + k) & 1);
+        const int ip = i + 1 == F.nx ? 0 : i + 1, im = i == 0 ? F.nx - 1 : i - 1;
+        const bool hs = k >= F.sig_lo && k < F.sig_hi;
+        const T rr = F.r[q];
+        const T sg = F.sig[hs ? (k - F.sig_lo) * plane + j * hx + m : 0];
+        const T ex0 = blk(row + (ip >> 1), ip, j, k), ex1 = blk(row + (im >> 1), im, j, k);
+        // one row (ny = 1): the y terms carry a zero coefficient and read the
+        // pair's black cell, as the red half-sweep does
+        const T ey0 = F.ny > 1 ? blk(q + oy0, i, jp, k) : blk(q, i ^ 1, j, k);
+        const T ey1 = F.ny > 1 ? blk(q + oy1, i, jm, k) : blk(q, i ^ 1, j, k);
+        const T ez0 = k > 0 ? blk(q - plane, i, j, k - 1) : blk(q, i ^ 1, j, k);
+        const T ez1 = k < F.nz - 1 ? blk(q + plane, i, j, k + 1) : blk(q, i ^ 1, j, k);
+        const T acc = rb_nb_sum(F, k, ex0, ex1, ey0, ey1, ez0, ez1);
+        er[q] = (rr + acc) / (F.dg[k] + (hs ? sg : T(0)));
+    }
+}
+
+template <typename T, int ZT>
+__global__ __launch_bounds__(256) void k_prolong_red(const Inst<T> *I, Work w, int level, int lbx) {
+    const Blk b = find_block(w);
+    if (!b.ok) return;
+    const Inst<T> &a = I[b.inst];
+    if (asp<1>(a.st)->done) return;
+    const Lv<T, 1> F = gview(a.lv[level]);
+    if (!F.rb) return;                               // the host fuses only all-red/black levels
+    const Lv<T, 1> C = gview(a.lv[level + 1]);
+    const Xv<T> X = xview(a.xf[level]);
+    if (X.xy) prolong_red_body<true, T, ZT>(F, C, X, b.t, lbx);
+    else prolong_red_body<false, T, ZT>(F, C, X, b.t, lbx);
+}
+
 template <typename T>
 __global__ __launch_bounds__(256) void k_prolong(const Inst<T> *I, Work w, int level) {
     const Blk b = find_block(w);
@@ -1617,6 +1677,18 @@ void launch_smooth_zpair(const Inst<T> *I, const Work &w, int level, const Smoot
 }
 
 template <typename T>
+void launch_prolong_red(const Inst<T> *I, const Work &w, int level, const SmoothCfg &c, hipStream_t st) {
+    if (w.total <= 0) return;
+    const dim3 g = grid_of(w.total);
+    switch (c.zt) {
+        case 8: hipLaunchKernelGGL((k_prolong_red<T, 8>), g, dim3(256), 0, st, I, w, level, c.lbx); break;
+        case 4: hipLaunchKernelGGL((k_prolong_red<T, 4>), g, dim3(256), 0, st, I, w, level, c.lbx); break;
+        case 2: hipLaunchKernelGGL((k_prolong_red<T, 2>), g, dim3(256), 0, st, I, w, level, c.lbx); break;
+        default: hipLaunchKernelGGL((k_prolong_red<T, 1>), g, dim3(256), 0, st, I, w, level, c.lbx); break;
+    }
+}
+
+template <typename T>
 void launch_restrict(const Inst<T> *I, const Work &w, int level, hipStream_t st) {
     FX_LAUNCH(k_restrict<T>, w, I, w, level);
 }
@@ -1677,6 +1749,7 @@ void launch_fill(double *x, size_t n, double v, hipStream_t st) {
     template void launch_smooth<T>(const Inst<T> *, const Work &, int, int, int, int, const SmoothCfg &,     \
                                    double *, hipStream_t, hipEvent_t, hipEvent_t);                           \
     template void launch_smooth_zpair<T>(const Inst<T> *, const Work &, int, const SmoothCfg &, hipStream_t); \
+    template void launch_prolong_red<T>(const Inst<T> *, const Work &, int, const SmoothCfg &, hipStream_t);  \
     template void launch_restrict<T>(const Inst<T> *, const Work &, int, hipStream_t);                       \
     template void launch_prolong<T>(const Inst<T> *, const Work &, int, hipStream_t);                        \
     template void launch_coarse<T>(const Inst<T> *, int, int, hipStream_t);                                  \

@@ -334,6 +334,7 @@ struct Engine {
     std::vector<Work> w_sm, w_rs, w_pr;
     std::vector<SmoothCfg> scfg;        // smoother launch shape per level
     std::vector<int> ncol;
+    std::vector<char> small;            // per level: few enough cells that launch latency dominates
     int max_lc = 0, lds_max = 0, max_cycles = 1;
     int any_unfolded = 0;               // some instance forms phi + clip(e) in the residual kernel
     int any_order2 = 0;                 // some instance takes predictor-corrector steps
@@ -428,6 +429,7 @@ void plan_launches(Engine *e) {
     }
     e->scfg.assign(e->max_lc, SmoothCfg{6, 1, 0});
     e->ncol.assign(e->max_lc, 2);
+    e->small.assign(e->max_lc, 0);
     const int zt_env = env_int("FERROX_ZT", 0);
     for (int l = 0; l < e->max_lc; ++l) {
         size_t cells = 0;
@@ -442,6 +444,7 @@ void plan_launches(Engine *e) {
         // before tuning: large levels 4 planes per thread, small ones one plane per
         // thread for parallelism, 64 x 4 tiles
         e->scfg[l].zt = cells >= ((size_t)1 << 19) && min_nz >= 8 ? 4 : 1;
+        e->small[l] = cells < ((size_t)1 << 18);
         if (zt_env == 1 || zt_env == 2 || zt_env == 4 || zt_env == 8) e->scfg[l].zt = zt_env;
     }
 }
@@ -809,10 +812,18 @@ void enq_vcycle(Engine *e) {
     }
     launch_coarse(I, e->n, e->lds_max, e->st);
     for (int l = e->max_lc - 1; l >= 0; --l) {
-        launch_prolong(I, e->w_pr[l], l, e->st);
         const int nu2 = l == 0 ? e->nu2 : e->nu2c;
+        // on a small red/black level the correction is formed inside the first
+        // red half-sweep: one launch fewer, where launches cost more than the
+        // six interpolations per red cell the fused kernel repeats
+        const bool pred = l > 0 && e->small[l] && e->ncol[l] == 2 && e->w_sm[l].total > 0;
+        if (pred) launch_prolong_red(I, e->w_sm[l], l, e->scfg[l], e->st);
+        else launch_prolong(I, e->w_pr[l], l, e->st);
         for (int q = 0; q < nu2; ++q)
-            for (int c = 0; c < e->ncol[l]; ++c) smooth_l<T>(e, l, c, 0, l == 0 && q == nu2 - 1 && c == 1);
+            for (int c = 0; c < e->ncol[l]; ++c) {
+                if (pred && q == 0 && c == 0) continue;
+                smooth_l<T>(e, l, c, 0, l == 0 && q == nu2 - 1 && c == 1);
+            }
     }
 }
 
