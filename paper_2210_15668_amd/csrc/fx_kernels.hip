@@ -1236,27 +1236,12 @@ __device__ __forceinline__ void split_c(int c, const Split3 &s, int &i, int &j, 
     j = row - k * s.fy.d;
 }
 
-// Work split of a coarse-kernel phase: the whole workgroup (stride blockDim.x,
-// separated by workgroup barriers) or, on the smallest levels, the first wave
-// alone (stride 64).  One wave's LDS operations complete in program order, so
-// its phases only need the compiler kept from moving memory operations across
-// the boundary.
-template <bool WAVE>
-__device__ __forceinline__ void phase_sync() {
-    if (WAVE) {
-        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-    } else {
-        __syncthreads();
-    }
-}
-template <bool WAVE>
-__device__ __forceinline__ int phase_stride() { return WAVE ? 64 : (int)blockDim.x; }
-
-template <bool WAVE, typename V>
+// A coarse-kernel phase: the whole workgroup strides over the level's cells,
+// and a workgroup barrier separates it from the next phase.
+template <typename V>
 __device__ void smooth_color(const V &L, int color, int zero_init) {
     using T = typename V::value_type;
-    const int st = phase_stride<WAVE>();
+    const int st = (int)blockDim.x;
     if (L.rb) {
         const int hx = L.nx >> 1;
         const int n = hx * L.ny * L.nz;
@@ -1279,37 +1264,37 @@ __device__ void smooth_color(const V &L, int color, int zero_init) {
 }
 
 // One full Gauss-Seidel sweep (2 colours on split levels, 4 otherwise).
-template <bool WAVE, typename V>
+template <typename V>
 __device__ void smooth_sweep(const V &L, int zero_init) {
     const int ncol = L.rb ? 2 : 4;
     for (int c = 0; c < ncol; ++c) {
-        smooth_color<WAVE>(L, c, zero_init && c == 0);
-        phase_sync<WAVE>();
+        smooth_color(L, c, zero_init && c == 0);
+        __syncthreads();
     }
 }
 
 // Restriction into level C and prolongation from it, as one phase each.
-template <bool WAVE, typename T, typename X_>
+template <typename T, typename X_>
 __device__ void restrict_phase(const Lv<T, 3> &L, const Lv<T, 3> &C, const X_ &X) {
     const int n = C.nx * C.ny * C.nz;
     const Split3 sp{fdiv_of(C.nx), fdiv_of(C.ny)};
-    for (int c = threadIdx.x; c < n; c += phase_stride<WAVE>()) {
+    for (int c = threadIdx.x; c < n; c += blockDim.x) {
         int I0, J0, K0;
         split_c(c, sp, I0, J0, K0);
         restrict_cell(L, C, X, I0, J0, K0);
     }
-    phase_sync<WAVE>();
+    __syncthreads();
 }
-template <bool WAVE, typename T, typename X_>
+template <typename T, typename X_>
 __device__ void prolong_phase(const Lv<T, 3> &L, const Lv<T, 3> &C, const X_ &X) {
     const int n = L.nx * L.ny * L.nz;
     const Split3 sp{fdiv_of(L.nx), fdiv_of(L.ny)};
-    for (int c = threadIdx.x; c < n; c += phase_stride<WAVE>()) {
+    for (int c = threadIdx.x; c < n; c += blockDim.x) {
         int i, j, k;
         split_c(c, sp, i, j, k);
         prolong_cell(L, C, X, i, j, k);
     }
-    phase_sync<WAVE>();
+    __syncthreads();
 }
 
 // Dot product over a whole workgroup, accumulated in double in a fixed order
@@ -1524,15 +1509,15 @@ __global__ __launch_bounds__(512) void k_coarse(const Inst<T> *I) {
     }
     for (int q = 0; q < nl - 1; ++q) {
         const Lv<T, 3> L = lvl(q);
-        for (int s = 0; s < A.nu1; ++s) smooth_sweep<false>(L, s == 0);
-        restrict_phase<false>(L, lvl(q + 1), xlds(q));
+        for (int s = 0; s < A.nu1; ++s) smooth_sweep(L, s == 0);
+        restrict_phase(L, lvl(q + 1), xlds(q));
     }
     bottom_cg<T>(lvl(nl - 1), (T FX_AS(3) *)(lds + A.off_p), (T FX_AS(3) *)(lds + A.off_q),
                  (double FX_AS(3) *)(lds + A.off_red), A.bottom_iters, A.bottom_tol2);
     for (int q = nl - 2; q >= 0; --q) {
         const Lv<T, 3> L = lvl(q);
-        prolong_phase<false>(L, lvl(q + 1), xlds(q));
-        for (int s = 0; s < A.nu2; ++s) smooth_sweep<false>(L, 0);
+        prolong_phase(L, lvl(q + 1), xlds(q));
+        for (int s = 0; s < A.nu2; ++s) smooth_sweep(L, 0);
     }
     {
         const Lv<T, 1> G = gview(A.lv[l0]);
