@@ -340,6 +340,7 @@ struct Engine {
     int any_order2 = 0;                 // some instance takes predictor-corrector steps
     int nu1 = 2, nu2 = 2;               // sweeps before / after the coarse correction, finest level
     int nu1c = 2, nu2c = 2;             // the same on every coarser level
+    int fuse = 1;                       // fused launches below the finest level (same values)
     int k_pred = 4;                     // cycles enqueued before the first check of a plain solve
     int trace = 0;
     int ucap = 16;                      // units enqueued between host checks of a run
@@ -800,7 +801,7 @@ void enq_vcycle(Engine *e) {
         const int nu1 = l == 0 ? e->nu1 : e->nu1c;
         // below the finest level (whose launches the probe times one by one) the
         // zero-start red and black half-sweeps of a red/black level are one launch
-        const bool zpair = l > 0 && e->ncol[l] == 2 && e->w_sm[l].total > 0;
+        const bool zpair = e->fuse && l > 0 && e->ncol[l] == 2 && e->w_sm[l].total > 0;
         for (int q = 0; q < nu1; ++q) {
             if (q == 0 && zpair) {
                 launch_smooth_zpair(I, e->w_sm[l], l, e->scfg[l], e->st);
@@ -816,7 +817,7 @@ void enq_vcycle(Engine *e) {
         // on a small red/black level the correction is formed inside the first
         // red half-sweep: one launch fewer, where launches cost more than the
         // six interpolations per red cell the fused kernel repeats
-        const bool pred = l > 0 && e->small[l] && e->ncol[l] == 2 && e->w_sm[l].total > 0;
+        const bool pred = e->fuse && l > 0 && e->small[l] && e->ncol[l] == 2 && e->w_sm[l].total > 0;
         if (pred) launch_prolong_red(I, e->w_sm[l], l, e->scfg[l], e->st);
         else launch_prolong(I, e->w_pr[l], l, e->st);
         for (int q = 0; q < nu2; ++q)
@@ -1116,6 +1117,7 @@ fx_status engine_init(Engine *e, double *const *d_P, double *const *d_phi, void 
     e->nu2 = std::max(1, env_int("FERROX_NU2", 2));
     e->nu1c = std::max(1, env_int("FERROX_NU1C", e->nu1));
     e->nu2c = std::max(1, env_int("FERROX_NU2C", e->nu2));
+    e->fuse = env_int("FERROX_FUSE", 1) != 0;
     e->trace = env_int("FERROX_TRACE", 0);
     e->ucap = std::max(1, std::min(1 << (kUnitPow - 1), env_int("FERROX_UNITS", 16)));
     for (int i = 0; i < e->n; ++i) {

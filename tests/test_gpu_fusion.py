@@ -1,0 +1,79 @@
+"""The fused launches below the finest level -- the zero-start red/black pair and, on small
+levels, the prolongation formed inside the first red half-sweep -- reproduce the separate
+launches bit for bit (FERROX_FUSE=0 keeps every half-sweep and prolongation a launch of its
+own), for single stacks in both precisions and for a batch; the fused stack also meets the
+oracle's 1e-10 parity bar."""
+import sys
+
+import numpy as np
+import pytest
+
+from paper_2210_15668_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def rel(a, b):
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+@pytest.fixture(scope="module")
+def fx():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2210_15668_amd import ferrox
+    ferrox.lib()
+    return ferrox
+
+
+def run_stack(fx, monkeypatch, fuse, spec, P0, n):
+    monkeypatch.setenv("FERROX_FUSE", fuse)
+    s = fx.Stack(spec, P0)
+    info = s.run_steps(n, W.DT)
+    out = s.get(fx.FIELD_P), s.get(fx.FIELD_PHI), info.total_cycles
+    s.close()
+    return out
+
+
+@pytest.mark.parametrize("prec", [W.PREC_FP64, W.PREC_MIXED])
+def test_fused_equals_separate_launches_on_a_stack(fx, orc, monkeypatch, prec):
+    # 64 x 64 MFISM: levels 1.. are red/black and under 2^18 cells, so both fusions run
+    spec = W.shrink_lateral(W.mfism_large(prec), 64, 64).copy(tol_rel=1e-12)
+    P0 = W.random_P(spec, 90, amp=0.05)
+    n = 6
+    say(f"  prec {prec}: fused ...")
+    Pf, phif, cf = run_stack(fx, monkeypatch, "1", spec, P0, n)
+    say(f"  prec {prec}: separate ...")
+    Ps, phis, cs = run_stack(fx, monkeypatch, "0", spec, P0, n)
+    say(f"  V-cycles fused {cf} separate {cs}")
+    assert cf == cs
+    assert np.array_equal(Pf, Ps) and np.array_equal(phif, phis)
+    if prec == W.PREC_FP64:
+        P_o, phi_o, _ = orc.run(spec, P0, n, W.DT, tol=1e-12)
+        rp, rf = rel(Pf, P_o), rel(phif, phi_o)
+        say(f"  vs oracle: relP {rp:.2e} relphi {rf:.2e}")
+        assert rp <= 1e-10 and rf <= 1e-10
+
+
+def test_fused_equals_separate_launches_in_a_batch(fx, monkeypatch):
+    specs = [W.layered(32, 32, 32, [(W.FE, 16, W.EPS_FE, 0.0), (W.DE, 4, W.EPS_SIO2, 0.0)], v_top=0.5,
+                       tol_rel=1e-12),
+             W.layered(48, 32, 48, [(W.FE, 24, W.EPS_FE, 0.0), (W.DE, 4, W.EPS_SIO2, 0.0),
+                                    (W.SC, 12, W.EPS_SI, 1e24)], v_top=-0.8, tol_rel=1e-12, time_order=2)]
+    Ps = [W.random_P(sp, 91 + q, amp=0.05) for q, sp in enumerate(specs)]
+    out = {}
+    for fuse in ("1", "0"):
+        monkeypatch.setenv("FERROX_FUSE", fuse)
+        b = fx.Batch(specs, Ps)
+        info = b.run(5, W.DT)
+        assert all(i.status == fx.FX_OK and i.steps_done == 5 for i in info)
+        out[fuse] = [(b.get(q, fx.FIELD_P), b.get(q, fx.FIELD_PHI)) for q in range(len(specs))]
+        b.close()
+    for q in range(len(specs)):
+        assert np.array_equal(out["1"][q][0], out["0"][q][0]) and np.array_equal(out["1"][q][1], out["0"][q][1]), q
