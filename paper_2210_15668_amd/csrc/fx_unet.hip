@@ -143,6 +143,122 @@ __global__ __launch_bounds__(256) void k_conv3(const bf16_t *__restrict__ X, int
 // reads 512 contiguous bytes per fragment: no bank conflicts).  Needs nx a
 // multiple of 64 and ny a multiple of 4.
 // Move a 4 x bf16 fragment between lanes of a 16-lane row with DPP (register only).
+
+// The same convolution for small grids with the reduction split over the four
+// waves of a block: a block owns 16 NTW voxels and every output channel, each
+// wave a quarter of the (16-channel chunk, tap) products in the order of
+// k_conv3, and wave 0 adds the four partial sums in a fixed order
+// (deterministic).  On the coarsest level (32 x 32 x 15 voxels) a wave of
+// k_conv3 walks all 27 CIN/16 products one after another; here each wave walks
+// a quarter of them with NTW voxel tiles per weight fragment (the fragments of
+// 64 output channels, a quarter used per cache line, are the traffic that bounds
+// these layers).
+template <int CIN, int COUT, int NTW, int OUT>
+__global__ __launch_bounds__(256) void k_conv3k(const bf16_t *__restrict__ X, int ldx, const bf16_t *__restrict__ Wt,
+                                                const float *__restrict__ bias, void *Yv, int ldy, int nx, int ny,
+                                                int nz) {
+    constexpr int MT = COUT / 16, KC = CIN / 16, NIT = KC * 27;
+    __shared__ f4 part[3][MT][NTW][64];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int n = nx * ny * nz;
+    const int col = lane & 15, kq = lane >> 4;
+    int px[NTW], py[NTW], pz[NTW];
+    bool ok[NTW];
+#pragma unroll
+    for (int t = 0; t < NTW; ++t) {
+        const int v = (blockIdx.x * NTW + t) * 16 + col;
+        ok[t] = v < n;
+        const int vv = ok[t] ? v : 0;
+        px[t] = vv % nx;
+        const int q = vv / nx;
+        py[t] = q % ny;
+        pz[t] = q / ny;
+    }
+    f4 acc[MT][NTW];
+#pragma unroll
+    for (int m = 0; m < MT; ++m)
+#pragma unroll
+        for (int t = 0; t < NTW; ++t) acc[m][t] = f4{0.f, 0.f, 0.f, 0.f};
+    const s4 zero4 = {0, 0, 0, 0};
+    const int it0 = wave * NIT / 4, it1 = (wave + 1) * NIT / 4;
+    // operands of product it: the input fragments (zero beyond the z-ends, read
+    // from a valid row and discarded there, so that no load sits under a branch)
+    // and the weight fragments of every output tile
+    auto fetch = [&](int it, s4 *b, s4 *a) {
+        const int kc = it / 27, tap = it - kc * 27;
+        const int dz = tap / 9 - 1, dy = (tap / 3) % 3 - 1, dx = tap % 3 - 1;
+#pragma unroll
+        for (int t = 0; t < NTW; ++t) {
+            const int z2 = pz[t] + dz;
+            int y2 = py[t] + dy, x2 = px[t] + dx;
+            y2 = y2 < 0 ? y2 + ny : (y2 >= ny ? y2 - ny : y2);
+            x2 = x2 < 0 ? x2 + nx : (x2 >= nx ? x2 - nx : x2);
+            const bool in = ok[t] && z2 >= 0 && z2 < nz;
+            const int nb = in ? (z2 * ny + y2) * nx + x2 : 0;
+            const s4 bv = *(const s4 *)(X + (size_t)nb * ldx + kc * 16 + 4 * kq);
+            b[t] = in ? bv : zero4;
+        }
+        const bf16_t *wtap = Wt + (size_t)tap * COUT * CIN + kc * 16 + 4 * kq;
+#pragma unroll
+        for (int m = 0; m < MT; ++m) a[m] = *(const s4 *)(wtap + (size_t)(m * 16 + col) * CIN);
+    };
+    // groups of G products: all their loads first, then their MFMAs in order
+    constexpr int G = (MT + 1) * NTW <= 20 ? 3 : 1;
+    int it = it0;
+    for (; it + G <= it1; it += G) {
+        s4 b[G][NTW], a[G][MT];
+#pragma unroll
+        for (int u = 0; u < G; ++u) fetch(it + u, b[u], a[u]);
+#pragma unroll
+        for (int u = 0; u < G; ++u)
+#pragma unroll
+            for (int m = 0; m < MT; ++m)
+#pragma unroll
+                for (int t = 0; t < NTW; ++t)
+                    acc[m][t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[u][m], b[u][t], acc[m][t], 0, 0, 0);
+    }
+    for (; it < it1; ++it) {
+        s4 b[NTW], a[MT];
+        fetch(it, b, a);
+#pragma unroll
+        for (int m = 0; m < MT; ++m)
+#pragma unroll
+            for (int t = 0; t < NTW; ++t)
+                acc[m][t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[m], b[t], acc[m][t], 0, 0, 0);
+    }
+    if (wave > 0) {
+#pragma unroll
+        for (int m = 0; m < MT; ++m)
+#pragma unroll
+            for (int t = 0; t < NTW; ++t) part[wave - 1][m][t][lane] = acc[m][t];
+    }
+    __syncthreads();
+    if (wave > 0) return;
+#pragma unroll
+    for (int t = 0; t < NTW; ++t) {
+        if (!ok[t]) continue;
+        const size_t v = (size_t)(blockIdx.x * NTW + t) * 16 + col;
+#pragma unroll
+        for (int m = 0; m < MT; ++m) {
+            f4 s = acc[m][t];
+            s = s + part[0][m][t][lane];
+            s = s + part[1][m][t][lane];
+            s = s + part[2][m][t][lane];
+            const int co = m * 16 + 4 * kq;
+            if (OUT == 0) {
+                s4 o;
+#pragma unroll
+                for (int r = 0; r < 4; ++r) o[r] = (short)f2bf(fmaxf(s[r] + bias[co + r], 0.f));
+                *(s4 *)((bf16_t *)Yv + v * ldy + co) = o;
+            } else {
+                f4 *dst = (f4 *)((float *)Yv + v * ldy + co);
+                if (OUT == 2) *dst = *dst + s;
+                else *dst = s;
+            }
+        }
+    }
+}
+
 template <int CTRL>
 __device__ __forceinline__ s4 dpp_s4(s4 v) {
     union {
@@ -608,6 +724,17 @@ void conv_launch(const bf16_t *X, int ldx, const bf16_t *W, const float *b, void
         return;
     }
     const int n = nx * ny * nz, per = 64 * NTW;
+    // small grid the staged kernel cannot take: reduction split over the waves (where
+    // the staged kernel applies, the direct one keeps its accumulation order)
+    if constexpr (NTW == 1 && CIN >= 32) {
+        if (!(nx % 64 == 0 && ny % 4 == 0)) {
+            // four voxel tiles per weight fragment where there are four output tiles
+            constexpr int KT = COUT >= 64 ? 4 : 1;
+            hipLaunchKernelGGL((k_conv3k<CIN, COUT, KT, OUT>), dim3((n + 16 * KT - 1) / (16 * KT)), dim3(256), 0, st, X,
+                               ldx, W, b, Y, ldy, nx, ny, nz);
+            return;
+        }
+    }
     hipLaunchKernelGGL((k_conv3<CIN, COUT, NTW, OUT>), dim3((n + per - 1) / per, CIN <= 32 ? COUT / 16 : 1), dim3(256),
                        0, st, X, ldx, W, b, Y, ldy, nx, ny, nz);
 }
