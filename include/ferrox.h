@@ -118,10 +118,12 @@ typedef struct {
                                     forward-Euler Steps 1a + 1b; 2 the predictor-corrector
                                     Steps 1a, 1b, 2a, 2b (two solves per step; each
                                     predictor solve starts from the extrapolation plus the
-                                    last step's phi* - phi^n, which takes one more full
-                                    grid of workspace and, unlike the stored levels, is not
-                                    part of a field checkpoint: a restarted run reaches the
-                                    same roots, not the same bits)                        */
+                                    last step's phi* - phi^n, each corrector solve from the
+                                    extrapolation through phi^n .. phi^{n-3}; this takes two
+                                    more full grids of workspace, phi* and phi^{n-3}, which,
+                                    unlike the levels n-1 .. n-3, are not part of a field
+                                    checkpoint: a restarted run reaches the same roots, not
+                                    the same bits)                                        */
     int carriers;                /* fx_carriers: semiconductor carrier statistics           */
     double m_e, m_p;             /* effective masses / free-electron mass (FX_CARRIERS_FD;
                                     Table 1: 1.08 and 0.81)                                 */

@@ -46,9 +46,12 @@ __host__ __device__ inline void fd_half(double eta, double &F, double &dF) {
 enum : int { PF_SC = 1, PF_P = 2 };
 
 constexpr int kMaxLevels = 24;
-constexpr int kPhiBufs = 7;       // phi^n, up to 3 stored levels, two iterate buffers, and for
-                                  // predictor-corrector instances the last predictor's phi*
-constexpr int kMaxHist = 3;
+constexpr int kMaxOrder = 3;      // highest order of the extrapolated starting iterate
+constexpr int kPhiBufs = 8;       // phi^n, up to 3 stored levels, two iterate buffers; for
+                                  // predictor-corrector instances a fourth stored level (the
+                                  // corrector extrapolates through phi^n .. phi^{n-3}) and
+                                  // the last predictor's phi*
+constexpr int kMaxHist = 4;       // stored levels of a predictor-corrector instance (Euler: 3)
 constexpr int kCoarseLdsBytes = 64 * 1024;
 constexpr int kQvBlocks = 8;      // blocks per instance of the interface-plane reductions
 constexpr int kRecSteps = 1024;   // recorded steps per instance held on the device
@@ -67,7 +70,7 @@ constexpr int kRecSteps = 1024;   // recorded steps per instance held on the dev
 struct InstState {
     int done, cycles;
     int cur, start, oth0, oth1;       // phi buffers: phi^n, iterate before cycle 0, cycle outputs
-    int prev[kMaxHist], hist;         // stored time levels phi^{n-1..n-3}
+    int prev[kMaxHist], hist;         // stored time levels phi^{n-1..n-4}
     int order;                        // extrapolation order of this solve
     int zpend;                        // right-hand side exactly zero with a nonzero residual
     int zero_fix;                     // phi := 0 for the solve finalized in this slot
@@ -122,7 +125,7 @@ struct Inst {
     int nlev, lc, fold;                // levels; first level of the coarse kernel; update folded into smoothing
     int max_cycles, warm;
     int order2;                        // predictor-corrector time steps
-    int nbuf;                          // phi buffers in use (kPhiBufs - 1 without order2)
+    int nbuf;                          // phi buffers in use (kPhiBufs - 2 without order2)
     double tol2;
     // TDGL
     double h, alpha, beta, gamma, g11, g44, Gamma, lambda;

@@ -568,9 +568,12 @@ __global__ void k_head(const Inst<T> *I, int ninst, int advance) {
                 // Euler step, or the predictor of a second-order step: phi^n
                 // becomes the newest stored level
                 if (fin != s->cur) {
-                    for (int m = kMaxHist - 1; m > 0; --m) s->prev[m] = s->prev[m - 1];
+                    // Euler keeps 3 levels; a predictor-corrector instance 4, so that
+                    // its corrector, whose newest level is phi^n, extrapolates cubically
+                    const int hmax = I[n].order2 ? kMaxHist : kMaxHist - 1;
+                    for (int m = hmax - 1; m > 0; --m) s->prev[m] = s->prev[m - 1];
                     s->prev[0] = s->cur;
-                    s->hist = min(s->hist + 1, kMaxHist);
+                    s->hist = min(s->hist + 1, hmax);
                 } else {
                     s->hist = 0;
                 }

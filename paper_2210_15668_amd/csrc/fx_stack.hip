@@ -132,8 +132,8 @@ fx_status validate(const fx_stack_desc *d, Plan *p) {
         return fail(FX_EINVAL, "plane tables must not be NULL");
     if (d->prec != FX_PREC_FP64 && d->prec != FX_PREC_MIXED) return fail(FX_EINVAL, "unknown precision");
     if (!(d->tol_rel > 0) || d->max_cycles < 1) return fail(FX_EINVAL, "tol_rel > 0 and max_cycles >= 1 required");
-    if (d->warm_start < 0 || d->warm_start > kMaxHist)
-        return fail(FX_EINVAL, "warm_start must be 0..%d", kMaxHist);
+    if (d->warm_start < 0 || d->warm_start > kMaxOrder)
+        return fail(FX_EINVAL, "warm_start must be 0..%d", kMaxOrder);
     if (d->time_order < 0 || d->time_order > 2) return fail(FX_EINVAL, "time_order must be 0, 1 or 2");
     if (d->carriers != FX_CARRIERS_BOLTZMANN && d->carriers != FX_CARRIERS_FD)
         return fail(FX_EINVAL, "carriers must be FX_CARRIERS_BOLTZMANN or FX_CARRIERS_FD");
@@ -476,7 +476,7 @@ size_t carve(Engine *e, void *ws) {
         const Plan &p = h.plan;
         const size_t nfull = (size_t)p.nx * p.ny * p.nz;
         h.P[1] = (double *)cv.take(nfull * sizeof(double));
-        const int nbuf = h.d.time_order == 2 ? kPhiBufs : kPhiBufs - 1;
+        const int nbuf = h.d.time_order == 2 ? kPhiBufs : kPhiBufs - 2;
         for (int b = 1; b < nbuf; ++b) h.phi[b] = (double *)cv.take(nfull * sizeof(double));
         const int nzd = p.nzd;
         h.t_cxy = (double *)cv.take(nzd * sizeof(double));
@@ -622,7 +622,7 @@ Inst<T> make_inst(const Engine *e, int i) {
     a.max_cycles = d.max_cycles;
     a.warm = d.warm_start;
     a.order2 = d.time_order == 2;
-    a.nbuf = a.order2 ? kPhiBufs : kPhiBufs - 1;
+    a.nbuf = a.order2 ? kPhiBufs : kPhiBufs - 2;
     a.tol2 = d.tol_rel * d.tol_rel;
     a.h = d.h; a.alpha = d.alpha; a.beta = d.beta; a.gamma = d.gamma;
     a.g11 = d.g11; a.g44 = d.g44; a.Gamma = d.Gamma; a.lambda = d.lambda; a.pbc = d.pbc;
