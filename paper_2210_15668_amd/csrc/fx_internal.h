@@ -46,6 +46,7 @@ __host__ __device__ inline void fd_half(double eta, double &F, double &dF) {
 enum : int { PF_SC = 1, PF_P = 2 };
 
 constexpr int kMaxLevels = 24;
+constexpr double kLightRatio = 3.0;  // see InstState::light
 constexpr int kMaxOrder = 3;      // highest order of the extrapolated starting iterate
 constexpr int kPhiBufs = 8;       // phi^n, up to 3 stored levels, two iterate buffers; for
                                   // predictor-corrector instances a fourth stored level (the
@@ -85,6 +86,9 @@ struct InstState {
     int stepped;                      // a time step was completed in this advance slot
     int fresh;                        // solve started in this slot (first residual pending)
     int insolve;                      // a solve is running or awaits finalization
+    int light;                        // this cycle skips one pre- and one post-smoothing sweep
+                                      // per level: the last one left ||r|| within kLightRatio
+                                      // of the tolerance
     int adv;                          // starts a time step in this advance slot
     int parked;                       // run target reached or a solve failed
     int solves, failed, total_cycles, max_cycles_step;
@@ -126,6 +130,7 @@ struct Inst {
     int max_cycles, warm;
     int order2;                        // predictor-corrector time steps
     int nbuf;                          // phi buffers in use (kPhiBufs - 2 without order2)
+    int light_ok;                      // light cycles allowed (InstState::light)
     double tol2;
     // TDGL
     double h, alpha, beta, gamma, g11, g44, Gamma, lambda;
@@ -196,9 +201,10 @@ template <typename T> void launch_reduce(const Inst<T> *I, int ninst, int count_
 struct SmoothCfg {
     int lbx, zt, w8;
 };
+// skip_light: the launch is one of the sweeps a light cycle leaves out
 template <typename T> void launch_smooth(const Inst<T> *I, const Work &w, int level, int color, int zero_init,
                                          int upd, const SmoothCfg &c, double *probe, hipStream_t st,
-                                         hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
+                                         hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr, int skip_light = 0);
 // the first two half-sweeps of a cycle on a level stored red/black at every
 // instance (zero start, red then black) as one launch; the same values as the
 // two separate launches

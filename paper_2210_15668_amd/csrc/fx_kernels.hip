@@ -496,6 +496,7 @@ __global__ void k_begin(const Inst<T> *I, int ninst, int sel) {
     s->zpend = 0;
     s->fresh = 1;
     s->insolve = 1;
+    s->light = 0;
 }
 
 // Lagrange extrapolation to t^{n+1} through t^n, t^{n-1}, ... (equal steps).
@@ -881,6 +882,9 @@ __global__ __launch_bounds__(1024) void k_reduce(const Inst<T> *I, int count_cyc
         else if (y == 0.0) { s->done = 1; s->zpend = x != 0.0; }
         else if (x <= a.tol2 * y || x == 0.0) s->done = 1;
         else if (s->cycles >= a.max_cycles) s->done = 3;
+        // within kLightRatio of the tolerance, one V(1,1)-like cycle (contraction
+        // about 0.2) finishes the solve at a little over half the cost
+        s->light = a.light_ok && count_cycle && x <= kLightRatio * kLightRatio * a.tol2 * y;
     }
 }
 
@@ -1064,11 +1068,12 @@ __global__ __launch_bounds__(256) void k_smooth_zpair(const Inst<T> *I, Work w, 
 // and the phi pair read and written where the update is folded in.
 template <typename T, int ZI, int ZT, int UPD>
 __device__ __forceinline__ void smooth_kernel(const Inst<T> *I, const Work &w, int level, int color, int lbx,
-                                              double *probe) {
+                                              double *probe, int skip_light) {
     const Blk b = find_block(w);
     if (!b.ok) return;
     const Inst<T> &a = I[b.inst];
-    if (asp<1>(a.st)->done) return;
+    const GState *st = asp<1>(a.st);
+    if (st->done || (skip_light && st->light)) return;
     const Lv<T, 1> L = gview(a.lv[level]);
     if (L.rb) {
         if (color > 1) return;
@@ -1091,14 +1096,14 @@ __device__ __forceinline__ void smooth_kernel(const Inst<T> *I, const Work &w, i
 // waves per SIMD resident (64 VGPRs); the autotuner picks per level.
 template <typename T, int ZI, int ZT, int UPD>
 __global__ __launch_bounds__(256) void k_smooth(const Inst<T> *I, Work w, int level, int color, int lbx,
-                                                double *probe) {
-    smooth_kernel<T, ZI, ZT, UPD>(I, w, level, color, lbx, probe);
+                                                double *probe, int skip_light) {
+    smooth_kernel<T, ZI, ZT, UPD>(I, w, level, color, lbx, probe, skip_light);
 }
 
 template <typename T, int ZI, int ZT, int UPD>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void k_smooth_w8(
-    const Inst<T> *I, Work w, int level, int color, int lbx, double *probe) {
-    smooth_kernel<T, ZI, ZT, UPD>(I, w, level, color, lbx, probe);
+    const Inst<T> *I, Work w, int level, int color, int lbx, double *probe, int skip_light) {
+    smooth_kernel<T, ZI, ZT, UPD>(I, w, level, color, lbx, probe, skip_light);
 }
 
 template <typename T>
@@ -1510,9 +1515,11 @@ __global__ __launch_bounds__(512) void k_coarse(const Inst<T> *I) {
         for (int c = threadIdx.x; c < ns; c += blockDim.x) L0.sig[c] = G.sig[c];
         __syncthreads();
     }
+    const int light = asp<1>(A.st)->light;
+    const int nu1 = light ? 1 : A.nu1, nu2 = light ? 1 : A.nu2;
     for (int q = 0; q < nl - 1; ++q) {
         const Lv<T, 3> L = lvl(q);
-        for (int s = 0; s < A.nu1; ++s) smooth_sweep(L, s == 0);
+        for (int s = 0; s < nu1; ++s) smooth_sweep(L, s == 0);
         restrict_phase(L, lvl(q + 1), xlds(q));
     }
     bottom_cg<T>(lvl(nl - 1), (T FX_AS(3) *)(lds + A.off_p), (T FX_AS(3) *)(lds + A.off_q),
@@ -1520,7 +1527,7 @@ __global__ __launch_bounds__(512) void k_coarse(const Inst<T> *I) {
     for (int q = nl - 2; q >= 0; --q) {
         const Lv<T, 3> L = lvl(q);
         prolong_phase(L, lvl(q + 1), xlds(q));
-        for (int s = 0; s < A.nu2; ++s) smooth_sweep(L, 0);
+        for (int s = 0; s < nu2; ++s) smooth_sweep(L, 0);
     }
     {
         const Lv<T, 1> G = gview(A.lv[l0]);
@@ -1636,13 +1643,13 @@ struct SmoothSet {
 
 template <typename T>
 void launch_smooth(const Inst<T> *I, const Work &w, int level, int color, int zero_init, int upd, const SmoothCfg &c,
-                   double *probe, hipStream_t st, hipEvent_t ev0, hipEvent_t ev1) {
+                   double *probe, hipStream_t st, hipEvent_t ev0, hipEvent_t ev1, int skip_light) {
     if (w.total <= 0) return;
     const dim3 g = grid_of(w.total);
     const int lbx = c.lbx;
     auto go = [&](auto kern) {
-        if (ev0) hipExtLaunchKernelGGL(kern, g, dim3(256), 0, st, ev0, ev1, 0, I, w, level, color, lbx, probe);
-        else hipLaunchKernelGGL(kern, g, dim3(256), 0, st, I, w, level, color, lbx, probe);
+        if (ev0) hipExtLaunchKernelGGL(kern, g, dim3(256), 0, st, ev0, ev1, 0, I, w, level, color, lbx, probe, skip_light);
+        else hipLaunchKernelGGL(kern, g, dim3(256), 0, st, I, w, level, color, lbx, probe, skip_light);
     };
     switch (c.zt) {
         case 8: SmoothSet<T, 8>::pick(upd, zero_init, c.w8, go); break;
@@ -1735,7 +1742,7 @@ void launch_fill(double *x, size_t n, double v, hipStream_t st) {
     template void launch_residual<T>(const Inst<T> *, const Work &, int, int, hipStream_t);                  \
     template void launch_reduce<T>(const Inst<T> *, int, int, hipStream_t);                                  \
     template void launch_smooth<T>(const Inst<T> *, const Work &, int, int, int, int, const SmoothCfg &,     \
-                                   double *, hipStream_t, hipEvent_t, hipEvent_t);                           \
+                                   double *, hipStream_t, hipEvent_t, hipEvent_t, int);                      \
     template void launch_smooth_zpair<T>(const Inst<T> *, const Work &, int, const SmoothCfg &, hipStream_t); \
     template void launch_prolong_red<T>(const Inst<T> *, const Work &, int, const SmoothCfg &, hipStream_t);  \
     template void launch_restrict<T>(const Inst<T> *, const Work &, int, hipStream_t);                       \

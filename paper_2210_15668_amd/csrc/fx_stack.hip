@@ -623,6 +623,7 @@ Inst<T> make_inst(const Engine *e, int i) {
     a.warm = d.warm_start;
     a.order2 = d.time_order == 2;
     a.nbuf = a.order2 ? kPhiBufs : kPhiBufs - 2;
+    a.light_ok = env_int("FERROX_LIGHT", 1) != 0;
     a.tol2 = d.tol_rel * d.tol_rel;
     a.h = d.h; a.alpha = d.alpha; a.beta = d.beta; a.gamma = d.gamma;
     a.g11 = d.g11; a.g44 = d.g44; a.Gamma = d.Gamma; a.lambda = d.lambda; a.pbc = d.pbc;
@@ -776,7 +777,7 @@ const Inst<T> *idev(const Engine *e) { return (const Inst<T> *)e->inst_dev; }
 // One smoother colour at level l; finest-level launches are timed while the
 // probe is on.
 template <typename T>
-void smooth_l(Engine *e, int l, int color, int zi, int upd) {
+void smooth_l(Engine *e, int l, int color, int zi, int upd, int skip_light = 0) {
     const Work &w = e->w_sm[l];
     if (w.total <= 0) return;
     hipEvent_t e0 = nullptr, e1 = nullptr;
@@ -787,7 +788,7 @@ void smooth_l(Engine *e, int l, int color, int zi, int upd) {
         pb = e->probe_dev + e->ev_used / 2;
         e->ev_used += 2;
     }
-    launch_smooth(idev<T>(e), w, l, color, zi, upd, e->scfg[l], pb, e->st, e0, e1);
+    launch_smooth(idev<T>(e), w, l, color, zi, upd, e->scfg[l], pb, e->st, e0, e1, skip_light);
 }
 
 // One V(nu1, nu2) cycle over every running instance.  Levels 0 .. lc-1 of an
@@ -802,12 +803,13 @@ void enq_vcycle(Engine *e) {
         // below the finest level (whose launches the probe times one by one) the
         // zero-start red and black half-sweeps of a red/black level are one launch
         const bool zpair = e->fuse && l > 0 && e->ncol[l] == 2 && e->w_sm[l].total > 0;
+        // a light cycle (InstState::light) leaves out the sweeps after the first
         for (int q = 0; q < nu1; ++q) {
             if (q == 0 && zpair) {
                 launch_smooth_zpair(I, e->w_sm[l], l, e->scfg[l], e->st);
                 continue;
             }
-            for (int c = 0; c < e->ncol[l]; ++c) smooth_l<T>(e, l, c, q == 0 && c == 0, 0);
+            for (int c = 0; c < e->ncol[l]; ++c) smooth_l<T>(e, l, c, q == 0 && c == 0, 0, q > 0);
         }
         launch_restrict(I, e->w_rs[l], l, e->st);
     }
@@ -820,11 +822,16 @@ void enq_vcycle(Engine *e) {
         const bool pred = e->fuse && l > 0 && e->small[l] && e->ncol[l] == 2 && e->w_sm[l].total > 0;
         if (pred) launch_prolong_red(I, e->w_sm[l], l, e->scfg[l], e->st);
         else launch_prolong(I, e->w_pr[l], l, e->st);
-        for (int q = 0; q < nu2; ++q)
+        // a light cycle leaves out one sweep: on the finest level one before the
+        // last (which folds the update in), elsewhere one after the first (whose red
+        // half holds the fused prolongation)
+        for (int q = 0; q < nu2; ++q) {
+            const int skip = nu2 > 1 && (l == 0 ? q == nu2 - 2 : q == nu2 - 1);
             for (int c = 0; c < e->ncol[l]; ++c) {
                 if (pred && q == 0 && c == 0) continue;
-                smooth_l<T>(e, l, c, 0, l == 0 && q == nu2 - 1 && c == 1);
+                smooth_l<T>(e, l, c, 0, l == 0 && q == nu2 - 1 && c == 1, skip);
             }
+        }
     }
 }
 
