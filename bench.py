@@ -220,7 +220,7 @@ def main():
     traffic = measured_traffic("fp64")
     roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                "kernel": "k_smooth<double,*,4,*> (finest-level red/black Gauss-Seidel half-sweep, FP64, all variants)",
+                "kernel": "k_smooth / k_smooth_w8 <double, ...> (finest-level red/black Gauss-Seidel half-sweep, FP64, all variants; launches a light cycle leaves empty are not counted)",
                 "avg_launch_us": avg_us, "algorithmic_bytes_per_launch": per_launch,
                 "launches_timed": r64["probe_launches"]}
     batch = None

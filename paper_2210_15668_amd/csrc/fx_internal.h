@@ -46,7 +46,8 @@ __host__ __device__ inline void fd_half(double eta, double &F, double &dF) {
 enum : int { PF_SC = 1, PF_P = 2 };
 
 constexpr int kMaxLevels = 24;
-constexpr double kLightRatio = 3.0;  // see InstState::light
+constexpr double kLightRatio = 3.0;        // see InstState::light
+constexpr double kLightContraction = 6.0;  // the cycle before reduced ||r|| at least this much
 constexpr int kMaxOrder = 3;      // highest order of the extrapolated starting iterate
 constexpr int kPhiBufs = 8;       // phi^n, up to 3 stored levels, two iterate buffers; for
                                   // predictor-corrector instances a fourth stored level (the
@@ -88,7 +89,7 @@ struct InstState {
     int insolve;                      // a solve is running or awaits finalization
     int light;                        // this cycle skips one pre- and one post-smoothing sweep
                                       // per level: the last one left ||r|| within kLightRatio
-                                      // of the tolerance
+                                      // of the tolerance after a kLightContraction-fold cut
     int adv;                          // starts a time step in this advance slot
     int parked;                       // run target reached or a solve failed
     int solves, failed, total_cycles, max_cycles_step;

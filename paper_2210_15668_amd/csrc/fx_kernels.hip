@@ -874,6 +874,7 @@ __global__ __launch_bounds__(1024) void k_reduce(const Inst<T> *I, int count_cyc
     if (threadIdx.x == 0) {
         double x = 0.0, y = 0.0;
         for (int q = 0; q < (int)(blockDim.x >> 6); ++q) { x += lr[q]; y += lf[q]; }
+        const double x_prev = s->rn2;
         s->rn2 = x;
         s->fn2 = y;
         s->fresh = 0;
@@ -882,9 +883,12 @@ __global__ __launch_bounds__(1024) void k_reduce(const Inst<T> *I, int count_cyc
         else if (y == 0.0) { s->done = 1; s->zpend = x != 0.0; }
         else if (x <= a.tol2 * y || x == 0.0) s->done = 1;
         else if (s->cycles >= a.max_cycles) s->done = 3;
-        // within kLightRatio of the tolerance, one V(1,1)-like cycle (contraction
-        // about 0.2) finishes the solve at a little over half the cost
-        s->light = a.light_ok && count_cycle && x <= kLightRatio * kLightRatio * a.tol2 * y;
+        // within kLightRatio of the tolerance, after a cycle that contracted the
+        // residual at least kLightContraction-fold (the linear regime, as in a
+        // time step's first cycle), one V(1,1)-like cycle (contraction about 0.2)
+        // finishes the solve at a little over half the cost
+        s->light = a.light_ok && count_cycle && x <= kLightRatio * kLightRatio * a.tol2 * y &&
+                   x * kLightContraction * kLightContraction <= x_prev;
     }
 }
 

@@ -73,21 +73,31 @@ def copy():
     print(f"copied {COPY_BYTES} bytes", flush=True)
 
 
+def _working(values):
+    """The launches that did work: a light cycle's skipped sweeps still launch, and every
+    block returns at once (a few us, next to no bytes), far below the median."""
+    med = sorted(values)[len(values) // 2] if values else 0.0
+    return [v for v in values if v >= 0.25 * med]
+
+
 def stats(trace_dir):
     db = _db(trace_dir)
     rows = db.execute("select name, grid_x, duration from kernels").fetchall()
     agg = defaultdict(lambda: [0, 0.0])
+    durs = defaultdict(list)
     for name, gx, d in rows:
         key = (_short(name), gx)
         agg[key][0] += 1
         agg[key][1] += d
+        durs[key].append(d)
     tot = sum(v[1] for v in agg.values())
     fine = _finest(list(agg))
     if fine:
-        c = sum(agg[k][0] for k in fine)
-        t = sum(agg[k][1] for k in fine)
+        allv = [d for k in fine for d in durs[k]]
+        work = _working(allv)
         print(f"Dominant kernel (finest-level FP64 smoother, {', '.join(f'`{k[0]}`' for k in fine)}): "
-              f"{c} launches, average {t / c / 1e3:.2f} us\n")
+              f"{len(allv)} launches, average {sum(allv) / len(allv) / 1e3:.2f} us; the {len(work)} that did work "
+              f"(a light cycle leaves the others empty) average {sum(work) / len(work) / 1e3:.2f} us\n")
     print("| kernel | grid (threads) | calls | avg us | total ms | % |")
     print("|---|---|---|---|---|---|")
     for (k, gx), (c, t) in sorted(agg.items(), key=lambda x: -x[1][1])[:24]:
@@ -106,7 +116,8 @@ def _counter(d, counter):
 
 def traffic(base):
     """Measured HBM bytes per launch of the finest-level FP64 smoother (all its variants,
-    weighted by their launch counts in the counter run)."""
+    weighted by their launch counts in the counter run; the empty launches of light
+    cycles left out, as the in-run probe leaves them out)."""
     cf = _counter(os.path.join(base, "cfetch"), "FETCH_SIZE")
     cw = _counter(os.path.join(base, "cwrite"), "WRITE_SIZE")
     big_f = max(max(v) for v in cf.values()) * 1024.0
@@ -115,14 +126,16 @@ def traffic(base):
     fe = _counter(os.path.join(base, "fetch"), "FETCH_SIZE")
     wr = _counter(os.path.join(base, "write"), "WRITE_SIZE")
     fine = _finest(list(fe))
-    n = sum(len(fe[k]) for k in fine)
-    fetch = sum(sum(fe[k]) for k in fine) * 1024.0 / f_fetch / n
-    write = sum(sum(wr.get(k, [0])) for k in fine) * 1024.0 / f_write / max(1, sum(len(wr.get(k, [])) for k in fine))
+    fvals = _working([v for k in fine for v in fe[k]])
+    wvals = _working([v for k in fine for v in wr.get(k, [])])
+    fetch = sum(fvals) * 1024.0 / f_fetch / len(fvals)
+    write = sum(wvals) * 1024.0 / f_write / max(1, len(wvals))
     with open(KERNEL_SRC, "rb") as f:
         sha = hashlib.sha256(f.read()).hexdigest()
     out = {
         "kernel": "finest-level red/black Gauss-Seidel half-sweep (FP64), all variants",
         "variants": {f"{k[0]} grid {k[1]}": len(fe[k]) for k in fine},
+        "dispatches_with_work": len(fvals),
         "copy_calibration": {"bytes": COPY_BYTES, "fetch_factor": f_fetch, "write_factor": f_write},
         "fetch_bytes_per_launch": fetch,
         "write_bytes_per_launch": write,
