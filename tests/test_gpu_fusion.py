@@ -1,4 +1,4 @@
-"""The fused launches below the finest level -- the zero-start red/black pair and, on small
+"""Launch-level choices that must not change results: the fused launches below the finest level -- the zero-start red/black pair and, on small
 levels, the prolongation formed inside the first red half-sweep -- reproduce the separate
 launches bit for bit (FERROX_FUSE=0 keeps every half-sweep and prolongation a launch of its
 own), for single stacks in both precisions and for a batch; the fused stack also meets the
@@ -77,3 +77,22 @@ def test_fused_equals_separate_launches_in_a_batch(fx, monkeypatch):
         b.close()
     for q in range(len(specs)):
         assert np.array_equal(out["1"][q][0], out["0"][q][0]) and np.array_equal(out["1"][q][1], out["0"][q][1]), q
+
+
+@pytest.mark.parametrize("prec", [W.PREC_FP64, W.PREC_MIXED])
+def test_light_cycles_reach_the_oracle_root(fx, orc, monkeypatch, prec):
+    """Light cycles (one sweep fewer per level after a cycle that left the residual near the
+    tolerance) change the iterates, not the root: with and without them the run meets the
+    oracle's trajectory to 1e-10."""
+    spec = W.shrink_lateral(W.mfism_large(prec), 32, 32).copy(tol_rel=1e-13)
+    P0 = W.random_P(spec, 92, amp=0.05)
+    n = 12
+    P_o, phi_o, _ = orc.run(spec, P0, n, W.DT, tol=1e-13)
+    for light in ("1", "0"):
+        monkeypatch.setenv("FERROX_LIGHT", light)
+        s = fx.Stack(spec, P0)
+        info = s.run_steps(n, W.DT)
+        rp, rf = rel(s.get(fx.FIELD_P), P_o), rel(s.get(fx.FIELD_PHI), phi_o)
+        say(f"  prec {prec} light {light}: cycles {info.total_cycles} relP {rp:.2e} relphi {rf:.2e}")
+        assert info.steps_done == n and rp <= 1e-10 and rf <= 1e-10
+        s.close()
