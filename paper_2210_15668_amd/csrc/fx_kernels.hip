@@ -228,7 +228,7 @@ __device__ __forceinline__ void restrict_cell(const V &F, const V &C, const X &X
 // red child is the one with dx = (dy + k) & 1, a coarse plane with a single
 // child reads that plane twice (the copy is skipped below), and sigma outside
 // the semiconductor planes is read from the cell's own residual and ignored.
-// Without conditional loads the compiler keeps all 40 loads in flight at
+// Without conditional loads the compiler keeps all of them (48) in flight at
 // once instead of waiting on each child's stencil in turn.
 template <typename V, typename X>
 __device__ __forceinline__ void restrict_cell_rbxy(const V &F, const V &C, const X &Xf, int I, int J, int K) {
