@@ -1462,10 +1462,13 @@ __global__ __launch_bounds__(512) void k_coarse(const Inst<T> *I) {
         L.dg = tab + 3 * L.nz;
         return L;
     };
-    for (int q = 0; q < nl; ++q) {        // per-plane coefficient tables into LDS
+    // Per-plane coefficient tables into LDS, a wave per level: the levels' loads
+    // are in flight together instead of one level's round trips after another's.
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nwave = blockDim.x >> 6;
+    for (int q = wave; q < nl; q += nwave) {
         const Lv<T, 1> G = gview(A.lv[l0 + q]);
         T FX_AS(3) *tab = (T FX_AS(3) *)(lds + A.off_t[q]);
-        for (int c = threadIdx.x; c < G.nz; c += blockDim.x) {
+        for (int c = lane; c < G.nz; c += 64) {
             tab[c] = G.cxy[c];
             tab[G.nz + c] = G.czm[c];
             tab[2 * G.nz + c] = G.czp[c];
@@ -1491,18 +1494,18 @@ __global__ __launch_bounds__(512) void k_coarse(const Inst<T> *I) {
         X.xy = A.xf[l0 + q].xy;
         return X;
     };
-    for (int q = 0; q + 1 < nl; ++q) {
+    for (int q = wave; q + 1 < nl; q += nwave) {             // likewise a wave per level pair
         const Xv<T> G = xview(A.xf[l0 + q]);
         const int nf = A.lv[l0 + q].nz, nc = A.lv[l0 + q + 1].nz;
         const Xv<T, 3> X = xlds(q);
         int FX_AS(3) *ib = (int FX_AS(3) *)X.cks;
         T FX_AS(3) *wb = (T FX_AS(3) *)X.pwa;
-        for (int c = threadIdx.x; c < nc; c += blockDim.x) {
+        for (int c = lane; c < nc; c += 64) {
             ib[c] = G.cks[c];
             ib[nc + c] = G.ccnt[c];
             ib[2 * nc + c] = G.cthick[c];
         }
-        for (int c = threadIdx.x; c < nf; c += blockDim.x) {
+        for (int c = lane; c < nf; c += 64) {
             ib[3 * nc + c] = G.fthick[c];
             ib[3 * nc + nf + c] = G.pka[c];
             ib[3 * nc + 2 * nf + c] = G.pkb[c];
@@ -1515,8 +1518,21 @@ __global__ __launch_bounds__(512) void k_coarse(const Inst<T> *I) {
         const Lv<T, 3> L0 = lvl(0);
         const int n = G.nx * G.ny * G.nz;
         const int ns = G.nx * G.ny * (G.sig_hi - G.sig_lo);
-        for (int c = threadIdx.x; c < n; c += blockDim.x) L0.r[c] = G.r[c];
-        for (int c = threadIdx.x; c < ns; c += blockDim.x) L0.sig[c] = G.sig[c];
+        // four elements per thread and pass, loaded before they are stored
+        for (int c0 = threadIdx.x; c0 < n + ns; c0 += 4 * blockDim.x) {
+            T v[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int c = c0 + u * blockDim.x;
+                v[u] = c < n ? G.r[c] : (c < n + ns ? G.sig[c - n] : T(0));
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int c = c0 + u * blockDim.x;
+                if (c < n) L0.r[c] = v[u];
+                else if (c < n + ns) L0.sig[c - n] = v[u];
+            }
+        }
         __syncthreads();
     }
     const int light = asp<1>(A.st)->light;
