@@ -74,7 +74,7 @@ int env_int(const char *name, int dflt) {
     return v && *v ? atoi(v) : dflt;
 }
 
-constexpr int kBottomTarget = 8;         // stop coarsening at this many cells
+constexpr int kBottomTarget = 64;        // stop coarsening at this many cells (one-wave CG below)
 
 // One multigrid level, host view.
 struct HostLevel {
@@ -196,7 +196,7 @@ void build_plan(const fx_stack_desc *d, Plan *p) {
     p->lv.push_back(L0);
     for (;;) {
         const HostLevel &F = p->lv.back();
-        if (F.ncell() <= (size_t)kBottomTarget) break;
+        if (F.ncell() <= (size_t)env_int("FERROX_BOTTOM_CELLS", kBottomTarget)) break;
         const bool cxy = F.nx % 2 == 0 && F.ny % 2 == 0 && F.nx >= 4 && F.ny >= 4;
         const bool cz = F.nz >= 2;
         if (!cxy && !cz) break;
