@@ -74,7 +74,7 @@ int env_int(const char *name, int dflt) {
     return v && *v ? atoi(v) : dflt;
 }
 
-constexpr int kBottomTarget = 64;        // stop coarsening at this many cells (one-wave CG below)
+constexpr int kBottomTarget = 8;         // stop coarsening at this many cells
 
 // One multigrid level, host view.
 struct HostLevel {
