@@ -46,7 +46,7 @@ __host__ __device__ inline void fd_half(double eta, double &F, double &dF) {
 enum : int { PF_SC = 1, PF_P = 2 };
 
 constexpr int kMaxLevels = 24;
-constexpr double kLightRatio = 3.0;        // see InstState::light
+constexpr double kLightRatio = 5.0;        // see InstState::light
 constexpr double kLightContraction = 6.0;  // the cycle before reduced ||r|| at least this much
 constexpr int kMaxOrder = 3;      // highest order of the extrapolated starting iterate
 constexpr int kPhiBufs = 8;       // phi^n, up to 3 stored levels, two iterate buffers; for
@@ -132,6 +132,7 @@ struct Inst {
     int order2;                        // predictor-corrector time steps
     int nbuf;                          // phi buffers in use (kPhiBufs - 2 without order2)
     int light_ok;                      // light cycles allowed (InstState::light)
+    double light_r2, light_c2;         // squares of kLightRatio and kLightContraction
     double tol2;
     // TDGL
     double h, alpha, beta, gamma, g11, g44, Gamma, lambda;

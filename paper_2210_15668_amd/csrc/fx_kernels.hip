@@ -887,8 +887,7 @@ __global__ __launch_bounds__(1024) void k_reduce(const Inst<T> *I, int count_cyc
         // residual at least kLightContraction-fold (the linear regime, as in a
         // time step's first cycle), one V(1,1)-like cycle (contraction about 0.2)
         // finishes the solve at a little over half the cost
-        s->light = a.light_ok && count_cycle && x <= kLightRatio * kLightRatio * a.tol2 * y &&
-                   x * kLightContraction * kLightContraction <= x_prev;
+        s->light = a.light_ok && count_cycle && x <= a.light_r2 * a.tol2 * y && x * a.light_c2 <= x_prev;
     }
 }
 

@@ -624,6 +624,12 @@ Inst<T> make_inst(const Engine *e, int i) {
     a.order2 = d.time_order == 2;
     a.nbuf = a.order2 ? kPhiBufs : kPhiBufs - 2;
     a.light_ok = env_int("FERROX_LIGHT", 1) != 0;
+    {
+        const char *lr = getenv("FERROX_LIGHT_RATIO"), *lc = getenv("FERROX_LIGHT_CUT");
+        const double r = lr ? atof(lr) : kLightRatio, c = lc ? atof(lc) : kLightContraction;
+        a.light_r2 = r * r;
+        a.light_c2 = c * c;
+    }
     a.tol2 = d.tol_rel * d.tol_rel;
     a.h = d.h; a.alpha = d.alpha; a.beta = d.beta; a.gamma = d.gamma;
     a.g11 = d.g11; a.g44 = d.g44; a.Gamma = d.Gamma; a.lambda = d.lambda; a.pbc = d.pbc;
