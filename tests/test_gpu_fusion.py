@@ -1,4 +1,4 @@
-"""Launch-level choices that must not change results: the fused launches below the finest level -- the zero-start red/black pair and, on small
+"""Solver choices that must not change results: the fused launches below the finest level -- the zero-start red/black pair and, on small
 levels, the prolongation formed inside the first red half-sweep -- reproduce the separate
 launches bit for bit (FERROX_FUSE=0 keeps every half-sweep and prolongation a launch of its
 own), for single stacks in both precisions and for a batch; the fused stack also meets the
@@ -96,3 +96,21 @@ def test_light_cycles_reach_the_oracle_root(fx, orc, monkeypatch, prec):
         say(f"  prec {prec} light {light}: cycles {info.total_cycles} relP {rp:.2e} relphi {rf:.2e}")
         assert info.steps_done == n and rp <= 1e-10 and rf <= 1e-10
         s.close()
+
+
+@pytest.mark.parametrize("cells", ["8", "64"])
+def test_bottom_size_reaches_the_oracle_root(fx, orc, monkeypatch, cells):
+    """The size at which coarsening stops (FERROX_BOTTOM_CELLS; 64 lets the one-wave conjugate
+    gradients take a 4x4x2 bottom) changes the cycles, not the root."""
+    monkeypatch.setenv("FERROX_BOTTOM_CELLS", cells)
+    spec = W.shrink_lateral(W.mfism_large(), 32, 32).copy(tol_rel=1e-13)
+    P0 = W.random_P(spec, 93, amp=0.05)
+    n = 6
+    s = fx.Stack(spec, P0)
+    info = s.run_steps(n, W.DT)
+    levels = fx.lib().stack_num_levels(s._h)
+    P_o, phi_o, _ = orc.run(spec, P0, n, W.DT, tol=1e-13)
+    rp, rf = rel(s.get(fx.FIELD_P), P_o), rel(s.get(fx.FIELD_PHI), phi_o)
+    say(f"  bottom <= {cells} cells: {levels} levels, cycles {info.total_cycles} relP {rp:.2e} relphi {rf:.2e}")
+    assert info.steps_done == n and rp <= 1e-10 and rf <= 1e-10
+    s.close()
