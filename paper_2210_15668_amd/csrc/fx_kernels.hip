@@ -916,7 +916,7 @@ __device__ __forceinline__ void smooth_rb_body(const Inst<T> &a, const Lv<T, 1> 
     const int mm = (tt.tx << lbx) + (threadIdx.x & ((1 << lbx) - 1));
     const int jj = (tt.ty << (8 - lbx)) + (threadIdx.x >> lbx);
     const bool live = mm < hx && jj < L.ny;
-    const int m = live ? mm : 0, j = live ? jj : 0;
+    const int m = live ? mm : 0, j = live ? jj : 0;           // (0, 0): see the stores
     const int half = (L.nx * L.ny * L.nz) >> 1;
     const int plane = L.ny * hx;
     const T FX_AS(1) *eo = L.e + (color ? 0 : half);
@@ -936,8 +936,9 @@ __device__ __forceinline__ void smooth_rb_body(const Inst<T> &a, const Lv<T, 1> 
         phi_out = asp<1>(a.phi[cyc_dst(s)]) + off;
     }
     T out[ZT];
-    T rr[ZT], sg[ZT], ex0[ZT], ex1[ZT], ey0[ZT], ey1[ZT], ez0[ZT], ez1[ZT], ep[ZT];
+    T rr[ZT], sg[ZT], ex0[ZT], ex1[ZT], ey0[ZT], ey1[ZT], ez0[ZT], ez1[ZT];
     dpair ph[ZT];
+    double lim[ZT];
 #pragma unroll
     for (int z = 0; z < ZT; ++z) {
         const int k = min(tt.tz * ZT + z, L.nz - 1);
@@ -957,8 +958,8 @@ __device__ __forceinline__ void smooth_rb_body(const Inst<T> &a, const Lv<T, 1> 
             ez1[z] = eo[k < L.nz - 1 ? q + plane : q];
         }
         if (upd) {
-            ep[z] = eo[q];                       // the red partner of this black cell's pair
             ph[z] = *(const dpair FX_AS(1) *)(phi_in + (size_t)k * L.nx * L.ny + (size_t)j * L.nx + 2 * m);
+            lim[z] = (pflags[k] & PF_SC) ? a.dmax : 1e300;
         }
     }
 #pragma unroll
@@ -969,21 +970,24 @@ __device__ __forceinline__ void smooth_rb_body(const Inst<T> &a, const Lv<T, 1> 
         if (!ZI) acc = rb_nb_sum(L, k, ex0[z], ex1[z], ey0[z], ey1[z], ez0[z], ez1[z]);
         out[z] = (rr[z] + acc) / (L.dg[k] + (hs ? sg[z] : T(0)));
     }
+    // Stores outside branches: a lane past the row end works on cell (0, 0) and a slot past
+    // the top on plane nz - 1, from the same inputs as the lane owning that cell, so its store
+    // repeats the owner's bits.  (A store under a branch made the next plane's arithmetic
+    // wait for it to complete.)
 #pragma unroll
     for (int z = 0; z < ZT; ++z) {
-        const int k = tt.tz * ZT + z;
-        if (live && k < L.nz) {
-            es[k * plane + j * hx + m] = out[z];
-            if (upd) {
-                const double lim = (pflags[k] & PF_SC) ? a.dmax : 1e300;
-                const double db = fmin(fmax((double)out[z], -lim), lim);
-                const double dr = fmin(fmax((double)ep[z], -lim), lim);
-                const bool odd = ((color + j + k) & 1) != 0;          // black cell at 2m+1
-                dpair o;
-                o.x = ph[z].x + (odd ? dr : db);
-                o.y = ph[z].y + (odd ? db : dr);
-                *(dpair FX_AS(1) *)(phi_out + (size_t)k * L.nx * L.ny + (size_t)j * L.nx + 2 * m) = o;
-            }
+        const int k = min(tt.tz * ZT + z, L.nz - 1);
+        es[k * plane + j * hx + m] = out[z];
+        if (upd) {
+            // the pair's red cell is this black cell's x - 1 (black at 2m + 1) or x + 1
+            // neighbour (black at 2m), already read as ex1 / ex0
+            const bool odd = ((color + j + k) & 1) != 0;
+            const double db = fmin(fmax((double)out[z], -lim[z]), lim[z]);
+            const double dr = fmin(fmax((double)(odd ? ex1[z] : ex0[z]), -lim[z]), lim[z]);
+            dpair o;
+            o.x = ph[z].x + (odd ? dr : db);
+            o.y = ph[z].y + (odd ? db : dr);
+            *(dpair FX_AS(1) *)(phi_out + (size_t)k * L.nx * L.ny + (size_t)j * L.nx + 2 * m) = o;
         }
     }
 }
