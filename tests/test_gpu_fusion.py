@@ -1,8 +1,9 @@
-"""Solver choices that must not change results: the fused launches below the finest level -- the zero-start red/black pair and, on small
-levels, the prolongation formed inside the first red half-sweep -- reproduce the separate
-launches bit for bit (FERROX_FUSE=0 keeps every half-sweep and prolongation a launch of its
-own), for single stacks in both precisions and for a batch; the fused stack also meets the
-oracle's 1e-10 parity bar."""
+"""Solver choices that must not change results.  The fused launches below the finest level
+(the zero-start red/black pair and, on small levels, the prolongation formed inside the
+first red half-sweep) reproduce the separate launches bit for bit (FERROX_FUSE=0 keeps every
+half-sweep and prolongation a launch of its own), for single stacks in both precisions and
+for a batch, and the fused stack meets the oracle's 1e-10 parity bar.  Light cycles and
+either coarsening stop (8 or 64 bottom cells) change the cycles, not the root."""
 import sys
 
 import numpy as np
