@@ -120,7 +120,7 @@ struct XferArgs {
     const int *fthick, *cthick;      // plane thickness in finest planes
     const int *pka, *pkb;            // coarse planes interpolated into each fine plane (pkb -1: contact)
     const T *pwa, *pwb;
-    int xy;                          // x and y halved
+    int xy;                          // lateral transfer: 0 none, 1 x and y halved, 2 x halved (one row)
 };
 
 // Constant description of one instance (device memory, read by every kernel).

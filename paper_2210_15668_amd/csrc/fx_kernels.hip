@@ -185,11 +185,12 @@ __device__ __forceinline__ int nat_color(const V &L, int i, int j, int k) {
 // children are skipped: right after a black half-sweep their residual is
 // zero (each black equation has just been solved exactly).
 // The child loops are unrolled (XY fixes their extent, a coarse plane has one
-// or two children) so that a thread issues all its loads together.
-template <bool XY, typename V, typename X>
+// or two children) so that a thread issues all its loads together.  XY is the
+// lateral transfer mode: 0 none, 1 x and y halved, 2 x halved on a single row.
+template <int XY, typename V, typename X>
 __device__ __forceinline__ void restrict_cell_t(const V &F, const V &C, const X &Xf, int I, int J, int K) {
     using T = typename V::value_type;
-    constexpr int nsub = XY ? 2 : 1;
+    constexpr int nsx = XY ? 2 : 1, nsy = XY == 1 ? 2 : 1;
     double sr = 0.0, ss = 0.0;
     const int ks = Xf.cks[K], cnt = Xf.ccnt[K];
 #pragma unroll
@@ -199,10 +200,10 @@ __device__ __forceinline__ void restrict_cell_t(const V &F, const V &C, const X 
         const double wz = (double)Xf.fthick[k] / (double)Xf.cthick[K];
         const bool hs = has_sig(F, k);
 #pragma unroll
-        for (int dy = 0; dy < nsub; ++dy) {
-            const int j = XY ? 2 * J + dy : J;
+        for (int dy = 0; dy < nsy; ++dy) {
+            const int j = XY == 1 ? 2 * J + dy : J;
 #pragma unroll
-            for (int dx = 0; dx < nsub; ++dx) {
+            for (int dx = 0; dx < nsx; ++dx) {
                 const int i = XY ? 2 * I + dx : I;
                 const T sg = hs ? F.sig[sidx(F, i, j, k)] : T(0);
                 ss += wz * (double)sg;
@@ -213,14 +214,15 @@ __device__ __forceinline__ void restrict_cell_t(const V &F, const V &C, const X 
             }
         }
     }
-    const double wxy = XY ? 0.25 : 1.0;
+    const double wxy = XY == 1 ? 0.25 : (XY == 2 ? 0.5 : 1.0);
     C.r[cidx(C, I, J, K)] = (T)(sr * wxy);
     if (has_sig(C, K)) C.sig[sidx(C, I, J, K)] = (T)(ss * wxy);
 }
 template <typename V, typename X>
 __device__ __forceinline__ void restrict_cell(const V &F, const V &C, const X &Xf, int I, int J, int K) {
-    if (Xf.xy) restrict_cell_t<true>(F, C, Xf, I, J, K);
-    else restrict_cell_t<false>(F, C, Xf, I, J, K);
+    if (Xf.xy == 1) restrict_cell_t<1>(F, C, Xf, I, J, K);
+    else if (Xf.xy == 2) restrict_cell_t<2>(F, C, Xf, I, J, K);
+    else restrict_cell_t<0>(F, C, Xf, I, J, K);
 }
 
 // The same restriction for a red/black level halved in x and y, in global
@@ -299,19 +301,28 @@ __device__ __forceinline__ void restrict_cell_rbxy(const V &F, const V &C, const
 // overwritten by the next red half-sweep without being read.
 // Unrolled like the restriction: all coarse values are loaded together; a
 // missing second plane (contact side) reads the first with weight zero.
-// prolong_value returns the interpolated correction of fine cell (i, j, k).
-template <bool XY, typename V, typename X>
+// prolong_value returns the interpolated correction of fine cell (i, j, k);
+// XY is the lateral transfer mode as in the restriction (2: linear in x only).
+template <int XY, typename V, typename X>
 __device__ __forceinline__ typename V::value_type prolong_value(const V &C, const X &Xf, int i, int j, int k) {
     using T = typename V::value_type;
-    constexpr int ns = XY ? 2 : 1;
+    constexpr int nsx = XY ? 2 : 1, nsy = XY == 1 ? 2 : 1;
     int ix[2], jy[2];
     T wx[2], wy[2];
-    if (XY) {
+    if (XY == 1) {
         const int I = i >> 1, J = j >> 1;
         ix[0] = I; ix[1] = (i & 1) ? wrap_p(I, C.nx) : wrap_m(I, C.nx);
         jy[0] = J; jy[1] = (j & 1) ? wrap_p(J, C.ny) : wrap_m(J, C.ny);
         wx[0] = wy[0] = T(0.75);
         wx[1] = wy[1] = T(0.25);
+    } else if (XY == 2) {
+        const int I = i >> 1;
+        ix[0] = I; ix[1] = (i & 1) ? wrap_p(I, C.nx) : wrap_m(I, C.nx);
+        jy[0] = jy[1] = j;
+        wx[0] = T(0.75);
+        wx[1] = T(0.25);
+        wy[0] = T(1);
+        wy[1] = T(0);
     } else {
         ix[0] = ix[1] = i; jy[0] = jy[1] = j; wx[0] = wy[0] = T(1);
         wx[1] = wy[1] = T(0);
@@ -324,9 +335,9 @@ __device__ __forceinline__ typename V::value_type prolong_value(const V &C, cons
     for (int q = 0; q < 2; ++q) {
         T s = 0;
 #pragma unroll
-        for (int yy = 0; yy < ns; ++yy)
+        for (int yy = 0; yy < nsy; ++yy)
 #pragma unroll
-            for (int xx = 0; xx < ns; ++xx) s += wx[xx] * wy[yy] * C.e[cidx(C, ix[xx], jy[yy], kz[q])];
+            for (int xx = 0; xx < nsx; ++xx) s += wx[xx] * wy[yy] * C.e[cidx(C, ix[xx], jy[yy], kz[q])];
         v += wz[q] * s;
     }
     return v;
@@ -334,7 +345,9 @@ __device__ __forceinline__ typename V::value_type prolong_value(const V &C, cons
 template <typename V, typename X>
 __device__ __forceinline__ void prolong_cell(const V &F, const V &C, const X &Xf, int i, int j, int k) {
     if (F.rb && !((i + j + k) & 1)) return;
-    F.e[cidx(F, i, j, k)] += Xf.xy ? prolong_value<true>(C, Xf, i, j, k) : prolong_value<false>(C, Xf, i, j, k);
+    F.e[cidx(F, i, j, k)] += Xf.xy == 1   ? prolong_value<1>(C, Xf, i, j, k)
+                             : Xf.xy == 2 ? prolong_value<2>(C, Xf, i, j, k)
+                                          : prolong_value<0>(C, Xf, i, j, k);
 }
 
 // Sum over a 256-thread block; result valid in thread 0.
@@ -763,10 +776,13 @@ __device__ __forceinline__ void residual_body(const Inst<T> &a, const GState *s,
     for (int z = 0; z < ZT; ++z) {
         const int k = kcl(k0 + z);
         const int pn = par0 ^ (k & 1) ^ 1;
+        // one row (ny = 1): the y neighbours are the cell itself, of its own colour, so
+        // that their terms cancel as in the operator
+        const int py = ny > 1 ? pn : pn ^ 1;
         at(k, ox0, pn, &vx0[z]);
         at(k, ox1, pn, &vx1[z]);
-        at(k, oy0, pn, &vy0[z]);
-        at(k, oy1, pn, &vy1[z]);
+        at(k, oy0, py, &vy0[z]);
+        at(k, oy1, py, &vy1[z]);
     }
     const double v_b = a.v_b, v_t = s->v_top;
     double res[ZT], sg[ZT];
@@ -1126,14 +1142,14 @@ __global__ __launch_bounds__(256) void k_restrict(const Inst<T> *I, Work w, int 
     if (I0 >= C.nx || J0 >= C.ny) return;
     const Lv<T, 1> F = gview(a.lv[level]);
     const Xv<T> X = xview(a.xf[level]);
-    if (F.rb && X.xy) restrict_cell_rbxy(F, C, X, I0, J0, t.tz);
+    if (F.rb && X.xy == 1) restrict_cell_rbxy(F, C, X, I0, J0, t.tz);
     else restrict_cell(F, C, X, I0, J0, t.tz);
 }
 
 // A thread per column of kProZ planes (black cells only on a red/black
 // level): every correction is formed, and every corrected cell read, before
 // any cell is updated, so the column's loads are all in flight together.
-template <bool XY, typename T>
+template <int XY, typename T>
 __device__ __forceinline__ void prolong_column(const Lv<T, 1> &F, const Lv<T, 1> &C, const Xv<T> &X, int m, int j,
                                                int k0) {
     T v[kProZ], e[kProZ];
@@ -1158,7 +1174,7 @@ __device__ __forceinline__ void prolong_column(const Lv<T, 1> &F, const Lv<T, 1>
 // corrects its six black neighbours in registers (same operands, same order as
 // prolong_column) and updates itself from them (same expression as the red
 // half-sweep); nothing but the red cells is stored.
-template <bool XY, typename T, int ZT>
+template <int XY, typename T, int ZT>
 __device__ __forceinline__ void prolong_red_body(const Lv<T, 1> &F, const Lv<T, 1> &C, const Xv<T> &X, int t,
                                                  int lbx) {
     const int hx = F.nx >> 1;
@@ -1207,8 +1223,9 @@ __global__ __launch_bounds__(256) void k_prolong_red(const Inst<T> *I, Work w, i
     if (!F.rb) return;                               // the host fuses only all-red/black levels
     const Lv<T, 1> C = gview(a.lv[level + 1]);
     const Xv<T> X = xview(a.xf[level]);
-    if (X.xy) prolong_red_body<true, T, ZT>(F, C, X, b.t, lbx);
-    else prolong_red_body<false, T, ZT>(F, C, X, b.t, lbx);
+    if (X.xy == 1) prolong_red_body<1, T, ZT>(F, C, X, b.t, lbx);
+    else if (X.xy == 2) prolong_red_body<2, T, ZT>(F, C, X, b.t, lbx);
+    else prolong_red_body<0, T, ZT>(F, C, X, b.t, lbx);
 }
 
 template <typename T>
@@ -1225,8 +1242,9 @@ __global__ __launch_bounds__(256) void k_prolong(const Inst<T> *I, Work w, int l
     if (m >= nxe || j >= F.ny) return;
     const Lv<T, 1> C = gview(a.lv[level + 1]);
     const Xv<T> X = xview(a.xf[level]);
-    if (X.xy) prolong_column<true>(F, C, X, m, j, t.tz * kProZ);
-    else prolong_column<false>(F, C, X, m, j, t.tz * kProZ);
+    if (X.xy == 1) prolong_column<1>(F, C, X, m, j, t.tz * kProZ);
+    else if (X.xy == 2) prolong_column<2>(F, C, X, m, j, t.tz * kProZ);
+    else prolong_column<0>(F, C, X, m, j, t.tz * kProZ);
 }
 
 // --------------------------------------------- coarse levels in one workgroup

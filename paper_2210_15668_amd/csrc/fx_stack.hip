@@ -79,7 +79,8 @@ constexpr int kBottomTarget = 8;         // stop coarsening at this many cells
 // One multigrid level, host view.
 struct HostLevel {
     int nx = 0, ny = 0, nz = 0;
-    int xy_from_finer = 0;              // x,y halved relative to the finer level
+    int xy_from_finer = 0;              // relative to the finer level: 1 x and y halved, 2 x halved
+                                        // (a single row: ny = 1), 0 neither
     int z_from_finer = 0;               // z paired relative to the finer level
     std::vector<int> s0, e0;            // covered finest device planes [s0, e0)
     std::vector<double> cxy, czm, czp, dg;
@@ -198,11 +199,14 @@ void build_plan(const fx_stack_desc *d, Plan *p) {
         const HostLevel &F = p->lv.back();
         if (F.ncell() <= (size_t)env_int("FERROX_BOTTOM_CELLS", kBottomTarget)) break;
         const bool cxy = F.nx % 2 == 0 && F.ny % 2 == 0 && F.nx >= 4 && F.ny >= 4;
+        // a single row (the 2D x-z reduction) halves x alone
+        const bool cx1 = !cxy && F.ny == 1 && F.nx % 2 == 0 && F.nx >= 4;
         const bool cz = F.nz >= 2;
-        if (!cxy && !cz) break;
+        if (!cxy && !cx1 && !cz) break;
         HostLevel C;
-        C.xy_from_finer = cxy; C.z_from_finer = cz;
-        C.nx = cxy ? F.nx / 2 : F.nx;
+        C.xy_from_finer = cxy ? 1 : (cx1 ? 2 : 0);
+        C.z_from_finer = cz;
+        C.nx = cxy || cx1 ? F.nx / 2 : F.nx;
         C.ny = cxy ? F.ny / 2 : F.ny;
         C.nz = cz ? (F.nz + 1) / 2 : F.nz;
         for (int K = 0; K < C.nz; ++K) {

@@ -8,6 +8,7 @@ import numpy as np
 import pytest
 
 from paper_2210_15668_amd import workloads as W
+from parity_check import worst
 
 pytestmark = pytest.mark.gpu
 
@@ -39,12 +40,12 @@ def test_fig4_mfism_parity(fx, orc, prec):
     P0 = W.random_P(spec, 41, amp=0.2)
     s = fx.Stack(spec, P0)
     phi_o, _ = orc.solve(spec, P0, tol=1e-13)
-    r0 = rel(s.get(fx.FIELD_PHI), phi_o)
+    r0 = worst(spec, s.get(fx.FIELD_PHI), phi_o)
     n = 6
     vs = np.linspace(0.5, 3.0, n)
     info = s.run_steps(n, W.DT_TABLE1, vs)
     P_o, phi_o, _ = orc.run(spec, P0, n, W.DT_TABLE1, v_sched=vs, tol=1e-13, phi0=phi_o, init=False)
-    rp, rf = rel(s.get(fx.FIELD_P), P_o), rel(s.get(fx.FIELD_PHI), phi_o)
+    rp, rf = worst(spec, s.get(fx.FIELD_P), P_o), worst(spec, s.get(fx.FIELD_PHI), phi_o)
     say(f"  step 0 rel {r0:.2e}; cycles/step {info.total_cycles / n:.2f} relP {rp:.2e} relphi {rf:.2e}")
     assert r0 <= 1e-10 and rp <= 1e-10 and rf <= 1e-10
 
@@ -63,7 +64,7 @@ def test_doped_and_degenerate_silicon(fx, orc, Na, Nd, v):
     phi_o, _ = orc.solve(spec, P0, tol=1e-13)
     s.run_steps(3, W.DT)
     P_o, phi_o, _ = orc.run(spec, P0, 3, W.DT, tol=1e-13, phi0=phi_o, init=False)
-    rp, rf = rel(s.get(fx.FIELD_P), P_o), rel(s.get(fx.FIELD_PHI), phi_o)
+    rp, rf = worst(spec, s.get(fx.FIELD_P), P_o), worst(spec, s.get(fx.FIELD_PHI), phi_o)
     # the same stack with Boltzmann carriers lands measurably elsewhere
     sb = spec.copy(carriers=W.CARRIERS_BOLTZMANN, ni=1.0e16)
     phi_b, _ = orc.solve(sb, P0, tol=1e-13)
@@ -88,7 +89,7 @@ def test_batch_mixes_carrier_models(fx, orc):
     for q, sp in enumerate(specs):
         assert info[q].status == fx.FX_OK and info[q].steps_done == n
         P_o, phi_o, _ = orc.run(sp, Ps[q], n, W.DT, tol=1e-13)
-        rp, rf = rel(bt.get(q, fx.FIELD_P), P_o), rel(bt.get(q, fx.FIELD_PHI), phi_o)
+        rp, rf = worst(sp, bt.get(q, fx.FIELD_P), P_o), worst(sp, bt.get(q, fx.FIELD_PHI), phi_o)
         say(f"  inst {q} carriers {sp.carriers}: relP {rp:.2e} relphi {rf:.2e}")
         assert rp <= 1e-10 and rf <= 1e-10, q
 

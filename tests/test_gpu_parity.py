@@ -3,8 +3,9 @@
 Tolerances: the time step is explicit and the discrete Poisson root is unique, so both sides
 compute the same numbers up to rounding and solver tolerance.  Parity runs solve to
 ||r|| <= 1e-13 ||f|| on both sides; two such solutions differ by at most cond(J) * 2e-13
-relative, and the comparisons below use the stated relative-L2 bound 1e-10 for phi and P
-after N steps.  The TDGL kernel alone is a fixed formula: 1e-13 relative.
+relative, and the comparisons below use the stated bound 1e-10 for phi and P after N steps,
+both as relative L2 over the device cells and as the largest per-cell difference relative to
+the largest oracle value (parity_check).  The TDGL kernel alone is a fixed formula: 1e-13.
 """
 import sys
 
@@ -12,6 +13,7 @@ import numpy as np
 import pytest
 
 from paper_2210_15668_amd import workloads as W
+from parity_check import check
 
 pytestmark = pytest.mark.gpu
 
@@ -52,7 +54,7 @@ def test_tdgl_kernel_parity(fx, orc, pbc):
     P_gpu = s.get(fx.FIELD_P)
     P_orc = orc.tdgl_step(spec, P0, phi_o, W.DT)
     f0, f1 = spec.fe_range()
-    assert rel(P_gpu, P_orc) <= 1e-13
+    check(spec, P_gpu, P_orc, 1e-13, "P")
     assert rel(P_gpu[f0:f1] - P0[f0:f1], P_orc[f0:f1] - P0[f0:f1]) <= 1e-11   # the increment itself
     assert np.all(P_gpu[:f0] == 0) and np.all(P_gpu[f1:] == 0)
 
@@ -62,7 +64,7 @@ def test_step0_parity_mfim(fx, orc):
     P0 = W.random_P(spec, 0)
     s = make_stack(fx, spec, P0)
     phi_o, _ = orc.solve(spec, P0, tol=1e-13)
-    assert rel(s.get(fx.FIELD_PHI), phi_o) <= 1e-10
+    check(spec, s.get(fx.FIELD_PHI), phi_o, 1e-10, "phi")
 
 
 @pytest.mark.parametrize("prec", [W.PREC_FP64, W.PREC_MIXED])
@@ -74,10 +76,10 @@ def test_run_steps_parity_mfim_small(fx, orc, prec):
     info = s.run_steps(100, W.DT)
     assert info.steps_done == 100
     P_o, phi_o, _ = orc.run(spec, P0, 100, W.DT, tol=1e-13)
-    say(f"  cycles/step {info.total_cycles / 100:.2f}  relP {rel(s.get(fx.FIELD_P), P_o):.2e} "
-        f"relphi {rel(s.get(fx.FIELD_PHI), phi_o):.2e}")
-    assert rel(s.get(fx.FIELD_P), P_o) <= 1e-10
-    assert rel(s.get(fx.FIELD_PHI), phi_o) <= 1e-10
+    eP = check(spec, s.get(fx.FIELD_P), P_o, 1e-10, "P")
+    ephi = check(spec, s.get(fx.FIELD_PHI), phi_o, 1e-10, "phi")
+    say(f"  cycles/step {info.total_cycles / 100:.2f}  P (L2, max) {eP[0]:.2e} {eP[1]:.2e}  "
+        f"phi {ephi[0]:.2e} {ephi[1]:.2e}")
 
 
 @pytest.mark.parametrize("prec", [W.PREC_FP64, W.PREC_MIXED])
@@ -88,12 +90,12 @@ def test_mfism_parity_shrunk(fx, orc, prec):
     s = make_stack(fx, spec, P0)
     phi0 = s.get(fx.FIELD_PHI)
     phi_o0, _ = orc.solve(spec, P0, tol=1e-13)
-    assert rel(phi0, phi_o0) <= 1e-10
+    check(spec, phi0, phi_o0, 1e-10, "phi0")
     info = s.run_steps(5, W.DT)
     P_o, phi_o, _ = orc.run(spec, P0, 5, W.DT, tol=1e-13, phi0=phi_o0, init=False)
     say(f"  cycles/step {info.total_cycles / 5:.2f}")
-    assert rel(s.get(fx.FIELD_P), P_o) <= 1e-10
-    assert rel(s.get(fx.FIELD_PHI), phi_o) <= 1e-10
+    check(spec, s.get(fx.FIELD_P), P_o, 1e-10, "P")
+    check(spec, s.get(fx.FIELD_PHI), phi_o, 1e-10, "phi")
 
 
 def test_ramp_parity(fx, orc):
@@ -104,8 +106,8 @@ def test_ramp_parity(fx, orc):
     s = make_stack(fx, spec, P0)
     s.run_steps(12, W.DT, vs)
     P_o, phi_o, _ = orc.run(spec, P0, 12, W.DT, v_sched=vs, tol=1e-13)
-    assert rel(s.get(fx.FIELD_P), P_o) <= 1e-10
-    assert rel(s.get(fx.FIELD_PHI), phi_o) <= 1e-10
+    check(spec, s.get(fx.FIELD_P), P_o, 1e-10, "P")
+    check(spec, s.get(fx.FIELD_PHI), phi_o, 1e-10, "phi")
 
 
 ODD = [
@@ -118,6 +120,18 @@ ODD = [
                             pbc=W.PBC_FREE, v=1.7)),
     ("6x2x5 tiny", dict(nx=6, ny=2, nz=7, layers=[(W.FE, 3, W.EPS_FE, 0.0), (W.DE, 2, W.EPS_SIO2, 0.0)],
                         pbc=W.PBC_LAMBDA, v=0.3)),
+    # the paper's 2D reduction (ny = 1, Results, MFIM): red/black storage with a single row;
+    # the first has every level inside the coarse kernel (the update formed in the residual
+    # kernel), the second its own finest-level launches (the update folded into the smoother)
+    ("16x1 2D MFIM", dict(nx=16, ny=1, nz=32, layers=[(W.FE, 16, W.EPS_FE, 0.0), (W.DE, 4, W.EPS_SIO2, 0.0)],
+                          pbc=W.PBC_LAMBDA, v=1.0)),
+    ("20x1 2D MFISM", dict(nx=20, ny=1, nz=30, layers=[(W.FE, 10, W.EPS_FE, 0.0), (W.DE, 4, W.EPS_SIO2, 0.0),
+                                                       (W.SC, 14, W.EPS_SI, 1e24)], pbc=W.PBC_LAMBDA, v=0.9)),
+    # (a single row halves x alone on the way down)
+    ("64x1 2D MFISM", dict(nx=64, ny=1, nz=128, layers=[(W.FE, 48, W.EPS_FE, 0.0), (W.DE, 8, W.EPS_SIO2, 0.0),
+                                                        (W.SC, 64, W.EPS_SI, 1e24)], pbc=W.PBC_LAMBDA, v=1.0)),
+    ("256x1 2D MFISM", dict(nx=256, ny=1, nz=128, layers=[(W.FE, 48, W.EPS_FE, 0.0), (W.DE, 8, W.EPS_SIO2, 0.0),
+                                                          (W.SC, 64, W.EPS_SI, 1e24)], pbc=W.PBC_LAMBDA, v=1.0)),
 ]
 
 
@@ -125,13 +139,14 @@ ODD = [
 @pytest.mark.parametrize("prec", [W.PREC_FP64, W.PREC_MIXED])
 def test_edge_shapes(fx, orc, name, cfg, prec):
     spec = W.layered(cfg["nx"], cfg["ny"], cfg["nz"], cfg["layers"], pbc=cfg["pbc"], v_top=cfg["v"],
-                     tol_rel=1e-13, prec=prec)
+                     tol_rel=1e-13, prec=prec, max_cycles=cfg.get("max_cycles", 60))
     P0 = W.random_P(spec, 9, amp=0.05)
     s = make_stack(fx, spec, P0)
-    s.run_steps(4, W.DT)
+    info = s.run_steps(4, W.DT)
+    say(f"    {info.total_cycles / 4:.1f} V-cycles per step, {fx.lib().stack_num_levels(s._h)} levels")
     P_o, phi_o, _ = orc.run(spec, P0, 4, W.DT, tol=1e-13)
-    assert rel(s.get(fx.FIELD_P), P_o) <= 1e-10
-    assert rel(s.get(fx.FIELD_PHI), phi_o) <= 1e-10
+    check(spec, s.get(fx.FIELD_P), P_o, 1e-10, "P")
+    check(spec, s.get(fx.FIELD_PHI), phi_o, 1e-10, "phi")
 
 
 def test_zero_rhs_gives_zero_phi(fx):
@@ -171,7 +186,7 @@ def test_resume_and_determinism(fx):
     with pytest.raises(fx.FerroxError):
         d.get(fx.FIELD_PHI_PREV)
     d.run_steps(3, W.DT)
-    assert rel(d.get(fx.FIELD_PHI), a.get(fx.FIELD_PHI)) <= 1e-10
+    check(spec, d.get(fx.FIELD_PHI), a.get(fx.FIELD_PHI), 1e-10, "phi after restart")
 
 
 def test_error_paths(fx):
@@ -204,5 +219,5 @@ def test_warm_start_orders_reach_the_same_root(fx, orc, order):
     info = s.run_steps(6, W.DT)
     P_o, phi_o, _ = orc.run(spec, P0, 6, W.DT, tol=1e-13)
     say(f"  warm_start {order}: {info.total_cycles / 6:.2f} cycles/step")
-    assert rel(s.get(fx.FIELD_P), P_o) <= 1e-10
-    assert rel(s.get(fx.FIELD_PHI), phi_o) <= 1e-10
+    check(spec, s.get(fx.FIELD_P), P_o, 1e-10, "P")
+    check(spec, s.get(fx.FIELD_PHI), phi_o, 1e-10, "phi")
