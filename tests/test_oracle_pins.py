@@ -489,14 +489,21 @@ def test_T7_T12_cg_newton_matches_dense_lu(orc):
 
 
 def test_T7_mfism_newton_matches_dense_newton(orc):
-    """MFISM 2x2x(4 FE, 2 DE, 6 SC): root equals a dense Newton iteration started from the oracle's
-    linearisation, each step solved by numpy.linalg.solve, and sigma matches -d rho/d phi."""
+    """MFISM 2x2x(4 FE, 2 DE, 6 SC): the oracle's root equals a dense Newton iteration, each
+    step solved by numpy.linalg.solve, and sigma matches -d rho/d phi.
+
+    The dense iteration shares only the linear operator with the oracle: L and f are assembled
+    column by column from a copy of the stack whose silicon planes carry no carriers (same
+    permittivity, so the same L and f), while the Boltzmann charge rho_c = e[p0 expm1(-phi/VT)
+    - n0 expm1(phi/VT)] and its derivative are written out here from eq. (MaxBolt_ne_np) with
+    the neutral-bulk densities of the doping.  Newton: (L + diag sigma) d = f - L phi + rho_c,
+    halving the step until ||G|| falls."""
     spec = W.layered(2, 2, 14, [(W.FE, 4, W.EPS_FE, 0.0), (W.DE, 2, W.EPS_SIO2, 0.0),
                                 (W.SC, 6, W.EPS_SI, 1e24)], v_top=0.4, pbc=W.PBC_LAMBDA)
     P = W.random_P(spec, 5, amp=0.05)
     phi, _ = orc.solve(spec, P, tol=1e-14)
-    # Jacobian of N at the root by central differences must be L + diag(sigma)
     kb, kt = spec.device_range()
+    # Jacobian of N at the root by central differences must be L + diag(sigma)
     f, N0, rho, sig = orc.poisson_parts(spec, P, phi)
     dv = 1e-7
     _, Np, rp, _ = orc.poisson_parts(spec, P, phi + dv)
@@ -506,6 +513,44 @@ def test_T7_mfism_newton_matches_dense_newton(orc):
     assert np.allclose(-drho[sc], sig[sc], rtol=1e-6)
     # the root satisfies the equations to round-off
     assert np.abs((f - N0)[kb:kt]).max() <= 1e-12 * np.abs(f[kb:kt]).max()
+    # dense Newton with independently written carriers
+    lin = spec.copy(plane_mat=np.where(sc, W.DE, spec.plane_mat).astype(np.int32))
+    L, fl, idx = _dense_operator(orc, lin, np.zeros((spec.nz, spec.ny, spec.nx)), P)
+    assert np.array_equal(fl, f.ravel()[idx])
+    qe, kB = 1.602176634e-19, 1.380649e-23
+    VT = kB * spec.T / qe
+    Na = spec.plane_Na[:, None, None] * np.ones((1, spec.ny, spec.nx))
+    p0 = (Na / 2 + np.sqrt(Na ** 2 / 4 + spec.ni ** 2)).ravel()[idx]
+    n0 = spec.ni ** 2 / p0
+    is_sc = np.broadcast_to(sc[:, None, None], (spec.nz, spec.ny, spec.nx)).ravel()[idx]
+
+    def rho_sig(x):
+        u = x / VT
+        r = np.where(is_sc, qe * (p0 * np.expm1(-u) - n0 * np.expm1(u)), 0.0)
+        s = np.where(is_sc, qe * (p0 * np.exp(-u) + n0 * np.exp(u)) / VT, 0.0)
+        return r, s
+
+    x = np.zeros(len(idx))
+    r0, _ = rho_sig(x)
+    g = fl - (L @ x - r0)
+    fnorm = np.linalg.norm(fl)
+    for _ in range(100):
+        if np.linalg.norm(g) <= 1e-14 * fnorm:
+            break
+        _, s = rho_sig(x)
+        d = np.linalg.solve(L + np.diag(s), g)
+        t = 1.0
+        while True:
+            r1, _ = rho_sig(x + t * d)
+            g1 = fl - (L @ (x + t * d) - r1)
+            if np.linalg.norm(g1) < np.linalg.norm(g) or t < 1e-6:
+                break
+            t *= 0.5
+        x, g = x + t * d, g1
+    assert np.linalg.norm(g) <= 1e-13 * fnorm
+    ref = phi.ravel()[idx]
+    assert np.linalg.norm(x - ref) <= 1e-12 * np.linalg.norm(ref)
+    assert np.abs(x - ref).max() <= 1e-12 * np.abs(ref).max()
 
 
 def test_T8_lateral_reductions(orc):
