@@ -155,21 +155,30 @@ def relu(z):
 
 
 # ----------------------------------------------------------------- the network
-def forward(theta: np.ndarray, x: np.ndarray, keep: bool = False):
+# Optional rounding hooks state a reduced-precision evaluation of the same network:
+# `rnd` is applied to every stored activation (each convolution's ReLU output and each
+# pooled tensor), `grnd` to every back-propagated signal entering a convolution's
+# backward pass (after the ReLU mask).  Both default to none (plain float64).
+def _id(v):
+    return v
+
+
+def forward(theta: np.ndarray, x: np.ndarray, keep: bool = False, rnd=None):
     """Network output (D, H, W) for input x (D, H, W, 16); with keep, also the activations."""
+    rnd = rnd or _id
     p = unpack(theta)
     a = {}
 
     def layer(name, inp):
         W, b = p[name]
-        out = relu(conv3(inp, W, b))
+        out = rnd(relu(conv3(inp, W, b)))
         a[name + ".in"] = inp
         a[name] = out
         return out
 
     s0 = layer("e0b", layer("e0a", x))
-    s1 = layer("e1b", layer("e1a", pool(s0)))
-    bt = layer("b2b", layer("b2a", pool(s1)))
+    s1 = layer("e1b", layer("e1a", rnd(pool(s0))))
+    bt = layer("b2b", layer("b2a", rnd(pool(s1))))
     c1 = np.concatenate([up(bt), s1], axis=3)
     u1 = layer("d1b", layer("d1a", c1))
     c0 = np.concatenate([up(u1), s0], axis=3)
@@ -185,9 +194,11 @@ def loss(theta: np.ndarray, x: np.ndarray, target: np.ndarray) -> float:
     return float(np.mean(d * d))
 
 
-def gradient(theta: np.ndarray, x: np.ndarray, target: np.ndarray):
-    """(loss, d loss / d theta) by the chain rule through the layers above."""
-    out, a = forward(theta, x, keep=True)
+def gradient(theta: np.ndarray, x: np.ndarray, target: np.ndarray, rnd=None, grnd=None, keep: bool = False):
+    """(loss, d loss / d theta) by the chain rule through the layers above; with keep, also
+    the signal entering each convolution's backward pass ({layer: dz})."""
+    grnd = grnd or _id
+    out, a = forward(theta, x, keep=True, rnd=rnd)
     p = unpack(theta)
     g = np.zeros_like(theta)
     gp = unpack(g)
@@ -200,10 +211,13 @@ def gradient(theta: np.ndarray, x: np.ndarray, target: np.ndarray):
     gb[0] = d_out.sum()
     d = d_out[..., None] * w
 
+    sig = {}
+
     def back(name, dy):
         W, _ = p[name]
         gW, gbb = gp[name]
-        dz = dy * (a[name] > 0)
+        dz = grnd(dy * (a[name] > 0))
+        sig[name] = dz
         dx, dW, db = conv3_backward(a[name + ".in"], W, dz)
         gW += dW
         gbb += db
@@ -222,7 +236,8 @@ def gradient(theta: np.ndarray, x: np.ndarray, target: np.ndarray):
     d = back("e1a", back("e1b", d_s1))                 # w.r.t. pool(s0)
     d_s0 += pool_backward(d)
     back("e0a", back("e0b", d_s0))
-    return float(np.mean((out - target) ** 2)), g
+    L = float(np.mean((out - target) ** 2))
+    return (L, g, sig) if keep else (L, g)
 
 
 # --------------------------------------------------- inputs, targets, phi_lin
