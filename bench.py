@@ -91,6 +91,64 @@ def run_gpu(prec_name, steps, warmup, tune=True, tune_cache=None):
     return out
 
 
+def model_bytes_per_step(spec, vcycles, prec_name):
+    """The one-touch byte model of a time step: the TDGL update reads P and phi and writes P
+    (24 B per ferroelectric cell); each V(2,2) cycle moves about 149 B (FP64) or 114 B (FP32
+    multigrid inside the FP64 defect correction) per device cell over all levels, residual
+    and update included; the residual of the starting iterate reads phi and writes r (24 B,
+    mixed 20 B per device cell)."""
+    per_cycle, per_res = (149.0, 24.0) if prec_name == "fp64" else (114.0, 20.0)
+    return 24.0 * spec.n_fe() + (vcycles * per_cycle + per_res) * spec.n_active()
+
+
+def copy_bandwidth(nbytes=1 << 30, reps=20):
+    """Device-to-device copy of a 1 GiB buffer: read + write bytes per second (GB/s)."""
+    import torch
+    x = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda:0").fill_(1.0)
+    y = torch.empty_like(x)
+    for _ in range(3):
+        y.copy_(x)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(reps):
+        y.copy_(x)
+    e1.record()
+    torch.cuda.synchronize()
+    gbs = 2.0 * nbytes * reps / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    del x, y
+    torch.cuda.empty_cache()
+    return gbs
+
+
+def whole_step(spec, r, prec_name, copy_gbs):
+    b = model_bytes_per_step(spec, r["vcycles_per_step"], prec_name)
+    gbs = b * r["steps_per_s"] / 1e9
+    return {"model_bytes_per_step": b, "GBs": gbs, "frac_of_8TBs": gbs / HBM_PEAK_GBS,
+            "frac_of_measured_copy": gbs / copy_gbs if copy_gbs else None,
+            "vcycles_per_step": r["vcycles_per_step"]}
+
+
+def run_ramp(prec_name="fp64", nsteps=2000):
+    """The 128 x 128 x 64 MFIM with its gate ramped 0 -> 1.5 V over 2000 steps, run in full:
+    Step 0 untimed, then the 2000 steps timed."""
+    import torch
+    from paper_2210_15668_amd import ferrox
+    from paper_2210_15668_amd import workloads as W
+    spec = W.mfim_ramp().copy(prec=W.PREC_FP64 if prec_name == "fp64" else W.PREC_MIXED)
+    vs = W.ramp_schedule(nsteps, 1.5, 2000)
+    s = ferrox.Stack(spec, W.random_P(spec, 1), device="cuda:0")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    info = s.run_steps(nsteps, W.DT, vs)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    s.close()
+    r = {"steps_per_s": nsteps / dt, "ms_per_step": 1e3 * dt / nsteps, "steps": nsteps,
+         "vcycles_per_step": info.total_cycles / nsteps, "last_rel_residual": info.last_res_rel}
+    return spec, r
+
+
 def run_batch64(prec_name, steps, warmup, tune=True, tune_cache=None):
     """The 64 uneven MFIM instances advanced together (one launch per kernel for all of
     them, graph replay): time steps of the whole batch per second."""
@@ -176,10 +234,99 @@ def cpu_baseline(sample_steps):
     oracle.run(spec, P0, sample_steps, W.DT, tol=full.tol_rel, phi0=phi0, init=False)
     dt = time.perf_counter() - t0
     ratio = (spec.nx * spec.ny) / (full.nx * full.ny)
-    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    cores = oracle_threads()
     return {"value": sample_steps / dt * ratio, "unit": "steps/s", "cores": cores, "kind": "oracle",
+            "cpu_model": cpu_model(),
             "sample": f"{sample_steps} steps of the same stack on a 64x64 footprint (1/16 of the cells), "
                       f"{dt:.1f} s, rate scaled by the cell ratio; Step 0 untimed"}
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def oracle_threads():
+    """Threads the oracle's OpenMP loops use: OMP_NUM_THREADS, else the CPUs this process may run on."""
+    v = os.environ.get("OMP_NUM_THREADS")
+    if v and v.isdigit():
+        return int(v)
+    try:
+        return len(os.sched_getaffinity(0))
+    except AttributeError:
+        return os.cpu_count() or 1
+
+
+def oracle_configs(path, which):
+    """The oracle, as it stands, timed on the workloads in full (the 16x16x32 MFIM: Step 0 +
+    100 steps; the 128x128x64 MFIM ramp: Step 0 + 2000 steps; the 64 uneven MFIM instances:
+    Step 0 + 500 steps each) and on a stated subset of the 256x256x128 MFISM (Step 0 + 20
+    steps), all at ||r|| <= 1e-10 ||f|| as on the GPU.  Writes a JSON summary to `path`
+    after each workload and prints a progress line per workload (and per 100 steps)."""
+    import numpy as np
+    import oracle
+    from paper_2210_15668_amd import workloads as W
+    out = {"cpu_model": cpu_model(), "threads": oracle_threads(), "kind": "oracle",
+           "tolerance": "||r|| <= 1e-10 ||f|| per solve", "workloads": {}}
+
+    def save():
+        with open(path, "w") as f:
+            json.dump(out, f, indent=1)
+
+    def timed_run(spec, P0, nsteps, sched, label, chunk=100):
+        t0 = time.perf_counter()
+        phi, _ = oracle.solve(spec, P0, tol=spec.tol_rel)
+        t_step0 = time.perf_counter() - t0
+        P = P0
+        t1 = time.perf_counter()
+        done = 0
+        while done < nsteps:
+            n = min(chunk, nsteps - done)
+            vs = None if sched is None else sched[done:done + n]
+            P, phi, _ = oracle.run(spec, P, n, W.DT, v_sched=vs, tol=spec.tol_rel, phi0=phi, init=False)
+            done += n
+            print(f"  {label}: {done}/{nsteps} steps, {time.perf_counter() - t1:.1f} s", flush=True)
+        return t_step0, time.perf_counter() - t1
+
+    if "c0" in which:
+        spec = W.mfim_small()
+        t0, ts = timed_run(spec, W.random_P(spec, 0), 100, None, "MFIM 16x16x32")
+        out["workloads"]["mfim16_small"] = {"workload": "MFIM 16x16x32, 1 V, 100 steps (in full)",
+                                            "step0_s": t0, "steps": 100, "steps_s": ts, "steps_per_s": 100 / ts}
+        save()
+    if "c1" in which:
+        spec = W.mfim_ramp()
+        vs = W.ramp_schedule(2000, 1.5, 2000)
+        t0, ts = timed_run(spec, W.random_P(spec, 1), 2000, vs, "MFIM 128x128x64 ramp")
+        out["workloads"]["mfim128_ramp"] = {"workload": "MFIM 128x128x64, gate ramp 0 -> 1.5 V over 2000 steps "
+                                                        "(in full)", "step0_s": t0, "steps": 2000, "steps_s": ts,
+                                            "steps_per_s": 2000 / ts}
+        save()
+    if "c2" in which:
+        spec = W.mfism_large()
+        t0, ts = timed_run(spec, W.random_P(spec, 2), 20, None, "MFISM 256x256x128", chunk=5)
+        out["workloads"]["mfism256"] = {"workload": "MFISM 256x256x128, 1 V: Step 0 + 20 of the bench's 210 "
+                                                    "steps (subset)", "step0_s": t0, "steps": 20, "steps_s": ts,
+                                        "steps_per_s": 20 / ts}
+        save()
+    if "c3" in which:
+        t_all0 = t_all = 0.0
+        for q, (spec, P0) in enumerate(W.batch_instances(64)):
+            t0, ts = timed_run(spec, P0, 500, None, f"batch instance {q} {spec.nx}x{spec.ny}x{spec.nz}", chunk=500)
+            t_all0 += t0
+            t_all += ts
+        out["workloads"]["batch64"] = {"workload": "64 uneven MFIM instances, 500 steps each (in full), "
+                                                   "one instance after another", "step0_s": t_all0, "steps": 500,
+                                       "steps_s": t_all, "batch_steps_per_s": 500 / t_all,
+                                       "instance_steps_per_s": 64 * 500 / t_all}
+        save()
+    return out
 
 
 def main():
@@ -197,7 +344,16 @@ def main():
     ap.add_argument("--no-learned", action="store_true")
     ap.add_argument("--no-variants", action="store_true", help="skip the predictor-corrector, Fermi-Dirac and Q-V lines")
     ap.add_argument("--batch-steps", type=int, default=500)
+    ap.add_argument("--no-ramp", action="store_true", help="skip the 128x128x64 gate-ramp line")
+    ap.add_argument("--oracle-configs", metavar="JSON", default=None,
+                    help="only time the CPU oracle on the workloads in full (no GPU) and write JSON")
+    ap.add_argument("--oracle-which", default="c0,c1,c2,c3",
+                    help="workloads of --oracle-configs: c0 16x16x32, c1 128x128x64 ramp, c2 256^2x128 subset, "
+                         "c3 batch of 64")
     args = ap.parse_args()
+    if args.oracle_configs:
+        oracle_configs(args.oracle_configs, set(args.oracle_which.split(",")))
+        return
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print("bench.py measures one GPU: the library has no multi-GPU path (--gpus must be 1)", file=sys.stderr)
@@ -205,7 +361,11 @@ def main():
     import numpy as np
     import oracle  # noqa: F401  (only for the cpu_baseline leg)
 
+    from paper_2210_15668_amd import workloads as W
     r64 = run_gpu("fp64", args.steps, args.warmup, not args.no_tune, args.tune_cache)
+    copy_gbs = copy_bandwidth()
+    spec_l = W.mfism_large()
+    step64 = whole_step(spec_l, r64, "fp64", copy_gbs)
     mixed = None
     if not args.no_mixed:
         rmx = run_gpu("mixed", args.steps, args.warmup, not args.no_tune, args.tune_cache)
@@ -213,7 +373,15 @@ def main():
         mixed = {"value": rmx["steps_per_s"], "ms_per_step": rmx["ms_per_step"],
                  "vcycles_per_step": rmx["vcycles_per_step"], "dtype": "f32 multigrid in f64 defect correction",
                  "rel_l2_phi_vs_fp64_after_steps": diff,
-                 "smoother_GBs": rmx["probe_bytes"] / (rmx["probe_ms"] * 1e-3) / 1e9 if rmx["probe_ms"] else None}
+                 "smoother_GBs": rmx["probe_bytes"] / (rmx["probe_ms"] * 1e-3) / 1e9 if rmx["probe_ms"] else None,
+                 "whole_step": whole_step(spec_l, rmx, "mixed", copy_gbs)}
+    ramp = None
+    if not args.no_ramp:
+        spec_r, rr = run_ramp("fp64")
+        rr["whole_step"] = whole_step(spec_r, rr, "fp64", copy_gbs)
+        rr["workload"] = ("MFIM 128x128x64 (metal 8 | FE 40 | SiO2 8 | metal 8), gate ramped 0 -> 1.5 V over "
+                          "2000 steps, FP64, ||r||/||f|| <= 1e-10, Step 0 untimed")
+        ramp = rr
     avg_us = 1e3 * r64["probe_ms"] / max(1, r64["probe_launches"])
     per_launch = r64["probe_bytes"] / max(1, r64["probe_launches"])
     achieved = per_launch / (avg_us * 1e-6) / 1e9 if avg_us > 0 else 0.0
@@ -245,7 +413,10 @@ def main():
                    "vcycles_per_step": r64["vcycles_per_step"],
                    "autotune": r64["autotune"],
                    "last_rel_residual": r64["last_rel_residual"]},
+        "whole_step": step64,
+        "copy_GBs_measured": copy_gbs,
         "mixed_precision": mixed,
+        "mfim128_ramp": ramp,
         "batch64": batch,
         "learned": learned,
         "variants": variants,
