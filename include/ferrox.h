@@ -34,7 +34,8 @@
  *    last_error() returns a message for the most recent failure on the
  *    calling thread.  A stack is not thread-safe: use it from one thread.
  *  - The library allocates no device memory: the caller passes the fields
- *    and one workspace buffer.  init_stack allocates a small pinned host
+ *    and one workspace buffer (poisson_solve_static uses the library's own
+ *    static device array instead).  init_stack allocates a small pinned host
  *    buffer for reading the solver state back, and host-side tables.
  *  - Batches (init_batch ...) hold many independent stacks of different
  *    sizes that advance together: each launch covers the tiles of all
@@ -170,6 +171,30 @@ size_t stack_workspace_bytes(const fx_stack_desc *desc);
  */
 fx_status init_stack(const fx_stack_desc *desc, double *d_P, double *d_phi, void *d_ws,
                      size_t ws_bytes, void *stream, fx_stack **out);
+
+/*
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the Step 0
+ * of init_stack -- phi := 0, then the Poisson solve for the P in d_P at
+ * desc->v_top to desc->tol_rel -- with no caller workspace and no stack
+ * handle.  Its workspace is a static device array of the library, 64 MiB on
+ * each GPU it runs on (allocated with the library's code, held until the
+ * process ends); no hipMalloc, hipHostMalloc, stream, event or graph is
+ * created, and host-side planning uses ordinary heap memory only.
+ *   d_P, d_phi : as for init_stack (d_P's entries off ferroelectric planes
+ *                are set to zero; d_phi receives phi, metal planes their
+ *                contact potential).
+ *   stream     : hipStream_t (as void*); the call synchronises it.
+ *   info       : NULL or receives the solve's cycles, status and norms.
+ * Same kernels and launch sequence as init_stack's Step 0, so phi is the
+ * same bit for bit.  Returns FX_EINVAL as init_stack, FX_ENOMEM if
+ * stack_workspace_bytes(desc) exceeds 64 MiB (the 128 x 128 x 64 MFIM stack
+ * fits), FX_ENOCONV / FX_ENONFINITE as poisson_solve.  Every call on one GPU
+ * uses that GPU's one array, and the call initialises all of it that it reads:
+ * calls that overlap on one GPU (from several threads or streams) race.
+ */
+fx_status poisson_solve_static(const fx_stack_desc *desc, double *d_P, double *d_phi, void *stream,
+                               fx_solve_info *info);
 
 /*
  * Step 1a of the time scheme: P <- P + dt f(P, phi) with eq. (TDGL2), the

@@ -34,6 +34,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <type_traits>
@@ -326,7 +327,10 @@ struct Engine {
     std::vector<InstHost> in;
     void *inst_dev = nullptr;           // Inst<T>[n]
     InstState *st_dev = nullptr;        // InstState[n]
-    InstState *mir = nullptr;           // pinned host mirror, valid between calls
+    InstState *mir = nullptr;           // host mirror of the states, valid between calls: pinned,
+                                        // or ordinary memory (mir_plain) for poisson_solve_static
+    std::vector<InstState> mir_plain;
+    int no_alloc = 0;                   // allocates no device or pinned memory (poisson_solve_static)
     int *prefix_dev = nullptr;
     double *sched_dev = nullptr;        // n x kSchedChunk gate potentials
     double *probe_dev = nullptr;        // kProbeMax byte counters
@@ -1141,8 +1145,12 @@ fx_status engine_init(Engine *e, double *const *d_P, double *const *d_phi, void 
         e->in[i].P[0] = d_P[i];
         e->in[i].phi[0] = d_phi[i];
     }
-    if (hipHostMalloc((void **)&e->mir, (size_t)e->n * sizeof(InstState), 0) != hipSuccess)
+    if (e->no_alloc) {
+        e->mir_plain.assign(e->n, InstState{});
+        e->mir = e->mir_plain.data();
+    } else if (hipHostMalloc((void **)&e->mir, (size_t)e->n * sizeof(InstState), 0) != hipSuccess) {
         return fail(FX_EDEVICE, "hipHostMalloc failed");
+    }
     fx_status st = build_work(e);
     if (st) return st;
     st = e->prec == FX_PREC_MIXED ? upload_all<float>(e) : upload_all<double>(e);
@@ -1185,7 +1193,8 @@ void engine_release(Engine *e) {
         if (e->unit_exec[q]) (void)hipGraphExecDestroy(e->unit_exec[q]);
     for (int q = 0; q < kUnitPow; ++q) e->unit_exec[q] = nullptr;
     if (e->cap) (void)hipStreamDestroy(e->cap);
-    if (e->mir) (void)hipHostFree(e->mir);
+    if (e->mir && !e->no_alloc) (void)hipHostFree(e->mir);
+    e->mir = nullptr;
     for (hipEvent_t ev : e->ev) (void)hipEventDestroy(ev);
 }
 
@@ -1541,6 +1550,39 @@ fx_status unet_tables(const Engine *e, fx_unet *u, double v_top, bool doping) {
 }  // namespace
 
 
+// ------------------------------------------- workspace without allocation
+// The workspace of poisson_solve_static: a file-scope device array, one copy on
+// every GPU the library runs on, held until the process ends.  Host code never
+// uses the array's name as an address: each device's copy is looked up once,
+// with that device current, and that address is what the kernels receive.
+constexpr size_t kStaticWsBytes = (size_t)64 << 20;
+static __device__ __align__(256) unsigned char scratch[kStaticWsBytes];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+
+// Address of the current device's copy of the static workspace.
+fx_status static_workspace(void **out) {
+    int dev = -1;
+    HIP_OK(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) return fail(FX_EDEVICE, "device %d outside 0..%d", dev, kMaxDevices - 1);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *ptr = nullptr;
+        const hipError_t err = hipGetSymbolAddress((void **)&ptr, HIP_SYMBOL(scratch));
+        if (err != hipSuccess || !ptr)
+            return fail(FX_EDEVICE, "hipGetSymbolAddress of the static workspace failed: %s", hipGetErrorString(err));
+        g_scratch_ptr[dev] = ptr;
+    }
+    *out = g_scratch_ptr[dev];
+    return FX_OK;
+}
+
+}  // namespace
+
 extern "C" {
 
 size_t stack_workspace_bytes(const fx_stack_desc *desc) {
@@ -1578,6 +1620,44 @@ fx_status init_stack(const fx_stack_desc *desc, double *d_P, double *d_phi, void
     fx_status st2 = sync_to_caller(e);
     if (!st2) st2 = status_message(e->mir[0], -1);
     return st2;
+}
+
+fx_status poisson_solve_static(const fx_stack_desc *desc, double *d_P, double *d_phi, void *stream,
+                               fx_solve_info *info) {
+    g_err.clear();
+    if (!d_P || !d_phi) return fail(FX_EINVAL, "device pointers must not be NULL");
+    if (((uintptr_t)d_P & 15) != 0 || ((uintptr_t)d_phi & 15) != 0)
+        return fail(FX_EINVAL, "d_P and d_phi must be 16-byte aligned");
+    Engine e;
+    e.no_alloc = 1;
+    fx_status st = validate_all(desc, 1, &e);
+    if (st) return st;
+    plan_launches(&e);
+    e.mode = FX_LAUNCH_STREAM;                     // no graphs: capturing one would allocate
+    const size_t need = carve(&e, nullptr);
+    if (need > kStaticWsBytes)
+        return fail(FX_ENOMEM, "this stack needs %zu bytes of workspace; the static workspace holds %zu", need,
+                    kStaticWsBytes);
+    void *ws = nullptr;
+    if ((st = static_workspace(&ws))) return st;
+    st = engine_init(&e, &d_P, &d_phi, ws, kStaticWsBytes, stream);
+    if (!st || st == FX_ENOCONV || st == FX_ENONFINITE) {
+        const fx_status st2 = sync_to_caller(&e);
+        if (!st2 && e.mir) {
+            const InstState &c = e.mir[0];
+            if (info) {
+                info->cycles = c.cycles;
+                info->status = c.status;
+                info->res_norm = c.status == FX_OK && c.zero_fix ? 0.0 : std::sqrt(c.rn2);
+                info->rhs_norm = std::sqrt(c.fn2);
+            }
+            if (!st) st = status_message(c, -1);
+        } else if (st2) {
+            st = st2;
+        }
+    }
+    engine_release(&e);
+    return st;
 }
 
 fx_status tdgl_step(fx_stack *s, double dt) {

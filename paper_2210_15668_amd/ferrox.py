@@ -78,6 +78,7 @@ _D = ctypes.POINTER(StackDesc)
 SIGNATURES = [
     ("stack_workspace_bytes", ctypes.c_size_t, [_D]),
     ("init_stack", ctypes.c_int, [_D, _vp, _vp, _vp, ctypes.c_size_t, _vp, ctypes.POINTER(_vp)]),
+    ("poisson_solve_static", ctypes.c_int, [_D, _vp, _vp, _vp, ctypes.POINTER(SolveInfo)]),
     ("tdgl_step", ctypes.c_int, [_vp, ctypes.c_double]),
     ("poisson_solve", ctypes.c_int, [_vp, ctypes.c_double, ctypes.POINTER(SolveInfo)]),
     ("run_steps", ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_double, _dp, ctypes.POINTER(RunInfo)]),
@@ -168,6 +169,26 @@ class _DescHolder:
 def workspace_bytes(spec: W.StackSpec) -> int:
     h = _DescHolder(spec)
     return int(lib().stack_workspace_bytes(ctypes.byref(h.d)))
+
+
+def poisson_solve_static(spec: W.StackSpec, P, phi, stream=None, check: bool = True) -> SolveInfo:
+    """init_stack's Step 0 through poisson_solve_static: P and phi are float64 CUDA tensors of
+    shape (nz, ny, nx) (P's entries off the ferroelectric are zeroed, phi receives the root);
+    the library's static device workspace is used, nothing is allocated."""
+    import torch
+    shape = (spec.nz, spec.ny, spec.nx)
+    for t in (P, phi):
+        if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == torch.float64 and t.is_contiguous()
+                and tuple(t.shape) == shape):
+            raise ValueError("P and phi must be contiguous float64 CUDA tensors of shape (nz, ny, nx)")
+    h = _DescHolder(spec)
+    st = stream if stream is not None else torch.cuda.current_stream(P.device)
+    info = SolveInfo()
+    status = lib().poisson_solve_static(ctypes.byref(h.d), P.data_ptr(), phi.data_ptr(), st.cuda_stream,
+                                        ctypes.byref(info))
+    if check:
+        _check(status)
+    return info
 
 
 class Stack:
