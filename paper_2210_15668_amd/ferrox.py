@@ -191,6 +191,30 @@ def poisson_solve_static(spec: W.StackSpec, P, phi, stream=None, check: bool = T
     return info
 
 
+class _Workspace:
+    """The caller-owned workspace as a torch uint8 buffer; with guard > 0 (a multiple of
+    256 bytes) it sits between two guard regions filled with 0xA5, which `intact()`
+    checks (the library must never write outside the bytes it asked for)."""
+
+    def __init__(self, torch, nbytes: int, device, guard: int = 0):
+        if guard % 256:
+            raise ValueError("guard must be a multiple of 256 bytes")
+        self.guard, self.nbytes = guard, nbytes
+        self.buf = torch.empty(nbytes + 2 * guard, dtype=torch.uint8, device=device)
+        if guard:
+            self.buf[:guard].fill_(0xA5)
+            self.buf[guard + nbytes:].fill_(0xA5)
+
+    def ptr(self) -> int:
+        return self.buf.data_ptr() + self.guard
+
+    def intact(self) -> bool:
+        if not self.guard:
+            return True
+        g = self.guard
+        return bool((self.buf[:g] == 0xA5).all().item()) and bool((self.buf[g + self.nbytes:] == 0xA5).all().item())
+
+
 class Stack:
     """One device stack: P, phi and the workspace live in torch CUDA tensors.
 
@@ -198,7 +222,8 @@ class Stack:
     tensors of shape (nz, ny, nx) that always hold the current state.
     """
 
-    def __init__(self, spec: W.StackSpec, P0, device: str = "cuda:0", stream=None, check_init: bool = True):
+    def __init__(self, spec: W.StackSpec, P0, device: str = "cuda:0", stream=None, check_init: bool = True,
+                 guard: int = 0):
         import torch
         self._torch = torch
         self.spec = spec
@@ -214,11 +239,12 @@ class Stack:
         nbytes = int(lib().stack_workspace_bytes(ctypes.byref(self._desc.d)))
         if nbytes == 0:
             raise FerroxError(FX_EINVAL, lib().last_error().decode())
-        self.ws = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        self._ws = _Workspace(torch, nbytes, self.device, guard)
+        self.ws = self._ws.buf
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
         self._h = ctypes.c_void_p()
         st = lib().init_stack(ctypes.byref(self._desc.d), self.P.data_ptr(), self.phi.data_ptr(),
-                              self.ws.data_ptr(), nbytes, self.stream.cuda_stream, ctypes.byref(self._h))
+                              self._ws.ptr(), nbytes, self.stream.cuda_stream, ctypes.byref(self._h))
         if not self._h.value:
             _check(st)
         self.init_status = st
@@ -317,6 +343,10 @@ class Stack:
             out.append((a.value, b.value, c.value))
         return out
 
+    def guard_intact(self) -> bool:
+        """The guard regions around the workspace still hold their fill (see _Workspace)."""
+        return self._ws.intact()
+
     def close(self):
         if getattr(self, "_h", None) is not None and self._h.value:
             lib().destroy_stack(self._h)
@@ -342,7 +372,7 @@ class Batch:
     every call.  Construction runs Step 0 for every instance."""
 
     def __init__(self, specs: Sequence[W.StackSpec], P0s, device: str = "cuda:0", stream=None,
-                 check_init: bool = True):
+                 check_init: bool = True, guard: int = 0):
         import torch
         self.specs = list(specs)
         self.n = len(self.specs)
@@ -362,12 +392,13 @@ class Batch:
         nbytes = int(lib().batch_workspace_bytes(self._descs, self.n))
         if nbytes == 0:
             raise FerroxError(FX_EINVAL, lib().last_error().decode())
-        self.ws = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        self._ws = _Workspace(torch, nbytes, self.device, guard)
+        self.ws = self._ws.buf
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
         pP = (_vp * self.n)(*[t.data_ptr() for t in self.P])
         pphi = (_vp * self.n)(*[t.data_ptr() for t in self.phi])
         self._h = ctypes.c_void_p()
-        st = lib().init_batch(self._descs, self.n, pP, pphi, self.ws.data_ptr(), nbytes,
+        st = lib().init_batch(self._descs, self.n, pP, pphi, self._ws.ptr(), nbytes,
                               self.stream.cuda_stream, ctypes.byref(self._h))
         if not self._h.value:
             _check(st)
@@ -426,6 +457,10 @@ class Batch:
         path = cache_path.encode() if cache_path else None
         _check(lib().batch_autotune(self._h, path, TUNE_FORCE if force else 0, ctypes.byref(info)))
         return info
+
+    def guard_intact(self) -> bool:
+        """The guard regions around the workspace still hold their fill (see _Workspace)."""
+        return self._ws.intact()
 
     def close(self):
         if getattr(self, "_h", None) is not None and self._h.value:
