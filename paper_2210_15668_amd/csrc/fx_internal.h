@@ -219,6 +219,9 @@ template <typename T> void launch_prolong_red(const Inst<T> *I, const Work &w, i
                                               hipStream_t st);
 template <typename T> void launch_restrict(const Inst<T> *I, const Work &w, int level, hipStream_t st);
 template <typename T> void launch_prolong(const Inst<T> *I, const Work &w, int level, hipStream_t st);
+// the same prolongation by coarse columns, for red/black levels halved in x and y and
+// paired in z (the work table counts exactly those instances' tiles)
+template <typename T> void launch_prolong_cc(const Inst<T> *I, const Work &w, int level, int cz, hipStream_t st);
 template <typename T> void launch_coarse(const Inst<T> *I, int ninst, int lds_bytes, hipStream_t st);
 template <typename T> void launch_head(const Inst<T> *I, int ninst, int advance, hipStream_t st);
 template <typename T> void launch_zero_fix(const Inst<T> *I, const Work &w, hipStream_t st);
@@ -239,6 +242,9 @@ inline int tiles_cfg(int nxw, int ny, int nz, const SmoothCfg &c) {
 }
 constexpr int kResZ = 4;            // planes per thread in the fine-level residual
 constexpr int kProZ = 4;            // planes per thread in the prolongation kernel
+constexpr int kProCZ = 4;           // coarse planes per thread in the coarse-column prolongation
+                                    // into a level of at least kProCZBig coarse cells (else 1)
+constexpr size_t kProCZBig = (size_t)1 << 19;
 constexpr int kExtrapChunk = 1024;  // cells per extrapolation tile
 
 }  // namespace fx

@@ -295,6 +295,32 @@ __device__ __forceinline__ void restrict_cell_rbxy(const V &F, const V &C, const
     if (has_sig(C, K)) C.sig[sidx(C, I, J, K)] = (T)(ss * 0.25);
 }
 
+// Fused multiply-add of the working precision, written out so that every kernel that
+// interpolates rounds alike whatever the compiler would contract.
+__device__ __forceinline__ double fmad(double a, double b, double c) { return __builtin_fma(a, b, c); }
+__device__ __forceinline__ float fmad(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+
+// The lateral interpolant of one coarse plane: sum of w[yy][xx] v[yy][xx] in row order,
+// the first term a product and the others fused multiply-adds.  With lint_z, the value
+// of a fine plane from its parent plane s0 and the neighbour plane s1.  Every
+// prolongation (per fine cell, fused into the red half-sweep, by coarse columns, and
+// inside the coarse kernel) goes through these two, so their corrections agree bit for
+// bit.
+template <int NY, int NX, typename T>
+__device__ __forceinline__ T lint_xy(const T (&w)[2][2], const T (&v)[2][2]) {
+    T s = w[0][0] * v[0][0];
+#pragma unroll
+    for (int yy = 0; yy < NY; ++yy)
+#pragma unroll
+        for (int xx = 0; xx < NX; ++xx)
+            if (yy + xx > 0) s = fmad(w[yy][xx], v[yy][xx], s);
+    return s;
+}
+template <typename T>
+__device__ __forceinline__ T lint_z(T wa, T s0, T wb, T s1) {
+    return fmad(wb, s1, wa * s0);
+}
+
 // e_f += I e_c: bilinear in x,y (cell-centred 3/4, 1/4), in z linear in the
 // series resistance between coarse plane centres (zero on contact faces).  On
 // a red/black level only black cells are corrected: the red values are
@@ -329,18 +355,21 @@ __device__ __forceinline__ typename V::value_type prolong_value(const V &C, cons
     }
     const int ka = Xf.pka[k], kb = Xf.pkb[k];
     const int kz[2] = {ka, kb >= 0 ? kb : ka};
-    const T wz[2] = {Xf.pwa[k], kb >= 0 ? Xf.pwb[k] : T(0)};
-    T v = 0;
+    T w[2][2], s[2];
+#pragma unroll
+    for (int yy = 0; yy < 2; ++yy)
+#pragma unroll
+        for (int xx = 0; xx < 2; ++xx) w[yy][xx] = wx[xx] * wy[yy];
 #pragma unroll
     for (int q = 0; q < 2; ++q) {
-        T s = 0;
+        T v[2][2] = {{T(0), T(0)}, {T(0), T(0)}};
 #pragma unroll
         for (int yy = 0; yy < nsy; ++yy)
 #pragma unroll
-            for (int xx = 0; xx < nsx; ++xx) s += wx[xx] * wy[yy] * C.e[cidx(C, ix[xx], jy[yy], kz[q])];
-        v += wz[q] * s;
+            for (int xx = 0; xx < nsx; ++xx) v[yy][xx] = C.e[cidx(C, ix[xx], jy[yy], kz[q])];
+        s[q] = lint_xy<nsy, nsx>(w, v);
     }
-    return v;
+    return lint_z(T(Xf.pwa[k]), s[0], kb >= 0 ? T(Xf.pwb[k]) : T(0), s[1]);
 }
 template <typename V, typename X>
 __device__ __forceinline__ void prolong_cell(const V &F, const V &C, const X &Xf, int i, int j, int k) {
@@ -1228,6 +1257,100 @@ __global__ __launch_bounds__(256) void k_prolong_red(const Inst<T> *I, Work w, i
     else prolong_red_body<0, T, ZT>(F, C, X, b.t, lbx);
 }
 
+// Prolongation into a red/black level halved in x and y and paired in z, a thread
+// per coarse column of cz planes.  For each coarse plane the thread loads the
+// 3 x 3 neighbourhood of its column once and forms the bilinear values at its four
+// child columns; every fine plane of its children then combines the values of its
+// parent plane and of the neighbour plane named by the z tables, kept in registers
+// as the thread marches up.  Each value goes through lint_xy and lint_z with the
+// operands of prolong_value, so the corrections are those of prolong_column bit for
+// bit; only black children are corrected (the red ones are overwritten by the next
+// red half-sweep without being read).
+template <typename T>
+__device__ __forceinline__ void prolong_cc_interp(const Lv<T, 1> &C, int K, int Im, int I, int Ip, int Jm, int J,
+                                                  int Jp, T (&s)[2][2]) {
+    const int ii[3] = {Im, I, Ip}, jj[3] = {Jm, J, Jp};
+    T v[3][3];
+#pragma unroll
+    for (int b = 0; b < 3; ++b)
+#pragma unroll
+        for (int a = 0; a < 3; ++a) v[b][a] = C.e[cidx(C, ii[a], jj[b], K)];
+    const T wx[2] = {T(0.75), T(0.25)}, wy[2] = {T(0.75), T(0.25)};
+    T w[2][2];
+#pragma unroll
+    for (int yy = 0; yy < 2; ++yy)
+#pragma unroll
+        for (int xx = 0; xx < 2; ++xx) w[yy][xx] = wx[xx] * wy[yy];
+#pragma unroll
+    for (int dy = 0; dy < 2; ++dy)
+#pragma unroll
+        for (int dx = 0; dx < 2; ++dx) {
+            const int ix[2] = {1, dx ? 2 : 0}, jy[2] = {1, dy ? 2 : 0};
+            T u[2][2];
+#pragma unroll
+            for (int yy = 0; yy < 2; ++yy)
+#pragma unroll
+                for (int xx = 0; xx < 2; ++xx) u[yy][xx] = v[jy[yy]][ix[xx]];
+            s[dy][dx] = lint_xy<2, 2>(w, u);
+        }
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_prolong_cc(const Inst<T> *Ia, Work w, int level, int cz) {
+    const Blk b = find_block(w);
+    if (!b.ok) return;
+    const Inst<T> &a = Ia[b.inst];
+    if (asp<1>(a.st)->done) return;
+    const Lv<T, 1> C = gview(a.lv[level + 1]);
+    const T3 t = split3(b.t, C.nx, C.ny);
+    const int I = t.tx * BX + threadIdx.x;
+    const int J = t.ty * BY + threadIdx.y;
+    if (I >= C.nx || J >= C.ny) return;
+    const Lv<T, 1> F = gview(a.lv[level]);
+    const Xv<T> X = xview(a.xf[level]);
+    const int Im = wrap_m(I, C.nx), Ip = wrap_p(I, C.nx), Jm = wrap_m(J, C.ny), Jp = wrap_p(J, C.ny);
+    const int K0 = t.tz * cz, K1 = min(K0 + cz, C.nz);
+    T sp[2][2], sc[2][2], sn[2][2];
+    prolong_cc_interp(C, K0 > 0 ? K0 - 1 : K0, Im, I, Ip, Jm, J, Jp, sp);
+    prolong_cc_interp(C, K0, Im, I, Ip, Jm, J, Jp, sc);
+    for (int K = K0; K < K1; ++K) {
+        prolong_cc_interp(C, K + 1 < C.nz ? K + 1 : K, Im, I, Ip, Jm, J, Jp, sn);
+        int c[4];
+        T e[4], v[4];
+        int nf = 0;
+#pragma unroll
+        for (int dz = 0; dz < 2; ++dz) {
+            const int k = 2 * K + dz;
+            if (k >= F.nz) break;
+            const int kb = X.pkb[k];
+            const T wa = X.pwa[k], wb = kb >= 0 ? X.pwb[k] : T(0);
+#pragma unroll
+            for (int dy = 0; dy < 2; ++dy) {
+                // the black child of this row on plane k: (dx + dy + k) odd
+                const int dx = (1 + dy + k) & 1;
+                const T s0 = sc[dy][dx];
+                const T s1 = kb < 0 ? s0 : (kb < K ? sp[dy][dx] : sn[dy][dx]);
+                const T val = lint_z(wa, s0, wb, s1);
+                const int q = 2 * dz + dy;
+                c[q] = cidx(F, 2 * I + dx, 2 * J + dy, k);
+                e[q] = F.e[c[q]];
+                v[q] = val;
+            }
+            nf = 2 * dz + 2;
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+            if (q < nf) F.e[c[q]] = e[q] + v[q];
+#pragma unroll
+        for (int dy = 0; dy < 2; ++dy)
+#pragma unroll
+            for (int dx = 0; dx < 2; ++dx) {
+                sp[dy][dx] = sc[dy][dx];
+                sc[dy][dx] = sn[dy][dx];
+            }
+    }
+}
+
 template <typename T>
 __global__ __launch_bounds__(256) void k_prolong(const Inst<T> *I, Work w, int level) {
     const Blk b = find_block(w);
@@ -1735,6 +1858,11 @@ void launch_prolong(const Inst<T> *I, const Work &w, int level, hipStream_t st) 
 }
 
 template <typename T>
+void launch_prolong_cc(const Inst<T> *I, const Work &w, int level, int cz, hipStream_t st) {
+    FX_LAUNCH(k_prolong_cc<T>, w, I, w, level, cz);
+}
+
+template <typename T>
 void launch_coarse(const Inst<T> *I, int ninst, int lds_bytes, hipStream_t st) {
     hipLaunchKernelGGL(k_coarse<T>, dim3(ninst), dim3(512), lds_bytes, st, I);
 }
@@ -1788,6 +1916,7 @@ void launch_fill(double *x, size_t n, double v, hipStream_t st) {
     template void launch_prolong_red<T>(const Inst<T> *, const Work &, int, const SmoothCfg &, hipStream_t);  \
     template void launch_restrict<T>(const Inst<T> *, const Work &, int, hipStream_t);                       \
     template void launch_prolong<T>(const Inst<T> *, const Work &, int, hipStream_t);                        \
+    template void launch_prolong_cc<T>(const Inst<T> *, const Work &, int, int, hipStream_t);                \
     template void launch_coarse<T>(const Inst<T> *, int, int, hipStream_t);                                  \
     template void launch_head<T>(const Inst<T> *, int, int, hipStream_t);                                    \
     template void launch_zero_fix<T>(const Inst<T> *, const Work &, hipStream_t);                            \

@@ -339,7 +339,8 @@ struct Engine {
     int graphs_rec = 0;                 // the captured unit graphs include the recording
     std::vector<int> prefix_host;
     Work w_tdgl{}, w_ext{}, w_res{};
-    std::vector<Work> w_sm, w_rs, w_pr;
+    std::vector<Work> w_sm, w_rs, w_pr, w_prc;   // w_pr / w_prc: prolongation by fine or by coarse columns
+    std::vector<int> prc_cz;            // coarse planes per thread of w_prc, per level
     std::vector<SmoothCfg> scfg;        // smoother launch shape per level
     std::vector<int> ncol;
     std::vector<char> small;            // per level: few enough cells that launch latency dominates
@@ -524,7 +525,7 @@ size_t carve(Engine *e, void *ws) {
     const size_t inst_bytes = mixed ? sizeof(Inst<float>) : sizeof(Inst<double>);
     e->inst_dev = cv.take((size_t)e->n * inst_bytes);
     e->st_dev = (InstState *)cv.take((size_t)e->n * sizeof(InstState));
-    const size_t ntab = 3 + 3 * (size_t)e->max_lc;
+    const size_t ntab = 3 + 4 * (size_t)e->max_lc;
     e->prefix_dev = (int *)cv.take(ntab * (e->n + 1) * sizeof(int));
     e->sched_dev = (double *)cv.take((size_t)e->n * kSchedChunk * sizeof(double));
     e->probe_dev = (double *)cv.take(kProbeMax * sizeof(double));
@@ -559,7 +560,12 @@ fx_status build_work(Engine *e) {
         return (int)(((size_t)p.nx * p.ny * p.nzd + kExtrapChunk - 1) / kExtrapChunk);
     });
     e->w_res = mk([](const InstHost &h) { const Plan &p = h.plan; return tiles3(p.nx, p.ny, (p.nzd + kResZ - 1) / kResZ); });
-    e->w_sm.clear(); e->w_rs.clear(); e->w_pr.clear();
+    e->w_sm.clear(); e->w_rs.clear(); e->w_pr.clear(); e->w_prc.clear(); e->prc_cz.clear();
+    const int cc_ok = env_int("FERROX_PROLONG_CC", 1) != 0;
+    // the coarse-column prolongation: red/black fine level, x and y halved, z paired
+    auto by_cc = [cc_ok](const Plan &p, int l) {
+        return cc_ok && p.lv[l].rb && p.lv[l + 1].xy_from_finer == 1 && p.lv[l + 1].z_from_finer;
+    };
     for (int l = 0; l < e->max_lc; ++l) {
         const SmoothCfg c = e->scfg[l];
         e->w_sm.push_back(mk([&](const InstHost &h) { return l < h.plan.lc ? tiles_smooth(h.plan.lv[l], c) : 0; }));
@@ -569,10 +575,22 @@ fx_status build_work(Engine *e) {
             return tiles3(C.nx, C.ny, C.nz);
         }));
         e->w_pr.push_back(mk([&](const InstHost &h) {
-            if (l >= h.plan.lc) return 0;
+            if (l >= h.plan.lc || by_cc(h.plan, l)) return 0;
             const HostLevel &F = h.plan.lv[l];
             const int zt = (F.nz + kProZ - 1) / kProZ;
             return F.rb ? tiles3(F.nx / 2, F.ny, zt) : tiles3(F.nx, F.ny, zt);
+        }));
+        // several coarse planes per thread where the coarse level is large, one where
+        // more threads are needed to fill the chip
+        size_t ccells = 0;
+        for (const InstHost &h : e->in)
+            if (l < h.plan.lc && by_cc(h.plan, l)) ccells += h.plan.lv[l + 1].ncell();
+        const int cz = ccells >= kProCZBig ? kProCZ : 1;
+        e->prc_cz.push_back(cz);
+        e->w_prc.push_back(mk([&](const InstHost &h) {
+            if (l >= h.plan.lc || !by_cc(h.plan, l)) return 0;
+            const HostLevel &C = h.plan.lv[l + 1];
+            return tiles3(C.nx, C.ny, (C.nz + cz - 1) / cz);
         }));
     }
     if (bad) return fail(FX_EINVAL, "a launch would exceed 2^30 tiles");
@@ -834,8 +852,12 @@ void enq_vcycle(Engine *e) {
         // red half-sweep: one launch fewer, where launches cost more than the
         // six interpolations per red cell the fused kernel repeats
         const bool pred = e->fuse && l > 0 && e->small[l] && e->ncol[l] == 2 && e->w_sm[l].total > 0;
-        if (pred) launch_prolong_red(I, e->w_sm[l], l, e->scfg[l], e->st);
-        else launch_prolong(I, e->w_pr[l], l, e->st);
+        if (pred) {
+            launch_prolong_red(I, e->w_sm[l], l, e->scfg[l], e->st);
+        } else {
+            launch_prolong_cc(I, e->w_prc[l], l, e->prc_cz[l], e->st);
+            launch_prolong(I, e->w_pr[l], l, e->st);
+        }
         // a light cycle leaves out one sweep: on the finest level one before the
         // last (which folds the update in), elsewhere one after the first (whose red
         // half holds the fused prolongation)
@@ -1387,8 +1409,10 @@ std::vector<std::pair<std::string, TuneEntry>> read_tune_cache(const char *path)
 
 // Prefix table of level l's smoother launches for launch shape c.
 fx_status set_smooth_work(Engine *e, int l, const SmoothCfg &c) {
-    const int n = e->n, tab = 3 + 3 * l;
-    int *hp = e->prefix_host.data() + (size_t)tab * (n + 1);
+    const int n = e->n;
+    // this level's smoother table, wherever build_work placed it
+    const size_t tab = (size_t)(e->w_sm[l].prefix - e->prefix_dev) / (size_t)(n + 1);
+    int *hp = e->prefix_host.data() + tab * (n + 1);
     long long tot = 0;
     hp[0] = 0;
     for (int i = 0; i < n; ++i) {
@@ -1398,7 +1422,7 @@ fx_status set_smooth_work(Engine *e, int l, const SmoothCfg &c) {
         hp[i + 1] = (int)tot;
     }
     HIP_OK(hipStreamSynchronize(e->st));
-    HIP_OK(hipMemcpy(e->prefix_dev + (size_t)tab * (n + 1), hp, (n + 1) * sizeof(int), hipMemcpyHostToDevice));
+    HIP_OK(hipMemcpy(e->prefix_dev + tab * (n + 1), hp, (n + 1) * sizeof(int), hipMemcpyHostToDevice));
     e->w_sm[l].total = (int)tot;
     return FX_OK;
 }

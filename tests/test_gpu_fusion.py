@@ -115,3 +115,35 @@ def test_bottom_size_reaches_the_oracle_root(fx, orc, monkeypatch, cells):
     say(f"  bottom <= {cells} cells: {levels} levels, cycles {info.total_cycles} relP {rp:.2e} relphi {rf:.2e}")
     assert info.steps_done == n and rp <= 1e-10 and rf <= 1e-10
     s.close()
+
+
+@pytest.mark.parametrize("prec", [W.PREC_FP64, W.PREC_MIXED])
+def test_coarse_column_prolongation_is_bitwise(fx, monkeypatch, prec):
+    """The prolongation by coarse columns (a thread per coarse column marching in z, reusing
+    each plane's bilinear values) forms every correction with the operands and order of the
+    per-fine-cell kernel (FERROX_PROLONG_CC=0): same bits, on a stack whose first two levels
+    take it (160 x 160 lateral, level 1 above the fused small-level limit) and in a batch."""
+    spec = W.shrink_lateral(W.mfism_large(prec), 160, 160).copy(tol_rel=1e-12)
+    P0 = W.random_P(spec, 94, amp=0.05)
+    specs = [W.layered(96, 64, 48, [(W.FE, 30, W.EPS_FE, 0.0), (W.DE, 4, W.EPS_SIO2, 0.0)], v_top=0.5,
+                       tol_rel=1e-12, prec=prec),
+             W.layered(48, 32, 47, [(W.FE, 24, W.EPS_FE, 0.0), (W.DE, 4, W.EPS_SIO2, 0.0),
+                                    (W.SC, 11, W.EPS_SI, 1e24)], v_top=-0.8, tol_rel=1e-12, time_order=2, prec=prec)]
+    Ps = [W.random_P(sp, 95 + q, amp=0.05) for q, sp in enumerate(specs)]
+    out = {}
+    for cc in ("1", "0"):
+        monkeypatch.setenv("FERROX_PROLONG_CC", cc)
+        s = fx.Stack(spec, P0)
+        info = s.run_steps(4, W.DT)
+        b = fx.Batch(specs, Ps)
+        bi = b.run(4, W.DT)
+        assert all(i.status == fx.FX_OK for i in bi)
+        out[cc] = (s.get(fx.FIELD_P), s.get(fx.FIELD_PHI), info.total_cycles,
+                   [(b.get(q, fx.FIELD_P), b.get(q, fx.FIELD_PHI)) for q in range(len(specs))])
+        say(f"  prolong by coarse columns {cc}: {info.total_cycles} V-cycles")
+        s.close()
+        b.close()
+    a, c = out["1"], out["0"]
+    assert a[2] == c[2] and np.array_equal(a[0], c[0]) and np.array_equal(a[1], c[1])
+    for q in range(len(specs)):
+        assert np.array_equal(a[3][q][0], c[3][q][0]) and np.array_equal(a[3][q][1], c[3][q][1]), q
