@@ -190,12 +190,17 @@ template <typename T> void launch_flip(const Inst<T> *I, int ninst, hipStream_t 
 template <typename T> void launch_qv(const Inst<T> *I, int ninst, int record, double *out, hipStream_t st);
 template <typename T> void launch_begin(const Inst<T> *I, int ninst, int sel, hipStream_t st);
 template <typename T> void launch_extrap(const Inst<T> *I, const Work &w, hipStream_t st);
+// Work tables of the residual: cell0 -- every instance (mode 0, the current
+// iterate; after a cycle the kernel skips the instances of cell2); cell2 --
+// instances whose update is not folded into the smoother (mode 2: forms
+// phi_in + clip(e) itself, after a cycle).
+struct ResWork {
+    Work cell0, cell2;
+};
 // after_cycle 0: residual at the starting iterate of freshly begun solves;
 // 1: at the output of the cycle just run (forming phi_in + clip(e) first
-// where the update is not folded into the smoother: any_unfolded says
-// whether some instance is of that kind).
-template <typename T> void launch_residual(const Inst<T> *I, const Work &w, int after_cycle, int any_unfolded,
-                                           hipStream_t st);
+// where the update is not folded into the smoother).
+template <typename T> void launch_residual(const Inst<T> *I, const ResWork &w, int after_cycle, hipStream_t st);
 template <typename T> void launch_reduce(const Inst<T> *I, int ninst, int count_cycle, hipStream_t st);
 // Launch shape of one level's smoother: tile of 2^lbx x 2^(8-lbx) threads,
 // zt planes per thread, w8: register budget for 8 waves per SIMD.  Only the

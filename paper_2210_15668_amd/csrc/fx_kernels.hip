@@ -738,6 +738,67 @@ __global__ __launch_bounds__(256) void k_zero_fix(const Inst<T> *I, Work w) {
 }
 
 // ------------------------------------------------------ fine-level residual
+// Per-plane tables of the finest level the residual reads (scaled by h^2/eps0).
+struct ResTab {
+    const double FX_AS(1) *cxy, *czm, *czp, *wl, *wr, *p0e, *n0e;
+};
+template <typename T>
+__device__ __forceinline__ ResTab res_tab(const Inst<T> &a) {
+    return ResTab{asp<1>(a.cxy0), asp<1>(a.czm0), asp<1>(a.czp0), asp<1>(a.wl), asp<1>(a.wr), asp<1>(a.p0e),
+                  asp<1>(a.n0e)};
+}
+
+// One device cell of plane k (eq. (Poisson) with eq. (rho), scaled by h^2/eps0): the
+// right-hand side f (contact terms and the bound charge -(P_f(k+1/2) - P_f(k-1/2))/h),
+// the residual r = f - N(phi) and the Newton sigma = -d rho_c/d phi (semiconductor
+// planes).  v0 is the cell's phi, vx0/vx1 and vy0/vy1 its x+1/x-1 and y+1/y-1
+// neighbours, vzm/vzp its z neighbours (not used on the contact planes), pm/pc/pp P on
+// planes k-1, k, k+1 (read only where a polarised face touches the plane).  Fused
+// multiply-adds are written out, so that every residual kernel rounds alike.
+template <typename T>
+__device__ __forceinline__ void res_cell(const Inst<T> &a, const ResTab &tb, int k, int nzd, int fl, double v_t,
+                                        double v0, double vx0, double vx1, double vy0, double vy1, double vzm,
+                                        double vzp, double pm, double pc, double pp, double &f_o, double &r_o,
+                                        double &sg_o) {
+    const double nb = fmad(-2.0, v0, vx0 + vx1) + fmad(-2.0, v0, vy0 + vy1);
+    const double dn = k > 0 ? vzm : 0.0;
+    const double up = k < nzd - 1 ? vzp : 0.0;
+    const double Lphi = fmad(tb.czp[k], v0 - up, fmad(tb.czm[k], v0 - dn, -tb.cxy[k] * nb));
+    double f = 0.0;
+    if (fl & PF_P) {
+        const double pup = k == nzd - 1 ? pc : fmad(tb.wr[k], pp, tb.wl[k] * pc);
+        const double pdn = k == 0 ? pc : fmad(tb.wr[k - 1], pc, tb.wl[k - 1] * pm);
+        f = -(pup - pdn) * a.p_scale;
+    }
+    if (k == 0) f = fmad(tb.czm[k], a.v_b, f);
+    if (k == nzd - 1) f = fmad(tb.czp[k], v_t, f);
+    double r = f - Lphi, sg = 0.0;
+    if (fl & PF_SC) {
+        const double u = v0 * a.vt_inv;
+        const double p0e = tb.p0e[k], n0e = tb.n0e[k];
+        if (a.fd) {
+            // differences from the neutral state: rho_c(0) = 0 exactly
+            const double FX_AS(1) *ft = asp<1>(a.fdt) + 4 * k;
+            double Fp, dFp, Fn, dFn;
+            fd_half(ft[0] - u, Fp, dFp);
+            fd_half(ft[1] + u, Fn, dFn);
+            r = fmad(fmad(p0e, Fp - ft[2], -(n0e * (Fn - ft[3]))), a.rho_scale, r);
+            sg = fmad(p0e, dFp, n0e * dFn) * a.sig_scale;
+        } else {
+            // e^u - 1 and e^-u - 1 from one expm1: with t = e^|u| - 1 the other
+            // is -t / (1 + t), free of cancellation for either sign of u
+            const double t1 = expm1(fabs(u));
+            const double t2 = -t1 / (1.0 + t1);
+            const double ep = u >= 0.0 ? t1 : t2, em = u >= 0.0 ? t2 : t1;
+            r = fmad(fmad(p0e, em, -(n0e * ep)), a.rho_scale, r);           // + rho_c
+            sg = fmad(p0e, 1.0 + em, n0e * (1.0 + ep)) * a.sig_scale;
+        }
+    }
+    f_o = f;
+    r_o = r;
+    sg_o = sg;
+}
+
 // Each thread owns a column of kResZ planes.  All loads are issued before any
 // arithmetic (clamped indices instead of boundary branches; the column's
 // z-neighbours are loaded once) and all stores follow it, so a wave makes one
@@ -761,9 +822,6 @@ __device__ __forceinline__ void residual_body(const Inst<T> &a, const GState *s,
     const double FX_AS(1) *P = asp<1>(a.P[s->pcur]) + off;
     const Lv<T, 1> L = gview(a.lv[0]);
     const int FX_AS(1) *pflags = asp<1>(a.pflags);
-    const double FX_AS(1) *cxy0 = asp<1>(a.cxy0), *czm0 = asp<1>(a.czm0), *czp0 = asp<1>(a.czp0);
-    const double FX_AS(1) *wl = asp<1>(a.wl), *wr = asp<1>(a.wr);
-    const double FX_AS(1) *p0ev = asp<1>(a.p0e), *n0ev = asp<1>(a.n0e);
     const int col = j * nx + i;
     const int ox0 = wrap_p(i, nx) - i, ox1 = wrap_m(i, nx) - i;
     const int oy0 = (wrap_p(j, ny) - j) * nx, oy1 = (wrap_m(j, ny) - j) * nx;
@@ -813,7 +871,8 @@ __device__ __forceinline__ void residual_body(const Inst<T> &a, const GState *s,
         at(k, oy0, py, &vy0[z]);
         at(k, oy1, py, &vy1[z]);
     }
-    const double v_b = a.v_b, v_t = s->v_top;
+    const double v_t = s->v_top;
+    const ResTab tb = res_tab(a);
     double res[ZT], sg[ZT];
 #pragma unroll
     for (int z = 0; z < ZT; ++z) {
@@ -821,46 +880,12 @@ __device__ __forceinline__ void residual_body(const Inst<T> &a, const GState *s,
         res[z] = 0.0;
         sg[z] = 0.0;
         if (k >= nzd) break;
-        const double v0 = vc[z + 1];
-        const double nb = (vx0[z] + vx1[z] - 2.0 * v0) + (vy0[z] + vy1[z] - 2.0 * v0);
-        const double dn = k > 0 ? vc[z] : 0.0;
-        const double up = k < nzd - 1 ? vc[z + 2] : 0.0;
-        const double Lphi = -cxy0[k] * nb + czm0[k] * (v0 - dn) + czp0[k] * (v0 - up);
-        double f = 0.0;
-        if (fl[z] & PF_P) {
-            const double pc = pz[z + 1];
-            const double pup = k == nzd - 1 ? pc : wl[k] * pc + wr[k] * pz[z + 2];
-            const double pdn = k == 0 ? pc : wl[k - 1] * pz[z] + wr[k - 1] * pc;
-            f = -(pup - pdn) * a.p_scale;
-        }
-        if (k == 0) f += czm0[k] * v_b;
-        if (k == nzd - 1) f += czp0[k] * v_t;
-        double r = f - Lphi;
-        if (fl[z] & PF_SC) {
-            const double u = v0 * a.vt_inv;
-            const double p0e = p0ev[k], n0e = n0ev[k];
-            if (a.fd) {
-                // differences from the neutral state: rho_c(0) = 0 exactly
-                const double FX_AS(1) *ft = asp<1>(a.fdt) + 4 * k;
-                double Fp, dFp, Fn, dFn;
-                fd_half(ft[0] - u, Fp, dFp);
-                fd_half(ft[1] + u, Fn, dFn);
-                r += (p0e * (Fp - ft[2]) - n0e * (Fn - ft[3])) * a.rho_scale;
-                sg[z] = (p0e * dFp + n0e * dFn) * a.sig_scale;
-            } else {
-                // e^u - 1 and e^-u - 1 from one expm1: with t = e^|u| - 1 the other
-                // is -t / (1 + t), free of cancellation for either sign of u
-                const double t1 = expm1(fabs(u));
-                const double t2 = -t1 / (1.0 + t1);
-                const double ep = u >= 0.0 ? t1 : t2, em = u >= 0.0 ? t2 : t1;
-                r += (p0e * em - n0e * ep) * a.rho_scale;                         // + rho_c
-                sg[z] = (p0e * (1.0 + em) + n0e * (1.0 + ep)) * a.sig_scale;
-            }
-        }
-        res[z] = r;
+        double f;
+        res_cell(a, tb, k, nzd, fl[z], v_t, vc[z + 1], vx0[z], vx1[z], vy0[z], vy1[z], vc[z], vc[z + 2], pz[z],
+                 pz[z + 1], pz[z + 2], f, res[z], sg[z]);
         if (live) {
-            rr += r * r;
-            ff += f * f;
+            rr = fmad(res[z], res[z], rr);
+            ff = fmad(f, f, ff);
         }
     }
     if (!live) return;
@@ -1777,11 +1802,11 @@ void launch_extrap(const Inst<T> *I, const Work &w, hipStream_t st) {
 }
 
 template <typename T>
-void launch_residual(const Inst<T> *I, const Work &w, int after_cycle, int any_unfolded, hipStream_t st) {
+void launch_residual(const Inst<T> *I, const ResWork &w, int after_cycle, hipStream_t st) {
     auto *k0 = &k_residual<T, 0>;
     auto *k2 = &k_residual<T, 2>;
-    FX_LAUNCH(k0, w, I, w, after_cycle);
-    if (after_cycle && any_unfolded) FX_LAUNCH(k2, w, I, w, after_cycle);
+    FX_LAUNCH(k0, w.cell0, I, w.cell0, after_cycle);
+    if (after_cycle) FX_LAUNCH(k2, w.cell2, I, w.cell2, after_cycle);
 }
 
 template <typename T>
@@ -1908,7 +1933,7 @@ void launch_fill(double *x, size_t n, double v, hipStream_t st) {
     template void launch_qv<T>(const Inst<T> *, int, int, double *, hipStream_t);                            \
     template void launch_begin<T>(const Inst<T> *, int, int, hipStream_t);                                  \
     template void launch_extrap<T>(const Inst<T> *, const Work &, hipStream_t);                              \
-    template void launch_residual<T>(const Inst<T> *, const Work &, int, int, hipStream_t);                  \
+    template void launch_residual<T>(const Inst<T> *, const ResWork &, int, hipStream_t);                    \
     template void launch_reduce<T>(const Inst<T> *, int, int, hipStream_t);                                  \
     template void launch_smooth<T>(const Inst<T> *, const Work &, int, int, int, int, const SmoothCfg &,     \
                                    double *, hipStream_t, hipEvent_t, hipEvent_t, int);                      \

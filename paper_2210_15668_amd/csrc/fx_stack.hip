@@ -338,14 +338,14 @@ struct Engine {
     int rec = 0;                        // advance slots record Q and V_fe of completed steps
     int graphs_rec = 0;                 // the captured unit graphs include the recording
     std::vector<int> prefix_host;
-    Work w_tdgl{}, w_ext{}, w_res{};
+    Work w_tdgl{}, w_ext{};
+    ResWork w_res{};
     std::vector<Work> w_sm, w_rs, w_pr, w_prc;   // w_pr / w_prc: prolongation by fine or by coarse columns
     std::vector<int> prc_cz;            // coarse planes per thread of w_prc, per level
     std::vector<SmoothCfg> scfg;        // smoother launch shape per level
     std::vector<int> ncol;
     std::vector<char> small;            // per level: few enough cells that launch latency dominates
     int max_lc = 0, lds_max = 0, max_cycles = 1;
-    int any_unfolded = 0;               // some instance forms phi + clip(e) in the residual kernel
     int any_order2 = 0;                 // some instance takes predictor-corrector steps
     int nu1 = 2, nu2 = 2;               // sweeps before / after the coarse correction, finest level
     int nu1c = 2, nu2c = 2;             // the same on every coarser level
@@ -422,6 +422,11 @@ int coarse_layout(const Plan &p, Inst<T> *a) {
     return off;
 }
 
+// The Newton update is folded into the finest level's last black half-sweep (red/black
+// storage and levels of its own above the coarse kernel); else the residual kernel
+// forms it.
+bool fold_of(const Plan &p) { return p.lv[0].rb && p.lc > 0; }
+
 int tiles_smooth(const HostLevel &H, const SmoothCfg &c) { return tiles_cfg(H.rb ? H.nx / 2 : H.nx, H.ny, H.nz, c); }
 
 // Launch shapes that depend on all instances: levels with their own
@@ -429,12 +434,10 @@ int tiles_smooth(const HostLevel &H, const SmoothCfg &c) { return tiles_cfg(H.rb
 void plan_launches(Engine *e) {
     e->max_lc = 0;
     e->max_cycles = 1;
-    e->any_unfolded = 0;
     e->any_order2 = 0;
     for (const InstHost &h : e->in) {
         e->max_lc = std::max(e->max_lc, h.plan.lc);
         e->max_cycles = std::max(e->max_cycles, h.d.max_cycles);
-        if (!(h.plan.lv[0].rb && h.plan.lc > 0)) e->any_unfolded = 1;
         if (h.d.time_order == 2) e->any_order2 = 1;
     }
     e->scfg.assign(e->max_lc, SmoothCfg{6, 1, 0});
@@ -525,7 +528,7 @@ size_t carve(Engine *e, void *ws) {
     const size_t inst_bytes = mixed ? sizeof(Inst<float>) : sizeof(Inst<double>);
     e->inst_dev = cv.take((size_t)e->n * inst_bytes);
     e->st_dev = (InstState *)cv.take((size_t)e->n * sizeof(InstState));
-    const size_t ntab = 3 + 4 * (size_t)e->max_lc;
+    const size_t ntab = 4 + 4 * (size_t)e->max_lc;
     e->prefix_dev = (int *)cv.take(ntab * (e->n + 1) * sizeof(int));
     e->sched_dev = (double *)cv.take((size_t)e->n * kSchedChunk * sizeof(double));
     e->probe_dev = (double *)cv.take(kProbeMax * sizeof(double));
@@ -559,7 +562,10 @@ fx_status build_work(Engine *e) {
         const Plan &p = h.plan;
         return (int)(((size_t)p.nx * p.ny * p.nzd + kExtrapChunk - 1) / kExtrapChunk);
     });
-    e->w_res = mk([](const InstHost &h) { const Plan &p = h.plan; return tiles3(p.nx, p.ny, (p.nzd + kResZ - 1) / kResZ); });
+    // residual: every instance in mode 0; after the cycles of unfolded instances, mode 2
+    auto nzc = [](const Plan &p) { return (p.nzd + kResZ - 1) / kResZ; };
+    e->w_res.cell0 = mk([&](const InstHost &h) { const Plan &p = h.plan; return tiles3(p.nx, p.ny, nzc(p)); });
+    e->w_res.cell2 = mk([&](const InstHost &h) { const Plan &p = h.plan; return fold_of(p) ? 0 : tiles3(p.nx, p.ny, nzc(p)); });
     e->w_sm.clear(); e->w_rs.clear(); e->w_pr.clear(); e->w_prc.clear(); e->prc_cz.clear();
     const int cc_ok = env_int("FERROX_PROLONG_CC", 1) != 0;
     // the coarse-column prolongation: red/black fine level, x and y halved, z paired
@@ -644,7 +650,7 @@ Inst<T> make_inst(const Engine *e, int i) {
     a.f1 = p.f0 >= 0 ? p.f1 : 0;
     a.nlev = (int)p.lv.size();
     a.lc = p.lc;
-    a.fold = p.lv[0].rb && p.lc > 0;
+    a.fold = fold_of(p);
     a.max_cycles = d.max_cycles;
     a.warm = d.warm_start;
     a.order2 = d.time_order == 2;
@@ -875,7 +881,7 @@ void enq_vcycle(Engine *e) {
 template <typename T>
 void enq_cycle(Engine *e) {
     enq_vcycle<T>(e);
-    launch_residual(idev<T>(e), e->w_res, 1, e->any_unfolded, e->st);
+    launch_residual(idev<T>(e), e->w_res, 1, e->st);
     launch_reduce(idev<T>(e), e->n, 1, e->st);
 }
 
@@ -890,7 +896,7 @@ void enq_advance(Engine *e) {
     if (e->any_order2) launch_tdgl_corr(I, e->w_tdgl, e->st);
     launch_begin(I, e->n, 1, e->st);
     launch_extrap(I, e->w_ext, e->st);
-    launch_residual(I, e->w_res, 0, 0, e->st);
+    launch_residual(I, e->w_res, 0, e->st);
     launch_reduce(I, e->n, 0, e->st);
 }
 
@@ -957,7 +963,7 @@ template <typename T>
 fx_status solve_plain_t(Engine *e) {
     const Inst<T> *I = idev<T>(e);
     launch_begin(I, e->n, 0, e->st);
-    launch_residual(I, e->w_res, 0, 0, e->st);
+    launch_residual(I, e->w_res, 0, e->st);
     launch_reduce(I, e->n, 0, e->st);
     int enq = 0;
     int batch = e->trace ? 0 : std::max(1, e->k_pred);
