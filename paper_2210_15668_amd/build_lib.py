@@ -8,7 +8,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libferrox.so")
-SOURCES = ["fx_kernels.hip", "fx_stack.hip", "fx_unet.hip"]
+SOURCES = ["fx_kernels.hip", "fx_stack.hip", "fx_unet.hip", "fx_unet_conv.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",

@@ -42,7 +42,8 @@ constexpr float kPScale = 0.2f;          // C/m^2
 constexpr double kDopingScale = 1e24;    // m^-3
 constexpr double kVScale = 2.0;          // V
 constexpr double kPhiScale = 1.0;        // V
-constexpr int kInC = 16;
+constexpr int kInC = 4;                  // device input channels: P, doping, V and a zero
+constexpr int kInCApi = 16;              // input channels of the parameter layout and the host API
 
 __device__ __forceinline__ float bf2f(bf16_t h) { return __uint_as_float((unsigned)h << 16); }
 
@@ -377,7 +378,7 @@ __global__ __launch_bounds__(256) void k_conv3s(const bf16_t *__restrict__ X, in
 // 128 voxels of both operands in LDS, transposed ([channel][voxel]) so that every
 // matrix-core fragment is one 8-byte read; staging moves 8 channels (16 bytes) of one
 // voxel per load, its neighbour index worked out once per such piece.
-template <int CIN, int COUT>
+template <int CIN, int COUT, int XL = CIN>
 __global__ __launch_bounds__(256) void k_wgrad(const bf16_t *__restrict__ X, int ldx, const bf16_t *__restrict__ G,
                                                int nx, int ny, int nz, float *__restrict__ part) {
     constexpr int VB = 128;
@@ -422,7 +423,14 @@ __global__ __launch_bounds__(256) void k_wgrad(const bf16_t *__restrict__ X, int
                     int y2 = y + dy, x2 = x + dx;
                     y2 = y2 < 0 ? y2 + ny : (y2 >= ny ? y2 - ny : y2);
                     x2 = x2 < 0 ? x2 + nx : (x2 >= nx ? x2 - nx : x2);
-                    val.w = *(const i4 *)(X + (size_t)((z2 * ny + y2) * nx + x2) * ldx + c8);
+                    if constexpr (XL >= 8) {
+                        val.w = *(const i4 *)(X + (size_t)((z2 * ny + y2) * nx + x2) * ldx + c8);
+                    } else if (c8 == 0) {   // XL = 4 channels present, the rest zero
+                        typedef int i2 __attribute__((ext_vector_type(2)));
+                        const i2 h = *(const i2 *)(X + (size_t)((z2 * ny + y2) * nx + x2) * ldx);
+                        val.w[0] = h[0];
+                        val.w[1] = h[1];
+                    }
                 }
             }
 #pragma unroll
@@ -672,16 +680,12 @@ template <typename T>
 __global__ void k_pack(const T *__restrict__ P, const float *__restrict__ dop, float vs, bf16_t *__restrict__ in,
                        int nxy, size_t n) {
     for (size_t v = blockIdx.x * (size_t)blockDim.x + threadIdx.x; v < n; v += (size_t)gridDim.x * blockDim.x) {
-        s4 q0, q1 = {0, 0, 0, 0};
+        s4 q0;
         q0[0] = (short)f2bf((float)P[v] / kPScale);
         q0[1] = (short)f2bf(dop[v / nxy]);
         q0[2] = (short)f2bf(vs);
         q0[3] = 0;
-        s4 *dst = (s4 *)(in + v * kInC);
-        dst[0] = q0;
-        dst[1] = q1;
-        dst[2] = q1;
-        dst[3] = q1;
+        *(s4 *)(in + v * kInC) = q0;
     }
 }
 
@@ -739,20 +743,20 @@ void conv_launch(const bf16_t *X, int ldx, const bf16_t *W, const float *b, void
                        0, st, X, ldx, W, b, Y, ldy, nx, ny, nz);
 }
 
-// (cin, cout) pairs of the forward layers and of their input gradients
-#define FX_CONV_PAIRS(F) \
-    F(16, 16) F(16, 32) F(32, 32) F(32, 64) F(64, 64) F(96, 32) F(48, 16) F(32, 16) F(64, 32) F(32, 96) F(16, 48)
+// (cin, cout) of the forward layers (weight gradients) and of the convolutions
+// that carry the gradient back through them (input gradients)
+#define FX_WG_PAIRS(F) F(16, 16) F(16, 32) F(32, 32) F(32, 64) F(64, 64) F(96, 32) F(48, 16)
+#define FX_IG_PAIRS(F) F(16, 16) F(16, 48) F(32, 32) F(32, 96) F(64, 64) F(64, 32) F(32, 16)
 
-// Convolution dispatch: NTW = 4 on large grids, 1 on small ones (more blocks).
+// Input-gradient convolutions (out 1: Y = conv, out 2: Y += conv, FP32): NTW = 4 on
+// large grids, 1 on small ones (more blocks).  The forward pass runs on the
+// z-marching kernel (fx_unet_conv.hip).
 bool conv_any(int cin, int cout, int out, const bf16_t *X, int ldx, const bf16_t *W, const float *b, void *Y, int ldy,
               int nx, int ny, int nz, bool staged, hipStream_t st) {
     const bool big = (size_t)nx * ny * nz >= (size_t)256 * 64 * 4;
 #define FX_CONV_CASE(ci, co)                                                                               \
     if (cin == ci && cout == co) {                                                                         \
-        if (out == 0) {                                                                                    \
-            if (big) conv_launch<ci, co, 4, 0>(X, ldx, W, b, Y, ldy, nx, ny, nz, staged, st);                       \
-            else conv_launch<ci, co, 1, 0>(X, ldx, W, b, Y, ldy, nx, ny, nz, staged, st);                           \
-        } else if (out == 1) {                                                                             \
+        if (out == 1) {                                                                                    \
             if (big) conv_launch<ci, co, 4, 1>(X, ldx, W, b, Y, ldy, nx, ny, nz, staged, st);                       \
             else conv_launch<ci, co, 1, 1>(X, ldx, W, b, Y, ldy, nx, ny, nz, staged, st);                           \
         } else {                                                                                           \
@@ -761,19 +765,25 @@ bool conv_any(int cin, int cout, int out, const bf16_t *X, int ldx, const bf16_t
         }                                                                                                  \
         return true;                                                                                       \
     }
-    FX_CONV_PAIRS(FX_CONV_CASE)
+    if (out == 1 || out == 2) {
+        FX_IG_PAIRS(FX_CONV_CASE)
+    }
 #undef FX_CONV_CASE
     return false;
 }
 
 bool wgrad_any(int cin, int cout, const bf16_t *X, int ldx, const bf16_t *G, int nx, int ny, int nz, float *part,
                int nparts, hipStream_t st) {
+    if (cin == 16 && cout == 16 && ldx == kInC) {       // the first layer on the 4-channel input
+        hipLaunchKernelGGL((k_wgrad<16, 16, kInC>), dim3(nparts, 27), dim3(256), 0, st, X, ldx, G, nx, ny, nz, part);
+        return true;
+    }
 #define FX_WG_CASE(ci, co)                                                                                        \
     if (cin == ci && cout == co) {                                                                                \
         hipLaunchKernelGGL((k_wgrad<ci, co>), dim3(nparts, 27), dim3(256), 0, st, X, ldx, G, nx, ny, nz, part);  \
         return true;                                                                                              \
     }
-    FX_CONV_PAIRS(FX_WG_CASE)
+    FX_WG_PAIRS(FX_WG_CASE)
 #undef FX_WG_CASE
     return false;
 }
@@ -794,9 +804,27 @@ static const Layer kLayerTemplate[10] = {
     {"d0a", 48, 16, 0, 0, 0, 0}, {"d0b", 16, 16, 0, 0, 0, 0}};
 enum { E0A, E0B, E1A, E1B, B2A, B2B, D1A, D1B, D0A, D0B, NLAYER };
 
+// Launches of the forward pass on the z-marching kernel: input channels from
+// tensor A (ca, upsampled when upa) and B (cb), output mode, first input channel
+// of the layer's weights, offset of the fragment-ordered weights.
+struct ZLaunch {
+    int layer, ca, upa, cb, out, ci_off;
+    size_t wz_off;
+};
+static const ZLaunch kZTemplate[] = {
+    {E0A, 4, 0, 0, 0, 0, 0},  {E0B, 16, 0, 0, 0, 0, 0}, {E1A, 16, 0, 0, 0, 0, 0}, {E1B, 32, 0, 0, 0, 0, 0},
+    {B2A, 32, 0, 0, 0, 0, 0},
+    {B2B, 32, 0, 0, 1, 0, 0},  // input channels 0..31 into an FP32 partial sum,
+    {B2B, 32, 0, 0, 2, 32, 0}, // then 32..63, the partial sum, bias and ReLU
+    {D1A, 64, 1, 0, 1, 0, 0},  // upsampled 64 channels into an FP32 partial sum,
+    {D1A, 32, 0, 0, 2, 64, 0}, // then the 32 skip channels, the partial sum, bias and ReLU
+    {D1B, 32, 0, 0, 0, 0, 0}, {D0A, 32, 1, 16, 0, 0, 0}, {D0B, 16, 0, 0, 0, 0, 0}};
+enum { ZE0A, ZE0B, ZE1A, ZE1B, ZB2A, ZB2B_LO, ZB2B_HI, ZD1A_UP, ZD1A_SKIP, ZD1B, ZD0A, ZD0B, NZ };
+
 struct UnetLayout {
     Layer L[NLAYER];
-    size_t nparams = 0, head_off = 0, nbf = 0;
+    ZLaunch Z[NZ];
+    size_t nparams = 0, head_off = 0, nbf = 0, nwz = 0;
     UnetLayout() {
         size_t o = 0, bo = 0;
         for (int i = 0; i < NLAYER; ++i) {
@@ -811,6 +839,13 @@ struct UnetLayout {
         head_off = o;
         nparams = o + 17;
         nbf = bo;
+        size_t zo = 0;
+        for (int i = 0; i < NZ; ++i) {
+            Z[i] = kZTemplate[i];
+            Z[i].wz_off = zo;
+            zo += (size_t)convz_nfrags(Z[i].ca, Z[i].cb) * (L[Z[i].layer].cout / 16) * 512;
+        }
+        nwz = zo;
     }
 };
 
@@ -831,10 +866,12 @@ struct fx_unet {
     // parameters and optimiser
     float *theta, *grad, *m, *v;
     bf16_t *wt, *wf;
+    bf16_t *wz;                         // fragment-ordered weights of the forward launches
     int adam_t;
     // activations (BF16)
     bf16_t *in, *a_e0a, *cat0, *p0, *a_e1a, *cat1, *p1, *a_b2a, *a_b2b, *a_d1a, *a_d1b, *a_d0a, *a_d0b;
     float *out;
+    float *zpart;                       // FP32 partial sums of b2b (level 2, 64 channels) and d1a (level 1, 32)
     // gradients (training)
     float *dout, *g0_16, *g0_48, *g1_32a, *g1_32b, *g1_96, *g1_16, *g2_64a, *g2_64b, *g2_32;
     bf16_t *z0, *z1, *z2;
@@ -898,6 +935,7 @@ size_t carve_unet(fx_unet *u, void *ws) {
     u->theta = cv.take<float>(lay.nparams);
     u->wt = cv.take<bf16_t>(lay.nbf);
     u->wf = cv.take<bf16_t>(lay.nbf);
+    u->wz = cv.take<bf16_t>(lay.nwz);
     u->in = cv.take<bf16_t>(n0 * kInC);
     u->a_e0a = cv.take<bf16_t>(n0 * 16);
     u->cat0 = cv.take<bf16_t>(n0 * 48);
@@ -912,6 +950,7 @@ size_t carve_unet(fx_unet *u, void *ws) {
     u->a_d0a = cv.take<bf16_t>(n0 * 16);
     u->a_d0b = cv.take<bf16_t>(n0 * 16);
     u->out = cv.take<float>(n0);
+    u->zpart = cv.take<float>(std::max(n1 * 32, n2 * 64));
     u->dop = cv.take<float>(u->nz);
     u->lin = cv.take<double>(u->nz);
     u->dpart = cv.take<double>(8192);
@@ -960,14 +999,17 @@ Dims dims_of(const fx_unet *u, int level) {
     return Dims{u->nx >> level, u->ny >> level, u->nz >> level};
 }
 
-const bf16_t *wt_of(const fx_unet *u, int l) { return u->wt + layout().L[l].bf_off; }
 const bf16_t *wf_of(const fx_unet *u, int l) { return u->wf + layout().L[l].bf_off; }
 const float *bias_of(const fx_unet *u, int l) { return u->theta + layout().L[l].boff; }
 
-void conv_fwd(fx_unet *u, int l, const bf16_t *X, int ldx, bf16_t *Y, int ldy) {
-    const Layer &L = layout().L[l];
+// Forward launch zi of the z-marching convolution on the level of its layer.
+void zconv(fx_unet *u, int zi, const bf16_t *XA, int lda, const bf16_t *XB, int ldb, bf16_t *Y, int ldy) {
+    const UnetLayout &lay = layout();
+    const ZLaunch &Z = lay.Z[zi];
+    const Layer &L = lay.L[Z.layer];
     const Dims d = dims_of(u, L.level);
-    conv_any(L.cin, L.cout, 0, X, ldx, wt_of(u, l), bias_of(u, l), Y, ldy, d.nx, d.ny, d.nz, u->staged, u->st);
+    convz_forward(Z.ca, Z.upa != 0, Z.cb, L.cout, Z.out, XA, lda, XB, ldb, u->wz + Z.wz_off, bias_of(u, Z.layer), Y,
+                  ldy, u->zpart, d.nx, d.ny, d.nz, u->st);
 }
 
 void prep_weights(fx_unet *u) {
@@ -977,25 +1019,39 @@ void prep_weights(fx_unet *u) {
         hipLaunchKernelGGL(k_prep, grid_for((size_t)27 * L.cin * L.cout), dim3(256), 0, u->st, u->theta + L.woff, L.cin,
                            L.cout, u->wt + L.bf_off, u->wf + L.bf_off);
     }
+    for (int i = 0; i < NZ; ++i) {
+        const ZLaunch &Z = lay.Z[i];
+        const Layer &L = lay.L[Z.layer];
+        convz_prep(u->theta + L.woff, L.cin, L.cout, Z.ca, Z.cb, Z.ci_off, u->wz + Z.wz_off, u->st);
+    }
 }
 
 void enqueue_forward(fx_unet *u) {
     const Dims d1 = dims_of(u, 1), d2 = dims_of(u, 2);
     hipStream_t st = u->st;
-    conv_fwd(u, E0A, u->in, kInC, u->a_e0a, 16);
-    conv_fwd(u, E0B, u->a_e0a, 16, u->cat0 + 32, 48);
-    hipLaunchKernelGGL(k_pool, grid_for(u->n1 * 4), dim3(256), 0, st, u->cat0 + 32, 48, u->p0, 16, d1.nx, d1.ny, d1.nz);
-    conv_fwd(u, E1A, u->p0, 16, u->a_e1a, 32);
-    conv_fwd(u, E1B, u->a_e1a, 32, u->cat1 + 64, 96);
-    hipLaunchKernelGGL(k_pool, grid_for(u->n2 * 8), dim3(256), 0, st, u->cat1 + 64, 96, u->p1, 32, d2.nx, d2.ny, d2.nz);
-    conv_fwd(u, B2A, u->p1, 32, u->a_b2a, 64);
-    conv_fwd(u, B2B, u->a_b2a, 64, u->a_b2b, 64);
-    hipLaunchKernelGGL(k_up, grid_for(u->n2 * 16), dim3(256), 0, st, u->a_b2b, u->cat1, 96, 64, d2.nx, d2.ny, d2.nz);
-    conv_fwd(u, D1A, u->cat1, 96, u->a_d1a, 32);
-    conv_fwd(u, D1B, u->a_d1a, 32, u->a_d1b, 32);
-    hipLaunchKernelGGL(k_up, grid_for(u->n1 * 8), dim3(256), 0, st, u->a_d1b, u->cat0, 48, 32, d1.nx, d1.ny, d1.nz);
-    conv_fwd(u, D0A, u->cat0, 48, u->a_d0a, 16);
-    conv_fwd(u, D0B, u->a_d0a, 16, u->a_d0b, 16);
+    // skip connections: inside the concatenated tensors when training (their weight
+    // gradients read [upsampled | skip]); compact in the same buffers otherwise (the
+    // decoders read the upsampled channels straight from the coarser level)
+    bf16_t *s0 = u->train ? u->cat0 + 32 : u->cat0, *s1 = u->train ? u->cat1 + 64 : u->cat1;
+    const int l0 = u->train ? 48 : 16, l1 = u->train ? 96 : 32;
+    zconv(u, ZE0A, u->in, kInC, nullptr, 0, u->a_e0a, 16);
+    zconv(u, ZE0B, u->a_e0a, 16, nullptr, 0, s0, l0);
+    hipLaunchKernelGGL(k_pool, grid_for(u->n1 * 4), dim3(256), 0, st, s0, l0, u->p0, 16, d1.nx, d1.ny, d1.nz);
+    zconv(u, ZE1A, u->p0, 16, nullptr, 0, u->a_e1a, 32);
+    zconv(u, ZE1B, u->a_e1a, 32, nullptr, 0, s1, l1);
+    hipLaunchKernelGGL(k_pool, grid_for(u->n2 * 8), dim3(256), 0, st, s1, l1, u->p1, 32, d2.nx, d2.ny, d2.nz);
+    zconv(u, ZB2A, u->p1, 32, nullptr, 0, u->a_b2a, 64);
+    zconv(u, ZB2B_LO, u->a_b2a, 64, nullptr, 0, nullptr, 0);
+    zconv(u, ZB2B_HI, u->a_b2a + 32, 64, nullptr, 0, u->a_b2b, 64);
+    if (u->train)
+        hipLaunchKernelGGL(k_up, grid_for(u->n2 * 16), dim3(256), 0, st, u->a_b2b, u->cat1, 96, 64, d2.nx, d2.ny, d2.nz);
+    zconv(u, ZD1A_UP, u->a_b2b, 64, nullptr, 0, nullptr, 0);
+    zconv(u, ZD1A_SKIP, s1, l1, nullptr, 0, u->a_d1a, 32);
+    zconv(u, ZD1B, u->a_d1a, 32, nullptr, 0, u->a_d1b, 32);
+    if (u->train)
+        hipLaunchKernelGGL(k_up, grid_for(u->n1 * 8), dim3(256), 0, st, u->a_d1b, u->cat0, 48, 32, d1.nx, d1.ny, d1.nz);
+    zconv(u, ZD0A, u->a_d1b, 32, s0, l0, u->a_d0a, 16);
+    zconv(u, ZD0B, u->a_d0a, 16, nullptr, 0, u->a_d0b, 16);
     hipLaunchKernelGGL(k_head, grid_for(u->n0), dim3(256), 0, st, u->a_d0b, u->theta + layout().head_off, u->out, u->n0);
 }
 
@@ -1218,10 +1274,17 @@ fx_status unet_pack_input(fx_unet *u, const float *d_P, const double *h_doping, 
 fx_status unet_set_input(fx_unet *u, const float *h_in) {
     fx::set_error("");
     if (!u || !h_in) return ufail(FX_EINVAL, "NULL argument");
-    // stage through the output-gradient buffer or the activations: a float copy of n0*16 values
+    // channels 3..15 of the API layout are zero; the device keeps 4 per voxel
+    std::vector<float> c(u->n0 * kInC);
+    for (size_t v = 0; v < u->n0; ++v) {
+        const float *x = h_in + v * kInCApi;
+        for (int k = 3; k < kInCApi; ++k)
+            if (x[k] != 0.f) return ufail(FX_EINVAL, "input channel %d of voxel %zu is %g: channels 3..15 must be zero", k, v, (double)x[k]);
+        for (int k = 0; k < kInC; ++k) c[v * kInC + k] = x[k];
+    }
     const size_t n = u->n0 * kInC;
-    float *tmp = (float *)u->cat0;      // n0*48 BF16 = n0*24 floats >= n0*16
-    UHIP(hipMemcpyAsync(tmp, h_in, n * sizeof(float), hipMemcpyHostToDevice, u->st));
+    float *tmp = (float *)u->cat0;      // n0*48 BF16 = n0*24 floats >= n0*4
+    UHIP(hipMemcpyAsync(tmp, c.data(), n * sizeof(float), hipMemcpyHostToDevice, u->st));
     hipLaunchKernelGGL(k_f_to_bf, grid_for(n), dim3(256), 0, u->st, tmp, u->in, n);
     UHIP(hipStreamSynchronize(u->st));
     return FX_OK;
@@ -1231,10 +1294,13 @@ fx_status unet_get_input(fx_unet *u, float *h_in) {
     fx::set_error("");
     if (!u || !h_in) return ufail(FX_EINVAL, "NULL argument");
     const size_t n = u->n0 * kInC;
+    std::vector<float> c(n);
     float *tmp = (float *)u->cat0;
     hipLaunchKernelGGL(k_bf_to_f, grid_for(n), dim3(256), 0, u->st, u->in, tmp, n);
-    UHIP(hipMemcpyAsync(h_in, tmp, n * sizeof(float), hipMemcpyDeviceToHost, u->st));
+    UHIP(hipMemcpyAsync(c.data(), tmp, n * sizeof(float), hipMemcpyDeviceToHost, u->st));
     UHIP(hipStreamSynchronize(u->st));
+    for (size_t v = 0; v < u->n0; ++v)
+        for (int k = 0; k < kInCApi; ++k) h_in[v * kInCApi + k] = k < kInC ? c[v * kInC + k] : 0.f;
     return FX_OK;
 }
 

@@ -25,4 +25,28 @@ void unet_forward_enqueue(fx_unet *u);
 void unet_apply(fx_unet *u, double *phi_slab);
 void unet_make_target(fx_unet *u, const double *phi_slab, float *target);
 
+// Forward convolutions on the z-marching kernel (fx_unet_conv.hip).  A launch
+// reads CA channels from tensor A (upsampled from the next coarser level when
+// upa) and CB channels from tensor B (the skip connection), in that channel
+// order; CA = 4 is the packed first layer (3 input channels and a zero).
+// out 0: Y = relu(conv + bias) (BF16); out 1: Pf = conv (FP32, ld cout);
+// out 2: Y = relu(conv + Pf + bias).  (ca, upa, cb, cout, out) of the network's
+// launches (d1a in two: the upsampled 64 channels, then the 32 skip channels; b2b in
+// two: input channels 0..31, then 32..63):
+#define FX_Z_CONFIGS(F)                                                                               \
+    F(4, false, 0, 16, 0) F(16, false, 0, 16, 0) F(32, true, 16, 16, 0) F(16, false, 0, 32, 0)           \
+    F(32, false, 0, 32, 0) F(64, true, 0, 32, 1) F(32, false, 0, 32, 2) F(32, false, 0, 64, 0)           \
+    F(32, false, 0, 64, 1) F(32, false, 0, 64, 2)
+// weight fragments per 16 output channels
+int convz_nfrags(int ca, int cb);
+bool convz_supported(int ca, bool upa, int cb, int cout, int out);
+// fragment-ordered BF16 weights wz ((cout/16) * nfrags * 512 values) from the
+// layer's FP32 W[27][cout][cin] (cin as in the parameter vector; the launch's
+// channels start at ci_off)
+void convz_prep(const float *theta_w, int cin, int cout, int ca, int cb, int ci_off, bf16_t *wz, hipStream_t st);
+// false for an unsupported launch
+bool convz_forward(int ca, bool upa, int cb, int cout, int out, const bf16_t *XA, int lda, const bf16_t *XB, int ldb,
+                   const bf16_t *wz, const float *bias, bf16_t *Y, int ldy, float *Pf, int nx, int ny, int nz,
+                   hipStream_t st);
+
 }  // namespace fx

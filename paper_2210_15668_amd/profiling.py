@@ -16,6 +16,12 @@ runs use the same shapes without the tuner's own timing launches:
 `copy` runs one plain device-to-device copy of 1 GiB (larger than the 256 MB
 last-level cache, so every byte crosses HBM): FETCH_SIZE and WRITE_SIZE of that
 dispatch, divided by 1 GiB, are the factors that turn the counters into bytes.
+
+The learned start's network, per layer (forward passes of the committed weights on a
+held-out state of the 128x128x64 MFISM stack):
+
+  rocprofv3 --kernel-trace --stats -d OUT/unet -o run -- python3 -m paper_2210_15668_amd.profiling unet 20
+  python3 -m paper_2210_15668_amd.profiling unet_layers OUT/unet
 """
 from __future__ import annotations
 
@@ -145,6 +151,74 @@ def traffic(base):
     print(json.dumps(out, indent=1))
 
 
+# Launches of one forward pass in order: (name, input channels of real work, output
+# channels, level); None for the elementwise kernels (pooling, head).
+UNET_LAUNCHES = [("e0a 3->16", 3, 16, 0), ("e0b 16->16", 16, 16, 0), ("pool 0", None, 16, 1),
+                 ("e1a 16->32", 16, 32, 1), ("e1b 32->32", 32, 32, 1), ("pool 1", None, 32, 2),
+                 ("b2a 32->64", 32, 64, 2), ("b2b 64->64, in 0..31", 32, 64, 2),
+                 ("b2b 64->64, in 32..63", 32, 64, 2), ("d1a 96->32, upsampled 64", 64, 32, 1),
+                 ("d1a 96->32, skip 32", 32, 32, 1), ("d1b 32->32", 32, 32, 1), ("d0a 48->16", 48, 16, 0),
+                 ("d0b 16->16", 16, 16, 0), ("head", None, 1, 0)]
+
+
+def unet(reps):
+    """reps forward passes (after three untimed ones) of the trained network."""
+    import numpy as np
+    import torch
+    from paper_2210_15668_amd import ferrox, learn
+    from paper_2210_15668_amd import workloads as W
+    spec = learn.spec_c4()
+    kb, kt = spec.device_range()
+    net = ferrox.UNet(spec.nx, spec.ny, kt - kb)
+    net.set_params(np.load(learn.WEIGHTS))
+    st = ferrox.Stack(spec, W.random_P(spec, learn.TEST_SEED0 + 1))
+    net.input_from_stack(st, 1.0)
+    for _ in range(3):
+        net.forward()
+    torch.cuda.synchronize()
+    for _ in range(reps):
+        net.forward()
+    torch.cuda.synchronize()
+    st.close()
+    net.close()
+    print(f"{reps} forward passes of {spec.nx}x{spec.ny}x{kt - kb}", flush=True)
+
+
+def unet_layers(trace_dir):
+    """Median duration of each launch of a forward pass, with its real FLOP (multiply-adds
+    counted as 2) and matrix-core rate."""
+    from paper_2210_15668_amd import learn
+    spec = learn.spec_c4()
+    kb, kt = spec.device_range()
+    n0 = spec.nx * spec.ny * (kt - kb)
+    db = _db(trace_dir)
+    rows = db.execute("select name, start, end from kernels order by start").fetchall()
+    passes, cur = [], []
+    for name, a, b in rows:
+        k = _short(name)
+        if not (k.startswith("k_convz") or k.startswith("k_pool") or k.startswith("k_head")):
+            continue
+        cur.append((k, (b - a) / 1e3))
+        if k.startswith("k_head"):
+            if len(cur) == len(UNET_LAUNCHES):
+                passes.append(cur)
+            cur = []
+    passes = passes[3:]                        # the untimed passes first
+    print(f"{len(passes)} forward passes of {spec.nx}x{spec.ny}x{kt - kb}; median per launch\n")
+    print("| launch | kernel | us | GFLOP | TFLOP/s |")
+    print("|---|---|---|---|---|")
+    tot_us = tot_fl = 0.0
+    for i, (lname, ci, co, lev) in enumerate(UNET_LAUNCHES):
+        d = sorted(p[i][1] for p in passes)[len(passes) // 2]
+        fl = 2.0 * 27 * ci * co * n0 / 8 ** lev if ci else 0.0
+        tot_us += d
+        tot_fl += fl
+        rate = f"{fl / d / 1e6:.0f}" if ci else "-"
+        print(f"| {lname} | `{passes[0][i][0]}` | {d:.2f} | {fl / 1e9:.2f} | {rate} |")
+    print(f"| forward pass | (sum of medians) | {tot_us:.1f} | {tot_fl / 1e9:.1f} | {tot_fl / tot_us / 1e6:.0f} "
+          f"({tot_fl / tot_us / 1e6 / 2500:.3f} of 2.5 PFLOP/s) |")
+
+
 if __name__ == "__main__":
     cmd = sys.argv[1] if len(sys.argv) > 1 else ""
     if cmd == "copy":
@@ -153,6 +227,10 @@ if __name__ == "__main__":
         stats(sys.argv[2])
     elif cmd == "traffic":
         traffic(sys.argv[2])
+    elif cmd == "unet":
+        unet(int(sys.argv[2]) if len(sys.argv) > 2 else 20)
+    elif cmd == "unet_layers":
+        unet_layers(sys.argv[2])
     else:
         print(__doc__)
         sys.exit(1)

@@ -67,3 +67,25 @@ def test_trained_network_saves_cycles_on_held_out_cold_starts(fx):
     assert diff <= 1e-8 and diff_u <= 1e-8           # the same root, judged by multigrid
     assert learned.mean() <= plain.mean() - 2.0
     assert learned.mean() < untrained.mean() - 2.0
+
+
+def test_learned_start_at_gate_jumps_saves_wall_time(fx):
+    """End to end under a stepped gate (jumps of 1 to 2 V every 10 steps, held-out P^0): the
+    solves at the jumps take less wall time started from the network's prediction than
+    started from phi^n, and so does the whole run; both reach the same trajectory
+    (multigrid to 1e-10 judges)."""
+    from paper_2210_15668_amd import learn
+    spec = learn.spec_c4()
+    kb, kt = spec.device_range()
+    net = fx.UNet(spec.nx, spec.ny, kt - kb)
+    net.set_params(np.load(learn.WEIGHTS))
+    r = learn.evaluate_gate_steps(net, spec)
+    net.close()
+    for k in ("restart", "learned"):
+        say(f"  {k}: {r[k]['cycles']} V-cycles ({r[k]['jump_cycles']} at {r[k]['jumps']} jumps), "
+            f"{r[k]['ms']:.2f} ms ({r[k]['jump_ms']:.2f} ms at the jumps)")
+    say(f"  rel phi learned vs restart {r['rel_l2_phi_learned_vs_restart']:.1e}")
+    assert r["learned"]["jump_cycles"] < r["restart"]["jump_cycles"]
+    assert r["learned"]["jump_ms"] < r["restart"]["jump_ms"]
+    assert r["learned"]["ms"] < r["restart"]["ms"]
+    assert r["rel_l2_phi_learned_vs_restart"] <= 1e-7

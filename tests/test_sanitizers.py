@@ -92,7 +92,7 @@ def test_planner_under_asan_and_ubsan(tmp_path):
     if not os.path.exists(HIPCC):
         pytest.skip("no hipcc")
     objs = []
-    for src in ("fx_stack.hip", "fx_kernels.hip", "fx_unet.hip"):
+    for src in ("fx_stack.hip", "fx_kernels.hip", "fx_unet.hip", "fx_unet_conv.hip"):
         o = str(tmp_path / src.replace(".hip", ".o"))
         # the device code is built as usual; the sanitizers instrument the host code alone
         run([HIPCC, "--offload-arch=gfx950", "-O1", "-g", "-std=c++17", "-fPIC", "-fno-omit-frame-pointer",
