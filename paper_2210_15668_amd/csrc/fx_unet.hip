@@ -678,7 +678,7 @@ __global__ void k_prep(const float *__restrict__ th, int cin, int cout, bf16_t *
 // Network input from P over the device planes (z-major), doping per plane and V.
 template <typename T>
 __global__ void k_pack(const T *__restrict__ P, const float *__restrict__ dop, float vs, bf16_t *__restrict__ in,
-                       int nxy, size_t n) {
+                       bf16_t *__restrict__ in_xp, int nx, int nxy, size_t n) {
     for (size_t v = blockIdx.x * (size_t)blockDim.x + threadIdx.x; v < n; v += (size_t)gridDim.x * blockDim.x) {
         s4 q0;
         q0[0] = (short)f2bf((float)P[v] / kPScale);
@@ -686,6 +686,25 @@ __global__ void k_pack(const T *__restrict__ P, const float *__restrict__ dop, f
         q0[2] = (short)f2bf(vs);
         q0[3] = 0;
         *(s4 *)(in + v * kInC) = q0;
+        // the x-padded copy: x + 1 in rows of nx + 2; the row ends also land in the
+        // wrapped voxels at 0 and nx + 1
+        const int x = (int)(v % nx), r = (int)(v / nx);
+        bf16_t *row = in_xp + (size_t)r * (nx + 2) * kInC;
+        *(s4 *)(row + (x + 1) * kInC) = q0;
+        if (x == 0) *(s4 *)(row + (nx + 1) * kInC) = q0;
+        if (x == nx - 1) *(s4 *)(row) = q0;
+    }
+}
+
+// The x-padded copy of the input (after the input was set directly).
+__global__ void k_pad_x(const bf16_t *__restrict__ in, bf16_t *__restrict__ in_xp, int nx, size_t n) {
+    for (size_t v = blockIdx.x * (size_t)blockDim.x + threadIdx.x; v < n; v += (size_t)gridDim.x * blockDim.x) {
+        const s4 q = *(const s4 *)(in + v * kInC);
+        const int x = (int)(v % nx), r = (int)(v / nx);
+        bf16_t *row = in_xp + (size_t)r * (nx + 2) * kInC;
+        *(s4 *)(row + (x + 1) * kInC) = q;
+        if (x == 0) *(s4 *)(row + (nx + 1) * kInC) = q;
+        if (x == nx - 1) *(s4 *)(row) = q;
     }
 }
 
@@ -870,6 +889,7 @@ struct fx_unet {
     int adam_t;
     // activations (BF16)
     bf16_t *in, *a_e0a, *cat0, *p0, *a_e1a, *cat1, *p1, *a_b2a, *a_b2b, *a_d1a, *a_d1b, *a_d0a, *a_d0b;
+    bf16_t *in_xp;                      // the input with one wrapped voxel at each x-end (rows of nx + 2)
     float *out;
     float *zpart;                       // FP32 partial sums of b2b (level 2, 64 channels) and d1a (level 1, 32)
     // gradients (training)
@@ -937,6 +957,7 @@ size_t carve_unet(fx_unet *u, void *ws) {
     u->wf = cv.take<bf16_t>(lay.nbf);
     u->wz = cv.take<bf16_t>(lay.nwz);
     u->in = cv.take<bf16_t>(n0 * kInC);
+    u->in_xp = cv.take<bf16_t>((size_t)(u->nx + 2) * u->ny * u->nz * kInC);
     u->a_e0a = cv.take<bf16_t>(n0 * 16);
     u->cat0 = cv.take<bf16_t>(n0 * 48);
     u->p0 = cv.take<bf16_t>(n1 * 16);
@@ -1034,7 +1055,7 @@ void enqueue_forward(fx_unet *u) {
     // decoders read the upsampled channels straight from the coarser level)
     bf16_t *s0 = u->train ? u->cat0 + 32 : u->cat0, *s1 = u->train ? u->cat1 + 64 : u->cat1;
     const int l0 = u->train ? 48 : 16, l1 = u->train ? 96 : 32;
-    zconv(u, ZE0A, u->in, kInC, nullptr, 0, u->a_e0a, 16);
+    zconv(u, ZE0A, u->in_xp, kInC, nullptr, 0, u->a_e0a, 16);      // x-padded rows of nx + 2
     zconv(u, ZE0B, u->a_e0a, 16, nullptr, 0, s0, l0);
     hipLaunchKernelGGL(k_pool, grid_for(u->n1 * 4), dim3(256), 0, st, s0, l0, u->p0, 16, d1.nx, d1.ny, d1.nz);
     zconv(u, ZE1A, u->p0, 16, nullptr, 0, u->a_e1a, 32);
@@ -1168,7 +1189,7 @@ void unet_geometry(const fx_unet *u, int *nx, int *ny, int *nz, hipStream_t *st)
 
 void unet_pack_from_f64(fx_unet *u, const double *P_slab, double v_top) {
     hipLaunchKernelGGL(k_pack<double>, grid_for(u->n0), dim3(256), 0, u->st, P_slab, u->dop, (float)(v_top / kVScale),
-                       u->in, u->nx * u->ny, u->n0);
+                       u->in, u->in_xp, u->nx, u->nx * u->ny, u->n0);
 }
 
 void unet_forward_enqueue(fx_unet *u) { enqueue_forward(u); }
@@ -1267,7 +1288,7 @@ fx_status unet_pack_input(fx_unet *u, const float *d_P, const double *h_doping, 
     fx_status st = unet_upload_doping(u, h_doping);
     if (st) return st;
     hipLaunchKernelGGL(k_pack<float>, grid_for(u->n0), dim3(256), 0, u->st, d_P, u->dop, (float)(v_top / kVScale), u->in,
-                       u->nx * u->ny, u->n0);
+                       u->in_xp, u->nx, u->nx * u->ny, u->n0);
     return FX_OK;
 }
 
@@ -1286,6 +1307,7 @@ fx_status unet_set_input(fx_unet *u, const float *h_in) {
     float *tmp = (float *)u->cat0;      // n0*48 BF16 = n0*24 floats >= n0*4
     UHIP(hipMemcpyAsync(tmp, c.data(), n * sizeof(float), hipMemcpyHostToDevice, u->st));
     hipLaunchKernelGGL(k_f_to_bf, grid_for(n), dim3(256), 0, u->st, tmp, u->in, n);
+    hipLaunchKernelGGL(k_pad_x, grid_for(u->n0), dim3(256), 0, u->st, u->in, u->in_xp, u->nx, u->n0);
     UHIP(hipStreamSynchronize(u->st));
     return FX_OK;
 }

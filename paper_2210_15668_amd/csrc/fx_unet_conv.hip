@@ -165,9 +165,10 @@ struct ZCfg {
     static constexpr int G = PK ? 1 : CIN / 8;          // 16-byte groups per voxel (packed: one 8-byte voxel)
     static constexpr int GA = PK ? 1 : CA / 8;          // of them from source A
     static constexpr int PLANE = R * XC * (PK ? 8 : G * 16);   // bytes of one staged plane
-    // transfers: 16 bytes per lane ([row][group][column] order), packed 4 bytes
-    // ([row][column][half]); one wave instruction moves 64 consecutive units
-    static constexpr int DU = PK ? 4 : 16;
+    // transfers of 16 bytes per lane, one wave instruction moving 64 consecutive units:
+    // [row][group][column] order, packed [row][voxel pair] (the packed input has its
+    // rows padded by one wrapped voxel at each x-end, so a staged row is contiguous)
+    static constexpr int DU = 16;
     static constexpr int UNITS = PLANE / DU;
     static constexpr int NI = (UNITS + 63) / 64;        // transfer instructions per plane
     static constexpr int PSTRIDE = NI * 64 * DU;        // a staged plane padded to whole instructions
@@ -177,6 +178,7 @@ struct ZCfg {
     static constexpr int LDS = 3 * PSTRIDE + RED;
     static_assert(MS * KS * WX * WY == 4, "4 compute waves per block");
     static_assert(KS == 1 || !PK, "the packed layer is not split");
+    static_assert(!PK || XC % 2 == 0, "packed rows are whole voxel pairs");
     static_assert(NI <= 31, "two planes of transfers in flight must fit the load counter");
     // weight fragments of wave part kp, and the local index of chunk c's first one
     static constexpr int nfk(int kp) {
@@ -318,17 +320,20 @@ __global__ __launch_bounds__(320) void k_convz(const bf16_t *__restrict__ XA, in
         // plane) and source; units past the plane read unit 0's voxel into the padding
         int gofs[NI];
         unsigned srcb = 0;
-        const int nxc = UPA ? nx >> 1 : nx, nyc = UPA ? ny >> 1 : ny;
+        const int nxc = UPA ? nx >> 1 : (C::PK ? nx + 2 : nx), nyc = UPA ? ny >> 1 : ny;
 #pragma unroll
         for (int k = 0; k < NI; ++k) {
             const int u = 64 * k + lane, uu = u < C::UNITS ? u : 0;
             int xc, r, g, e0;                          // e0: first element of the unit in its voxel
             if constexpr (C::PK) {
-                const int h = uu & 1, t = uu >> 1;
-                xc = t % XC;
-                r = t / XC;
-                g = 0;
-                e0 = 2 * h;
+                // voxel pair j of row r: padded x = x0 + 2j (staged column 2j is x0 - 1 + 2j);
+                // pairs past the padded row (outputs there are not stored) read its last pair
+                const int j = uu % (XC / 2);
+                r = uu / (XC / 2);
+                int yy = (y0 - 1 + r) % ny;
+                yy += yy < 0 ? ny : 0;
+                gofs[k] = (yy * (nx + 2) + min(x0 + 2 * j, nx)) * lda;
+                continue;
             } else {
                 xc = uu % XC;
                 const int t = uu / XC;
