@@ -489,24 +489,6 @@ __device__ __forceinline__ Kids kids_of(size_t p, int nx, int ny) {
     return k;
 }
 
-// Y[parent][c] = mean of X[children][c].
-__global__ void k_pool(const bf16_t *__restrict__ X, int ldx, bf16_t *__restrict__ Y, int C, int nx, int ny, int nz) {
-    const int G = C / 4;
-    const size_t total = (size_t)nx * ny * nz * G;
-    for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < total; e += (size_t)gridDim.x * blockDim.x) {
-        const int g = (int)(e % G);
-        const size_t p = e / G;
-        const Kids k = kids_of(p, nx, ny);
-        float s[4] = {0.f, 0.f, 0.f, 0.f};
-        for (int q = 0; q < 8; ++q) {
-            const s4 a = *(const s4 *)(X + k.v[q] * ldx + 4 * g);
-            for (int j = 0; j < 4; ++j) s[j] += bf2f((bf16_t)a[j]);
-        }
-        s4 o;
-        for (int j = 0; j < 4; ++j) o[j] = (short)f2bf(s[j] * 0.125f);
-        *(s4 *)(Y + p * C + 4 * g) = o;
-    }
-}
 
 // D[children][c] += G[parent][c] / 8.
 __global__ void k_pool_bwd(const float *__restrict__ Gr, float *__restrict__ D, int ldd, int C, int nx, int ny, int nz) {
@@ -1023,14 +1005,18 @@ Dims dims_of(const fx_unet *u, int level) {
 const bf16_t *wf_of(const fx_unet *u, int l) { return u->wf + layout().L[l].bf_off; }
 const float *bias_of(const fx_unet *u, int l) { return u->theta + layout().L[l].boff; }
 
-// Forward launch zi of the z-marching convolution on the level of its layer.
-void zconv(fx_unet *u, int zi, const bf16_t *XA, int lda, const bf16_t *XB, int ldb, bf16_t *Y, int ldy) {
+// Forward launch zi of the z-marching convolution on the level of its layer; out >= 3
+// replaces the launch's output mode (3: the head folded in, 4: the pooling folded in,
+// into Yp).
+void zconv(fx_unet *u, int zi, const bf16_t *XA, int lda, const bf16_t *XB, int ldb, bf16_t *Y, int ldy, int out = -1,
+           bf16_t *Yp = nullptr) {
     const UnetLayout &lay = layout();
     const ZLaunch &Z = lay.Z[zi];
     const Layer &L = lay.L[Z.layer];
     const Dims d = dims_of(u, L.level);
-    convz_forward(Z.ca, Z.upa != 0, Z.cb, L.cout, Z.out, XA, lda, XB, ldb, u->wz + Z.wz_off, bias_of(u, Z.layer), Y,
-                  ldy, u->zpart, d.nx, d.ny, d.nz, u->st);
+    const int o = out >= 0 ? out : Z.out;
+    convz_forward(Z.ca, Z.upa != 0, Z.cb, L.cout, o, XA, lda, XB, ldb, u->wz + Z.wz_off, bias_of(u, Z.layer), Y, ldy,
+                  o == 3 ? u->out : u->zpart, u->theta + lay.head_off, Yp, d.nx, d.ny, d.nz, u->st);
 }
 
 void prep_weights(fx_unet *u) {
@@ -1056,11 +1042,10 @@ void enqueue_forward(fx_unet *u) {
     bf16_t *s0 = u->train ? u->cat0 + 32 : u->cat0, *s1 = u->train ? u->cat1 + 64 : u->cat1;
     const int l0 = u->train ? 48 : 16, l1 = u->train ? 96 : 32;
     zconv(u, ZE0A, u->in_xp, kInC, nullptr, 0, u->a_e0a, 16);      // x-padded rows of nx + 2
-    zconv(u, ZE0B, u->a_e0a, 16, nullptr, 0, s0, l0);
-    hipLaunchKernelGGL(k_pool, grid_for(u->n1 * 4), dim3(256), 0, st, s0, l0, u->p0, 16, d1.nx, d1.ny, d1.nz);
+    // the skip layers also write their 2x2x2 averages (the next level's input)
+    zconv(u, ZE0B, u->a_e0a, 16, nullptr, 0, s0, l0, 4, u->p0);
     zconv(u, ZE1A, u->p0, 16, nullptr, 0, u->a_e1a, 32);
-    zconv(u, ZE1B, u->a_e1a, 32, nullptr, 0, s1, l1);
-    hipLaunchKernelGGL(k_pool, grid_for(u->n2 * 8), dim3(256), 0, st, s1, l1, u->p1, 32, d2.nx, d2.ny, d2.nz);
+    zconv(u, ZE1B, u->a_e1a, 32, nullptr, 0, s1, l1, 4, u->p1);
     zconv(u, ZB2A, u->p1, 32, nullptr, 0, u->a_b2a, 64);
     zconv(u, ZB2B_LO, u->a_b2a, 64, nullptr, 0, nullptr, 0);
     zconv(u, ZB2B_HI, u->a_b2a + 32, 64, nullptr, 0, u->a_b2b, 64);
@@ -1072,8 +1057,13 @@ void enqueue_forward(fx_unet *u) {
     if (u->train)
         hipLaunchKernelGGL(k_up, grid_for(u->n1 * 8), dim3(256), 0, st, u->a_d1b, u->cat0, 48, 32, d1.nx, d1.ny, d1.nz);
     zconv(u, ZD0A, u->a_d1b, 32, s0, l0, u->a_d0a, 16);
-    zconv(u, ZD0B, u->a_d0a, 16, nullptr, 0, u->a_d0b, 16);
-    hipLaunchKernelGGL(k_head, grid_for(u->n0), dim3(256), 0, st, u->a_d0b, u->theta + layout().head_off, u->out, u->n0);
+    if (u->train) {                     // the head's gradient reads the last layer's output
+        zconv(u, ZD0B, u->a_d0a, 16, nullptr, 0, u->a_d0b, 16);
+        hipLaunchKernelGGL(k_head, grid_for(u->n0), dim3(256), 0, st, u->a_d0b, u->theta + layout().head_off, u->out,
+                           u->n0);
+    } else {                            // the head folded into the last layer
+        zconv(u, ZD0B, u->a_d0a, 16, nullptr, 0, nullptr, 0, 3);
+    }
 }
 
 // Bias gradient of layer l from its BF16 output gradient Z ([n][cout]).

@@ -179,6 +179,7 @@ struct ZCfg {
     static_assert(MS * KS * WX * WY == 4, "4 compute waves per block");
     static_assert(KS == 1 || !PK, "the packed layer is not split");
     static_assert(!PK || XC % 2 == 0, "packed rows are whole voxel pairs");
+    static_assert(RY % 2 == 0, "pooling pairs the rows of a wave");
     static_assert(NI <= 31, "two planes of transfers in flight must fit the load counter");
     // weight fragments of wave part kp, and the local index of chunk c's first one
     static constexpr int nfk(int kp) {
@@ -293,11 +294,15 @@ __device__ __forceinline__ void zsteps(int nsteps, F &&fn) {
 }
 
 // OUT 0: Y (BF16) = relu(conv + bias); OUT 1: Pf (FP32, ld cout) = conv;
-// OUT 2: Y (BF16) = relu(conv + Pf + bias) with Pf an OUT 1 result (FP32, ld cout).
+// OUT 2: Y (BF16) = relu(conv + Pf + bias) with Pf an OUT 1 result (FP32, ld cout);
+// OUT 3: the network's 1x1x1 head on Y as OUT 0 would store it: Pf[v] = hw[16] +
+//        sum over c of hw[c] Y[v][c] (FP32; Y itself is not stored);
+// OUT 4: Y as OUT 0, and Yp (BF16, ld cout) = its 2x2x2 average on the coarser level.
 template <int CA, bool UPA, int CB, int MS, int KS, int RY, int WX, int OUT>
 __global__ __launch_bounds__(320) void k_convz(const bf16_t *__restrict__ XA, int lda, const bf16_t *__restrict__ XB,
                                                int ldb, const bf16_t *__restrict__ wz, const float *__restrict__ bias,
-                                               bf16_t *__restrict__ Y, int ldy, float *__restrict__ Pf, int nx, int ny,
+                                               bf16_t *__restrict__ Y, int ldy, float *__restrict__ Pf,
+                                               const float *__restrict__ hw, bf16_t *__restrict__ Yp, int nx, int ny,
                                                int nz, int zb, int ntx, int nty, int ntiles) {
     using C = ZCfg<CA, UPA, CB, MS, KS, RY, WX>;
     constexpr int G = C::G, XC = C::XC, NI = C::NI, NF = znfrags(CA, CB);
@@ -414,10 +419,16 @@ __global__ __launch_bounds__(320) void k_convz(const bf16_t *__restrict__ XA, in
     const int off16b = (((kq >> 1) * G + (kq & 1)) * XC + 2) * 16;
 
     const int out_c0 = 16 * m + 4 * kq;
-    float bv[4] = {0.f, 0.f, 0.f, 0.f};
+    float bv[4] = {0.f, 0.f, 0.f, 0.f}, hv[5] = {0.f, 0.f, 0.f, 0.f, 0.f};
     if constexpr (OUT != 1)
 #pragma unroll
         for (int i = 0; i < 4; ++i) bv[i] = bias[out_c0 + i];
+    if constexpr (OUT == 3) {
+        static_assert(MS == 1 && KS == 1, "the head follows one 16-channel tile");
+#pragma unroll
+        for (int i = 0; i < 4; ++i) hv[i] = hw[out_c0 + i];
+        hv[4] = hw[16];
+    }
     const int gx = x0 + 16 * wx + col;
     const int gy0 = y0 + RY * wy;
     const unsigned y_off = (unsigned)(col * ldy + out_c0), pf_off = (unsigned)(col * 16 * MS + out_c0);
@@ -448,12 +459,21 @@ __global__ __launch_bounds__(320) void k_convz(const bf16_t *__restrict__ XA, in
             for (int f = 0; f < NFK; ++f) asm volatile("" : "+v"(af[f]));
 #pragma unroll
             for (int i = 0; i < 4; ++i) asm volatile("" : "+v"(bv[i]));
+            if constexpr (OUT == 3)
+#pragma unroll
+                for (int i = 0; i < 5; ++i) asm volatile("" : "+v"(hv[i]));
         }
         f4 acc[3][RY];
 #pragma unroll
         for (int a = 0; a < 3; ++a)
 #pragma unroll
             for (int r = 0; r < RY; ++r) acc[a][r] = f4{0.f, 0.f, 0.f, 0.f};
+        // pooling (OUT 4): the row pair in progress and the pooled rows of an even plane
+        f4 prow = {0.f, 0.f, 0.f, 0.f}, pacc[(RY + 1) / 2];
+#pragma unroll
+        for (int r = 0; r < (RY + 1) / 2; ++r) pacc[r] = f4{0.f, 0.f, 0.f, 0.f};
+        (void)prow;
+        (void)pacc;
 
         // the NR fragments of row r of a staged plane
         auto read_row = [&](const unsigned char *cur, auto rr, bf8 (&fr)[NR]) {
@@ -543,15 +563,56 @@ __global__ __launch_bounds__(320) void k_convz(const bf16_t *__restrict__ XA, in
                         // the row's first voxel of this wave (uniform) plus a per-lane
                         // offset that stays in one register for every row
                         const size_t v0 = (size_t)(gz * ny + gy) * nx + x0 + 16 * wx;
-                        if (gx < nx) {
-                            if constexpr (OUT == 1) {
-                                *(f4 *)(Pf + v0 * (16 * MS) + pf_off) = a;
-                            } else {
-                                const f2 lo = {fmaxf(a[0] + bv[0], 0.f), fmaxf(a[1] + bv[1], 0.f)};
-                                const f2 hi = {fmaxf(a[2] + bv[2], 0.f), fmaxf(a[3] + bv[3], 0.f)};
-                                const i2 o = {__builtin_bit_cast(int, __builtin_convertvector(lo, bf2)),
-                                              __builtin_bit_cast(int, __builtin_convertvector(hi, bf2))};
-                                *(i2 *)(Y + v0 * ldy + y_off) = o;
+                        if constexpr (OUT == 1) {
+                            if (gx < nx) *(f4 *)(Pf + v0 * (16 * MS) + pf_off) = a;
+                        } else {
+                            const f2 lo = {fmaxf(a[0] + bv[0], 0.f), fmaxf(a[1] + bv[1], 0.f)};
+                            const f2 hi = {fmaxf(a[2] + bv[2], 0.f), fmaxf(a[3] + bv[3], 0.f)};
+                            const bf2 blo = __builtin_convertvector(lo, bf2), bhi = __builtin_convertvector(hi, bf2);
+                            const i2 o = {__builtin_bit_cast(int, blo), __builtin_bit_cast(int, bhi)};
+                            if constexpr (OUT != 3) {
+                                if (gx < nx) *(i2 *)(Y + v0 * ldy + y_off) = o;
+                            }
+                            if constexpr (OUT == 3 || OUT == 4) {
+                                // the stored (rounded) values, widened from the rounded pairs
+                                // themselves (taken back out of the packed vector o, the high
+                                // pair was compiled as a copy of the low one)
+                                const f2 rl = __builtin_convertvector(blo, f2);
+                                const f2 rh = __builtin_convertvector(bhi, f2);
+                                if constexpr (OUT == 3) {
+                                    // head: this lane's 4 channels, then the 4 lane groups of the voxel
+                                    float h = hv[0] * rl[0];
+                                    h = fmaf(hv[1], rl[1], h);
+                                    h = fmaf(hv[2], rh[0], h);
+                                    h = fmaf(hv[3], rh[1], h);
+                                    h += __shfl_xor(h, 16, 64);
+                                    h += __shfl_xor(h, 32, 64);
+                                    if (kq == 0 && gx < nx) Pf[v0 + col] = h + hv[4];
+                                } else {
+                                    // average pooling: x pairs (lanes col, col ^ 1), then the
+                                    // row pair (ro, ro + 1), then the plane pair (gz, gz + 1)
+                                    f4 t = {rl[0], rl[1], rh[0], rh[1]};
+#pragma unroll
+                                    for (int i = 0; i < 4; ++i) t[i] += __shfl_xor(t[i], 1, 64);
+                                    if ((ro & 1) == 0) {
+                                        prow = t;
+                                    } else {
+                                        t = prow + t;
+                                        if ((gz & 1) == 0) {
+                                            pacc[ro >> 1] = t;
+                                        } else {
+                                            t = (pacc[ro >> 1] + t) * 0.125f;
+                                            if ((col & 1) == 0 && gx < nx) {
+                                                const f2 a0 = {t[0], t[1]}, a1 = {t[2], t[3]};
+                                                const i2 po = {__builtin_bit_cast(int, __builtin_convertvector(a0, bf2)),
+                                                               __builtin_bit_cast(int, __builtin_convertvector(a1, bf2))};
+                                                const size_t pv = ((size_t)(gz >> 1) * (ny >> 1) + (gy >> 1)) * (nx >> 1) +
+                                                                  (gx >> 1);
+                                                *(i2 *)(Yp + pv * (16 * MS) + out_c0) = po;
+                                            }
+                                        }
+                                    }
+                                }
                             }
                         }
                     }
@@ -623,7 +684,7 @@ struct ZShape {
 
 // Planes per block: the fewest rounds of blocks over the chip, then the least
 // staging overhead ((zb + 2) / zb input planes per output plane).
-ZShape zshape(int nx, int ny, int nz, int bx, int by, int blocks_per_cu) {
+ZShape zshape(int nx, int ny, int nz, int bx, int by, int blocks_per_cu, bool even) {
     ZShape s;
     s.ntx = (nx + bx - 1) / bx;
     s.nty = (ny + by - 1) / by;
@@ -631,9 +692,9 @@ ZShape zshape(int nx, int ny, int nz, int bx, int by, int blocks_per_cu) {
     const long slots = 256L * blocks_per_cu;
     double best = 1e30;
     s.zb = nz;
-    for (int zb = 1; zb <= nz; ++zb) {
+    for (int zb = even ? 2 : 1; zb <= nz; zb += even ? 2 : 1) {
         const long nzc = (nz + zb - 1) / zb;
-        if (zb > 1 && (long)((nz + zb - 2) / (zb - 1)) == nzc) continue;   // same chunk count, smaller chunks
+        if (!even && zb > 1 && (long)((nz + zb - 2) / (zb - 1)) == nzc) continue;   // same chunk count, smaller chunks
         const long rounds = (xy * nzc + slots - 1) / slots;
         const double cost = (double)rounds * (zb + 2);
         if (cost < best - 1e-9) {
@@ -647,7 +708,7 @@ ZShape zshape(int nx, int ny, int nz, int bx, int by, int blocks_per_cu) {
 
 template <int CA, bool UPA, int CB, int MS, int KS, int RY, int WX, int OUT>
 void launch_z(const bf16_t *XA, int lda, const bf16_t *XB, int ldb, const bf16_t *wz, const float *bias, bf16_t *Y,
-              int ldy, float *Pf, int nx, int ny, int nz, hipStream_t st) {
+              int ldy, float *Pf, const float *hw, bf16_t *Yp, int nx, int ny, int nz, hipStream_t st) {
     using C = ZCfg<CA, UPA, CB, MS, KS, RY, WX>;
     // resident blocks per compute unit (registers and LDS), asked once per instantiation
     static int bpc = 0;
@@ -658,10 +719,11 @@ void launch_z(const bf16_t *XA, int lda, const bf16_t *XB, int ldb, const bf16_t
             n = 1;
         bpc = n;
     }
-    const ZShape s = zshape(nx, ny, nz, C::BX, C::BY, bpc);
+    // pooling pairs planes: blocks start on even planes (nz is even there)
+    const ZShape s = zshape(nx, ny, nz, C::BX, C::BY, bpc, OUT == 4);
     const int ntiles = s.ntx * s.nty * s.nzc;
     hipLaunchKernelGGL((k_convz<CA, UPA, CB, MS, KS, RY, WX, OUT>), dim3((ntiles + 7) / 8 * 8), dim3(320), 0, st, XA,
-                       lda, XB, ldb, wz, bias, Y, ldy, Pf, nx, ny, nz, s.zb, s.ntx, s.nty, ntiles);
+                       lda, XB, ldb, wz, bias, Y, ldy, Pf, hw, Yp, nx, ny, nz, s.zb, s.ntx, s.nty, ntiles);
 }
 
 // Rows per wave: 6 (fewer halo rows per staged row) for the 16-channel layers, whose
@@ -681,16 +743,16 @@ constexpr int zrows(int ca, int cb, int ms, int ks, int wx) {
 // tile is the widest x-extent that fits nx.
 template <int CA, bool UPA, int CB, int MS, int OUT>
 void launch_zw(const bf16_t *XA, int lda, const bf16_t *XB, int ldb, const bf16_t *wz, const float *bias, bf16_t *Y,
-               int ldy, float *Pf, int nx, int ny, int nz, hipStream_t st) {
+               int ldy, float *Pf, const float *hw, bf16_t *Yp, int nx, int ny, int nz, hipStream_t st) {
     constexpr int KS = MS <= 2 && znfrags(CA, CB) > 36 ? 2 : 1;
     static_assert(znfrags(CA, CB) / KS <= 36, "weight fragments per wave");
     constexpr int WXMAX = 4 / (MS * KS);
     if (WXMAX > 1 && nx > 16 * (WXMAX / 2))
         launch_z<CA, UPA, CB, MS, KS, zrows(CA, CB, MS, KS, WXMAX), WXMAX, OUT>(XA, lda, XB, ldb, wz, bias, Y, ldy,
-                                                                                 Pf, nx, ny, nz, st);
+                                                                                 Pf, hw, Yp, nx, ny, nz, st);
     else
-        launch_z<CA, UPA, CB, MS, KS, zrows(CA, CB, MS, KS, 1), 1, OUT>(XA, lda, XB, ldb, wz, bias, Y, ldy, Pf, nx,
-                                                                          ny, nz, st);
+        launch_z<CA, UPA, CB, MS, KS, zrows(CA, CB, MS, KS, 1), 1, OUT>(XA, lda, XB, ldb, wz, bias, Y, ldy, Pf, hw,
+                                                                          Yp, nx, ny, nz, st);
 }
 
 }  // namespace
@@ -712,12 +774,12 @@ void convz_prep(const float *theta_w, int cin, int cout, int ca, int cb, int ci_
 }
 
 bool convz_forward(int ca, bool upa, int cb, int cout, int out, const bf16_t *XA, int lda, const bf16_t *XB, int ldb,
-                   const bf16_t *wz, const float *bias, bf16_t *Y, int ldy, float *Pf, int nx, int ny, int nz,
-                   hipStream_t st) {
-    if (upa && ((nx | ny | nz) & 1)) return false;     // the coarser level is exactly half
+                   const bf16_t *wz, const float *bias, bf16_t *Y, int ldy, float *Pf, const float *hw, bf16_t *Yp,
+                   int nx, int ny, int nz, hipStream_t st) {
+    if ((upa || out == 4) && ((nx | ny | nz) & 1)) return false;     // the coarser level is exactly half
 #define FX_Z_CASE(a, u, b, co, o)                                                                               \
     if (ca == a && upa == u && cb == b && cout == co && out == o) {                                             \
-        launch_zw<a, u, b, co / 16, o>(XA, lda, XB, ldb, wz, bias, Y, ldy, Pf, nx, ny, nz, st);                 \
+        launch_zw<a, u, b, co / 16, o>(XA, lda, XB, ldb, wz, bias, Y, ldy, Pf, hw, Yp, nx, ny, nz, st);         \
         return true;                                                                                            \
     }
     FX_Z_CONFIGS(FX_Z_CASE)

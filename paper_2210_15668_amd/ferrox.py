@@ -521,9 +521,14 @@ class UNet:
         self._dop = np.ascontiguousarray(doping_planes, np.float64)
         _check(lib().unet_pack_input(self._h, P_slab.data_ptr(), self._dop.ctypes.data_as(_dp), float(v_top)))
 
-    def forward(self, out=None):
-        """Runs the network on its current input; returns a float32 tensor (nzd, ny, nx)."""
+    def forward(self, out=None, copy: bool = True):
+        """Runs the network on its current input; returns a float32 tensor (nzd, ny, nx).
+        With copy=False the output stays in the workspace (as in a learned solve, which
+        places it into phi directly) and None is returned."""
         import torch
+        if not copy:
+            _check(lib().unet_forward(self._h, None))
+            return None
         if out is None:
             out = torch.empty(self.shape, dtype=torch.float32, device=self.device)
         _check(lib().unet_forward(self._h, out.data_ptr()))

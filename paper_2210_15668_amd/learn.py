@@ -325,8 +325,8 @@ def evaluate_gate_steps(net: ferrox.UNet, spec: W.StackSpec, n_steps: int = 120,
 
 
 def inference_rate(net: ferrox.UNet, reps: int = 20) -> Dict:
-    """Forward passes per second on the current input and the matrix-core throughput they
-    imply (multiply-adds of the 3x3x3 convolutions counted as 2 FLOP).  Only real work
+    """Forward passes per second on the current input (the output left in the workspace,
+    as a learned solve uses it) and the matrix-core throughput they imply (multiply-adds of the 3x3x3 convolutions counted as 2 FLOP).  Only real work
     counts: the first layer has 3 input channels (P, doping, V), whatever width the
     kernel pads them to."""
     nz, ny, nx = net.shape
@@ -336,8 +336,8 @@ def inference_rate(net: ferrox.UNet, reps: int = 20) -> Dict:
         n = n0 if q in (0, 1, 8, 9) else (n0 // 8 if q in (2, 3, 6, 7) else n0 // 64)
         flops += 2 * 27 * (IN_CHANNELS if q == 0 else ci) * co * n
     for _ in range(3):
-        net.forward()
-    _, dt = timed(lambda: [net.forward() for _ in range(reps)])
+        net.forward(copy=False)
+    _, dt = timed(lambda: [net.forward(copy=False) for _ in range(reps)])
     s = dt / reps
     return {"ms": 1e3 * s, "flop": flops, "tflops": flops / s / 1e12, "peak_tflops_bf16": 2500.0,
             "frac": flops / s / 1e12 / 2500.0}

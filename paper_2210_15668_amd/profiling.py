@@ -152,13 +152,14 @@ def traffic(base):
 
 
 # Launches of one forward pass in order: (name, input channels of real work, output
-# channels, level); None for the elementwise kernels (pooling, head).
-UNET_LAUNCHES = [("e0a 3->16", 3, 16, 0), ("e0b 16->16", 16, 16, 0), ("pool 0", None, 16, 1),
-                 ("e1a 16->32", 16, 32, 1), ("e1b 32->32", 32, 32, 1), ("pool 1", None, 32, 2),
+# channels, level).  The skip layers also write the pooled tensor of the next level, the
+# last layer applies the head.
+UNET_LAUNCHES = [("e0a 3->16", 3, 16, 0), ("e0b 16->16 (+ 2x2x2 pooling)", 16, 16, 0),
+                 ("e1a 16->32", 16, 32, 1), ("e1b 32->32 (+ 2x2x2 pooling)", 32, 32, 1),
                  ("b2a 32->64", 32, 64, 2), ("b2b 64->64, in 0..31", 32, 64, 2),
                  ("b2b 64->64, in 32..63", 32, 64, 2), ("d1a 96->32, upsampled 64", 64, 32, 1),
                  ("d1a 96->32, skip 32", 32, 32, 1), ("d1b 32->32", 32, 32, 1), ("d0a 48->16", 48, 16, 0),
-                 ("d0b 16->16", 16, 16, 0), ("head", None, 1, 0)]
+                 ("d0b 16->16 (+ 1x1x1 head)", 16, 16, 0)]
 
 
 def unet(reps):
@@ -174,10 +175,10 @@ def unet(reps):
     st = ferrox.Stack(spec, W.random_P(spec, learn.TEST_SEED0 + 1))
     net.input_from_stack(st, 1.0)
     for _ in range(3):
-        net.forward()
+        net.forward(copy=False)
     torch.cuda.synchronize()
     for _ in range(reps):
-        net.forward()
+        net.forward(copy=False)
     torch.cuda.synchronize()
     st.close()
     net.close()
@@ -193,16 +194,9 @@ def unet_layers(trace_dir):
     n0 = spec.nx * spec.ny * (kt - kb)
     db = _db(trace_dir)
     rows = db.execute("select name, start, end from kernels order by start").fetchall()
-    passes, cur = [], []
-    for name, a, b in rows:
-        k = _short(name)
-        if not (k.startswith("k_convz") or k.startswith("k_pool") or k.startswith("k_head")):
-            continue
-        cur.append((k, (b - a) / 1e3))
-        if k.startswith("k_head"):
-            if len(cur) == len(UNET_LAUNCHES):
-                passes.append(cur)
-            cur = []
+    conv = [(_short(n), (b - a) / 1e3) for n, a, b in rows if _short(n).startswith("k_convz")]
+    m = len(UNET_LAUNCHES)
+    passes = [conv[i:i + m] for i in range(0, len(conv) - m + 1, m)]
     passes = passes[3:]                        # the untimed passes first
     print(f"{len(passes)} forward passes of {spec.nx}x{spec.ny}x{kt - kb}; median per launch\n")
     print("| launch | kernel | us | GFLOP | TFLOP/s |")
@@ -210,10 +204,10 @@ def unet_layers(trace_dir):
     tot_us = tot_fl = 0.0
     for i, (lname, ci, co, lev) in enumerate(UNET_LAUNCHES):
         d = sorted(p[i][1] for p in passes)[len(passes) // 2]
-        fl = 2.0 * 27 * ci * co * n0 / 8 ** lev if ci else 0.0
+        fl = 2.0 * 27 * ci * co * n0 / 8 ** lev
         tot_us += d
         tot_fl += fl
-        rate = f"{fl / d / 1e6:.0f}" if ci else "-"
+        rate = f"{fl / d / 1e6:.0f}"
         print(f"| {lname} | `{passes[0][i][0]}` | {d:.2f} | {fl / 1e9:.2f} | {rate} |")
     print(f"| forward pass | (sum of medians) | {tot_us:.1f} | {tot_fl / 1e9:.1f} | {tot_fl / tot_us / 1e6:.0f} "
           f"({tot_fl / tot_us / 1e6 / 2500:.3f} of 2.5 PFLOP/s) |")
