@@ -174,6 +174,7 @@ struct Work {
     const int *prefix;
     int ninst;
     int total;
+    InstState *st;                     // the instances' states (InstState[ninst])
 };
 
 // ------------------------------------------------------------------ launchers
@@ -201,7 +202,7 @@ struct ResWork {
 // 1: at the output of the cycle just run (forming phi_in + clip(e) first
 // where the update is not folded into the smoother).
 template <typename T> void launch_residual(const Inst<T> *I, const ResWork &w, int after_cycle, hipStream_t st);
-template <typename T> void launch_reduce(const Inst<T> *I, int ninst, int count_cycle, hipStream_t st);
+template <typename T> void launch_reduce(const Inst<T> *I, InstState *S, int ninst, int count_cycle, hipStream_t st);
 // Launch shape of one level's smoother: tile of 2^lbx x 2^(8-lbx) threads,
 // zt planes per thread, w8: register budget for 8 waves per SIMD.  Only the
 // division of the work changes, never a cell's arithmetic.
@@ -227,7 +228,7 @@ template <typename T> void launch_prolong(const Inst<T> *I, const Work &w, int l
 // the same prolongation by coarse columns, for red/black levels halved in x and y and
 // paired in z (the work table counts exactly those instances' tiles)
 template <typename T> void launch_prolong_cc(const Inst<T> *I, const Work &w, int level, int cz, hipStream_t st);
-template <typename T> void launch_coarse(const Inst<T> *I, int ninst, int lds_bytes, hipStream_t st);
+template <typename T> void launch_coarse(const Inst<T> *I, InstState *S, int ninst, int lds_bytes, hipStream_t st);
 template <typename T> void launch_head(const Inst<T> *I, int ninst, int advance, hipStream_t st);
 template <typename T> void launch_zero_fix(const Inst<T> *I, const Work &w, hipStream_t st);
 template <typename T> void launch_run_setup(const Inst<T> *I, int ninst, int nsteps, int has_sched, double dt,

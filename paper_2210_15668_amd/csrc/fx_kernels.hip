@@ -67,6 +67,10 @@ __device__ __forceinline__ Xv<T> xview(const XferArgs<T> &X) {
     return v;
 }
 
+// State of instance inst of a work-table launch, addressed from the kernel argument
+// (one load, not a load of the pointer held in the instance and then of the state).
+__device__ __forceinline__ GState *wstate(const Work &w, int inst) { return asp<1>(w.st + inst); }
+
 struct Blk {
     int inst, t;
     bool ok;
@@ -442,7 +446,7 @@ __global__ __launch_bounds__(256) void k_tdgl(const Inst<T> *I, Work w, int sel)
     const Blk b = find_block(w);
     if (!b.ok) return;
     const Inst<T> &a = I[b.inst];
-    const GState *s = asp<1>(a.st);
+    const GState *s = wstate(w, b.inst);
     if (sel && !s->adv) return;
     const int pcur = s->pcur;
     const T3 t = split3(b.t, a.nx, a.ny);
@@ -464,7 +468,7 @@ __global__ __launch_bounds__(256) void k_tdgl_corr(const Inst<T> *I, Work w) {
     const Blk b = find_block(w);
     if (!b.ok) return;
     const Inst<T> &a = I[b.inst];
-    const GState *s = asp<1>(a.st);
+    const GState *s = wstate(w, b.inst);
     if (!s->corr) return;
     const int pcur = s->pcur;
     const T3 t = split3(b.t, a.nx, a.ny);
@@ -549,7 +553,7 @@ __global__ __launch_bounds__(256) void k_extrap(const Inst<T> *I, Work w) {
     const Blk b = find_block(w);
     if (!b.ok) return;
     const Inst<T> &a = I[b.inst];
-    const GState *s = asp<1>(a.st);
+    const GState *s = wstate(w, b.inst);
     const int order = s->order;
     if (!s->fresh || (order == 0 && !s->usestar)) return;
     const size_t nxy = (size_t)a.nx * a.ny, off = (size_t)a.kb * nxy, n = (size_t)a.nzd * nxy;
@@ -725,7 +729,7 @@ __global__ __launch_bounds__(256) void k_zero_fix(const Inst<T> *I, Work w) {
     const Blk b = find_block(w);
     if (!b.ok) return;
     const Inst<T> &a = I[b.inst];
-    const GState *s = asp<1>(a.st);
+    const GState *s = wstate(w, b.inst);
     if (!s->zero_fix) return;
     const size_t nxy = (size_t)a.nx * a.ny, n = (size_t)a.nzd * nxy;
     double FX_AS(1) *out = asp<1>(a.phi[s->cur]) + (size_t)a.kb * nxy;
@@ -909,7 +913,7 @@ __global__ __launch_bounds__(256) void k_residual(const Inst<T> *I, Work w, int 
     const Blk b = find_block(w);
     if (!b.ok) return;
     const Inst<T> &a = I[b.inst];
-    const GState *s = asp<1>(a.st);
+    const GState *s = wstate(w, b.inst);
     if (after_cycle ? s->done != 0 : !s->fresh) return;
     if ((MODE == 2) != (after_cycle && !a.fold)) return;
     const T3 t = split3(b.t, a.nx, a.ny);
@@ -927,11 +931,11 @@ __global__ __launch_bounds__(256) void k_residual(const Inst<T> *I, Work w, int 
 // Deterministic final sum of one instance's residual partials (a block per
 // instance) and its stop decision.
 template <typename T>
-__global__ __launch_bounds__(1024) void k_reduce(const Inst<T> *I, int count_cycle) {
+__global__ __launch_bounds__(1024) void k_reduce(const Inst<T> *I, InstState *S, int count_cycle) {
     __shared__ double lr[16];
     __shared__ double lf[16];
     const Inst<T> &a = I[blockIdx.x];
-    GState *s = asp<1>(a.st);
+    GState *s = asp<1>(S + blockIdx.x);
     if (count_cycle ? s->done != 0 : !s->fresh) return;
     const int n = tiles3(a.nx, a.ny, (a.nzd + kResZ - 1) / kResZ);
     const double FX_AS(1) *part = asp<1>(a.part);
@@ -980,7 +984,7 @@ __device__ __forceinline__ T rb_nb_sum(const Lv<T, 1> &L, int k, T ex0, T ex1, T
 // update is folded in) also writes phi_out = phi_in + clip(e) for each black
 // cell and its red partner (the pair 2m, 2m+1 of a row).
 template <typename T, int ZI, int ZT, int UPD>
-__device__ __forceinline__ void smooth_rb_body(const Inst<T> &a, const Lv<T, 1> &L, int t, int color, int lbx) {
+__device__ __forceinline__ void smooth_rb_body(const Inst<T> &a, const GState *st, const Lv<T, 1> &L, int t, int color, int lbx) {
     const int hx = L.nx >> 1;
     const T3 tt = split3r(t, hx, L.ny, lbx);
     const int mm = (tt.tx << lbx) + (threadIdx.x & ((1 << lbx) - 1));
@@ -1000,7 +1004,7 @@ __device__ __forceinline__ void smooth_rb_body(const Inst<T> &a, const Lv<T, 1> 
     double FX_AS(1) *phi_out = nullptr;
     const int FX_AS(1) *pflags = asp<1>(a.pflags);
     if (upd) {
-        const GState *s = asp<1>(a.st);
+        const GState *s = st;
         const size_t off = (size_t)a.kb * a.nx * a.ny;
         phi_in = asp<1>(a.phi[cyc_src(s)]) + off;
         phi_out = asp<1>(a.phi[cyc_dst(s)]) + off;
@@ -1133,7 +1137,7 @@ __global__ __launch_bounds__(256) void k_smooth_zpair(const Inst<T> *I, Work w, 
     const Blk b = find_block(w);
     if (!b.ok) return;
     const Inst<T> &a = I[b.inst];
-    if (asp<1>(a.st)->done) return;
+    if (wstate(w, b.inst)->done) return;
     const Lv<T, 1> L = gview(a.lv[level]);
     if (!L.rb) return;                               // the host fuses only all-red/black levels
     smooth_zpair_body<T, ZT>(L, b.t, lbx);
@@ -1149,12 +1153,12 @@ __device__ __forceinline__ void smooth_kernel(const Inst<T> *I, const Work &w, i
     const Blk b = find_block(w);
     if (!b.ok) return;
     const Inst<T> &a = I[b.inst];
-    const GState *st = asp<1>(a.st);
+    const GState *st = wstate(w, b.inst);
     if (st->done || (skip_light && st->light)) return;
     const Lv<T, 1> L = gview(a.lv[level]);
     if (L.rb) {
         if (color > 1) return;
-        smooth_rb_body<T, ZI, ZT, UPD>(a, L, b.t, color, lbx);
+        smooth_rb_body<T, ZI, ZT, UPD>(a, st, L, b.t, color, lbx);
     } else {
         smooth_nat_body<T, ZT>(L, b.t, color, ZI, lbx);
     }
@@ -1188,7 +1192,7 @@ __global__ __launch_bounds__(256) void k_restrict(const Inst<T> *I, Work w, int 
     const Blk b = find_block(w);
     if (!b.ok) return;
     const Inst<T> &a = I[b.inst];
-    if (asp<1>(a.st)->done) return;
+    if (wstate(w, b.inst)->done) return;
     const Lv<T, 1> C = gview(a.lv[level + 1]);
     const T3 t = split3(b.t, C.nx, C.ny);
     const int I0 = t.tx * BX + threadIdx.x;
@@ -1272,7 +1276,7 @@ __global__ __launch_bounds__(256) void k_prolong_red(const Inst<T> *I, Work w, i
     const Blk b = find_block(w);
     if (!b.ok) return;
     const Inst<T> &a = I[b.inst];
-    if (asp<1>(a.st)->done) return;
+    if (wstate(w, b.inst)->done) return;
     const Lv<T, 1> F = gview(a.lv[level]);
     if (!F.rb) return;                               // the host fuses only all-red/black levels
     const Lv<T, 1> C = gview(a.lv[level + 1]);
@@ -1325,7 +1329,7 @@ __global__ __launch_bounds__(256) void k_prolong_cc(const Inst<T> *Ia, Work w, i
     const Blk b = find_block(w);
     if (!b.ok) return;
     const Inst<T> &a = Ia[b.inst];
-    if (asp<1>(a.st)->done) return;
+    if (wstate(w, b.inst)->done) return;
     const Lv<T, 1> C = gview(a.lv[level + 1]);
     const T3 t = split3(b.t, C.nx, C.ny);
     const int I = t.tx * BX + threadIdx.x;
@@ -1381,7 +1385,7 @@ __global__ __launch_bounds__(256) void k_prolong(const Inst<T> *I, Work w, int l
     const Blk b = find_block(w);
     if (!b.ok) return;
     const Inst<T> &a = I[b.inst];
-    if (asp<1>(a.st)->done) return;
+    if (wstate(w, b.inst)->done) return;
     const Lv<T, 1> F = gview(a.lv[level]);
     const int nxe = F.rb ? F.nx >> 1 : F.nx;      // black cells per row on a red/black level
     const T3 t = split3(b.t, nxe, F.ny);
@@ -1610,10 +1614,11 @@ __device__ void bottom_cg(const Lv<T, 3> &B, T FX_AS(3) *p, T FX_AS(3) *q, doubl
 // A block per instance: the V-cycle from level lc down to the coarsest with
 // every level's e, r, sigma and coefficient tables resident in LDS.
 template <typename T>
-__global__ __launch_bounds__(512) void k_coarse(const Inst<T> *I) {
+__global__ __launch_bounds__(512) void k_coarse(const Inst<T> *I, InstState *S) {
     extern __shared__ double lds_raw[];
     const Inst<T> &A = I[blockIdx.x];
-    if (asp<1>(A.st)->done) return;
+    const GState *sta = asp<1>(S + blockIdx.x);
+    if (sta->done) return;
     unsigned char FX_AS(3) *lds = asp<3>((unsigned char *)lds_raw);
     const int l0 = A.lc, nl = A.nlev - A.lc;
     auto lvl = [&](int q) {
@@ -1631,21 +1636,7 @@ __global__ __launch_bounds__(512) void k_coarse(const Inst<T> *I) {
         L.dg = tab + 3 * L.nz;
         return L;
     };
-    // Per-plane coefficient tables into LDS, a wave per level: the levels' loads
-    // are in flight together instead of one level's round trips after another's.
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nwave = blockDim.x >> 6;
-    for (int q = wave; q < nl; q += nwave) {
-        const Lv<T, 1> G = gview(A.lv[l0 + q]);
-        T FX_AS(3) *tab = (T FX_AS(3) *)(lds + A.off_t[q]);
-        for (int c = lane; c < G.nz; c += 64) {
-            tab[c] = G.cxy[c];
-            tab[G.nz + c] = G.czm[c];
-            tab[2 * G.nz + c] = G.czp[c];
-            tab[3 * G.nz + c] = G.dg[c];
-        }
-    }
-    // transfer tables into LDS: restriction and prolongation then wait on no
-    // global load
+    // transfer tables between levels q and q + 1 in LDS
     auto xlds = [&](int q) {
         const int nf = A.lv[l0 + q].nz, nc = A.lv[l0 + q + 1].nz;
         int FX_AS(3) *ib = (int FX_AS(3) *)(lds + A.off_x[q]);
@@ -1663,18 +1654,91 @@ __global__ __launch_bounds__(512) void k_coarse(const Inst<T> *I) {
         X.xy = A.xf[l0 + q].xy;
         return X;
     };
-    for (int q = wave; q + 1 < nl; q += nwave) {             // likewise a wave per level pair
+    // Copy into LDS: the top level's r and sigma (all threads), one level's per-plane
+    // coefficient tables and one level pair's transfer tables per wave.  Every load of the
+    // first pass is issued before the first LDS store, so the copy costs one round trip to
+    // memory; the later passes (levels with more than 64 planes, more than 8 levels, more
+    // than 8 values per thread) follow.
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nwave = blockDim.x >> 6;
+    constexpr int kU = 8;
+    const Lv<T, 1> G0 = gview(A.lv[l0]);
+    const Lv<T, 3> L0 = lvl(0);
+    const int n0 = G0.nx * G0.ny * G0.nz;
+    const int ns0 = G0.nx * G0.ny * (G0.sig_hi - G0.sig_lo);
+    T v[kU];
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+        const int c = threadIdx.x + u * blockDim.x;
+        v[u] = c < n0 ? G0.r[c] : (c < n0 + ns0 ? G0.sig[c - n0] : T(0));
+    }
+    const bool tq = wave < nl, xq = wave + 1 < nl;
+    T tv[4] = {T(0), T(0), T(0), T(0)};
+    int tnz = 0;
+    if (tq) {
+        const Lv<T, 1> G = gview(A.lv[l0 + wave]);
+        tnz = G.nz;
+        if (lane < tnz) { tv[0] = G.cxy[lane]; tv[1] = G.czm[lane]; tv[2] = G.czp[lane]; tv[3] = G.dg[lane]; }
+    }
+    int xc[3] = {0, 0, 0}, xf[3] = {0, 0, 0};
+    T xw[2] = {T(0), T(0)};
+    int xnf = 0, xnc = 0;
+    if (xq) {
+        const Xv<T> G = xview(A.xf[l0 + wave]);
+        xnf = A.lv[l0 + wave].nz;
+        xnc = A.lv[l0 + wave + 1].nz;
+        if (lane < xnc) { xc[0] = G.cks[lane]; xc[1] = G.ccnt[lane]; xc[2] = G.cthick[lane]; }
+        if (lane < xnf) {
+            xf[0] = G.fthick[lane]; xf[1] = G.pka[lane]; xf[2] = G.pkb[lane];
+            xw[0] = G.pwa[lane]; xw[1] = G.pwb[lane];
+        }
+    }
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+        const int c = threadIdx.x + u * blockDim.x;
+        if (c < n0) L0.r[c] = v[u];
+        else if (c < n0 + ns0) L0.sig[c - n0] = v[u];
+    }
+    if (tq && lane < tnz) {
+        T FX_AS(3) *tab = (T FX_AS(3) *)(lds + A.off_t[wave]);
+        tab[lane] = tv[0]; tab[tnz + lane] = tv[1]; tab[2 * tnz + lane] = tv[2]; tab[3 * tnz + lane] = tv[3];
+    }
+    if (xq) {
+        const Xv<T, 3> X = xlds(wave);
+        int FX_AS(3) *ib = (int FX_AS(3) *)X.cks;
+        T FX_AS(3) *wb = (T FX_AS(3) *)X.pwa;
+        if (lane < xnc) { ib[lane] = xc[0]; ib[xnc + lane] = xc[1]; ib[2 * xnc + lane] = xc[2]; }
+        if (lane < xnf) {
+            ib[3 * xnc + lane] = xf[0]; ib[3 * xnc + xnf + lane] = xf[1]; ib[3 * xnc + 2 * xnf + lane] = xf[2];
+            wb[lane] = xw[0]; wb[xnf + lane] = xw[1];
+        }
+    }
+    for (int c = threadIdx.x + kU * blockDim.x; c < n0 + ns0; c += blockDim.x) {
+        if (c < n0) L0.r[c] = G0.r[c];
+        else L0.sig[c - n0] = G0.sig[c - n0];
+    }
+    for (int q = wave; q < nl; q += nwave) {
+        const Lv<T, 1> G = gview(A.lv[l0 + q]);
+        T FX_AS(3) *tab = (T FX_AS(3) *)(lds + A.off_t[q]);
+        for (int c = (q == wave ? 64 : 0) + lane; c < G.nz; c += 64) {
+            tab[c] = G.cxy[c];
+            tab[G.nz + c] = G.czm[c];
+            tab[2 * G.nz + c] = G.czp[c];
+            tab[3 * G.nz + c] = G.dg[c];
+        }
+    }
+    for (int q = wave; q + 1 < nl; q += nwave) {
         const Xv<T> G = xview(A.xf[l0 + q]);
         const int nf = A.lv[l0 + q].nz, nc = A.lv[l0 + q + 1].nz;
         const Xv<T, 3> X = xlds(q);
         int FX_AS(3) *ib = (int FX_AS(3) *)X.cks;
         T FX_AS(3) *wb = (T FX_AS(3) *)X.pwa;
-        for (int c = lane; c < nc; c += 64) {
+        const int c0 = q == wave ? 64 : 0;
+        for (int c = c0 + lane; c < nc; c += 64) {
             ib[c] = G.cks[c];
             ib[nc + c] = G.ccnt[c];
             ib[2 * nc + c] = G.cthick[c];
         }
-        for (int c = lane; c < nf; c += 64) {
+        for (int c = c0 + lane; c < nf; c += 64) {
             ib[3 * nc + c] = G.fthick[c];
             ib[3 * nc + nf + c] = G.pka[c];
             ib[3 * nc + 2 * nf + c] = G.pkb[c];
@@ -1682,29 +1746,8 @@ __global__ __launch_bounds__(512) void k_coarse(const Inst<T> *I) {
             wb[nf + c] = G.pwb[c];
         }
     }
-    {
-        const Lv<T, 1> G = gview(A.lv[l0]);
-        const Lv<T, 3> L0 = lvl(0);
-        const int n = G.nx * G.ny * G.nz;
-        const int ns = G.nx * G.ny * (G.sig_hi - G.sig_lo);
-        // four elements per thread and pass, loaded before they are stored
-        for (int c0 = threadIdx.x; c0 < n + ns; c0 += 4 * blockDim.x) {
-            T v[4];
-#pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                const int c = c0 + u * blockDim.x;
-                v[u] = c < n ? G.r[c] : (c < n + ns ? G.sig[c - n] : T(0));
-            }
-#pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                const int c = c0 + u * blockDim.x;
-                if (c < n) L0.r[c] = v[u];
-                else if (c < n + ns) L0.sig[c - n] = v[u];
-            }
-        }
-        __syncthreads();
-    }
-    const int light = asp<1>(A.st)->light;
+    __syncthreads();
+    const int light = sta->light;
     const int nu1 = light ? 1 : A.nu1, nu2 = light ? 1 : A.nu2;
     for (int q = 0; q < nl - 1; ++q) {
         const Lv<T, 3> L = lvl(q);
@@ -1810,8 +1853,8 @@ void launch_residual(const Inst<T> *I, const ResWork &w, int after_cycle, hipStr
 }
 
 template <typename T>
-void launch_reduce(const Inst<T> *I, int ninst, int count_cycle, hipStream_t st) {
-    hipLaunchKernelGGL(k_reduce<T>, dim3(ninst), dim3(1024), 0, st, I, count_cycle);
+void launch_reduce(const Inst<T> *I, InstState *S, int ninst, int count_cycle, hipStream_t st) {
+    hipLaunchKernelGGL(k_reduce<T>, dim3(ninst), dim3(1024), 0, st, I, S, count_cycle);
 }
 
 template <typename T, int ZT>
@@ -1888,8 +1931,8 @@ void launch_prolong_cc(const Inst<T> *I, const Work &w, int level, int cz, hipSt
 }
 
 template <typename T>
-void launch_coarse(const Inst<T> *I, int ninst, int lds_bytes, hipStream_t st) {
-    hipLaunchKernelGGL(k_coarse<T>, dim3(ninst), dim3(512), lds_bytes, st, I);
+void launch_coarse(const Inst<T> *I, InstState *S, int ninst, int lds_bytes, hipStream_t st) {
+    hipLaunchKernelGGL(k_coarse<T>, dim3(ninst), dim3(512), lds_bytes, st, I, S);
 }
 
 template <typename T>
@@ -1934,7 +1977,7 @@ void launch_fill(double *x, size_t n, double v, hipStream_t st) {
     template void launch_begin<T>(const Inst<T> *, int, int, hipStream_t);                                  \
     template void launch_extrap<T>(const Inst<T> *, const Work &, hipStream_t);                              \
     template void launch_residual<T>(const Inst<T> *, const ResWork &, int, hipStream_t);                    \
-    template void launch_reduce<T>(const Inst<T> *, int, int, hipStream_t);                                  \
+    template void launch_reduce<T>(const Inst<T> *, InstState *, int, int, hipStream_t);                                  \
     template void launch_smooth<T>(const Inst<T> *, const Work &, int, int, int, int, const SmoothCfg &,     \
                                    double *, hipStream_t, hipEvent_t, hipEvent_t, int);                      \
     template void launch_smooth_zpair<T>(const Inst<T> *, const Work &, int, const SmoothCfg &, hipStream_t); \
@@ -1942,7 +1985,7 @@ void launch_fill(double *x, size_t n, double v, hipStream_t st) {
     template void launch_restrict<T>(const Inst<T> *, const Work &, int, hipStream_t);                       \
     template void launch_prolong<T>(const Inst<T> *, const Work &, int, hipStream_t);                        \
     template void launch_prolong_cc<T>(const Inst<T> *, const Work &, int, int, hipStream_t);                \
-    template void launch_coarse<T>(const Inst<T> *, int, int, hipStream_t);                                  \
+    template void launch_coarse<T>(const Inst<T> *, InstState *, int, int, hipStream_t);                                  \
     template void launch_head<T>(const Inst<T> *, int, int, hipStream_t);                                    \
     template void launch_zero_fix<T>(const Inst<T> *, const Work &, hipStream_t);                            \
     template void launch_run_setup<T>(const Inst<T> *, int, int, int, double, int, hipStream_t);             \

@@ -546,6 +546,7 @@ fx_status build_work(Engine *e) {
         Work w;
         w.prefix = e->prefix_dev + (size_t)tab * (n + 1);
         w.ninst = n;
+        w.st = e->st_dev;
         long long tot = 0;
         e->prefix_host.push_back(0);
         for (int i = 0; i < n; ++i) {
@@ -851,7 +852,7 @@ void enq_vcycle(Engine *e) {
         }
         launch_restrict(I, e->w_rs[l], l, e->st);
     }
-    launch_coarse(I, e->n, e->lds_max, e->st);
+    launch_coarse(I, e->st_dev, e->n, e->lds_max, e->st);
     for (int l = e->max_lc - 1; l >= 0; --l) {
         const int nu2 = l == 0 ? e->nu2 : e->nu2c;
         // on a small red/black level the correction is formed inside the first
@@ -882,7 +883,7 @@ template <typename T>
 void enq_cycle(Engine *e) {
     enq_vcycle<T>(e);
     launch_residual(idev<T>(e), e->w_res, 1, e->st);
-    launch_reduce(idev<T>(e), e->n, 1, e->st);
+    launch_reduce(idev<T>(e), e->st_dev, e->n, 1, e->st);
 }
 
 // Advance slot: finalize stopped solves, start the next time step where due.
@@ -897,7 +898,7 @@ void enq_advance(Engine *e) {
     launch_begin(I, e->n, 1, e->st);
     launch_extrap(I, e->w_ext, e->st);
     launch_residual(I, e->w_res, 0, e->st);
-    launch_reduce(I, e->n, 0, e->st);
+    launch_reduce(I, e->st_dev, e->n, 0, e->st);
 }
 
 template <typename T>
@@ -964,7 +965,7 @@ fx_status solve_plain_t(Engine *e) {
     const Inst<T> *I = idev<T>(e);
     launch_begin(I, e->n, 0, e->st);
     launch_residual(I, e->w_res, 0, e->st);
-    launch_reduce(I, e->n, 0, e->st);
+    launch_reduce(I, e->st_dev, e->n, 0, e->st);
     int enq = 0;
     int batch = e->trace ? 0 : std::max(1, e->k_pred);
     fx_status st;
