@@ -55,6 +55,12 @@ constexpr int kPhiBufs = 8;       // phi^n, up to 3 stored levels, two iterate b
                                   // the last predictor's phi*
 constexpr int kMaxHist = 4;       // stored levels of a predictor-corrector instance (Euler: 3)
 constexpr int kCoarseLdsBytes = 64 * 1024;
+// temporal blocking of the smoothing below the finest level (k_pre_tb / k_post_tb)
+constexpr int kTbT = 8;                    // tile edge (cells)
+constexpr int kTbH = 4;                    // ring (cells): 2 nu for nu <= 2 sweeps
+constexpr int kTbW = kTbT + 2 * kTbH;      // box edge; a thread per box column
+constexpr int kTbMaxNz = 30;               // planes of a blocked level (a column's values in registers)
+constexpr int kTbLdsBytes = 64 * 1024;     // largest box (all planes of a level) and its tables
 constexpr int kQvBlocks = 8;      // blocks per instance of the interface-plane reductions
 constexpr int kRecSteps = 1024;   // recorded steps per instance held on the device
 
@@ -111,6 +117,7 @@ struct LevelArgs {
     T *r;
     T *sig;
     int sig_lo, sig_hi;
+    T *ealt;                         // black values between the blocked pre- and post-smoothing (or null)
 };
 
 // Transfer tables between a level and the next coarser one.
@@ -229,6 +236,10 @@ template <typename T> void launch_prolong(const Inst<T> *I, const Work &w, int l
 // paired in z (the work table counts exactly those instances' tiles)
 template <typename T> void launch_prolong_cc(const Inst<T> *I, const Work &w, int level, int cz, hipStream_t st);
 template <typename T> void launch_coarse(const Inst<T> *I, InstState *S, int ninst, int lds_bytes, hipStream_t st);
+// pre-smoothing (nu zero-start sweeps) + restriction of level `level`, and prolongation +
+// post-smoothing (nu sweeps), a block per kTbT x kTbT tile with lds_bytes of LDS
+template <typename T> void launch_pre_tb(const Inst<T> *I, const Work &w, int level, int nu, int lds_bytes, hipStream_t st);
+template <typename T> void launch_post_tb(const Inst<T> *I, const Work &w, int level, int nu, int lds_bytes, hipStream_t st);
 template <typename T> void launch_head(const Inst<T> *I, int ninst, int advance, hipStream_t st);
 template <typename T> void launch_zero_fix(const Inst<T> *I, const Work &w, hipStream_t st);
 template <typename T> void launch_run_setup(const Inst<T> *I, int ninst, int nsteps, int has_sched, double dt,

@@ -969,8 +969,8 @@ __global__ __launch_bounds__(1024) void k_reduce(const Inst<T> *I, InstState *S,
 // Neighbour sum of a red/black cell from the other colour's six values (the
 // z terms vanish on the contact planes); one expression shared by every kernel
 // that updates a cell, so that they round alike.
-template <typename T>
-__device__ __forceinline__ T rb_nb_sum(const Lv<T, 1> &L, int k, T ex0, T ex1, T ey0, T ey1, T ez0, T ez1) {
+template <typename T, int AS>
+__device__ __forceinline__ T rb_nb_sum(const Lv<T, AS> &L, int k, T ex0, T ex1, T ey0, T ey1, T ez0, T ez1) {
     const T cx = L.cxy[k];
     const T cy = L.ny > 1 ? cx : T(0);
     return cx * (ex0 + ex1) + cy * (ey0 + ey1) + (k > 0 ? L.czm[k] : T(0)) * ez0 +
@@ -1397,6 +1397,386 @@ __global__ __launch_bounds__(256) void k_prolong(const Inst<T> *I, Work w, int l
     if (X.xy == 1) prolong_column<1>(F, C, X, m, j, t.tz * kProZ);
     else if (X.xy == 2) prolong_column<2>(F, C, X, m, j, t.tz * kProZ);
     else prolong_column<0>(F, C, X, m, j, t.tz * kProZ);
+}
+
+// --------------------------------------- temporal blocking below the finest level
+// On a red/black level small enough for its launches to be latency-bound, the
+// pre-smoothing sweeps and the restriction are one launch, and so are the
+// prolongation and the post-smoothing sweeps.  A block owns a tile of kTbT x kTbT
+// columns of every plane and keeps a box of the tile plus a kTbH-cell ring of
+// e in LDS, kTbQ threads per box column (each a share of its planes).  Each
+// half-sweep over the box leaves one ring fewer valid, so nu sweeps need a ring of
+// 2 nu cells (nu <= 2 here), recomputed by every block that needs it.  Every value
+// goes through the expressions of the separate launches (the zero-start value,
+// rb_nb_sum and the division by the same divisor; the lateral and z interpolants of
+// prolong_value; the restriction's residual and sums in the same order) with the same
+// operands, so the results are theirs bit for bit.
+//   pre:  nu zero-start sweeps on e (red then black), the restriction of the
+//         red children's residuals and of sigma into the coarse level, and the
+//         tile's black values stored in ealt (the only ones the post launch reads);
+//   post: black values of ealt plus the interpolated correction, nu sweeps (the
+//         first red half-sweep reads the corrected black values, as the fused
+//         prolongation does), and both colours of the tile stored in e.
+// The post launch reads ealt around its tile while other blocks store e, so the
+// two arrays keep the launches free of races.  Every global value a thread needs
+// (its cells' r and sigma, the coarse values it interpolates, its black values) is
+// loaded at the start in one round trip; the per-plane tables go to LDS, and the
+// sweeps then touch LDS alone.
+static_assert(kTbW * kTbW == 256, "a 256-column box");
+// Q threads per box column (256 Q per block), each with ZQ cells of one colour.
+template <int Q>
+struct TbShape {
+    static constexpr int threads = Q * kTbW * kTbW;
+    static constexpr int zq = (kTbMaxNz / 2 + Q - 1) / Q;
+};
+// Threads per column: four where the registers allow (FP32); in FP64 three for the
+// pre-smoothing and two for the post-smoothing, whose half-sweeps form two cells at a
+// time, so that neither spills registers.
+template <typename T> struct TbCfg {
+    static constexpr int pre_q = sizeof(T) == 8 ? 3 : 4, post_q = sizeof(T) == 8 ? 2 : 4;
+    static constexpr int post_g = sizeof(T) == 8 ? 2 : TbShape<post_q>::zq;
+};
+
+struct TbCol {
+    int gi, gj, ring, q0;                  // global column, its ring (0 inside the tile), pair index in a plane
+    int bx, by, tx, ty;                    // box column, tile
+    int z0;                                // first colour-cell index of this thread's share of the column
+};
+
+template <int ZQ, typename V>
+__device__ __forceinline__ TbCol tb_col(const V &L, int t) {
+    const int ntx = L.nx / kTbT;
+    TbCol c;
+    c.ty = t / ntx;
+    c.tx = t - c.ty * ntx;
+    c.bx = threadIdx.x & (kTbW - 1);
+    c.by = (threadIdx.x >> 4) & (kTbW - 1);
+    c.z0 = (threadIdx.x >> 8) * ZQ;       // threads 256 q .. 256 q + 255 take share q
+    int gi = c.tx * kTbT - kTbH + c.bx, gj = c.ty * kTbT - kTbH + c.by;
+    gi += gi < 0 ? L.nx : (gi >= L.nx ? -L.nx : 0);
+    gj += gj < 0 ? L.ny : (gj >= L.ny ? -L.ny : 0);
+    c.gi = gi;
+    c.gj = gj;
+    const int rx = c.bx < kTbH ? kTbH - c.bx : (c.bx >= kTbH + kTbT ? c.bx - (kTbH + kTbT - 1) : 0);
+    const int ry = c.by < kTbH ? kTbH - c.by : (c.by >= kTbH + kTbT ? c.by - (kTbH + kTbT - 1) : 0);
+    c.ring = rx > ry ? rx : ry;
+    c.q0 = gj * (L.nx >> 1) + (gi >> 1);
+    return c;
+}
+
+// Plane of this thread's z-th cell of colour col (planes past the top are clamped: their
+// values are formed but never stored).
+__device__ __forceinline__ int tb_k(const TbCol &c, int col, int z, int nz) {
+    return min(2 * (c.z0 + z) + ((col + c.bx + c.by) & 1), nz - 1);
+}
+__device__ __forceinline__ bool tb_in(const TbCol &c, int col, int z, int nz) {
+    return 2 * (c.z0 + z) + ((col + c.bx + c.by) & 1) < nz;
+}
+__device__ __forceinline__ int tb_l(const TbCol &c, int k) { return (k * kTbW + c.by) * kTbW + c.bx; }
+
+// LDS after the box: the level's per-plane tables (cxy, czm, czp, dg), the z weights
+// and parent planes of its prolongation (pwa, pwb, pka, pkb).
+template <typename T>
+struct TbTab {
+    Lv<T, 3> L;                            // the level with its tables in LDS (no arrays)
+    const T FX_AS(3) *pwa, *pwb;
+    const int FX_AS(3) *pka, *pkb;
+};
+
+template <typename T>
+__device__ __forceinline__ TbTab<T> tb_tables(const Lv<T, 1> &L, const Xv<T> &X, T FX_AS(3) *box, int with_z) {
+    T FX_AS(3) *tab = box + L.nz * kTbW * kTbW;
+    int FX_AS(3) *itab = (int FX_AS(3) *)(tab + 6 * L.nz);
+    for (int c = threadIdx.x; c < L.nz; c += blockDim.x) {
+        tab[c] = L.cxy[c];
+        tab[L.nz + c] = L.czm[c];
+        tab[2 * L.nz + c] = L.czp[c];
+        tab[3 * L.nz + c] = L.dg[c];
+        if (with_z) {
+            tab[4 * L.nz + c] = X.pwa[c];
+            tab[5 * L.nz + c] = X.pwb[c];
+            itab[c] = X.pka[c];
+            itab[L.nz + c] = X.pkb[c];
+        }
+    }
+    TbTab<T> t;
+    t.L.nx = L.nx; t.L.ny = L.ny; t.L.nz = L.nz; t.L.rb = L.rb;
+    t.L.cxy = tab; t.L.czm = tab + L.nz; t.L.czp = tab + 2 * L.nz; t.L.dg = tab + 3 * L.nz;
+    t.L.e = nullptr; t.L.r = nullptr; t.L.sig = nullptr;
+    t.L.sig_lo = L.sig_lo; t.L.sig_hi = L.sig_hi;
+    t.pwa = tab + 4 * L.nz; t.pwb = tab + 5 * L.nz;
+    t.pka = itab; t.pkb = itab + L.nz;
+    return t;
+}
+
+// This thread's cells of colour col: right-hand sides and sigma (0 off the
+// semiconductor planes), loaded without conditions.
+template <typename T, int ZQ>
+__device__ __forceinline__ void tb_col_rs(const Lv<T, 1> &L, const TbCol &c, int col, T (&rr)[ZQ], T (&sg)[ZQ]) {
+    const int plane = L.ny * (L.nx >> 1);
+    const int half = plane * L.nz;
+    const int hsz = plane * (L.sig_hi - L.sig_lo);
+    const T FX_AS(1) *rs = L.r + (col ? half : 0);
+    const T FX_AS(1) *ss = L.sig + (col ? hsz : 0);
+#pragma unroll
+    for (int z = 0; z < ZQ; ++z) {
+        const int k = tb_k(c, col, z, L.nz);
+        const bool hs = k >= L.sig_lo && k < L.sig_hi;
+        rr[z] = rs[k * plane + c.q0];
+        const T v = ss[hs ? (k - L.sig_lo) * plane + c.q0 : 0];
+        sg[z] = hs ? v : T(0);
+    }
+}
+// The divisors, as the separate half-sweeps form them (tables in LDS hold the same values).
+template <typename T, int ZQ>
+__device__ __forceinline__ void tb_col_den(const Lv<T, 3> &Lt, const TbCol &c, int col, T (&sg)[ZQ]) {
+#pragma unroll
+    for (int z = 0; z < ZQ; ++z) {
+        const int k = tb_k(c, col, z, Lt.nz);
+        const bool hs = k >= Lt.sig_lo && k < Lt.sig_hi;
+        sg[z] = Lt.dg[k] + (hs ? sg[z] : T(0));
+    }
+}
+
+// One half-sweep of colour col over the box columns within ring R (ZI: from a zero
+// start).  The box origin is even in x and y, so a box cell's colour is the parity of
+// its box coordinates and plane, and its red/black partner (the other cell of its
+// storage pair, the stand-in operand of the zero-coefficient z terms) is box x ^ 1.
+// Cells of one colour are not neighbours, so the new values of a group of G cells are
+// formed before any of them is stored (G bounds the registers held by the operands).
+template <typename T, int ZI, int ZQ, int G = ZQ>
+__device__ __forceinline__ void tb_half(const Lv<T, 3> &Lt, const TbCol &c, T FX_AS(3) *box, int col, int R,
+                                        const T (&rr)[ZQ], const T (&den)[ZQ]) {
+    if (c.ring <= R) {
+#pragma unroll
+        for (int z0 = 0; z0 < ZQ; z0 += G) {
+            T v[G];
+#pragma unroll
+            for (int g = 0; g < G; ++g) {
+                const int z = z0 + g < ZQ ? z0 + g : ZQ - 1;
+                const int k = tb_k(c, col, z, Lt.nz);
+                const int l = tb_l(c, k);
+                T acc = 0;
+                if (!ZI) {
+                    const T ez0 = k > 0 ? box[l - kTbW * kTbW] : box[l ^ 1];
+                    const T ez1 = k < Lt.nz - 1 ? box[l + kTbW * kTbW] : box[l ^ 1];
+                    acc = rb_nb_sum(Lt, k, box[l + 1], box[l - 1], box[l + kTbW], box[l - kTbW], ez0, ez1);
+                }
+                v[g] = (rr[z] + acc) / den[z];
+            }
+#pragma unroll
+            for (int g = 0; g < G; ++g)
+                if (z0 + g < ZQ && tb_in(c, col, z0 + g, Lt.nz)) box[tb_l(c, tb_k(c, col, z0 + g, Lt.nz))] = v[g];
+        }
+    }
+    __syncthreads();
+}
+
+// Restriction of coarse cell (I, J, K) from the box (restrict_cell_rbxy's loads and
+// arithmetic; the box holds e, the tile's red cells and their black neighbours valid).
+template <typename T, typename X>
+__device__ __forceinline__ void tb_restrict_cell(const Lv<T, 1> &F, const Lv<T, 1> &C, const X &Xf, const T FX_AS(3) *box,
+                                                 int I, int J, int K, int bx0, int by0) {
+    const int ks = Xf.cks[K], cnt = Xf.ccnt[K];
+    T sg[2][2][2], rv[2][2], ev[2][2], nb[2][2][6], cx[2], czm[2], czp[2], dg[2];
+#pragma unroll
+    for (int dz = 0; dz < 2; ++dz) {
+        const int k = ks + (dz < cnt ? dz : 0);
+        const bool hs = has_sig(F, k);
+        const int km = k > 0 ? k - 1 : k, kp = k < F.nz - 1 ? k + 1 : k;
+        cx[dz] = F.cxy[k];
+        czm[dz] = F.czm[k];
+        czp[dz] = F.czp[k];
+        dg[dz] = F.dg[k];
+#pragma unroll
+        for (int dy = 0; dy < 2; ++dy) {
+            const int j = 2 * J + dy;
+#pragma unroll
+            for (int dx = 0; dx < 2; ++dx) {
+                const int i = 2 * I + dx;
+                const T FX_AS(1) *sp = hs ? F.sig + sidx(F, i, j, k) : F.r + cidx(F, i, j, k);
+                sg[dz][dy][dx] = *sp;
+            }
+            const int dxr = (dy + k) & 1;
+            const int i = 2 * I + dxr;
+            rv[dz][dy] = F.r[cidx(F, i, j, k)];
+            const int l = (k * kTbW + by0 + dy) * kTbW + bx0 + dxr;
+            ev[dz][dy] = box[l];
+            nb[dz][dy][0] = box[l + 1];
+            nb[dz][dy][1] = box[l - 1];
+            nb[dz][dy][2] = box[l + kTbW];
+            nb[dz][dy][3] = box[l - kTbW];
+            nb[dz][dy][4] = box[l + (km - k) * kTbW * kTbW];
+            nb[dz][dy][5] = box[l + (kp - k) * kTbW * kTbW];
+        }
+    }
+    double sr = 0.0, ss = 0.0;
+#pragma unroll
+    for (int dz = 0; dz < 2; ++dz) {
+        if (dz >= cnt) break;
+        const int k = ks + dz;
+        const double wz = (double)Xf.fthick[k] / (double)Xf.cthick[K];
+        const bool hs = has_sig(F, k);
+#pragma unroll
+        for (int dy = 0; dy < 2; ++dy) {
+#pragma unroll
+            for (int dx = 0; dx < 2; ++dx) {
+                const T sgc = hs ? sg[dz][dy][dx] : T(0);
+                ss += wz * (double)sgc;
+                if (dx != ((dy + k) & 1)) continue;
+                T nbs = 0;
+                nbs += cx[dz] * (nb[dz][dy][0] + nb[dz][dy][1]);
+                nbs += cx[dz] * (nb[dz][dy][2] + nb[dz][dy][3]);
+                if (k > 0) nbs += czm[dz] * nb[dz][dy][4];
+                if (k < F.nz - 1) nbs += czp[dz] * nb[dz][dy][5];
+                const T res = rv[dz][dy] - ((dg[dz] + sgc) * ev[dz][dy] - nbs);
+                sr += wz * (double)res;
+            }
+        }
+    }
+    C.r[cidx(C, I, J, K)] = (T)(sr * 0.25);
+    if (has_sig(C, K)) C.sig[sidx(C, I, J, K)] = (T)(ss * 0.25);
+}
+
+template <typename T>
+__global__ __launch_bounds__(TbShape<TbCfg<T>::pre_q>::threads) void k_pre_tb(const Inst<T> *I, Work w, int level,
+                                                                                int nu) {
+    constexpr int ZQ = TbShape<TbCfg<T>::pre_q>::zq;
+    extern __shared__ double tb_raw[];
+    const Blk b = find_block(w);
+    if (!b.ok) return;
+    const Inst<T> &a = I[b.inst];
+    const GState *st = wstate(w, b.inst);
+    if (st->done) return;
+    if (st->light) nu = 1;                         // the sweeps after the first are left out
+    const Lv<T, 1> L = gview(a.lv[level]);
+    const Xv<T> X = xview(a.xf[level]);
+    T FX_AS(3) *box = asp<3>((T *)tb_raw);
+    const TbCol c = tb_col<ZQ>(L, b.t);
+    T rr0[ZQ], den0[ZQ], rr1[ZQ], den1[ZQ];
+    tb_col_rs(L, c, 0, rr0, den0);
+    tb_col_rs(L, c, 1, rr1, den1);
+    const TbTab<T> tt = tb_tables(L, X, box, 0);
+    __syncthreads();                               // tables
+    tb_col_den(tt.L, c, 0, den0);
+    tb_col_den(tt.L, c, 1, den1);
+    tb_half<T, 1>(tt.L, c, box, 0, 2 * nu, rr0, den0);
+    tb_half<T, 0>(tt.L, c, box, 1, 2 * nu - 1, rr1, den1);
+    if (nu > 1) {
+        tb_half<T, 0>(tt.L, c, box, 0, 2, rr0, den0);
+        tb_half<T, 0>(tt.L, c, box, 1, 1, rr1, den1);
+    }
+    // the tile's black values for the post launch
+    if (c.ring == 0) {
+        const int plane = L.ny * (L.nx >> 1), half = plane * L.nz;
+        T FX_AS(1) *ealt = asp<1>(a.lv[level].ealt);
+#pragma unroll
+        for (int z = 0; z < ZQ; ++z) {
+            const int k = tb_k(c, 1, z, L.nz);
+            if (tb_in(c, 1, z, L.nz)) ealt[half + k * plane + c.q0] = box[tb_l(c, k)];
+        }
+    }
+    // restriction: kTbT/2 x kTbT/2 coarse columns of the tile, every coarse plane
+    const Lv<T, 1> C = gview(a.lv[level + 1]);
+    constexpr int kC = kTbT / 2;
+    for (int u = threadIdx.x; u < kC * kC * C.nz; u += blockDim.x) {
+        const int K = u / (kC * kC), cc = u - K * kC * kC;
+        const int cj = cc / kC, ci = cc - cj * kC;
+        tb_restrict_cell(L, C, X, box, c.tx * kC + ci, c.ty * kC + cj, K, kTbH + 2 * ci, kTbH + 2 * cj);
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(TbShape<TbCfg<T>::post_q>::threads) void k_post_tb(const Inst<T> *I, Work w, int level,
+                                                                                  int nu) {
+    constexpr int ZQ = TbShape<TbCfg<T>::post_q>::zq;
+    constexpr int G = TbCfg<T>::post_g;
+    extern __shared__ double tb_raw[];
+    const Blk b = find_block(w);
+    if (!b.ok) return;
+    const Inst<T> &a = I[b.inst];
+    const GState *st = wstate(w, b.inst);
+    if (st->done) return;
+    if (st->light) nu = 1;                         // one sweep: the fused prolongation's and the black after it
+    const Lv<T, 1> F = gview(a.lv[level]);
+    const Lv<T, 1> C = gview(a.lv[level + 1]);
+    const Xv<T> X = xview(a.xf[level]);
+    T FX_AS(3) *box = asp<3>((T *)tb_raw);
+    const TbCol c = tb_col<ZQ>(F, b.t);
+    const int plane = F.ny * (F.nx >> 1), half = plane * F.nz;
+    const bool corr = c.ring <= 2 * nu;
+    // every global load of the correction first: this thread's share of the coarse planes
+    // at its column (prolong_value's lateral operands) and its black values
+    const int Ic = c.gi >> 1, Jc = c.gj >> 1;
+    const int ix[2] = {Ic, (c.gi & 1) ? wrap_p(Ic, C.nx) : wrap_m(Ic, C.nx)};
+    const int jy[2] = {Jc, (c.gj & 1) ? wrap_p(Jc, C.ny) : wrap_m(Jc, C.ny)};
+    T cv[ZQ][2][2];
+#pragma unroll
+    for (int q = 0; q < ZQ; ++q) {
+        const int K = min(c.z0 + q, C.nz - 1);
+#pragma unroll
+        for (int yy = 0; yy < 2; ++yy)
+#pragma unroll
+            for (int xx = 0; xx < 2; ++xx) cv[q][yy][xx] = C.e[cidx(C, ix[xx], jy[yy], K)];
+    }
+    T ebv[ZQ];
+    const T FX_AS(1) *eb = asp<1>(a.lv[level].ealt) + half;
+#pragma unroll
+    for (int z = 0; z < ZQ; ++z) ebv[z] = eb[tb_k(c, 1, z, F.nz) * plane + c.q0];
+    const TbTab<T> tt = tb_tables(F, X, box, 1);
+    // the lateral interpolants, parked in the box for the z interpolation
+    if (corr) {
+        const T wx[2] = {T(0.75), T(0.25)}, wy[2] = {T(0.75), T(0.25)};
+        T wgt[2][2];
+#pragma unroll
+        for (int yy = 0; yy < 2; ++yy)
+#pragma unroll
+            for (int xx = 0; xx < 2; ++xx) wgt[yy][xx] = wx[xx] * wy[yy];
+#pragma unroll
+        for (int q = 0; q < ZQ; ++q)
+            if (c.z0 + q < C.nz) box[tb_l(c, c.z0 + q)] = lint_xy<2, 2>(wgt, cv[q]);
+    }
+    __syncthreads();                               // interpolants, tables
+    // black values with the correction: eb + lint_z of the parent and neighbour planes
+    T vb[ZQ];
+    if (corr) {
+#pragma unroll
+        for (int z = 0; z < ZQ; ++z) {
+            const int k = tb_k(c, 1, z, F.nz);
+            const int ka = tt.pka[k], kb = tt.pkb[k];
+            const T s0 = box[tb_l(c, ka)];
+            const T s1 = box[tb_l(c, kb >= 0 ? kb : ka)];
+            vb[z] = ebv[z] + lint_z(tt.pwa[k], s0, kb >= 0 ? tt.pwb[k] : T(0), s1);
+        }
+    }
+    __syncthreads();                               // interpolants read
+    if (corr) {
+#pragma unroll
+        for (int z = 0; z < ZQ; ++z)
+            if (tb_in(c, 1, z, F.nz)) box[tb_l(c, tb_k(c, 1, z, F.nz))] = vb[z];
+    }
+    // this thread's cells' r and sigma (loaded after the correction, which needs the registers)
+    T rr0[ZQ], den0[ZQ], rr1[ZQ], den1[ZQ];
+    tb_col_rs(F, c, 0, rr0, den0);
+    tb_col_rs(F, c, 1, rr1, den1);
+    tb_col_den(tt.L, c, 0, den0);
+    tb_col_den(tt.L, c, 1, den1);
+    __syncthreads();
+    tb_half<T, 0, ZQ, G>(tt.L, c, box, 0, 2 * nu - 1, rr0, den0);
+    tb_half<T, 0, ZQ, G>(tt.L, c, box, 1, 2 * nu - 2, rr1, den1);
+    if (nu > 1) {
+        tb_half<T, 0, ZQ, G>(tt.L, c, box, 0, 1, rr0, den0);
+        tb_half<T, 0, ZQ, G>(tt.L, c, box, 1, 0, rr1, den1);
+    }
+    if (c.ring == 0) {
+#pragma unroll
+        for (int col = 0; col < 2; ++col)
+#pragma unroll
+            for (int z = 0; z < ZQ; ++z) {
+                const int k = tb_k(c, col, z, F.nz);
+                if (tb_in(c, col, z, F.nz)) F.e[(col ? half : 0) + k * plane + c.q0] = box[tb_l(c, k)];
+            }
+    }
 }
 
 // --------------------------------------------- coarse levels in one workgroup
@@ -1931,6 +2311,18 @@ void launch_prolong_cc(const Inst<T> *I, const Work &w, int level, int cz, hipSt
 }
 
 template <typename T>
+void launch_pre_tb(const Inst<T> *I, const Work &w, int level, int nu, int lds_bytes, hipStream_t st) {
+    if (w.total <= 0) return;
+    hipLaunchKernelGGL(k_pre_tb<T>, grid_of(w.total), dim3(TbShape<TbCfg<T>::pre_q>::threads), lds_bytes, st, I, w,
+                       level, nu);
+}
+template <typename T>
+void launch_post_tb(const Inst<T> *I, const Work &w, int level, int nu, int lds_bytes, hipStream_t st) {
+    if (w.total <= 0) return;
+    hipLaunchKernelGGL(k_post_tb<T>, grid_of(w.total), dim3(TbShape<TbCfg<T>::post_q>::threads), lds_bytes, st, I, w,
+                       level, nu);
+}
+template <typename T>
 void launch_coarse(const Inst<T> *I, InstState *S, int ninst, int lds_bytes, hipStream_t st) {
     hipLaunchKernelGGL(k_coarse<T>, dim3(ninst), dim3(512), lds_bytes, st, I, S);
 }
@@ -1985,7 +2377,9 @@ void launch_fill(double *x, size_t n, double v, hipStream_t st) {
     template void launch_restrict<T>(const Inst<T> *, const Work &, int, hipStream_t);                       \
     template void launch_prolong<T>(const Inst<T> *, const Work &, int, hipStream_t);                        \
     template void launch_prolong_cc<T>(const Inst<T> *, const Work &, int, int, hipStream_t);                \
-    template void launch_coarse<T>(const Inst<T> *, InstState *, int, int, hipStream_t);                                  \
+    template void launch_coarse<T>(const Inst<T> *, InstState *, int, int, hipStream_t);                      \
+    template void launch_pre_tb<T>(const Inst<T> *, const Work &, int, int, int, hipStream_t);                 \
+    template void launch_post_tb<T>(const Inst<T> *, const Work &, int, int, int, hipStream_t);                                  \
     template void launch_head<T>(const Inst<T> *, int, int, hipStream_t);                                    \
     template void launch_zero_fix<T>(const Inst<T> *, const Work &, hipStream_t);                            \
     template void launch_run_setup<T>(const Inst<T> *, int, int, int, double, int, hipStream_t);             \

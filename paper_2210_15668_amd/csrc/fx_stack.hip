@@ -119,6 +119,7 @@ struct DevLevel {
     T *cxy = nullptr, *czm = nullptr, *czp = nullptr, *dg = nullptr;
     T *pwa = nullptr, *pwb = nullptr;
     int *ks = nullptr, *cnt = nullptr, *thick = nullptr, *pka = nullptr, *pkb = nullptr;
+    T *ealt = nullptr;                  // blocked smoothing's black values (levels that may use it)
 };
 
 
@@ -341,6 +342,8 @@ struct Engine {
     Work w_tdgl{}, w_ext{};
     ResWork w_res{};
     std::vector<Work> w_sm, w_rs, w_pr, w_prc;   // w_pr / w_prc: prolongation by fine or by coarse columns
+    std::vector<Work> w_tb;             // blocked smoothing: a block per tile
+    std::vector<int> tb, tb_lds;        // level smoothed in blocks; LDS bytes of its box
     std::vector<int> prc_cz;            // coarse planes per thread of w_prc, per level
     std::vector<SmoothCfg> scfg;        // smoother launch shape per level
     std::vector<int> ncol;
@@ -426,6 +429,24 @@ int coarse_layout(const Plan &p, Inst<T> *a) {
 // storage and levels of its own above the coarse kernel); else the residual kernel
 // forms it.
 bool fold_of(const Plan &p) { return p.lv[0].rb && p.lc > 0; }
+
+// LDS of a blocked level's box (every plane), its per-plane tables and z-transfer tables.
+size_t tb_lds_bytes(const HostLevel &H, size_t w) {
+    return ((size_t)H.nz * kTbW * kTbW + 6 * (size_t)H.nz) * w + 2 * (size_t)H.nz * sizeof(int);
+}
+
+// Level l of p may be smoothed in blocks (k_pre_tb / k_post_tb): a red/black level
+// below the finest with launches of its own, small enough for its launches to be
+// latency-bound (the blocks recompute their rings), halved in x and y into the next,
+// tiles that divide both extents, no column twice in one box (extents of at least a
+// box edge), at most kTbMaxNz planes, and the box in kTbLdsBytes of LDS.
+bool tb_geom(const Plan &p, int l, size_t w) {
+    if (l < 1 || l >= p.lc) return false;
+    const HostLevel &H = p.lv[l];
+    return H.rb && p.lv[l + 1].xy_from_finer == 1 && H.ncell() < ((size_t)1 << 18) && H.nx % kTbT == 0 &&
+           H.ny % kTbT == 0 && H.nx >= kTbW && H.ny >= kTbW && H.nz <= kTbMaxNz &&
+           tb_lds_bytes(H, w) <= (size_t)kTbLdsBytes;
+}
 
 int tiles_smooth(const HostLevel &H, const SmoothCfg &c) { return tiles_cfg(H.rb ? H.nx / 2 : H.nx, H.ny, H.nz, c); }
 
@@ -518,6 +539,12 @@ size_t carve(Engine *e, void *ws) {
         for (int l = 0; l < nlev; ++l) {
             if (mixed) lay(h.L32[l], p.lv[l], 4);
             else lay(h.L64[l], p.lv[l], 8);
+            const size_t w = mixed ? 4 : 8;
+            if (tb_geom(p, l, w)) {
+                void *ea = cv.take(p.lv[l].ncell() * w);
+                if (mixed) h.L32[l].ealt = (float *)ea;
+                else h.L64[l].ealt = (double *)ea;
+            }
         }
         // residual partial sums: one pair per residual tile
         const size_t nres = (size_t)tiles3(p.nx, p.ny, (p.nzd + kResZ - 1) / kResZ);
@@ -528,7 +555,7 @@ size_t carve(Engine *e, void *ws) {
     const size_t inst_bytes = mixed ? sizeof(Inst<float>) : sizeof(Inst<double>);
     e->inst_dev = cv.take((size_t)e->n * inst_bytes);
     e->st_dev = (InstState *)cv.take((size_t)e->n * sizeof(InstState));
-    const size_t ntab = 4 + 4 * (size_t)e->max_lc;
+    const size_t ntab = 4 + 5 * (size_t)e->max_lc;
     e->prefix_dev = (int *)cv.take(ntab * (e->n + 1) * sizeof(int));
     e->sched_dev = (double *)cv.take((size_t)e->n * kSchedChunk * sizeof(double));
     e->probe_dev = (double *)cv.take(kProbeMax * sizeof(double));
@@ -568,6 +595,7 @@ fx_status build_work(Engine *e) {
     e->w_res.cell0 = mk([&](const InstHost &h) { const Plan &p = h.plan; return tiles3(p.nx, p.ny, nzc(p)); });
     e->w_res.cell2 = mk([&](const InstHost &h) { const Plan &p = h.plan; return fold_of(p) ? 0 : tiles3(p.nx, p.ny, nzc(p)); });
     e->w_sm.clear(); e->w_rs.clear(); e->w_pr.clear(); e->w_prc.clear(); e->prc_cz.clear();
+    e->w_tb.clear(); e->tb.clear(); e->tb_lds.clear();
     const int cc_ok = env_int("FERROX_PROLONG_CC", 1) != 0;
     // the coarse-column prolongation: red/black fine level, x and y halved, z paired
     auto by_cc = [cc_ok](const Plan &p, int l) {
@@ -598,6 +626,23 @@ fx_status build_work(Engine *e) {
             if (l >= h.plan.lc || !by_cc(h.plan, l)) return 0;
             const HostLevel &C = h.plan.lv[l + 1];
             return tiles3(C.nx, C.ny, (C.nz + cz - 1) / cz);
+        }));
+        // blocked smoothing where every instance that has this level qualifies
+        const size_t w = e->prec == FX_PREC_MIXED ? 4 : 8;
+        bool ok = e->fuse && env_int("FERROX_TB", 1) != 0 && e->nu1c <= 2 && e->nu2c <= 2;
+        bool any = false;
+        int lds = 0;
+        for (const InstHost &h : e->in) {
+            if (l >= h.plan.lc) continue;
+            any = true;
+            ok = ok && tb_geom(h.plan, l, w);
+            lds = std::max(lds, (int)tb_lds_bytes(h.plan.lv[l], w));
+        }
+        e->tb.push_back(ok && any);
+        e->tb_lds.push_back(lds);
+        e->w_tb.push_back(mk([&](const InstHost &h) {
+            if (!e->tb[l] || l >= h.plan.lc) return 0;
+            return (h.plan.lv[l].nx / kTbT) * (h.plan.lv[l].ny / kTbT);
         }));
     }
     if (bad) return fail(FX_EINVAL, "a launch would exceed 2^30 tiles");
@@ -702,6 +747,7 @@ Inst<T> make_inst(const Engine *e, int i) {
         L.cxy = D[l].cxy; L.czm = D[l].czm; L.czp = D[l].czp; L.dg = D[l].dg;
         L.e = D[l].e; L.r = D[l].r; L.sig = D[l].sig;
         L.sig_lo = H.sig_lo; L.sig_hi = H.sig_hi;
+        L.ealt = D[l].ealt;
         if (l + 1 < a.nlev) {
             XferArgs<T> &X = a.xf[l];
             X.cks = D[l + 1].ks; X.ccnt = D[l + 1].cnt;
@@ -838,6 +884,10 @@ template <typename T>
 void enq_vcycle(Engine *e) {
     const Inst<T> *I = idev<T>(e);
     for (int l = 0; l < e->max_lc; ++l) {
+        if (e->tb[l]) {                                  // sweeps and restriction in blocks
+            launch_pre_tb(I, e->w_tb[l], l, e->nu1c, e->tb_lds[l], e->st);
+            continue;
+        }
         const int nu1 = l == 0 ? e->nu1 : e->nu1c;
         // below the finest level (whose launches the probe times one by one) the
         // zero-start red and black half-sweeps of a red/black level are one launch
@@ -854,6 +904,10 @@ void enq_vcycle(Engine *e) {
     }
     launch_coarse(I, e->st_dev, e->n, e->lds_max, e->st);
     for (int l = e->max_lc - 1; l >= 0; --l) {
+        if (e->tb[l]) {                                  // prolongation and sweeps in blocks
+            launch_post_tb(I, e->w_tb[l], l, e->nu2c, e->tb_lds[l], e->st);
+            continue;
+        }
         const int nu2 = l == 0 ? e->nu2 : e->nu2c;
         // on a small red/black level the correction is formed inside the first
         // red half-sweep: one launch fewer, where launches cost more than the
