@@ -1423,6 +1423,7 @@ __global__ __launch_bounds__(256) void k_prolong(const Inst<T> *I, Work w, int l
 // loaded at the start in one round trip; the per-plane tables go to LDS, and the
 // sweeps then touch LDS alone.
 static_assert(kTbW * kTbW == 256, "a 256-column box");
+constexpr int kTbCW = kTbW / 2 + 2;           // coarse columns under a box, with the interpolation's neighbours
 // Q threads per box column (256 Q per block), each with ZQ cells of one colour.
 template <int Q>
 struct TbShape {
@@ -1705,26 +1706,29 @@ __global__ __launch_bounds__(TbShape<TbCfg<T>::post_q>::threads) void k_post_tb(
     const TbCol c = tb_col<ZQ>(F, b.t);
     const int plane = F.ny * (F.nx >> 1), half = plane * F.nz;
     const bool corr = c.ring <= 2 * nu;
-    // every global load of the correction first: this thread's share of the coarse planes
-    // at its column (prolong_value's lateral operands) and its black values
-    const int Ic = c.gi >> 1, Jc = c.gj >> 1;
-    const int ix[2] = {Ic, (c.gi & 1) ? wrap_p(Ic, C.nx) : wrap_m(Ic, C.nx)};
-    const int jy[2] = {Jc, (c.gj & 1) ? wrap_p(Jc, C.ny) : wrap_m(Jc, C.ny)};
-    T cv[ZQ][2][2];
-#pragma unroll
-    for (int q = 0; q < ZQ; ++q) {
-        const int K = min(c.z0 + q, C.nz - 1);
-#pragma unroll
-        for (int yy = 0; yy < 2; ++yy)
-#pragma unroll
-            for (int xx = 0; xx < 2; ++xx) cv[q][yy][xx] = C.e[cidx(C, ix[xx], jy[yy], K)];
+    // The coarse values under the box (kTbCW x kTbCW coarse columns, every coarse plane),
+    // one load each, into the box's planes above those the interpolants take; then this
+    // thread's black values.  Box column bx lies over coarse box column
+    // (tile x - kTbH + bx) / 2 - (tile x kTbT/2 - kTbH/2 - 1), its x neighbour one further
+    // on the side of its parity, as prolong_value takes them (wrapping included).
+    T FX_AS(3) *cb = box + C.nz * kTbW * kTbW;
+    const int cx0 = c.tx * (kTbT / 2) - kTbH / 2 - 1, cy0 = c.ty * (kTbT / 2) - kTbH / 2 - 1;
+    for (int u = threadIdx.x; u < kTbCW * kTbCW * C.nz; u += blockDim.x) {
+        const int K = u / (kTbCW * kTbCW), rem = u - K * kTbCW * kTbCW;
+        const int cj = rem / kTbCW, ci = rem - cj * kTbCW;
+        int I = cx0 + ci, J = cy0 + cj;
+        I += I < 0 ? C.nx : (I >= C.nx ? -C.nx : 0);
+        J += J < 0 ? C.ny : (J >= C.ny ? -C.ny : 0);
+        cb[u] = C.e[cidx(C, I, J, K)];
     }
     T ebv[ZQ];
     const T FX_AS(1) *eb = asp<1>(a.lv[level].ealt) + half;
 #pragma unroll
     for (int z = 0; z < ZQ; ++z) ebv[z] = eb[tb_k(c, 1, z, F.nz) * plane + c.q0];
     const TbTab<T> tt = tb_tables(F, X, box, 1);
-    // the lateral interpolants, parked in the box for the z interpolation
+    __syncthreads();                               // coarse values, tables
+    // the lateral interpolants (prolong_value's weights and operands), parked in the box
+    // for the z interpolation
     if (corr) {
         const T wx[2] = {T(0.75), T(0.25)}, wy[2] = {T(0.75), T(0.25)};
         T wgt[2][2];
@@ -1732,11 +1736,25 @@ __global__ __launch_bounds__(TbShape<TbCfg<T>::post_q>::threads) void k_post_tb(
         for (int yy = 0; yy < 2; ++yy)
 #pragma unroll
             for (int xx = 0; xx < 2; ++xx) wgt[yy][xx] = wx[xx] * wy[yy];
+        const int gu = c.tx * kTbT - kTbH + c.bx, gv = c.ty * kTbT - kTbH + c.by;   // unwrapped
+        const int ci[2] = {(gu >> 1) - cx0, (gu >> 1) - cx0 + ((gu & 1) ? 1 : -1)};
+        const int cj[2] = {(gv >> 1) - cy0, (gv >> 1) - cy0 + ((gv & 1) ? 1 : -1)};
+        T sv[ZQ];
+#pragma unroll
+        for (int q = 0; q < ZQ; ++q) {
+            const int K = min(c.z0 + q, C.nz - 1);
+            T v[2][2];
+#pragma unroll
+            for (int yy = 0; yy < 2; ++yy)
+#pragma unroll
+                for (int xx = 0; xx < 2; ++xx) v[yy][xx] = cb[(K * kTbCW + cj[yy]) * kTbCW + ci[xx]];
+            sv[q] = lint_xy<2, 2>(wgt, v);
+        }
 #pragma unroll
         for (int q = 0; q < ZQ; ++q)
-            if (c.z0 + q < C.nz) box[tb_l(c, c.z0 + q)] = lint_xy<2, 2>(wgt, cv[q]);
+            if (c.z0 + q < C.nz) box[tb_l(c, c.z0 + q)] = sv[q];
     }
-    __syncthreads();                               // interpolants, tables
+    __syncthreads();                               // interpolants
     // black values with the correction: eb + lint_z of the parent and neighbour planes
     T vb[ZQ];
     if (corr) {

@@ -445,7 +445,9 @@ bool tb_geom(const Plan &p, int l, size_t w) {
     const HostLevel &H = p.lv[l];
     return H.rb && p.lv[l + 1].xy_from_finer == 1 && H.ncell() < ((size_t)1 << 18) && H.nx % kTbT == 0 &&
            H.ny % kTbT == 0 && H.nx >= kTbW && H.ny >= kTbW && H.nz <= kTbMaxNz &&
-           tb_lds_bytes(H, w) <= (size_t)kTbLdsBytes;
+           tb_lds_bytes(H, w) <= (size_t)kTbLdsBytes &&
+           // the coarse values under a box fit above the interpolants (k_post_tb)
+           (size_t)p.lv[l + 1].nz * (kTbW * kTbW + (kTbW / 2 + 2) * (kTbW / 2 + 2)) <= (size_t)H.nz * kTbW * kTbW;
 }
 
 int tiles_smooth(const HostLevel &H, const SmoothCfg &c) { return tiles_cfg(H.rb ? H.nx / 2 : H.nx, H.ny, H.nz, c); }
