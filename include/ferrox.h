@@ -318,6 +318,15 @@ fx_status stack_tune_config(const fx_stack *s, int level, int *tile_x, int *zt, 
 int stack_num_levels(const fx_stack *s);
 fx_status stack_level_shape(const fx_stack *s, int level, int *nx, int *ny, int *nz);
 
+/* How level l is smoothed (for diagnostics; the arithmetic, and so the result, is the
+ * same in every mode): FX_LEVEL_LAUNCHES, a launch per half-sweep and per transfer
+ * (some pairs fused); FX_LEVEL_BLOCKED, the pre-smoothing sweeps with the restriction
+ * and the prolongation with the post-smoothing sweeps each one launch, over LDS tiles
+ * that recompute a ring of neighbour cells; FX_LEVEL_COARSE, inside the one-workgroup
+ * coarse kernel.  FX_EINVAL for a bad handle or level. */
+enum { FX_LEVEL_LAUNCHES = 0, FX_LEVEL_BLOCKED = 1, FX_LEVEL_COARSE = 2 };
+fx_status stack_level_mode(const fx_stack *s, int level, int *mode);
+
 /* Release the stack handle (not the caller's device buffers). */
 fx_status destroy_stack(fx_stack *s);
 

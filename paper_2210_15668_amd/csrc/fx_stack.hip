@@ -1892,6 +1892,15 @@ fx_status stack_level_shape(const fx_stack *s, int level, int *nx, int *ny, int 
     return FX_OK;
 }
 
+fx_status stack_level_mode(const fx_stack *s, int level, int *mode) {
+    if (!s || !mode || level < 0 || level >= (int)s->e.in[0].plan.lv.size()) return fail(FX_EINVAL, "bad level");
+    const Engine &e = s->e;
+    if (level >= e.in[0].plan.lc) *mode = FX_LEVEL_COARSE;
+    else if (level < (int)e.tb.size() && e.tb[level]) *mode = FX_LEVEL_BLOCKED;
+    else *mode = FX_LEVEL_LAUNCHES;
+    return FX_OK;
+}
+
 fx_status destroy_stack(fx_stack *s) {
     if (!s) return FX_OK;
     engine_release(&s->e);

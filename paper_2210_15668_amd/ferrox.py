@@ -21,6 +21,7 @@ LIB_PATH = os.path.join(_HERE, "libferrox.so")
 FX_OK, FX_EINVAL, FX_ENOMEM, FX_EDEVICE, FX_ENOCONV, FX_ENONFINITE, FX_ESTATE = range(7)
 FIELD_P, FIELD_PHI, FIELD_PHI_PREV, FIELD_PHI_PREV2, FIELD_PHI_PREV3 = 0, 1, 2, 3, 4
 PROBE_OFF, PROBE_SMOOTH_FINE = 0, 1
+LEVEL_LAUNCHES, LEVEL_BLOCKED, LEVEL_COARSE = 0, 1, 2
 LAUNCH_STREAM, LAUNCH_GRAPH = 0, 1
 TUNE_FORCE = 1
 _STATUS = {0: "FX_OK", 1: "FX_EINVAL", 2: "FX_ENOMEM", 3: "FX_EDEVICE", 4: "FX_ENOCONV",
@@ -90,6 +91,7 @@ SIGNATURES = [
     ("stack_probe_read", ctypes.c_int, [_vp, _dp, _ip, _dp]),
     ("stack_num_levels", ctypes.c_int, [_vp]),
     ("stack_level_shape", ctypes.c_int, [_vp, ctypes.c_int, _ip, _ip, _ip]),
+    ("stack_level_mode", ctypes.c_int, [_vp, ctypes.c_int, _ip]),
     ("destroy_stack", ctypes.c_int, [_vp]),
     ("stack_set_launch", ctypes.c_int, [_vp, ctypes.c_int]),
     ("stack_autotune", ctypes.c_int, [_vp, ctypes.c_char_p, ctypes.c_int, ctypes.POINTER(TuneInfo)]),
@@ -341,6 +343,15 @@ class Stack:
             a, b, c = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
             _check(lib().stack_level_shape(self._h, l, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)))
             out.append((a.value, b.value, c.value))
+        return out
+
+    def level_modes(self):
+        """Per level: LEVEL_LAUNCHES, LEVEL_BLOCKED or LEVEL_COARSE (how it is smoothed)."""
+        out = []
+        for l in range(lib().stack_num_levels(self._h)):
+            m = ctypes.c_int()
+            _check(lib().stack_level_mode(self._h, l, ctypes.byref(m)))
+            out.append(m.value)
         return out
 
     def guard_intact(self) -> bool:

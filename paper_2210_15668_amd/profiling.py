@@ -22,6 +22,16 @@ held-out state of the 128x128x64 MFISM stack):
 
   rocprofv3 --kernel-trace --stats -d OUT/unet -o run -- python3 -m paper_2210_15668_amd.profiling unet 20
   python3 -m paper_2210_15668_amd.profiling unet_layers OUT/unet
+
+The V-cycle with and without the blocked smoothing of the small levels (FERROX_TB; the
+same arithmetic either way): `steps N` runs Step 0, 10 untimed steps and N timed steps of
+the 256x256x128 MFISM stack (FP64, or mixed with a second argument `mixed`) and prints
+steps/s; `per_step OUT N` sums a kernel trace per time step (N steps in the trace):
+
+  FERROX_TB=0 rocprofv3 --kernel-trace -d OUT/tb0 -o run -- python3 -m paper_2210_15668_amd.profiling steps 110
+  FERROX_TB=1 rocprofv3 --kernel-trace -d OUT/tb1 -o run -- python3 -m paper_2210_15668_amd.profiling steps 110
+  python3 -m paper_2210_15668_amd.profiling per_step OUT/tb0 120
+  python3 -m paper_2210_15668_amd.profiling per_step OUT/tb1 120
 """
 from __future__ import annotations
 
@@ -213,6 +223,46 @@ def unet_layers(trace_dir):
           f"({tot_fl / tot_us / 1e6 / 2500:.3f} of 2.5 PFLOP/s) |")
 
 
+def steps(n, prec_name="fp64"):
+    import time
+    import torch
+    from paper_2210_15668_amd import ferrox
+    from paper_2210_15668_amd import workloads as W
+    prec = W.PREC_MIXED if prec_name == "mixed" else W.PREC_FP64
+    spec = W.mfism_large(prec)
+    s = ferrox.Stack(spec, W.random_P(spec, 2), device="cuda:0")
+    s.run_steps(10, W.DT)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    info = s.run_steps(n, W.DT)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    modes = s.levels(), s.level_modes()
+    s.close()
+    print(json.dumps({"prec": prec_name, "steps": n, "steps_per_s": n / (t1 - t0),
+                      "vcycles_per_step": info.total_cycles / n, "levels": modes[0], "level_modes": modes[1]}),
+          flush=True)
+
+
+def per_step(trace_dir, n):
+    """Kernel time per time step: launches, summed durations and the span from the first
+    start to the last end, and the kernels with the largest share."""
+    db = _db(trace_dir)
+    rows = db.execute("select name, grid_x, duration, start, end from kernels order by start").fetchall()
+    agg = defaultdict(lambda: [0, 0.0])
+    for name, gx, d, _, _ in rows:
+        agg[(_short(name), gx)][0] += 1
+        agg[(_short(name), gx)][1] += d
+    tot = sum(v[1] for v in agg.values())
+    span = rows[-1][4] - rows[0][3]
+    print(f"{len(rows) / n:.1f} launches, {tot / 1e3 / n:.1f} us of kernel time and {span / 1e3 / n:.1f} us of span "
+          f"per time step ({n} steps in the trace)\n")
+    print("| kernel | grid (threads) | calls per step | avg us | us per step |")
+    print("|---|---|---|---|---|")
+    for (k, gx), (c, t) in sorted(agg.items(), key=lambda x: -x[1][1])[:24]:
+        print(f"| `{k}` | {gx} | {c / n:.2f} | {t / c / 1e3:.2f} | {t / 1e3 / n:.1f} |")
+
+
 if __name__ == "__main__":
     cmd = sys.argv[1] if len(sys.argv) > 1 else ""
     if cmd == "copy":
@@ -225,6 +275,10 @@ if __name__ == "__main__":
         unet(int(sys.argv[2]) if len(sys.argv) > 2 else 20)
     elif cmd == "unet_layers":
         unet_layers(sys.argv[2])
+    elif cmd == "steps":
+        steps(int(sys.argv[2]), sys.argv[3] if len(sys.argv) > 3 else "fp64")
+    elif cmd == "per_step":
+        per_step(sys.argv[2], float(sys.argv[3]))
     else:
         print(__doc__)
         sys.exit(1)

@@ -1,8 +1,10 @@
 """Solver choices that must not change results.  The fused launches below the finest level
-(the zero-start red/black pair and, on small levels, the prolongation formed inside the
-first red half-sweep) reproduce the separate launches bit for bit (FERROX_FUSE=0 keeps every
-half-sweep and prolongation a launch of its own), for single stacks in both precisions and
-for a batch, and the fused stack meets the oracle's 1e-10 parity bar.  Light cycles and
+(the zero-start red/black pair; on small levels the prolongation formed inside the first
+red half-sweep; on small red/black levels the blocked smoothing, where the pre-smoothing
+sweeps with the restriction and the prolongation with the post-smoothing sweeps are one
+launch each over LDS tiles) reproduce the separate launches bit for bit (FERROX_FUSE=0
+keeps every half-sweep and transfer a launch of its own), for single stacks in both
+precisions and for a batch, and the fused stack meets the oracle's 1e-10 parity bar.  Light cycles and
 either coarsening stop (8 or 64 bottom cells) change the cycles, not the root."""
 import sys
 
@@ -33,9 +35,11 @@ def fx():
     return ferrox
 
 
-def run_stack(fx, monkeypatch, fuse, spec, P0, n):
+def run_stack(fx, monkeypatch, fuse, spec, P0, n, modes=None):
     monkeypatch.setenv("FERROX_FUSE", fuse)
     s = fx.Stack(spec, P0)
+    if modes is not None:
+        modes.extend(s.level_modes())
     info = s.run_steps(n, W.DT)
     out = s.get(fx.FIELD_P), s.get(fx.FIELD_PHI), info.total_cycles
     s.close()
@@ -49,10 +53,12 @@ def test_fused_equals_separate_launches_on_a_stack(fx, orc, monkeypatch, prec):
     P0 = W.random_P(spec, 90, amp=0.05)
     n = 6
     say(f"  prec {prec}: fused ...")
-    Pf, phif, cf = run_stack(fx, monkeypatch, "1", spec, P0, n)
+    mf, ms = [], []
+    Pf, phif, cf = run_stack(fx, monkeypatch, "1", spec, P0, n, mf)
     say(f"  prec {prec}: separate ...")
-    Ps, phis, cs = run_stack(fx, monkeypatch, "0", spec, P0, n)
-    say(f"  V-cycles fused {cf} separate {cs}")
+    Ps, phis, cs = run_stack(fx, monkeypatch, "0", spec, P0, n, ms)
+    say(f"  V-cycles fused {cf} separate {cs}; level modes fused {mf} separate {ms}")
+    assert fx.LEVEL_BLOCKED in mf and fx.LEVEL_BLOCKED not in ms
     assert cf == cs
     assert np.array_equal(Pf, Ps) and np.array_equal(phif, phis)
     if prec == W.PREC_FP64:
@@ -78,6 +84,33 @@ def test_fused_equals_separate_launches_in_a_batch(fx, monkeypatch):
         b.close()
     for q in range(len(specs)):
         assert np.array_equal(out["1"][q][0], out["0"][q][0]) and np.array_equal(out["1"][q][1], out["0"][q][1]), q
+
+
+@pytest.mark.parametrize("prec", [W.PREC_FP64, W.PREC_MIXED])
+@pytest.mark.parametrize("nu", ["1", "2"])
+def test_blocked_smoothing_equals_launches(fx, monkeypatch, prec, nu):
+    """The blocked smoothing (FERROX_TB=1, the default) against the same levels launched
+    half-sweep by half-sweep with every other fusion kept (FERROX_TB=0): the same bits, with
+    one or two sweeps before and after the coarse correction on the levels below the finest
+    (nu), light cycles included.  The 128 x 128 x 64 MFIM of the ramp (a 48-plane device
+    slab) runs its levels 64 x 64 x 24 and 32 x 32 x 12 blocked."""
+    monkeypatch.setenv("FERROX_NU1C", nu)
+    monkeypatch.setenv("FERROX_NU2C", nu)
+    spec = W.mfim_ramp().copy(tol_rel=1e-12, prec=prec, v_top=1.0)
+    P0 = W.random_P(spec, 95, amp=0.05)
+    n = 6
+    out = {}
+    for tb in ("1", "0"):
+        monkeypatch.setenv("FERROX_TB", tb)
+        s = fx.Stack(spec, P0)
+        modes = s.level_modes()
+        info = s.run_steps(n, W.DT)
+        out[tb] = (s.get(fx.FIELD_P), s.get(fx.FIELD_PHI), info.total_cycles, modes)
+        s.close()
+    say(f"  prec {prec} nu {nu}: level modes {out['1'][3]} / {out['0'][3]}, V-cycles {out['1'][2]} / {out['0'][2]}")
+    assert out["1"][3].count(fx.LEVEL_BLOCKED) >= 2 and fx.LEVEL_BLOCKED not in out["0"][3]
+    assert out["1"][2] == out["0"][2]
+    assert np.array_equal(out["1"][0], out["0"][0]) and np.array_equal(out["1"][1], out["0"][1])
 
 
 @pytest.mark.parametrize("prec", [W.PREC_FP64, W.PREC_MIXED])
