@@ -1826,13 +1826,38 @@ __device__ void smooth_color(const V &L, int color, int zero_init) {
     using T = typename V::value_type;
     const int st = (int)blockDim.x;
     if (L.rb) {
+        // gs_cell on split storage with the indices written out: the cell's pair q, its
+        // x neighbours at the pairs of i +- 1 in its row, the others at pair q of the
+        // neighbouring row or plane (the other colour's array throughout); the sum in
+        // nb_sum's order, the divisor as diag_of forms it
         const int hx = L.nx >> 1;
-        const int n = hx * L.ny * L.nz;
+        const int plane = hx * L.ny;
+        const int n = plane * L.nz;
+        const int hsz = plane * (L.sig_hi - L.sig_lo);
+        T FX_AS(3) *es = L.e + (color ? n : 0);
+        const T FX_AS(3) *eo = L.e + (color ? 0 : n);
+        const T FX_AS(3) *rs = L.r + (color ? n : 0);
+        const T FX_AS(3) *ss = L.sig + (color ? hsz : 0);
         const Split3 sp{fdiv_of(hx), fdiv_of(L.ny)};
         for (int q = threadIdx.x; q < n; q += st) {
             int m, j, k;
             split_c(q, sp, m, j, k);
-            gs_cell(L, 2 * m + ((color + j + k) & 1), j, k, zero_init);
+            T d = L.dg[k];
+            if (k >= L.sig_lo && k < L.sig_hi) d += ss[q - L.sig_lo * plane];
+            if (zero_init) {
+                es[q] = rs[q] / d;
+                continue;
+            }
+            const int i = 2 * m + ((color + j + k) & 1);
+            const int row = q - m;
+            const int ip = i + 1 == L.nx ? 0 : i + 1, im = i == 0 ? L.nx - 1 : i - 1;
+            T s = 0;
+            const T cx = L.cxy[k];
+            s += cx * (eo[row + (ip >> 1)] + eo[row + (im >> 1)]);
+            if (L.ny > 1) s += cx * (eo[q + (wrap_p(j, L.ny) - j) * hx] + eo[q + (wrap_m(j, L.ny) - j) * hx]);
+            if (k > 0) s += L.czm[k] * eo[q - plane];
+            if (k < L.nz - 1) s += L.czp[k] * eo[q + plane];
+            es[q] = (rs[q] + s) / d;
         }
     } else {
         const int n = L.nx * L.ny * L.nz;
@@ -2009,10 +2034,12 @@ __device__ void bottom_cg(const Lv<T, 3> &B, T FX_AS(3) *p, T FX_AS(3) *q, doubl
     }
 }
 
+constexpr int kCoarseThreads = 1024;
+
 // A block per instance: the V-cycle from level lc down to the coarsest with
 // every level's e, r, sigma and coefficient tables resident in LDS.
 template <typename T>
-__global__ __launch_bounds__(512) void k_coarse(const Inst<T> *I, InstState *S) {
+__global__ __launch_bounds__(kCoarseThreads) void k_coarse(const Inst<T> *I, InstState *S) {
     extern __shared__ double lds_raw[];
     const Inst<T> &A = I[blockIdx.x];
     const GState *sta = asp<1>(S + blockIdx.x);
@@ -2342,7 +2369,7 @@ void launch_post_tb(const Inst<T> *I, const Work &w, int level, int nu, int lds_
 }
 template <typename T>
 void launch_coarse(const Inst<T> *I, InstState *S, int ninst, int lds_bytes, hipStream_t st) {
-    hipLaunchKernelGGL(k_coarse<T>, dim3(ninst), dim3(512), lds_bytes, st, I, S);
+    hipLaunchKernelGGL(k_coarse<T>, dim3(ninst), dim3(kCoarseThreads), lds_bytes, st, I, S);
 }
 
 template <typename T>
