@@ -113,6 +113,18 @@ __device__ __forceinline__ T3 split3(int t, int nxw, int ny) {
     return r;
 }
 
+// The same tiles in z-fastest order (nzt tiles per column): consecutive tiles of one
+// column share their halo planes, which the next tile then finds in L2.
+__device__ __forceinline__ T3 split3z(int t, int nxw, int nzt) {
+    const int ntx = (nxw + BX - 1) / BX;
+    T3 r;
+    r.tz = t % nzt;
+    const int q = t / nzt;
+    r.tx = q % ntx;
+    r.ty = q / ntx;
+    return r;
+}
+
 // Tile of 2^lbx x 2^(8-lbx) threads (a 256-thread block, x fastest); the
 // smoother's tile shape is chosen per level at run time.
 __device__ __forceinline__ T3 split3r(int t, int nxw, int ny, int lbx) {
@@ -916,15 +928,19 @@ __global__ __launch_bounds__(256) void k_residual(const Inst<T> *I, Work w, int 
     const GState *s = wstate(w, b.inst);
     if (after_cycle ? s->done != 0 : !s->fresh) return;
     if ((MODE == 2) != (after_cycle && !a.fold)) return;
-    const T3 t = split3(b.t, a.nx, a.ny);
+    // tiles walk each column up in z (halo planes shared through L2); the partial sums
+    // keep the x-fastest tile index, so the reduction's order does not depend on it
+    const int nzt = (a.nzd + kResZ - 1) / kResZ;
+    const T3 t = split3z(b.t, a.nx, nzt);
+    const int tl = t.tx + ((a.nx + BX - 1) / BX) * (t.ty + ((a.ny + BY - 1) / BY) * t.tz);
     double rr = 0.0, ff = 0.0;
     residual_body<T, MODE>(a, s, t, after_cycle, rr, ff);
     const double sr = block_sum(rr, lds_r);
     const double sf = block_sum(ff, lds_f);
     if (threadIdx.x == 0 && threadIdx.y == 0) {
         double FX_AS(1) *part = asp<1>(a.part);
-        part[2 * b.t] = sr;
-        part[2 * b.t + 1] = sf;
+        part[2 * tl] = sr;
+        part[2 * tl + 1] = sf;
     }
 }
 

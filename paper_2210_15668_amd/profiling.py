@@ -32,6 +32,14 @@ steps/s; `per_step OUT N` sums a kernel trace per time step (N steps in the trac
   FERROX_TB=1 rocprofv3 --kernel-trace -d OUT/tb1 -o run -- python3 -m paper_2210_15668_amd.profiling steps 110
   python3 -m paper_2210_15668_amd.profiling per_step OUT/tb0 120
   python3 -m paper_2210_15668_amd.profiling per_step OUT/tb1 120
+
+Measured HBM bytes and instruction counts per launch of every kernel of a time step
+(FETCH_SIZE / WRITE_SIZE calibrated by the copy runs above, in OUT/cfetch and OUT/cwrite):
+
+  rocprofv3 --pmc FETCH_SIZE -d OUT/kfetch -o run -- python3 -m paper_2210_15668_amd.profiling steps 30
+  rocprofv3 --pmc WRITE_SIZE -d OUT/kwrite -o run -- python3 -m paper_2210_15668_amd.profiling steps 30
+  rocprofv3 --pmc SQ_WAVES SQ_INSTS_VALU SQ_INSTS_VALU_ADD_F64 SQ_INSTS_VALU_MUL_F64 SQ_INSTS_VALU_FMA_F64 -d OUT/ksq -o run -- python3 -m paper_2210_15668_amd.profiling steps 20
+  python3 -m paper_2210_15668_amd.profiling kernels OUT
 """
 from __future__ import annotations
 
@@ -223,6 +231,34 @@ def unet_layers(trace_dir):
           f"({tot_fl / tot_us / 1e6 / 2500:.3f} of 2.5 PFLOP/s) |")
 
 
+def kernels(base):
+    """Per kernel (name, grid), medians over its dispatches: calibrated HBM bytes fetched
+    and written, and VALU instructions per wave (all, and FP64 add/mul/fma)."""
+    cf = _counter(os.path.join(base, "cfetch"), "FETCH_SIZE")
+    cw = _counter(os.path.join(base, "cwrite"), "WRITE_SIZE")
+    f_fetch = max(max(v) for v in cf.values()) * 1024.0 / COPY_BYTES
+    f_write = max(max(v) for v in cw.values()) * 1024.0 / COPY_BYTES
+    fe = _counter(os.path.join(base, "kfetch"), "FETCH_SIZE")
+    wr = _counter(os.path.join(base, "kwrite"), "WRITE_SIZE")
+    sq = {c: _counter(os.path.join(base, "ksq"), c) for c in
+          ("SQ_WAVES", "SQ_INSTS_VALU", "SQ_INSTS_VALU_ADD_F64", "SQ_INSTS_VALU_MUL_F64", "SQ_INSTS_VALU_FMA_F64")}
+    med = lambda v: sorted(v)[len(v) // 2] if v else 0.0
+    rows = []
+    for k, v in fe.items():
+        f = med(v) * 1024.0 / f_fetch
+        w = med(wr.get(k, [])) * 1024.0 / f_write
+        rows.append((k, len(v), f, w))
+    print(f"Calibration: a 1 GiB copy reads FETCH_SIZE x {f_fetch:.3f} and WRITE_SIZE x {f_write:.3f} of its bytes.\n")
+    print("| kernel | grid | dispatches | fetch MB | write MB | VALU instr. per wave | FP64 add+mul+fma per wave |")
+    print("|---|---|---|---|---|---|---|")
+    for k, n, f, w in sorted(rows, key=lambda r: -(r[2] + r[3]) * r[1])[:16]:
+        waves = med(sq["SQ_WAVES"].get(k, []))
+        valu = med(sq["SQ_INSTS_VALU"].get(k, [])) / waves if waves else float("nan")
+        f64 = sum(med(sq[c].get(k, [])) for c in ("SQ_INSTS_VALU_ADD_F64", "SQ_INSTS_VALU_MUL_F64",
+                                                    "SQ_INSTS_VALU_FMA_F64")) / waves if waves else float("nan")
+        print(f"| `{k[0]}` | {k[1]} | {n} | {f / 1e6:.1f} | {w / 1e6:.1f} | {valu:.0f} | {f64:.0f} |")
+
+
 def steps(n, prec_name="fp64"):
     import time
     import torch
@@ -279,6 +315,8 @@ if __name__ == "__main__":
         steps(int(sys.argv[2]), sys.argv[3] if len(sys.argv) > 3 else "fp64")
     elif cmd == "per_step":
         per_step(sys.argv[2], float(sys.argv[3]))
+    elif cmd == "kernels":
+        kernels(sys.argv[2])
     else:
         print(__doc__)
         sys.exit(1)
