@@ -209,6 +209,37 @@ struct ZCfg {
 // memory clobber keeps the compiler from moving memory accesses across it.
 __device__ __forceinline__ void lds_barrier() { asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory"); }
 
+// Cross-lane sums of the epilogues without the LDS unit.  v + v(lane ^ 1) with a DPP quad
+// permutation; v + v(lane ^ 16) and v + v(lane ^ 32) with gfx950's half-row swaps: swapping
+// a register with itself leaves in every lane the pair (v(lane), v(lane ^ d)) in some order,
+// and their sum is the same value either way.
+__device__ __forceinline__ float lane_add_xor1(float v) {
+#if defined(__HIP_DEVICE_COMPILE__)
+    return v + __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0xB1, 0xF, 0xF,
+                                                                       false));
+#else
+    return v;
+#endif
+}
+__device__ __forceinline__ float lane_sum16(float v) {
+#if defined(__HIP_DEVICE_COMPILE__)
+    const int x = __builtin_bit_cast(int, v);
+    const auto p = __builtin_amdgcn_permlane16_swap(x, x, false, false);
+    return __builtin_bit_cast(float, (int)p[0]) + __builtin_bit_cast(float, (int)p[1]);
+#else
+    return v;
+#endif
+}
+__device__ __forceinline__ float lane_sum32(float v) {
+#if defined(__HIP_DEVICE_COMPILE__)
+    const int x = __builtin_bit_cast(int, v);
+    const auto p = __builtin_amdgcn_permlane32_swap(x, x, false, false);
+    return __builtin_bit_cast(float, (int)p[0]) + __builtin_bit_cast(float, (int)p[1]);
+#else
+    return v;
+#endif
+}
+
 // One global->LDS transfer of BYTES per lane: lane l's bytes land at dst + l * BYTES
 // (dst is the same for the whole wave).  The 16-byte form exists on gfx950 only, so
 // the call is left out of the host pass, which never runs a kernel body.
@@ -585,15 +616,15 @@ __global__ __launch_bounds__(320) void k_convz(const bf16_t *__restrict__ XA, in
                                     h = fmaf(hv[1], rl[1], h);
                                     h = fmaf(hv[2], rh[0], h);
                                     h = fmaf(hv[3], rh[1], h);
-                                    h += __shfl_xor(h, 16, 64);
-                                    h += __shfl_xor(h, 32, 64);
+                                    h = lane_sum16(h);
+                                    h = lane_sum32(h);
                                     if (kq == 0 && gx < nx) Pf[v0 + col] = h + hv[4];
                                 } else {
                                     // average pooling: x pairs (lanes col, col ^ 1), then the
                                     // row pair (ro, ro + 1), then the plane pair (gz, gz + 1)
                                     f4 t = {rl[0], rl[1], rh[0], rh[1]};
 #pragma unroll
-                                    for (int i = 0; i < 4; ++i) t[i] += __shfl_xor(t[i], 1, 64);
+                                    for (int i = 0; i < 4; ++i) t[i] = lane_add_xor1(t[i]);
                                     if ((ro & 1) == 0) {
                                         prow = t;
                                     } else {
