@@ -268,7 +268,7 @@ __device__ __forceinline__ void restrict_cell_rbxy(const V &F, const V &C, const
 #pragma unroll
             for (int dx = 0; dx < 2; ++dx) {
                 const int i = 2 * I + dx;
-                const T FX_AS(1) *sp = hs ? F.sig + sidx(F, i, j, k) : F.r + cidx(F, i, j, k);
+                const auto sp = hs ? F.sig + sidx(F, i, j, k) : F.r + cidx(F, i, j, k);
                 sg[dz][dy][dx] = *sp;
             }
             const int i = 2 * I + ((dy + k) & 1);
@@ -1898,25 +1898,45 @@ __device__ void smooth_sweep(const V &L, int zero_init) {
 }
 
 // Restriction into level C and prolongation from it, as one phase each.
+// On a red/black level halved in x and y both take the global kernels' forms (every load
+// of a coarse cell's children before its arithmetic; black cells alone corrected), which
+// compute what restrict_cell and prolong_cell compute, in the same order.
 template <typename T, typename X_>
 __device__ void restrict_phase(const Lv<T, 3> &L, const Lv<T, 3> &C, const X_ &X) {
     const int n = C.nx * C.ny * C.nz;
     const Split3 sp{fdiv_of(C.nx), fdiv_of(C.ny)};
+    const bool rbxy = L.rb && X.xy == 1;
     for (int c = threadIdx.x; c < n; c += blockDim.x) {
         int I0, J0, K0;
         split_c(c, sp, I0, J0, K0);
-        restrict_cell(L, C, X, I0, J0, K0);
+        if (rbxy) restrict_cell_rbxy(L, C, X, I0, J0, K0);
+        else restrict_cell(L, C, X, I0, J0, K0);
     }
     __syncthreads();
 }
 template <typename T, typename X_>
 __device__ void prolong_phase(const Lv<T, 3> &L, const Lv<T, 3> &C, const X_ &X) {
-    const int n = L.nx * L.ny * L.nz;
-    const Split3 sp{fdiv_of(L.nx), fdiv_of(L.ny)};
-    for (int c = threadIdx.x; c < n; c += blockDim.x) {
-        int i, j, k;
-        split_c(c, sp, i, j, k);
-        prolong_cell(L, C, X, i, j, k);
+    if (L.rb) {
+        const int hx = L.nx >> 1;
+        const int n = hx * L.ny * L.nz;
+        T FX_AS(3) *eb = L.e + n;
+        const Split3 sp{fdiv_of(hx), fdiv_of(L.ny)};
+        for (int q = threadIdx.x; q < n; q += blockDim.x) {
+            int m, j, k;
+            split_c(q, sp, m, j, k);
+            const int i = 2 * m + ((1 + j + k) & 1);
+            const T v = X.xy == 1 ? prolong_value<1>(C, X, i, j, k)
+                        : X.xy == 2 ? prolong_value<2>(C, X, i, j, k) : prolong_value<0>(C, X, i, j, k);
+            eb[q] += v;
+        }
+    } else {
+        const int n = L.nx * L.ny * L.nz;
+        const Split3 sp{fdiv_of(L.nx), fdiv_of(L.ny)};
+        for (int c = threadIdx.x; c < n; c += blockDim.x) {
+            int i, j, k;
+            split_c(c, sp, i, j, k);
+            prolong_cell(L, C, X, i, j, k);
+        }
     }
     __syncthreads();
 }
