@@ -373,6 +373,10 @@ fx_status run_batch_qv(fx_batch *b, int nsteps, double dt, const double *const *
  * memory, as get_field. */
 fx_status batch_get_field(fx_batch *b, int inst, int which, double *h_out);
 fx_status batch_set_launch(fx_batch *b, int mode);
+/* How level l is smoothed for the batch's instances that have launches of their own on it
+ * (stack_level_mode's FX_LEVEL_*; FX_LEVEL_COARSE once every instance holds it in the
+ * coarse kernel).  FX_EINVAL for a bad handle or a negative level. */
+fx_status batch_level_mode(const fx_batch *b, int level, int *mode);
 fx_status batch_autotune(fx_batch *b, const char *cache_path, int flags, fx_tune_info *info);
 fx_status destroy_batch(fx_batch *b);
 

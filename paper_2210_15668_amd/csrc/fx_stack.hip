@@ -2024,6 +2024,14 @@ fx_status batch_set_launch(fx_batch *b, int mode) {
     return FX_OK;
 }
 
+fx_status batch_level_mode(const fx_batch *b, int level, int *mode) {
+    if (!b || !mode || level < 0) return fail(FX_EINVAL, "bad level");
+    const Engine &e = b->e;
+    if (level >= e.max_lc) *mode = FX_LEVEL_COARSE;
+    else *mode = level < (int)e.tb.size() && e.tb[level] ? FX_LEVEL_BLOCKED : FX_LEVEL_LAUNCHES;
+    return FX_OK;
+}
+
 fx_status destroy_batch(fx_batch *b) {
     if (!b) return FX_OK;
     engine_release(&b->e);

@@ -124,6 +124,7 @@ SIGNATURES = [
     ("batch_qv", ctypes.c_int, [_vp, _dp, _dp]),
     ("batch_get_field", ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int, _dp]),
     ("batch_set_launch", ctypes.c_int, [_vp, ctypes.c_int]),
+    ("batch_level_mode", ctypes.c_int, [_vp, ctypes.c_int, _ip]),
     ("destroy_batch", ctypes.c_int, [_vp]),
     ("last_error", ctypes.c_char_p, []),
 ]
@@ -462,6 +463,15 @@ class Batch:
 
     def set_launch(self, mode: int):
         _check(lib().batch_set_launch(self._h, mode))
+
+    def level_modes(self, levels: int = 8):
+        """LEVEL_LAUNCHES, LEVEL_BLOCKED or LEVEL_COARSE for levels 0 .. levels-1."""
+        out = []
+        for l in range(levels):
+            m = ctypes.c_int()
+            _check(lib().batch_level_mode(self._h, l, ctypes.byref(m)))
+            out.append(m.value)
+        return out
 
     def autotune(self, cache_path: Optional[str] = None, force: bool = False) -> TuneInfo:
         info = TuneInfo()

@@ -114,6 +114,34 @@ def test_blocked_smoothing_equals_launches(fx, monkeypatch, prec, nu):
 
 
 @pytest.mark.parametrize("prec", [W.PREC_FP64, W.PREC_MIXED])
+def test_blocked_smoothing_equals_launches_in_a_batch(fx, monkeypatch, prec):
+    """A batch of uneven instances whose levels below the finest all qualify (lateral sizes
+    multiples of 16, at most 30 planes there), some with semiconductor planes: blocked
+    smoothing against FERROX_TB=0, every instance bit for bit."""
+    specs = []
+    for q, (nx, ny, nz) in enumerate([(64, 64, 48), (96, 64, 48), (64, 96, 40), (128, 64, 48)]):
+        layers = [(W.FE, 16 + 4 * q, W.EPS_FE, 0.0), (W.DE, 4, W.EPS_SIO2, 0.0)]
+        if q % 2:
+            layers.append((W.SC, 16, W.EPS_SI, 1e24))
+        specs.append(W.layered(nx, ny, nz, layers, v_top=1.0 - 0.5 * q, tol_rel=1e-12, prec=prec,
+                               **({"ni": 1.0e16, "T": 300.0} if q % 2 else {})))
+    Ps = [W.random_P(sp, 96 + q, amp=0.05) for q, sp in enumerate(specs)]
+    out, modes = {}, {}
+    for tb in ("1", "0"):
+        monkeypatch.setenv("FERROX_TB", tb)
+        b = fx.Batch(specs, Ps)
+        modes[tb] = b.level_modes()
+        info = b.run(5, W.DT)
+        assert all(i.status == fx.FX_OK and i.steps_done == 5 for i in info)
+        out[tb] = [(b.get(q, fx.FIELD_P), b.get(q, fx.FIELD_PHI)) for q in range(len(specs))]
+        b.close()
+    say(f"  prec {prec}: batch level modes {modes['1']} / {modes['0']}")
+    assert fx.LEVEL_BLOCKED in modes["1"] and fx.LEVEL_BLOCKED not in modes["0"]
+    for q in range(len(specs)):
+        assert np.array_equal(out["1"][q][0], out["0"][q][0]) and np.array_equal(out["1"][q][1], out["0"][q][1]), q
+
+
+@pytest.mark.parametrize("prec", [W.PREC_FP64, W.PREC_MIXED])
 def test_light_cycles_reach_the_oracle_root(fx, orc, monkeypatch, prec):
     """Light cycles (one sweep fewer per level after a cycle that left the residual near the
     tolerance) change the iterates, not the root: with and without them the run meets the
