@@ -208,7 +208,8 @@ struct ResWork {
 // after_cycle 0: residual at the starting iterate of freshly begun solves;
 // 1: at the output of the cycle just run (forming phi_in + clip(e) first
 // where the update is not folded into the smoother).
-template <typename T> void launch_residual(const Inst<T> *I, const ResWork &w, int after_cycle, hipStream_t st);
+// any_fd: some instance takes Fermi-Dirac carriers (else the kernel without that branch)
+template <typename T> void launch_residual(const Inst<T> *I, const ResWork &w, int after_cycle, int any_fd, hipStream_t st);
 template <typename T> void launch_reduce(const Inst<T> *I, InstState *S, int ninst, int count_cycle, hipStream_t st);
 // Launch shape of one level's smoother: tile of 2^lbx x 2^(8-lbx) threads,
 // zt planes per thread, w8: register budget for 8 waves per SIMD.  Only the

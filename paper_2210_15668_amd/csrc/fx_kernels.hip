@@ -770,8 +770,10 @@ __device__ __forceinline__ ResTab res_tab(const Inst<T> &a) {
 // planes).  v0 is the cell's phi, vx0/vx1 and vy0/vy1 its x+1/x-1 and y+1/y-1
 // neighbours, vzm/vzp its z neighbours (not used on the contact planes), pm/pc/pp P on
 // planes k-1, k, k+1 (read only where a polarised face touches the plane).  Fused
-// multiply-adds are written out, so that every residual kernel rounds alike.
-template <typename T>
+// multiply-adds are written out, so that every residual kernel rounds alike.  FD = 0
+// leaves the Fermi-Dirac branch out (launches whose instances all take Boltzmann carriers:
+// fewer registers, no scalar registers parked in vector lanes).
+template <typename T, int FD>
 __device__ __forceinline__ void res_cell(const Inst<T> &a, const ResTab &tb, int k, int nzd, int fl, double v_t,
                                         double v0, double vx0, double vx1, double vy0, double vy1, double vzm,
                                         double vzp, double pm, double pc, double pp, double &f_o, double &r_o,
@@ -792,7 +794,7 @@ __device__ __forceinline__ void res_cell(const Inst<T> &a, const ResTab &tb, int
     if (fl & PF_SC) {
         const double u = v0 * a.vt_inv;
         const double p0e = tb.p0e[k], n0e = tb.n0e[k];
-        if (a.fd) {
+        if (FD && a.fd) {
             // differences from the neutral state: rho_c(0) = 0 exactly
             const double FX_AS(1) *ft = asp<1>(a.fdt) + 4 * k;
             double Fp, dFp, Fn, dFn;
@@ -820,7 +822,7 @@ __device__ __forceinline__ void res_cell(const Inst<T> &a, const ResTab &tb, int
 // z-neighbours are loaded once) and all stores follow it, so a wave makes one
 // memory round trip for kResZ cells.  Mode 0 evaluates the current iterate; mode 2 (update not
 // folded into the smoother) first forms phi_out = phi_in + clip(e).
-template <typename T, int MODE>
+template <typename T, int MODE, int FD>
 __device__ __forceinline__ void residual_body(const Inst<T> &a, const GState *s, const T3 &t, int after_cycle,
                                               double &rr, double &ff) {
     const int ZT = kResZ;
@@ -897,7 +899,7 @@ __device__ __forceinline__ void residual_body(const Inst<T> &a, const GState *s,
         sg[z] = 0.0;
         if (k >= nzd) break;
         double f;
-        res_cell(a, tb, k, nzd, fl[z], v_t, vc[z + 1], vx0[z], vx1[z], vy0[z], vy1[z], vc[z], vc[z + 2], pz[z],
+        res_cell<T, FD>(a, tb, k, nzd, fl[z], v_t, vc[z + 1], vx0[z], vx1[z], vy0[z], vy1[z], vc[z], vc[z + 2], pz[z],
                  pz[z + 1], pz[z + 2], f, res[z], sg[z]);
         if (live) {
             rr = fmad(res[z], res[z], rr);
@@ -918,7 +920,7 @@ __device__ __forceinline__ void residual_body(const Inst<T> &a, const GState *s,
 // MODE 0 covers every instance except, after a cycle, those whose update is
 // not folded into the smoother; MODE 2 covers exactly those (two kernels
 // rather than one branch: each keeps its own, smaller register budget).
-template <typename T, int MODE>
+template <typename T, int MODE, int FD>
 __global__ __launch_bounds__(256) void k_residual(const Inst<T> *I, Work w, int after_cycle) {
     __shared__ double lds_r[4];
     __shared__ double lds_f[4];
@@ -934,7 +936,7 @@ __global__ __launch_bounds__(256) void k_residual(const Inst<T> *I, Work w, int 
     const T3 t = split3z(b.t, a.nx, nzt);
     const int tl = t.tx + ((a.nx + BX - 1) / BX) * (t.ty + ((a.ny + BY - 1) / BY) * t.tz);
     double rr = 0.0, ff = 0.0;
-    residual_body<T, MODE>(a, s, t, after_cycle, rr, ff);
+    residual_body<T, MODE, FD>(a, s, t, after_cycle, rr, ff);
     const double sr = block_sum(rr, lds_r);
     const double sf = block_sum(ff, lds_f);
     if (threadIdx.x == 0 && threadIdx.y == 0) {
@@ -2306,9 +2308,9 @@ void launch_extrap(const Inst<T> *I, const Work &w, hipStream_t st) {
 }
 
 template <typename T>
-void launch_residual(const Inst<T> *I, const ResWork &w, int after_cycle, hipStream_t st) {
-    auto *k0 = &k_residual<T, 0>;
-    auto *k2 = &k_residual<T, 2>;
+void launch_residual(const Inst<T> *I, const ResWork &w, int after_cycle, int any_fd, hipStream_t st) {
+    auto *k0 = any_fd ? &k_residual<T, 0, 1> : &k_residual<T, 0, 0>;
+    auto *k2 = any_fd ? &k_residual<T, 2, 1> : &k_residual<T, 2, 0>;
     FX_LAUNCH(k0, w.cell0, I, w.cell0, after_cycle);
     if (after_cycle) FX_LAUNCH(k2, w.cell2, I, w.cell2, after_cycle);
 }
@@ -2449,7 +2451,7 @@ void launch_fill(double *x, size_t n, double v, hipStream_t st) {
     template void launch_qv<T>(const Inst<T> *, int, int, double *, hipStream_t);                            \
     template void launch_begin<T>(const Inst<T> *, int, int, hipStream_t);                                  \
     template void launch_extrap<T>(const Inst<T> *, const Work &, hipStream_t);                              \
-    template void launch_residual<T>(const Inst<T> *, const ResWork &, int, hipStream_t);                    \
+    template void launch_residual<T>(const Inst<T> *, const ResWork &, int, int, hipStream_t);                    \
     template void launch_reduce<T>(const Inst<T> *, InstState *, int, int, hipStream_t);                                  \
     template void launch_smooth<T>(const Inst<T> *, const Work &, int, int, int, int, const SmoothCfg &,     \
                                    double *, hipStream_t, hipEvent_t, hipEvent_t, int);                      \

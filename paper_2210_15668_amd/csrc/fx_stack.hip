@@ -350,6 +350,7 @@ struct Engine {
     std::vector<char> small;            // per level: few enough cells that launch latency dominates
     int max_lc = 0, lds_max = 0, max_cycles = 1;
     int any_order2 = 0;                 // some instance takes predictor-corrector steps
+    int any_fd = 0;                     // some instance takes Fermi-Dirac carriers
     int nu1 = 2, nu2 = 2;               // sweeps before / after the coarse correction, finest level
     int nu1c = 2, nu2c = 2;             // the same on every coarser level
     int fuse = 1;                       // fused launches below the finest level (same values)
@@ -458,10 +459,12 @@ void plan_launches(Engine *e) {
     e->max_lc = 0;
     e->max_cycles = 1;
     e->any_order2 = 0;
+    e->any_fd = 0;
     for (const InstHost &h : e->in) {
         e->max_lc = std::max(e->max_lc, h.plan.lc);
         e->max_cycles = std::max(e->max_cycles, h.d.max_cycles);
         if (h.d.time_order == 2) e->any_order2 = 1;
+        if (h.d.carriers == FX_CARRIERS_FD) e->any_fd = 1;
     }
     e->scfg.assign(e->max_lc, SmoothCfg{6, 1, 0});
     e->ncol.assign(e->max_lc, 2);
@@ -938,7 +941,7 @@ void enq_vcycle(Engine *e) {
 template <typename T>
 void enq_cycle(Engine *e) {
     enq_vcycle<T>(e);
-    launch_residual(idev<T>(e), e->w_res, 1, e->st);
+    launch_residual(idev<T>(e), e->w_res, 1, e->any_fd, e->st);
     launch_reduce(idev<T>(e), e->st_dev, e->n, 1, e->st);
 }
 
@@ -953,7 +956,7 @@ void enq_advance(Engine *e) {
     if (e->any_order2) launch_tdgl_corr(I, e->w_tdgl, e->st);
     launch_begin(I, e->n, 1, e->st);
     launch_extrap(I, e->w_ext, e->st);
-    launch_residual(I, e->w_res, 0, e->st);
+    launch_residual(I, e->w_res, 0, e->any_fd, e->st);
     launch_reduce(I, e->st_dev, e->n, 0, e->st);
 }
 
@@ -1020,7 +1023,7 @@ template <typename T>
 fx_status solve_plain_t(Engine *e) {
     const Inst<T> *I = idev<T>(e);
     launch_begin(I, e->n, 0, e->st);
-    launch_residual(I, e->w_res, 0, e->st);
+    launch_residual(I, e->w_res, 0, e->any_fd, e->st);
     launch_reduce(I, e->st_dev, e->n, 0, e->st);
     int enq = 0;
     int batch = e->trace ? 0 : std::max(1, e->k_pred);
