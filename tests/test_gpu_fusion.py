@@ -141,6 +141,55 @@ def test_blocked_smoothing_equals_launches_in_a_batch(fx, monkeypatch, prec):
         assert np.array_equal(out["1"][q][0], out["0"][q][0]) and np.array_equal(out["1"][q][1], out["0"][q][1]), q
 
 
+# (lateral x, lateral y, layers gate-first, the level-1 shape that is to run blocked)
+TB_EDGES = [
+    # 30 planes on level 1: the most a box holds (its FP64 LDS is 63 KB of 64); the finest
+    # level's odd 59th plane is left unpaired
+    (32, 32, [(W.FE, 24, W.EPS_FE, 0.0), (W.DE, 5, W.EPS_SIO2, 0.0), (W.SC, 30, W.EPS_SI, 1e24)], (16, 16, 30)),
+    # an odd plane count on the blocked level itself (29 into 15: the top coarse plane
+    # has one child), semiconductor planes below
+    (32, 32, [(W.FE, 20, W.EPS_FE, 0.0), (W.DE, 6, W.EPS_SIO2, 0.0), (W.SC, 32, W.EPS_SI, 1e24)], (16, 16, 29)),
+    # extents that are multiples of the 8-cell tile but not of the 16-cell box: 3 x 5 tiles
+    (48, 80, [(W.FE, 32, W.EPS_FE, 0.0), (W.DE, 8, W.EPS_SIO2, 0.0)], (24, 40, 20)),
+]
+
+
+@pytest.mark.parametrize("prec", [W.PREC_FP64, W.PREC_MIXED])
+@pytest.mark.parametrize("case", range(len(TB_EDGES)))
+def test_blocked_smoothing_at_its_geometry_limits(fx, orc, monkeypatch, prec, case):
+    """Blocked smoothing where its geometry is tightest (box planes at the LDS limit, an odd
+    plane count with an unpaired top plane, tiles that do not fill a whole box): the blocked
+    level runs blocked, the result is bitwise that of the half-sweep launches (FERROX_TB=0),
+    and in FP64 it meets the oracle's trajectory to 1e-10."""
+    nx, ny, layers, shape = TB_EDGES[case]
+    nzd = sum(l[1] for l in layers)
+    sc = any(l[0] == W.SC for l in layers)
+    spec = W.layered(nx, ny, nzd + 4, layers, v_top=0.7, tol_rel=1e-12, prec=prec,
+                     **({"ni": 1.0e16, "T": 300.0} if sc else {}))
+    P0 = W.random_P(spec, 97 + case, amp=0.05)
+    n = 5
+    out = {}
+    for tb in ("1", "0"):
+        monkeypatch.setenv("FERROX_TB", tb)
+        s = fx.Stack(spec, P0)
+        shapes, modes = s.levels(), s.level_modes()
+        info = s.run_steps(n, W.DT)
+        assert info.steps_done == n
+        out[tb] = (s.get(fx.FIELD_P), s.get(fx.FIELD_PHI), info.total_cycles, shapes, modes)
+        s.close()
+    shapes, modes = out["1"][3], out["1"][4]
+    say(f"  prec {prec} case {case}: levels {shapes}, modes {modes} / {out['0'][4]}, "
+        f"V-cycles {out['1'][2]} / {out['0'][2]}")
+    assert shapes[1] == shape and modes[1] == fx.LEVEL_BLOCKED and fx.LEVEL_BLOCKED not in out["0"][4]
+    assert out["1"][2] == out["0"][2]
+    assert np.array_equal(out["1"][0], out["0"][0]) and np.array_equal(out["1"][1], out["0"][1])
+    if prec == W.PREC_FP64:
+        P_o, phi_o, _ = orc.run(spec, P0, n, W.DT, tol=1e-12)
+        rp, rf = rel(out["1"][0], P_o), rel(out["1"][1], phi_o)
+        say(f"  vs oracle: relP {rp:.2e} relphi {rf:.2e}")
+        assert rp <= 1e-10 and rf <= 1e-10
+
+
 @pytest.mark.parametrize("prec", [W.PREC_FP64, W.PREC_MIXED])
 def test_light_cycles_reach_the_oracle_root(fx, orc, monkeypatch, prec):
     """Light cycles (one sweep fewer per level after a cycle that left the residual near the
