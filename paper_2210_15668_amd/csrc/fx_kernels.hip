@@ -948,17 +948,35 @@ __global__ __launch_bounds__(256) void k_residual(const Inst<T> *I, Work w, int 
 
 // Deterministic final sum of one instance's residual partials (a block per
 // instance) and its stop decision.
-template <typename T>
-__global__ __launch_bounds__(1024) void k_reduce(const Inst<T> *I, InstState *S, int count_cycle) {
+template <typename T, int CC>
+__global__ __launch_bounds__(1024) void k_reduce(const Inst<T> *I, InstState *S) {
     __shared__ double lr[16];
     __shared__ double lf[16];
     const Inst<T> &a = I[blockIdx.x];
     GState *s = asp<1>(S + blockIdx.x);
-    if (count_cycle ? s->done != 0 : !s->fresh) return;
-    const int n = tiles3(a.nx, a.ny, (a.nzd + kResZ - 1) / kResZ);
+    // the state and the partials are read together, the partials two per thread at a
+    // time, so that the block waits on memory once for them (an instance that is not
+    // reduced here ignores what it read); each thread still adds its partials in
+    // index order
     const double FX_AS(1) *part = asp<1>(a.part);
+    const bool skip = CC ? s->done != 0 : !s->fresh;
+    // what the stop decision reads, fetched with the rest
+    const double x_prev = s->rn2, tol2 = a.tol2, light_r2 = a.light_r2, light_c2 = a.light_c2;
+    const int cycles = s->cycles + (CC ? 1 : 0), max_cycles = a.max_cycles, light_ok = a.light_ok;
+    const int n = tiles3(a.nx, a.ny, (a.nzd + kResZ - 1) / kResZ);
+    const int B = blockDim.x;
     double r = 0.0, f = 0.0;
-    for (int q = threadIdx.x; q < n; q += blockDim.x) { r += part[2 * q]; f += part[2 * q + 1]; }
+    int q = threadIdx.x;
+    for (; q + B < n; q += 2 * B) {
+        const double r0 = part[2 * q], f0 = part[2 * q + 1];
+        const double r1 = part[2 * (q + B)], f1 = part[2 * (q + B) + 1];
+        r += r0;
+        f += f0;
+        r += r1;
+        f += f1;
+    }
+    if (q < n) { r += part[2 * q]; f += part[2 * q + 1]; }
+    if (skip) return;
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) { r += __shfl_down(r, off, 64); f += __shfl_down(f, off, 64); }
     if ((threadIdx.x & 63) == 0) { lr[threadIdx.x >> 6] = r; lf[threadIdx.x >> 6] = f; }
@@ -966,20 +984,19 @@ __global__ __launch_bounds__(1024) void k_reduce(const Inst<T> *I, InstState *S,
     if (threadIdx.x == 0) {
         double x = 0.0, y = 0.0;
         for (int q = 0; q < (int)(blockDim.x >> 6); ++q) { x += lr[q]; y += lf[q]; }
-        const double x_prev = s->rn2;
         s->rn2 = x;
         s->fn2 = y;
         s->fresh = 0;
-        if (count_cycle) s->cycles += 1;
+        if (CC) s->cycles = cycles;
         if (!isfinite(x) || !isfinite(y)) s->done = 2;
         else if (y == 0.0) { s->done = 1; s->zpend = x != 0.0; }
-        else if (x <= a.tol2 * y || x == 0.0) s->done = 1;
-        else if (s->cycles >= a.max_cycles) s->done = 3;
+        else if (x <= tol2 * y || x == 0.0) s->done = 1;
+        else if (cycles >= max_cycles) s->done = 3;
         // within kLightRatio of the tolerance, after a cycle that contracted the
         // residual at least kLightContraction-fold (the linear regime, as in a
         // time step's first cycle), one V(1,1)-like cycle (contraction about 0.2)
         // finishes the solve at a little over half the cost
-        s->light = a.light_ok && count_cycle && x <= a.light_r2 * a.tol2 * y && x * a.light_c2 <= x_prev;
+        s->light = light_ok && CC && x <= light_r2 * tol2 * y && x * light_c2 <= x_prev;
     }
 }
 
@@ -2317,7 +2334,8 @@ void launch_residual(const Inst<T> *I, const ResWork &w, int after_cycle, int an
 
 template <typename T>
 void launch_reduce(const Inst<T> *I, InstState *S, int ninst, int count_cycle, hipStream_t st) {
-    hipLaunchKernelGGL(k_reduce<T>, dim3(ninst), dim3(1024), 0, st, I, S, count_cycle);
+    if (count_cycle) hipLaunchKernelGGL((k_reduce<T, 1>), dim3(ninst), dim3(1024), 0, st, I, S);
+    else hipLaunchKernelGGL((k_reduce<T, 0>), dim3(ninst), dim3(1024), 0, st, I, S);
 }
 
 template <typename T, int ZT>
