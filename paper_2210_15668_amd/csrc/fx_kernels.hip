@@ -517,8 +517,12 @@ __global__ void k_begin(const Inst<T> *I, int ninst, int sel) {
     const int n = blockIdx.x * blockDim.x + threadIdx.x;
     if (n >= ninst) return;
     const Inst<T> &a = I[n];
-    GState *s = asp<1>(a.st);
-    if (sel && !s->adv && !s->corr) return;
+    GState *gs = asp<1>(a.st);
+    // read whole, updated in registers and written back once; an instance that
+    // starts no solve here is computed alike and not written back, so that no
+    // branch stands between the kernel's loads
+    InstState st = *(const InstState *)gs, *s = &st;
+    const bool run = !(sel && !s->adv && !s->corr);
     if (sel) {
         s->pcur ^= 1;
         const int q = s->step - s->sched_base;
@@ -540,7 +544,8 @@ __global__ void k_begin(const Inst<T> *I, int ninst, int sel) {
     int oth[2] = {0, 0}, no = 0;
     for (int q = 0; q < a.nbuf && no < 2; ++q) {
         bool used = q == s->cur || q == s->pstar;
-        for (int m = 0; m < s->hist; ++m) used |= s->prev[m] == q;
+#pragma unroll
+        for (int m = 0; m < kMaxHist; ++m) used |= m < s->hist && s->prev[m] == q;
         if (!used) oth[no++] = q;
     }
     s->oth0 = oth[0];
@@ -555,6 +560,7 @@ __global__ void k_begin(const Inst<T> *I, int ninst, int sel) {
     s->fresh = 1;
     s->insolve = 1;
     s->light = 0;
+    if (run) *(InstState *)gs = st;
 }
 
 // Lagrange extrapolation to t^{n+1} through t^n, t^{n-1}, ... (equal steps).
@@ -599,7 +605,13 @@ template <typename T>
 __global__ void k_head(const Inst<T> *I, int ninst, int advance) {
     const int n = blockIdx.x * blockDim.x + threadIdx.x;
     if (n >= ninst) return;
-    GState *s = asp<1>(I[n].st);
+    // the state is read whole, updated in registers and written back once (one
+    // round trip instead of one per dependent field); the copies go through a generic
+    // view (the implicit copy operations take no address-space-qualified operand),
+    // which the compiler maps back to global loads and stores
+    GState *gs = asp<1>(I[n].st);
+    InstState st = *(const InstState *)gs, *s = &st;
+    const int order2 = I[n].order2;
     int zf = 0, corr = 0, stepped = 0;
     if (s->insolve && s->done != 0) {
         const int c = s->cycles;
@@ -629,14 +641,16 @@ __global__ void k_head(const Inst<T> *I, int ninst, int advance) {
                 if (fin != s->cur) {
                     // Euler keeps 3 levels; a predictor-corrector instance 4, so that
                     // its corrector, whose newest level is phi^n, extrapolates cubically
-                    const int hmax = I[n].order2 ? kMaxHist : kMaxHist - 1;
-                    for (int m = hmax - 1; m > 0; --m) s->prev[m] = s->prev[m - 1];
+                    const int hmax = order2 ? kMaxHist : kMaxHist - 1;
+#pragma unroll
+                    for (int m = kMaxHist - 1; m > 0; --m)
+                        if (m < hmax) s->prev[m] = s->prev[m - 1];
                     s->prev[0] = s->cur;
                     s->hist = min(s->hist + 1, hmax);
                 } else {
                     s->hist = 0;
                 }
-                if (I[n].order2) { s->phase = 1; corr = 1; }
+                if (order2) { s->phase = 1; corr = 1; }
                 else { s->step += 1; stepped = 1; }
                 s->pstar = -1;
             } else {
@@ -657,6 +671,7 @@ __global__ void k_head(const Inst<T> *I, int ninst, int advance) {
     s->adv = adv;
     s->corr = corr;
     s->stepped = stepped;
+    *(InstState *)gs = st;
 }
 
 // Q-V diagnostics (Results, MFIM).  Across the ferroelectric/dielectric face, with L
