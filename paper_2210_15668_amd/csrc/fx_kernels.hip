@@ -456,10 +456,10 @@ __device__ __forceinline__ double tdgl_force(const Inst<T> &a, const double FX_A
 template <typename T>
 __global__ __launch_bounds__(256) void k_tdgl(const Inst<T> *I, Work w, int sel) {
     const Blk b = find_block(w);
-    if (!b.ok) return;
     const Inst<T> &a = I[b.inst];
     const GState *s = wstate(w, b.inst);
-    if (sel && !s->adv) return;
+    const int adv = s->adv;
+    if (!b.ok | ((sel != 0) & (adv == 0))) return;  // one exit test: see smooth_kernel
     const int pcur = s->pcur;
     const T3 t = split3(b.t, a.nx, a.ny);
     const int i = t.tx * BX + threadIdx.x;
@@ -478,10 +478,10 @@ __global__ __launch_bounds__(256) void k_tdgl(const Inst<T> *I, Work w, int sel)
 template <typename T>
 __global__ __launch_bounds__(256) void k_tdgl_corr(const Inst<T> *I, Work w) {
     const Blk b = find_block(w);
-    if (!b.ok) return;
     const Inst<T> &a = I[b.inst];
     const GState *s = wstate(w, b.inst);
-    if (!s->corr) return;
+    const int corr = s->corr;
+    if (!b.ok | (corr == 0)) return;  // one exit test: see smooth_kernel
     const int pcur = s->pcur;
     const T3 t = split3(b.t, a.nx, a.ny);
     const int i = t.tx * BX + threadIdx.x;
@@ -569,11 +569,10 @@ __constant__ double kExtrapC[4][4] = {{1, 0, 0, 0}, {2, -1, 0, 0}, {3, -3, 1, 0}
 template <typename T>
 __global__ __launch_bounds__(256) void k_extrap(const Inst<T> *I, Work w) {
     const Blk b = find_block(w);
-    if (!b.ok) return;
     const Inst<T> &a = I[b.inst];
     const GState *s = wstate(w, b.inst);
-    const int order = s->order;
-    if (!s->fresh || (order == 0 && !s->usestar)) return;
+    const int order = s->order, fresh = s->fresh, usestar = s->usestar;
+    if (!b.ok | (fresh == 0) | ((order == 0) & (usestar == 0))) return;  // one exit test: see smooth_kernel
     const size_t nxy = (size_t)a.nx * a.ny, off = (size_t)a.kb * nxy, n = (size_t)a.nzd * nxy;
     const double FX_AS(1) *in[4];
     // newest level phi^n: the current iterate, or for a corrector the last stored level
@@ -754,10 +753,10 @@ __global__ void k_qv_fin(const Inst<T> *I, int ninst, int record, double *out) {
 template <typename T>
 __global__ __launch_bounds__(256) void k_zero_fix(const Inst<T> *I, Work w) {
     const Blk b = find_block(w);
-    if (!b.ok) return;
     const Inst<T> &a = I[b.inst];
     const GState *s = wstate(w, b.inst);
-    if (!s->zero_fix) return;
+    const int zero_fix = s->zero_fix;
+    if (!b.ok | (zero_fix == 0)) return;  // one exit test: see smooth_kernel
     const size_t nxy = (size_t)a.nx * a.ny, n = (size_t)a.nzd * nxy;
     double FX_AS(1) *out = asp<1>(a.phi[s->cur]) + (size_t)a.kb * nxy;
     const size_t base = (size_t)b.t * kExtrapChunk;
@@ -940,11 +939,11 @@ __global__ __launch_bounds__(256) void k_residual(const Inst<T> *I, Work w, int 
     __shared__ double lds_r[4];
     __shared__ double lds_f[4];
     const Blk b = find_block(w);
-    if (!b.ok) return;
     const Inst<T> &a = I[b.inst];
     const GState *s = wstate(w, b.inst);
-    if (after_cycle ? s->done != 0 : !s->fresh) return;
-    if ((MODE == 2) != (after_cycle && !a.fold)) return;
+    // one exit test: see smooth_kernel
+    const int done = s->done, fresh = s->fresh, fold = a.fold;
+    if (!b.ok | (after_cycle ? done != 0 : fresh == 0) | ((MODE == 2) != ((after_cycle != 0) & (fold == 0)))) return;
     // tiles walk each column up in z (halo planes shared through L2); the partial sums
     // keep the x-fastest tile index, so the reduction's order does not depend on it
     const int nzt = (a.nzd + kResZ - 1) / kResZ;
@@ -1185,9 +1184,9 @@ __device__ __forceinline__ void smooth_zpair_body(const Lv<T, 1> &L, int t, int 
 template <typename T, int ZT>
 __global__ __launch_bounds__(256) void k_smooth_zpair(const Inst<T> *I, Work w, int level, int lbx) {
     const Blk b = find_block(w);
-    if (!b.ok) return;
     const Inst<T> &a = I[b.inst];
-    if (wstate(w, b.inst)->done) return;
+    const int done = wstate(w, b.inst)->done;
+    if (!b.ok | (done != 0) | (level < 0)) return;  // one exit test: see smooth_kernel
     const Lv<T, 1> L = gview(a.lv[level]);
     if (!L.rb) return;                               // the host fuses only all-red/black levels
     smooth_zpair_body<T, ZT>(L, b.t, lbx);
@@ -1201,10 +1200,13 @@ template <typename T, int ZI, int ZT, int UPD>
 __device__ __forceinline__ void smooth_kernel(const Inst<T> *I, const Work &w, int level, int color, int lbx,
                                               double *probe, int skip_light) {
     const Blk b = find_block(w);
-    if (!b.ok) return;
     const Inst<T> &a = I[b.inst];
     const GState *st = wstate(w, b.inst);
-    if (st->done || (skip_light && st->light)) return;
+    // one exit test with no short-circuit, so that the state's fields and the
+    // launch's arguments are read in one round trip (a block past the table's end
+    // reads instance 0's; level < 0 never holds)
+    const int done = st->done, light = st->light;
+    if (!b.ok | (done != 0) | ((skip_light != 0) & (light != 0)) | (level < 0)) return;
     const Lv<T, 1> L = gview(a.lv[level]);
     if (L.rb) {
         if (color > 1) return;
@@ -1240,9 +1242,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void k
 template <typename T>
 __global__ __launch_bounds__(256) void k_restrict(const Inst<T> *I, Work w, int level) {
     const Blk b = find_block(w);
-    if (!b.ok) return;
     const Inst<T> &a = I[b.inst];
-    if (wstate(w, b.inst)->done) return;
+    const int done = wstate(w, b.inst)->done;
+    if (!b.ok | (done != 0) | (level < 0)) return;  // one exit test: see smooth_kernel
     const Lv<T, 1> C = gview(a.lv[level + 1]);
     const T3 t = split3(b.t, C.nx, C.ny);
     const int I0 = t.tx * BX + threadIdx.x;
@@ -1324,9 +1326,9 @@ __device__ __forceinline__ void prolong_red_body(const Lv<T, 1> &F, const Lv<T, 
 template <typename T, int ZT>
 __global__ __launch_bounds__(256) void k_prolong_red(const Inst<T> *I, Work w, int level, int lbx) {
     const Blk b = find_block(w);
-    if (!b.ok) return;
     const Inst<T> &a = I[b.inst];
-    if (wstate(w, b.inst)->done) return;
+    const int done = wstate(w, b.inst)->done;
+    if (!b.ok | (done != 0) | (level < 0)) return;  // one exit test: see smooth_kernel
     const Lv<T, 1> F = gview(a.lv[level]);
     if (!F.rb) return;                               // the host fuses only all-red/black levels
     const Lv<T, 1> C = gview(a.lv[level + 1]);
@@ -1377,9 +1379,9 @@ __device__ __forceinline__ void prolong_cc_interp(const Lv<T, 1> &C, int K, int 
 template <typename T>
 __global__ __launch_bounds__(256) void k_prolong_cc(const Inst<T> *Ia, Work w, int level, int cz) {
     const Blk b = find_block(w);
-    if (!b.ok) return;
     const Inst<T> &a = Ia[b.inst];
-    if (wstate(w, b.inst)->done) return;
+    const int done = wstate(w, b.inst)->done;
+    if (!b.ok | (done != 0) | (level < 0)) return;  // one exit test: see smooth_kernel
     const Lv<T, 1> C = gview(a.lv[level + 1]);
     const T3 t = split3(b.t, C.nx, C.ny);
     const int I = t.tx * BX + threadIdx.x;
@@ -1433,9 +1435,9 @@ __global__ __launch_bounds__(256) void k_prolong_cc(const Inst<T> *Ia, Work w, i
 template <typename T>
 __global__ __launch_bounds__(256) void k_prolong(const Inst<T> *I, Work w, int level) {
     const Blk b = find_block(w);
-    if (!b.ok) return;
     const Inst<T> &a = I[b.inst];
-    if (wstate(w, b.inst)->done) return;
+    const int done = wstate(w, b.inst)->done;
+    if (!b.ok | (done != 0) | (level < 0)) return;  // one exit test: see smooth_kernel
     const Lv<T, 1> F = gview(a.lv[level]);
     const int nxe = F.rb ? F.nx >> 1 : F.nx;      // black cells per row on a red/black level
     const T3 t = split3(b.t, nxe, F.ny);
@@ -1695,11 +1697,11 @@ __global__ __launch_bounds__(TbShape<TbCfg<T>::pre_q>::threads) void k_pre_tb(co
     constexpr int ZQ = TbShape<TbCfg<T>::pre_q>::zq;
     extern __shared__ double tb_raw[];
     const Blk b = find_block(w);
-    if (!b.ok) return;
     const Inst<T> &a = I[b.inst];
     const GState *st = wstate(w, b.inst);
-    if (st->done) return;
-    if (st->light) nu = 1;                         // the sweeps after the first are left out
+    const int done = st->done, light = st->light;
+    if (!b.ok | (done != 0) | (level < 0)) return;  // one exit test: see smooth_kernel
+    if (light) nu = 1;                         // the sweeps after the first are left out
     const Lv<T, 1> L = gview(a.lv[level]);
     const Xv<T> X = xview(a.xf[level]);
     T FX_AS(3) *box = asp<3>((T *)tb_raw);
@@ -1744,11 +1746,11 @@ __global__ __launch_bounds__(TbShape<TbCfg<T>::post_q>::threads) void k_post_tb(
     constexpr int G = TbCfg<T>::post_g;
     extern __shared__ double tb_raw[];
     const Blk b = find_block(w);
-    if (!b.ok) return;
     const Inst<T> &a = I[b.inst];
     const GState *st = wstate(w, b.inst);
-    if (st->done) return;
-    if (st->light) nu = 1;                         // one sweep: the fused prolongation's and the black after it
+    const int done = st->done, light = st->light;
+    if (!b.ok | (done != 0) | (level < 0)) return;  // one exit test: see smooth_kernel
+    if (light) nu = 1;                         // one sweep: the fused prolongation's and the black after it
     const Lv<T, 1> F = gview(a.lv[level]);
     const Lv<T, 1> C = gview(a.lv[level + 1]);
     const Xv<T> X = xview(a.xf[level]);
