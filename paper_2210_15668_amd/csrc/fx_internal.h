@@ -196,7 +196,7 @@ template <typename T> void launch_flip(const Inst<T> *I, int ninst, hipStream_t 
 // current state into out[2 i], out[2 i + 1] (NaN without an interface); record 1: the
 // instances that completed a time step in this advance slot, into their per-step record.
 template <typename T> void launch_qv(const Inst<T> *I, int ninst, int record, double *out, hipStream_t st);
-template <typename T> void launch_begin(const Inst<T> *I, int ninst, int sel, hipStream_t st);
+template <typename T> void launch_begin(const Inst<T> *I, InstState *S, int ninst, int sel, hipStream_t st);
 template <typename T> void launch_extrap(const Inst<T> *I, const Work &w, hipStream_t st);
 // Work tables of the residual: cell0 -- every instance (mode 0, the current
 // iterate; after a cycle the kernel skips the instances of cell2); cell2 --
@@ -241,7 +241,7 @@ template <typename T> void launch_coarse(const Inst<T> *I, InstState *S, int nin
 // post-smoothing (nu sweeps), a block per kTbT x kTbT tile with lds_bytes of LDS
 template <typename T> void launch_pre_tb(const Inst<T> *I, const Work &w, int level, int nu, int lds_bytes, hipStream_t st);
 template <typename T> void launch_post_tb(const Inst<T> *I, const Work &w, int level, int nu, int lds_bytes, hipStream_t st);
-template <typename T> void launch_head(const Inst<T> *I, int ninst, int advance, hipStream_t st);
+template <typename T> void launch_head(const Inst<T> *I, InstState *S, int ninst, int advance, hipStream_t st);
 template <typename T> void launch_zero_fix(const Inst<T> *I, const Work &w, hipStream_t st);
 template <typename T> void launch_run_setup(const Inst<T> *I, int ninst, int nsteps, int has_sched, double dt,
                                             int first, hipStream_t st);

@@ -513,11 +513,12 @@ __global__ void k_flip(const Inst<T> *I, int ninst) {
 // starting iterate may be extrapolated in time.  sel = 0: a plain solve of
 // every instance from its current phi.
 template <typename T>
-__global__ void k_begin(const Inst<T> *I, int ninst, int sel) {
+__global__ void k_begin(const Inst<T> *I, InstState *S, int ninst, int sel) {
     const int n = blockIdx.x * blockDim.x + threadIdx.x;
     if (n >= ninst) return;
     const Inst<T> &a = I[n];
-    GState *gs = asp<1>(a.st);
+    GState *gs = asp<1>(S + n);                   // the state array itself (not through the
+                                                  // instance): one dependent load fewer
     // read whole, updated in registers and written back once; an instance that
     // starts no solve here is computed alike and not written back, so that no
     // branch stands between the kernel's loads
@@ -601,14 +602,14 @@ __global__ __launch_bounds__(256) void k_extrap(const Inst<T> *I, Work w) {
 // whose last solve succeeded) is flagged to start the next time step in this
 // slot; one that has reached the target or failed is parked.
 template <typename T>
-__global__ void k_head(const Inst<T> *I, int ninst, int advance) {
+__global__ void k_head(const Inst<T> *I, InstState *S, int ninst, int advance) {
     const int n = blockIdx.x * blockDim.x + threadIdx.x;
     if (n >= ninst) return;
     // the state is read whole, updated in registers and written back once (one
     // round trip instead of one per dependent field); the copies go through a generic
     // view (the implicit copy operations take no address-space-qualified operand),
     // which the compiler maps back to global loads and stores
-    GState *gs = asp<1>(I[n].st);
+    GState *gs = asp<1>(S + n);
     InstState st = *(const InstState *)gs, *s = &st;
     const int order2 = I[n].order2;
     int zf = 0, corr = 0, stepped = 0;
@@ -2332,8 +2333,8 @@ void launch_flip(const Inst<T> *I, int ninst, hipStream_t st) {
 }
 
 template <typename T>
-void launch_begin(const Inst<T> *I, int ninst, int sel, hipStream_t st) {
-    hipLaunchKernelGGL(k_begin<T>, per_inst(ninst), dim3(64), 0, st, I, ninst, sel);
+void launch_begin(const Inst<T> *I, InstState *S, int ninst, int sel, hipStream_t st) {
+    hipLaunchKernelGGL(k_begin<T>, per_inst(ninst), dim3(64), 0, st, I, S, ninst, sel);
 }
 
 template <typename T>
@@ -2446,8 +2447,8 @@ void launch_coarse(const Inst<T> *I, InstState *S, int ninst, int lds_bytes, hip
 }
 
 template <typename T>
-void launch_head(const Inst<T> *I, int ninst, int advance, hipStream_t st) {
-    hipLaunchKernelGGL(k_head<T>, per_inst(ninst), dim3(64), 0, st, I, ninst, advance);
+void launch_head(const Inst<T> *I, InstState *S, int ninst, int advance, hipStream_t st) {
+    hipLaunchKernelGGL(k_head<T>, per_inst(ninst), dim3(64), 0, st, I, S, ninst, advance);
 }
 
 template <typename T>
@@ -2484,7 +2485,7 @@ void launch_fill(double *x, size_t n, double v, hipStream_t st) {
     template void launch_tdgl_corr<T>(const Inst<T> *, const Work &, hipStream_t);                           \
     template void launch_flip<T>(const Inst<T> *, int, hipStream_t);                                        \
     template void launch_qv<T>(const Inst<T> *, int, int, double *, hipStream_t);                            \
-    template void launch_begin<T>(const Inst<T> *, int, int, hipStream_t);                                  \
+    template void launch_begin<T>(const Inst<T> *, InstState *, int, int, hipStream_t);                                  \
     template void launch_extrap<T>(const Inst<T> *, const Work &, hipStream_t);                              \
     template void launch_residual<T>(const Inst<T> *, const ResWork &, int, int, hipStream_t);                    \
     template void launch_reduce<T>(const Inst<T> *, InstState *, int, int, hipStream_t);                                  \
@@ -2498,7 +2499,7 @@ void launch_fill(double *x, size_t n, double v, hipStream_t st) {
     template void launch_coarse<T>(const Inst<T> *, InstState *, int, int, hipStream_t);                      \
     template void launch_pre_tb<T>(const Inst<T> *, const Work &, int, int, int, hipStream_t);                 \
     template void launch_post_tb<T>(const Inst<T> *, const Work &, int, int, int, hipStream_t);                                  \
-    template void launch_head<T>(const Inst<T> *, int, int, hipStream_t);                                    \
+    template void launch_head<T>(const Inst<T> *, InstState *, int, int, hipStream_t);                                    \
     template void launch_zero_fix<T>(const Inst<T> *, const Work &, hipStream_t);                            \
     template void launch_run_setup<T>(const Inst<T> *, int, int, int, double, int, hipStream_t);             \
     template void launch_set_vtop<T>(const Inst<T> *, int, double, hipStream_t);

@@ -949,12 +949,12 @@ void enq_cycle(Engine *e) {
 template <typename T>
 void enq_advance(Engine *e) {
     const Inst<T> *I = idev<T>(e);
-    launch_head(I, e->n, 1, e->st);
+    launch_head(I, e->st_dev, e->n, 1, e->st);
     launch_zero_fix(I, e->w_ext, e->st);
     if (e->rec) launch_qv(I, e->n, 1, nullptr, e->st);
     launch_tdgl(I, e->w_tdgl, 1, e->st);
     if (e->any_order2) launch_tdgl_corr(I, e->w_tdgl, e->st);
-    launch_begin(I, e->n, 1, e->st);
+    launch_begin(I, e->st_dev, e->n, 1, e->st);
     launch_extrap(I, e->w_ext, e->st);
     launch_residual(I, e->w_res, 0, e->any_fd, e->st);
     launch_reduce(I, e->st_dev, e->n, 0, e->st);
@@ -1022,7 +1022,7 @@ fx_status read_states(Engine *e) {
 template <typename T>
 fx_status solve_plain_t(Engine *e) {
     const Inst<T> *I = idev<T>(e);
-    launch_begin(I, e->n, 0, e->st);
+    launch_begin(I, e->st_dev, e->n, 0, e->st);
     launch_residual(I, e->w_res, 0, e->any_fd, e->st);
     launch_reduce(I, e->st_dev, e->n, 0, e->st);
     int enq = 0;
@@ -1041,7 +1041,7 @@ fx_status solve_plain_t(Engine *e) {
         if (enq >= e->max_cycles) return fail(FX_EDEVICE, "solver state did not stop after %d cycles", enq);
         batch = 1;
     }
-    launch_head(I, e->n, 0, e->st);
+    launch_head(I, e->st_dev, e->n, 0, e->st);
     launch_zero_fix(I, e->w_ext, e->st);
     if ((st = read_states(e))) return st;
     int kmax = 1;
