@@ -81,7 +81,8 @@ struct InstState {
     int prev[kMaxHist], hist;         // stored time levels phi^{n-1..n-4}
     int order;                        // extrapolation order of this solve
     int zpend;                        // right-hand side exactly zero with a nonzero residual
-    int zero_fix;                     // phi := 0 for the solve finalized in this slot
+    int zero_fix;                     // the solve finalized in this slot had f = 0 exactly (its
+                                      // last iterate was set to 0 when it stopped)
     int status;                       // fx_status of the last finalized solve
     int step, target, sched_base, sched_len;
     int pcur;                         // P buffer holding the current P
@@ -242,7 +243,6 @@ template <typename T> void launch_coarse(const Inst<T> *I, InstState *S, int nin
 template <typename T> void launch_pre_tb(const Inst<T> *I, const Work &w, int level, int nu, int lds_bytes, hipStream_t st);
 template <typename T> void launch_post_tb(const Inst<T> *I, const Work &w, int level, int nu, int lds_bytes, hipStream_t st);
 template <typename T> void launch_head(const Inst<T> *I, InstState *S, int ninst, int advance, hipStream_t st);
-template <typename T> void launch_zero_fix(const Inst<T> *I, const Work &w, hipStream_t st);
 template <typename T> void launch_run_setup(const Inst<T> *I, int ninst, int nsteps, int has_sched, double dt,
                                             int first, hipStream_t st);
 template <typename T> void launch_set_vtop(const Inst<T> *I, int ninst, double v, hipStream_t st);

@@ -749,25 +749,6 @@ __global__ void k_qv_fin(const Inst<T> *I, int ninst, int record, double *out) {
     }
 }
 
-// f = 0 exactly: N(0) = 0, so phi = 0 is the root (applied in the slot that
-// finalizes the solve).
-template <typename T>
-__global__ __launch_bounds__(256) void k_zero_fix(const Inst<T> *I, Work w) {
-    const Blk b = find_block(w);
-    const Inst<T> &a = I[b.inst];
-    const GState *s = wstate(w, b.inst);
-    const int zero_fix = s->zero_fix;
-    if (!b.ok | (zero_fix == 0)) return;  // one exit test: see smooth_kernel
-    const size_t nxy = (size_t)a.nx * a.ny, n = (size_t)a.nzd * nxy;
-    double FX_AS(1) *out = asp<1>(a.phi[s->cur]) + (size_t)a.kb * nxy;
-    const size_t base = (size_t)b.t * kExtrapChunk;
-    const int tid = threadIdx.y * BX + threadIdx.x;
-    for (int q = 0; q < kExtrapChunk / 256; ++q) {
-        const size_t c = base + (size_t)q * 256 + tid;
-        if (c < n) out[c] = 0.0;
-    }
-}
-
 // ------------------------------------------------------ fine-level residual
 // Per-plane tables of the finest level the residual reads (scaled by h^2/eps0).
 struct ResTab {
@@ -962,11 +943,14 @@ __global__ __launch_bounds__(256) void k_residual(const Inst<T> *I, Work w, int 
 }
 
 // Deterministic final sum of one instance's residual partials (a block per
-// instance) and its stop decision.
+// instance) and its stop decision.  f = 0 exactly with a nonzero residual: N(0) = 0,
+// so phi = 0 is the root; the block sets the solve's last iterate to it at once
+// (the slot that finalizes the solve reads that buffer as phi^{n+1}).
 template <typename T, int CC>
 __global__ __launch_bounds__(1024) void k_reduce(const Inst<T> *I, InstState *S) {
     __shared__ double lr[16];
     __shared__ double lf[16];
+    __shared__ int lz;
     const Inst<T> &a = I[blockIdx.x];
     GState *s = asp<1>(S + blockIdx.x);
     // the state and the partials are read together, the partials two per thread at a
@@ -978,6 +962,8 @@ __global__ __launch_bounds__(1024) void k_reduce(const Inst<T> *I, InstState *S)
     // what the stop decision reads, fetched with the rest
     const double x_prev = s->rn2, tol2 = a.tol2, light_r2 = a.light_r2, light_c2 = a.light_c2;
     const int cycles = s->cycles + (CC ? 1 : 0), max_cycles = a.max_cycles, light_ok = a.light_ok;
+    // the solve's last iterate: the start before any cycle, else the latest cycle's output
+    const int fin = cycles == 0 ? s->start : ((cycles - 1) % 2 == 0 ? s->oth0 : s->oth1);
     const int n = tiles3(a.nx, a.ny, (a.nzd + kResZ - 1) / kResZ);
     const int B = blockDim.x;
     double r = 0.0, f = 0.0;
@@ -1003,8 +989,13 @@ __global__ __launch_bounds__(1024) void k_reduce(const Inst<T> *I, InstState *S)
         s->fn2 = y;
         s->fresh = 0;
         if (CC) s->cycles = cycles;
+        int zb = -1;
         if (!isfinite(x) || !isfinite(y)) s->done = 2;
-        else if (y == 0.0) { s->done = 1; s->zpend = x != 0.0; }
+        else if (y == 0.0) {
+            s->done = 1;
+            s->zpend = x != 0.0;
+            if (x != 0.0) zb = fin;
+        }
         else if (x <= tol2 * y || x == 0.0) s->done = 1;
         else if (cycles >= max_cycles) s->done = 3;
         // within kLightRatio of the tolerance, after a cycle that contracted the
@@ -1012,6 +1003,14 @@ __global__ __launch_bounds__(1024) void k_reduce(const Inst<T> *I, InstState *S)
         // time step's first cycle), one V(1,1)-like cycle (contraction about 0.2)
         // finishes the solve at a little over half the cost
         s->light = light_ok && CC && x <= light_r2 * tol2 * y && x * light_c2 <= x_prev;
+        lz = zb;
+    }
+    __syncthreads();
+    const int zb = lz;
+    if (zb >= 0) {
+        const size_t nxy = (size_t)a.nx * a.ny, nn = (size_t)a.nzd * nxy;
+        double FX_AS(1) *out = asp<1>(a.phi[zb]) + (size_t)a.kb * nxy;
+        for (size_t c = threadIdx.x; c < nn; c += blockDim.x) out[c] = 0.0;
     }
 }
 
@@ -2451,10 +2450,6 @@ void launch_head(const Inst<T> *I, InstState *S, int ninst, int advance, hipStre
     hipLaunchKernelGGL(k_head<T>, per_inst(ninst), dim3(64), 0, st, I, S, ninst, advance);
 }
 
-template <typename T>
-void launch_zero_fix(const Inst<T> *I, const Work &w, hipStream_t st) {
-    FX_LAUNCH(k_zero_fix<T>, w, I, w);
-}
 
 template <typename T>
 void launch_run_setup(const Inst<T> *I, int ninst, int nsteps, int has_sched, double dt, int first, hipStream_t st) {
@@ -2500,7 +2495,6 @@ void launch_fill(double *x, size_t n, double v, hipStream_t st) {
     template void launch_pre_tb<T>(const Inst<T> *, const Work &, int, int, int, hipStream_t);                 \
     template void launch_post_tb<T>(const Inst<T> *, const Work &, int, int, int, hipStream_t);                                  \
     template void launch_head<T>(const Inst<T> *, InstState *, int, int, hipStream_t);                                    \
-    template void launch_zero_fix<T>(const Inst<T> *, const Work &, hipStream_t);                            \
     template void launch_run_setup<T>(const Inst<T> *, int, int, int, double, int, hipStream_t);             \
     template void launch_set_vtop<T>(const Inst<T> *, int, double, hipStream_t);
 FX_INST(double)

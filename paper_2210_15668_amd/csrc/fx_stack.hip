@@ -950,7 +950,6 @@ template <typename T>
 void enq_advance(Engine *e) {
     const Inst<T> *I = idev<T>(e);
     launch_head(I, e->st_dev, e->n, 1, e->st);
-    launch_zero_fix(I, e->w_ext, e->st);
     if (e->rec) launch_qv(I, e->n, 1, nullptr, e->st);
     launch_tdgl(I, e->w_tdgl, 1, e->st);
     if (e->any_order2) launch_tdgl_corr(I, e->w_tdgl, e->st);
@@ -1042,7 +1041,6 @@ fx_status solve_plain_t(Engine *e) {
         batch = 1;
     }
     launch_head(I, e->st_dev, e->n, 0, e->st);
-    launch_zero_fix(I, e->w_ext, e->st);
     if ((st = read_states(e))) return st;
     int kmax = 1;
     for (int i = 0; i < e->n; ++i)

@@ -158,6 +158,26 @@ def test_zero_rhs_gives_zero_phi(fx):
     assert np.all(s.get(fx.FIELD_PHI) == 0.0)
 
 
+def test_zero_rhs_from_a_nonzero_start(fx):
+    """P = 0 and V = 0 with a nonzero phi to start from: the first residual finds f = 0
+    exactly and a nonzero residual, so the solve stops at the root phi = 0 (N(0) = 0) with
+    no cycle: every device cell exactly 0, the reported residual 0.  Then time steps from
+    that state keep phi exactly 0."""
+    spec = W.shrink_lateral(W.mfism_large(), 16, 16).copy(v_top=0.0)
+    s = make_stack(fx, spec, np.zeros((spec.nz, spec.ny, spec.nx)))
+    rng = np.random.default_rng(7)
+    s.set(fx.FIELD_PHI, rng.uniform(-0.5, 0.5, (spec.nz, spec.ny, spec.nx)))
+    info = s.poisson_solve(0.0)
+    dev = np.asarray(spec.plane_mat) != W.METAL
+    phi = s.get(fx.FIELD_PHI)
+    say(f"  cycles {info.cycles}, residual {info.res_norm}, max |phi| on device planes {np.abs(phi[dev]).max()}")
+    assert info.cycles == 0 and info.res_norm == 0.0
+    assert np.all(phi[dev] == 0.0)
+    run = s.run_steps(3, W.DT, v_sched=[0.0, 0.0, 0.0])
+    assert run.steps_done == 3
+    assert np.all(s.get(fx.FIELD_PHI)[dev] == 0.0) and np.all(s.get(fx.FIELD_P) == 0.0)
+
+
 def test_resume_and_determinism(fx):
     """N1 + N2 steps equal N steps bitwise, and two identical runs agree bitwise."""
     spec = W.shrink_lateral(W.mfism_large(), 32, 32).copy(tol_rel=1e-13)
