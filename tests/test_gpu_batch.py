@@ -130,6 +130,34 @@ def test_batch_equals_single_stacks(fx, prec):
         s.close()
 
 
+def test_gate_to_zero_in_a_batch(fx):
+    """A MOS stack (no ferroelectric) whose gate steps from 1 V to 0 V: from then on the
+    right-hand side is exactly zero while the extrapolated start is not, so each such
+    solve stops at its root phi = 0 (N(0) = 0) with every device cell exactly 0; an
+    MFIM instance in the same launches still equals its own single-stack run bitwise."""
+    mos = W.layered(32, 32, 24, [(W.DE, 4, W.EPS_SIO2, 0.0), (W.SC, 16, W.EPS_SI, 1e24)], v_top=1.0,
+                    tol_rel=1e-10, ni=1.0e16, T=300.0)
+    mfim = W.layered(32, 32, 32, [(W.FE, 16, W.EPS_FE, 0.0), (W.DE, 4, W.EPS_SIO2, 0.0)], v_top=0.5,
+                     tol_rel=1e-10)
+    specs = [mos, mfim]
+    Ps = [np.zeros((mos.nz, mos.ny, mos.nx)), W.random_P(mfim, 98, amp=0.05)]
+    vs = [[1.0, 0.0, 0.0, 0.0], [0.5, 0.5, -0.5, -0.5]]
+    b = fx.Batch(specs, Ps)
+    info = b.run(4, W.DT, vs)
+    assert all(i.status == fx.FX_OK and i.steps_done == 4 for i in info)
+    dev = np.asarray(mos.plane_mat) != W.METAL
+    phi0 = b.get(0, fx.FIELD_PHI)
+    say(f"  MOS at 0 V: max |phi| on device planes {np.abs(phi0[dev]).max()}, last rel. residual "
+        f"{info[0].last_res_rel}")
+    assert np.all(phi0[dev] == 0.0) and info[0].last_res_rel == 0.0
+    s = fx.Stack(mfim, Ps[1])
+    s.run_steps(4, W.DT, vs[1])
+    assert np.array_equal(s.get(fx.FIELD_P), b.get(1, fx.FIELD_P))
+    assert np.array_equal(s.get(fx.FIELD_PHI), b.get(1, fx.FIELD_PHI))
+    s.close()
+    b.close()
+
+
 def test_batch_failure_is_isolated(fx):
     """An instance that cannot converge stops with FX_ENOCONV; the others finish every step
     and still equal their single-stack results."""
