@@ -178,6 +178,23 @@ def test_zero_rhs_from_a_nonzero_start(fx):
     assert np.all(s.get(fx.FIELD_PHI)[dev] == 0.0) and np.all(s.get(fx.FIELD_P) == 0.0)
 
 
+def test_mos_stack_matches_oracle(fx, orc):
+    """A stack without a ferroelectric (metal / SiO2 / p-Si / metal, Boltzmann carriers):
+    Step 0 and three steps with the gate stepped 1 -> 0.5 -> -0.5 V meet the oracle to
+    1e-10 over device cells; P stays exactly 0 (no polarisation to update)."""
+    spec = W.layered(32, 32, 24, [(W.DE, 4, W.EPS_SIO2, 0.0), (W.SC, 16, W.EPS_SI, 1e24)], v_top=1.0,
+                     tol_rel=1e-13, ni=1.0e16, T=300.0)
+    P0 = np.zeros((spec.nz, spec.ny, spec.nx))
+    vs = [1.0, 0.5, -0.5]
+    s = make_stack(fx, spec, P0)
+    info = s.run_steps(3, W.DT, v_sched=vs)
+    assert info.steps_done == 3
+    P_o, phi_o, _ = orc.run(spec, P0, 3, W.DT, v_sched=vs, tol=1e-13)
+    r, m = check(spec, s.get(fx.FIELD_PHI), phi_o, 1e-10, "phi")
+    say(f"    {info.total_cycles} V-cycles; phi rel L2 {r:.2e}, max-abs {m:.2e}")
+    assert np.all(s.get(fx.FIELD_P) == 0.0) and np.all(P_o == 0.0)
+
+
 def test_resume_and_determinism(fx):
     """N1 + N2 steps equal N steps bitwise, and two identical runs agree bitwise."""
     spec = W.shrink_lateral(W.mfism_large(), 32, 32).copy(tol_rel=1e-13)
